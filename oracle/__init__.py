@@ -1,0 +1,143 @@
+"""Oracle -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, double-precision CPU reference of everything the GPU path computes.  Only the
+test-suite, the smoke check and the CPU-baseline leg of the benchmark may import this package;
+the product library never does, and this package never imports the product.
+
+Parts:
+  srp_oracle.c   brute-force FP64 ray-grid SRP tracer (Philox draws, grid frames, bounce loop,
+                 force/torque sums, per-ray records and degeneracy flags) -- loaded here via ctypes
+  design.py      hinge rotation of panel vertices (design apply), FP64
+  (further modules add the adjoint, the MLP surrogate and the orbit integrator)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain C, -O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        src = os.path.join(_HERE, "srp_oracle.c")
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+               "-o", tmp, src, "-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        L.oracle_philox4x32_10.argtypes = [P, P, P]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_basis.argtypes = [P, P, P]
+        L.oracle_basis.restype = None
+        L.oracle_frames.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P]
+        L.oracle_frames.restype = ctypes.c_int
+        L.oracle_default_pspec.argtypes = [ctypes.c_float, ctypes.c_float]
+        L.oracle_default_pspec.restype = ctypes.c_float
+        L.oracle_trace.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, P,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, P, ctypes.c_int64,
+                                   P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_trace.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 block: 4 x uint32 counter, 2 x uint32 key -> 4 x uint32."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def basis(n) -> tuple[np.ndarray, np.ndarray]:
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    b1 = np.zeros(3)
+    b2 = np.zeros(3)
+    lib().oracle_basis(_ptr(n), _ptr(b1), _ptr(b2))
+    return b1, b2
+
+
+def frames(verts, sun_dirs, nu: int, nv: int) -> np.ndarray:
+    """Grid frames [D][12] = u[3], v[3], o0[3], du, dv, 0 for each sun direction."""
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    sun = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((len(sun), 12))
+    st = lib().oracle_frames(_ptr(verts), len(verts), _ptr(sun), len(sun), nu, nv, _ptr(out))
+    if st != 0:
+        raise ValueError(f"oracle_frames failed ({st})")
+    return out
+
+
+def default_pspec(rho_s, rho_d) -> np.ndarray:
+    rs = np.asarray(rho_s, dtype=np.float32).ravel()
+    rd = np.asarray(rho_d, dtype=np.float32).ravel()
+    f = lib().oracle_default_pspec
+    return np.array([f(float(a), float(b)) for a, b in zip(rs, rd)], dtype=np.float32)
+
+
+class TraceResult:
+    def __init__(self, force, torque, hit_prim=None, degen=None, ray_force=None, ray_torque=None):
+        self.force = force
+        self.torque = torque
+        self.hit_prim = hit_prim
+        self.degen = degen
+        self.ray_force = ray_force
+        self.ray_torque = ray_torque
+
+
+def trace(verts, tris, rho_s, rho_d, sun_dirs, *, nu: int, nv: int, bounces: int, jitter: bool = True,
+          flux: float = 1361.0, seed: int = 0, dir_index_base: int = 0, design_index: int = 0,
+          p_spec=None, com=None, frames_in=None, pix=None, records: bool = False, threads: int | None = None
+          ) -> TraceResult:
+    """FP64 brute-force ray-grid SRP estimate; see srp_oracle.c for the definition."""
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    rs = np.ascontiguousarray(rho_s, dtype=np.float32)
+    rd = np.ascontiguousarray(rho_d, dtype=np.float32)
+    ps = None if p_spec is None else np.ascontiguousarray(p_spec, dtype=np.float32)
+    c = None if com is None else np.ascontiguousarray(com, dtype=np.float64)
+    sun = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
+    D = len(sun)
+    fr = None if frames_in is None else np.ascontiguousarray(frames_in, dtype=np.float64).reshape(D, 12)
+    px = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
+    n_pix = nu * nv if px is None else len(px)
+    force = np.zeros((D, 3))
+    torque = np.zeros((D, 3))
+    hp = dg = rf = rt = None
+    if records:
+        hp = np.zeros((D, n_pix, bounces), dtype=np.int32)
+        dg = np.zeros((D, n_pix, bounces), dtype=np.uint8)
+        rf = np.zeros((D, n_pix, 3))
+        rt = np.zeros((D, n_pix, 3))
+    if threads is None:
+        threads = os.cpu_count() or 1
+    st = lib().oracle_trace(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd), _ptr(ps), _ptr(c),
+                            _ptr(sun), D, _ptr(fr), nu, nv, bounces, int(bool(jitter)), float(flux), int(seed),
+                            int(dir_index_base), int(design_index), _ptr(px), n_pix, _ptr(force), _ptr(torque),
+                            _ptr(hp), _ptr(dg), _ptr(rf), _ptr(rt), int(threads))
+    if st != 0:
+        raise ValueError(f"oracle_trace failed ({st})")
+    return TraceResult(force, torque, hp, dg, rf, rt)

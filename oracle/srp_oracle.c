@@ -1,0 +1,638 @@
+/*
+ * srp_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, double-precision CPU reference of the ray-grid Monte Carlo estimate of solar
+ * radiation pressure (SRP) force and torque on a triangle mesh.  Only the test-suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load this library; the product path never
+ * links or calls it.  It shares no code with the GPU library: every formula here is written out
+ * again from the paper and from the published methods it names.
+ *
+ * What it computes (paper, Sec. 3.2 "Radiation Pressure Simulation"):
+ *   - Eq. (Force) / the light-to-force map l2f: a photon packet of power P arriving along the
+ *     propagation direction d and leaving along o deposits (P/c)(d - o); the clamped cosine
+ *     <n, w_in>+ is realised by the ray-grid footprint (rays are spaced on a plane normal to d,
+ *     so each ray carries the flux through its pixel: w = Phi * du * dv / c).
+ *   - F = integral over the surface, tau = integral of (x - x_COM) x f  (Sec. 3.2, force and
+ *     torque integrals): every deposit is added to F and (x - x_COM) x deposit to tau.
+ *   - Single distant light from one direction (Sec. 3.2, first paragraph).
+ *   - Per-face materials (Sec. 3.2, "Estimation"): here ideal mirror (rho_s), Lambertian (rho_d)
+ *     and absorbed (1 - rho_s - rho_d).
+ *   - Light followed as a path over several surface interactions (Sec. 3.2, "Estimation").
+ *   - Lambertian momentum factor 2/3 (Sec. 5.9, thermal recoil of a Lambertian emitter): the
+ *     expected momentum leaving a Lambertian reflector is (2/3) rho_d n per unit incident.
+ * Readings where the paper is silent (ray grid, basis, RNG, tie rules, offsets) are listed in the
+ * design document; each is restated at the point of use below.
+ *
+ * Everything is double precision except the per-facet reflectances and specular-sampling
+ * probabilities, which arrive as float32 arrays so that the specular/diffuse decision
+ * (u_e < p_s) is taken on exactly the same numbers as in the GPU path.
+ *
+ * Pinned by tests/test_oracle_pins.py (plate and sphere closed forms, dihedral retro-reflection,
+ * Lambertian 2/3 mean, invariants, intersection against numpy.linalg.solve, Philox against the
+ * rocRAND library implementation).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_EDEGENERATE (-4)
+
+static const double kSpeedOfLight = 299792458.0; /* m/s, exact by definition */
+
+/* ------------------------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as easy as 1, 2, 3",   */
+/* SC'11).  Ten rounds of the 4x32 Philox S-box with the published multipliers and Weyl key    */
+/* increments.                                                                                 */
+/* ------------------------------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod_a = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod_b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi_a = (uint32_t)(prod_a >> 32), lo_a = (uint32_t)prod_a;
+        uint32_t hi_b = (uint32_t)(prod_b >> 32), lo_b = (uint32_t)prod_b;
+        uint32_t n0 = hi_b ^ c1 ^ k0;
+        uint32_t n1 = lo_b;
+        uint32_t n2 = hi_a ^ c3 ^ k1;
+        uint32_t n3 = lo_a;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 24 high bits -> [0, 1): exactly representable in float and double. */
+static double u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+static void draw4(uint64_t seed, uint32_t pixel, uint32_t dir, uint32_t bounce, uint32_t design,
+                  double u[4])
+{
+    uint32_t ctr[4] = {pixel, dir, bounce, design};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    oracle_philox4x32_10(ctr, key, r);
+    for (int i = 0; i < 4; ++i) u[i] = u01(r[i]);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* small vector helpers (double)                                                               */
+/* ------------------------------------------------------------------------------------------ */
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double a[3], const double b[3], double r[3])
+{
+    double x = a[1] * b[2] - a[2] * b[1];
+    double y = a[2] * b[0] - a[0] * b[2];
+    double z = a[0] * b[1] - a[1] * b[0];
+    r[0] = x; r[1] = y; r[2] = z;
+}
+static void sub3(const double a[3], const double b[3], double r[3]) { r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2]; }
+
+/* Orthonormal basis (b1, b2) completing the unit vector n to a right-handed frame
+ * (b1 x b2 = n): Duff, Burgess, Christensen, Hery, Kensler, Liani, Villemin, "Building an
+ * Orthonormal Basis, Revisited", JCGT 6(1), 2017.  sign(0) is taken as +1. */
+void oracle_basis(const double n[3], double b1[3], double b2[3])
+{
+    double s = (n[2] >= 0.0) ? 1.0 : -1.0;
+    double a = -1.0 / (s + n[2]);
+    double b = n[0] * n[1] * a;
+    b1[0] = 1.0 + s * n[0] * n[0] * a;
+    b1[1] = s * b;
+    b1[2] = -s * n[0];
+    b2[0] = b;
+    b2[1] = s + n[1] * n[1] * a;
+    b2[2] = -n[1];
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Grid frame of one sun direction.                                                            */
+/* Layout of a frame (12 doubles): u[3], v[3], o0[3], du, dv, unused.                          */
+/* Ray origin of pixel (i, k) with in-pixel offsets (a, b):  o0 + (i + a) du u + (k + b) dv v. */
+/* The rectangle spans the projections of the 8 corners of the mesh's axis-aligned bounding   */
+/* box on (u, v); the entry plane sits 0.01 L in front of the nearest corner, where L is the    */
+/* scene size: twice the largest distance of a vertex from the vertex mean (rotation-invariant).*/
+/* ------------------------------------------------------------------------------------------ */
+static void mesh_aabb(const double* verts, int64_t n_verts, double lo[3], double hi[3])
+{
+    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    for (int64_t i = 0; i < n_verts; ++i)
+        for (int a = 0; a < 3; ++a) {
+            double x = verts[3 * i + a];
+            if (x < lo[a]) lo[a] = x;
+            if (x > hi[a]) hi[a] = x;
+        }
+}
+
+static double scene_size(const double* verts, int64_t n_verts)
+{
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n_verts; ++i)
+        for (int a = 0; a < 3; ++a) m[a] += verts[3 * i + a];
+    for (int a = 0; a < 3; ++a) m[a] /= (double)n_verts;
+    double r2 = 0.0;
+    for (int64_t i = 0; i < n_verts; ++i) {
+        double q[3];
+        sub3(verts + 3 * i, m, q);
+        double d2 = dot3(q, q);
+        if (d2 > r2) r2 = d2;
+    }
+    return 2.0 * sqrt(r2);
+}
+
+static void propagation_dir(const double sun[3], double d[3])
+{
+    double len = sqrt(dot3(sun, sun));
+    d[0] = -sun[0] / len; d[1] = -sun[1] / len; d[2] = -sun[2] / len;
+}
+
+static void frame_from_box(const double lo[3], const double hi[3], double L, const double sun[3], int32_t nu,
+                           int32_t nv, double fr[12])
+{
+    double d[3], u[3], v[3];
+    propagation_dir(sun, d);
+    oracle_basis(d, u, v);
+    double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, smin = INFINITY;
+    for (int c = 0; c < 8; ++c) {
+        double p[3] = {(c & 1) ? hi[0] : lo[0], (c & 2) ? hi[1] : lo[1], (c & 4) ? hi[2] : lo[2]};
+        double pu = dot3(p, u), pv = dot3(p, v), ps = dot3(p, d);
+        if (pu < umin) umin = pu;
+        if (pu > umax) umax = pu;
+        if (pv < vmin) vmin = pv;
+        if (pv > vmax) vmax = pv;
+        if (ps < smin) smin = ps;
+    }
+    double s0 = smin - 0.01 * L;
+    for (int a = 0; a < 3; ++a) {
+        fr[a] = u[a];
+        fr[3 + a] = v[a];
+        fr[6 + a] = s0 * d[a] + umin * u[a] + vmin * v[a];
+    }
+    fr[9] = (umax - umin) / (double)nu;
+    fr[10] = (vmax - vmin) / (double)nv;
+    fr[11] = 0.0;
+}
+
+int oracle_frames(const double* verts, int64_t n_verts, const double* sun_dirs, int64_t n_dirs,
+                  int32_t nu, int32_t nv, double* frames)
+{
+    if (!verts || n_verts <= 0 || !sun_dirs || n_dirs < 0 || nu <= 0 || nv <= 0 || !frames)
+        return ORC_EINVAL;
+    double lo[3], hi[3];
+    mesh_aabb(verts, n_verts, lo, hi);
+    const double L = scene_size(verts, n_verts);
+    for (int64_t j = 0; j < n_dirs; ++j) frame_from_box(lo, hi, L, sun_dirs + 3 * j, nu, nv, frames + 12 * j);
+    return ORC_OK;
+}
+
+/* Default probability of sampling the specular event at a facet, in float arithmetic:
+ * rho_s / (rho_s + rho_d) clamped to [0.01, 0.99] when both are positive, else 1 or 0. */
+float oracle_default_pspec(float rs, float rd)
+{
+    if (rs > 0.0f && rd > 0.0f) {
+        float p = rs / (rs + rd);
+        if (p < 0.01f) p = 0.01f;
+        if (p > 0.99f) p = 0.99f;
+        return p;
+    }
+    return rs > 0.0f ? 1.0f : 0.0f;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* scene                                                                                       */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n_tris;
+    double* v0;  /* [T][3] */
+    double* e1;  /* [T][3] */
+    double* e2;  /* [T][3] */
+    double* nrm; /* [T][3] unit outward normal, (v1-v0) x (v2-v0) */
+    double* pv;  /* [T][9] vertices, for the degeneracy tests */
+    const float* rho_s;
+    const float* rho_d;
+    float* p_spec;
+    double com[3];
+    double L;  /* scene size (see scene_size) */
+} scene_t;
+
+static int scene_init(scene_t* S, const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                      const float* rho_s, const float* rho_d, const float* p_spec, const double com[3])
+{
+    memset(S, 0, sizeof(*S));
+    S->n_tris = n_tris;
+    S->v0 = malloc(sizeof(double) * 3 * n_tris);
+    S->e1 = malloc(sizeof(double) * 3 * n_tris);
+    S->e2 = malloc(sizeof(double) * 3 * n_tris);
+    S->nrm = malloc(sizeof(double) * 3 * n_tris);
+    S->pv = malloc(sizeof(double) * 9 * n_tris);
+    S->p_spec = malloc(sizeof(float) * n_tris);
+    if (!S->v0 || !S->e1 || !S->e2 || !S->nrm || !S->pv || !S->p_spec) return ORC_ENOMEM;
+    for (int64_t f = 0; f < n_tris; ++f) {
+        const double* p[3];
+        for (int c = 0; c < 3; ++c) {
+            int32_t id = tris[3 * f + c];
+            if (id < 0 || id >= n_verts) return ORC_EINVAL;
+            p[c] = verts + 3 * (int64_t)id;
+            for (int a = 0; a < 3; ++a) S->pv[9 * f + 3 * c + a] = p[c][a];
+        }
+        sub3(p[1], p[0], S->e1 + 3 * f);
+        sub3(p[2], p[0], S->e2 + 3 * f);
+        for (int a = 0; a < 3; ++a) S->v0[3 * f + a] = p[0][a];
+        double n[3];
+        cross3(S->e1 + 3 * f, S->e2 + 3 * f, n);
+        double len = sqrt(dot3(n, n));
+        if (!(len > 0.0) || !isfinite(len)) return ORC_EDEGENERATE;
+        for (int a = 0; a < 3; ++a) S->nrm[3 * f + a] = n[a] / len;
+        S->p_spec[f] = p_spec ? p_spec[f] : oracle_default_pspec(rho_s[f], rho_d[f]);
+    }
+    S->rho_s = rho_s;
+    S->rho_d = rho_d;
+    for (int a = 0; a < 3; ++a) S->com[a] = com ? com[a] : 0.0;
+    S->L = scene_size(verts, n_verts);
+    return ORC_OK;
+}
+
+static void scene_free(scene_t* S)
+{
+    free(S->v0); free(S->e1); free(S->e2); free(S->nrm); free(S->pv); free(S->p_spec);
+}
+
+/* Closest front-facing hit over all triangles, brute force (Moller & Trumbore 1997, "Fast,
+ * minimum storage ray-triangle intersection"), one-sided: a hit counts only when the ray meets
+ * the outward side (d . n < 0).  Barycentric bounds are inclusive, t must exceed 0, the
+ * triangle `skip` (the one the ray leaves) is never hit, and an exact tie in t goes to the lower
+ * triangle index. */
+static int64_t closest_hit(const scene_t* S, const double o[3], const double d[3], int64_t skip, double* t_out)
+{
+    int64_t best = -1;
+    double tbest = INFINITY;
+    for (int64_t f = 0; f < S->n_tris; ++f) {
+        if (f == skip) continue;
+        const double* e1 = S->e1 + 3 * f;
+        const double* e2 = S->e2 + 3 * f;
+        double pvec[3];
+        cross3(d, e2, pvec);
+        double det = dot3(e1, pvec);
+        if (!(det > 0.0)) continue;
+        double tvec[3];
+        sub3(o, S->v0 + 3 * f, tvec);
+        double uu = dot3(tvec, pvec);
+        if (uu < 0.0 || uu > det) continue;
+        double qvec[3];
+        cross3(tvec, e1, qvec);
+        double vv = dot3(d, qvec);
+        if (vv < 0.0 || uu + vv > det) continue;
+        double t = dot3(e2, qvec) / det;
+        if (!(t > 0.0)) continue;
+        if (t < tbest) { tbest = t; best = f; }
+    }
+    *t_out = tbest;
+    return best;
+}
+
+/* ---- degeneracy classification of one segment ------------------------------------------- */
+/* A segment is flagged when a float32 evaluation could plausibly choose a different closest
+ * hit than this double evaluation:
+ *   (i)   another front-facing hit lies within TIE * L of the closest one in t;
+ *   (ii)  the ray passes within EDGE * L (measured in the plane normal to the ray) of an edge of
+ *         a triangle that lies along the ray no farther than the closest hit (+ TIE * L);
+ *   (iii) the closest hit is grazing: cos(theta) < GRAZE;
+ *   (v)   the closest hit is at t < NEAR * L, or a front-facing triangle containing the ray's
+ *         projection (within EDGE * L) has its plane within NEAR * L of the origin.
+ * (The specular/diffuse event needs no margin: both paths compare the same float32 numbers.) */
+#define DEG_TIE 1e-5
+#define DEG_EDGE 1e-5
+#define DEG_GRAZE 1e-5
+#define DEG_NEAR 3e-6
+
+static double point_segment_dist(const double p[3], const double a[3], const double b[3])
+{
+    double ab[3], ap[3];
+    sub3(b, a, ab);
+    sub3(p, a, ap);
+    double l2 = dot3(ab, ab);
+    double s = l2 > 0.0 ? dot3(ap, ab) / l2 : 0.0;
+    if (s < 0.0) s = 0.0;
+    if (s > 1.0) s = 1.0;
+    double q[3] = {a[0] + s * ab[0] - p[0], a[1] + s * ab[1] - p[1], a[2] + s * ab[2] - p[2]};
+    return sqrt(dot3(q, q));
+}
+
+static int segment_degenerate(const scene_t* S, const double o[3], const double d[3], int64_t skip, int64_t hit,
+                              double thit)
+{
+    const double L = S->L;
+    const double tmax = (hit >= 0) ? thit + DEG_TIE * L : INFINITY;
+    if (hit >= 0) {
+        double c = -dot3(d, S->nrm + 3 * hit);
+        if (c < DEG_GRAZE) return 1;
+        if (thit < DEG_NEAR * L) return 1;
+    }
+    const double zero[3] = {0.0, 0.0, 0.0};
+    for (int64_t f = 0; f < S->n_tris; ++f) {
+        if (f == skip) continue;
+        /* project the vertices on the plane through o normal to d */
+        double q[3][3], along[3];
+        for (int c = 0; c < 3; ++c) {
+            double rel[3];
+            sub3(S->pv + 9 * f + 3 * c, o, rel);
+            along[c] = dot3(rel, d);
+            for (int a = 0; a < 3; ++a) q[c][a] = rel[a] - along[c] * d[a];
+        }
+        double amin = fmin(along[0], fmin(along[1], along[2]));
+        double amax = fmax(along[0], fmax(along[1], along[2]));
+        if (amax < -DEG_NEAR * L - DEG_EDGE * L || amin > tmax) continue;
+        double e0 = point_segment_dist(zero, q[0], q[1]);
+        double e1 = point_segment_dist(zero, q[1], q[2]);
+        double e2 = point_segment_dist(zero, q[2], q[0]);
+        double emin = fmin(e0, fmin(e1, e2));
+        /* is the projected ray point inside the projected triangle? (signed areas) */
+        double n1[3], n2[3], n3[3];
+        double a0[3], a1[3], a2[3];
+        sub3(q[1], q[0], a0); sub3(q[2], q[1], a1); sub3(q[0], q[2], a2);
+        double m0[3], m1[3], m2[3];
+        sub3(zero, q[0], m0); sub3(zero, q[1], m1); sub3(zero, q[2], m2);
+        cross3(a0, m0, n1); cross3(a1, m1, n2); cross3(a2, m2, n3);
+        double s1 = dot3(n1, d), s2 = dot3(n2, d), s3 = dot3(n3, d);
+        int inside = (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
+        if (!inside && emin >= DEG_EDGE * L) continue;
+        /* (ii) near an edge of a triangle the ray meets or narrowly misses */
+        if (emin < DEG_EDGE * L && amin <= tmax) return 1;
+        /* plane distance along the ray for a non-grazing triangle */
+        double cosn = dot3(d, S->nrm + 3 * f);
+        if (fabs(cosn) > DEG_GRAZE) {
+            double tplane = dot3(S->nrm + 3 * f, (double[3]){S->pv[9 * f] - o[0], S->pv[9 * f + 1] - o[1], S->pv[9 * f + 2] - o[2]}) / cosn;
+            /* (i) a second front-facing hit close to the closest one */
+            if (cosn < 0.0 && f != hit && hit >= 0 && fabs(tplane - thit) < DEG_TIE * L) return 1;
+            /* (v) a front-facing plane crossing very near the origin */
+            if (cosn < 0.0 && fabs(tplane) < DEG_NEAR * L) return 1;
+        } else if (amin <= tmax && amax >= -DEG_NEAR * L) {
+            return 1; /* grazing triangle the ray passes through */
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* one path                                                                                    */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    int32_t nu, nv, bounces, jitter;
+    double flux;
+    uint64_t seed;
+    int64_t dir_index_base;
+    uint32_t design_index;
+} params_t;
+
+/* Traces primary pixel `pixel` of direction j (global index dir_global) and returns the force
+ * and torque it deposits.  Optionally records, per surface interaction, the hit triangle
+ * (-1 = the path escaped) and the degeneracy flag. */
+static void trace_path(const scene_t* S, const double fr[12], const double sun[3], const params_t* P, int64_t pixel,
+                       uint32_t dir_global, double F[3], double T[3], int32_t* hits, uint8_t* degen)
+{
+    const int32_t nu = P->nu;
+    const int64_t i = pixel % nu, k = pixel / nu;
+    double a = 0.5, b = 0.5;
+    if (P->jitter) {
+        double r[4];
+        draw4(P->seed, (uint32_t)pixel, dir_global, 0u, P->design_index, r);
+        a = r[0];
+        b = r[1];
+    }
+    const double* u = fr;
+    const double* v = fr + 3;
+    const double* o0 = fr + 6;
+    const double du = fr[9], dv = fr[10];
+    double o[3], d[3];
+    for (int c = 0; c < 3; ++c) o[c] = o0[c] + ((double)i + a) * du * u[c] + ((double)k + b) * dv * v[c];
+    propagation_dir(sun, d);
+    double w = P->flux * du * dv / kSpeedOfLight; /* force carried by the ray tube, N */
+    const double eps = 1e-5 * S->L;
+    int64_t skip = -1;
+    F[0] = F[1] = F[2] = 0.0;
+    T[0] = T[1] = T[2] = 0.0;
+    int deg = 0;
+    for (int bnc = 1; bnc <= P->bounces; ++bnc) {
+        double t;
+        int64_t f = closest_hit(S, o, d, skip, &t);
+        if (degen) {
+            if (!deg) deg = segment_degenerate(S, o, d, skip, f, t);
+            degen[bnc - 1] = (uint8_t)deg;
+        }
+        if (hits) hits[bnc - 1] = (int32_t)f;
+        if (f < 0) {
+            for (int rest = bnc; rest < P->bounces; ++rest) {
+                if (hits) hits[rest] = -1;
+                if (degen) degen[rest] = (uint8_t)deg;
+            }
+            break;
+        }
+        const double* n = S->nrm + 3 * f;
+        double x[3], lever[3];
+        for (int c = 0; c < 3; ++c) {
+            x[c] = o[c] + t * d[c];
+            lever[c] = x[c] - S->com[c];
+        }
+        const double cth = -dot3(d, n);
+        double r[3];
+        for (int c = 0; c < 3; ++c) r[c] = d[c] + 2.0 * cth * n[c];
+        const double rs = (double)S->rho_s[f], rd = (double)S->rho_d[f];
+        /* incoming momentum */
+        double dep[3] = {w * d[0], w * d[1], w * d[2]};
+        double tq[3];
+        for (int c = 0; c < 3; ++c) F[c] += dep[c];
+        cross3(lever, dep, tq);
+        for (int c = 0; c < 3; ++c) T[c] += tq[c];
+        if (bnc == P->bounces || (S->rho_s[f] == 0.0f && S->rho_d[f] == 0.0f)) {
+            /* last traced interaction: the expected outgoing momentum leaves the body */
+            double out[3];
+            for (int c = 0; c < 3; ++c) out[c] = w * (rs * r[c] + (2.0 / 3.0) * rd * n[c]);
+            for (int c = 0; c < 3; ++c) F[c] -= out[c];
+            cross3(lever, out, tq);
+            for (int c = 0; c < 3; ++c) T[c] -= tq[c];
+            for (int rest = bnc; rest < P->bounces; ++rest) {
+                if (hits) hits[rest] = -1;
+                if (degen) degen[rest] = (uint8_t)deg;
+            }
+            break;
+        }
+        double ev[4];
+        draw4(P->seed, (uint32_t)pixel, dir_global, (uint32_t)bnc, P->design_index, ev);
+        const float ps = S->p_spec[f];
+        double odir[3], w2;
+        if ((float)ev[0] < ps) {
+            for (int c = 0; c < 3; ++c) odir[c] = r[c];
+            w2 = w * rs / (double)ps;
+        } else {
+            /* cosine-weighted direction about n (Malley's method) */
+            double rad = sqrt(ev[1]);
+            double phi = 2.0 * M_PI * ev[2];
+            double lx = rad * cos(phi), ly = rad * sin(phi), lz = sqrt(fmax(0.0, 1.0 - ev[1]));
+            double t1[3], t2[3];
+            oracle_basis(n, t1, t2);
+            for (int c = 0; c < 3; ++c) odir[c] = lx * t1[c] + ly * t2[c] + lz * n[c];
+            w2 = w * rd / (1.0 - (double)ps);
+        }
+        double out[3] = {w2 * odir[0], w2 * odir[1], w2 * odir[2]};
+        for (int c = 0; c < 3; ++c) F[c] -= out[c];
+        cross3(lever, out, tq);
+        for (int c = 0; c < 3; ++c) T[c] -= tq[c];
+        for (int c = 0; c < 3; ++c) {
+            o[c] = x[c] + eps * n[c];
+            d[c] = odir[c];
+        }
+        w = w2;
+        skip = f;
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* threaded driver                                                                             */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    const scene_t* S;
+    const params_t* P;
+    const double* frames;
+    const double* sun_dirs;
+    int64_t n_dirs;
+    const int64_t* pix;
+    int64_t n_pix;
+    double* part_f; /* [D][chunks][3] per-chunk sums, added in chunk order afterwards */
+    double* part_t;
+    int64_t n_chunks;
+    int32_t* hit_prim;
+    uint8_t* degen;
+    double* ray_force;
+    double* ray_torque;
+    int64_t next; /* work counter (rows of 64 pixels) */
+    pthread_mutex_t lock;
+    int32_t n_threads;
+} job_t;
+
+typedef struct {
+    job_t* J;
+    int32_t tid;
+} worker_arg_t;
+
+#define CHUNK 64
+
+static void* worker(void* argp)
+{
+    worker_arg_t* A = (worker_arg_t*)argp;
+    job_t* J = A->J;
+    const int64_t per_dir = (J->n_pix + CHUNK - 1) / CHUNK;
+    const int64_t total = per_dir * J->n_dirs;
+    const int32_t B = J->P->bounces;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t item = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (item >= total) break;
+        int64_t j = item / per_dir;
+        int64_t p0 = (item % per_dir) * CHUNK;
+        int64_t p1 = p0 + CHUNK < J->n_pix ? p0 + CHUNK : J->n_pix;
+        double* pf = J->part_f + 3 * item;
+        double* pt = J->part_t + 3 * item;
+        for (int64_t q = p0; q < p1; ++q) {
+            int64_t pixel = J->pix ? J->pix[q] : q;
+            int64_t rec = j * J->n_pix + q;
+            double F[3], T[3];
+            trace_path(J->S, J->frames + 12 * j, J->sun_dirs + 3 * j, J->P, pixel,
+                       (uint32_t)(J->P->dir_index_base + j), F, T,
+                       J->hit_prim ? J->hit_prim + rec * B : NULL, J->degen ? J->degen + rec * B : NULL);
+            for (int c = 0; c < 3; ++c) {
+                pf[c] += F[c];
+                pt[c] += T[c];
+            }
+            if (J->ray_force)
+                for (int c = 0; c < 3; ++c) J->ray_force[3 * rec + c] = F[c];
+            if (J->ray_torque)
+                for (int c = 0; c < 3; ++c) J->ray_torque[3 * rec + c] = T[c];
+        }
+    }
+    return NULL;
+}
+
+/*
+ * oracle_trace: ray-grid SRP estimate for n_dirs sun directions.
+ *   verts [n_verts][3] (m, body frame), tris [n_tris][3] (counter-clockwise seen from outside),
+ *   rho_s, rho_d [n_tris] float32, p_spec [n_tris] float32 or NULL (default rule),
+ *   com [3] or NULL (origin), sun_dirs [n_dirs][3] unit vectors toward the Sun,
+ *   frames [n_dirs][12] or NULL (computed from the mesh bounding box),
+ *   pix [n_pix] explicit pixel list (pixel = i + k*nu) or NULL (all nu*nv pixels; n_pix ignored),
+ *   force, torque [n_dirs][3] sums over the traced pixels (N, N m),
+ *   hit_prim, degen [n_dirs][n_pix][bounces], ray_force, ray_torque [n_dirs][n_pix][3]: optional
+ *   per-ray records.  Pixels are summed sequentially within chunks of 64; chunk sums are added
+ *   in chunk order, so the result does not depend on the thread count.
+ */
+int oracle_trace(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris, const float* rho_s,
+                 const float* rho_d, const float* p_spec, const double* com, const double* sun_dirs, int64_t n_dirs,
+                 const double* frames, int32_t nu, int32_t nv, int32_t bounces, int32_t jitter, double flux,
+                 uint64_t seed, int64_t dir_index_base, uint32_t design_index, const int64_t* pix, int64_t n_pix,
+                 double* force, double* torque, int32_t* hit_prim, uint8_t* degen, double* ray_force,
+                 double* ray_torque, int32_t n_threads)
+{
+    if (!verts || n_verts <= 0 || !tris || n_tris <= 0 || !rho_s || !rho_d || !sun_dirs || n_dirs < 0 || nu <= 0 ||
+        nv <= 0 || bounces < 1 || !force || !torque)
+        return ORC_EINVAL;
+    if (!pix) n_pix = (int64_t)nu * nv;
+    if (n_pix < 0) return ORC_EINVAL;
+    for (int64_t f = 0; f < n_tris; ++f)
+        if (!(rho_s[f] >= 0.0f) || !(rho_d[f] >= 0.0f) || rho_s[f] + rho_d[f] > 1.0f) return ORC_EINVAL;
+    scene_t S;
+    int st = scene_init(&S, verts, n_verts, tris, n_tris, rho_s, rho_d, p_spec, com);
+    if (st != ORC_OK) {
+        scene_free(&S);
+        return st;
+    }
+    double* fr = NULL;
+    if (!frames) {
+        fr = malloc(sizeof(double) * 12 * (n_dirs > 0 ? n_dirs : 1));
+        if (!fr) { scene_free(&S); return ORC_ENOMEM; }
+        oracle_frames(verts, n_verts, sun_dirs, n_dirs, nu, nv, fr);
+        frames = fr;
+    }
+    params_t P = {nu, nv, bounces, jitter, flux, seed, dir_index_base, design_index};
+    if (n_threads < 1) n_threads = 1;
+    job_t J;
+    memset(&J, 0, sizeof(J));
+    J.S = &S; J.P = &P; J.frames = frames; J.sun_dirs = sun_dirs; J.n_dirs = n_dirs;
+    J.pix = pix; J.n_pix = n_pix; J.hit_prim = hit_prim; J.degen = degen;
+    J.ray_force = ray_force; J.ray_torque = ray_torque; J.n_threads = n_threads;
+    J.n_chunks = (n_pix + CHUNK - 1) / CHUNK;
+    J.part_f = calloc((size_t)3 * J.n_chunks * (n_dirs > 0 ? n_dirs : 1) + 3, sizeof(double));
+    J.part_t = calloc((size_t)3 * J.n_chunks * (n_dirs > 0 ? n_dirs : 1) + 3, sizeof(double));
+    if (!J.part_f || !J.part_t) {
+        free(J.part_f); free(J.part_t); free(fr); scene_free(&S);
+        return ORC_ENOMEM;
+    }
+    pthread_mutex_init(&J.lock, NULL);
+    pthread_t* th = malloc(sizeof(pthread_t) * n_threads);
+    worker_arg_t* args = malloc(sizeof(worker_arg_t) * n_threads);
+    for (int32_t t = 0; t < n_threads; ++t) {
+        args[t].J = &J;
+        args[t].tid = t;
+        pthread_create(&th[t], NULL, worker, &args[t]);
+    }
+    for (int32_t t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    for (int64_t j = 0; j < n_dirs; ++j)
+        for (int c = 0; c < 3; ++c) {
+            double sf = 0.0, stq = 0.0;
+            for (int64_t q = 0; q < J.n_chunks; ++q) {
+                sf += J.part_f[3 * (j * J.n_chunks + q) + c];
+                stq += J.part_t[3 * (j * J.n_chunks + q) + c];
+            }
+            force[3 * j + c] = sf;
+            torque[3 * j + c] = stq;
+        }
+    pthread_mutex_destroy(&J.lock);
+    free(th); free(args); free(J.part_f); free(J.part_t); free(fr);
+    scene_free(&S);
+    return ORC_OK;
+}
