@@ -1,0 +1,142 @@
+/*
+ * srp.h -- C ABI of libsrp: ray-grid Monte Carlo solar radiation pressure (SRP) on MI355X.
+ *
+ * The problem (paper Sec. 3.2, "Radiation Pressure Simulation"): light arrives from a single,
+ * infinitely distant direction; a spacecraft is a triangle mesh with per-face materials whose
+ * geometry depends on design parameters; the outputs are the body-frame force F(w, theta) and
+ * torque tau(w, theta) about the centre of mass (Sec. 3.2, force and torque integrals; Sec.
+ * 3.4.1 uses them in the body frame).  The estimator is a parallel ray grid per sun direction:
+ * every grid ray carries the flux through its pixel, is traced through a BVH to its closest
+ * front-facing hit, deposits photon momentum there through the light-to-force map l2f
+ * (Sec. 3.2: incident momentum minus reflected momentum, over c) with an ideal-mirror part
+ * rho_s, a Lambertian part rho_d and an absorbed part 1 - rho_s - rho_d, and is followed over
+ * up to `bounces` surface interactions.  Deposits are reduced to one FP64 force and torque per
+ * direction.
+ *
+ * Conventions
+ *   - Body frame, metres, newtons.  Triangles are counter-clockwise seen from outside; the
+ *     outward normal is normalize((v1 - v0) x (v2 - v0)); only the outward side is hit.
+ *   - Sun directions are unit vectors pointing TOWARD the Sun; light travels along -s.
+ *   - Every call returns an srp_status; 0 is success.  On failure nothing is enqueued and
+ *     srp_last_error() returns a message (thread-local, valid until the next call on the thread).
+ *   - "device" pointers are HIP device memory (e.g. torch.Tensor.data_ptr() of a cuda tensor);
+ *     they stay owned by the caller and must stay alive until the enqueued work completes.
+ *     "host" pointers are read during the call only (copied where kept).
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Launches are enqueued
+ *     on it without synchronising, except where a call says otherwise.  Device faults surface
+ *     as SRP_EDEVICE from a later call or from srp_sync().
+ *   - Random draws: Philox4x32-10 (Salmon et al., SC'11) with key = seed and counter =
+ *     (pixel, global direction index, bounce, design index); uniforms are the top 24 bits
+ *     times 2^-24.  Identical arguments give bit-identical ray sets on every call.
+ */
+#ifndef SRP_H
+#define SRP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t srp_status;
+#define SRP_OK 0
+#define SRP_EINVAL (-1)         /* bad argument */
+#define SRP_ENOMEM (-2)         /* host or device allocation failed */
+#define SRP_EDEVICE (-3)        /* a HIP runtime error */
+#define SRP_EDEGENERATE (-4)    /* unusable mesh: zero-area facet or non-finite vertex */
+#define SRP_EUNSUPPORTED (-5)   /* valid request this build cannot serve */
+
+typedef struct srp_scene_s* srp_scene;
+
+/* A hinge line in the body frame: panel vertices assigned to it rotate about (origin, axis) by
+ * the hinge angle, right-hand rule.  axis need not be normalised (it is normalised on copy). */
+typedef struct {
+    double origin[3];
+    double axis[3];
+} srp_hinge;
+
+/* Parameters of one trace.
+ *   nu, nv        grid resolution per direction (pixels along the frame's u and v axes), >= 1
+ *   bounces       surface interactions followed per path, 1..8; at the last one the expected
+ *                 reflected momentum leaves the body
+ *   jitter        1: one Philox-drawn point per pixel; 0: pixel centres
+ *   flux          solar flux Phi in W/m^2 (e.g. 1361)
+ *   seed          Philox key
+ *   dir_index_base  global index of direction 0 of this call (Philox counter word 1)
+ *   design_index  Philox counter word 3
+ *   frame_mode    0: the grid frame of each direction is derived from the mesh (Duff et al. 2017
+ *                 basis of the propagation direction, rectangle bounding the projected box,
+ *                 entry plane 0.01 L in front, L = twice the largest vertex distance from the
+ *                 vertex mean); 1: the caller passes frames (see srp_frames for the layout) */
+typedef struct {
+    int32_t nu, nv;
+    int32_t bounces;
+    int32_t jitter;
+    double flux;
+    uint64_t seed;
+    int64_t dir_index_base;
+    int32_t design_index;
+    int32_t frame_mode;
+} srp_trace_params;
+
+/* Creates a scene from a rest-pose mesh.  Host arrays, copied:
+ *   verts [n_verts][3], tris [n_tris][3] (vertex indices), vert_hinge [n_verts] (-1 rigid, k: carried
+ *   by hinge k; NULL = all rigid), hinges [n_hinges], com [3] (NULL = origin).
+ * The scene is bound to the current HIP device.  Until srp_scene_set_design is called every
+ * facet is black (rho_s = rho_d = 0) and all hinge angles are 0.
+ * Errors: SRP_EINVAL (bad index, sizes, n_tris > 2^26), SRP_EDEGENERATE (zero-area facet, NaN). */
+srp_status srp_scene_create(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                            const int32_t* vert_hinge, const srp_hinge* hinges, int32_t n_hinges,
+                            const double* com, srp_scene* out);
+
+/* Applies a design (paper Sec. 3.1: the design maps to a mesh with per-face materials):
+ *   hinge_angles host [n_hinges] radians (NULL = keep the current angles); the panel vertices
+ *   are rotated in FP64 and the BVH is rebuilt on the host when the angles change;
+ *   rho_s, rho_d device float [n_tris] (original facet order), 0 <= rho, rho_s + rho_d <= 1;
+ *   p_spec device float [n_tris] or NULL: frozen probability of sampling the specular event at
+ *   each facet.  NULL selects rho_s/(rho_s + rho_d) clamped to [0.01, 0.99] when both are
+ *   positive, else 1 (mirror only) or 0.
+ * Synchronises `stream` once to validate the materials (SRP_EINVAL if out of range). */
+srp_status srp_scene_set_design(srp_scene scene, const double* hinge_angles, const float* rho_s,
+                                const float* rho_d, const float* p_spec, void* stream);
+
+/* Host copy of the current (hinge-rotated) vertices, [n_verts][3]. */
+srp_status srp_scene_get_vertices(srp_scene scene, double* verts_out, int64_t n_verts);
+
+/* BVH statistics: number of BVH nodes, tree depth, triangles (host ints, any may be NULL). */
+srp_status srp_scene_info(srp_scene scene, int32_t* n_nodes, int32_t* depth, int32_t* n_tris);
+
+/* Grid frames for D directions, device double [D][12]: u[3], v[3], o0[3], du, dv, 0; the ray of
+ * pixel (i, k) with in-pixel offsets (a, b) starts at o0 + (i+a) du u + (k+b) dv v and travels
+ * along -s.  sun_dirs device double [D][3]. */
+srp_status srp_frames(srp_scene scene, const double* sun_dirs, int64_t D, int32_t nu, int32_t nv, double* frames,
+                      void* stream);
+
+/* Forward trace.  sun_dirs device double [D][3] (unit, toward the Sun), frames device double
+ * [D][12] when params->frame_mode == 1 (else ignored, may be NULL); force device double [D][3]
+ * and torque device double [D][3] (torque may be NULL) are overwritten with the per-direction
+ * sums.  The sum is deterministic: FP32 per ray and per wavefront, FP64 per workgroup and a
+ * fixed-order FP64 sum per direction. */
+srp_status srp_trace(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
+                     const double* frames, double* force, double* torque, void* stream);
+
+/* Per-ray records of the same estimator for an explicit pixel list (parity and debugging).
+ *   pix device int64 [n_pix] pixel ids (i + k*nu), or NULL for all nu*nv pixels in order;
+ *   hit_prim device int32 [D][n_pix][bounces]: ORIGINAL index of the facet hit at each
+ *   interaction, -1 after the path ended; ray_force device float [D][n_pix][3] or NULL. */
+srp_status srp_trace_records(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
+                             const double* frames, const int64_t* pix, int64_t n_pix, int32_t* hit_prim,
+                             float* ray_force, void* stream);
+
+srp_status srp_scene_destroy(srp_scene scene);
+
+/* Waits for `stream` and reports any pending device error as SRP_EDEVICE. */
+srp_status srp_sync(void* stream);
+
+const char* srp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRP_H */

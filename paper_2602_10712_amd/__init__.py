@@ -1,0 +1,21 @@
+"""MI355X-native ray-grid solar radiation pressure (SRP).
+
+The compute path is libsrp.so (hand-written HIP kernels for gfx950 behind the C ABI declared in
+include/srp.h); the Python modules only marshal arguments to it.  The first use of any binding
+loads the library and raises ImportError if it has not been built
+(`python -m paper_2602_10712_amd`) -- there is no CPU fallback.
+"""
+import importlib
+
+_BINDING_NAMES = {"SRPError", "Scene", "TraceParams", "lib_path", "srp_frames", "srp_scene_create",
+                  "srp_scene_destroy", "srp_scene_get_vertices", "srp_scene_info", "srp_scene_set_design",
+                  "srp_sync", "srp_trace", "srp_trace_records"}
+
+
+def __getattr__(name):
+    if name in _BINDING_NAMES:
+        return getattr(importlib.import_module("._binding", __name__), name)
+    raise AttributeError(name)
+
+
+__all__ = sorted(_BINDING_NAMES)

@@ -1,0 +1,242 @@
+"""ctypes binding of libsrp (include/srp.h): argument marshalling only.
+
+Functions keep the C names and take torch tensors for device arrays (their data_ptr() is passed)
+and numpy arrays for host arrays.  `stream` defaults to torch's current stream on the scene's
+device.  Every non-zero status raises SRPError with srp_last_error().
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libsrp.so")
+
+if not os.path.exists(_LIB):
+    raise ImportError(f"{_LIB} is not built; run `python -m paper_2602_10712_amd.build` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(_LIB)
+
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+I64 = ctypes.c_int64
+
+
+class srp_hinge(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("axis", ctypes.c_double * 3)]
+
+
+class TraceParams(ctypes.Structure):
+    _fields_ = [("nu", I32), ("nv", I32), ("bounces", I32), ("jitter", I32), ("flux", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("dir_index_base", I64), ("design_index", I32), ("frame_mode", I32)]
+
+    def __init__(self, nu=256, nv=256, bounces=1, jitter=1, flux=1361.0, seed=0, dir_index_base=0, design_index=0,
+                 frame_mode=0):
+        super().__init__(int(nu), int(nv), int(bounces), int(bool(jitter)), float(flux), int(seed),
+                         int(dir_index_base), int(design_index), int(frame_mode))
+
+
+_sigs = {
+    "srp_scene_create": [P, I64, P, I64, P, P, I32, P, ctypes.POINTER(P)],
+    "srp_scene_set_design": [P, P, P, P, P, P],
+    "srp_scene_get_vertices": [P, P, I64],
+    "srp_scene_info": [P, P, P, P],
+    "srp_frames": [P, P, I64, I32, I32, P, P],
+    "srp_trace": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P],
+    "srp_trace_records": [P, P, I64, ctypes.POINTER(TraceParams), P, P, I64, P, P, P],
+    "srp_scene_destroy": [P],
+    "srp_sync": [P],
+}
+for _name, _args in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = I32
+_lib.srp_last_error.argtypes = []
+_lib.srp_last_error.restype = ctypes.c_char_p
+
+
+class SRPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libsrp status {status}: {msg}")
+        self.status = status
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def _check(st: int) -> None:
+    if st != 0:
+        raise SRPError(st, _lib.srp_last_error().decode())
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _hptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dtype_check(t, dtype, name):
+    if t is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+# ------------------------------------------------------------------------------------------------
+# C functions, same names
+# ------------------------------------------------------------------------------------------------
+def srp_scene_create(verts, tris, vert_hinge=None, hinge_origin=None, hinge_axis=None, com=None):
+    v = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    vh = None if vert_hinge is None else np.ascontiguousarray(vert_hinge, dtype=np.int32)
+    n_h = 0 if hinge_origin is None else len(hinge_origin)
+    harr = None
+    if n_h:
+        harr = (srp_hinge * n_h)()
+        for k in range(n_h):
+            harr[k].origin[:] = [float(x) for x in hinge_origin[k]]
+            harr[k].axis[:] = [float(x) for x in hinge_axis[k]]
+    c = None if com is None else np.ascontiguousarray(com, dtype=np.float64)
+    out = P()
+    _check(_lib.srp_scene_create(_hptr(v), len(v), _hptr(t), len(t), _hptr(vh),
+                                 ctypes.cast(harr, P) if harr is not None else None, n_h, _hptr(c),
+                                 ctypes.byref(out)))
+    return out
+
+
+def srp_scene_set_design(scene, hinge_angles, rho_s, rho_d, p_spec=None, stream=None):
+    import torch
+    _dtype_check(rho_s, torch.float32, "rho_s")
+    _dtype_check(rho_d, torch.float32, "rho_d")
+    _dtype_check(p_spec, torch.float32, "p_spec")
+    ang = None if hinge_angles is None else np.ascontiguousarray(hinge_angles, dtype=np.float64)
+    _check(_lib.srp_scene_set_design(scene, _hptr(ang), _dptr(rho_s), _dptr(rho_d), _dptr(p_spec), _stream(stream)))
+
+
+def srp_scene_get_vertices(scene, n_verts):
+    out = np.zeros((n_verts, 3))
+    _check(_lib.srp_scene_get_vertices(scene, _hptr(out), n_verts))
+    return out
+
+
+def srp_scene_info(scene):
+    a, b, c = I32(), I32(), I32()
+    _check(_lib.srp_scene_info(scene, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return {"n_nodes": a.value, "depth": b.value, "n_tris": c.value}
+
+
+def srp_frames(scene, sun_dirs, nu, nv, frames, stream=None):
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(frames, torch.float64, "frames")
+    _check(_lib.srp_frames(scene, _dptr(sun_dirs), sun_dirs.shape[0], nu, nv, _dptr(frames), _stream(stream)))
+
+
+def srp_trace(scene, sun_dirs, params: TraceParams, force, torque=None, frames=None, stream=None):
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(force, torch.float64, "force")
+    _dtype_check(torque, torch.float64, "torque")
+    _dtype_check(frames, torch.float64, "frames")
+    _check(_lib.srp_trace(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params), _dptr(frames),
+                          _dptr(force), _dptr(torque), _stream(stream)))
+
+
+def srp_trace_records(scene, sun_dirs, params: TraceParams, hit_prim, ray_force=None, pix=None, frames=None,
+                      stream=None):
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(hit_prim, torch.int32, "hit_prim")
+    _dtype_check(ray_force, torch.float32, "ray_force")
+    _dtype_check(pix, torch.int64, "pix")
+    n_pix = 0 if pix is None else pix.shape[0]
+    _check(_lib.srp_trace_records(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params), _dptr(frames),
+                                  _dptr(pix), n_pix, _dptr(hit_prim), _dptr(ray_force), _stream(stream)))
+
+
+def srp_scene_destroy(scene):
+    _check(_lib.srp_scene_destroy(scene))
+
+
+def srp_sync(stream=None):
+    _check(_lib.srp_sync(_stream(stream)))
+
+
+# ------------------------------------------------------------------------------------------------
+# convenience object over the same calls
+# ------------------------------------------------------------------------------------------------
+class Scene:
+    """A mesh on the GPU: srp_scene_create + srp_scene_set_design + traces."""
+
+    def __init__(self, verts, tris, vert_hinge=None, hinge_origin=None, hinge_axis=None, com=None):
+        self.n_verts = int(np.asarray(verts).reshape(-1, 3).shape[0])
+        self.n_tris = int(np.asarray(tris).reshape(-1, 3).shape[0])
+        self.n_hinges = 0 if hinge_origin is None else len(hinge_origin)
+        self.handle = srp_scene_create(verts, tris, vert_hinge, hinge_origin, hinge_axis, com)
+
+    @classmethod
+    def from_mesh(cls, mesh):
+        return cls(mesh.verts, mesh.tris, mesh.vert_hinge, mesh.hinge_origin if mesh.n_hinges else None,
+                   mesh.hinge_axis if mesh.n_hinges else None, mesh.com)
+
+    def set_design(self, rho_s, rho_d, hinge_angles=None, p_spec=None, stream=None):
+        import torch
+        dev = torch.device("cuda")
+        as_dev = lambda x: None if x is None else torch.as_tensor(x, dtype=torch.float32, device=dev).contiguous()
+        srp_scene_set_design(self.handle, hinge_angles, as_dev(rho_s), as_dev(rho_d), as_dev(p_spec), stream)
+
+    def vertices(self):
+        return srp_scene_get_vertices(self.handle, self.n_verts)
+
+    def info(self):
+        return srp_scene_info(self.handle)
+
+    def trace(self, sun_dirs, params: TraceParams, frames=None, stream=None):
+        import torch
+        sd = torch.as_tensor(sun_dirs, dtype=torch.float64, device="cuda").contiguous()
+        D = sd.shape[0]
+        F = torch.empty((D, 3), dtype=torch.float64, device="cuda")
+        T = torch.empty((D, 3), dtype=torch.float64, device="cuda")
+        fr = None if frames is None else torch.as_tensor(frames, dtype=torch.float64, device="cuda").contiguous()
+        srp_trace(self.handle, sd, params, F, T, fr, stream)
+        return F, T
+
+    def records(self, sun_dirs, params: TraceParams, pix=None, frames=None, stream=None):
+        import torch
+        sd = torch.as_tensor(sun_dirs, dtype=torch.float64, device="cuda").contiguous()
+        D = sd.shape[0]
+        n_pix = params.nu * params.nv if pix is None else len(pix)
+        hp = torch.empty((D, n_pix, params.bounces), dtype=torch.int32, device="cuda")
+        rf = torch.empty((D, n_pix, 3), dtype=torch.float32, device="cuda")
+        px = None if pix is None else torch.as_tensor(np.asarray(pix), dtype=torch.int64, device="cuda").contiguous()
+        fr = None if frames is None else torch.as_tensor(frames, dtype=torch.float64, device="cuda").contiguous()
+        srp_trace_records(self.handle, sd, params, hp, rf, px, fr, stream)
+        return hp, rf
+
+    def close(self):
+        if getattr(self, "handle", None):
+            srp_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

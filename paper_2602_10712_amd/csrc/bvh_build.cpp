@@ -1,0 +1,233 @@
+// Host BVH builder: binned surface-area heuristic (Wald, "On fast Construction of SAH-based
+// Bounding Volume Hierarchies", IEEE RT 2007), emitted as a two-wide tree whose nodes carry both
+// child boxes (the layout of Aila & Laine, "Understanding the Efficiency of Ray Traversal on
+// GPUs", HPG 2009), so one 64-byte fetch feeds two box tests.
+#include "bvh_build.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+namespace srp {
+namespace {
+
+constexpr int kBins = 16;
+constexpr int kSahDepthCap = 36;  // deeper than this: object-median splits only (bounded depth)
+constexpr double kCostTraverse = 1.0;
+constexpr double kCostTriangle = 1.0;
+
+struct Box {
+    double lo[3], hi[3];
+    void reset()
+    {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::numeric_limits<double>::infinity();
+            hi[a] = -std::numeric_limits<double>::infinity();
+        }
+    }
+    void grow(const Box& b)
+    {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], b.lo[a]);
+            hi[a] = std::max(hi[a], b.hi[a]);
+        }
+    }
+    void grow(const double p[3])
+    {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], p[a]);
+            hi[a] = std::max(hi[a], p[a]);
+        }
+    }
+    double area() const
+    {
+        double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+        if (!(dx >= 0) || !(dy >= 0) || !(dz >= 0)) return 0.0;
+        return 2.0 * (dx * dy + dy * dz + dz * dx);
+    }
+};
+
+struct Prim {
+    Box box;
+    double c[3];
+};
+
+struct Ref {
+    int32_t code;
+    Box box;
+};
+
+struct Builder {
+    std::vector<Prim> prims;
+    std::vector<int32_t> idx;
+    std::vector<BvhNode> nodes;
+    double pad = 0.0;
+    int max_depth = 0;
+
+    static float down(double x) { return std::nextafter(static_cast<float>(x), -std::numeric_limits<float>::infinity()); }
+    static float up(double x) { return std::nextafter(static_cast<float>(x), std::numeric_limits<float>::infinity()); }
+
+    Ref make_leaf(int32_t begin, int32_t end, const Box& b)
+    {
+        Ref r;
+        r.code = ~((begin << 3) | (end - begin));
+        r.box = b;
+        return r;
+    }
+
+    void write_child(BvhNode& n, int slot, const Ref& r)
+    {
+        float lx = down(r.box.lo[0] - pad), hx = up(r.box.hi[0] + pad);
+        float ly = down(r.box.lo[1] - pad), hy = up(r.box.hi[1] + pad);
+        float lz = down(r.box.lo[2] - pad), hz = up(r.box.hi[2] + pad);
+        if (slot == 0) {
+            n.f[0] = make_float4(lx, hx, ly, hy);
+            n.f[2].x = lz;
+            n.f[2].y = hz;
+        } else {
+            n.f[1] = make_float4(lx, hx, ly, hy);
+            n.f[2].z = lz;
+            n.f[2].w = hz;
+        }
+        int32_t* ints = reinterpret_cast<int32_t*>(&n.f[3]);
+        ints[slot] = r.code;
+    }
+
+    Ref build(int32_t begin, int32_t end, int depth)
+    {
+        max_depth = std::max(max_depth, depth);
+        Box bounds, cb;
+        bounds.reset();
+        cb.reset();
+        for (int32_t i = begin; i < end; ++i) {
+            bounds.grow(prims[idx[i]].box);
+            cb.grow(prims[idx[i]].c);
+        }
+        const int32_t n = end - begin;
+        if (n <= 2) return make_leaf(begin, end, bounds);
+
+        int32_t mid = -1;
+        if (depth < kSahDepthCap) {
+            double best = std::numeric_limits<double>::infinity();
+            int best_axis = -1, best_bin = -1;
+            for (int a = 0; a < 3; ++a) {
+                double ext = cb.hi[a] - cb.lo[a];
+                if (!(ext > 0.0)) continue;
+                int cnt[kBins] = {};
+                Box bb[kBins];
+                for (auto& b : bb) b.reset();
+                const double scale = kBins / ext;
+                for (int32_t i = begin; i < end; ++i) {
+                    const Prim& p = prims[idx[i]];
+                    int k = std::min(kBins - 1, static_cast<int>((p.c[a] - cb.lo[a]) * scale));
+                    ++cnt[k];
+                    bb[k].grow(p.box);
+                }
+                double rarea[kBins];
+                int rcnt[kBins];
+                Box acc;
+                acc.reset();
+                int c = 0;
+                for (int k = kBins - 1; k > 0; --k) {
+                    acc.grow(bb[k]);
+                    c += cnt[k];
+                    rarea[k] = acc.area();
+                    rcnt[k] = c;
+                }
+                acc.reset();
+                c = 0;
+                for (int k = 0; k < kBins - 1; ++k) {
+                    acc.grow(bb[k]);
+                    c += cnt[k];
+                    if (c == 0 || rcnt[k + 1] == 0) continue;
+                    double cost = acc.area() * c + rarea[k + 1] * rcnt[k + 1];
+                    if (cost < best) {
+                        best = cost;
+                        best_axis = a;
+                        best_bin = k;
+                    }
+                }
+            }
+            const double parea = bounds.area();
+            const double split_cost =
+                best_axis >= 0 && parea > 0 ? kCostTraverse + kCostTriangle * best / parea : std::numeric_limits<double>::infinity();
+            if (n <= 4 && kCostTriangle * n <= split_cost) return make_leaf(begin, end, bounds);
+            if (best_axis >= 0) {
+                const double ext = cb.hi[best_axis] - cb.lo[best_axis];
+                const double scale = kBins / ext;
+                auto it = std::partition(idx.begin() + begin, idx.begin() + end, [&](int32_t t) {
+                    int k = std::min(kBins - 1, static_cast<int>((prims[t].c[best_axis] - cb.lo[best_axis]) * scale));
+                    return k <= best_bin;
+                });
+                mid = static_cast<int32_t>(it - idx.begin());
+                if (mid == begin || mid == end) mid = -1;
+            }
+        }
+        if (mid < 0) {
+            if (n <= kLeafMax && depth >= kSahDepthCap) return make_leaf(begin, end, bounds);
+            // object median along the widest centroid axis
+            int a = 0;
+            double ext = -1.0;
+            for (int k = 0; k < 3; ++k)
+                if (cb.hi[k] - cb.lo[k] > ext) {
+                    ext = cb.hi[k] - cb.lo[k];
+                    a = k;
+                }
+            mid = begin + n / 2;
+            std::nth_element(idx.begin() + begin, idx.begin() + mid, idx.begin() + end,
+                             [&](int32_t x, int32_t y) { return prims[x].c[a] < prims[y].c[a]; });
+        }
+        const int32_t me = static_cast<int32_t>(nodes.size());
+        nodes.push_back(BvhNode{});
+        Ref l = build(begin, mid, depth + 1);
+        Ref r = build(mid, end, depth + 1);
+        write_child(nodes[me], 0, l);
+        write_child(nodes[me], 1, r);
+        Ref out;
+        out.code = me;
+        out.box = bounds;
+        return out;
+    }
+};
+
+}  // namespace
+
+BvhBuildResult build_bvh(const double* verts, const int32_t* tris, int64_t n_tris, double pad)
+{
+    Builder b;
+    b.pad = pad;
+    b.prims.resize(n_tris);
+    b.idx.resize(n_tris);
+    for (int64_t f = 0; f < n_tris; ++f) {
+        Prim& p = b.prims[f];
+        p.box.reset();
+        for (int c = 0; c < 3; ++c) p.box.grow(verts + 3 * static_cast<int64_t>(tris[3 * f + c]));
+        for (int a = 0; a < 3; ++a) p.c[a] = 0.5 * (p.box.lo[a] + p.box.hi[a]);
+        b.idx[f] = static_cast<int32_t>(f);
+    }
+    b.nodes.reserve(static_cast<size_t>(n_tris));
+    Ref root = b.build(0, static_cast<int32_t>(n_tris), 0);
+    BvhBuildResult res;
+    if (root.code < 0) {
+        // a single leaf: wrap it in an inner root whose second child is an empty leaf placed at a
+        // point no ray can reach
+        BvhNode n{};
+        b.write_child(n, 0, root);
+        Ref empty;
+        empty.code = ~0;
+        for (int a = 0; a < 3; ++a) empty.box.lo[a] = empty.box.hi[a] = 1e30;
+        double keep = b.pad;
+        b.pad = 0.0;
+        b.write_child(n, 1, empty);
+        b.pad = keep;
+        b.nodes.insert(b.nodes.begin(), n);
+        b.max_depth += 1;
+    }
+    res.nodes = std::move(b.nodes);
+    res.perm = std::move(b.idx);
+    res.depth = b.max_depth;
+    return res;
+}
+
+}  // namespace srp

@@ -1,0 +1,438 @@
+// libsrp host side: C ABI (include/srp.h), scene lifecycle, design application (hinge rotation
+// in FP64 + host BVH rebuild), workspace management and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/srp.h"
+#include "bvh_build.h"
+#include "srp_internal.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+srp_status fail(srp_status st, const std::string& msg)
+{
+    g_error = msg;
+    return st;
+}
+
+#define SRP_HIP(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(SRP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+hipError_t ensure(T*& ptr, size_t& cap, size_t n)
+{
+    if (n <= cap && ptr) return hipSuccess;
+    if (ptr) {
+        hipError_t e = hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&ptr), bytes);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return e;
+    }
+    cap = std::max<size_t>(n, 1);
+    return hipSuccess;
+}
+
+}  // namespace
+
+struct srp_scene_s {
+    int device = 0;
+    int64_t n_verts = 0, n_tris = 0;
+    int32_t n_hinges = 0;
+    std::vector<double> rest, cur;
+    std::vector<int32_t> tris, vhinge;
+    std::vector<srp_hinge> hinges;
+    std::vector<double> angles;
+    double com[3] = {0, 0, 0};
+    double lo[3], hi[3], L = 0;
+    int32_t n_nodes = 0, depth = 0;
+    std::vector<int32_t> perm;
+    srp::BvhNode* d_nodes = nullptr;
+    size_t nodes_cap = 0;
+    srp::TriRec* d_tris = nullptr;
+    size_t tris_cap = 0;
+    float4* d_mat = nullptr;
+    size_t mat_cap = 0;
+    int32_t* d_perm = nullptr;
+    size_t perm_cap = 0;
+    int32_t* d_flag = nullptr;
+    size_t flag_cap = 0;
+    srp::DevFrame* d_frames = nullptr;
+    size_t frames_cap = 0;
+    double* d_partials = nullptr;
+    size_t partials_cap = 0;
+};
+
+namespace {
+
+void rotate_hinges(srp_scene_s* s)
+{
+    s->cur = s->rest;
+    for (int32_t k = 0; k < s->n_hinges; ++k) {
+        const double ang = s->angles[k];
+        if (ang == 0.0) continue;
+        const double* o = s->hinges[k].origin;
+        const double* ax = s->hinges[k].axis;
+        const double c = std::cos(ang), sn = std::sin(ang);
+        for (int64_t i = 0; i < s->n_verts; ++i) {
+            if (s->vhinge[i] != k) continue;
+            double p[3] = {s->rest[3 * i] - o[0], s->rest[3 * i + 1] - o[1], s->rest[3 * i + 2] - o[2]};
+            const double kd = ax[0] * p[0] + ax[1] * p[1] + ax[2] * p[2];
+            const double kx[3] = {ax[1] * p[2] - ax[2] * p[1], ax[2] * p[0] - ax[0] * p[2], ax[0] * p[1] - ax[1] * p[0]};
+            for (int a = 0; a < 3; ++a) s->cur[3 * i + a] = o[a] + p[a] * c + kx[a] * sn + ax[a] * kd * (1.0 - c);
+        }
+    }
+}
+
+// Scene size L: twice the largest distance of a vertex from the vertex mean (rotation-invariant).
+double scene_size(const std::vector<double>& v, int64_t n)
+{
+    double m[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) m[a] += v[3 * i + a];
+    for (int a = 0; a < 3; ++a) m[a] /= static_cast<double>(n);
+    double r2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double q[3] = {v[3 * i] - m[0], v[3 * i + 1] - m[1], v[3 * i + 2] - m[2]};
+        r2 = std::max(r2, q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    }
+    return 2.0 * std::sqrt(r2);
+}
+
+// Rebuilds the BVH and the triangle records from the current vertices and uploads them.
+srp_status rebuild(srp_scene_s* s, hipStream_t stream)
+{
+    const auto& V = s->cur;
+    for (int a = 0; a < 3; ++a) {
+        s->lo[a] = INFINITY;
+        s->hi[a] = -INFINITY;
+    }
+    for (int64_t i = 0; i < s->n_verts; ++i)
+        for (int a = 0; a < 3; ++a) {
+            s->lo[a] = std::min(s->lo[a], V[3 * i + a]);
+            s->hi[a] = std::max(s->hi[a], V[3 * i + a]);
+        }
+    s->L = scene_size(V, s->n_verts);
+    srp::BvhBuildResult bvh = srp::build_bvh(V.data(), s->tris.data(), s->n_tris, 1e-6 * s->L);
+    if (bvh.depth >= srp::kStackDepth - 1) return fail(SRP_EUNSUPPORTED, "BVH deeper than the traversal stack");
+    s->n_nodes = static_cast<int32_t>(bvh.nodes.size());
+    s->depth = bvh.depth;
+    s->perm = std::move(bvh.perm);
+    std::vector<srp::TriRec> recs(s->n_tris);
+    for (int64_t p = 0; p < s->n_tris; ++p) {
+        const int32_t f = s->perm[p];
+        const double* a = &V[3 * static_cast<int64_t>(s->tris[3 * f])];
+        const double* b = &V[3 * static_cast<int64_t>(s->tris[3 * f + 1])];
+        const double* c = &V[3 * static_cast<int64_t>(s->tris[3 * f + 2])];
+        double e1[3], e2[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = b[k] - a[k];
+            e2[k] = c[k] - a[k];
+        }
+        double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (!(len > 0.0) || !std::isfinite(len)) return fail(SRP_EDEGENERATE, "zero-area or non-finite facet");
+        for (int k = 0; k < 3; ++k) n[k] /= len;
+        srp::TriRec& r = recs[p];
+        int32_t fid = f;
+        float fid_bits;
+        std::memcpy(&fid_bits, &fid, 4);
+        r.f[0] = make_float4(static_cast<float>(a[0]), static_cast<float>(a[1]), static_cast<float>(a[2]), fid_bits);
+        r.f[1] = make_float4(static_cast<float>(e1[0]), static_cast<float>(e1[1]), static_cast<float>(e1[2]),
+                             static_cast<float>(n[0]));
+        r.f[2] = make_float4(static_cast<float>(e2[0]), static_cast<float>(e2[1]), static_cast<float>(e2[2]),
+                             static_cast<float>(n[1]));
+        r.f[3] = make_float4(static_cast<float>(n[2]), 0.0f, 0.0f, 0.0f);
+    }
+    SRP_HIP(ensure(s->d_nodes, s->nodes_cap, bvh.nodes.size()));
+    SRP_HIP(ensure(s->d_tris, s->tris_cap, static_cast<size_t>(s->n_tris)));
+    SRP_HIP(ensure(s->d_perm, s->perm_cap, static_cast<size_t>(s->n_tris)));
+    SRP_HIP(hipMemcpyAsync(s->d_nodes, bvh.nodes.data(), bvh.nodes.size() * sizeof(srp::BvhNode),
+                           hipMemcpyHostToDevice, stream));
+    SRP_HIP(hipMemcpyAsync(s->d_tris, recs.data(), recs.size() * sizeof(srp::TriRec), hipMemcpyHostToDevice, stream));
+    SRP_HIP(hipMemcpyAsync(s->d_perm, s->perm.data(), s->perm.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           stream));
+    SRP_HIP(hipStreamSynchronize(stream));
+    return SRP_OK;
+}
+
+srp_status check_params(const srp_trace_params* p)
+{
+    if (!p) return fail(SRP_EINVAL, "params is NULL");
+    if (p->nu < 1 || p->nv < 1) return fail(SRP_EINVAL, "nu and nv must be >= 1");
+    if (static_cast<int64_t>(p->nu) * p->nv > (int64_t(1) << 31)) return fail(SRP_EINVAL, "nu * nv exceeds 2^31");
+    if (p->bounces < 1 || p->bounces > srp::kMaxBounces) return fail(SRP_EINVAL, "bounces must be in 1..8");
+    if (!(p->flux >= 0.0) || !std::isfinite(p->flux)) return fail(SRP_EINVAL, "flux must be finite and >= 0");
+    if (p->frame_mode != 0 && p->frame_mode != 1) return fail(SRP_EINVAL, "frame_mode must be 0 or 1");
+    if (p->dir_index_base < 0) return fail(SRP_EINVAL, "dir_index_base must be >= 0");
+    return SRP_OK;
+}
+
+srp_status bind_device(const srp_scene_s* s)
+{
+    int cur = -1;
+    SRP_HIP(hipGetDevice(&cur));
+    if (cur != s->device) SRP_HIP(hipSetDevice(s->device));
+    return SRP_OK;
+}
+
+// Frames + trace launch shared by srp_trace and srp_trace_records.
+srp_status enqueue_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                         const double* frames, bool records, const int64_t* pix, int64_t n_pix, int32_t* rec_hit,
+                         float* rec_force, hipStream_t stream, int32_t* bpd_out)
+{
+    SRP_HIP(ensure(s->d_frames, s->frames_cap, static_cast<size_t>(D)));
+    SRP_HIP(srp::launch_frames(sun_dirs, D, s->lo, s->hi, s->L, p->nu, p->nv, p->flux,
+                               p->frame_mode == 1 ? frames : nullptr, nullptr, s->d_frames, stream));
+    srp::TraceArgs a{};
+    a.nodes = s->d_nodes;
+    a.tris = s->d_tris;
+    a.mat = s->d_mat;
+    a.frames = s->d_frames;
+    a.D = D;
+    a.nu = p->nu;
+    a.nv = p->nv;
+    a.bounces = p->bounces;
+    a.jitter = p->jitter ? 1 : 0;
+    a.seed_lo = static_cast<uint32_t>(p->seed);
+    a.seed_hi = static_cast<uint32_t>(p->seed >> 32);
+    a.dir_index_base = p->dir_index_base;
+    a.design_index = static_cast<uint32_t>(p->design_index);
+    for (int k = 0; k < 3; ++k) a.com[k] = static_cast<float>(s->com[k]);
+    a.eps = static_cast<float>(1e-5 * s->L);
+    a.tiles_x = (p->nu + srp::kTileW - 1) / srp::kTileW;
+    a.tiles_y = (p->nv + srp::kTileH - 1) / srp::kTileH;
+    if (records) {
+        a.pix = pix;
+        a.n_pix = pix ? n_pix : static_cast<int64_t>(p->nu) * p->nv;
+        a.tiles_per_dir = (a.n_pix + 63) / 64;
+        a.rec_hit = rec_hit;
+        a.rec_force = rec_force;
+    } else {
+        a.tiles_per_dir = static_cast<int64_t>(a.tiles_x) * a.tiles_y;
+    }
+    // enough workgroups to fill 256 CUs many times over, few enough partials per direction
+    const int64_t total_tiles = a.tiles_per_dir * D;
+    int64_t tpw = total_tiles / (int64_t(srp::kWaves) * 8192);
+    tpw = std::max<int64_t>(1, std::min<int64_t>(16, tpw));
+    a.tiles_per_wave = static_cast<int32_t>(tpw);
+    const int64_t per_block = tpw * srp::kWaves;
+    const int64_t bpd = std::max<int64_t>(1, (a.tiles_per_dir + per_block - 1) / per_block);
+    if (bpd * D > 0x7fffffffLL) return fail(SRP_EINVAL, "trace too large for one launch");
+    a.blocks_per_dir = static_cast<int32_t>(bpd);
+    SRP_HIP(ensure(s->d_partials, s->partials_cap, static_cast<size_t>(bpd * D * 6)));
+    a.partials = s->d_partials;
+    SRP_HIP(srp::launch_trace(a, records, stream));
+    *bpd_out = a.blocks_per_dir;
+    return SRP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* srp_last_error(void) { return g_error.c_str(); }
+
+srp_status srp_sync(void* stream)
+{
+    SRP_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    SRP_HIP(hipGetLastError());
+    return SRP_OK;
+}
+
+srp_status srp_scene_create(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                            const int32_t* vert_hinge, const srp_hinge* hinges, int32_t n_hinges, const double* com,
+                            srp_scene* out)
+{
+    if (!out) return fail(SRP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!verts || n_verts < 3 || !tris || n_tris < 1) return fail(SRP_EINVAL, "empty mesh");
+    if (n_tris > (int64_t(1) << 26)) return fail(SRP_EINVAL, "more than 2^26 triangles");
+    if (n_hinges < 0 || (n_hinges > 0 && !hinges)) return fail(SRP_EINVAL, "bad hinges");
+    for (int64_t i = 0; i < 3 * n_verts; ++i)
+        if (!std::isfinite(verts[i])) return fail(SRP_EDEGENERATE, "non-finite vertex");
+    for (int64_t i = 0; i < 3 * n_tris; ++i)
+        if (tris[i] < 0 || tris[i] >= n_verts) return fail(SRP_EINVAL, "triangle index out of range");
+    if (vert_hinge)
+        for (int64_t i = 0; i < n_verts; ++i)
+            if (vert_hinge[i] < -1 || vert_hinge[i] >= n_hinges) return fail(SRP_EINVAL, "vert_hinge out of range");
+    srp_scene_s* s = new (std::nothrow) srp_scene_s();
+    if (!s) return fail(SRP_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(SRP_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    s->n_verts = n_verts;
+    s->n_tris = n_tris;
+    s->n_hinges = n_hinges;
+    s->rest.assign(verts, verts + 3 * n_verts);
+    s->tris.assign(tris, tris + 3 * n_tris);
+    s->vhinge.assign(n_verts, -1);
+    if (vert_hinge) s->vhinge.assign(vert_hinge, vert_hinge + n_verts);
+    for (int32_t k = 0; k < n_hinges; ++k) {
+        srp_hinge h = hinges[k];
+        const double len = std::sqrt(h.axis[0] * h.axis[0] + h.axis[1] * h.axis[1] + h.axis[2] * h.axis[2]);
+        if (!(len > 0.0) || !std::isfinite(len)) {
+            delete s;
+            return fail(SRP_EINVAL, "hinge axis must be non-zero");
+        }
+        for (int a = 0; a < 3; ++a) h.axis[a] /= len;
+        s->hinges.push_back(h);
+    }
+    s->angles.assign(n_hinges, 0.0);
+    if (com)
+        for (int a = 0; a < 3; ++a) s->com[a] = com[a];
+    rotate_hinges(s);
+    srp_status st = rebuild(s, nullptr);
+    if (st != SRP_OK) {
+        srp_scene_destroy(s);
+        return st;
+    }
+    e = ensure(s->d_mat, s->mat_cap, static_cast<size_t>(n_tris));
+    if (e == hipSuccess) e = hipMemset(s->d_mat, 0, sizeof(float4) * n_tris);
+    if (e == hipSuccess) e = ensure(s->d_flag, s->flag_cap, 1);
+    if (e != hipSuccess) {
+        srp_scene_destroy(s);
+        return fail(SRP_EDEVICE, std::string("scene buffers: ") + hipGetErrorString(e));
+    }
+    *out = s;
+    return SRP_OK;
+}
+
+srp_status srp_scene_set_design(srp_scene s, const double* hinge_angles, const float* rho_s, const float* rho_d,
+                                const float* p_spec, void* stream_)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    if (!rho_s || !rho_d) return fail(SRP_EINVAL, "rho_s and rho_d are required");
+    srp_status st = bind_device(s);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if (hinge_angles) {
+        bool changed = false;
+        for (int32_t k = 0; k < s->n_hinges; ++k) {
+            if (!std::isfinite(hinge_angles[k])) return fail(SRP_EINVAL, "non-finite hinge angle");
+            if (hinge_angles[k] != s->angles[k]) changed = true;
+        }
+        if (changed) {
+            SRP_HIP(hipStreamSynchronize(stream));  // kernels in flight may still read the old BVH
+            s->angles.assign(hinge_angles, hinge_angles + s->n_hinges);
+            rotate_hinges(s);
+            st = rebuild(s, stream);
+            if (st != SRP_OK) return st;
+        }
+    }
+    SRP_HIP(hipMemsetAsync(s->d_flag, 0, sizeof(int32_t), stream));
+    SRP_HIP(srp::launch_pack_materials(rho_s, rho_d, p_spec, s->d_perm, s->n_tris, s->d_mat, s->d_flag, stream));
+    int32_t flag = 0;
+    SRP_HIP(hipMemcpyAsync(&flag, s->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    SRP_HIP(hipStreamSynchronize(stream));
+    if (flag & 1) return fail(SRP_EINVAL, "reflectances must satisfy rho_s >= 0, rho_d >= 0, rho_s + rho_d <= 1");
+    if (flag & 2) return fail(SRP_EINVAL, "p_spec must lie in [0, 1]");
+    return SRP_OK;
+}
+
+srp_status srp_scene_get_vertices(srp_scene s, double* out, int64_t n_verts)
+{
+    if (!s || !out) return fail(SRP_EINVAL, "NULL argument");
+    if (n_verts != s->n_verts) return fail(SRP_EINVAL, "n_verts does not match the scene");
+    std::memcpy(out, s->cur.data(), sizeof(double) * 3 * n_verts);
+    return SRP_OK;
+}
+
+srp_status srp_scene_info(srp_scene s, int32_t* n_nodes, int32_t* depth, int32_t* n_tris)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    if (n_nodes) *n_nodes = s->n_nodes;
+    if (depth) *depth = s->depth;
+    if (n_tris) *n_tris = static_cast<int32_t>(s->n_tris);
+    return SRP_OK;
+}
+
+srp_status srp_frames(srp_scene s, const double* sun_dirs, int64_t D, int32_t nu, int32_t nv, double* frames,
+                      void* stream)
+{
+    if (!s || (D > 0 && (!sun_dirs || !frames))) return fail(SRP_EINVAL, "NULL argument");
+    if (D < 0 || nu < 1 || nv < 1) return fail(SRP_EINVAL, "bad sizes");
+    srp_status st = bind_device(s);
+    if (st != SRP_OK) return st;
+    SRP_HIP(srp::launch_frames(sun_dirs, D, s->lo, s->hi, s->L, nu, nv, 0.0, nullptr, frames, nullptr,
+                               static_cast<hipStream_t>(stream)));
+    return SRP_OK;
+}
+
+srp_status srp_trace(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p, const double* frames,
+                     double* force, double* torque, void* stream_)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (D < 0) return fail(SRP_EINVAL, "D must be >= 0");
+    if (D == 0) return SRP_OK;
+    if (!sun_dirs || !force) return fail(SRP_EINVAL, "sun_dirs and force are required");
+    if (p->frame_mode == 1 && !frames) return fail(SRP_EINVAL, "frame_mode 1 needs frames");
+    if (p->dir_index_base + D > (int64_t(1) << 32)) return fail(SRP_EINVAL, "direction index exceeds 32 bits");
+    st = bind_device(s);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    int32_t bpd = 0;
+    st = enqueue_trace(s, sun_dirs, D, p, frames, false, nullptr, 0, nullptr, nullptr, stream, &bpd);
+    if (st != SRP_OK) return st;
+    SRP_HIP(srp::launch_reduce(s->d_partials, D, bpd, force, torque, stream));
+    return SRP_OK;
+}
+
+srp_status srp_trace_records(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                             const double* frames, const int64_t* pix, int64_t n_pix, int32_t* hit_prim,
+                             float* ray_force, void* stream_)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (D < 0 || (pix && n_pix < 0)) return fail(SRP_EINVAL, "bad sizes");
+    if (D == 0 || (pix && n_pix == 0)) return SRP_OK;
+    if (!sun_dirs || !hit_prim) return fail(SRP_EINVAL, "sun_dirs and hit_prim are required");
+    if (p->frame_mode == 1 && !frames) return fail(SRP_EINVAL, "frame_mode 1 needs frames");
+    if (p->dir_index_base + D > (int64_t(1) << 32)) return fail(SRP_EINVAL, "direction index exceeds 32 bits");
+    st = bind_device(s);
+    if (st != SRP_OK) return st;
+    int32_t bpd = 0;
+    return enqueue_trace(s, sun_dirs, D, p, frames, true, pix, n_pix, hit_prim, ray_force,
+                         static_cast<hipStream_t>(stream_), &bpd);
+}
+
+srp_status srp_scene_destroy(srp_scene s)
+{
+    if (!s) return SRP_OK;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    (void)hipFree(s->d_nodes);
+    (void)hipFree(s->d_tris);
+    (void)hipFree(s->d_mat);
+    (void)hipFree(s->d_perm);
+    (void)hipFree(s->d_flag);
+    (void)hipFree(s->d_frames);
+    (void)hipFree(s->d_partials);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete s;
+    return SRP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal data layouts of libsrp, shared by the host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srp {
+
+constexpr double kSpeedOfLight = 299792458.0;  // m/s, exact
+constexpr int kMaxBounces = 8;
+constexpr int kStackDepth = 64;    // wave-uniform traversal stack (tree depth is capped below it)
+constexpr int kMaxTreeDepth = 56;
+constexpr int kLeafMax = 7;        // triangles per leaf (3-bit count in the child code)
+constexpr int kWaves = 4;          // wavefronts per trace workgroup
+constexpr int kTileW = 8;          // a wavefront traces an 8 x 8 pixel tile
+constexpr int kTileH = 8;
+
+// BVH2 node, 64 bytes, both child boxes stored in the parent:
+//   f[0] = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
+//   f[1] = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
+//   f[2] = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
+//   f[3] = (child0, child1, -, -) as int bits; child >= 0: inner node index;
+//          child < 0: leaf, ~child = first_triangle << 3 | count (count 0..7)
+struct BvhNode {
+    float4 f[4];
+};
+
+// Triangle record in BVH order, 64 bytes:
+//   (v0.x, v0.y, v0.z, original index as int bits), (e1.xyz, n.x), (e2.xyz, n.y), (n.z, 0, 0, 0)
+struct TriRec {
+    float4 f[4];
+};
+
+// Per-direction grid frame as the trace kernel consumes it (FP32, rounded from FP64):
+// origin of pixel (i, k) with offsets (a, b): o0 + (i + a) U + (k + b) V; propagation d;
+// w = Phi du dv / c is the force carried by one ray tube.
+struct DevFrame {
+    float o0[3];
+    float U[3];
+    float V[3];
+    float d[3];
+    float w;
+    float pad[3];
+};
+
+struct TraceArgs {
+    const BvhNode* nodes;
+    const TriRec* tris;
+    const float4* mat;        // BVH order: (rho_s, rho_d, p_spec, 0)
+    const DevFrame* frames;   // [D]
+    int64_t D;
+    int32_t nu, nv;
+    int32_t bounces;
+    int32_t jitter;
+    uint32_t seed_lo, seed_hi;
+    int64_t dir_index_base;
+    uint32_t design_index;
+    float com[3];
+    float eps;                // secondary-ray offset along the normal
+    int32_t tiles_x, tiles_y; // wave tiles per direction (grid mode)
+    int64_t tiles_per_dir;
+    int32_t tiles_per_wave;
+    int32_t blocks_per_dir;
+    const int64_t* pix;       // records mode: explicit pixel list, or null = all pixels
+    int64_t n_pix;
+    double* partials;         // [D][blocks_per_dir][6]
+    int32_t* rec_hit;         // [D][n_pix][bounces]
+    float* rec_force;         // [D][n_pix][3]
+};
+
+// Host-side launchers (defined in trace_kernels.hip).
+hipError_t launch_frames(const double* sun_dirs, int64_t D, const double lo[3], const double hi[3], double L,
+                         int32_t nu, int32_t nv, double flux, const double* caller_frames, double* frames64,
+                         DevFrame* frames32, hipStream_t stream);
+hipError_t launch_pack_materials(const float* rho_s, const float* rho_d, const float* p_spec, const int32_t* perm,
+                                 int64_t n, float4* mat, int32_t* bad_flag, hipStream_t stream);
+hipError_t launch_trace(const TraceArgs& a, bool records, hipStream_t stream);
+hipError_t launch_reduce(const double* partials, int64_t D, int32_t blocks_per_dir, double* force, double* torque,
+                         hipStream_t stream);
+
+}  // namespace srp

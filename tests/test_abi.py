@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every function declared in include/srp.h (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not hdr.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_\s\*]*?\b(srp_[a-z0-9_]+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("srp_scene_create", "srp_scene_set_design", "srp_trace", "srp_trace_records", "srp_frames",
+              "srp_scene_destroy", "srp_sync", "srp_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib_path = os.path.join(ROOT, "paper_2602_10712_amd", "libsrp.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("libsrp.so not built")
+    lib = ctypes.CDLL(lib_path)
+    missing = [n for n in sorted(declared_functions()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_last_error_callable_without_gpu():
+    lib_path = os.path.join(ROOT, "paper_2602_10712_amd", "libsrp.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("libsrp.so not built")
+    lib = ctypes.CDLL(lib_path)
+    lib.srp_last_error.restype = ctypes.c_char_p
+    assert isinstance(lib.srp_last_error(), bytes)
+    # argument validation happens before any device call
+    lib.srp_scene_create.restype = ctypes.c_int32
+    out = ctypes.c_void_p()
+    st = lib.srp_scene_create(None, ctypes.c_int64(0), None, ctypes.c_int64(0), None, None, 0, None,
+                              ctypes.byref(out))
+    assert st == -1
+    assert b"empty" in lib.srp_last_error()

@@ -1,0 +1,179 @@
+"""GPU forward trace vs the FP64 oracle (parity), through the C ABI.
+
+Bars (documented in the design notes):
+  * force and torque per direction: relative L2 over the stacked [D][3] array <= 1e-4;
+  * hit indices: identical on every segment the oracle does not flag as degenerate (a path is
+    degenerate from its first flagged segment on); the degenerate fraction is reported.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import srp_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lib():
+    import paper_2602_10712_amd as p
+    return p
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make_scene(mesh, rs, rd, angles=None, p_spec=None):
+    p = _lib()
+    sc = p.Scene.from_mesh(mesh)
+    sc.set_design(rs, rd, hinge_angles=angles, p_spec=p_spec)
+    return sc
+
+
+def check_hits(gpu_hits, orc, label):
+    """gpu_hits [D][P][B] int32; orc: oracle TraceResult with records."""
+    deg = orc.degen.astype(bool)
+    ok = ~deg
+    mism = (gpu_hits != orc.hit_prim) & ok
+    n_seg = int(ok.sum())
+    print(f"[{label}] segments checked {n_seg}, degenerate fraction {deg.mean():.2e}, mismatches {int(mism.sum())}")
+    assert mism.sum() == 0, np.argwhere(mism)[:10]
+    return deg.mean()
+
+
+def test_box_wing_full_config():
+    """Box-wing: 20 tris, 64 Fibonacci dirs, 256 x 256 rays, 1 bounce (the small workload)."""
+    m = si.box_wing()
+    rs, rd = si.materials(m.n_tris, 1)
+    sun = si.fibonacci_dirs(64)
+    p = _lib()
+    params = p.TraceParams(nu=256, nv=256, bounces=1, jitter=1, seed=2)
+    sc = make_scene(m, rs, rd)
+    F, T = sc.trace(sun, params)
+    torch.cuda.synchronize()
+    ref = oracle.trace(m.verts, m.tris, rs, rd, sun, nu=256, nv=256, bounces=1, seed=2)
+    eF, eT = rel_l2(F.cpu().numpy(), ref.force), rel_l2(T.cpu().numpy(), ref.torque)
+    print(f"box-wing force rel L2 {eF:.3e} torque rel L2 {eT:.3e}")
+    assert eF <= 1e-4 and eT <= 1e-4
+    # per-ray hits on 4 directions, all pixels
+    sel = [0, 17, 40, 63]
+    for j in sel:
+        pj = p.TraceParams(nu=256, nv=256, bounces=1, jitter=1, seed=2, dir_index_base=j)
+        hp, rf = sc.records(sun[j:j + 1], pj)
+        orc = oracle.trace(m.verts, m.tris, rs, rd, sun[j:j + 1], nu=256, nv=256, bounces=1, seed=2,
+                           dir_index_base=j, records=True)
+        check_hits(hp.cpu().numpy(), orc, f"box-wing dir {j}")
+
+
+@pytest.mark.parametrize("bounces", [1, 3])
+def test_meo_small_hits_and_force(bounces):
+    """MEO-style 20.6k-triangle satellite with hinges at +-20 degrees, 8 directions x 96 x 80."""
+    m = si.meo_satellite()
+    rs, rd = si.materials(m.n_tris, 1)
+    ang = np.deg2rad([20.0, -20.0])
+    sun = si.fibonacci_dirs(1024)[::128]
+    nu, nv = 96, 80
+    p = _lib()
+    sc = make_scene(m, rs, rd, angles=ang)
+    V = sc.vertices()
+    from oracle.design import apply_hinges
+    V_ref = apply_hinges(m.verts, m.vert_hinge, m.hinge_origin, m.hinge_axis, ang)
+    assert np.allclose(V, V_ref, rtol=0, atol=1e-12)
+    params = p.TraceParams(nu=nu, nv=nv, bounces=bounces, jitter=1, seed=7)
+    F, T = sc.trace(sun, params)
+    hp, rf = sc.records(sun, params)
+    torch.cuda.synchronize()
+    orc = oracle.trace(V_ref, m.tris, rs, rd, sun, nu=nu, nv=nv, bounces=bounces, seed=7, records=True)
+    frac = check_hits(hp.cpu().numpy(), orc, f"meo B={bounces}")
+    assert frac < 0.03
+    eF, eT = rel_l2(F.cpu().numpy(), orc.force), rel_l2(T.cpu().numpy(), orc.torque)
+    print(f"meo B={bounces} force rel L2 {eF:.3e} torque rel L2 {eT:.3e}")
+    assert eF <= 1e-4 and eT <= 1e-4
+    # per-ray force on the non-degenerate paths
+    ok = ~orc.degen.any(-1)
+    rfg = rf.cpu().numpy().astype(np.float64)
+    err = np.abs(rfg - orc.ray_force)[ok].max()
+    scale = np.abs(orc.ray_force).max()
+    assert err <= 1e-5 * scale
+
+
+def test_ragged_grid_centres_and_single_pixel():
+    m = si.box_wing()
+    rs, rd = si.materials(m.n_tris, 3)
+    sun = si.fibonacci_dirs(5)
+    p = _lib()
+    sc = make_scene(m, rs, rd)
+    for nu, nv, jit in ((37, 23, 1), (1, 1, 0), (9, 64, 0), (130, 7, 1)):
+        params = p.TraceParams(nu=nu, nv=nv, bounces=2, jitter=jit, seed=5)
+        F, T = sc.trace(sun, params)
+        hp, _ = sc.records(sun, params)
+        torch.cuda.synchronize()
+        orc = oracle.trace(m.verts, m.tris, rs, rd, sun, nu=nu, nv=nv, bounces=2, jitter=bool(jit), seed=5,
+                           records=True)
+        check_hits(hp.cpu().numpy(), orc, f"ragged {nu}x{nv}")
+        ref = orc.force
+        if np.linalg.norm(ref) > 0:
+            assert rel_l2(F.cpu().numpy(), ref) <= 1e-4
+
+
+def test_caller_frames_and_plate_closed_form():
+    """A plate seen head-on through caller frames: exact closed form up to FP32 rounding."""
+    W, H = 2.0, 1.5
+    m = si.plate(W, H, tilt_deg=30.0)
+    rs = np.full(2, 0.3, np.float32)
+    rd = np.full(2, 0.2, np.float32)
+    p = _lib()
+    sc = make_scene(m, rs, rd)
+    sun = np.array([[0.0, 0.0, 1.0]])
+    fr = oracle.frames(m.verts, sun, 64, 48)
+    params = p.TraceParams(nu=64, nv=48, bounces=1, jitter=0, frame_mode=1)
+    F, T = sc.trace(sun, params, frames=fr)
+    orc = oracle.trace(m.verts, m.tris, rs, rd, sun, nu=64, nv=48, bounces=1, jitter=False, frames_in=fr)
+    assert rel_l2(F.cpu().numpy(), orc.force) <= 1e-6
+    # frames computed by the library agree with the oracle's in FP64
+    frd = torch.empty((1, 12), dtype=torch.float64, device="cuda")
+    p.srp_frames(sc.handle, torch.as_tensor(sun, device="cuda"), 64, 48, frd)
+    torch.cuda.synchronize()
+    assert np.allclose(frd.cpu().numpy(), fr, rtol=1e-12, atol=1e-12)
+
+
+def test_deterministic_and_dir_index_base():
+    m = si.meo_satellite(bus_n=6, cyl_sides=16, panel_n=4, dish_rings=8, dish_sectors=16, strut_sides=6)
+    rs, rd = si.materials(m.n_tris, 4)
+    sun = si.fibonacci_dirs(12)
+    p = _lib()
+    sc = make_scene(m, rs, rd)
+    params = p.TraceParams(nu=64, nv=64, bounces=3, seed=11)
+    F1, T1 = sc.trace(sun, params)
+    F2, T2 = sc.trace(sun, params)
+    assert torch.equal(F1, F2) and torch.equal(T1, T2)
+    # tracing the last 4 directions alone with dir_index_base = 8 reproduces them bit for bit
+    p2 = p.TraceParams(nu=64, nv=64, bounces=3, seed=11, dir_index_base=8)
+    F3, _ = sc.trace(sun[8:], p2)
+    torch.cuda.synchronize()
+    ref = oracle.trace(m.verts, m.tris, rs, rd, sun[8:], nu=64, nv=64, bounces=3, seed=11, dir_index_base=8)
+    assert rel_l2(F3.cpu().numpy(), ref.force) <= 1e-4
+    assert rel_l2(F3.cpu().numpy(), F1[8:].cpu().numpy()) <= 1e-6
+
+
+def test_invalid_arguments_raise():
+    p = _lib()
+    m = si.box_wing()
+    sc = p.Scene.from_mesh(m)
+    with pytest.raises(p.SRPError) as e:
+        sc.set_design(np.full(m.n_tris, 0.7, np.float32), np.full(m.n_tris, 0.7, np.float32))
+    assert e.value.status == -1
+    with pytest.raises(p.SRPError):
+        sc.trace(si.fibonacci_dirs(2), p.TraceParams(nu=0, nv=4))
+    with pytest.raises(p.SRPError):
+        sc.trace(si.fibonacci_dirs(2), p.TraceParams(nu=4, nv=4, bounces=9))
+    with pytest.raises(p.SRPError):
+        p.Scene(np.zeros((3, 3)), np.array([[0, 1, 5]]))
+    with pytest.raises(p.SRPError) as e:
+        p.Scene(np.zeros((3, 3)), np.array([[0, 1, 2]]))
+    assert e.value.status == -4
+    # zero directions is a no-op
+    F, T = sc.trace(np.zeros((0, 3)), p.TraceParams(nu=4, nv=4))
+    assert F.shape == (0, 3)
