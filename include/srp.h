@@ -128,6 +128,14 @@ srp_status srp_trace_records(srp_scene scene, const double* sun_dirs, int64_t D,
                              const double* frames, const int64_t* pix, int64_t n_pix, int32_t* hit_prim,
                              float* ray_force, void* stream);
 
+/* Traversal statistics for the bandwidth model: a host-side single-ray depth-first closest-hit
+ * traversal (nearer child first) of this scene's BVH on the same rays as srp_trace, for every
+ * pixel_stride-th pixel of each direction.  sun_dirs and frames are HOST arrays here.
+ * out host double [5]: primary rays, ray segments (traversals), BVH nodes fetched, triangles
+ * tested, surface hits.  Synchronous; reads the materials back from the device. */
+srp_status srp_scene_ray_stats(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
+                               const double* frames, int64_t pixel_stride, double* out);
+
 srp_status srp_scene_destroy(srp_scene scene);
 
 /* Waits for `stream` and reports any pending device error as SRP_EDEVICE. */

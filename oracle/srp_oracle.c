@@ -636,3 +636,368 @@ int oracle_trace(const double* verts, int64_t n_verts, const int32_t* tris, int6
     scene_free(&S);
     return ORC_OK;
 }
+
+/* ========================================================================================== */
+/* Gradients.                                                                                 */
+/*                                                                                            */
+/* With every Philox counter and the specular-sampling probabilities p_s frozen, the estimator */
+/* is a polynomial in the per-facet reflectances: along a path with interactions b = 1..K the */
+/* weights are W_b = w k_1 ... k_b with k_b = rho_s/p_s (mirror event) or rho_d/(1 - p_s)      */
+/* (Lambertian event); interaction b < K deposits W_{b-1} d_{b-1} - W_b o_b and the last one    */
+/* W_{K-1} (d_{K-1} - rho_s r_K - (2/3) rho_d n_K).  For a loss L = sum_j gF_j . F_j +           */
+/* gT_j . tau_j every deposit v at x contributes v . (gF + gT x (x - x_COM)).                  */
+/* oracle_trace_adjoint_rho returns dL/d rho_s[f], dL/d rho_d[f] of that polynomial, written   */
+/* out per path in FP64 (no division by k: products leaving k_i out are formed directly).       */
+/* ========================================================================================== */
+
+typedef struct {
+    int32_t facet;
+    int32_t mirror; /* 1: mirror event, 0: Lambertian event */
+    double k;       /* weight factor of the event */
+    double c;       /* loss coefficient of the W_b term: -(G_b . o_b) */
+} grad_step_t;
+
+static void adjoint_path(const scene_t* S, const double fr[12], const double sun[3], const params_t* P, int64_t pixel,
+                         uint32_t dir_global, const double gF[3], const double gT[3], double* g_rs, double* g_rd)
+{
+    const int32_t nu = P->nu;
+    const int64_t i = pixel % nu, k = pixel / nu;
+    double a = 0.5, b = 0.5;
+    if (P->jitter) {
+        double r[4];
+        draw4(P->seed, (uint32_t)pixel, dir_global, 0u, P->design_index, r);
+        a = r[0];
+        b = r[1];
+    }
+    const double* u = fr;
+    const double* v = fr + 3;
+    const double* o0 = fr + 6;
+    double o[3], d[3];
+    for (int c = 0; c < 3; ++c) o[c] = o0[c] + ((double)i + a) * fr[9] * u[c] + ((double)k + b) * fr[10] * v[c];
+    propagation_dir(sun, d);
+    const double w = P->flux * fr[9] * fr[10] / kSpeedOfLight;
+    const double eps = 1e-5 * S->L;
+    grad_step_t st[16];
+    int K = 0;            /* non-terminal interactions recorded */
+    double coef0 = 0.0;   /* coefficient of W_0 = w */
+    int64_t skip = -1;
+    /* terminal data */
+    int have_term = 0;
+    int64_t tf = -1;
+    double tg = 0.0, td = 0.0; /* G . r and G . n at the terminal interaction */
+    double W_in = w;           /* current weight (for the terminal coefficients) */
+    for (int bnc = 1; bnc <= P->bounces; ++bnc) {
+        double t;
+        int64_t f = closest_hit(S, o, d, skip, &t);
+        if (f < 0) break;
+        const double* n = S->nrm + 3 * f;
+        double x[3], lever[3], G[3], gx[3];
+        for (int c = 0; c < 3; ++c) {
+            x[c] = o[c] + t * d[c];
+            lever[c] = x[c] - S->com[c];
+        }
+        cross3(gT, lever, gx);
+        for (int c = 0; c < 3; ++c) G[c] = gF[c] + gx[c];
+        const double cth = -dot3(d, n);
+        double r[3];
+        for (int c = 0; c < 3; ++c) r[c] = d[c] + 2.0 * cth * n[c];
+        /* incoming term: W_{b-1} (G . d_{b-1}) */
+        const double gin = dot3(G, d);
+        if (K == 0) coef0 += gin; else st[K - 1].c += gin;
+        if (bnc == P->bounces || (S->rho_s[f] == 0.0f && S->rho_d[f] == 0.0f)) {
+            have_term = 1;
+            tf = f;
+            tg = dot3(G, r);
+            td = dot3(G, n);
+            break;
+        }
+        double ev[4];
+        draw4(P->seed, (uint32_t)pixel, dir_global, (uint32_t)bnc, P->design_index, ev);
+        const float ps = S->p_spec[f];
+        double odir[3], kf;
+        int mirror;
+        if ((float)ev[0] < ps) {
+            for (int c = 0; c < 3; ++c) odir[c] = r[c];
+            kf = (double)S->rho_s[f] / (double)ps;
+            mirror = 1;
+        } else {
+            double rad = sqrt(ev[1]);
+            double phi = 2.0 * M_PI * ev[2];
+            double lx = rad * cos(phi), ly = rad * sin(phi), lz = sqrt(fmax(0.0, 1.0 - ev[1]));
+            double t1[3], t2[3];
+            oracle_basis(n, t1, t2);
+            for (int c = 0; c < 3; ++c) odir[c] = lx * t1[c] + ly * t2[c] + lz * n[c];
+            kf = (double)S->rho_d[f] / (1.0 - (double)ps);
+            mirror = 0;
+        }
+        st[K].facet = (int32_t)f;
+        st[K].mirror = mirror;
+        st[K].k = kf;
+        st[K].c = -dot3(G, odir);
+        ++K;
+        W_in *= kf;
+        for (int c = 0; c < 3; ++c) {
+            o[c] = x[c] + eps * n[c];
+            d[c] = odir[c];
+        }
+        skip = f;
+    }
+    (void)W_in;
+    /* L = w coef0 + sum_b W_b c_b + W_K (-(rho_s G.r + 2/3 rho_d G.n)) at the terminal one */
+    double term_c = 0.0;
+    if (have_term) term_c = -((double)S->rho_s[tf] * tg + (2.0 / 3.0) * (double)S->rho_d[tf] * td);
+    for (int q = 0; q < K; ++q) {
+        /* dL/dk_q = sum over m >= q of (W_m / k_q) c_m  (+ terminal) */
+        double acc = 0.0;
+        for (int m = q; m < K; ++m) {
+            double prod = w;
+            for (int l = 0; l <= m; ++l)
+                if (l != q) prod *= st[l].k;
+            acc += prod * st[m].c;
+        }
+        if (have_term) {
+            double prod = w;
+            for (int l = 0; l < K; ++l)
+                if (l != q) prod *= st[l].k;
+            acc += prod * term_c;
+        }
+        const int32_t f = st[q].facet;
+        const float ps = S->p_spec[f];
+        if (st[q].mirror) g_rs[f] += acc / (double)ps;
+        else g_rd[f] += acc / (1.0 - (double)ps);
+    }
+    if (have_term) {
+        double WK = w;
+        for (int l = 0; l < K; ++l) WK *= st[l].k;
+        g_rs[tf] += -WK * tg;
+        g_rd[tf] += -WK * (2.0 / 3.0) * td;
+    }
+}
+
+typedef struct {
+    const scene_t* S;
+    const params_t* P;
+    const double* frames;
+    const double* sun_dirs;
+    int64_t n_dirs;
+    const int64_t* pix;
+    int64_t n_pix;
+    const double* gF;
+    const double* gT;
+    double* g_rs; /* [threads][T] */
+    double* g_rd;
+    int32_t n_threads;
+} adj_job_t;
+
+typedef struct {
+    adj_job_t* J;
+    int32_t tid;
+} adj_arg_t;
+
+static void* adj_worker(void* argp)
+{
+    adj_arg_t* A = (adj_arg_t*)argp;
+    adj_job_t* J = A->J;
+    const int64_t per_dir = (J->n_pix + CHUNK - 1) / CHUNK;
+    const int64_t total = per_dir * J->n_dirs;
+    const int64_t T = J->S->n_tris;
+    double* gs = J->g_rs + (int64_t)A->tid * T;
+    double* gd = J->g_rd + (int64_t)A->tid * T;
+    for (int64_t item = A->tid; item < total; item += J->n_threads) { /* static assignment: deterministic */
+        int64_t j = item / per_dir;
+        int64_t p0 = (item % per_dir) * CHUNK;
+        int64_t p1 = p0 + CHUNK < J->n_pix ? p0 + CHUNK : J->n_pix;
+        for (int64_t q = p0; q < p1; ++q) {
+            int64_t pixel = J->pix ? J->pix[q] : q;
+            adjoint_path(J->S, J->frames + 12 * j, J->sun_dirs + 3 * j, J->P, pixel,
+                         (uint32_t)(J->P->dir_index_base + j), J->gF + 3 * j, J->gT + 3 * j, gs, gd);
+        }
+    }
+    return NULL;
+}
+
+/* oracle_trace_adjoint_rho: dL/d rho_s and dL/d rho_d per facet (ADDED to g_rho_s, g_rho_d
+ * [n_tris]) for L = sum_j gF[j] . F_j + gT[j] . tau_j, with the inputs of oracle_trace.
+ * gT may be NULL (zero). */
+int oracle_trace_adjoint_rho(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                             const float* rho_s, const float* rho_d, const float* p_spec, const double* com,
+                             const double* sun_dirs, int64_t n_dirs, const double* frames, int32_t nu, int32_t nv,
+                             int32_t bounces, int32_t jitter, double flux, uint64_t seed, int64_t dir_index_base,
+                             uint32_t design_index, const int64_t* pix, int64_t n_pix, const double* gF,
+                             const double* gT, double* g_rho_s, double* g_rho_d, int32_t n_threads)
+{
+    if (!verts || !tris || !rho_s || !rho_d || !sun_dirs || !gF || !g_rho_s || !g_rho_d || nu <= 0 || nv <= 0 ||
+        bounces < 1 || bounces > 15 || n_dirs < 0)
+        return ORC_EINVAL;
+    if (!pix) n_pix = (int64_t)nu * nv;
+    scene_t S;
+    int st = scene_init(&S, verts, n_verts, tris, n_tris, rho_s, rho_d, p_spec, com);
+    if (st != ORC_OK) {
+        scene_free(&S);
+        return st;
+    }
+    double* fr = NULL;
+    if (!frames) {
+        fr = malloc(sizeof(double) * 12 * (n_dirs > 0 ? n_dirs : 1));
+        oracle_frames(verts, n_verts, sun_dirs, n_dirs, nu, nv, fr);
+        frames = fr;
+    }
+    double* zero = NULL;
+    if (!gT) {
+        zero = calloc(3 * (size_t)(n_dirs > 0 ? n_dirs : 1), sizeof(double));
+        gT = zero;
+    }
+    params_t P = {nu, nv, bounces, jitter, flux, seed, dir_index_base, design_index};
+    if (n_threads < 1) n_threads = 1;
+    adj_job_t J = {&S, &P, frames, sun_dirs, n_dirs, pix, n_pix, gF, gT, NULL, NULL, n_threads};
+    J.g_rs = calloc((size_t)n_threads * n_tris, sizeof(double));
+    J.g_rd = calloc((size_t)n_threads * n_tris, sizeof(double));
+    pthread_t* th = malloc(sizeof(pthread_t) * n_threads);
+    adj_arg_t* args = malloc(sizeof(adj_arg_t) * n_threads);
+    for (int32_t t = 0; t < n_threads; ++t) {
+        args[t].J = &J;
+        args[t].tid = t;
+        pthread_create(&th[t], NULL, adj_worker, &args[t]);
+    }
+    for (int32_t t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    for (int32_t t = 0; t < n_threads; ++t)
+        for (int64_t f = 0; f < n_tris; ++f) {
+            g_rho_s[f] += J.g_rs[(int64_t)t * n_tris + f];
+            g_rho_d[f] += J.g_rd[(int64_t)t * n_tris + f];
+        }
+    free(J.g_rs); free(J.g_rd); free(th); free(args); free(fr); free(zero);
+    scene_free(&S);
+    return ORC_OK;
+}
+
+/* ========================================================================================== */
+/* Frozen-visibility estimator (for hinge-angle gradients).                                   */
+/*                                                                                            */
+/* Each path keeps the facet sequence it had at the reference design (ref_hits, from           */
+/* oracle_trace records at theta_0); at the current vertices each segment meets the PLANE of   */
+/* its frozen facet, so hit points move with the facets, normals and mirror directions turn,    */
+/* and the Lambertian direction is rebuilt in the basis of the turned normal from the same      */
+/* draws.  The path's deposits are scaled by P_f(theta)/P_f(theta_0), where P_f is the area of  */
+/* the primary facet projected on the grid plane (1/2 ((v1-v0) x (v2-v0)) . (-d)): the ray grid */
+/* samples each facet in proportion to its projected area, and this factor carries the          */
+/* first-order change of that share for a facet no other facet shadows.  Visibility changes     */
+/* between facets (silhouettes, shadows) are excluded.  Its derivative at theta_0 is the        */
+/* gradient the GPU adjoint computes for hinge angles.                                         */
+/* ========================================================================================== */
+static double proj_area(const double* pv, const double d[3])
+{
+    double e1[3], e2[3], cr[3];
+    sub3(pv + 3, pv, e1);
+    sub3(pv + 6, pv, e2);
+    cross3(e1, e2, cr);
+    return -0.5 * dot3(cr, d);
+}
+
+int oracle_trace_frozen(const double* verts, const double* verts0, int64_t n_verts, const int32_t* tris,
+                        int64_t n_tris, const float* rho_s, const float* rho_d, const float* p_spec, const double* com,
+                        const double* sun_dirs, int64_t n_dirs, const double* frames, int32_t nu, int32_t nv,
+                        int32_t bounces, int32_t jitter, double flux, uint64_t seed, int64_t dir_index_base,
+                        uint32_t design_index, const int64_t* pix, int64_t n_pix, const int32_t* ref_hits,
+                        double* force, double* torque)
+{
+    if (!verts || !verts0 || !tris || !rho_s || !rho_d || !sun_dirs || !frames || !ref_hits || !force || !torque ||
+        nu <= 0 || nv <= 0 || bounces < 1)
+        return ORC_EINVAL;
+    if (!pix) n_pix = (int64_t)nu * nv;
+    scene_t S, S0;
+    int st = scene_init(&S, verts, n_verts, tris, n_tris, rho_s, rho_d, p_spec, com);
+    int st0 = scene_init(&S0, verts0, n_verts, tris, n_tris, rho_s, rho_d, p_spec, com);
+    if (st != ORC_OK || st0 != ORC_OK) {
+        scene_free(&S);
+        scene_free(&S0);
+        return st != ORC_OK ? st : st0;
+    }
+    /* the offset scale is taken at the reference design (its derivative is excluded) */
+    const double eps = 1e-5 * S0.L;
+    for (int64_t j = 0; j < n_dirs; ++j) {
+        const double* fr = frames + 12 * j;
+        double Fj[3] = {0, 0, 0}, Tj[3] = {0, 0, 0};
+        const uint32_t dir_global = (uint32_t)(dir_index_base + j);
+        for (int64_t q = 0; q < n_pix; ++q) {
+            const int64_t pixel = pix ? pix[q] : q;
+            const int32_t* hits = ref_hits + (j * n_pix + q) * bounces;
+            if (hits[0] < 0) continue;
+            const int64_t i = pixel % nu, k = pixel / nu;
+            double a = 0.5, b = 0.5;
+            if (jitter) {
+                double r[4];
+                draw4(seed, (uint32_t)pixel, dir_global, 0u, design_index, r);
+                a = r[0];
+                b = r[1];
+            }
+            double o[3], d[3];
+            for (int c = 0; c < 3; ++c)
+                o[c] = fr[6 + c] + ((double)i + a) * fr[9] * fr[c] + ((double)k + b) * fr[10] * fr[3 + c];
+            propagation_dir(sun_dirs + 3 * j, d);
+            const double scale = proj_area(S.pv + 9 * hits[0], d) / proj_area(S0.pv + 9 * hits[0], d);
+            double w = flux * fr[9] * fr[10] / kSpeedOfLight;
+            double PF[3] = {0, 0, 0}, PT[3] = {0, 0, 0};
+            for (int bnc = 1; bnc <= bounces; ++bnc) {
+                const int32_t f = hits[bnc - 1];
+                if (f < 0) break;
+                const double* n = S.nrm + 3 * f;
+                double rel[3];
+                sub3(S.v0 + 3 * f, o, rel);
+                const double t = dot3(n, rel) / dot3(n, d);
+                double x[3], lever[3];
+                for (int c = 0; c < 3; ++c) {
+                    x[c] = o[c] + t * d[c];
+                    lever[c] = x[c] - S.com[c];
+                }
+                const double cth = -dot3(d, n);
+                double r[3];
+                for (int c = 0; c < 3; ++c) r[c] = d[c] + 2.0 * cth * n[c];
+                const double rs = (double)rho_s[f], rd = (double)rho_d[f];
+                double dep[3] = {w * d[0], w * d[1], w * d[2]}, tq[3];
+                if (bnc == bounces || (rho_s[f] == 0.0f && rho_d[f] == 0.0f)) {
+                    for (int c = 0; c < 3; ++c) dep[c] -= w * (rs * r[c] + (2.0 / 3.0) * rd * n[c]);
+                    for (int c = 0; c < 3; ++c) PF[c] += dep[c];
+                    cross3(lever, dep, tq);
+                    for (int c = 0; c < 3; ++c) PT[c] += tq[c];
+                    break;
+                }
+                double ev[4];
+                draw4(seed, (uint32_t)pixel, dir_global, (uint32_t)bnc, design_index, ev);
+                const float ps = S.p_spec[f];
+                double odir[3], w2;
+                if ((float)ev[0] < ps) {
+                    for (int c = 0; c < 3; ++c) odir[c] = r[c];
+                    w2 = w * rs / (double)ps;
+                } else {
+                    double rad = sqrt(ev[1]);
+                    double phi = 2.0 * M_PI * ev[2];
+                    double lx = rad * cos(phi), ly = rad * sin(phi), lz = sqrt(fmax(0.0, 1.0 - ev[1]));
+                    double t1[3], t2[3];
+                    oracle_basis(n, t1, t2);
+                    for (int c = 0; c < 3; ++c) odir[c] = lx * t1[c] + ly * t2[c] + lz * n[c];
+                    w2 = w * rd / (1.0 - (double)ps);
+                }
+                for (int c = 0; c < 3; ++c) dep[c] -= w2 * odir[c];
+                for (int c = 0; c < 3; ++c) PF[c] += dep[c];
+                cross3(lever, dep, tq);
+                for (int c = 0; c < 3; ++c) PT[c] += tq[c];
+                for (int c = 0; c < 3; ++c) {
+                    o[c] = x[c] + eps * n[c];
+                    d[c] = odir[c];
+                }
+                w = w2;
+            }
+            for (int c = 0; c < 3; ++c) {
+                Fj[c] += scale * PF[c];
+                Tj[c] += scale * PT[c];
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            force[3 * j + c] = Fj[c];
+            torque[3 * j + c] = Tj[c];
+        }
+    }
+    scene_free(&S);
+    scene_free(&S0);
+    return ORC_OK;
+}

@@ -9,7 +9,7 @@ import importlib
 
 _BINDING_NAMES = {"SRPError", "Scene", "TraceParams", "lib_path", "srp_frames", "srp_scene_create",
                   "srp_scene_destroy", "srp_scene_get_vertices", "srp_scene_info", "srp_scene_set_design",
-                  "srp_sync", "srp_trace", "srp_trace_records"}
+                  "srp_sync", "srp_trace", "srp_trace_records", "srp_scene_ray_stats", "ray_stats"}
 
 
 def __getattr__(name):

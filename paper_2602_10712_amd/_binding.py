@@ -46,6 +46,7 @@ _sigs = {
     "srp_frames": [P, P, I64, I32, I32, P, P],
     "srp_trace": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P],
     "srp_trace_records": [P, P, I64, ctypes.POINTER(TraceParams), P, P, I64, P, P, P],
+    "srp_scene_ray_stats": [P, P, I64, ctypes.POINTER(TraceParams), P, I64, P],
     "srp_scene_destroy": [P],
     "srp_sync": [P],
 }
@@ -169,6 +170,38 @@ def srp_trace_records(scene, sun_dirs, params: TraceParams, hit_prim, ray_force=
     n_pix = 0 if pix is None else pix.shape[0]
     _check(_lib.srp_trace_records(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params), _dptr(frames),
                                   _dptr(pix), n_pix, _dptr(hit_prim), _dptr(ray_force), _stream(stream)))
+
+
+def srp_scene_ray_stats(scene, sun_dirs, params: TraceParams, pixel_stride=1, frames=None):
+    """Host arrays in, dict out: rays, segments, nodes, tris, hits (see srp.h)."""
+    sd = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
+    fr = None if frames is None else np.ascontiguousarray(frames, dtype=np.float64).reshape(-1, 12)
+    out = np.zeros(5)
+    _check(_lib.srp_scene_ray_stats(scene, _hptr(sd), len(sd), ctypes.byref(params), _hptr(fr), int(pixel_stride),
+                                    _hptr(out)))
+    return dict(zip(("rays", "segments", "nodes", "tris", "hits"), out.tolist()))
+
+
+# bytes a single ray must touch (bandwidth model): one 64-byte node record per node fetched,
+# 36 bytes (v0, e1, e2 as float) per triangle tested, 20 bytes (normal + rho_s, rho_d) per hit
+NODE_BYTES, TRI_BYTES, HIT_BYTES = 64.0, 36.0, 20.0
+
+
+def ray_stats(scene, sun_dirs, params: TraceParams, n_dirs=16, pixel_stride=97):
+    """Per-ray averages of srp_scene_ray_stats over n_dirs directions spread over sun_dirs."""
+    sd = np.asarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
+    idx = np.linspace(0, len(sd) - 1, min(n_dirs, len(sd))).astype(int)
+    tot = {"rays": 0.0, "segments": 0.0, "nodes": 0.0, "tris": 0.0, "hits": 0.0}
+    for j in idx:
+        p = TraceParams(params.nu, params.nv, params.bounces, params.jitter, params.flux, params.seed,
+                        params.dir_index_base + int(j), params.design_index, 0)
+        st = srp_scene_ray_stats(scene.handle if isinstance(scene, Scene) else scene, sd[j:j + 1], p, pixel_stride)
+        for k in tot:
+            tot[k] += st[k]
+    r, s = max(tot["rays"], 1.0), max(tot["segments"], 1.0)
+    return {"rays": tot["rays"], "segments_per_ray": tot["segments"] / r, "nodes_per_segment": tot["nodes"] / s,
+            "tris_per_segment": tot["tris"] / s, "hits_per_ray": tot["hits"] / r,
+            "bytes_per_ray": (NODE_BYTES * tot["nodes"] + TRI_BYTES * tot["tris"] + HIT_BYTES * tot["hits"]) / r}
 
 
 def srp_scene_destroy(scene):

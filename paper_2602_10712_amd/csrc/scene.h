@@ -1,0 +1,44 @@
+// Scene object of libsrp (host view), shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/srp.h"
+#include "srp_internal.h"
+
+struct srp_scene_s {
+    int device = 0;
+    int64_t n_verts = 0, n_tris = 0;
+    int32_t n_hinges = 0;
+    std::vector<double> rest, cur;       // rest-pose and current (hinge-rotated) vertices
+    std::vector<int32_t> tris, vhinge;
+    std::vector<srp_hinge> hinges;       // axes normalised
+    std::vector<double> angles;
+    double com[3] = {0, 0, 0};
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // current vertex bounding box
+    double L = 0;                        // scene size: twice the largest vertex distance from the mean
+    int32_t n_nodes = 0, depth = 0;
+    std::vector<int32_t> perm;           // BVH triangle position -> original index
+    std::vector<srp::BvhNode> h_nodes;   // host copies for the instrumented traversal
+    std::vector<srp::TriRec> h_tris;
+    srp::BvhNode* d_nodes = nullptr;
+    size_t nodes_cap = 0;
+    srp::TriRec* d_tris = nullptr;
+    size_t tris_cap = 0;
+    float4* d_mat = nullptr;             // BVH order: rho_s, rho_d, p_spec, 0
+    size_t mat_cap = 0;
+    int32_t* d_perm = nullptr;
+    size_t perm_cap = 0;
+    int32_t* d_flag = nullptr;
+    size_t flag_cap = 0;
+    srp::DevFrame* d_frames = nullptr;
+    size_t frames_cap = 0;
+    double* d_partials = nullptr;
+    size_t partials_cap = 0;
+};
+
+// Records `msg` as the thread's last error and returns `st`.
+srp_status srp_fail(srp_status st, const std::string& msg);

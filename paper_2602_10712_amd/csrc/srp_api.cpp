@@ -11,6 +11,7 @@
 
 #include "../../include/srp.h"
 #include "bvh_build.h"
+#include "scene.h"
 #include "srp_internal.h"
 
 namespace {
@@ -51,33 +52,7 @@ hipError_t ensure(T*& ptr, size_t& cap, size_t n)
 
 }  // namespace
 
-struct srp_scene_s {
-    int device = 0;
-    int64_t n_verts = 0, n_tris = 0;
-    int32_t n_hinges = 0;
-    std::vector<double> rest, cur;
-    std::vector<int32_t> tris, vhinge;
-    std::vector<srp_hinge> hinges;
-    std::vector<double> angles;
-    double com[3] = {0, 0, 0};
-    double lo[3], hi[3], L = 0;
-    int32_t n_nodes = 0, depth = 0;
-    std::vector<int32_t> perm;
-    srp::BvhNode* d_nodes = nullptr;
-    size_t nodes_cap = 0;
-    srp::TriRec* d_tris = nullptr;
-    size_t tris_cap = 0;
-    float4* d_mat = nullptr;
-    size_t mat_cap = 0;
-    int32_t* d_perm = nullptr;
-    size_t perm_cap = 0;
-    int32_t* d_flag = nullptr;
-    size_t flag_cap = 0;
-    srp::DevFrame* d_frames = nullptr;
-    size_t frames_cap = 0;
-    double* d_partials = nullptr;
-    size_t partials_cap = 0;
-};
+srp_status srp_fail(srp_status st, const std::string& msg) { return fail(st, msg); }
 
 namespace {
 
@@ -160,6 +135,7 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream)
                              static_cast<float>(n[1]));
         r.f[3] = make_float4(static_cast<float>(n[2]), 0.0f, 0.0f, 0.0f);
     }
+    s->h_nodes = bvh.nodes;
     SRP_HIP(ensure(s->d_nodes, s->nodes_cap, bvh.nodes.size()));
     SRP_HIP(ensure(s->d_tris, s->tris_cap, static_cast<size_t>(s->n_tris)));
     SRP_HIP(ensure(s->d_perm, s->perm_cap, static_cast<size_t>(s->n_tris)));
@@ -169,6 +145,7 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream)
     SRP_HIP(hipMemcpyAsync(s->d_perm, s->perm.data(), s->perm.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                            stream));
     SRP_HIP(hipStreamSynchronize(stream));
+    s->h_tris = std::move(recs);
     return SRP_OK;
 }
 

@@ -18,46 +18,10 @@
 #include <float.h>
 
 #include "srp_internal.h"
+#include "srp_path.h"
 
 namespace srp {
 namespace {
-
-// ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ------------------------------------
-__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
-                                              uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi_b ^ c1 ^ k0;
-        const uint32_t n2 = hi_a ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo_b;
-        c2 = n2;
-        c3 = lo_a;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-__device__ __forceinline__ float unit24(uint32_t x) { return static_cast<float>(x >> 8) * (1.0f / 16777216.0f); }
-
-// ---- frames (FP64) ----------------------------------------------------------------------------
-__device__ void duff_basis(const double n[3], double b1[3], double b2[3])
-{
-    const double s = n[2] >= 0.0 ? 1.0 : -1.0;
-    const double a = -1.0 / (s + n[2]);
-    const double b = n[0] * n[1] * a;
-    b1[0] = 1.0 + s * n[0] * n[0] * a;
-    b1[1] = s * b;
-    b1[2] = -s * n[0];
-    b2[0] = b;
-    b2[1] = s + n[1] * n[1] * a;
-    b2[2] = -n[1];
-}
 
 struct BoxArg {
     double lo[3], hi[3];
@@ -69,62 +33,16 @@ __global__ void k_frames(const double* __restrict__ sun, int64_t D, BoxArg box, 
 {
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j >= D) return;
-    const double sx = sun[3 * j], sy = sun[3 * j + 1], sz = sun[3 * j + 2];
-    const double len = sqrt(sx * sx + sy * sy + sz * sz);
-    const double d[3] = {-sx / len, -sy / len, -sz / len};
-    double u[3], v[3], o0[3], du, dv;
+    const double s[3] = {sun[3 * j], sun[3 * j + 1], sun[3 * j + 2]};
+    double f[12];
     if (caller) {
-        const double* c = caller + 12 * j;
-        for (int a = 0; a < 3; ++a) {
-            u[a] = c[a];
-            v[a] = c[3 + a];
-            o0[a] = c[6 + a];
-        }
-        du = c[9];
-        dv = c[10];
+        for (int a = 0; a < 12; ++a) f[a] = caller[12 * j + a];
     } else {
-        duff_basis(d, u, v);
-        double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, smin = INFINITY;
-        for (int c = 0; c < 8; ++c) {
-            const double p[3] = {(c & 1) ? box.hi[0] : box.lo[0], (c & 2) ? box.hi[1] : box.lo[1],
-                                 (c & 4) ? box.hi[2] : box.lo[2]};
-            const double pu = p[0] * u[0] + p[1] * u[1] + p[2] * u[2];
-            const double pv = p[0] * v[0] + p[1] * v[1] + p[2] * v[2];
-            const double ps = p[0] * d[0] + p[1] * d[1] + p[2] * d[2];
-            umin = fmin(umin, pu);
-            umax = fmax(umax, pu);
-            vmin = fmin(vmin, pv);
-            vmax = fmax(vmax, pv);
-            smin = fmin(smin, ps);
-        }
-        const double s0 = smin - 0.01 * L;
-        for (int a = 0; a < 3; ++a) o0[a] = s0 * d[a] + umin * u[a] + vmin * v[a];
-        du = (umax - umin) / nu;
-        dv = (vmax - vmin) / nv;
+        frame_from_box(s, box.lo, box.hi, L, nu, nv, f);
     }
-    if (f64) {
-        double* o = f64 + 12 * j;
-        for (int a = 0; a < 3; ++a) {
-            o[a] = u[a];
-            o[3 + a] = v[a];
-            o[6 + a] = o0[a];
-        }
-        o[9] = du;
-        o[10] = dv;
-        o[11] = 0.0;
-    }
-    if (f32) {
-        DevFrame fr;
-        for (int a = 0; a < 3; ++a) {
-            fr.o0[a] = static_cast<float>(o0[a]);
-            fr.U[a] = static_cast<float>(du * u[a]);
-            fr.V[a] = static_cast<float>(dv * v[a]);
-            fr.d[a] = static_cast<float>(d[a]);
-        }
-        fr.w = static_cast<float>(flux * du * dv / kSpeedOfLight);
-        fr.pad[0] = fr.pad[1] = fr.pad[2] = 0.0f;
-        f32[j] = fr;
-    }
+    if (f64)
+        for (int a = 0; a < 12; ++a) f64[12 * j + a] = f[a];
+    if (f32) f32[j] = frame_to_device(s, f, flux);
 }
 
 // ---- materials ----------------------------------------------------------------------------------
@@ -153,24 +71,20 @@ __global__ void k_pack_mat(const float* __restrict__ rs, const float* __restrict
 }
 
 // ---- traversal -------------------------------------------------------------------------------------
-__device__ __forceinline__ float safe_rcp(float x)
-{
-    const float m = 1e-20f;
-    return 1.0f / (fabsf(x) < m ? copysignf(m, x) : x);
-}
-
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Closest front-facing hit of each lane's ray (o, d) among all triangles except `skip` (the
-// triangle the ray leaves).  Lanes with alive == false never hit.  The traversal is
-// wavefront-coherent: one node sequence for the whole wave, a child is entered when any lane's
-// ray overlaps it, and the nearer child (by majority over the lanes that overlap both) first.
+// triangle the ray leaves); an exact tie in t goes to the lower original triangle index.  Lanes
+// with alive == false never hit.  The traversal is wavefront-coherent: one node sequence for the
+// whole wave (so node and triangle records arrive through scalar loads), a child is entered when
+// any lane's ray overlaps its box, the nearer child first by majority over the lanes that overlap
+// both, and the stack of deferred children is wave-uniform in LDS.
 __device__ __forceinline__ void closest_hit(const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris,
-                                            float ox, float oy, float oz, float dx, float dy, float dz, bool alive,
-                                            int skip, float& t_out, int& hit_out, int* __restrict__ stack)
+                                            const float o[3], const float d[3], bool alive, int skip, float& t_out,
+                                            int& hit_out, int* __restrict__ stack)
 {
-    const float ix = safe_rcp(dx), iy = safe_rcp(dy), iz = safe_rcp(dz);
-    const float nx = -ox * ix, ny = -oy * iy, nz = -oz * iz;
+    const float ix = safe_rcp(d[0]), iy = safe_rcp(d[1]), iz = safe_rcp(d[2]);
+    const float nx = -o[0] * ix, ny = -o[1] * iy, nz = -o[2] * iz;
     float tbest = alive ? FLT_MAX : -1.0f;
     int hit = -1;
     int hit_id = 0x7fffffff;
@@ -202,11 +116,9 @@ __device__ __forceinline__ void closest_hit(const BvhNode* __restrict__ nodes, c
             if (m0 && m1) {
                 const uint64_t first1 = wave_ballot(h0 && h1 && tn1 < tn0);
                 const bool swap = 2 * __popcll(first1) > __popcll(m0 & m1);
-                const int nearc = swap ? c1 : c0;
-                const int farc = swap ? c0 : c1;
-                stack[sp] = farc;
+                stack[sp] = swap ? c0 : c1;
                 ++sp;
-                cur = nearc;
+                cur = swap ? c1 : c0;
             } else if (m0) {
                 cur = c0;
             } else if (m1) {
@@ -226,23 +138,9 @@ __device__ __forceinline__ void closest_hit(const BvhNode* __restrict__ nodes, c
                 const float4 g0 = T->f[0];
                 const float4 g1 = T->f[1];
                 const float4 g2 = T->f[2];
-                // Moller-Trumbore (1997), one-sided: det > 0 <=> d . n < 0
-                const float px = dy * g2.z - dz * g2.y;
-                const float py = dz * g2.x - dx * g2.z;
-                const float pz = dx * g2.y - dy * g2.x;
-                const float det = g1.x * px + g1.y * py + g1.z * pz;
-                const float tx = ox - g0.x, ty = oy - g0.y, tz = oz - g0.z;
-                const float uu = tx * px + ty * py + tz * pz;
-                const float qx = ty * g1.z - tz * g1.y;
-                const float qy = tz * g1.x - tx * g1.z;
-                const float qz = tx * g1.y - ty * g1.x;
-                const float vv = dx * qx + dy * qy + dz * qz;
-                const float tnum = g2.x * qx + g2.y * qy + g2.z * qz;
-                const float t = tnum / det;
+                const float t = tri_hit(o, d, g0, g1, g2);
                 const int id = __float_as_int(g0.w);
-                const bool ok = det > 0.0f && uu >= 0.0f && uu <= det && vv >= 0.0f && uu + vv <= det && t > 0.0f &&
-                                tri != skip && (t < tbest || (t == tbest && id < hit_id));
-                if (ok) {
+                if (t > 0.0f && tri != skip && (t < tbest || (t == tbest && id < hit_id))) {
                     tbest = t;
                     hit = tri;
                     hit_id = id;
@@ -264,6 +162,24 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// Pixel of lane `lane` in wave tile `tile`: 8 x 8 pixel tiles in row-major order (trace mode) or
+// 64 consecutive entries of an explicit pixel list (records mode).
+template <bool RECORDS>
+__device__ __forceinline__ bool tile_pixel(const TraceArgs& a, int64_t tile, int lane, int64_t& pixel, int64_t& rec)
+{
+    if (RECORDS) {
+        rec = tile * 64 + lane;
+        const bool valid = rec < a.n_pix;
+        pixel = valid ? (a.pix ? a.pix[rec] : rec) : 0;
+        return valid;
+    }
+    rec = 0;
+    const int64_t tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int64_t pi = tx * kTileW + (lane & 7), pk = ty * kTileH + (lane >> 3);
+    pixel = pi + pk * a.nu;
+    return pi < a.nu && pk < a.nv;
+}
+
 template <bool RECORDS>
 __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
 {
@@ -279,46 +195,27 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
     const TriRec* __restrict__ tris = a.tris;
     int* stack = s_stack[wave];
 
-    float aF0 = 0.0f, aF1 = 0.0f, aF2 = 0.0f, aT0 = 0.0f, aT1 = 0.0f, aT2 = 0.0f;
+    float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int m = 0; m < a.tiles_per_wave; ++m) {
         const int64_t tile = (static_cast<int64_t>(blk) * a.tiles_per_wave + m) * kWaves + wave;
         if (tile >= a.tiles_per_dir) break;
-        int64_t pixel = 0, rec = 0;
-        bool valid;
-        if (RECORDS) {
-            rec = tile * 64 + lane;
-            valid = rec < a.n_pix;
-            if (valid) pixel = a.pix ? a.pix[rec] : rec;
-        } else {
-            const int64_t tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-            const int64_t pi = tx * kTileW + (lane & 7), pk = ty * kTileH + (lane >> 3);
-            valid = pi < a.nu && pk < a.nv;
-            pixel = pi + pk * a.nu;
-        }
+        int64_t pixel, rec;
+        const bool valid = tile_pixel<RECORDS>(a, tile, lane, pixel, rec);
         const int32_t pi = static_cast<int32_t>(pixel % a.nu);
         const int32_t pk = static_cast<int32_t>(pixel / a.nu);
-        float ja = 0.5f, jb = 0.5f;
-        if (a.jitter) {
-            uint32_t c0 = static_cast<uint32_t>(pixel), c1 = dir_global, c2 = 0u, c3 = a.design_index;
-            philox4x32_10(c0, c1, c2, c3, a.seed_lo, a.seed_hi);
-            ja = unit24(c0);
-            jb = unit24(c1);
-        }
-        const float fi = static_cast<float>(pi) + ja, fk = static_cast<float>(pk) + jb;
-        float ox = fr.o0[0] + fi * fr.U[0] + fk * fr.V[0];
-        float oy = fr.o0[1] + fi * fr.U[1] + fk * fr.V[1];
-        float oz = fr.o0[2] + fi * fr.U[2] + fk * fr.V[2];
-        float dx = fr.d[0], dy = fr.d[1], dz = fr.d[2];
+        float o[3], d[3];
+        primary_ray(fr, pi, pk, static_cast<uint32_t>(pixel), dir_global, a.design_index, a.seed_lo, a.seed_hi,
+                    a.jitter != 0, o, d);
         float w = fr.w;
         bool alive = valid;
         int skip = -1;
-        float rF0 = 0.0f, rF1 = 0.0f, rF2 = 0.0f, rT0 = 0.0f, rT1 = 0.0f, rT2 = 0.0f;
+        float ray[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         int b_done = 0;
         for (int b = 1; b <= a.bounces; ++b) {
             if (wave_ballot(alive) == 0) break;
             float t;
             int hit;
-            closest_hit(nodes, tris, ox, oy, oz, dx, dy, dz, alive, skip, t, hit, stack);
+            closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
             if (!alive) continue;
             if (hit < 0) {
                 alive = false;
@@ -328,103 +225,36 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
             const float4 mt = a.mat[hit];
             if (RECORDS) a.rec_hit[(j * a.n_pix + rec) * a.bounces + (b - 1)] = __float_as_int(tr.f[0].w);
             b_done = b;
-            const float nx = tr.f[1].w, ny = tr.f[2].w, nz = tr.f[3].x;
-            const float xx = ox + t * dx, xy = oy + t * dy, xz = oz + t * dz;
-            const float lx = xx - a.com[0], ly = xy - a.com[1], lz = xz - a.com[2];
-            const float cth = -(dx * nx + dy * ny + dz * nz);
-            const float rx = dx + 2.0f * cth * nx, ry = dy + 2.0f * cth * ny, rz = dz + 2.0f * cth * nz;
-            // incident momentum, minus what leaves
-            float ex, ey, ez;  // outgoing momentum (force units)
-            float gx = w * dx, gy = w * dy, gz = w * dz;
-            const float rs = mt.x, rd = mt.y, ps = mt.z;
-            bool last = (b == a.bounces) || (rs == 0.0f && rd == 0.0f);
-            float odx = 0.0f, ody = 0.0f, odz = 0.0f, w2 = 0.0f;
-            if (last) {
-                const float kd = (2.0f / 3.0f) * rd;
-                ex = w * (rs * rx + kd * nx);
-                ey = w * (rs * ry + kd * ny);
-                ez = w * (rs * rz + kd * nz);
-            } else {
-                uint32_t c0 = static_cast<uint32_t>(pixel), c1 = dir_global, c2 = static_cast<uint32_t>(b),
-                         c3 = a.design_index;
-                philox4x32_10(c0, c1, c2, c3, a.seed_lo, a.seed_hi);
-                const float ue = unit24(c0), u1 = unit24(c1), u2 = unit24(c2);
-                if (ue < ps) {
-                    odx = rx;
-                    ody = ry;
-                    odz = rz;
-                    w2 = w * rs / ps;
-                } else {
-                    // cosine-weighted direction about n (Malley's method) in the Duff basis of n
-                    const float rad = sqrtf(u1);
-                    float sphi, cphi;
-                    __sincosf(6.283185307179586f * u2, &sphi, &cphi);
-                    const float px = rad * cphi, py = rad * sphi, pz = sqrtf(fmaxf(0.0f, 1.0f - u1));
-                    const float sg = nz >= 0.0f ? 1.0f : -1.0f;
-                    const float aa = -1.0f / (sg + nz);
-                    const float bb = nx * ny * aa;
-                    const float t1x = 1.0f + sg * nx * nx * aa, t1y = sg * bb, t1z = -sg * nx;
-                    const float t2x = bb, t2y = sg + ny * ny * aa, t2z = -ny;
-                    odx = px * t1x + py * t2x + pz * nx;
-                    ody = px * t1y + py * t2y + pz * ny;
-                    odz = px * t1z + py * t2z + pz * nz;
-                    w2 = w * rd / (1.0f - ps);
-                }
-                ex = w2 * odx;
-                ey = w2 * ody;
-                ez = w2 * odz;
-            }
-            gx -= ex;
-            gy -= ey;
-            gz -= ez;
-            rF0 += gx;
-            rF1 += gy;
-            rF2 += gz;
-            rT0 += ly * gz - lz * gy;
-            rT1 += lz * gx - lx * gz;
-            rT2 += lx * gy - ly * gx;
-            if (last) {
-                alive = false;
-            } else {
-                ox = xx + a.eps * nx;
-                oy = xy + a.eps * ny;
-                oz = xz + a.eps * nz;
-                dx = odx;
-                dy = ody;
-                dz = odz;
-                w = w2;
-                skip = hit;
-            }
+            const float n[3] = {tr.f[1].w, tr.f[2].w, tr.f[3].x};
+            float x[3], g[3];
+            alive = interact(o, d, w, t, n, mt.x, mt.y, mt.z, b, a.bounces, static_cast<uint32_t>(pixel), dir_global,
+                             a.design_index, a.seed_lo, a.seed_hi, a.eps, x, g);
+            const float lx = x[0] - a.com[0], ly = x[1] - a.com[1], lz = x[2] - a.com[2];
+            ray[0] += g[0];
+            ray[1] += g[1];
+            ray[2] += g[2];
+            ray[3] += ly * g[2] - lz * g[1];
+            ray[4] += lz * g[0] - lx * g[2];
+            ray[5] += lx * g[1] - ly * g[0];
+            skip = hit;
         }
         if (RECORDS && valid) {
             for (int b = b_done + 1; b <= a.bounces; ++b) a.rec_hit[(j * a.n_pix + rec) * a.bounces + (b - 1)] = -1;
             if (a.rec_force) {
                 float* rf = a.rec_force + (j * a.n_pix + rec) * 3;
-                rf[0] = rF0;
-                rf[1] = rF1;
-                rf[2] = rF2;
+                rf[0] = ray[0];
+                rf[1] = ray[1];
+                rf[2] = ray[2];
             }
         }
-        aF0 += rF0;
-        aF1 += rF1;
-        aF2 += rF2;
-        aT0 += rT0;
-        aT1 += rT1;
-        aT2 += rT2;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += ray[c];
     }
-    aF0 = wave_sum(aF0);
-    aF1 = wave_sum(aF1);
-    aF2 = wave_sum(aF2);
-    aT0 = wave_sum(aT0);
-    aT1 = wave_sum(aT1);
-    aT2 = wave_sum(aT2);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] = wave_sum(acc[c]);
     if (lane == 0) {
-        s_red[wave][0] = aF0;
-        s_red[wave][1] = aF1;
-        s_red[wave][2] = aF2;
-        s_red[wave][3] = aT0;
-        s_red[wave][4] = aT1;
-        s_red[wave][5] = aT2;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s_red[wave][c] = acc[c];
     }
     __syncthreads();
     if (threadIdx.x < 6) {
