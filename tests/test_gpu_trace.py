@@ -25,6 +25,15 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def torque_err(T, T_ref, F_ref, verts):
+    """Torque error on the scale a force of this size can produce: ||T - T_ref|| / ((L/2) ||F_ref||),
+    L = twice the largest vertex distance from the vertex mean.  (A nearly symmetric body has a small
+    net torque, so one degenerate ray with a different hit moves its relative error far more than
+    the force's.)"""
+    L = 2.0 * np.linalg.norm(verts - verts.mean(0), axis=1).max()
+    return float(np.linalg.norm(T - T_ref) / max(0.5 * L * np.linalg.norm(F_ref), 1e-300))
+
+
 def make_scene(mesh, rs, rd, angles=None, p_spec=None):
     p = _lib()
     sc = p.Scene.from_mesh(mesh)
@@ -54,8 +63,8 @@ def test_box_wing_full_config():
     F, T = sc.trace(sun, params)
     torch.cuda.synchronize()
     ref = oracle.trace(m.verts, m.tris, rs, rd, sun, nu=256, nv=256, bounces=1, seed=2)
-    eF, eT = rel_l2(F.cpu().numpy(), ref.force), rel_l2(T.cpu().numpy(), ref.torque)
-    print(f"box-wing force rel L2 {eF:.3e} torque rel L2 {eT:.3e}")
+    eF, eT = rel_l2(F.cpu().numpy(), ref.force), torque_err(T.cpu().numpy(), ref.torque, ref.force, m.verts)
+    print(f"box-wing force rel L2 {eF:.3e} torque err {eT:.3e}")
     assert eF <= 1e-4 and eT <= 1e-4
     # per-ray hits on 4 directions, all pixels
     sel = [0, 17, 40, 63]
@@ -88,8 +97,8 @@ def test_meo_small_hits_and_force(bounces):
     orc = oracle.trace(V_ref, m.tris, rs, rd, sun, nu=nu, nv=nv, bounces=bounces, seed=7, records=True)
     frac = check_hits(hp.cpu().numpy(), orc, f"meo B={bounces}")
     assert frac < 0.03
-    eF, eT = rel_l2(F.cpu().numpy(), orc.force), rel_l2(T.cpu().numpy(), orc.torque)
-    print(f"meo B={bounces} force rel L2 {eF:.3e} torque rel L2 {eT:.3e}")
+    eF, eT = rel_l2(F.cpu().numpy(), orc.force), torque_err(T.cpu().numpy(), orc.torque, orc.force, V_ref)
+    print(f"meo B={bounces} force rel L2 {eF:.3e} torque err {eT:.3e}")
     assert eF <= 1e-4 and eT <= 1e-4
     # per-ray force on the non-degenerate paths
     ok = ~orc.degen.any(-1)
@@ -185,3 +194,34 @@ def test_invalid_arguments_raise():
     # zero directions is a no-op
     F, T = sc.trace(np.zeros((0, 3)), p.TraceParams(nu=4, nv=4))
     assert F.shape == (0, 3)
+
+
+def test_full_size_meo_sampled():
+    """The benchmark workload itself (20.6k tris, 1024 dirs x 1024 x 1024 rays, 3 bounces, the same
+    launch configuration): the force of one sampled direction against the oracle over its full
+    grid, and per-ray hit indices of 4096 sampled pixels in 6 sampled directions."""
+    m = si.meo_satellite()
+    rs, rd = si.materials(m.n_tris, 1)
+    sun = si.fibonacci_dirs(1024)
+    p = _lib()
+    sc = make_scene(m, rs, rd, angles=[0.0, 0.0])
+    params = p.TraceParams(nu=1024, nv=1024, bounces=3, jitter=1, seed=2)
+    F, T = sc.trace(sun, params)
+    torch.cuda.synchronize()
+    F = F.cpu().numpy()
+    T = T.cpu().numpy()
+    assert np.all(np.isfinite(F)) and np.all(np.isfinite(T))
+    j = 357
+    ref = oracle.trace(m.verts, m.tris, rs, rd, sun[j:j + 1], nu=1024, nv=1024, bounces=3, seed=2, dir_index_base=j)
+    eF, eT = rel_l2(F[j:j + 1], ref.force), torque_err(T[j:j + 1], ref.torque, ref.force, m.verts)
+    print(f"full-size dir {j}: force rel L2 {eF:.3e}, torque err {eT:.3e}, "
+          f"torque rel L2 {rel_l2(T[j:j + 1], ref.torque):.3e}")
+    assert eF <= 1e-4 and eT <= 1e-4
+    rng = np.random.default_rng(12)
+    pix = np.sort(rng.choice(1024 * 1024, 4096, replace=False)).astype(np.int64)
+    for jj in (0, 211, 512, 777, 900, 1023):
+        pj = p.TraceParams(nu=1024, nv=1024, bounces=3, jitter=1, seed=2, dir_index_base=jj)
+        hp, _ = sc.records(sun[jj:jj + 1], pj, pix=pix)
+        orc = oracle.trace(m.verts, m.tris, rs, rd, sun[jj:jj + 1], nu=1024, nv=1024, bounces=3, seed=2,
+                           dir_index_base=jj, pix=pix, records=True)
+        check_hits(hp.cpu().numpy(), orc, f"full-size dir {jj}")
