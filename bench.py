@@ -39,9 +39,11 @@ def parse():
     ap.add_argument("--dirs", type=int, default=1024)
     ap.add_argument("--grid", type=int, default=1024)
     ap.add_argument("--bounces", type=int, default=3)
+    ap.add_argument("--adjoint-grid", type=int, default=512)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-dirs", type=int, default=32)
-    ap.add_argument("--cpu-sample-grid", type=int, default=128)
+    ap.add_argument("--cpu-sample-dirs", type=int, default=64)
+    ap.add_argument("--cpu-sample-grid", type=int, default=256)
     return ap.parse_args()
 
 
@@ -109,6 +111,39 @@ def main():
     mrays = rays / (ms_per_step * 1e-3) / 1e6
     log(f"forward: {ms_per_step:.2f} ms/step, {mrays:.1f} Mrays/s (wall {wall:.2f} s)")
 
+    # ---- forward + adjoint (differentiable workload: 512^2 rays per direction) --------------------
+    fwd_adj = None
+    if not args.no_adjoint:
+        g = args.adjoint_grid
+        pa = p.TraceParams(nu=g, nv=g, bounces=args.bounces, jitter=1, seed=2)
+        gen = torch.Generator(device="cpu").manual_seed(3)
+        gF = torch.randn((D, 3), generator=gen, dtype=torch.float64).to(dev)
+        gT = torch.randn((D, 3), generator=gen, dtype=torch.float64).to(dev)
+        g_rs = torch.zeros(mesh.n_tris, dtype=torch.float32, device=dev)
+        g_rd = torch.zeros(mesh.n_tris, dtype=torch.float32, device=dev)
+        g_h = torch.zeros(2, dtype=torch.float64, device=dev)
+
+        def step_adj():
+            p.srp_trace(sc.handle, sun_d, pa, F, T, stream=stream.cuda_stream)
+            p.srp_trace_adjoint(sc.handle, sun_d, pa, gF, gT, g_rs, g_rd, g_h, stream=stream.cuda_stream)
+
+        for i in range(args.warmup):
+            step_adj()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(args.steps):
+            step_adj()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_adj = e0.elapsed_time(e1) / args.steps
+        rays_a = float(D) * g * g
+        fwd_adj = {"value": round(rays_a / (ms_adj * 1e-3) / 1e6, 2), "unit": "Mrays/s", "ms_per_step": round(ms_adj, 3),
+                   "workload": f"{D} dirs x {g}x{g} rays, {args.bounces} bounces: forward trace + adjoint replay "
+                               "(d/d rho_s, rho_d per facet, d/d 2 hinge angles)"}
+        log(f"forward+adjoint: {ms_adj:.2f} ms/step, {fwd_adj['value']:.1f} Mrays/s")
+
     # ---- roofline of the dominant kernel --------------------------------------------------------
     roofline = None
     try:
@@ -152,7 +187,7 @@ def main():
                                f"{args.grid}x{args.grid} rays, {args.bounces} bounces, forward",
                    "tris": mesh.n_tris, "dirs": D, "grid": args.grid, "bounces": args.bounces,
                    "bvh_nodes": info["n_nodes"], "bvh_build_s": round(build_s, 4)},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "fwd_adjoint": fwd_adj,
     }
     print(json.dumps(out), flush=True)
 

@@ -138,6 +138,52 @@ srp_status srp_scene_ray_stats(srp_scene scene, const double* sun_dirs, int64_t 
 
 srp_status srp_scene_destroy(srp_scene scene);
 
+/* ---------------------------------------------------------------------------------------------
+ * Force surrogate (paper Sec. 3.3, "Representation": an MLP maps light direction and design
+ * parameters to force and is trained with Adam on simulator samples).  Layers:
+ * n_in -> width (SiLU) -> ... depth hidden layers ... -> n_out (linear).  Parameters are FP32
+ * masters in the flat order W0 [width][n_in], b0 [width], W1, b1, ..., W_out [n_out][width],
+ * b_out [n_out].  Products use BF16 operands (round to nearest even) with FP32 accumulation;
+ * bias, SiLU and gradients dL/dz are FP32 and are rounded to BF16 where they enter a product.
+ * Initial weights: U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from Philox draws keyed by `seed`.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct srp_mlp_s* srp_mlp;
+
+/* 1 <= n_in, n_out <= 64; 1 <= depth <= 16; width a multiple of 8 in [8, 4096]. */
+srp_status srp_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, uint64_t seed, srp_mlp* out);
+
+srp_status srp_mlp_num_params(srp_mlp mlp, int64_t* n);
+
+/* y = MLP(x): x device float [N][n_in], y device float [N][n_out].  keep_activations = 1 keeps
+ * the pre-activations and BF16 activations for a following srp_mlp_backward on the same x and N
+ * (library-owned workspace); 0 runs the inference path. */
+srp_status srp_mlp_forward(srp_mlp mlp, const float* x, int64_t N, float* y, int32_t keep_activations, void* stream);
+
+/* Back-propagates g_y = dL/dy (device float [N][n_out]) through the kept activations: weight and
+ * bias gradients are ADDED to the library's gradient buffer; g_x (device float [N][n_in], may be
+ * NULL) receives dL/dx. */
+srp_status srp_mlp_backward(srp_mlp mlp, const float* g_y, int64_t N, float* g_x, void* stream);
+
+/* Adam (Kingma & Ba 2015) with bias correction on the FP32 masters, then clears the gradients
+ * and refreshes the BF16 copies. */
+srp_status srp_mlp_adam_step(srp_mlp mlp, float lr, float beta1, float beta2, float eps, void* stream);
+
+srp_status srp_mlp_zero_grad(srp_mlp mlp, void* stream);
+
+/* Mean squared error over the N x n_out entries: loss (device double [1]) and
+ * g_y = 2 (y - target) / (N n_out) (device float [N][n_out]). */
+srp_status srp_mlp_mse(srp_mlp mlp, const float* y, const float* target, int64_t N, float* g_y, double* loss,
+                       void* stream);
+
+/* Checkpoint / resume: host float arrays [n] (n = srp_mlp_num_params; any pointer may be NULL) of
+ * the masters, gradients (get only), Adam moments, and the Adam step count.  Synchronous. */
+srp_status srp_mlp_get_params(srp_mlp mlp, float* params, float* grads, float* adam_m, float* adam_v, int64_t* step,
+                              int64_t n);
+srp_status srp_mlp_set_params(srp_mlp mlp, const float* params, const float* adam_m, const float* adam_v,
+                              int64_t step, int64_t n);
+
+srp_status srp_mlp_destroy(srp_mlp mlp);
+
 /* Waits for `stream` and reports any pending device error as SRP_EDEVICE. */
 srp_status srp_sync(void* stream);
 

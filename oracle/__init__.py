@@ -55,6 +55,15 @@ def lib():
                                    ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, P, ctypes.c_int64,
                                    P, P, P, P, P, P, ctypes.c_int32]
         L.oracle_trace.restype = ctypes.c_int
+        L.oracle_trace_adjoint_rho.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, P,
+                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, P,
+                                               ctypes.c_int64, P, P, P, P, ctypes.c_int32]
+        L.oracle_trace_adjoint_rho.restype = ctypes.c_int
+        L.oracle_trace_frozen.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, P,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                          ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, P, ctypes.c_int64, P, P, P]
+        L.oracle_trace_frozen.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -141,3 +150,64 @@ def trace(verts, tris, rho_s, rho_d, sun_dirs, *, nu: int, nv: int, bounces: int
     if st != 0:
         raise ValueError(f"oracle_trace failed ({st})")
     return TraceResult(force, torque, hp, dg, rf, rt)
+
+
+def trace_adjoint_rho(verts, tris, rho_s, rho_d, sun_dirs, g_force, g_torque=None, *, nu: int, nv: int, bounces: int,
+                      jitter: bool = True, flux: float = 1361.0, seed: int = 0, dir_index_base: int = 0,
+                      design_index: int = 0, p_spec=None, com=None, frames_in=None, pix=None,
+                      threads: int | None = None):
+    """FP64 dL/d rho_s, dL/d rho_d [n_tris] of L = sum_j g_force[j] . F_j + g_torque[j] . tau_j for the
+    estimator with frozen counters and specular-sampling probabilities (see srp_oracle.c)."""
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    rs = np.ascontiguousarray(rho_s, dtype=np.float32)
+    rd = np.ascontiguousarray(rho_d, dtype=np.float32)
+    ps = None if p_spec is None else np.ascontiguousarray(p_spec, dtype=np.float32)
+    c = None if com is None else np.ascontiguousarray(com, dtype=np.float64)
+    sun = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
+    D = len(sun)
+    fr = None if frames_in is None else np.ascontiguousarray(frames_in, dtype=np.float64).reshape(D, 12)
+    px = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
+    n_pix = nu * nv if px is None else len(px)
+    gF = np.ascontiguousarray(g_force, dtype=np.float64).reshape(D, 3)
+    gT = None if g_torque is None else np.ascontiguousarray(g_torque, dtype=np.float64).reshape(D, 3)
+    g_rs = np.zeros(len(tris))
+    g_rd = np.zeros(len(tris))
+    if threads is None:
+        threads = os.cpu_count() or 1
+    st = lib().oracle_trace_adjoint_rho(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd), _ptr(ps),
+                                        _ptr(c), _ptr(sun), D, _ptr(fr), nu, nv, bounces, int(bool(jitter)),
+                                        float(flux), int(seed), int(dir_index_base), int(design_index), _ptr(px),
+                                        n_pix, _ptr(gF), _ptr(gT), _ptr(g_rs), _ptr(g_rd), int(threads))
+    if st != 0:
+        raise ValueError(f"oracle_trace_adjoint_rho failed ({st})")
+    return g_rs, g_rd
+
+
+def trace_frozen(verts, verts0, tris, rho_s, rho_d, sun_dirs, ref_hits, frames_in, *, nu: int, nv: int, bounces: int,
+                 jitter: bool = True, flux: float = 1361.0, seed: int = 0, dir_index_base: int = 0,
+                 design_index: int = 0, p_spec=None, com=None, pix=None):
+    """Frozen-visibility estimate (F, tau) at vertices `verts` with the facet sequences `ref_hits`
+    [D][n_pix][bounces] recorded at the reference vertices `verts0` (see srp_oracle.c)."""
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    verts0 = np.ascontiguousarray(verts0, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    rs = np.ascontiguousarray(rho_s, dtype=np.float32)
+    rd = np.ascontiguousarray(rho_d, dtype=np.float32)
+    ps = None if p_spec is None else np.ascontiguousarray(p_spec, dtype=np.float32)
+    c = None if com is None else np.ascontiguousarray(com, dtype=np.float64)
+    sun = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
+    D = len(sun)
+    fr = np.ascontiguousarray(frames_in, dtype=np.float64).reshape(D, 12)
+    px = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
+    n_pix = nu * nv if px is None else len(px)
+    hits = np.ascontiguousarray(ref_hits, dtype=np.int32).reshape(D, n_pix, bounces)
+    F = np.zeros((D, 3))
+    T = np.zeros((D, 3))
+    st = lib().oracle_trace_frozen(_ptr(verts), _ptr(verts0), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd),
+                                   _ptr(ps), _ptr(c), _ptr(sun), D, _ptr(fr), nu, nv, bounces, int(bool(jitter)),
+                                   float(flux), int(seed), int(dir_index_base), int(design_index), _ptr(px), n_pix,
+                                   _ptr(hits), _ptr(F), _ptr(T))
+    if st != 0:
+        raise ValueError(f"oracle_trace_frozen failed ({st})")
+    return F, T

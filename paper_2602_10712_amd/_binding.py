@@ -47,7 +47,18 @@ _sigs = {
     "srp_trace": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P],
     "srp_trace_records": [P, P, I64, ctypes.POINTER(TraceParams), P, P, I64, P, P, P],
     "srp_scene_ray_stats": [P, P, I64, ctypes.POINTER(TraceParams), P, I64, P],
+    "srp_trace_adjoint": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P, P, P, P],
     "srp_scene_destroy": [P],
+    "srp_mlp_create": [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)],
+    "srp_mlp_num_params": [P, ctypes.POINTER(I64)],
+    "srp_mlp_forward": [P, P, I64, P, I32, P],
+    "srp_mlp_backward": [P, P, I64, P, P],
+    "srp_mlp_adam_step": [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
+    "srp_mlp_zero_grad": [P, P],
+    "srp_mlp_mse": [P, P, P, I64, P, P, P],
+    "srp_mlp_get_params": [P, P, P, P, P, ctypes.POINTER(I64), I64],
+    "srp_mlp_set_params": [P, P, P, P, I64, I64],
+    "srp_mlp_destroy": [P],
     "srp_sync": [P],
 }
 for _name, _args in _sigs.items():
@@ -172,6 +183,23 @@ def srp_trace_records(scene, sun_dirs, params: TraceParams, hit_prim, ray_force=
                                   _dptr(pix), n_pix, _dptr(hit_prim), _dptr(ray_force), _stream(stream)))
 
 
+def srp_trace_adjoint(scene, sun_dirs, params: TraceParams, g_force, g_torque=None, g_rho_s=None, g_rho_d=None,
+                      g_hinge=None, frames=None, stream=None):
+    """Adds dL/d rho_s, dL/d rho_d (float32 [n_tris]) and dL/d hinge (float64 [n_hinges]) for
+    L = sum_j g_force[j] . F_j + g_torque[j] . tau_j (see srp.h)."""
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(g_force, torch.float64, "g_force")
+    _dtype_check(g_torque, torch.float64, "g_torque")
+    _dtype_check(g_rho_s, torch.float32, "g_rho_s")
+    _dtype_check(g_rho_d, torch.float32, "g_rho_d")
+    _dtype_check(g_hinge, torch.float64, "g_hinge")
+    _dtype_check(frames, torch.float64, "frames")
+    _check(_lib.srp_trace_adjoint(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params), _dptr(frames),
+                                  _dptr(g_force), _dptr(g_torque), _dptr(g_rho_s), _dptr(g_rho_d), _dptr(g_hinge),
+                                  _stream(stream)))
+
+
 def srp_scene_ray_stats(scene, sun_dirs, params: TraceParams, pixel_stride=1, frames=None):
     """Host arrays in, dict out: rays, segments, nodes, tris, hits (see srp.h)."""
     sd = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
@@ -251,6 +279,20 @@ class Scene:
         srp_trace(self.handle, sd, params, F, T, fr, stream)
         return F, T
 
+    def adjoint(self, sun_dirs, params: TraceParams, g_force, g_torque=None, frames=None, stream=None):
+        """Returns (dL/d rho_s, dL/d rho_d, dL/d hinge) as new device tensors."""
+        import torch
+        dev = torch.device("cuda")
+        sd = torch.as_tensor(sun_dirs, dtype=torch.float64, device=dev).contiguous()
+        gF = torch.as_tensor(g_force, dtype=torch.float64, device=dev).contiguous()
+        gT = None if g_torque is None else torch.as_tensor(g_torque, dtype=torch.float64, device=dev).contiguous()
+        fr = None if frames is None else torch.as_tensor(frames, dtype=torch.float64, device=dev).contiguous()
+        grs = torch.zeros(self.n_tris, dtype=torch.float32, device=dev)
+        grd = torch.zeros(self.n_tris, dtype=torch.float32, device=dev)
+        gh = torch.zeros(max(self.n_hinges, 1), dtype=torch.float64, device=dev)
+        srp_trace_adjoint(self.handle, sd, params, gF, gT, grs, grd, gh if self.n_hinges else None, fr, stream)
+        return grs, grd, gh[:self.n_hinges]
+
     def records(self, sun_dirs, params: TraceParams, pix=None, frames=None, stream=None):
         import torch
         sd = torch.as_tensor(sun_dirs, dtype=torch.float64, device="cuda").contiguous()
@@ -266,6 +308,118 @@ class Scene:
     def close(self):
         if getattr(self, "handle", None):
             srp_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------------------------------------
+# surrogate MLP
+# ------------------------------------------------------------------------------------------------
+def srp_mlp_create(n_in=11, width=256, depth=4, n_out=3, seed=0):
+    out = P()
+    _check(_lib.srp_mlp_create(n_in, width, depth, n_out, int(seed), ctypes.byref(out)))
+    return out
+
+
+def srp_mlp_num_params(mlp):
+    n = I64()
+    _check(_lib.srp_mlp_num_params(mlp, ctypes.byref(n)))
+    return n.value
+
+
+def srp_mlp_forward(mlp, x, y, keep_activations=False, stream=None):
+    import torch
+    _dtype_check(x, torch.float32, "x")
+    _dtype_check(y, torch.float32, "y")
+    _check(_lib.srp_mlp_forward(mlp, _dptr(x), x.shape[0], _dptr(y), int(bool(keep_activations)), _stream(stream)))
+
+
+def srp_mlp_backward(mlp, g_y, g_x=None, stream=None):
+    import torch
+    _dtype_check(g_y, torch.float32, "g_y")
+    _dtype_check(g_x, torch.float32, "g_x")
+    _check(_lib.srp_mlp_backward(mlp, _dptr(g_y), g_y.shape[0], _dptr(g_x), _stream(stream)))
+
+
+def srp_mlp_adam_step(mlp, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_lib.srp_mlp_adam_step(mlp, float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def srp_mlp_zero_grad(mlp, stream=None):
+    _check(_lib.srp_mlp_zero_grad(mlp, _stream(stream)))
+
+
+def srp_mlp_mse(mlp, y, target, g_y, loss, stream=None):
+    import torch
+    _dtype_check(y, torch.float32, "y")
+    _dtype_check(target, torch.float32, "target")
+    _dtype_check(g_y, torch.float32, "g_y")
+    _dtype_check(loss, torch.float64, "loss")
+    _check(_lib.srp_mlp_mse(mlp, _dptr(y), _dptr(target), y.shape[0], _dptr(g_y), _dptr(loss), _stream(stream)))
+
+
+def srp_mlp_get_params(mlp):
+    n = srp_mlp_num_params(mlp)
+    p, g, m, v = (np.zeros(n, dtype=np.float32) for _ in range(4))
+    step = I64()
+    _check(_lib.srp_mlp_get_params(mlp, _hptr(p), _hptr(g), _hptr(m), _hptr(v), ctypes.byref(step), n))
+    return {"params": p, "grads": g, "adam_m": m, "adam_v": v, "step": step.value}
+
+
+def srp_mlp_set_params(mlp, params, adam_m=None, adam_v=None, step=0):
+    n = srp_mlp_num_params(mlp)
+    arr = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+    p, m, v = arr(params), arr(adam_m), arr(adam_v)
+    for a in (p, m, v):
+        if a is not None and a.size != n:
+            raise ValueError(f"expected {n} values")
+    _check(_lib.srp_mlp_set_params(mlp, _hptr(p), _hptr(m), _hptr(v), int(step), n))
+
+
+def srp_mlp_destroy(mlp):
+    _check(_lib.srp_mlp_destroy(mlp))
+
+
+class Surrogate:
+    """The force surrogate on the GPU: srp_mlp_* calls with torch tensors."""
+
+    def __init__(self, n_in=11, width=256, depth=4, n_out=3, seed=0):
+        self.n_in, self.width, self.depth, self.n_out = n_in, width, depth, n_out
+        self.handle = srp_mlp_create(n_in, width, depth, n_out, seed)
+        self.n_params = srp_mlp_num_params(self.handle)
+
+    def forward(self, x, keep_activations=False, stream=None):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device="cuda")
+        srp_mlp_forward(self.handle, x, y, keep_activations, stream)
+        return y
+
+    def train_step(self, x, target, lr, betas=(0.9, 0.999), eps=1e-8, stream=None):
+        """One forward + MSE + backward + Adam step; returns the loss as a device double tensor."""
+        import torch
+        y = self.forward(x, keep_activations=True, stream=stream)
+        g_y = torch.empty_like(y)
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        srp_mlp_mse(self.handle, y, target, g_y, loss, stream)
+        srp_mlp_backward(self.handle, g_y, None, stream)
+        srp_mlp_adam_step(self.handle, lr, betas[0], betas[1], eps, stream)
+        return loss
+
+    def get_params(self):
+        return srp_mlp_get_params(self.handle)
+
+    def set_params(self, params, adam_m=None, adam_v=None, step=0):
+        srp_mlp_set_params(self.handle, params, adam_m, adam_v, step)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            srp_mlp_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,364 @@
+// Adjoint of the ray-grid SRP estimator (reverse mode in the reflectances, forward mode in the
+// hinge angles), gfx950.
+//
+// The paper differentiates only its neural proxy and notes that the simulator itself is
+// differentiable for continuous parameters away from visibility discontinuities (Sec. 3.3 and
+// Sec. 4.2, "differentiable by construction").  This kernel differentiates the ray-grid estimator
+// directly.  It replays every path of the forward trace with the same Philox counters, the same
+// traversal and the same interaction arithmetic (so it visits the same facets), and for
+// L = sum_j gF_j . F_j + gT_j . tau_j accumulates:
+//
+//  * dL/d rho_s[f], dL/d rho_d[f]: with the counters and the specular-sampling probabilities
+//    frozen, a path's contribution is a polynomial in the event factors k_b = rho_s/p_s (mirror) or
+//    rho_d/(1 - p_s) (Lambertian) and, at its last interaction, linear in (rho_s, rho_d).  The
+//    products that leave one factor out are carried forward per interaction slot, so no division
+//    by k occurs.  Per-facet sums use wavefront-aggregated FP64 atomics.
+//
+//  * dL/d theta_h (hinge angles): forward-mode tangents with each path's facet sequence frozen.
+//    Hit points slide along the ray onto the turned facet planes, normals and mirror directions
+//    turn, the Lambertian direction follows the basis of the turned normal, and the secondary
+//    origin x + eps n follows the hit point and the normal.  A footprint term scales the path by
+//    d log P_f / d theta for its primary facet f, where P_f is the facet's area projected on the
+//    grid plane: the ray grid samples a facet in proportion to P_f.  Visibility changes between
+//    facets (silhouette, shadow and occlusion edges) and the grid frame's own dependence on the
+//    design are excluded.
+#include <float.h>
+
+#include "srp_internal.h"
+#include "srp_path.h"
+#include "srp_traverse.h"
+
+namespace srp {
+namespace {
+
+constexpr int kSlots = kMaxBounces - 1;  // non-final interactions per path
+
+SRP_HD void cross3f(const float a[3], const float b[3], float r[3])
+{
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+SRP_HD float dot3f(const float a[3], const float b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Derivative of the Duff et al. basis (b1, b2) of n along the normal's derivative nd.
+SRP_HD void duff_basis_tangent(const float n[3], const float nd[3], float b1d[3], float b2d[3])
+{
+    const float s = n[2] >= 0.0f ? 1.0f : -1.0f;
+    const float a = -1.0f / (s + n[2]);
+    const float ad = a * a * nd[2];
+    b1d[0] = s * (2.0f * n[0] * nd[0] * a + n[0] * n[0] * ad);
+    b1d[1] = s * (nd[0] * n[1] * a + n[0] * nd[1] * a + n[0] * n[1] * ad);
+    b1d[2] = -s * nd[0];
+    b2d[0] = nd[0] * n[1] * a + n[0] * nd[1] * a + n[0] * n[1] * ad;
+    b2d[1] = 2.0f * n[1] * nd[1] * a + n[1] * n[1] * ad;
+    b2d[2] = -nd[1];
+}
+
+// Adds val into base[key] for every lane with `active`, one FP64 atomic per distinct key in the
+// wavefront (lanes of a coherent tile mostly hit the same few facets).
+__device__ __forceinline__ void wave_scatter_add(double* base, bool active, int key, float val)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = wave_ballot(active);
+    while (pending) {
+        const int leader = __ffsll(static_cast<unsigned long long>(pending)) - 1;
+        const int k = __shfl(key, leader, 64);
+        const bool match = active && key == k;
+        const float sum = wave_sum(match ? val : 0.0f);
+        if (lane == leader) atomicAdd(base + k, static_cast<double>(sum));
+        active = active && !match;
+        pending = wave_ballot(active);
+    }
+}
+
+template <int MAXH>
+__global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
+{
+    const TraceArgs& a = A.t;
+    __shared__ int s_stack[kWaves][kStackDepth];
+    __shared__ float s_red[kWaves][MAXH > 0 ? MAXH : 1];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t j = blockIdx.x / a.blocks_per_dir;
+    const int32_t blk = blockIdx.x % a.blocks_per_dir;
+    const DevFrame fr = a.frames[j];
+    const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
+    const BvhNode* __restrict__ nodes = a.nodes;
+    const TriRec* __restrict__ tris = a.tris;
+    int* stack = s_stack[wave];
+    const float gF[3] = {static_cast<float>(A.g_force[3 * j]), static_cast<float>(A.g_force[3 * j + 1]),
+                         static_cast<float>(A.g_force[3 * j + 2])};
+    float gT[3] = {0.0f, 0.0f, 0.0f};
+    if (A.g_torque)
+        for (int c = 0; c < 3; ++c) gT[c] = static_cast<float>(A.g_torque[3 * j + c]);
+    const int H = A.n_hinges < MAXH ? A.n_hinges : MAXH;
+
+    float accH[MAXH > 0 ? MAXH : 1];
+    for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h) accH[h] = 0.0f;
+
+    for (int m = 0; m < a.tiles_per_wave; ++m) {
+        const int64_t tile = (static_cast<int64_t>(blk) * a.tiles_per_wave + m) * kWaves + wave;
+        if (tile >= a.tiles_per_dir) break;
+        int64_t pixel, rec;
+        const bool valid = tile_pixel<false>(a, tile, lane, pixel, rec);
+        const int32_t pi = static_cast<int32_t>(pixel % a.nu);
+        const int32_t pk = static_cast<int32_t>(pixel / a.nu);
+        float o[3], d[3];
+        primary_ray(fr, pi, pk, static_cast<uint32_t>(pixel), dir_global, a.design_index, a.seed_lo, a.seed_hi,
+                    a.jitter != 0, o, d);
+        float w = fr.w;
+        bool alive = valid;
+        int skip = -1;
+
+        // reflectance adjoint state
+        float R[kSlots], Acc[kSlots], inv[kSlots];
+        int fac[kSlots], arr[kSlots];
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i) {
+            R[i] = 0.0f;
+            Acc[i] = 0.0f;
+            inv[i] = 0.0f;
+            fac[i] = 0;
+            arr[i] = 0;
+        }
+        int K = 0;
+        int term_f = -1;
+        float term_s = 0.0f, term_d = 0.0f;
+        float Lpath = 0.0f;
+        // hinge tangents: origin Od, direction Dd, accumulated dL, footprint factor
+        float Od[MAXH > 0 ? MAXH : 1][3], Dd[MAXH > 0 ? MAXH : 1][3], Ld[MAXH > 0 ? MAXH : 1],
+            phi[MAXH > 0 ? MAXH : 1];
+#pragma unroll
+        for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h) {
+            for (int c = 0; c < 3; ++c) {
+                Od[h][c] = 0.0f;
+                Dd[h][c] = 0.0f;
+            }
+            Ld[h] = 0.0f;
+            phi[h] = 0.0f;
+        }
+
+        for (int b = 1; b <= a.bounces; ++b) {
+            if (wave_ballot(alive) == 0) break;
+            float t;
+            int hit;
+            closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
+            if (!alive) continue;
+            if (hit < 0) {
+                alive = false;
+                continue;
+            }
+            const TriRec tr = tris[hit];
+            const float4 mt = a.mat[hit];
+            const float n[3] = {tr.f[1].w, tr.f[2].w, tr.f[3].x};
+            const float v0[3] = {tr.f[0].x, tr.f[0].y, tr.f[0].z};
+            const int fid = __float_as_int(tr.f[0].w);
+            const int hid = __float_as_int(tr.f[3].y);
+            const float d_in[3] = {d[0], d[1], d[2]};
+            float x[3], g[3];
+            InteractInfo inf;
+            alive = interact_ex(o, d, w, t, n, mt.x, mt.y, mt.z, b, a.bounces, static_cast<uint32_t>(pixel),
+                                dir_global, a.design_index, a.seed_lo, a.seed_hi, a.eps, x, g, &inf);
+            const float l[3] = {x[0] - a.com[0], x[1] - a.com[1], x[2] - a.com[2]};
+            float G[3];
+            cross3f(gT, l, G);
+            for (int c = 0; c < 3; ++c) G[c] += gF[c];
+            Lpath += dot3f(G, g);
+
+            // ---- reflectances: coefficient of the current weight W_K from the incident term
+            const float cin = dot3f(G, d_in);
+#pragma unroll
+            for (int i = 0; i < kSlots; ++i)
+                if (i < K) Acc[i] += R[i] * cin;
+            if (inf.last) {
+                const float tr_ = dot3f(G, inf.r), tn_ = dot3f(G, n);
+                const float term = -(mt.x * tr_ + (2.0f / 3.0f) * mt.y * tn_);
+#pragma unroll
+                for (int i = 0; i < kSlots; ++i)
+                    if (i < K) Acc[i] += R[i] * term;
+                term_f = fid;
+                term_s = -inf.w_in * tr_;
+                term_d = -inf.w_in * (2.0f / 3.0f) * tn_;
+            } else {
+                // new slot K with factor k; R_i *= k for the older slots, R_K = W before it
+#pragma unroll
+                for (int i = 0; i < kSlots; ++i) {
+                    if (i < K) R[i] *= inf.k;
+                    if (i == K) {
+                        R[i] = inf.w_in;
+                        fac[i] = fid;
+                        arr[i] = inf.mirror ? 0 : 1;
+                        inv[i] = inf.mirror ? 1.0f / mt.z : 1.0f / (1.0f - mt.z);
+                    }
+                }
+                const float cout = -dot3f(G, d);  // coefficient of the new weight: -G . o_b (d is o_b now)
+#pragma unroll
+                for (int i = 0; i < kSlots; ++i)
+                    if (i <= K) Acc[i] += R[i] * cout;
+                ++K;
+            }
+
+            // ---- hinge tangents
+#pragma unroll
+            for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h) {
+                if (h >= H) continue;
+                float nd[3] = {0.0f, 0.0f, 0.0f}, pd[3] = {0.0f, 0.0f, 0.0f};
+                if (hid == h) {
+                    const float* ax = A.hinge_axis[h];
+                    const float rel[3] = {v0[0] - A.hinge_origin[h][0], v0[1] - A.hinge_origin[h][1],
+                                          v0[2] - A.hinge_origin[h][2]};
+                    cross3f(ax, n, nd);
+                    cross3f(ax, rel, pd);
+                    if (b == 1) {
+                        // d log P_f / d theta, P_f = A_f (n . (-d))
+                        phi[h] = dot3f(nd, d_in) / dot3f(n, d_in);
+                    }
+                }
+                const float xp[3] = {x[0] - v0[0], x[1] - v0[1], x[2] - v0[2]};
+                float q[3];
+                for (int c = 0; c < 3; ++c) q[c] = Od[h][c] + t * Dd[h][c] - pd[c];
+                const float td = -(dot3f(nd, xp) + dot3f(n, q)) / dot3f(n, d_in);
+                float xd[3];
+                for (int c = 0; c < 3; ++c) xd[c] = Od[h][c] + td * d_in[c] + t * Dd[h][c];
+                const float cd = -(dot3f(Dd[h], n) + dot3f(d_in, nd));
+                float rd[3];
+                for (int c = 0; c < 3; ++c) rd[c] = Dd[h][c] + 2.0f * (cd * n[c] + inf.cth * nd[c]);
+                float gd[3];
+                for (int c = 0; c < 3; ++c) gd[c] = inf.w_in * Dd[h][c];
+                float odd[3] = {0.0f, 0.0f, 0.0f};
+                if (inf.last) {
+                    for (int c = 0; c < 3; ++c) gd[c] -= inf.w_in * (mt.x * rd[c] + (2.0f / 3.0f) * mt.y * nd[c]);
+                } else if (inf.mirror) {
+                    for (int c = 0; c < 3; ++c) {
+                        odd[c] = rd[c];
+                        gd[c] -= inf.w_out * rd[c];
+                    }
+                } else {
+                    float b1d[3], b2d[3];
+                    duff_basis_tangent(n, nd, b1d, b2d);
+                    for (int c = 0; c < 3; ++c) {
+                        odd[c] = inf.lam[0] * b1d[c] + inf.lam[1] * b2d[c] + inf.lam[2] * nd[c];
+                        gd[c] -= inf.w_out * odd[c];
+                    }
+                }
+                float c1[3], c2[3];
+                cross3f(xd, g, c1);
+                cross3f(l, gd, c2);
+                Ld[h] += dot3f(gF, gd) + gT[0] * (c1[0] + c2[0]) + gT[1] * (c1[1] + c2[1]) + gT[2] * (c1[2] + c2[2]);
+                if (!inf.last) {
+                    for (int c = 0; c < 3; ++c) {
+                        Od[h][c] = xd[c] + a.eps * nd[c];
+                        Dd[h][c] = odd[c];
+                    }
+                }
+            }
+            skip = hit;
+        }
+
+        // ---- scatter the reflectance gradients (original facet order, FP64)
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i) {
+            const bool act = valid && i < K;
+            if (wave_ballot(act) == 0) break;
+            wave_scatter_add(A.g_rho, act, arr[i] * A.n_tris + fac[i], Acc[i] * inv[i]);
+        }
+        const bool has_term = valid && term_f >= 0;
+        if (wave_ballot(has_term)) {
+            wave_scatter_add(A.g_rho, has_term, term_f, term_s);
+            wave_scatter_add(A.g_rho, has_term, A.n_tris + term_f, term_d);
+        }
+#pragma unroll
+        for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h)
+            if (valid && h < H) accH[h] += Ld[h] + Lpath * phi[h];
+    }
+
+    if (MAXH > 0) {
+#pragma unroll
+        for (int h = 0; h < MAXH; ++h) accH[h] = wave_sum(accH[h]);
+        if (lane == 0)
+            for (int h = 0; h < MAXH; ++h) s_red[wave][h] = accH[h];
+        __syncthreads();
+        if (threadIdx.x < MAXH) {
+            double s = 0.0;
+            for (int q = 0; q < kWaves; ++q) s += static_cast<double>(s_red[q][threadIdx.x]);
+            A.hinge_partials[(j * a.blocks_per_dir + blk) * kMaxHinges + threadIdx.x] = s;
+        }
+    }
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Per-direction sums of the hinge partials (fixed order over workgroups).
+__global__ void k_reduce_hinges(const double* __restrict__ hp, int64_t D, int32_t bpd, double* __restrict__ per_dir)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= D * kMaxHinges) return;
+    const int64_t j = t / kMaxHinges;
+    const int h = static_cast<int>(t % kMaxHinges);
+    double s = 0.0;
+    for (int32_t b = 0; b < bpd; ++b) s += hp[(j * bpd + b) * kMaxHinges + h];
+    per_dir[t] = s;
+}
+
+__global__ void k_finish_adjoint(const double* __restrict__ g_rho, int32_t n_tris, float* __restrict__ g_rs,
+                                 float* __restrict__ g_rd, const double* __restrict__ per_dir, int64_t D,
+                                 int32_t n_hinges, double* __restrict__ g_hinge)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n_tris) {
+        if (g_rs) g_rs[i] += static_cast<float>(g_rho[i]);
+        if (g_rd) g_rd[i] += static_cast<float>(g_rho[n_tris + i]);
+    }
+    if (i < n_hinges && g_hinge) {
+        double s = 0.0;  // fixed order over directions
+        for (int64_t j = 0; j < D; ++j) s += per_dir[j * kMaxHinges + i];
+        g_hinge[i] += s;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream)
+{
+    const unsigned blocks = static_cast<unsigned>(a.t.D * a.t.blocks_per_dir);
+    if (blocks == 0) return hipSuccess;
+    if (a.n_hinges == 0)
+        hipLaunchKernelGGL(k_adjoint<0>, dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+    else if (a.n_hinges <= 2)
+        hipLaunchKernelGGL(k_adjoint<2>, dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_adjoint<kMaxHinges>, dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int threads = 256;
+    hipLaunchKernelGGL(k_fill_f64, dim3(static_cast<unsigned>((n + threads - 1) / threads)), dim3(threads), 0, stream,
+                       p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_adjoint(const double* g_rho, int32_t n_tris, float* g_rho_s, float* g_rho_d,
+                                 const double* hinge_partials, int64_t D, int32_t blocks_per_dir, int32_t n_hinges,
+                                 double* per_dir, double* g_hinge, hipStream_t stream)
+{
+    const int threads = 256;
+    if (n_hinges > 0 && g_hinge) {
+        const int64_t nt = D * kMaxHinges;
+        hipLaunchKernelGGL(k_reduce_hinges, dim3(static_cast<unsigned>((nt + threads - 1) / threads)), dim3(threads), 0,
+                           stream, hinge_partials, D, blocks_per_dir, per_dir);
+    }
+    const int64_t n = n_tris > n_hinges ? n_tris : n_hinges;
+    hipLaunchKernelGGL(k_finish_adjoint, dim3(static_cast<unsigned>((n + threads - 1) / threads)), dim3(threads), 0,
+                       stream, g_rho, n_tris, g_rho_s, g_rho_d, per_dir, D, n_hinges, g_hinge);
+    return hipGetLastError();
+}
+
+}  // namespace srp

@@ -1,0 +1,51 @@
+// Internal interfaces of the surrogate-MLP part of libsrp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srp {
+
+enum GemmEpilogue : int32_t {
+    kEpiStore = 0,       // C = acc (+ bias[n])
+    kEpiHidden = 1,      // z = acc + bias[n]; C = z (if C); Cb = bf16(SiLU(z))
+    kEpiBackprop = 2,    // g = acc * SiLU'(Z[m][n]); C = g (if C); Cb = bf16(g)
+    kEpiAccumulate = 3,  // C += acc
+};
+
+// C[M][N] = op(A)[M][K] . op(B)[K][N]; op(A)[m][k] = A[m*lda + k] (or A[k*lda + m] transposed),
+// op(B)[k][n] = B[k*ldb + n] (or B[n*ldb + k] transposed); A, B are BF16 (uint16 bit patterns).
+struct GemmArgs {
+    const uint16_t* A;
+    const uint16_t* B;
+    int32_t M, N, K;
+    int32_t lda, ldb;
+    int32_t epi;
+    const float* bias;
+    float* C;
+    int32_t ldc;
+    uint16_t* Cb;
+    int32_t ldcb;
+    const float* Z;
+    int32_t ldz;
+};
+
+hipError_t launch_gemm(const GemmArgs& g, bool trans_a, bool trans_b, hipStream_t stream);
+hipError_t launch_colsum(const float* G, int64_t rows, int cols, int ldg, float* part, float* out, hipStream_t stream);
+hipError_t launch_to_bf16(const float* in, int64_t rows, int cols, int ld_in, uint16_t* out, int ld_out,
+                          hipStream_t stream);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, hipStream_t stream);
+hipError_t launch_pack(const float* W, int out, int in, uint16_t* Wb, int out_pad, int in_pad, hipStream_t stream);
+hipError_t launch_mse(const float* y, const float* t, int64_t count, float* gy, double* partial, double* loss,
+                      hipStream_t stream);
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t stream);
+
+// Fused inference (all layers in one kernel, weights staged in LDS, activations kept in registers).
+bool mlp_fused_supported(int n_in, int width, int depth, int n_out);
+hipError_t launch_mlp_infer(const float* x, int32_t N, const uint16_t* wb, const float* params, int n_in, int width,
+                            int depth, int n_out, const int64_t* wb_off, const int64_t* b_off, float* y,
+                            hipStream_t stream);
+
+}  // namespace srp

@@ -36,8 +36,12 @@ struct srp_scene_s {
     size_t flag_cap = 0;
     srp::DevFrame* d_frames = nullptr;
     size_t frames_cap = 0;
-    double* d_partials = nullptr;
+    double* d_partials = nullptr;        // per-workgroup FP64 partials (force/torque or hinge terms)
     size_t partials_cap = 0;
+    double* d_grho = nullptr;            // adjoint: FP64 reflectance-gradient accumulators [2][n_tris]
+    size_t grho_cap = 0;
+    double* d_hdir = nullptr;            // adjoint: per-direction hinge sums [D][kMaxHinges]
+    size_t hdir_cap = 0;
 };
 
 // Records `msg` as the thread's last error and returns `st`.

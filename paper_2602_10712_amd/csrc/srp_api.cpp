@@ -133,7 +133,13 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream)
                              static_cast<float>(n[0]));
         r.f[2] = make_float4(static_cast<float>(e2[0]), static_cast<float>(e2[1]), static_cast<float>(e2[2]),
                              static_cast<float>(n[1]));
-        r.f[3] = make_float4(static_cast<float>(n[2]), 0.0f, 0.0f, 0.0f);
+        // hinge carrying the facet (-1: rigid); a facet is carried by hinge k when all three
+        // vertices are
+        int32_t h0 = s->vhinge[s->tris[3 * f]], h1 = s->vhinge[s->tris[3 * f + 1]], h2 = s->vhinge[s->tris[3 * f + 2]];
+        int32_t hid = (h0 == h1 && h1 == h2) ? h0 : -1;
+        float hid_bits;
+        std::memcpy(&hid_bits, &hid, 4);
+        r.f[3] = make_float4(static_cast<float>(n[2]), hid_bits, 0.0f, 0.0f);
     }
     s->h_nodes = bvh.nodes;
     SRP_HIP(ensure(s->d_nodes, s->nodes_cap, bvh.nodes.size()));
@@ -169,15 +175,15 @@ srp_status bind_device(const srp_scene_s* s)
     return SRP_OK;
 }
 
-// Frames + trace launch shared by srp_trace and srp_trace_records.
-srp_status enqueue_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+// Frames launch + trace arguments shared by srp_trace, srp_trace_records and srp_trace_adjoint.
+srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
                          const double* frames, bool records, const int64_t* pix, int64_t n_pix, int32_t* rec_hit,
-                         float* rec_force, hipStream_t stream, int32_t* bpd_out)
+                         float* rec_force, hipStream_t stream, srp::TraceArgs& a)
 {
     SRP_HIP(ensure(s->d_frames, s->frames_cap, static_cast<size_t>(D)));
     SRP_HIP(srp::launch_frames(sun_dirs, D, s->lo, s->hi, s->L, p->nu, p->nv, p->flux,
                                p->frame_mode == 1 ? frames : nullptr, nullptr, s->d_frames, stream));
-    srp::TraceArgs a{};
+    a = srp::TraceArgs{};
     a.nodes = s->d_nodes;
     a.tris = s->d_tris;
     a.mat = s->d_mat;
@@ -213,8 +219,18 @@ srp_status enqueue_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
     const int64_t bpd = std::max<int64_t>(1, (a.tiles_per_dir + per_block - 1) / per_block);
     if (bpd * D > 0x7fffffffLL) return fail(SRP_EINVAL, "trace too large for one launch");
     a.blocks_per_dir = static_cast<int32_t>(bpd);
-    SRP_HIP(ensure(s->d_partials, s->partials_cap, static_cast<size_t>(bpd * D * 6)));
+    SRP_HIP(ensure(s->d_partials, s->partials_cap, static_cast<size_t>(bpd * D * std::max(6, srp::kMaxHinges))));
     a.partials = s->d_partials;
+    return SRP_OK;
+}
+
+srp_status enqueue_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                         const double* frames, bool records, const int64_t* pix, int64_t n_pix, int32_t* rec_hit,
+                         float* rec_force, hipStream_t stream, int32_t* bpd_out)
+{
+    srp::TraceArgs a;
+    srp_status st = prepare_trace(s, sun_dirs, D, p, frames, records, pix, n_pix, rec_hit, rec_force, stream, a);
+    if (st != SRP_OK) return st;
     SRP_HIP(srp::launch_trace(a, records, stream));
     *bpd_out = a.blocks_per_dir;
     return SRP_OK;
@@ -394,6 +410,46 @@ srp_status srp_trace_records(srp_scene s, const double* sun_dirs, int64_t D, con
                          static_cast<hipStream_t>(stream_), &bpd);
 }
 
+srp_status srp_trace_adjoint(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                             const double* frames, const double* g_force, const double* g_torque, float* g_rho_s,
+                             float* g_rho_d, double* g_hinge, void* stream_)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (D < 0) return fail(SRP_EINVAL, "D must be >= 0");
+    if (D == 0) return SRP_OK;
+    if (!sun_dirs || !g_force) return fail(SRP_EINVAL, "sun_dirs and g_force are required");
+    if (p->frame_mode == 1 && !frames) return fail(SRP_EINVAL, "frame_mode 1 needs frames");
+    if (p->dir_index_base + D > (int64_t(1) << 32)) return fail(SRP_EINVAL, "direction index exceeds 32 bits");
+    if (g_hinge && s->n_hinges > srp::kMaxHinges)
+        return fail(SRP_EUNSUPPORTED, "hinge gradients support at most 4 hinges");
+    st = bind_device(s);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    srp::AdjointArgs A{};
+    st = prepare_trace(s, sun_dirs, D, p, frames, false, nullptr, 0, nullptr, nullptr, stream, A.t);
+    if (st != SRP_OK) return st;
+    SRP_HIP(ensure(s->d_grho, s->grho_cap, static_cast<size_t>(2 * s->n_tris)));
+    SRP_HIP(ensure(s->d_hdir, s->hdir_cap, static_cast<size_t>(D * srp::kMaxHinges)));
+    SRP_HIP(srp::launch_fill_f64(s->d_grho, 2 * s->n_tris, 0.0, stream));
+    A.g_force = g_force;
+    A.g_torque = g_torque;
+    A.g_rho = s->d_grho;
+    A.n_tris = static_cast<int32_t>(s->n_tris);
+    A.n_hinges = g_hinge ? s->n_hinges : 0;
+    for (int k = 0; k < A.n_hinges; ++k)
+        for (int c = 0; c < 3; ++c) {
+            A.hinge_axis[k][c] = static_cast<float>(s->hinges[k].axis[c]);
+            A.hinge_origin[k][c] = static_cast<float>(s->hinges[k].origin[c]);
+        }
+    A.hinge_partials = s->d_partials;  // sized for kMaxHinges per workgroup
+    SRP_HIP(srp::launch_adjoint(A, stream));
+    SRP_HIP(srp::launch_finish_adjoint(s->d_grho, A.n_tris, g_rho_s, g_rho_d, s->d_partials, D, A.t.blocks_per_dir,
+                                       A.n_hinges, s->d_hdir, g_hinge, stream));
+    return SRP_OK;
+}
+
 srp_status srp_scene_destroy(srp_scene s)
 {
     if (!s) return SRP_OK;
@@ -407,6 +463,8 @@ srp_status srp_scene_destroy(srp_scene s)
     (void)hipFree(s->d_flag);
     (void)hipFree(s->d_frames);
     (void)hipFree(s->d_partials);
+    (void)hipFree(s->d_grho);
+    (void)hipFree(s->d_hdir);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete s;
     return SRP_OK;

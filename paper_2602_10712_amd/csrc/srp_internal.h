@@ -26,7 +26,8 @@ struct BvhNode {
 };
 
 // Triangle record in BVH order, 64 bytes:
-//   (v0.x, v0.y, v0.z, original index as int bits), (e1.xyz, n.x), (e2.xyz, n.y), (n.z, 0, 0, 0)
+//   (v0.x, v0.y, v0.z, original index as int bits), (e1.xyz, n.x), (e2.xyz, n.y),
+//   (n.z, hinge index as int bits (-1 rigid), 0, 0)
 struct TriRec {
     float4 f[4];
 };
@@ -68,7 +69,21 @@ struct TraceArgs {
     float* rec_force;         // [D][n_pix][3]
 };
 
-// Host-side launchers (defined in trace_kernels.hip).
+constexpr int kMaxHinges = 4;   // hinge-angle gradients supported by the adjoint
+
+struct AdjointArgs {
+    TraceArgs t;                 // geometry, frames and grid of the replayed forward trace
+    const double* g_force;       // [D][3] seed dL/dF
+    const double* g_torque;      // [D][3] seed dL/dtau, or null
+    double* g_rho;               // [2][n_tris] FP64 accumulators, original facet order
+    int32_t n_tris;
+    int32_t n_hinges;
+    float hinge_axis[kMaxHinges][3];
+    float hinge_origin[kMaxHinges][3];
+    double* hinge_partials;      // [D][blocks_per_dir][kMaxHinges]
+};
+
+// Host-side launchers (defined in trace_kernels.hip and adjoint_kernels.hip).
 hipError_t launch_frames(const double* sun_dirs, int64_t D, const double lo[3], const double hi[3], double L,
                          int32_t nu, int32_t nv, double flux, const double* caller_frames, double* frames64,
                          DevFrame* frames32, hipStream_t stream);
@@ -77,5 +92,10 @@ hipError_t launch_pack_materials(const float* rho_s, const float* rho_d, const f
 hipError_t launch_trace(const TraceArgs& a, bool records, hipStream_t stream);
 hipError_t launch_reduce(const double* partials, int64_t D, int32_t blocks_per_dir, double* force, double* torque,
                          hipStream_t stream);
+hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream);
+hipError_t launch_finish_adjoint(const double* g_rho, int32_t n_tris, float* g_rho_s, float* g_rho_d,
+                                 const double* hinge_partials, int64_t D, int32_t blocks_per_dir, int32_t n_hinges,
+                                 double* per_dir, double* g_hinge, hipStream_t stream);
 
 }  // namespace srp

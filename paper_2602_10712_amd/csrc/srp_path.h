@@ -125,6 +125,16 @@ SRP_HD void primary_ray(const DevFrame& fr, int32_t pi, int32_t pk, uint32_t pix
     }
 }
 
+// Internals of one interaction that the adjoint needs.
+struct InteractInfo {
+    float r[3];          // mirror direction
+    float cth;           // cos(theta) = -d . n
+    float w_in, w_out;   // weights before and after (w_out = 0 at the last interaction)
+    float k;             // w_out / w_in as rho_s / p_spec or rho_d / (1 - p_spec)
+    float lam[3];        // Lambertian draw in the (t1, t2, n) basis
+    bool last, mirror;
+};
+
 // One surface interaction (paper Sec. 3.2, l2f): at hit point x = o + t d on a facet with outward
 // normal n and material (rho_s, rho_d, p_spec), the deposit is the incident momentum w d minus the
 // momentum that leaves.  At the last interaction (b == bounces, or a black facet) the expected
@@ -134,18 +144,30 @@ SRP_HD void primary_ray(const DevFrame& fr, int32_t pi, int32_t pk, uint32_t pix
 // direction (Malley's method in the Duff basis of n) with weight w rho_d / (1 - p_spec); that
 // sampled momentum leaves and the path continues from x + eps n.
 // Returns the force deposit in g[3]; updates o, d, w; returns false when the path ends.
-SRP_HD bool interact(float o[3], float d[3], float& w, float t, const float n[3], float rs, float rd, float ps, int b,
-                     int bounces, uint32_t pixel, uint32_t dir, uint32_t design, uint32_t seed_lo, uint32_t seed_hi,
-                     float eps, float x[3], float g[3])
+// `info` (may be null) receives the internals the adjoint needs.
+template <class Info>
+SRP_HD bool interact_ex(float o[3], float d[3], float& w, float t, const float n[3], float rs, float rd, float ps, int b,
+                        int bounces, uint32_t pixel, uint32_t dir, uint32_t design, uint32_t seed_lo, uint32_t seed_hi,
+                        float eps, float x[3], float g[3], Info* info)
 {
     for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
     const float cth = -(d[0] * n[0] + d[1] * n[1] + d[2] * n[2]);
     float r[3];
     for (int a = 0; a < 3; ++a) r[a] = d[a] + 2.0f * cth * n[a];
     for (int a = 0; a < 3; ++a) g[a] = w * d[a];
+    if (info) {
+        for (int a = 0; a < 3; ++a) info->r[a] = r[a];
+        info->cth = cth;
+        info->w_in = w;
+        info->w_out = 0.0f;
+        info->k = 0.0f;
+        info->last = false;
+        info->mirror = false;
+    }
     if (b == bounces || (rs == 0.0f && rd == 0.0f)) {
         const float kd = (2.0f / 3.0f) * rd;
         for (int a = 0; a < 3; ++a) g[a] -= w * (rs * r[a] + kd * n[a]);
+        if (info) info->last = true;
         return false;
     }
     uint32_t c0 = pixel, c1 = dir, c2 = static_cast<uint32_t>(b), c3 = design;
@@ -155,6 +177,10 @@ SRP_HD bool interact(float o[3], float d[3], float& w, float t, const float n[3]
     if (ue < ps) {
         for (int a = 0; a < 3; ++a) od[a] = r[a];
         w2 = w * rs / ps;
+        if (info) {
+            info->mirror = true;
+            info->k = rs / ps;
+        }
     } else {
         const float rad = sqrtf(u1);
         float sphi, cphi;
@@ -164,7 +190,14 @@ SRP_HD bool interact(float o[3], float d[3], float& w, float t, const float n[3]
         duff_basis<float>(n, t1, t2);
         for (int a = 0; a < 3; ++a) od[a] = px * t1[a] + py * t2[a] + pz * n[a];
         w2 = w * rd / (1.0f - ps);
+        if (info) {
+            info->k = rd / (1.0f - ps);
+            info->lam[0] = px;
+            info->lam[1] = py;
+            info->lam[2] = pz;
+        }
     }
+    if (info) info->w_out = w2;
     for (int a = 0; a < 3; ++a) {
         g[a] -= w2 * od[a];
         o[a] = x[a] + eps * n[a];
@@ -172,6 +205,14 @@ SRP_HD bool interact(float o[3], float d[3], float& w, float t, const float n[3]
     }
     w = w2;
     return true;
+}
+
+SRP_HD bool interact(float o[3], float d[3], float& w, float t, const float n[3], float rs, float rd, float ps, int b,
+                     int bounces, uint32_t pixel, uint32_t dir, uint32_t design, uint32_t seed_lo, uint32_t seed_hi,
+                     float eps, float x[3], float g[3])
+{
+    return interact_ex<InteractInfo>(o, d, w, t, n, rs, rd, ps, b, bounces, pixel, dir, design, seed_lo, seed_hi, eps, x,
+                                     g, nullptr);
 }
 
 // Moller-Trumbore (1997), one-sided (det > 0 <=> the ray meets the outward side), inclusive

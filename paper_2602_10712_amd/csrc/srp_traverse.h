@@ -1,0 +1,120 @@
+// Device-side BVH traversal and wavefront helpers shared by the forward and adjoint kernels.
+#pragma once
+
+#include <float.h>
+
+#include "srp_internal.h"
+#include "srp_path.h"
+
+namespace srp {
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Closest front-facing hit of each lane's ray (o, d) among all triangles except `skip` (the
+// triangle the ray leaves); an exact tie in t goes to the lower original triangle index.  Lanes
+// with alive == false never hit.  The traversal is wavefront-coherent: one node sequence for the
+// whole wave (so node and triangle records arrive through scalar loads), a child is entered when
+// any lane's ray overlaps its box, the nearer child first by majority over the lanes that overlap
+// both, and the stack of deferred children is wave-uniform in LDS.
+__device__ __forceinline__ void closest_hit(const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris,
+                                            const float o[3], const float d[3], bool alive, int skip, float& t_out,
+                                            int& hit_out, int* __restrict__ stack)
+{
+    const float ix = safe_rcp(d[0]), iy = safe_rcp(d[1]), iz = safe_rcp(d[2]);
+    const float nx = -o[0] * ix, ny = -o[1] * iy, nz = -o[2] * iz;
+    float tbest = alive ? FLT_MAX : -1.0f;
+    int hit = -1;
+    int hit_id = 0x7fffffff;
+    int sp = 0;
+    int cur = 0;
+    for (;;) {
+        if (cur >= 0) {
+            const BvhNode* N = nodes + cur;
+            const float4 f0 = N->f[0];
+            const float4 f1 = N->f[1];
+            const float4 f2 = N->f[2];
+            const float4 f3 = N->f[3];
+            const int c0 = __float_as_int(f3.x);
+            const int c1 = __float_as_int(f3.y);
+            const float ax0 = fmaf(f0.x, ix, nx), ax1 = fmaf(f0.y, ix, nx);
+            const float ay0 = fmaf(f0.z, iy, ny), ay1 = fmaf(f0.w, iy, ny);
+            const float az0 = fmaf(f2.x, iz, nz), az1 = fmaf(f2.y, iz, nz);
+            const float bx0 = fmaf(f1.x, ix, nx), bx1 = fmaf(f1.y, ix, nx);
+            const float by0 = fmaf(f1.z, iy, ny), by1 = fmaf(f1.w, iy, ny);
+            const float bz0 = fmaf(f2.z, iz, nz), bz1 = fmaf(f2.w, iz, nz);
+            const float tn0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+            const float tf0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tbest));
+            const float tn1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+            const float tf1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tbest));
+            const bool h0 = tn0 <= tf0;
+            const bool h1 = tn1 <= tf1;
+            const uint64_t m0 = wave_ballot(h0);
+            const uint64_t m1 = wave_ballot(h1);
+            if (m0 && m1) {
+                const uint64_t first1 = wave_ballot(h0 && h1 && tn1 < tn0);
+                const bool swap = 2 * __popcll(first1) > __popcll(m0 & m1);
+                stack[sp] = swap ? c0 : c1;
+                ++sp;
+                cur = swap ? c1 : c0;
+            } else if (m0) {
+                cur = c0;
+            } else if (m1) {
+                cur = c1;
+            } else {
+                if (sp == 0) break;
+                --sp;
+                cur = __builtin_amdgcn_readfirstlane(stack[sp]);
+            }
+        } else {
+            const int code = ~cur;
+            const int first = code >> 3;
+            const int cnt = code & 7;
+            for (int q = 0; q < cnt; ++q) {
+                const int tri = first + q;
+                const TriRec* T = tris + tri;
+                const float4 g0 = T->f[0];
+                const float4 g1 = T->f[1];
+                const float4 g2 = T->f[2];
+                const float t = tri_hit(o, d, g0, g1, g2);
+                const int id = __float_as_int(g0.w);
+                if (t > 0.0f && tri != skip && (t < tbest || (t == tbest && id < hit_id))) {
+                    tbest = t;
+                    hit = tri;
+                    hit_id = id;
+                }
+            }
+            if (sp == 0) break;
+            --sp;
+            cur = __builtin_amdgcn_readfirstlane(stack[sp]);
+        }
+    }
+    t_out = tbest;
+    hit_out = hit;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Pixel of lane `lane` in wave tile `tile`: 8 x 8 pixel tiles in row-major order (trace mode) or
+// 64 consecutive entries of an explicit pixel list (records mode).
+template <bool RECORDS>
+__device__ __forceinline__ bool tile_pixel(const TraceArgs& a, int64_t tile, int lane, int64_t& pixel, int64_t& rec)
+{
+    if (RECORDS) {
+        rec = tile * 64 + lane;
+        const bool valid = rec < a.n_pix;
+        pixel = valid ? (a.pix ? a.pix[rec] : rec) : 0;
+        return valid;
+    }
+    rec = 0;
+    const int64_t tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int64_t pi = tx * kTileW + (lane & 7), pk = ty * kTileH + (lane >> 3);
+    pixel = pi + pk * a.nu;
+    return pi < a.nu && pk < a.nv;
+}
+
+}  // namespace srp
