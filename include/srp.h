@@ -184,6 +184,27 @@ srp_status srp_mlp_set_params(srp_mlp mlp, const float* params, const float* ada
 
 srp_status srp_mlp_destroy(srp_mlp mlp);
 
+/* ---------------------------------------------------------------------------------------------
+ * Orbit integration (paper Sec. 3.4.1, Eq. ODE, translational part; Sec. 3.4.3, adjoint).  Host
+ * FP64, classic fourth-order Runge-Kutta with step dt over n_steps steps of
+ *   dr/dt = v,  dv/dt = -mu r / |r|^3 + R_k F_k / mass,
+ * where F_body [2 n_steps + 1][3] holds the body-frame SRP force at the stage times t_k = k dt / 2
+ * (step n uses k = 2n, 2n+1, 2n+1, 2n+2) and R_body_to_inertial [2 n_steps + 1][9] the attitude
+ * (row-major 3x3) at those times.  The attitude is a function of time only.
+ * ------------------------------------------------------------------------------------------- */
+
+/* z0 [6] = (r, v) in m and m/s; z_all [n_steps + 1][6] may be NULL; z_final [6]. */
+srp_status srp_orbit_rk4(const double* z0, double mu, double mass, double dt, int64_t n_steps, const double* F_body,
+                         const double* R_body_to_inertial, double* z_all, double* z_final);
+
+/* Discrete adjoint of srp_orbit_rk4: for g_final = dL/dz_N [6] returns g_F = dL/dF_body
+ * [2 n_steps + 1][3] (overwritten) and g_z0 = dL/dz0 [6] (may be NULL).  The forward states are
+ * kept only every ckpt_every steps; each segment is recomputed from its checkpoint during the
+ * reverse sweep. */
+srp_status srp_orbit_rk4_adjoint(const double* z0, double mu, double mass, double dt, int64_t n_steps,
+                                 const double* F_body, const double* R_body_to_inertial, const double* g_final,
+                                 int64_t ckpt_every, double* g_F, double* g_z0);
+
 /* Waits for `stream` and reports any pending device error as SRP_EDEVICE. */
 srp_status srp_sync(void* stream);
 

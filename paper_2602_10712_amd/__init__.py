@@ -12,10 +12,11 @@ _BINDING_NAMES = {"SRPError", "Scene", "TraceParams", "lib_path", "srp_frames", 
                   "srp_sync", "srp_trace", "srp_trace_records", "srp_scene_ray_stats", "ray_stats",
                   "srp_trace_adjoint", "Surrogate", "srp_mlp_create", "srp_mlp_num_params", "srp_mlp_forward",
                   "srp_mlp_backward", "srp_mlp_adam_step", "srp_mlp_zero_grad", "srp_mlp_mse", "srp_mlp_get_params",
-                  "srp_mlp_set_params", "srp_mlp_destroy"}
+                  "srp_mlp_set_params", "srp_mlp_destroy", "srp_orbit_rk4", "srp_orbit_rk4_adjoint"}
 
 
 _AUTOGRAD_NAMES = {"SRPForce", "srp_force"}
+_ORBIT_NAMES = {"DesignProblem"}
 
 
 def __getattr__(name):
@@ -23,7 +24,9 @@ def __getattr__(name):
         return getattr(importlib.import_module("._binding", __name__), name)
     if name in _AUTOGRAD_NAMES:
         return getattr(importlib.import_module(".autograd", __name__), name)
+    if name in _ORBIT_NAMES:
+        return getattr(importlib.import_module(".orbit", __name__), name)
     raise AttributeError(name)
 
 
-__all__ = sorted(_BINDING_NAMES | _AUTOGRAD_NAMES)
+__all__ = sorted(_BINDING_NAMES | _AUTOGRAD_NAMES | _ORBIT_NAMES)

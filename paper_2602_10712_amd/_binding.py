@@ -59,6 +59,8 @@ _sigs = {
     "srp_mlp_get_params": [P, P, P, P, P, ctypes.POINTER(I64), I64],
     "srp_mlp_set_params": [P, P, P, P, I64, I64],
     "srp_mlp_destroy": [P],
+    "srp_orbit_rk4": [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I64, P, P, P, P],
+    "srp_orbit_rk4_adjoint": [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I64, P, P, P, I64, P, P],
     "srp_sync": [P],
 }
 for _name, _args in _sigs.items():
@@ -427,3 +429,29 @@ class Surrogate:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------------------------------------
+# orbit integration (host FP64)
+# ------------------------------------------------------------------------------------------------
+def srp_orbit_rk4(z0, mu, mass, dt, n_steps, F_body, R, keep_states=False):
+    z0 = np.ascontiguousarray(z0, dtype=np.float64)
+    F = np.ascontiguousarray(F_body, dtype=np.float64).reshape(2 * n_steps + 1, 3)
+    Rm = np.ascontiguousarray(R, dtype=np.float64).reshape(2 * n_steps + 1, 9)
+    zs = np.zeros((n_steps + 1, 6)) if keep_states else None
+    zf = np.zeros(6)
+    _check(_lib.srp_orbit_rk4(_hptr(z0), float(mu), float(mass), float(dt), int(n_steps), _hptr(F), _hptr(Rm),
+                              _hptr(zs), _hptr(zf)))
+    return (zf, zs) if keep_states else zf
+
+
+def srp_orbit_rk4_adjoint(z0, mu, mass, dt, n_steps, F_body, R, g_final, ckpt_every=60):
+    z0 = np.ascontiguousarray(z0, dtype=np.float64)
+    F = np.ascontiguousarray(F_body, dtype=np.float64).reshape(2 * n_steps + 1, 3)
+    Rm = np.ascontiguousarray(R, dtype=np.float64).reshape(2 * n_steps + 1, 9)
+    g = np.ascontiguousarray(g_final, dtype=np.float64)
+    gF = np.zeros((2 * n_steps + 1, 3))
+    gz = np.zeros(6)
+    _check(_lib.srp_orbit_rk4_adjoint(_hptr(z0), float(mu), float(mass), float(dt), int(n_steps), _hptr(F), _hptr(Rm),
+                                      _hptr(g), int(ckpt_every), _hptr(gF), _hptr(gz)))
+    return gF, gz

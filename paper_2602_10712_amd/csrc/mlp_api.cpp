@@ -53,6 +53,11 @@ struct srp_mlp_s {
     float* d_v = nullptr;
     uint16_t* d_wb = nullptr;  // BF16 weights, layer l: [fout_pad][fin_pad]
     int64_t wb_total = 0;
+    bool fused = false;        // the fused inference kernel serves this shape
+    uint16_t* d_wf = nullptr;  // BF16 weights in A-operand pieces for the fused kernel
+    std::vector<int64_t> wf_off;
+    int64_t* d_wf_off = nullptr;  // device copies of wf_off and b_off
+    int64_t* d_b_off = nullptr;
     // workspaces
     size_t cap_xb = 0, cap_Z = 0, cap_A = 0, cap_G = 0, cap_Gb = 0, cap_col = 0, cap_lp = 0;
     uint16_t* d_xb = nullptr;
@@ -77,9 +82,13 @@ srp_status bind(const srp_mlp_s* m)
 
 srp_status repack(srp_mlp_s* m, hipStream_t stream)
 {
-    for (int l = 0; l <= m->depth; ++l)
+    for (int l = 0; l <= m->depth; ++l) {
         MLP_HIP(srp::launch_pack(m->d_p + m->w_off[l], m->fout[l], m->fin[l], m->d_wb + m->wb_off[l], m->fout_pad[l],
                                  m->fin_pad[l], stream));
+        if (m->fused)
+            MLP_HIP(srp::launch_pack_mfma(m->d_p + m->w_off[l], m->fout[l], m->fin[l], l, m->depth,
+                                          m->d_wf + m->wf_off[l], stream));
+    }
     return SRP_OK;
 }
 
@@ -138,6 +147,12 @@ srp_status srp_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_
     }
     m->P = off;
     m->wb_total = woff;
+    m->fused = srp::mlp_fused_supported(n_in, width, depth, n_out);
+    int64_t foff = 0;
+    for (int l = 0; l <= depth; ++l) {
+        m->wf_off.push_back(foff);
+        if (m->fused) foff += srp::mlp_fused_layer_elems(l, depth);
+    }
     // seeded initial weights and biases: U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from Philox draws
     std::vector<float> h(m->P);
     for (int l = 0; l <= depth; ++l) {
@@ -154,6 +169,13 @@ srp_status srp_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_
     if (e == hipSuccess) e = hipMalloc(&m->d_m, sizeof(float) * m->P);
     if (e == hipSuccess) e = hipMalloc(&m->d_v, sizeof(float) * m->P);
     if (e == hipSuccess) e = hipMalloc(&m->d_wb, sizeof(uint16_t) * m->wb_total);
+    if (e == hipSuccess && m->fused) e = hipMalloc(&m->d_wf, sizeof(uint16_t) * std::max<int64_t>(foff, 1));
+    if (e == hipSuccess) e = hipMalloc(&m->d_wf_off, sizeof(int64_t) * (depth + 1));
+    if (e == hipSuccess) e = hipMalloc(&m->d_b_off, sizeof(int64_t) * (depth + 1));
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_wf_off, m->wf_off.data(), sizeof(int64_t) * (depth + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_b_off, m->b_off.data(), sizeof(int64_t) * (depth + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->d_p, h.data(), sizeof(float) * m->P, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(m->d_g, 0, sizeof(float) * m->P);
     if (e == hipSuccess) e = hipMemset(m->d_m, 0, sizeof(float) * m->P);
@@ -190,9 +212,9 @@ srp_status srp_mlp_forward(srp_mlp m, const float* x, int64_t N, float* y, int32
     if (st != SRP_OK) return st;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     const bool training = keep_activations != 0;
-    if (!training && srp::mlp_fused_supported(m->n_in, m->width, m->depth, m->n_out)) {
-        MLP_HIP(srp::launch_mlp_infer(x, static_cast<int32_t>(N), m->d_wb, m->d_p, m->n_in, m->width, m->depth,
-                                      m->n_out, m->wb_off.data(), m->b_off.data(), y, stream));
+    if (!training && m->fused) {
+        MLP_HIP(srp::launch_mlp_infer(x, static_cast<int32_t>(N), m->d_wf, m->d_wf_off, m->d_p, m->d_b_off, m->n_in,
+                                      m->depth, m->n_out, y, stream));
         m->cached_N = -1;
         return SRP_OK;
     }
@@ -385,7 +407,8 @@ srp_status srp_mlp_destroy(srp_mlp m)
     for (void* p : {static_cast<void*>(m->d_p), static_cast<void*>(m->d_g), static_cast<void*>(m->d_m),
                     static_cast<void*>(m->d_v), static_cast<void*>(m->d_wb), static_cast<void*>(m->d_xb),
                     static_cast<void*>(m->d_Z), static_cast<void*>(m->d_A), static_cast<void*>(m->d_G),
-                    static_cast<void*>(m->d_Gb), static_cast<void*>(m->d_col), static_cast<void*>(m->d_lpart)})
+                    static_cast<void*>(m->d_Gb), static_cast<void*>(m->d_col), static_cast<void*>(m->d_lpart),
+                    static_cast<void*>(m->d_wf), static_cast<void*>(m->d_wf_off), static_cast<void*>(m->d_b_off)})
         if (p) (void)hipFree(p);
     delete m;
     return SRP_OK;

@@ -42,10 +42,12 @@ hipError_t launch_mse(const float* y, const float* t, int64_t count, float* gy, 
 
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t stream);
 
-// Fused inference (all layers in one kernel, weights staged in LDS, activations kept in registers).
+// Fused inference (all layers in one kernel, weights staged in LDS, activations in registers).
 bool mlp_fused_supported(int n_in, int width, int depth, int n_out);
-hipError_t launch_mlp_infer(const float* x, int32_t N, const uint16_t* wb, const float* params, int n_in, int width,
-                            int depth, int n_out, const int64_t* wb_off, const int64_t* b_off, float* y,
+int64_t mlp_fused_layer_elems(int layer, int depth);
+hipError_t launch_pack_mfma(const float* W, int out, int in, int layer, int depth, uint16_t* dst, hipStream_t stream);
+hipError_t launch_mlp_infer(const float* x, int32_t N, const uint16_t* wf, const int64_t* wf_off_dev,
+                            const float* params, const int64_t* b_off_dev, int n_in, int depth, int n_out, float* y,
                             hipStream_t stream);
 
 }  // namespace srp

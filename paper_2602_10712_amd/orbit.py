@@ -1,0 +1,108 @@
+"""Design optimisation through the orbit (paper Sec. 3.4 and Alg. 1, design loop).
+
+One evaluation of the design vector
+    theta = [hinge_1, hinge_2, rho_s_bus, rho_d_bus, rho_s_panel, rho_d_panel, rho_s_payload, rho_d_payload]
+applies the design (hinge rotation + group reflectances), traces the body-frame force for the
+body-frame sun direction at every RK4 stage time in ONE batched srp_trace (the attitude depends on
+time only), integrates the orbit (srp_orbit_rk4) and scores L = |r_N - r_target|^2.  Its gradient
+chains the discrete RK4 adjoint (srp_orbit_rk4_adjoint, checkpointed) into the ray adjoint
+(srp_trace_adjoint, seeds = dL/dF at each stage time), then sums facet gradients per design group.
+All compute runs in libsrp; this module only sequences the calls.  Bounded parameters are clipped
+after every optimiser step (Sec. 3.4.3).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _binding as B
+
+GROUP_NAMES = ("hinge_1", "hinge_2", "rho_s_bus", "rho_d_bus", "rho_s_panel", "rho_d_panel", "rho_s_payload",
+               "rho_d_payload")
+
+
+class DesignProblem:
+    def __init__(self, mesh, scenario, params: B.TraceParams, lo, hi, r_target=None, ckpt_every=60):
+        self.mesh = mesh
+        self.sc = scenario
+        self.params = params
+        self.lo = np.asarray(lo, dtype=np.float64)
+        self.hi = np.asarray(hi, dtype=np.float64)
+        self.scene = B.Scene.from_mesh(mesh)
+        self.sun = torch.as_tensor(scenario.sun_body, dtype=torch.float64, device="cuda").contiguous()
+        self.group = np.asarray(mesh.group)
+        self.r_target = None if r_target is None else np.asarray(r_target, dtype=np.float64)
+        self.ckpt_every = ckpt_every
+        self.n_stage = 2 * scenario.n_steps + 1
+        assert self.sun.shape[0] == self.n_stage
+
+    def materials(self, theta):
+        rs = theta[2 + 2 * self.group].astype(np.float32)
+        rd = theta[3 + 2 * self.group].astype(np.float32)
+        return rs, rd
+
+    def forces(self, theta):
+        """Body-frame force at every stage time [2n+1][3] (host FP64)."""
+        rs, rd = self.materials(theta)
+        self.scene.set_design(rs, rd, hinge_angles=theta[:2])
+        F, _ = self.scene.trace(self.sun, self.params)
+        return F.cpu().numpy()
+
+    def final_state(self, theta):
+        F = self.forces(theta)
+        return B.srp_orbit_rk4(self.sc.z0, self.sc.mu, self.sc.mass, self.sc.dt, self.sc.n_steps, F, self.sc.R), F
+
+    def loss(self, theta):
+        z, _ = self.final_state(theta)
+        d = z[:3] - self.r_target
+        return float(d @ d)
+
+    def loss_and_grad(self, theta):
+        theta = np.asarray(theta, dtype=np.float64)
+        z, F = self.final_state(theta)
+        d = z[:3] - self.r_target
+        g_final = np.concatenate([2.0 * d, np.zeros(3)])
+        gF, _ = B.srp_orbit_rk4_adjoint(self.sc.z0, self.sc.mu, self.sc.mass, self.sc.dt, self.sc.n_steps, F,
+                                        self.sc.R, g_final, self.ckpt_every)
+        g_rs, g_rd, g_h = self.scene.adjoint(self.sun, self.params, gF)
+        g_rs = g_rs.cpu().numpy().astype(np.float64)
+        g_rd = g_rd.cpu().numpy().astype(np.float64)
+        grad = np.zeros(8)
+        grad[:2] = g_h.cpu().numpy()[:2]
+        for k in range(3):
+            m = self.group == k
+            grad[2 + 2 * k] = g_rs[m].sum()
+            grad[3 + 2 * k] = g_rd[m].sum()
+        return float(d @ d), grad
+
+    def clip(self, theta):
+        th = np.clip(theta, self.lo, self.hi)
+        for k in range(3):  # rho_s + rho_d <= 1 per group
+            s = th[2 + 2 * k] + th[3 + 2 * k]
+            if s > 1.0:
+                th[2 + 2 * k] /= s
+                th[3 + 2 * k] /= s
+        return th
+
+    def optimise(self, theta0, iters=30, lr=None, betas=(0.9, 0.999), eps=1e-12, callback=None):
+        """Adam on theta with per-parameter step sizes lr (default: 2 % of each parameter's range),
+        clipping after every step.  Returns (theta, history of losses)."""
+        theta = self.clip(np.asarray(theta0, dtype=np.float64))
+        lr = 0.02 * (self.hi - self.lo) if lr is None else np.asarray(lr, dtype=np.float64)
+        m = np.zeros(8)
+        v = np.zeros(8)
+        hist = []
+        for t in range(1, iters + 1):
+            L, g = self.loss_and_grad(theta)
+            hist.append(L)
+            m = betas[0] * m + (1 - betas[0]) * g
+            v = betas[1] * v + (1 - betas[1]) * g * g
+            step = lr * (m / (1 - betas[0] ** t)) / (np.sqrt(v / (1 - betas[1] ** t)) + eps)
+            theta = self.clip(theta - step)
+            if callback:
+                callback(t, L, theta)
+        hist.append(self.loss(theta))
+        return theta, hist
+
+    def close(self):
+        self.scene.close()

@@ -338,3 +338,46 @@ def design_materials(mesh: Mesh, theta) -> tuple[np.ndarray, np.ndarray]:
 def random_designs(n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return DESIGN_LO + (DESIGN_HI - DESIGN_LO) * rng.uniform(size=(n, 8))
+
+
+# ---------------------------------------------------------------------------------------------
+# orbit scenario (inputs of the orbit integration: initial state, attitude at the stage times,
+# body-frame sun directions); a circular MEO orbit with a nadir-pointing attitude law
+# ---------------------------------------------------------------------------------------------
+MU_EARTH = 3.986004418e14  # m^3/s^2
+
+
+@dataclass
+class OrbitScenario:
+    z0: np.ndarray          # [6] inertial position (m) and velocity (m/s)
+    mu: float
+    mass: float             # kg
+    dt: float               # s
+    n_steps: int
+    R: np.ndarray           # [2 n + 1][3][3] body -> inertial rotation at the stage times t = k dt / 2
+    sun_body: np.ndarray    # [2 n + 1][3] unit sun direction in the body frame at the stage times
+    sun_inertial: np.ndarray
+
+
+def meo_orbit(n_steps: int = 1440, dt: float = 60.0, radius: float = 26_560_000.0, incl_deg: float = 55.0,
+              beta_deg: float = 30.0, mass: float = 1000.0) -> OrbitScenario:
+    """Circular orbit (right ascension of the ascending node 0) starting at the ascending node; the
+    attitude follows the nominal circular orbit (body +z to nadir, +y against the orbit normal,
+    +x = y x z along track), so it is a function of time only; the Sun is fixed in inertial space at
+    elevation beta above the orbit plane (beta = 30 deg > 13.9 deg: no eclipse at this radius)."""
+    i = np.deg2rad(incl_deg)
+    n_mean = np.sqrt(MU_EARTH / radius ** 3)
+    z0 = np.array([radius, 0.0, 0.0, 0.0, radius * n_mean * np.cos(i), radius * n_mean * np.sin(i)])
+    h_hat = np.array([0.0, -np.sin(i), np.cos(i)])
+    beta = np.deg2rad(beta_deg)
+    sun = np.cos(beta) * np.array([1.0, 0.0, 0.0]) + np.sin(beta) * h_hat
+    t = np.arange(2 * n_steps + 1) * (dt / 2.0)
+    u = n_mean * t
+    r_hat = np.stack([np.cos(u), np.sin(u) * np.cos(i), np.sin(u) * np.sin(i)], 1)
+    z_b = -r_hat
+    y_b = np.broadcast_to(-h_hat, z_b.shape)
+    x_b = np.cross(y_b, z_b)
+    R = np.ascontiguousarray(np.stack([x_b, y_b, z_b], 2))  # columns = body axes in inertial coordinates
+    sun_body = np.ascontiguousarray(np.einsum("kij,i->kj", R, sun))
+    return OrbitScenario(z0=z0, mu=MU_EARTH, mass=mass, dt=dt, n_steps=n_steps, R=R, sun_body=sun_body,
+                         sun_inertial=sun)
