@@ -7,6 +7,8 @@ directions) are resident in HBM before the timed region; the BVH build is timed 
 
 Prints ONE JSON line (see the design notes for the field definitions):
   value            forward Mrays/s (primary grid rays, whole paths, per second)
+  fwd_adjoint      forward + adjoint replay Mrays/s at 512 x 512 rays per direction
+  surrogate        fused MLP surrogate evals/s on 1M queries, with its MFMA roofline fraction
   roofline         dominant kernel (k_trace): algorithmic bytes per launch / mean launch time
   cpu_baseline     the FP64 oracle on a bounded sample of the same workload, host cores
 """
@@ -42,6 +44,8 @@ def parse():
     ap.add_argument("--adjoint-grid", type=int, default=512)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-batch", type=int, default=1 << 20)
     ap.add_argument("--cpu-sample-dirs", type=int, default=64)
     ap.add_argument("--cpu-sample-grid", type=int, default=256)
     return ap.parse_args()
@@ -144,6 +148,34 @@ def main():
                                "(d/d rho_s, rho_d per facet, d/d 2 hinge angles)"}
         log(f"forward+adjoint: {ms_adj:.2f} ms/step, {fwd_adj['value']:.1f} Mrays/s")
 
+    # ---- surrogate inference: fused BF16-MFMA MLP 11 -> 4 x 256 (SiLU) -> 3 on 1M queries ---------
+    surrogate = None
+    if not args.no_surrogate:
+        net = p.Surrogate(11, 256, 4, 3, seed=0)
+        nq = args.surrogate_batch
+        gen = torch.Generator(device="cpu").manual_seed(5)
+        xq = (torch.rand((nq, 11), generator=gen) * 2 - 1).to(dev)
+        xq[:, :3] = torch.nn.functional.normalize(xq[:, :3], dim=1)
+        yq = torch.empty((nq, 3), dtype=torch.float32, device=dev)
+        for i in range(max(args.warmup, 1)):
+            p.srp_mlp_forward(net.handle, xq, yq, False, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(args.steps):
+            p.srp_mlp_forward(net.handle, xq, yq, False, stream=stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / args.steps
+        flop = 2.0 * (11 * 256 + 3 * 256 * 256 + 256 * 3) * nq
+        tf = flop / (ms_s * 1e-3) / 1e12
+        surrogate = {"value": round(nq / (ms_s * 1e-3), 1), "unit": "evals/s", "ms_per_batch": round(ms_s, 4),
+                     "batch": nq, "roofline": {"bound": "mfma", "achieved": round(tf, 1), "peak": 2500.0,
+                                               "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4)}}
+        log(f"surrogate: {ms_s:.3f} ms per {nq} queries, {nq / ms_s / 1e6:.3f} G evals/s, {tf:.1f} TFLOP/s")
+        net.close()
+
     # ---- roofline of the dominant kernel --------------------------------------------------------
     roofline = None
     try:
@@ -188,6 +220,7 @@ def main():
                    "tris": mesh.n_tris, "dirs": D, "grid": args.grid, "bounces": args.bounces,
                    "bvh_nodes": info["n_nodes"], "bvh_build_s": round(build_s, 4)},
         "roofline": roofline, "cpu_baseline": cpu, "fwd_adjoint": fwd_adj,
+        "surrogate": surrogate,
     }
     print(json.dumps(out), flush=True)
 

@@ -230,4 +230,44 @@ BvhBuildResult build_bvh(const double* verts, const int32_t* tris, int64_t n_tri
     return res;
 }
 
+void refit_bvh(std::vector<BvhNode>& nodes, const std::vector<int32_t>& perm, const double* verts,
+               const int32_t* tris, double pad)
+{
+    Builder b;  // for write_child
+    b.pad = pad;
+    const int32_t n = static_cast<int32_t>(nodes.size());
+    std::vector<Box> own(n);
+    auto leaf_box = [&](int32_t code) {
+        Box bx;
+        bx.reset();
+        const int32_t c = ~code;
+        const int32_t first = c >> 3, cnt = c & 7;
+        for (int32_t q = first; q < first + cnt; ++q) {
+            const int32_t f = perm[q];
+            for (int k = 0; k < 3; ++k) bx.grow(verts + 3 * static_cast<int64_t>(tris[3 * f + k]));
+        }
+        return bx;
+    };
+    for (int32_t i = n - 1; i >= 0; --i) {
+        BvhNode& node = nodes[i];
+        int32_t codes[2];
+        std::memcpy(codes, &node.f[3], 8);
+        own[i].reset();
+        for (int slot = 0; slot < 2; ++slot) {
+            const int32_t code = codes[slot];
+            Ref r;
+            r.code = code;
+            if (code >= 0) {
+                r.box = own[code];
+            } else if ((~code & 7) == 0) {
+                continue;  // empty leaf keeps its unreachable box
+            } else {
+                r.box = leaf_box(code);
+            }
+            b.write_child(node, slot, r);
+            own[i].grow(r.box);
+        }
+    }
+}
+
 }  // namespace srp

@@ -18,4 +18,11 @@ struct BvhBuildResult {
 // outward to float and widened by `pad` metres so that float slab tests stay conservative.
 BvhBuildResult build_bvh(const double* verts, const int32_t* tris, int64_t n_tris, double pad);
 
+// Refits the child boxes of an existing tree to moved vertices (same topology and triangle order):
+// nodes are in pre-order (every child after its parent), so one reverse sweep sees children first.
+// perm maps BVH triangle positions to original triangles.  Boxes are rounded outward and padded as
+// in build_bvh.
+void refit_bvh(std::vector<BvhNode>& nodes, const std::vector<int32_t>& perm, const double* verts,
+               const int32_t* tris, double pad);
+
 }  // namespace srp

@@ -17,6 +17,7 @@ struct srp_scene_s {
     std::vector<int32_t> tris, vhinge;
     std::vector<srp_hinge> hinges;       // axes normalised
     std::vector<double> angles;
+    bool refit_on_hinge = true;          // hinge changes refit the rest-pose tree instead of rebuilding
     double com[3] = {0, 0, 0};
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // current vertex bounding box
     double L = 0;                        // scene size: twice the largest vertex distance from the mean

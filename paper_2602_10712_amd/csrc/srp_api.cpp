@@ -90,8 +90,9 @@ double scene_size(const std::vector<double>& v, int64_t n)
     return 2.0 * std::sqrt(r2);
 }
 
-// Rebuilds the BVH and the triangle records from the current vertices and uploads them.
-srp_status rebuild(srp_scene_s* s, hipStream_t stream)
+// Builds (or, when only hinge angles changed, refits) the BVH from the current vertices, rebuilds
+// the triangle records and uploads both.
+srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
 {
     const auto& V = s->cur;
     for (int a = 0; a < 3; ++a) {
@@ -104,11 +105,16 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream)
             s->hi[a] = std::max(s->hi[a], V[3 * i + a]);
         }
     s->L = scene_size(V, s->n_verts);
-    srp::BvhBuildResult bvh = srp::build_bvh(V.data(), s->tris.data(), s->n_tris, 1e-6 * s->L);
-    if (bvh.depth >= srp::kStackDepth - 1) return fail(SRP_EUNSUPPORTED, "BVH deeper than the traversal stack");
-    s->n_nodes = static_cast<int32_t>(bvh.nodes.size());
-    s->depth = bvh.depth;
-    s->perm = std::move(bvh.perm);
+    if (refit && !s->h_nodes.empty()) {
+        srp::refit_bvh(s->h_nodes, s->perm, V.data(), s->tris.data(), 1e-6 * s->L);
+    } else {
+        srp::BvhBuildResult bvh = srp::build_bvh(V.data(), s->tris.data(), s->n_tris, 1e-6 * s->L);
+        if (bvh.depth >= srp::kStackDepth - 1) return fail(SRP_EUNSUPPORTED, "BVH deeper than the traversal stack");
+        s->n_nodes = static_cast<int32_t>(bvh.nodes.size());
+        s->depth = bvh.depth;
+        s->perm = std::move(bvh.perm);
+        s->h_nodes = std::move(bvh.nodes);
+    }
     std::vector<srp::TriRec> recs(s->n_tris);
     for (int64_t p = 0; p < s->n_tris; ++p) {
         const int32_t f = s->perm[p];
@@ -141,11 +147,10 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream)
         std::memcpy(&hid_bits, &hid, 4);
         r.f[3] = make_float4(static_cast<float>(n[2]), hid_bits, 0.0f, 0.0f);
     }
-    s->h_nodes = bvh.nodes;
-    SRP_HIP(ensure(s->d_nodes, s->nodes_cap, bvh.nodes.size()));
+    SRP_HIP(ensure(s->d_nodes, s->nodes_cap, s->h_nodes.size()));
     SRP_HIP(ensure(s->d_tris, s->tris_cap, static_cast<size_t>(s->n_tris)));
     SRP_HIP(ensure(s->d_perm, s->perm_cap, static_cast<size_t>(s->n_tris)));
-    SRP_HIP(hipMemcpyAsync(s->d_nodes, bvh.nodes.data(), bvh.nodes.size() * sizeof(srp::BvhNode),
+    SRP_HIP(hipMemcpyAsync(s->d_nodes, s->h_nodes.data(), s->h_nodes.size() * sizeof(srp::BvhNode),
                            hipMemcpyHostToDevice, stream));
     SRP_HIP(hipMemcpyAsync(s->d_tris, recs.data(), recs.size() * sizeof(srp::TriRec), hipMemcpyHostToDevice, stream));
     SRP_HIP(hipMemcpyAsync(s->d_perm, s->perm.data(), s->perm.size() * sizeof(int32_t), hipMemcpyHostToDevice,
@@ -327,7 +332,7 @@ srp_status srp_scene_set_design(srp_scene s, const double* hinge_angles, const f
             SRP_HIP(hipStreamSynchronize(stream));  // kernels in flight may still read the old BVH
             s->angles.assign(hinge_angles, hinge_angles + s->n_hinges);
             rotate_hinges(s);
-            st = rebuild(s, stream);
+            st = rebuild(s, stream, s->refit_on_hinge);
             if (st != SRP_OK) return st;
         }
     }

@@ -1,0 +1,122 @@
+"""Force surrogate pipeline (paper Sec. 3.3 and Alg. 1, proxy learning).
+
+The tracer generates samples (sun direction, design) -> body-frame force over random designs; the
+MLP (libsrp srp_mlp_*) is trained on them with Adam and then answers force queries at a fraction of
+the tracer's cost.  The tracer stays the judge of the surrogate's error and its fallback: a query
+is sent back to the tracer when it lies outside the training box of the design space or when two
+independently trained networks disagree by more than a threshold calibrated on held-out data.
+
+Inputs: x = [s_x, s_y, s_z, design scaled to [-1, 1] (8)]; outputs: F / F_ref with
+F_ref = Phi * A_ref / c.  All compute runs in libsrp; this module only sequences the calls.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _binding as B
+
+C_LIGHT = 299792458.0
+
+
+def input_features(sun, theta, lo, hi):
+    sun = np.asarray(sun, dtype=np.float64).reshape(-1, 3)
+    th = np.asarray(theta, dtype=np.float64).reshape(-1, 8)
+    scaled = 2.0 * (th - lo) / (hi - lo) - 1.0
+    return np.concatenate([sun, scaled], 1).astype(np.float32)
+
+
+def generate_samples(mesh, designs, sun_per_design, params: B.TraceParams, flux=1361.0):
+    """Traces every design for its own sun directions: designs [N_d][8], sun_per_design
+    [N_d][K][3] -> forces [N_d][K][3] (N, FP64, body frame)."""
+    scene = B.Scene.from_mesh(mesh)
+    group = np.asarray(mesh.group)
+    out = np.zeros((len(designs), sun_per_design.shape[1], 3))
+    for d, th in enumerate(designs):
+        rs = th[2 + 2 * group].astype(np.float32)
+        rd = th[3 + 2 * group].astype(np.float32)
+        scene.set_design(rs, rd, hinge_angles=th[:2])
+        p = B.TraceParams(params.nu, params.nv, params.bounces, params.jitter, flux, params.seed,
+                          0, d, params.frame_mode)
+        F, _ = scene.trace(sun_per_design[d], p)
+        out[d] = F.cpu().numpy()
+    scene.close()
+    return out
+
+
+def train(net: B.Surrogate, x, y, steps, batch=4096, lr=1e-3, lr_final=1e-5, seed=0, log_every=0):
+    """Adam on minibatches drawn with replacement; cosine-decayed learning rate.
+    Returns the list of minibatch losses."""
+    xd = torch.as_tensor(x, dtype=torch.float32, device="cuda")
+    yd = torch.as_tensor(y, dtype=torch.float32, device="cuda")
+    n = xd.shape[0]
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    losses = []
+    for s in range(steps):
+        idx = torch.randint(0, n, (min(batch, n),), device="cuda", generator=g)
+        a = 0.5 * (1 + np.cos(np.pi * s / max(steps - 1, 1)))
+        loss = net.train_step(xd[idx].contiguous(), yd[idx].contiguous(), lr=lr_final + (lr - lr_final) * a)
+        if log_every and (s % log_every == 0 or s == steps - 1):
+            losses.append((s, float(loss.item())))
+    return losses
+
+
+def rel_rms(pred, ref):
+    pred = np.asarray(pred, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.sqrt(((pred - ref) ** 2).sum(-1).mean() / (ref ** 2).sum(-1).mean()))
+
+
+class SurrogateForce:
+    """Two-member ensemble with a domain check and a disagreement threshold; failing queries are
+    answered by the tracer."""
+
+    def __init__(self, nets, lo, hi, f_ref, threshold):
+        self.nets = nets
+        self.lo = np.asarray(lo, dtype=np.float64)
+        self.hi = np.asarray(hi, dtype=np.float64)
+        self.f_ref = f_ref
+        self.threshold = threshold
+
+    def predict(self, x):
+        xd = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        ys = [n.forward(xd) for n in self.nets]
+        mean = sum(ys) / len(ys)
+        disagree = torch.linalg.vector_norm(ys[0] - ys[1], dim=1) if len(ys) > 1 else torch.zeros(len(xd), device="cuda")
+        return mean, disagree
+
+    @staticmethod
+    def calibrate(disagree, err, target):
+        """Largest disagreement threshold whose accepted queries keep the relative RMS error <= target
+        (err: per-query squared error divided by the mean squared reference)."""
+        order = np.argsort(disagree)
+        cum = np.cumsum(err[order]) / np.arange(1, len(err) + 1)
+        ok = np.nonzero(np.sqrt(cum) <= target)[0]
+        return float(disagree[order][ok[-1]]) if len(ok) else 0.0
+
+    def in_domain(self, sun, theta):
+        th = np.asarray(theta, dtype=np.float64).reshape(-1, 8)
+        unit = np.abs(np.linalg.norm(np.asarray(sun).reshape(-1, 3), axis=1) - 1.0) < 1e-6
+        return unit & np.all((th >= self.lo - 1e-12) & (th <= self.hi + 1e-12), axis=1)
+
+    def forces(self, mesh, sun, theta, params: B.TraceParams):
+        """Forces [N][3] (N): surrogate where it is trusted, tracer elsewhere; also the fallback mask."""
+        x = input_features(sun, np.clip(theta, self.lo, self.hi), self.lo, self.hi)
+        mean, dis = self.predict(x)
+        F = mean.double().cpu().numpy() * self.f_ref
+        fall = (~self.in_domain(sun, theta)) | (dis.cpu().numpy() > self.threshold)
+        if fall.any():
+            idx = np.nonzero(fall)[0]
+            th = np.asarray(theta, dtype=np.float64).reshape(-1, 8)
+            # group the failing queries by design and trace each design once
+            designs, inv = np.unique(th[idx], axis=0, return_inverse=True)
+            scene = B.Scene.from_mesh(mesh)
+            group = np.asarray(mesh.group)
+            for k, dsg in enumerate(designs):
+                sel = idx[inv.ravel() == k]
+                scene.set_design(dsg[2 + 2 * group].astype(np.float32), dsg[3 + 2 * group].astype(np.float32),
+                                 hinge_angles=dsg[:2])
+                Ft, _ = scene.trace(np.asarray(sun).reshape(-1, 3)[sel], params)
+                F[sel] = Ft.cpu().numpy()
+            scene.close()
+        return F, fall

@@ -73,8 +73,14 @@ def test_adam_step_and_checkpoint_resume():
     grads, _ = om.backward(layers, cache, gy)
     g = om.flatten(grads)
     p1, m1, v1 = om.adam_step(flat, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-2, 0.9, 0.999, 1.0)
-    assert rel_l2(st["params"] - flat, p1 - flat) <= 1e-3
+    # the first moment is (1 - beta1) g: the gradient itself
     assert rel_l2(st["adam_m"], m1) <= 1e-3
+    # the update is ~1e-5 on weights ~0.25: compare it up to the float32 spacing of the weights
+    d_gpu = st["params"].astype(np.float64) - flat
+    d_ref = p1 - flat
+    tol = 1e-2 * np.abs(d_ref) + 4 * np.spacing(np.abs(flat).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(d_gpu - d_ref) <= tol)
+    assert rel_l2(d_gpu, d_ref) <= 3e-3
     assert st["step"] == 1 and not st["grads"].any()
     # checkpoint -> new network -> identical next step
     s2 = p.Surrogate(n_in, width, depth, n_out, seed=99)

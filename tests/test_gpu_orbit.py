@@ -1,0 +1,73 @@
+"""Design optimisation through the orbit on the GPU: batched trace -> RK4 -> discrete adjoint ->
+ray adjoint -> design-group gradients.
+
+  * gradient of L = |r_N - r_target|^2 with respect to the six group reflectances vs central
+    differences (h = 1e-4) of the same chain with frozen specular-sampling probabilities
+    (the estimator is then polynomial in the reflectances): relative error <= 1e-3;
+  * hinge-angle gradients vs central differences: reported (visibility-edge terms excluded);
+  * an optimisation from a perturbed design reduces the miss distance to a hidden design's end
+    point by at least 100x.
+"""
+import numpy as np
+import pytest
+
+import srp_inputs as si
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _problem(n_steps, grid, p_spec=None):
+    import paper_2602_10712_amd as p
+    mesh = si.meo_satellite()
+    sc = si.meo_orbit(n_steps=n_steps, dt=60.0)
+    params = p.TraceParams(nu=grid, nv=grid, bounces=3, seed=5)
+    prob = p.DesignProblem(mesh, sc, params, si.DESIGN_LO, si.DESIGN_HI)
+    return prob
+
+
+def test_group_gradient_vs_central_differences():
+    prob = _problem(240, 128)
+    theta_star = np.array([0.25, -0.15, 0.3, 0.2, 0.15, 0.35, 0.1, 0.3])
+    prob.r_target = prob.final_state(theta_star)[0][:3]
+    theta = np.array([0.1, -0.05, 0.2, 0.25, 0.2, 0.3, 0.15, 0.25])
+    # frozen specular-sampling probability 0.5 on every facet for all evaluations
+    ps = np.full(prob.mesh.n_tris, 0.5, np.float32)
+    orig = prob.scene.set_design
+
+    def set_design(rs, rd, hinge_angles=None, p_spec=None, stream=None):
+        return orig(rs, rd, hinge_angles=hinge_angles, p_spec=ps, stream=stream)
+
+    prob.scene.set_design = set_design
+    L, g = prob.loss_and_grad(theta)
+    h = 1e-4
+    for k in range(2, 8):
+        tp = theta.copy()
+        tp[k] += h
+        tm = theta.copy()
+        tm[k] -= h
+        # reflectances enter as float32: use the realised step
+        hk = float(np.float32(tp[k])) - float(np.float32(tm[k]))
+        fd = (prob.loss(tp) - prob.loss(tm)) / hk
+        print(f"group {k}: adjoint {g[k]:.6e} FD {fd:.6e}")
+        assert abs(fd - g[k]) <= 1e-3 * np.abs(g[2:]).max()
+    for k in range(2):
+        tp = theta.copy()
+        tp[k] += 1e-3
+        tm = theta.copy()
+        tm[k] -= 1e-3
+        fd = (prob.loss(tp) - prob.loss(tm)) / 2e-3
+        print(f"hinge {k}: adjoint {g[k]:.6e} full finite difference {fd:.6e} (visibility edges excluded)")
+    prob.close()
+
+
+def test_optimise_to_hidden_design():
+    prob = _problem(720, 128)
+    theta_star = np.array([0.3, -0.2, 0.35, 0.1, 0.2, 0.3, 0.05, 0.4])
+    prob.r_target = prob.final_state(theta_star)[0][:3]
+    theta0 = np.array([0.0, 0.0, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25])
+    L0 = prob.loss(theta0)
+    theta, hist = prob.optimise(theta0, iters=40)
+    print(f"miss distance {np.sqrt(L0):.3f} m -> {np.sqrt(hist[-1]):.4f} m; theta {np.round(theta, 3)}")
+    assert hist[-1] <= 1e-4 * L0
+    prob.close()
