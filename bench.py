@@ -33,6 +33,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ["srp_path.h", "srp_traverse.h", "srp_internal.h", "trace_kernels.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2602_10712_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_trace launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy's counters), or None when the kernel sources changed since then."""
+    path = os.path.join(ROOT, "profiles", "k_trace_meo20k_traffic.md")
+    try:
+        text = open(path).read()
+        blob = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(blob)
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,6 +73,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-batch", type=int, default=1 << 20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the HBM traffic counters)")
     ap.add_argument("--cpu-sample-dirs", type=int, default=64)
     ap.add_argument("--cpu-sample-grid", type=int, default=256)
     return ap.parse_args()
@@ -58,6 +87,17 @@ def main():
               "described in the design notes but not built", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.copy_calibration:
+        torch.cuda.set_device(0)
+        n = 1 << 28  # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
+        return
 
     import paper_2602_10712_amd as p
     import srp_inputs as si
@@ -185,7 +225,7 @@ def main():
         # one launch = all D x grid^2 rays; mean launch time ~ srp_trace time (frames + reduce < 1 %)
         achieved = bytes_per_ray * rays / (np.median(step_ms) * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                     "bytes_per_ray": round(bytes_per_ray, 1), "segments_per_ray": round(st["segments_per_ray"], 4),
                     "nodes_per_segment": round(st["nodes_per_segment"], 2),
                     "tris_per_segment": round(st["tris_per_segment"], 2)}

@@ -25,6 +25,9 @@
  *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Launches are enqueued
  *     on it without synchronising, except where a call says otherwise.  Device faults surface
  *     as SRP_EDEVICE from a later call or from srp_sync().
+ *   - A scene owns workspace (frames, partial sums, gradient accumulators) that every call on it
+ *     reuses: calls on one scene must be ordered, i.e. issued on one stream or synchronised by
+ *     the caller.  Calls on different scenes are independent.
  *   - Random draws: Philox4x32-10 (Salmon et al., SC'11) with key = seed and counter =
  *     (pixel, global direction index, bounce, design index); uniforms are the top 24 bits
  *     times 2^-24.  Identical arguments give bit-identical ray sets on every call.
@@ -91,7 +94,8 @@ srp_status srp_scene_create(const double* verts, int64_t n_verts, const int32_t*
 
 /* Applies a design (paper Sec. 3.1: the design maps to a mesh with per-face materials):
  *   hinge_angles host [n_hinges] radians (NULL = keep the current angles); the panel vertices
- *   are rotated in FP64 and the BVH is rebuilt on the host when the angles change;
+ *   are rotated in FP64 and, when the angles change, the boxes of the rest-pose BVH are refitted
+ *   on the host (same topology and triangle order) and uploaded;
  *   rho_s, rho_d device float [n_tris] (original facet order), 0 <= rho, rho_s + rho_d <= 1;
  *   p_spec device float [n_tris] or NULL: frozen probability of sampling the specular event at
  *   each facet.  NULL selects rho_s/(rho_s + rho_d) clamped to [0.01, 0.99] when both are
@@ -128,6 +132,27 @@ srp_status srp_trace_records(srp_scene scene, const double* sun_dirs, int64_t D,
                              const double* frames, const int64_t* pix, int64_t n_pix, int32_t* hit_prim,
                              float* ray_force, void* stream);
 
+/* Reverse-mode gradient of the forward estimator (paper Sec. 3.4, differentiable radiation
+ * pressure: gradients of force and torque with respect to the design), for the same rays as
+ * srp_trace with the same arguments.  Given cotangents g_force and g_torque (device double [D][3];
+ * g_torque may be NULL = 0) of L = sum_j g_force[j].F_j + g_torque[j].tau_j, the call ADDS
+ *   dL/d rho_s, dL/d rho_d  to g_rho_s, g_rho_d (device float [n_tris], original facet order, may be
+ *                           NULL): exact derivatives of the estimator with the sampled event
+ *                           sequences held fixed (the specular-sampling probabilities are
+ *                           frozen, so each path's weight is a polynomial in the reflectances);
+ *   dL/d hinge angle        to g_hinge (device double [n_hinges], may be NULL; at most 4 hinges,
+ *                           else SRP_EUNSUPPORTED): derivative of every hit point, normal, grid
+ *                           footprint and secondary ray under the rotation, with the facet hit at
+ *                           every interaction held fixed.  Terms from rays that cross a
+ *                           silhouette edge as the panel turns (visibility changes) are not
+ *                           included.
+ * Gradients are summed in FP64 (wavefront-aggregated atomics per facet, fixed-order sums per
+ * direction for the hinges) and rounded to float for g_rho_s and g_rho_d.  Uses scene workspace;
+ * calls on the same scene must be ordered on one stream. */
+srp_status srp_trace_adjoint(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
+                             const double* frames, const double* g_force, const double* g_torque, float* g_rho_s,
+                             float* g_rho_d, double* g_hinge, void* stream);
+
 /* Traversal statistics for the bandwidth model: a host-side single-ray depth-first closest-hit
  * traversal (nearer child first) of this scene's BVH on the same rays as srp_trace, for every
  * pixel_stride-th pixel of each direction.  sun_dirs and frames are HOST arrays here.
@@ -135,6 +160,16 @@ srp_status srp_trace_records(srp_scene scene, const double* sun_dirs, int64_t D,
  * tested, surface hits.  Synchronous; reads the materials back from the device. */
 srp_status srp_scene_ray_stats(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
                                const double* frames, int64_t pixel_stride, double* out);
+
+/* Batched designs (paper Sec. 3.2, "Estimation": samples are drawn over many designs at once): one
+ * launch traces S scenes for the same D sun directions (device double [D][3]).  Design s uses
+ * Philox design index params->design_index + s and its own mesh-derived frames (frame_mode must be
+ * 0).  force, torque: device double [S][D][3] (torque may be NULL).  Work is split design-major and
+ * each design runs on one XCD (its BVH stays in one L2).  Workspace belongs to scenes[0]; all scenes
+ * must be on the current device.  The design table is uploaded on `stream` from pinned staging; a
+ * call waits for the previous batch upload led by the same scene before reusing the staging. */
+srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
+                           const srp_trace_params* params, double* force, double* torque, void* stream);
 
 srp_status srp_scene_destroy(srp_scene scene);
 

@@ -48,6 +48,7 @@ _sigs = {
     "srp_trace_records": [P, P, I64, ctypes.POINTER(TraceParams), P, P, I64, P, P, P],
     "srp_scene_ray_stats": [P, P, I64, ctypes.POINTER(TraceParams), P, I64, P],
     "srp_trace_adjoint": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P, P, P, P],
+    "srp_batch_trace": [P, I32, P, I64, ctypes.POINTER(TraceParams), P, P, P],
     "srp_scene_destroy": [P],
     "srp_mlp_create": [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)],
     "srp_mlp_num_params": [P, ctypes.POINTER(I64)],
@@ -200,6 +201,18 @@ def srp_trace_adjoint(scene, sun_dirs, params: TraceParams, g_force, g_torque=No
     _check(_lib.srp_trace_adjoint(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params), _dptr(frames),
                                   _dptr(g_force), _dptr(g_torque), _dptr(g_rho_s), _dptr(g_rho_d), _dptr(g_hinge),
                                   _stream(stream)))
+
+
+def srp_batch_trace(scenes, sun_dirs, params: TraceParams, force, torque=None, stream=None):
+    """scenes: sequence of scene handles (or Scene objects); force/torque device double [S][D][3]."""
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(force, torch.float64, "force")
+    _dtype_check(torque, torch.float64, "torque")
+    hs = [s.handle if isinstance(s, Scene) else s for s in scenes]
+    arr = (P * len(hs))(*[h.value if isinstance(h, P) else h for h in hs])
+    _check(_lib.srp_batch_trace(ctypes.cast(arr, P), len(hs), _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params),
+                                _dptr(force), _dptr(torque), _stream(stream)))
 
 
 def srp_scene_ray_stats(scene, sun_dirs, params: TraceParams, pixel_stride=1, frames=None):

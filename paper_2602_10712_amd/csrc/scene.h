@@ -43,6 +43,13 @@ struct srp_scene_s {
     size_t grho_cap = 0;
     double* d_hdir = nullptr;            // adjoint: per-direction hinge sums [D][kMaxHinges]
     size_t hdir_cap = 0;
+    // batched traces led by this scene: design table, staged in pinned host memory and uploaded
+    // on the caller's stream; batch_ev marks the end of the last upload (staging reuse waits on it)
+    srp::SceneDesc* h_batch_desc = nullptr;
+    size_t h_batch_desc_cap = 0;
+    hipEvent_t batch_ev = nullptr;
+    srp::SceneDesc* d_batch_desc = nullptr;
+    size_t batch_desc_cap = 0;
 };
 
 // Records `msg` as the thread's last error and returns `st`.

@@ -455,6 +455,82 @@ srp_status srp_trace_adjoint(srp_scene s, const double* sun_dirs, int64_t D, con
     return SRP_OK;
 }
 
+srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
+                           const srp_trace_params* p, double* force, double* torque, void* stream_)
+{
+    if (!scenes || S < 1) return fail(SRP_EINVAL, "need at least one scene");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (p->frame_mode != 0) return fail(SRP_EUNSUPPORTED, "batched traces derive their frames from each mesh");
+    if (D < 0) return fail(SRP_EINVAL, "D must be >= 0");
+    if (D == 0) return SRP_OK;
+    if (!sun_dirs || !force) return fail(SRP_EINVAL, "sun_dirs and force are required");
+    if (p->dir_index_base + D > (int64_t(1) << 32)) return fail(SRP_EINVAL, "direction index exceeds 32 bits");
+    srp_scene_s* lead = scenes[0];
+    for (int32_t s = 0; s < S; ++s) {
+        if (!scenes[s]) return fail(SRP_EINVAL, "NULL scene in the batch");
+        if (scenes[s]->device != lead->device) return fail(SRP_EINVAL, "all scenes must live on one device");
+    }
+    st = bind_device(lead);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const int64_t units = static_cast<int64_t>(S) * D;
+    SRP_HIP(ensure(lead->d_frames, lead->frames_cap, static_cast<size_t>(units)));
+    for (int32_t s = 0; s < S; ++s)
+        SRP_HIP(srp::launch_frames(sun_dirs, D, scenes[s]->lo, scenes[s]->hi, scenes[s]->L, p->nu, p->nv, p->flux,
+                                   nullptr, nullptr, lead->d_frames + static_cast<int64_t>(s) * D, stream));
+    // the staging table is rewritten only after the previous upload from it has run
+    if (lead->batch_ev) SRP_HIP(hipEventSynchronize(lead->batch_ev));
+    if (lead->h_batch_desc_cap < static_cast<size_t>(S)) {
+        if (lead->h_batch_desc) SRP_HIP(hipHostFree(lead->h_batch_desc));
+        lead->h_batch_desc = nullptr;
+        lead->h_batch_desc_cap = 0;
+        SRP_HIP(hipHostMalloc(reinterpret_cast<void**>(&lead->h_batch_desc), sizeof(srp::SceneDesc) * S));
+        lead->h_batch_desc_cap = static_cast<size_t>(S);
+    }
+    for (int32_t s = 0; s < S; ++s) {
+        srp::SceneDesc& d = lead->h_batch_desc[s];
+        d.nodes = scenes[s]->d_nodes;
+        d.tris = scenes[s]->d_tris;
+        d.mat = scenes[s]->d_mat;
+        for (int k = 0; k < 3; ++k) d.com[k] = static_cast<float>(scenes[s]->com[k]);
+        d.eps = static_cast<float>(1e-5 * scenes[s]->L);
+    }
+    SRP_HIP(ensure(lead->d_batch_desc, lead->batch_desc_cap, static_cast<size_t>(S)));
+    SRP_HIP(hipMemcpyAsync(lead->d_batch_desc, lead->h_batch_desc, sizeof(srp::SceneDesc) * S,
+                           hipMemcpyHostToDevice, stream));
+    if (!lead->batch_ev) SRP_HIP(hipEventCreateWithFlags(&lead->batch_ev, hipEventDisableTiming));
+    SRP_HIP(hipEventRecord(lead->batch_ev, stream));
+    srp::TraceArgs a{};
+    a.scenes = lead->d_batch_desc;
+    a.n_scenes = S;
+    a.scene_slots = (S + 7) / 8 * 8;
+    a.frames = lead->d_frames;
+    a.D = D;
+    a.nu = p->nu;
+    a.nv = p->nv;
+    a.bounces = p->bounces;
+    a.jitter = p->jitter ? 1 : 0;
+    a.seed_lo = static_cast<uint32_t>(p->seed);
+    a.seed_hi = static_cast<uint32_t>(p->seed >> 32);
+    a.dir_index_base = p->dir_index_base;
+    a.design_index = static_cast<uint32_t>(p->design_index);
+    a.tiles_x = (p->nu + srp::kTileW - 1) / srp::kTileW;
+    a.tiles_y = (p->nv + srp::kTileH - 1) / srp::kTileH;
+    a.tiles_per_dir = static_cast<int64_t>(a.tiles_x) * a.tiles_y;
+    const int64_t total_tiles = a.tiles_per_dir * units;
+    int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(16, total_tiles / (int64_t(srp::kWaves) * 8192)));
+    a.tiles_per_wave = static_cast<int32_t>(tpw);
+    const int64_t bpd = std::max<int64_t>(1, (a.tiles_per_dir + tpw * srp::kWaves - 1) / (tpw * srp::kWaves));
+    if (bpd * D * a.scene_slots > 0x7fffffffLL) return fail(SRP_EINVAL, "batched trace too large for one launch");
+    a.blocks_per_dir = static_cast<int32_t>(bpd);
+    SRP_HIP(ensure(lead->d_partials, lead->partials_cap, static_cast<size_t>(bpd * units * 6)));
+    a.partials = lead->d_partials;
+    SRP_HIP(srp::launch_trace_batch(a, stream));
+    SRP_HIP(srp::launch_reduce(lead->d_partials, units, a.blocks_per_dir, force, torque, stream));
+    return SRP_OK;
+}
+
 srp_status srp_scene_destroy(srp_scene s)
 {
     if (!s) return SRP_OK;
@@ -470,6 +546,12 @@ srp_status srp_scene_destroy(srp_scene s)
     (void)hipFree(s->d_partials);
     (void)hipFree(s->d_grho);
     (void)hipFree(s->d_hdir);
+    (void)hipFree(s->d_batch_desc);
+    if (s->batch_ev) {
+        (void)hipEventSynchronize(s->batch_ev);
+        (void)hipEventDestroy(s->batch_ev);
+    }
+    (void)hipHostFree(s->h_batch_desc);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete s;
     return SRP_OK;

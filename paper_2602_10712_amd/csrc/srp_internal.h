@@ -44,11 +44,23 @@ struct DevFrame {
     float pad[3];
 };
 
+// One design of a batched trace (device array, one entry per scene).
+struct SceneDesc {
+    const BvhNode* nodes;
+    const TriRec* tris;
+    const float4* mat;
+    float com[3];
+    float eps;
+};
+
 struct TraceArgs {
+    const SceneDesc* scenes;  // batched trace: [n_scenes] (null for a single scene)
+    int32_t n_scenes;
+    int32_t scene_slots;      // designs in the launch grid (n_scenes rounded up to a multiple of 8)
     const BvhNode* nodes;
     const TriRec* tris;
     const float4* mat;        // BVH order: (rho_s, rho_d, p_spec, 0)
-    const DevFrame* frames;   // [D]
+    const DevFrame* frames;   // [D], or [n_scenes][D] for a batched trace
     int64_t D;
     int32_t nu, nv;
     int32_t bounces;
@@ -64,7 +76,7 @@ struct TraceArgs {
     int32_t blocks_per_dir;
     const int64_t* pix;       // records mode: explicit pixel list, or null = all pixels
     int64_t n_pix;
-    double* partials;         // [D][blocks_per_dir][6]
+    double* partials;         // [(scene *) D][blocks_per_dir][6]
     int32_t* rec_hit;         // [D][n_pix][bounces]
     float* rec_force;         // [D][n_pix][3]
 };
@@ -90,6 +102,7 @@ hipError_t launch_frames(const double* sun_dirs, int64_t D, const double lo[3], 
 hipError_t launch_pack_materials(const float* rho_s, const float* rho_d, const float* p_spec, const int32_t* perm,
                                  int64_t n, float4* mat, int32_t* bad_flag, hipStream_t stream);
 hipError_t launch_trace(const TraceArgs& a, bool records, hipStream_t stream);
+hipError_t launch_trace_batch(const TraceArgs& a, hipStream_t stream);
 hipError_t launch_reduce(const double* partials, int64_t D, int32_t blocks_per_dir, double* force, double* torque,
                          hipStream_t stream);
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream);

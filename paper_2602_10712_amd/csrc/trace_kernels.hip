@@ -71,19 +71,56 @@ __global__ void k_pack_mat(const float* __restrict__ rs, const float* __restrict
     mat[p] = make_float4(a, b, q, 0.0f);
 }
 
-template <bool RECORDS>
+// BATCH: the launch covers n_scenes designs; hardware block b runs on XCD b % 8, so design s is
+// handled entirely by XCD s % 8 (its BVH stays in that XCD's L2) in design-major order.
+template <bool RECORDS, bool BATCH>
 __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
 {
     __shared__ int s_stack[kWaves][kStackDepth];
     __shared__ float s_red[kWaves][6];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t j = blockIdx.x / a.blocks_per_dir;
-    const int32_t blk = blockIdx.x % a.blocks_per_dir;
-    const DevFrame fr = a.frames[j];
+    int64_t unit;  // (scene *) D + direction
+    int32_t blk;
+    const BvhNode* __restrict__ nodes;
+    const TriRec* __restrict__ tris;
+    const float4* __restrict__ mat;
+    float com[3], eps;
+    uint32_t design = a.design_index;
+    int64_t j;
+    if (BATCH) {
+        const int64_t per_design = a.D * a.blocks_per_dir;
+        const int64_t b = blockIdx.x;
+        const int64_t xcd = b & 7, k = b >> 3;
+        const int64_t s = xcd + 8 * (k / per_design);
+        if (s >= a.n_scenes) return;
+        const int64_t r = k % per_design;
+        j = r / a.blocks_per_dir;
+        blk = static_cast<int32_t>(r % a.blocks_per_dir);
+        unit = s * a.D + j;
+        const SceneDesc sd = a.scenes[s];
+        nodes = sd.nodes;
+        tris = sd.tris;
+        mat = sd.mat;
+        com[0] = sd.com[0];
+        com[1] = sd.com[1];
+        com[2] = sd.com[2];
+        eps = sd.eps;
+        design += static_cast<uint32_t>(s);
+    } else {
+        j = blockIdx.x / a.blocks_per_dir;
+        blk = blockIdx.x % a.blocks_per_dir;
+        unit = j;
+        nodes = a.nodes;
+        tris = a.tris;
+        mat = a.mat;
+        com[0] = a.com[0];
+        com[1] = a.com[1];
+        com[2] = a.com[2];
+        eps = a.eps;
+    }
+    const DevFrame fr = a.frames[unit];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
-    const BvhNode* __restrict__ nodes = a.nodes;
-    const TriRec* __restrict__ tris = a.tris;
     int* stack = s_stack[wave];
 
     float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
@@ -95,7 +132,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
         const int32_t pi = static_cast<int32_t>(pixel % a.nu);
         const int32_t pk = static_cast<int32_t>(pixel / a.nu);
         float o[3], d[3];
-        primary_ray(fr, pi, pk, static_cast<uint32_t>(pixel), dir_global, a.design_index, a.seed_lo, a.seed_hi,
+        primary_ray(fr, pi, pk, static_cast<uint32_t>(pixel), dir_global, design, a.seed_lo, a.seed_hi,
                     a.jitter != 0, o, d);
         float w = fr.w;
         bool alive = valid;
@@ -113,14 +150,14 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
                 continue;
             }
             const TriRec tr = tris[hit];
-            const float4 mt = a.mat[hit];
+            const float4 mt = mat[hit];
             if (RECORDS) a.rec_hit[(j * a.n_pix + rec) * a.bounces + (b - 1)] = __float_as_int(tr.f[0].w);
             b_done = b;
             const float n[3] = {tr.f[1].w, tr.f[2].w, tr.f[3].x};
             float x[3], g[3];
             alive = interact(o, d, w, t, n, mt.x, mt.y, mt.z, b, a.bounces, static_cast<uint32_t>(pixel), dir_global,
-                             a.design_index, a.seed_lo, a.seed_hi, a.eps, x, g);
-            const float lx = x[0] - a.com[0], ly = x[1] - a.com[1], lz = x[2] - a.com[2];
+                             design, a.seed_lo, a.seed_hi, eps, x, g);
+            const float lx = x[0] - com[0], ly = x[1] - com[1], lz = x[2] - com[2];
             ray[0] += g[0];
             ray[1] += g[1];
             ray[2] += g[2];
@@ -151,7 +188,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
     if (threadIdx.x < 6) {
         double s = 0.0;
         for (int q = 0; q < kWaves; ++q) s += static_cast<double>(s_red[q][threadIdx.x]);
-        a.partials[(j * a.blocks_per_dir + blk) * 6 + threadIdx.x] = s;
+        a.partials[(unit * a.blocks_per_dir + blk) * 6 + threadIdx.x] = s;
     }
 }
 
@@ -204,9 +241,18 @@ hipError_t launch_trace(const TraceArgs& a, bool records, hipStream_t stream)
     const unsigned blocks = static_cast<unsigned>(a.D * a.blocks_per_dir);
     if (blocks == 0) return hipSuccess;
     if (records)
-        hipLaunchKernelGGL(k_trace<true>, dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+        hipLaunchKernelGGL((k_trace<true, false>), dim3(blocks), dim3(64 * kWaves), 0, stream, a);
     else
-        hipLaunchKernelGGL(k_trace<false>, dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+        hipLaunchKernelGGL((k_trace<false, false>), dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_batch(const TraceArgs& a, hipStream_t stream)
+{
+    const int64_t blocks = static_cast<int64_t>(a.scene_slots) * a.D * a.blocks_per_dir;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_trace<false, true>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
     return hipGetLastError();
 }
 

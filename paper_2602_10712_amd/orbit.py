@@ -84,20 +84,24 @@ class DesignProblem:
                 th[3 + 2 * k] /= s
         return th
 
-    def optimise(self, theta0, iters=30, lr=None, betas=(0.9, 0.999), eps=1e-12, callback=None):
-        """Adam on theta with per-parameter step sizes lr (default: 2 % of each parameter's range),
-        clipping after every step.  Returns (theta, history of losses)."""
+    def optimise(self, theta0, iters=30, lr=None, betas=(0.9, 0.999), eps=1e-12, free=None, callback=None):
+        """Adam on theta with per-parameter step sizes lr (default: 2 % of each parameter's range)
+        decayed by a cosine schedule to 5 % of it, clipping after every step.  Returns (theta,
+        history of losses)."""
         theta = self.clip(np.asarray(theta0, dtype=np.float64))
         lr = 0.02 * (self.hi - self.lo) if lr is None else np.asarray(lr, dtype=np.float64)
+        mask = np.ones(8) if free is None else np.asarray(free, dtype=np.float64)
         m = np.zeros(8)
         v = np.zeros(8)
         hist = []
         for t in range(1, iters + 1):
             L, g = self.loss_and_grad(theta)
+            g = g * mask
             hist.append(L)
             m = betas[0] * m + (1 - betas[0]) * g
             v = betas[1] * v + (1 - betas[1]) * g * g
-            step = lr * (m / (1 - betas[0] ** t)) / (np.sqrt(v / (1 - betas[1] ** t)) + eps)
+            decay = 0.05 + 0.95 * 0.5 * (1.0 + np.cos(np.pi * (t - 1) / max(iters - 1, 1)))
+            step = decay * lr * (m / (1 - betas[0] ** t)) / (np.sqrt(v / (1 - betas[1] ** t)) + eps)
             theta = self.clip(theta - step)
             if callback:
                 callback(t, L, theta)

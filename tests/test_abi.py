@@ -50,3 +50,16 @@ def test_last_error_callable_without_gpu():
                               ctypes.byref(out))
     assert st == -1
     assert b"empty" in lib.srp_last_error()
+
+
+def test_every_exported_entry_point_is_declared():
+    import shutil
+    import subprocess
+    lib_path = os.path.join(ROOT, "paper_2602_10712_amd", "libsrp.so")
+    if not os.path.exists(lib_path) or not shutil.which("nm"):
+        pytest.skip("libsrp.so not built or nm missing")
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_path], capture_output=True, text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.split() and ln.split()[-2] == "T"}
+    exported = {n for n in exported if n.startswith("srp_")}
+    undeclared = sorted(exported - declared_functions())
+    assert not undeclared, undeclared
