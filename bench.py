@@ -238,7 +238,8 @@ def main():
         import oracle
         n_s, g_s = args.cpu_sample_dirs, args.cpu_sample_grid
         idx = np.linspace(0, D - 1, n_s).astype(int)
-        cores = os.cpu_count() or 1
+        # the host share of one GPU is 16 cores whatever the machine reports
+        cores = max(1, min(16, len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16"))))
         V = sc.vertices()
         t0 = time.perf_counter()
         for k, j in enumerate(idx):

@@ -23,6 +23,15 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+
+def default_threads():
+    """Worker threads for the oracle: the process's CPU affinity, capped at 16 (one GPU's host share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (plain C, -O2, no fast-math, no FMA contraction)."""
     if force or not os.path.exists(_LIB_PATH):
@@ -142,7 +151,7 @@ def trace(verts, tris, rho_s, rho_d, sun_dirs, *, nu: int, nv: int, bounces: int
         rf = np.zeros((D, n_pix, 3))
         rt = np.zeros((D, n_pix, 3))
     if threads is None:
-        threads = os.cpu_count() or 1
+        threads = default_threads()
     st = lib().oracle_trace(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd), _ptr(ps), _ptr(c),
                             _ptr(sun), D, _ptr(fr), nu, nv, bounces, int(bool(jitter)), float(flux), int(seed),
                             int(dir_index_base), int(design_index), _ptr(px), n_pix, _ptr(force), _ptr(torque),
@@ -174,7 +183,7 @@ def trace_adjoint_rho(verts, tris, rho_s, rho_d, sun_dirs, g_force, g_torque=Non
     g_rs = np.zeros(len(tris))
     g_rd = np.zeros(len(tris))
     if threads is None:
-        threads = os.cpu_count() or 1
+        threads = default_threads()
     st = lib().oracle_trace_adjoint_rho(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd), _ptr(ps),
                                         _ptr(c), _ptr(sun), D, _ptr(fr), nu, nv, bounces, int(bool(jitter)),
                                         float(flux), int(seed), int(dir_index_base), int(design_index), _ptr(px),
