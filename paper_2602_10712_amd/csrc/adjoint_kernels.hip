@@ -77,6 +77,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
 {
     const TraceArgs& a = A.t;
     __shared__ int s_stack[kWaves][kStackDepth];
+    __shared__ int s_lane[kWaves][kLaneStack][64];
     __shared__ float s_red[kWaves][MAXH > 0 ? MAXH : 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -87,6 +88,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
     const BvhNode* __restrict__ nodes = a.nodes;
     const TriRec* __restrict__ tris = a.tris;
     int* stack = s_stack[wave];
+    int* lstack = &s_lane[wave][0][lane];
     const float gF[3] = {static_cast<float>(A.g_force[3 * j]), static_cast<float>(A.g_force[3 * j + 1]),
                          static_cast<float>(A.g_force[3 * j + 2])};
     float gT[3] = {0.0f, 0.0f, 0.0f};
@@ -143,7 +145,10 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
             if (wave_ballot(alive) == 0) break;
             float t;
             int hit;
-            closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
+            if (b == 1 || !a.lane_walk)
+                closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
+            else
+                closest_hit_lane(nodes, tris, o, d, alive, skip, t, hit, lstack);
             if (!alive) continue;
             if (hit < 0) {
                 alive = false;

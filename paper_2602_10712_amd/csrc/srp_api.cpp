@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -160,6 +161,18 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
     return SRP_OK;
 }
 
+// Secondary segments take the per-lane walk when the tree fits its stack, unless the environment
+// sets SRP_SECONDARY_WALK=wave (every segment then takes the wave-coherent walk).  Both walks give
+// identical hits; the switch exists for performance comparisons.
+int32_t lane_walk_for(int32_t depth)
+{
+    static const bool wave_only = [] {
+        const char* e = std::getenv("SRP_SECONDARY_WALK");
+        return e != nullptr && std::strcmp(e, "wave") == 0;
+    }();
+    return !wave_only && depth <= srp::kLaneStack ? 1 : 0;
+}
+
 srp_status check_params(const srp_trace_params* p)
 {
     if (!p) return fail(SRP_EINVAL, "params is NULL");
@@ -206,6 +219,7 @@ srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
     a.eps = static_cast<float>(1e-5 * s->L);
     a.tiles_x = (p->nu + srp::kTileW - 1) / srp::kTileW;
     a.tiles_y = (p->nv + srp::kTileH - 1) / srp::kTileH;
+    a.lane_walk = lane_walk_for(s->depth);
     if (records) {
         a.pix = pix;
         a.n_pix = pix ? n_pix : static_cast<int64_t>(p->nu) * p->nv;
@@ -518,6 +532,9 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
     a.tiles_x = (p->nu + srp::kTileW - 1) / srp::kTileW;
     a.tiles_y = (p->nv + srp::kTileH - 1) / srp::kTileH;
     a.tiles_per_dir = static_cast<int64_t>(a.tiles_x) * a.tiles_y;
+    int32_t max_depth = 0;
+    for (int32_t s = 0; s < S; ++s) max_depth = std::max(max_depth, scenes[s]->depth);
+    a.lane_walk = lane_walk_for(max_depth);
     const int64_t total_tiles = a.tiles_per_dir * units;
     int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(16, total_tiles / (int64_t(srp::kWaves) * 8192)));
     a.tiles_per_wave = static_cast<int32_t>(tpw);

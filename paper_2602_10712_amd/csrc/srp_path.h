@@ -215,6 +215,27 @@ SRP_HD bool interact(float o[3], float d[3], float& w, float t, const float n[3]
                                      g, nullptr);
 }
 
+// Quotient and reciprocal: on the GPU the hardware reciprocal (1 ulp) replaces the IEEE division
+// sequence; these values only place hits along a ray and order them, where 1 ulp is far below
+// the geometric tolerances.  The host uses the correctly rounded operations.
+SRP_HD float fast_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+SRP_HD float fast_div(float a, float b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return a * __builtin_amdgcn_rcpf(b);
+#else
+    return a / b;
+#endif
+}
+
 // Moller-Trumbore (1997), one-sided (det > 0 <=> the ray meets the outward side), inclusive
 // barycentric bounds, returns t (or a negative value when there is no hit).
 SRP_HD float tri_hit(const float o[3], const float d[3], const float4& g0, const float4& g1, const float4& g2)
@@ -230,7 +251,7 @@ SRP_HD float tri_hit(const float o[3], const float d[3], const float4& g0, const
     const float qz = tx * g1.y - ty * g1.x;
     const float vv = d[0] * qx + d[1] * qy + d[2] * qz;
     const float tnum = g2.x * qx + g2.y * qy + g2.z * qz;
-    const float t = tnum / det;
+    const float t = fast_div(tnum, det);
     const bool ok = det > 0.0f && uu >= 0.0f && uu <= det && vv >= 0.0f && uu + vv <= det && t > 0.0f;
     return ok ? t : -1.0f;
 }
@@ -238,7 +259,7 @@ SRP_HD float tri_hit(const float o[3], const float d[3], const float4& g0, const
 SRP_HD float safe_rcp(float x)
 {
     const float m = 1e-20f;
-    return 1.0f / (fabsf(x) < m ? copysignf(m, x) : x);
+    return fast_rcp(fabsf(x) < m ? copysignf(m, x) : x);
 }
 
 }  // namespace srp

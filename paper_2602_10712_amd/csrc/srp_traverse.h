@@ -92,6 +92,91 @@ __device__ __forceinline__ void closest_hit(const BvhNode* __restrict__ nodes, c
     hit_out = hit;
 }
 
+// Closest hit with an independent walk per lane (same result as closest_hit): each lane follows
+// its own node sequence, nearer child first, with its own stack of deferred children in LDS
+// (lstack points at the lane's column; entry k sits at lstack[64 k], so the 64 lanes of a wave
+// touch 64 consecutive words).  Node and triangle records arrive through vector loads.  Used for
+// secondary segments, whose rays scatter over the scene: the lanes' node sets then barely
+// overlap, and a shared sequence would visit their union.  The tree depth must not exceed
+// kLaneStack (every push is matched by a descent, so the stack never holds more entries than
+// the depth of the current node).
+__device__ __forceinline__ void closest_hit_lane(const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris,
+                                                 const float o[3], const float d[3], bool alive, int skip,
+                                                 float& t_out, int& hit_out, int* __restrict__ lstack)
+{
+    const float ix = safe_rcp(d[0]), iy = safe_rcp(d[1]), iz = safe_rcp(d[2]);
+    const float nx = -o[0] * ix, ny = -o[1] * iy, nz = -o[2] * iz;
+    float tbest = alive ? FLT_MAX : -1.0f;
+    int hit = -1;
+    int hit_id = 0x7fffffff;
+    int sp = 0;
+    int cur = alive ? 0 : kWalkDone;
+    while (cur != kWalkDone) {
+        if (cur >= 0) {
+            const BvhNode* N = nodes + cur;
+            const float4 f0 = N->f[0];
+            const float4 f1 = N->f[1];
+            const float4 f2 = N->f[2];
+            const float4 f3 = N->f[3];
+            const int c0 = __float_as_int(f3.x);
+            const int c1 = __float_as_int(f3.y);
+            const float ax0 = fmaf(f0.x, ix, nx), ax1 = fmaf(f0.y, ix, nx);
+            const float ay0 = fmaf(f0.z, iy, ny), ay1 = fmaf(f0.w, iy, ny);
+            const float az0 = fmaf(f2.x, iz, nz), az1 = fmaf(f2.y, iz, nz);
+            const float bx0 = fmaf(f1.x, ix, nx), bx1 = fmaf(f1.y, ix, nx);
+            const float by0 = fmaf(f1.z, iy, ny), by1 = fmaf(f1.w, iy, ny);
+            const float bz0 = fmaf(f2.z, iz, nz), bz1 = fmaf(f2.w, iz, nz);
+            const float tn0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+            const float tf0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tbest));
+            const float tn1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+            const float tf1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tbest));
+            const bool h0 = tn0 <= tf0;
+            const bool h1 = tn1 <= tf1;
+            if (h0 && h1) {
+                const bool swap = tn1 < tn0;
+                lstack[sp * 64] = swap ? c0 : c1;
+                ++sp;
+                cur = swap ? c1 : c0;
+            } else if (h0) {
+                cur = c0;
+            } else if (h1) {
+                cur = c1;
+            } else if (sp > 0) {
+                --sp;
+                cur = lstack[sp * 64];
+            } else {
+                cur = kWalkDone;
+            }
+        } else {
+            const int code = ~cur;
+            const int first = code >> 3;
+            const int cnt = code & 7;
+            for (int q = 0; q < cnt; ++q) {
+                const int tri = first + q;
+                const TriRec* T = tris + tri;
+                const float4 g0 = T->f[0];
+                const float4 g1 = T->f[1];
+                const float4 g2 = T->f[2];
+                const float t = tri_hit(o, d, g0, g1, g2);
+                const int id = __float_as_int(g0.w);
+                if (t > 0.0f && tri != skip && (t < tbest || (t == tbest && id < hit_id))) {
+                    tbest = t;
+                    hit = tri;
+                    hit_id = id;
+                }
+            }
+            if (sp > 0) {
+                --sp;
+                cur = lstack[sp * 64];
+            } else {
+                cur = kWalkDone;
+            }
+        }
+    }
+    t_out = tbest;
+    hit_out = hit;
+}
+
 __device__ __forceinline__ float wave_sum(float v)
 {
 #pragma unroll

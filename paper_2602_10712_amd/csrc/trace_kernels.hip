@@ -77,6 +77,7 @@ template <bool RECORDS, bool BATCH>
 __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
 {
     __shared__ int s_stack[kWaves][kStackDepth];
+    __shared__ int s_lane[kWaves][kLaneStack][64];
     __shared__ float s_red[kWaves][6];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -122,6 +123,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
     const DevFrame fr = a.frames[unit];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
     int* stack = s_stack[wave];
+    int* lstack = &s_lane[wave][0][lane];
 
     float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int m = 0; m < a.tiles_per_wave; ++m) {
@@ -143,7 +145,11 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
             if (wave_ballot(alive) == 0) break;
             float t;
             int hit;
-            closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
+            // primary rays of a tile are coherent: one shared node sequence; secondary rays scatter
+            if (b == 1 || !a.lane_walk)
+                closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
+            else
+                closest_hit_lane(nodes, tris, o, d, alive, skip, t, hit, lstack);
             if (!alive) continue;
             if (hit < 0) {
                 alive = false;
