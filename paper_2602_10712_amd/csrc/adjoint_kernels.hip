@@ -31,7 +31,6 @@
 namespace srp {
 namespace {
 
-constexpr int kSlots = kMaxBounces - 1;  // non-final interactions per path
 
 SRP_HD void cross3f(const float a[3], const float b[3], float r[3])
 {
@@ -55,24 +54,33 @@ SRP_HD void duff_basis_tangent(const float n[3], const float nd[3], float b1d[3]
     b2d[2] = -nd[1];
 }
 
-// Adds val into base[key] for every lane with `active`, one FP64 atomic per distinct key in the
-// wavefront (lanes of a coherent tile mostly hit the same few facets).
+// Adds val into base[key] for every lane with `active`.  Lanes of a coherent tile mostly hit the
+// same few facets: up to kScatterGroups keys shared by several lanes are summed across the wave
+// first (one FP64 atomic per key); the remaining lanes, whose keys are scattered, add their own
+// values with one atomic each.
+constexpr int kScatterGroups = 4;
+
 __device__ __forceinline__ void wave_scatter_add(double* base, bool active, int key, float val)
 {
     const int lane = threadIdx.x & 63;
     uint64_t pending = wave_ballot(active);
-    while (pending) {
+    for (int it = 0; it < kScatterGroups && pending; ++it) {
         const int leader = __ffsll(static_cast<unsigned long long>(pending)) - 1;
         const int k = __shfl(key, leader, 64);
         const bool match = active && key == k;
+        const uint64_t group = wave_ballot(match);
+        if ((group & (group - 1)) == 0) break;  // the leader's key is its own: no sharing to exploit
         const float sum = wave_sum(match ? val : 0.0f);
         if (lane == leader) atomicAdd(base + k, static_cast<double>(sum));
         active = active && !match;
         pending = wave_ballot(active);
     }
+    if (active) atomicAdd(base + key, static_cast<double>(val));
 }
 
-template <int MAXH>
+// MAXH: hinge tangents carried (0, 2 or 4); NS: non-final interaction slots per path (bounces - 1
+// at most), so that paths of up to 3 bounces keep only two slots in registers.
+template <int MAXH, int NS>
 __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
 {
     const TraceArgs& a = A.t;
@@ -114,10 +122,10 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
         int skip = -1;
 
         // reflectance adjoint state
-        float R[kSlots], Acc[kSlots], inv[kSlots];
-        int fac[kSlots], arr[kSlots];
+        float R[NS], Acc[NS], inv[NS];
+        int fac[NS], arr[NS];
 #pragma unroll
-        for (int i = 0; i < kSlots; ++i) {
+        for (int i = 0; i < NS; ++i) {
             R[i] = 0.0f;
             Acc[i] = 0.0f;
             inv[i] = 0.0f;
@@ -174,13 +182,13 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
             // ---- reflectances: coefficient of the current weight W_K from the incident term
             const float cin = dot3f(G, d_in);
 #pragma unroll
-            for (int i = 0; i < kSlots; ++i)
+            for (int i = 0; i < NS; ++i)
                 if (i < K) Acc[i] += R[i] * cin;
             if (inf.last) {
                 const float tr_ = dot3f(G, inf.r), tn_ = dot3f(G, n);
                 const float term = -(mt.x * tr_ + (2.0f / 3.0f) * mt.y * tn_);
 #pragma unroll
-                for (int i = 0; i < kSlots; ++i)
+                for (int i = 0; i < NS; ++i)
                     if (i < K) Acc[i] += R[i] * term;
                 term_f = fid;
                 term_s = -inf.w_in * tr_;
@@ -188,7 +196,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
             } else {
                 // new slot K with factor k; R_i *= k for the older slots, R_K = W before it
 #pragma unroll
-                for (int i = 0; i < kSlots; ++i) {
+                for (int i = 0; i < NS; ++i) {
                     if (i < K) R[i] *= inf.k;
                     if (i == K) {
                         R[i] = inf.w_in;
@@ -199,7 +207,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
                 }
                 const float cout = -dot3f(G, d);  // coefficient of the new weight: -G . o_b (d is o_b now)
 #pragma unroll
-                for (int i = 0; i < kSlots; ++i)
+                for (int i = 0; i < NS; ++i)
                     if (i <= K) Acc[i] += R[i] * cout;
                 ++K;
             }
@@ -263,7 +271,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
 
         // ---- scatter the reflectance gradients (original facet order, FP64)
 #pragma unroll
-        for (int i = 0; i < kSlots; ++i) {
+        for (int i = 0; i < NS; ++i) {
             const bool act = valid && i < K;
             if (wave_ballot(act) == 0) break;
             wave_scatter_add(A.g_rho, act, arr[i] * A.n_tris + fac[i], Acc[i] * inv[i]);
@@ -328,16 +336,29 @@ __global__ void k_finish_adjoint(const double* __restrict__ g_rho, int32_t n_tri
 
 }  // namespace
 
+namespace {
+
+template <int MAXH>
+void launch_adjoint_h(const AdjointArgs& a, unsigned blocks, hipStream_t stream)
+{
+    if (a.t.bounces <= 3)
+        hipLaunchKernelGGL((k_adjoint<MAXH, 2>), dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_adjoint<MAXH, kMaxBounces - 1>), dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+}
+
+}  // namespace
+
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream)
 {
     const unsigned blocks = static_cast<unsigned>(a.t.D * a.t.blocks_per_dir);
     if (blocks == 0) return hipSuccess;
     if (a.n_hinges == 0)
-        hipLaunchKernelGGL(k_adjoint<0>, dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+        launch_adjoint_h<0>(a, blocks, stream);
     else if (a.n_hinges <= 2)
-        hipLaunchKernelGGL(k_adjoint<2>, dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+        launch_adjoint_h<2>(a, blocks, stream);
     else
-        hipLaunchKernelGGL(k_adjoint<kMaxHinges>, dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+        launch_adjoint_h<kMaxHinges>(a, blocks, stream);
     return hipGetLastError();
 }
 
