@@ -10,11 +10,22 @@
 // stored in that permuted order, already split into the 64-lane A-operand pieces (16 bytes per
 // lane per 32 x 16 block), so a wavefront reads its A operand from LDS with one ds_read_b128.
 //
-// Work split.  A workgroup of 4 wavefronts (one per SIMD) takes 256 queries, 64 per wavefront
-// (two 32-query column blocks share every A operand).  Each layer's weights (at most 128 KB) are
-// staged in LDS; activations (BF16) and accumulators (FP32) stay in registers.  Bias and SiLU are
-// applied in FP32 in the epilogue, and activations are rounded to BF16 (nearest even).
+// Work split.  A persistent workgroup of 4 wavefronts (one per SIMD, the whole 512-entry register
+// file each) takes tiles of 256 queries, 64 per wavefront (two 32-query column blocks share every A
+// operand).  A hidden layer is computed one 32-row block at a time over all 16 K blocks, so only
+// two accumulators are live and the bias + SiLU epilogue of one row block overlaps the MFMAs of
+// the next; input and output activations of the layer (BF16) stay in registers.
+//
+// Weight pipeline.  The input layer, the output layer and all biases stay in LDS for the whole
+// kernel.  A hidden layer (128 KiB) is streamed in two 64 KiB halves (row blocks 0-3 and 4-7)
+// through two LDS buffers: while the wavefronts multiply with one half, every thread loads its
+// 16 x 16 bytes of the next half into registers and writes them to the other buffer afterwards,
+// so one barrier per half separates the buffer swaps and the L2 latency hides behind the MFMAs.
+// Bias and SiLU are applied in FP32 in the epilogue, and activations are rounded to BF16 (nearest
+// even, packed conversion).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "mlp_internal.h"
@@ -23,13 +34,22 @@ namespace srp {
 namespace {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 constexpr int kW = 256;             // hidden width served by the fused kernel
 constexpr int kMB = kW / 32;        // 32-row blocks of a hidden layer
 constexpr int kKB = kW / 16;        // 16-wide K blocks of a hidden layer
 constexpr int kQ = 64;              // queries per wavefront
-constexpr int kLdsBytes = kMB * kKB * 64 * 16;  // one hidden layer: 128 KiB
+constexpr int kTileQ = 4 * kQ;      // queries per workgroup tile
+constexpr int kHalfMB = kMB / 2;    // row blocks per streamed half layer
+constexpr int kHalfU4 = kHalfMB * kKB * 64;     // one half layer: 64 KiB in 16-byte pieces
+constexpr int kInU4 = kMB * 64;                 // input layer (one K block): 8 KiB
+constexpr int kOutU4 = kKB * 64;                // output layer (one row block): 16 KiB
+constexpr int kStage = kHalfU4 / 256;           // 16-byte pieces of a half layer per thread
+constexpr int kLdsU4Max = 10240;                // 160 KiB
+constexpr int kMaxDepth = (kLdsU4Max - 2 * kHalfU4 - kInU4 - kOutU4) / 64 - 1;  // bias rows left
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -63,125 +83,211 @@ __global__ void k_pack_mfma(const float* __restrict__ W, int out, int in, int MB
     dst[i] = (m < out && k < in) ? f2bf(W[static_cast<int64_t>(m) * in + k]) : static_cast<uint16_t>(0);
 }
 
-__device__ __forceinline__ void stage(uint4* __restrict__ lds, const uint4* __restrict__ src, int n16)
+__device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+__device__ __forceinline__ bf16x8 pack8(const float* v)
 {
-    for (int i = threadIdx.x; i < n16; i += 256) lds[i] = src[i];
+    const bf16x2 p0 = __builtin_convertvector((f32x2){v[0], v[1]}, bf16x2);
+    const bf16x2 p1 = __builtin_convertvector((f32x2){v[2], v[3]}, bf16x2);
+    const bf16x2 p2 = __builtin_convertvector((f32x2){v[4], v[5]}, bf16x2);
+    const bf16x2 p3 = __builtin_convertvector((f32x2){v[6], v[7]}, bf16x2);
+    return __builtin_shufflevector(__builtin_shufflevector(p0, p1, 0, 1, 2, 3),
+                                   __builtin_shufflevector(p2, p3, 0, 1, 2, 3), 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-__device__ __forceinline__ float silu_fast(float z) { return z * __frcp_rn(1.0f + __expf(-z)); }
-
-// Bias + SiLU of the accumulators of row block mb into B-operand pieces 2*mb, 2*mb + 1.
+// Bias (LDS) + SiLU of the accumulators of row block mb into B-operand pieces 2*mb, 2*mb + 1.
 __device__ __forceinline__ void epilogue(const f32x16& acc, const float* __restrict__ bias, int mb, int h,
                                          bf16x8& lo, bf16x8& hi)
 {
-    uint16_t v[16];
+    float v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int feat = mb * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-        v[r] = f2bf(silu_fast(acc[r] + bias[feat]));
+    for (int g = 0; g < 4; ++g) {
+        const float4 b = *reinterpret_cast<const float4*>(&bias[mb * 32 + g * 8 + h * 4]);
+        v[4 * g + 0] = silu(acc[4 * g + 0] + b.x);
+        v[4 * g + 1] = silu(acc[4 * g + 1] + b.y);
+        v[4 * g + 2] = silu(acc[4 * g + 2] + b.z);
+        v[4 * g + 3] = silu(acc[4 * g + 3] + b.w);
     }
-    lo = *reinterpret_cast<const bf16x8*>(&v[0]);
-    hi = *reinterpret_cast<const bf16x8*>(&v[8]);
+    lo = pack8(&v[0]);
+    hi = pack8(&v[8]);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_infer(
-    const float* __restrict__ x, int32_t N, int32_t n_in, int32_t n_out, const uint16_t* __restrict__ wf,
-    const int64_t* __restrict__ wf_off, const float* __restrict__ params, const int64_t* __restrict__ b_off,
-    int32_t depth, float* __restrict__ y)
+__device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
 {
-    __shared__ uint4 lds[kLdsBytes / 16];
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+struct InferArgs {
+    const float* x;
+    float* y;
+    const uint16_t* wf;        // packed A-operand pieces of every layer
+    const int64_t* wf_off;     // [depth + 1] offsets into wf (elements)
+    const float* params;       // FP32 masters (biases read from here)
+    const int64_t* b_off;      // [depth + 1] bias offsets into params
+    int32_t N, n_in, n_out, depth;
+    int32_t n_tiles;
+};
+
+// Half `step & 1` of hidden layer 1 + (step / 2) % (depth - 1): the stream of half layers a
+// workgroup walks through, tile after tile.
+__device__ __forceinline__ const uint4* half_src(const InferArgs& a, int64_t step)
+{
+    const int nh = a.depth - 1;
+    const int l = 1 + static_cast<int>((step >> 1) % nh);
+    return reinterpret_cast<const uint4*>(a.wf + a.wf_off[l]) + (step & 1) * kHalfU4;
+}
+
+// Two row blocks of a hidden layer from LDS buffer W into `out`.
+template <int P, int M0>
+__device__ __forceinline__ void row_blocks(const uint4* __restrict__ W, const float* __restrict__ bias,
+                                           const bf16x8 (&in)[2][kKB], bf16x8 (&out)[2][kKB], int lane, int h)
+{
+#pragma unroll
+    for (int m = M0; m < M0 + 2; ++m) {
+        const int mb = P * kHalfMB + m;
+        f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+        for (int kb = 0; kb < kKB; ++kb) {
+            const bf16x8 A = *reinterpret_cast<const bf16x8*>(&W[(m * kKB + kb) * 64 + lane]);
+            acc0 = mfma(A, in[0][kb], acc0);
+            acc1 = mfma(A, in[1][kb], acc1);
+        }
+        epilogue(acc0, bias, mb, h, out[0][2 * mb], out[0][2 * mb + 1]);
+        epilogue(acc1, bias, mb, h, out[1][2 * mb], out[1][2 * mb + 1]);
+    }
+}
+
+// One half of a hidden layer: row blocks P*4 .. P*4+3 from LDS buffer W into `out`, while the next
+// half layer (`next`, 64 KiB) travels through registers into the other buffer Wn in two chunks.
+// Without a next half, `next` is the current half: the copy then lands in a buffer nobody reads.
+template <int P>
+__device__ __forceinline__ void hidden_half(const uint4* __restrict__ W, uint4* __restrict__ Wn,
+                                            const uint4* __restrict__ next, const float* __restrict__ bias,
+                                            const bf16x8 (&in)[2][kKB], bf16x8 (&out)[2][kKB], int lane, int h)
+{
+    constexpr int kChunk = kStage / 2;
+    uint4 st[kChunk];
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) st[i] = next[i * 256 + threadIdx.x];
+    row_blocks<P, 0>(W, bias, in, out, lane, h);
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) Wn[i * 256 + threadIdx.x] = st[i];
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) st[i] = next[(kChunk + i) * 256 + threadIdx.x];
+    row_blocks<P, 2>(W, bias, in, out, lane, h);
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) Wn[(kChunk + i) * 256 + threadIdx.x] = st[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void hidden_layer(const InferArgs& a, uint4* __restrict__ H0, uint4* __restrict__ H1,
+                                             const float* __restrict__ bias, int64_t& step, int64_t steps,
+                                             const bf16x8 (&in)[2][kKB], bf16x8 (&out)[2][kKB], int lane, int h)
+{
+    hidden_half<0>(H0, H1, half_src(a, step + 1 < steps ? step + 1 : step), bias, in, out, lane, h);
+    ++step;
+    hidden_half<1>(H1, H0, half_src(a, step + 1 < steps ? step + 1 : step), bias, in, out, lane, h);
+    ++step;
+}
+
+__device__ __forceinline__ void output_layer(const InferArgs& a, const uint4* __restrict__ Wout,
+                                             const float* __restrict__ bias, const bf16x8 (&in)[2][kKB],
+                                             int64_t q0, int lane, int h, int c)
+{
+    f32x16 out0 = {}, out1 = {};
+#pragma unroll
+    for (int kb = 0; kb < kKB; ++kb) {
+        const bf16x8 A = *reinterpret_cast<const bf16x8*>(&Wout[kb * 64 + lane]);
+        out0 = mfma(A, in[0][kb], out0);
+        out1 = mfma(A, in[1][kb], out1);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int64_t q = q0 + cb * 32 + c;
+        if (q >= a.N) continue;
+        const f32x16& o = cb == 0 ? out0 : out1;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int k = (r >> 2) * 8 + h * 4 + (r & 3);
+            if (k < a.n_out) a.y[q * a.n_out + k] = o[r] + bias[k];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_infer(InferArgs a)
+{
+    extern __shared__ uint4 smem[];
+    uint4* H0 = smem;
+    uint4* H1 = smem + kHalfU4;
+    uint4* Win = smem + 2 * kHalfU4;
+    uint4* Wout = Win + kInU4;
+    float* biases = reinterpret_cast<float*>(Wout + kOutU4);  // [depth + 1][256]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int h = lane >> 5, c = lane & 31;
-    const int64_t q0 = static_cast<int64_t>(blockIdx.x) * (4 * kQ) + wave * kQ;
+    const int nh = a.depth - 1;
+    const int64_t my_tiles = blockIdx.x < a.n_tiles ? (a.n_tiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+    const int64_t steps = 2 * nh * my_tiles;
 
-    // ---- layer 0: input (n_in <= 16, one K block, identity order) -------------------------------
-    bf16x8 xin[2];
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-        const int64_t q = q0 + cb * 32 + c;
-        uint16_t v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int f = 8 * h + j;
-            v[j] = (q < N && f < n_in) ? f2bf(x[q * n_in + f]) : static_cast<uint16_t>(0);
-        }
-        xin[cb] = *reinterpret_cast<const bf16x8*>(v);
-    }
-    stage(lds, reinterpret_cast<const uint4*>(wf + wf_off[0]), kMB * 1 * 64);
-    __syncthreads();
-    bf16x8 act[2][kKB];
+    // resident pieces: input and output layers, all biases, and the first streamed half layer
     {
-        const float* bias = params + b_off[0];
+        const uint4* src = reinterpret_cast<const uint4*>(a.wf + a.wf_off[0]);
+        for (int i = threadIdx.x; i < kInU4; i += 256) Win[i] = src[i];
+        src = reinterpret_cast<const uint4*>(a.wf + a.wf_off[a.depth]);
+        for (int i = threadIdx.x; i < kOutU4; i += 256) Wout[i] = src[i];
+        for (int i = threadIdx.x; i < (a.depth + 1) * kW; i += 256) {
+            const int l = i / kW, k = i % kW;
+            const int n = l == a.depth ? a.n_out : kW;
+            biases[i] = k < n ? a.params[a.b_off[l] + k] : 0.0f;
+        }
+        if (steps > 0) {
+            const uint4* first = half_src(a, 0);
+            for (int i = threadIdx.x; i < kHalfU4; i += 256) H0[i] = first[i];
+        }
+    }
+    __syncthreads();
+
+    int64_t step = 0;
+    for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const int64_t q0 = tile * kTileQ + wave * kQ;
+        bf16x8 xin[2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int64_t q = q0 + cb * 32 + c;
+            uint16_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int f = 8 * h + j;
+                v[j] = (q < a.N && f < a.n_in) ? f2bf(a.x[q * a.n_in + f]) : static_cast<uint16_t>(0);
+            }
+            xin[cb] = *reinterpret_cast<const bf16x8*>(v);
+        }
+        bf16x8 act[2][kKB], nxt[2][kKB];
 #pragma unroll
         for (int mb = 0; mb < kMB; ++mb) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&lds[mb * 64 + lane]);
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                f32x16 acc = {};
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xin[cb], acc, 0, 0, 0);
-                epilogue(acc, bias, mb, h, act[cb][2 * mb], act[cb][2 * mb + 1]);
-            }
+            const bf16x8 A = *reinterpret_cast<const bf16x8*>(&Win[mb * 64 + lane]);
+            const f32x16 z = {};
+            epilogue(mfma(A, xin[0], z), biases, mb, h, act[0][2 * mb], act[0][2 * mb + 1]);
+            epilogue(mfma(A, xin[1], z), biases, mb, h, act[1][2 * mb], act[1][2 * mb + 1]);
         }
-    }
-    __syncthreads();
-
-    // ---- hidden layers 1 .. depth-1 ----------------------------------------------------------------
-    for (int l = 1; l < depth; ++l) {
-        stage(lds, reinterpret_cast<const uint4*>(wf + wf_off[l]), kMB * kKB * 64);
-        __syncthreads();
-        f32x16 acc[2][kMB];
-#pragma unroll
-        for (int mb = 0; mb < kMB; ++mb)
+        for (int l = 1; l <= nh; ++l) {
+            hidden_layer(a, H0, H1, biases + l * kW, step, steps, act, nxt, lane, h);
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc[cb][mb][r] = 0.0f;
-#pragma unroll
-        for (int kb = 0; kb < kKB; ++kb) {
-#pragma unroll
-            for (int mb = 0; mb < kMB; ++mb) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&lds[(mb * kKB + kb) * 64 + lane]);
-                acc[0][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act[0][kb], acc[0][mb], 0, 0, 0);
-                acc[1][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act[1][kb], acc[1][mb], 0, 0, 0);
-            }
+                for (int kb = 0; kb < kKB; ++kb) act[cb][kb] = nxt[cb][kb];
         }
-        const float* bias = params + b_off[l];
-#pragma unroll
-        for (int mb = 0; mb < kMB; ++mb)
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) epilogue(acc[cb][mb], bias, mb, h, act[cb][2 * mb], act[cb][2 * mb + 1]);
-        __syncthreads();
-    }
-
-    // ---- output layer (n_out <= 32: one row block) -----------------------------------------------
-    stage(lds, reinterpret_cast<const uint4*>(wf + wf_off[depth]), kKB * 64);
-    __syncthreads();
-    f32x16 out[2] = {};
-#pragma unroll
-    for (int kb = 0; kb < kKB; ++kb) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&lds[kb * 64 + lane]);
-        out[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act[0][kb], out[0], 0, 0, 0);
-        out[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act[1][kb], out[1], 0, 0, 0);
-    }
-    const float* bias = params + b_off[depth];
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-        const int64_t q = q0 + cb * 32 + c;
-        if (q >= N) continue;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int o = (r >> 2) * 8 + h * 4 + (r & 3);
-            if (o < n_out) y[q * n_out + o] = out[cb][r] + bias[o];
-        }
+        output_layer(a, Wout, biases + a.depth * kW, act, q0, lane, h, c);
     }
 }
+
+size_t infer_lds_bytes(int depth) { return static_cast<size_t>(2 * kHalfU4 + kInU4 + kOutU4 + (depth + 1) * 64) * 16; }
 
 }  // namespace
 
 bool mlp_fused_supported(int n_in, int width, int depth, int n_out)
 {
-    return width == kW && n_in <= 16 && n_out <= 32 && depth >= 1;
+    return width == kW && n_in <= 16 && n_out <= 32 && depth >= 1 && depth <= kMaxDepth;
 }
 
 int64_t mlp_fused_layer_elems(int layer, int depth)
@@ -206,9 +312,29 @@ hipError_t launch_mlp_infer(const float* x, int32_t N, const uint16_t* wf, const
                             hipStream_t stream)
 {
     if (N <= 0) return hipSuccess;
-    const unsigned blocks = static_cast<unsigned>((static_cast<int64_t>(N) + 4 * kQ - 1) / (4 * kQ));
-    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), 0, stream, x, N, n_in, n_out, wf, wf_off_dev, params,
-                       b_off_dev, depth, y);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const size_t lds = infer_lds_bytes(depth);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_infer), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    InferArgs a{};
+    a.x = x;
+    a.y = y;
+    a.wf = wf;
+    a.wf_off = wf_off_dev;
+    a.params = params;
+    a.b_off = b_off_dev;
+    a.N = N;
+    a.n_in = n_in;
+    a.n_out = n_out;
+    a.depth = depth;
+    a.n_tiles = static_cast<int32_t>((static_cast<int64_t>(N) + kTileQ - 1) / kTileQ);
+    // persistent: one workgroup per compute unit (the LDS footprint allows no second one)
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(a.n_tiles, std::max(cus, 1)));
+    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), lds, stream, a);
     return hipGetLastError();
 }
 

@@ -55,6 +55,29 @@ def test_forward_backward_match_oracle(N, width, depth):
     assert rel_l2(g_x.cpu().numpy(), gx_ref) <= 2e-3
 
 
+@pytest.mark.parametrize("N,depth,n_in,n_out", [(1, 4, 11, 3), (257, 1, 11, 3), (1000, 2, 16, 32), (1000, 7, 11, 3),
+                                               (300000, 4, 11, 3)])
+def test_fused_inference_matches_oracle(N, depth, n_in, n_out):
+    """The fused width-256 inference kernel (persistent workgroups, streamed half layers) against the
+    emulating oracle; for N = 300000 every workgroup runs several tiles, checked on sampled rows
+    (queries are independent)."""
+    p = _lib()
+    s = p.Surrogate(n_in, 256, depth, n_out, seed=1)
+    flat = om.init_params(n_in, 256, depth, n_out, seed=11 + depth)
+    s.set_params(flat)
+    rng = np.random.default_rng(N + depth)
+    x = rng.uniform(-1, 1, (N, n_in)).astype(np.float32)
+    y = s.forward(x).cpu().numpy()
+    rows = np.arange(N) if N <= 4096 else np.sort(rng.choice(N, 3000, replace=False))
+    rows = np.union1d(rows, [N - 1])
+    layers = om.unpack(flat, n_in, 256, depth, n_out)
+    y_ref, _ = om.forward(layers, x[rows], emulate=True)
+    e = rel_l2(y[rows], y_ref)
+    print(f"fused N={N} depth={depth} n_in={n_in} n_out={n_out}: rel L2 {e:.2e}")
+    assert e <= 1e-3
+    assert np.isfinite(y).all()
+
+
 def test_adam_step_and_checkpoint_resume():
     p = _lib()
     n_in, width, depth, n_out = 11, 256, 4, 3
