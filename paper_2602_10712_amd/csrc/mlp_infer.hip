@@ -95,26 +95,39 @@ __device__ __forceinline__ bf16x8 pack8(const float* v)
                                    __builtin_shufflevector(p2, p3, 0, 1, 2, 3), 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// Bias (LDS) + SiLU of the accumulators of row block mb into B-operand pieces 2*mb, 2*mb + 1.
-__device__ __forceinline__ void epilogue(const f32x16& acc, const float* __restrict__ bias, int mb, int h,
-                                         bf16x8& lo, bf16x8& hi)
-{
-    float v[16];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const float4 b = *reinterpret_cast<const float4*>(&bias[mb * 32 + g * 8 + h * 4]);
-        v[4 * g + 0] = silu(acc[4 * g + 0] + b.x);
-        v[4 * g + 1] = silu(acc[4 * g + 1] + b.y);
-        v[4 * g + 2] = silu(acc[4 * g + 2] + b.z);
-        v[4 * g + 3] = silu(acc[4 * g + 3] + b.w);
-    }
-    lo = pack8(&v[0]);
-    hi = pack8(&v[8]);
-}
-
 __device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
 {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Bias of row block mb in accumulator order (LDS): the MFMA chain of the block starts from it.
+__device__ __forceinline__ f32x16 bias_acc(const float* __restrict__ bias, int mb, int h)
+{
+    f32x16 r;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float4 b = *reinterpret_cast<const float4*>(&bias[mb * 32 + g * 8 + h * 4]);
+        r[4 * g + 0] = b.x;
+        r[4 * g + 1] = b.y;
+        r[4 * g + 2] = b.z;
+        r[4 * g + 3] = b.w;
+    }
+    return r;
+}
+
+// SiLU of pre-activations (bias included) into B-operand pieces 2*mb, 2*mb + 1, one stage at a time
+// over the 16 values so that the transcendental latencies overlap.
+__device__ __forceinline__ void activate(const f32x16& z, bf16x8& lo, bf16x8& hi)
+{
+    float e[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) e[r] = __expf(-z[r]);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) e[r] = __builtin_amdgcn_rcpf(1.0f + e[r]);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) e[r] *= z[r];
+    lo = pack8(&e[0]);
+    hi = pack8(&e[8]);
 }
 
 struct InferArgs {
@@ -137,57 +150,83 @@ __device__ __forceinline__ const uint4* half_src(const InferArgs& a, int64_t ste
     return reinterpret_cast<const uint4*>(a.wf + a.wf_off[l]) + (step & 1) * kHalfU4;
 }
 
-// Two row blocks of a hidden layer from LDS buffer W into `out`.
-template <int P, int M0>
-__device__ __forceinline__ void row_blocks(const uint4* __restrict__ W, const float* __restrict__ bias,
-                                           const bf16x8 (&in)[2][kKB], bf16x8 (&out)[2][kKB], int lane, int h)
+// Row block MB of a hidden layer (both column blocks, all 16 K blocks; the chains start from the
+// bias), reading its A pieces from the LDS half-layer buffer W up front.  With EPI the SiLU of the
+// previous row block (pre-activations in a0, a1 on entry) is computed two values per MFMA pair, so
+// the vector ALU works while the matrix core runs; its BF16 pieces go to out[.][2 MB - 2 .. 2 MB - 1].
+template <int MB, bool EPI>
+__device__ __forceinline__ void row_block(const uint4* __restrict__ W, const float* __restrict__ bias,
+                                          const bf16x8 (&in)[2][kKB], bf16x8 (&out)[2][kKB], int lane, int h,
+                                          f32x16& a0, f32x16& a1)
 {
+    constexpr int m = MB % kHalfMB;
+    bf16x8 A[kKB];
 #pragma unroll
-    for (int m = M0; m < M0 + 2; ++m) {
-        const int mb = P * kHalfMB + m;
-        f32x16 acc0 = {}, acc1 = {};
+    for (int kb = 0; kb < kKB; ++kb) A[kb] = *reinterpret_cast<const bf16x8*>(&W[(m * kKB + kb) * 64 + lane]);
+    const f32x16 p0 = a0, p1 = a1;
+    a0 = bias_acc(bias, MB, h);
+    a1 = a0;
+    float s0[16], s1[16];
 #pragma unroll
-        for (int kb = 0; kb < kKB; ++kb) {
-            const bf16x8 A = *reinterpret_cast<const bf16x8*>(&W[(m * kKB + kb) * 64 + lane]);
-            acc0 = mfma(A, in[0][kb], acc0);
-            acc1 = mfma(A, in[1][kb], acc1);
+    for (int kb = 0; kb < kKB; ++kb) {
+        a0 = mfma(A[kb], in[0][kb], a0);
+        a1 = mfma(A[kb], in[1][kb], a1);
+        if (EPI) {
+            s0[kb] = silu(p0[kb]);
+            s1[kb] = silu(p1[kb]);
         }
-        epilogue(acc0, bias, mb, h, out[0][2 * mb], out[0][2 * mb + 1]);
-        epilogue(acc1, bias, mb, h, out[1][2 * mb], out[1][2 * mb + 1]);
+    }
+    if (EPI) {
+        out[0][2 * MB - 2] = pack8(&s0[0]);
+        out[0][2 * MB - 1] = pack8(&s0[8]);
+        out[1][2 * MB - 2] = pack8(&s1[0]);
+        out[1][2 * MB - 1] = pack8(&s1[8]);
     }
 }
 
-// One half of a hidden layer: row blocks P*4 .. P*4+3 from LDS buffer W into `out`, while the next
-// half layer (`next`, 64 KiB) travels through registers into the other buffer Wn in two chunks.
-// Without a next half, `next` is the current half: the copy then lands in a buffer nobody reads.
-template <int P>
-__device__ __forceinline__ void hidden_half(const uint4* __restrict__ W, uint4* __restrict__ Wn,
-                                            const uint4* __restrict__ next, const float* __restrict__ bias,
-                                            const bf16x8 (&in)[2][kKB], bf16x8 (&out)[2][kKB], int lane, int h)
+__device__ __forceinline__ void stage_load(const uint4* __restrict__ src, int chunk, uint4 (&st)[kStage / 2])
 {
-    constexpr int kChunk = kStage / 2;
-    uint4 st[kChunk];
 #pragma unroll
-    for (int i = 0; i < kChunk; ++i) st[i] = next[i * 256 + threadIdx.x];
-    row_blocks<P, 0>(W, bias, in, out, lane, h);
-#pragma unroll
-    for (int i = 0; i < kChunk; ++i) Wn[i * 256 + threadIdx.x] = st[i];
-#pragma unroll
-    for (int i = 0; i < kChunk; ++i) st[i] = next[(kChunk + i) * 256 + threadIdx.x];
-    row_blocks<P, 2>(W, bias, in, out, lane, h);
-#pragma unroll
-    for (int i = 0; i < kChunk; ++i) Wn[(kChunk + i) * 256 + threadIdx.x] = st[i];
-    __syncthreads();
+    for (int i = 0; i < kStage / 2; ++i) st[i] = src[(chunk * (kStage / 2) + i) * 256 + threadIdx.x];
 }
 
-__device__ __forceinline__ void hidden_layer(const InferArgs& a, uint4* __restrict__ H0, uint4* __restrict__ H1,
-                                             const float* __restrict__ bias, int64_t& step, int64_t steps,
-                                             const bf16x8 (&in)[2][kKB], bf16x8 (&out)[2][kKB], int lane, int h)
+__device__ __forceinline__ void stage_store(uint4* __restrict__ dst, int chunk, const uint4 (&st)[kStage / 2])
 {
-    hidden_half<0>(H0, H1, half_src(a, step + 1 < steps ? step + 1 : step), bias, in, out, lane, h);
-    ++step;
-    hidden_half<1>(H1, H0, half_src(a, step + 1 < steps ? step + 1 : step), bias, in, out, lane, h);
-    ++step;
+#pragma unroll
+    for (int i = 0; i < kStage / 2; ++i) dst[(chunk * (kStage / 2) + i) * 256 + threadIdx.x] = st[i];
+}
+
+// One hidden layer: row blocks 0-3 from buffer H0, 4-7 from H1.  While the first half is multiplied
+// the next streamed half (next0) travels through registers into H1, and during the second half
+// next1 into H0; one barrier after each half.  The SiLU of each row block runs with the MFMAs of
+// the next one; the last row block's runs after the second barrier.
+__device__ __forceinline__ void hidden_layer(uint4* __restrict__ H0, uint4* __restrict__ H1,
+                                             const uint4* __restrict__ next0, const uint4* __restrict__ next1,
+                                             const float* __restrict__ bias, const bf16x8 (&in)[2][kKB],
+                                             bf16x8 (&out)[2][kKB], int lane, int h)
+{
+    f32x16 a0, a1;
+    uint4 st[kStage / 2];
+    stage_load(next0, 0, st);
+    row_block<0, false>(H0, bias, in, out, lane, h, a0, a1);
+    row_block<1, true>(H0, bias, in, out, lane, h, a0, a1);
+    stage_store(H1, 0, st);
+    stage_load(next0, 1, st);
+    row_block<2, true>(H0, bias, in, out, lane, h, a0, a1);
+    row_block<3, true>(H0, bias, in, out, lane, h, a0, a1);
+    stage_store(H1, 1, st);
+    __syncthreads();
+    stage_load(next1, 0, st);
+    row_block<4, true>(H1, bias, in, out, lane, h, a0, a1);
+    row_block<5, true>(H1, bias, in, out, lane, h, a0, a1);
+    stage_store(H0, 0, st);
+    stage_load(next1, 1, st);
+    row_block<6, true>(H1, bias, in, out, lane, h, a0, a1);
+    row_block<7, true>(H1, bias, in, out, lane, h, a0, a1);
+    stage_store(H0, 1, st);
+    __syncthreads();
+    activate(a0, out[0][14], out[0][15]);
+    activate(a1, out[1][14], out[1][15]);
 }
 
 __device__ __forceinline__ void output_layer(const InferArgs& a, const uint4* __restrict__ Wout,
@@ -266,12 +305,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
         for (int mb = 0; mb < kMB; ++mb) {
             const bf16x8 A = *reinterpret_cast<const bf16x8*>(&Win[mb * 64 + lane]);
-            const f32x16 z = {};
-            epilogue(mfma(A, xin[0], z), biases, mb, h, act[0][2 * mb], act[0][2 * mb + 1]);
-            epilogue(mfma(A, xin[1], z), biases, mb, h, act[1][2 * mb], act[1][2 * mb + 1]);
+            const f32x16 b = bias_acc(biases, mb, h);
+            activate(mfma(A, xin[0], b), act[0][2 * mb], act[0][2 * mb + 1]);
+            activate(mfma(A, xin[1], b), act[1][2 * mb], act[1][2 * mb + 1]);
         }
         for (int l = 1; l <= nh; ++l) {
-            hidden_layer(a, H0, H1, biases + l * kW, step, steps, act, nxt, lane, h);
+            const uint4* next0 = half_src(a, step + 1 < steps ? step + 1 : step);
+            const uint4* next1 = half_src(a, step + 2 < steps ? step + 2 : step);
+            hidden_layer(H0, H1, next0, next1, biases + l * kW, act, nxt, lane, h);
+            step += 2;
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
