@@ -184,46 +184,43 @@ __device__ __forceinline__ void row_block(const uint4* __restrict__ W, const flo
     }
 }
 
-__device__ __forceinline__ void stage_load(const uint4* __restrict__ src, int chunk, uint4 (&st)[kStage / 2])
+__device__ __forceinline__ void stage_load(const uint4* __restrict__ src, uint4 (&st)[kStage])
 {
 #pragma unroll
-    for (int i = 0; i < kStage / 2; ++i) st[i] = src[(chunk * (kStage / 2) + i) * 256 + threadIdx.x];
+    for (int i = 0; i < kStage; ++i) st[i] = src[i * 256 + threadIdx.x];
 }
 
-__device__ __forceinline__ void stage_store(uint4* __restrict__ dst, int chunk, const uint4 (&st)[kStage / 2])
+__device__ __forceinline__ void stage_store(uint4* __restrict__ dst, const uint4 (&st)[kStage])
 {
 #pragma unroll
-    for (int i = 0; i < kStage / 2; ++i) dst[(chunk * (kStage / 2) + i) * 256 + threadIdx.x] = st[i];
+    for (int i = 0; i < kStage; ++i) dst[i * 256 + threadIdx.x] = st[i];
 }
 
 // One hidden layer: row blocks 0-3 from buffer H0, 4-7 from H1.  While the first half is multiplied
 // the next streamed half (next0) travels through registers into H1, and during the second half
-// next1 into H0; one barrier after each half.  The SiLU of each row block runs with the MFMAs of
-// the next one; the last row block's runs after the second barrier.
+// next1 into H0 (each thread's 16 pieces are loaded when the half starts and written when it
+// ends); one barrier after each half.  The SiLU of each row block runs with the MFMAs of the next
+// one; the last row block's runs after the second barrier.
 __device__ __forceinline__ void hidden_layer(uint4* __restrict__ H0, uint4* __restrict__ H1,
                                              const uint4* __restrict__ next0, const uint4* __restrict__ next1,
                                              const float* __restrict__ bias, const bf16x8 (&in)[2][kKB],
                                              bf16x8 (&out)[2][kKB], int lane, int h)
 {
     f32x16 a0, a1;
-    uint4 st[kStage / 2];
-    stage_load(next0, 0, st);
+    uint4 st[kStage];
+    stage_load(next0, st);
     row_block<0, false>(H0, bias, in, out, lane, h, a0, a1);
     row_block<1, true>(H0, bias, in, out, lane, h, a0, a1);
-    stage_store(H1, 0, st);
-    stage_load(next0, 1, st);
     row_block<2, true>(H0, bias, in, out, lane, h, a0, a1);
     row_block<3, true>(H0, bias, in, out, lane, h, a0, a1);
-    stage_store(H1, 1, st);
+    stage_store(H1, st);
     __syncthreads();
-    stage_load(next1, 0, st);
+    stage_load(next1, st);
     row_block<4, true>(H1, bias, in, out, lane, h, a0, a1);
     row_block<5, true>(H1, bias, in, out, lane, h, a0, a1);
-    stage_store(H0, 0, st);
-    stage_load(next1, 1, st);
     row_block<6, true>(H1, bias, in, out, lane, h, a0, a1);
     row_block<7, true>(H1, bias, in, out, lane, h, a0, a1);
-    stage_store(H0, 1, st);
+    stage_store(H0, st);
     __syncthreads();
     activate(a0, out[0][14], out[0][15]);
     activate(a1, out[1][14], out[1][15]);
@@ -286,21 +283,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     }
     __syncthreads();
 
-    int64_t step = 0;
-    for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    // network inputs of a tile: lane (h, c) reads features 8h .. 8h+7 of queries q0 + 32 cb + c; the
+    // next tile's are fetched while the current one computes
+    float xr[2][8];
+    auto fetch_x = [&](int64_t tile) {
         const int64_t q0 = tile * kTileQ + wave * kQ;
-        bf16x8 xin[2];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             const int64_t q = q0 + cb * 32 + c;
-            uint16_t v[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int f = 8 * h + j;
-                v[j] = (q < a.N && f < a.n_in) ? f2bf(a.x[q * a.n_in + f]) : static_cast<uint16_t>(0);
+                const bool ok = tile < a.n_tiles && q < a.N && f < a.n_in;
+                const float v = a.x[ok ? q * a.n_in + f : 0];
+                xr[cb][j] = ok ? v : 0.0f;
             }
-            xin[cb] = *reinterpret_cast<const bf16x8*>(v);
         }
+    };
+    fetch_x(blockIdx.x);
+
+    int64_t step = 0;
+    for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const int64_t q0 = tile * kTileQ + wave * kQ;
+        const bf16x8 xin[2] = {pack8(xr[0]), pack8(xr[1])};
+        fetch_x(tile + gridDim.x);
         bf16x8 act[2][kKB], nxt[2][kKB];
 #pragma unroll
         for (int mb = 0; mb < kMB; ++mb) {
