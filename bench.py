@@ -9,6 +9,7 @@ Prints ONE JSON line (see the design notes for the field definitions):
   value            forward Mrays/s (primary grid rays, whole paths, per second)
   fwd_adjoint      forward + adjoint replay Mrays/s at 512 x 512 rays per direction
   surrogate        fused MLP surrogate evals/s on 1M queries, with its MFMA roofline fraction
+  batched          one launch over 256 design variants (2k-50k tris) x 256 dirs x 512^2 rays
   roofline         dominant kernel (k_trace): algorithmic bytes per launch / mean launch time
   cpu_baseline     the FP64 oracle on a bounded sample of the same workload, host cores
 """
@@ -72,6 +73,10 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-designs", type=int, default=256)
+    ap.add_argument("--batch-dirs", type=int, default=256)
+    ap.add_argument("--batch-grid", type=int, default=512)
     ap.add_argument("--surrogate-batch", type=int, default=1 << 20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM traffic counters)")
@@ -216,6 +221,55 @@ def main():
         log(f"surrogate: {ms_s:.3f} ms per {nq} queries, {nq / ms_s / 1e6:.3f} G evals/s, {tf:.1f} TFLOP/s")
         net.close()
 
+    # ---- batched designs: 256 MEO-style variants, 256 directions each, one launch ---------------
+    batched = None
+    if not args.no_batch:
+        from concurrent.futures import ThreadPoolExecutor
+        S_n = args.batch_designs
+        rng = np.random.default_rng(6)
+        sizes = np.exp(rng.uniform(np.log(2000.0), np.log(50000.0), S_n)).astype(int)
+        dsg = si.random_designs(S_n, seed=6)
+
+        def make(k):
+            m = si.meo_variant(int(sizes[k]))
+            sck = p.Scene.from_mesh(m)
+            rsk, rdk = si.materials(m.n_tris, 100 + k)
+            sck.set_design(rsk, rdk, hinge_angles=dsg[k][:2])
+            return sck, m.n_tris
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(16) as ex:
+            built = list(ex.map(make, range(S_n)))
+        torch.cuda.synchronize()
+        build_b = time.perf_counter() - t0
+        scenes = [b[0] for b in built]
+        tris_b = np.array([b[1] for b in built])
+        sun_b = torch.as_tensor(si.fibonacci_dirs(args.batch_dirs), dtype=torch.float64, device=dev).contiguous()
+        pb = p.TraceParams(nu=args.batch_grid, nv=args.batch_grid, bounces=args.bounces, jitter=1, seed=2)
+        Fb = torch.empty((S_n, args.batch_dirs, 3), dtype=torch.float64, device=dev)
+        Tb = torch.empty_like(Fb)
+        for i in range(max(args.warmup, 1)):
+            p.srp_batch_trace(scenes, sun_b, pb, Fb, Tb, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        nb = max(1, min(args.steps, 3))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(nb):
+            p.srp_batch_trace(scenes, sun_b, pb, Fb, Tb, stream=stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / nb
+        rays_b = float(S_n) * args.batch_dirs * args.batch_grid ** 2
+        batched = {"value": round(rays_b / (ms_b * 1e-3) / 1e6, 1), "unit": "Mrays/s", "ms_per_launch": round(ms_b, 2),
+                   "launches": nb, "scene_build_s": round(build_b, 2),
+                   "workload": f"{S_n} MEO-style variants ({int(tris_b.min())}-{int(tris_b.max())} tris, "
+                               f"{int(tris_b.sum())} total), {args.batch_dirs} Fibonacci dirs x "
+                               f"{args.batch_grid}x{args.batch_grid} rays, {args.bounces} bounces, one launch"}
+        log(f"batched: {ms_b:.1f} ms per launch, {batched['value']:.0f} Mrays/s (scene build {build_b:.1f} s)")
+        for sck in scenes:
+            sck.close()
+
     # ---- roofline of the dominant kernel --------------------------------------------------------
     roofline = None
     try:
@@ -261,7 +315,7 @@ def main():
                    "tris": mesh.n_tris, "dirs": D, "grid": args.grid, "bounces": args.bounces,
                    "bvh_nodes": info["n_nodes"], "bvh_build_s": round(build_s, 4)},
         "roofline": roofline, "cpu_baseline": cpu, "fwd_adjoint": fwd_adj,
-        "surrogate": surrogate,
+        "surrogate": surrogate, "batched": batched,
     }
     print(json.dumps(out), flush=True)
 
