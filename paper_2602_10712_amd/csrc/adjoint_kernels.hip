@@ -153,7 +153,9 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
             if (wave_ballot(alive) == 0) break;
             float t;
             int hit;
-            if (b == 1 || !a.lane_walk)
+            if (b == 1)
+                closest_hit_parallel(nodes, tris, o, d, alive, skip, t, hit, stack, fr.d);
+            else if (!a.lane_walk)
                 closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
             else
                 closest_hit_lane(nodes, tris, o, d, alive, skip, t, hit, lstack);

@@ -12,27 +12,21 @@ namespace srp {
 
 #define SRP_HD __host__ __device__ __forceinline__
 
-SRP_HD uint32_t mulhi32(uint32_t a, uint32_t b)
-{
-    return static_cast<uint32_t>((static_cast<uint64_t>(a) * b) >> 32);
-}
-
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x32 S-box with the
 // published multipliers 0xD2511F53, 0xCD9E8D57 and key increments 0x9E3779B9, 0xBB67AE85.
 SRP_HD void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_a = mulhi32(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
-        const uint32_t hi_b = mulhi32(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi_b ^ c1 ^ k0;
-        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        // one 32 x 32 -> 64-bit product gives both halves of each S-box multiplication
+        const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo_b;
+        c1 = static_cast<uint32_t>(pb);
         c2 = n2;
-        c3 = lo_a;
+        c3 = static_cast<uint32_t>(pa);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

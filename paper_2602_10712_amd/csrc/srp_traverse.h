@@ -16,10 +16,19 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgc
 // whole wave (so node and triangle records arrive through scalar loads), a child is entered when
 // any lane's ray overlaps its box, the nearer child first by majority over the lanes that overlap
 // both, and the stack of deferred children is wave-uniform in LDS.
+//
+// SGN >= 0: every lane's direction has the sign pattern SGN (bit a set <=> axis a negative), as for
+// the parallel primary rays of one grid.  The near and far slab of each axis are then fixed at
+// compile time, so a box test needs no per-lane min/max of the slab distances.  Rounding is
+// monotonic, so the chosen slab equals the min/max of the general test and the hits are identical.
+template <int SGN = -1>
 __device__ __forceinline__ void closest_hit(const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris,
                                             const float o[3], const float d[3], bool alive, int skip, float& t_out,
                                             int& hit_out, int* __restrict__ stack)
 {
+    constexpr bool PARALLEL = SGN >= 0;
+    // safe_rcp keeps the sign (also of -0): a non-negative reciprocal makes the lower slab nearer
+    constexpr bool px = (SGN & 1) == 0, py = (SGN & 2) == 0, pz = (SGN & 4) == 0;
     const float ix = safe_rcp(d[0]), iy = safe_rcp(d[1]), iz = safe_rcp(d[2]);
     const float nx = -o[0] * ix, ny = -o[1] * iy, nz = -o[2] * iz;
     float tbest = alive ? FLT_MAX : -1.0f;
@@ -36,16 +45,31 @@ __device__ __forceinline__ void closest_hit(const BvhNode* __restrict__ nodes, c
             const float4 f3 = N->f[3];
             const int c0 = __float_as_int(f3.x);
             const int c1 = __float_as_int(f3.y);
-            const float ax0 = fmaf(f0.x, ix, nx), ax1 = fmaf(f0.y, ix, nx);
-            const float ay0 = fmaf(f0.z, iy, ny), ay1 = fmaf(f0.w, iy, ny);
-            const float az0 = fmaf(f2.x, iz, nz), az1 = fmaf(f2.y, iz, nz);
-            const float bx0 = fmaf(f1.x, ix, nx), bx1 = fmaf(f1.y, ix, nx);
-            const float by0 = fmaf(f1.z, iy, ny), by1 = fmaf(f1.w, iy, ny);
-            const float bz0 = fmaf(f2.z, iz, nz), bz1 = fmaf(f2.w, iz, nz);
-            const float tn0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
-            const float tf0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tbest));
-            const float tn1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
-            const float tf1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tbest));
+            float tn0, tf0, tn1, tf1;
+            if (PARALLEL) {
+                // near / far planes chosen per wave (scalar selects of the node's fields)
+                const float ax0 = fmaf(px ? f0.x : f0.y, ix, nx), ax1 = fmaf(px ? f0.y : f0.x, ix, nx);
+                const float ay0 = fmaf(py ? f0.z : f0.w, iy, ny), ay1 = fmaf(py ? f0.w : f0.z, iy, ny);
+                const float az0 = fmaf(pz ? f2.x : f2.y, iz, nz), az1 = fmaf(pz ? f2.y : f2.x, iz, nz);
+                const float bx0 = fmaf(px ? f1.x : f1.y, ix, nx), bx1 = fmaf(px ? f1.y : f1.x, ix, nx);
+                const float by0 = fmaf(py ? f1.z : f1.w, iy, ny), by1 = fmaf(py ? f1.w : f1.z, iy, ny);
+                const float bz0 = fmaf(pz ? f2.z : f2.w, iz, nz), bz1 = fmaf(pz ? f2.w : f2.z, iz, nz);
+                tn0 = fmaxf(fmaxf(ax0, ay0), fmaxf(az0, 0.0f));
+                tf0 = fminf(fminf(ax1, ay1), fminf(az1, tbest));
+                tn1 = fmaxf(fmaxf(bx0, by0), fmaxf(bz0, 0.0f));
+                tf1 = fminf(fminf(bx1, by1), fminf(bz1, tbest));
+            } else {
+                const float ax0 = fmaf(f0.x, ix, nx), ax1 = fmaf(f0.y, ix, nx);
+                const float ay0 = fmaf(f0.z, iy, ny), ay1 = fmaf(f0.w, iy, ny);
+                const float az0 = fmaf(f2.x, iz, nz), az1 = fmaf(f2.y, iz, nz);
+                const float bx0 = fmaf(f1.x, ix, nx), bx1 = fmaf(f1.y, ix, nx);
+                const float by0 = fmaf(f1.z, iy, ny), by1 = fmaf(f1.w, iy, ny);
+                const float bz0 = fmaf(f2.z, iz, nz), bz1 = fmaf(f2.w, iz, nz);
+                tn0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+                tf0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tbest));
+                tn1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+                tf1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tbest));
+            }
             const bool h0 = tn0 <= tf0;
             const bool h1 = tn1 <= tf1;
             const uint64_t m0 = wave_ballot(h0);
@@ -90,6 +114,28 @@ __device__ __forceinline__ void closest_hit(const BvhNode* __restrict__ nodes, c
     }
     t_out = tbest;
     hit_out = hit;
+}
+
+// closest_hit for rays that all travel along the wave-uniform direction `dir` (the primary rays of
+// one grid frame): dispatches on the sign pattern of dir.
+__device__ __forceinline__ void closest_hit_parallel(const BvhNode* __restrict__ nodes,
+                                                     const TriRec* __restrict__ tris, const float o[3],
+                                                     const float d[3], bool alive, int skip, float& t_out,
+                                                     int& hit_out, int* __restrict__ stack, const float dir[3])
+{
+    const uint32_t sgn = __builtin_amdgcn_readfirstlane((__float_as_uint(dir[0]) >> 31) |
+                                                        ((__float_as_uint(dir[1]) >> 31) << 1) |
+                                                        ((__float_as_uint(dir[2]) >> 31) << 2));
+    switch (sgn) {
+    case 0: closest_hit<0>(nodes, tris, o, d, alive, skip, t_out, hit_out, stack); break;
+    case 1: closest_hit<1>(nodes, tris, o, d, alive, skip, t_out, hit_out, stack); break;
+    case 2: closest_hit<2>(nodes, tris, o, d, alive, skip, t_out, hit_out, stack); break;
+    case 3: closest_hit<3>(nodes, tris, o, d, alive, skip, t_out, hit_out, stack); break;
+    case 4: closest_hit<4>(nodes, tris, o, d, alive, skip, t_out, hit_out, stack); break;
+    case 5: closest_hit<5>(nodes, tris, o, d, alive, skip, t_out, hit_out, stack); break;
+    case 6: closest_hit<6>(nodes, tris, o, d, alive, skip, t_out, hit_out, stack); break;
+    default: closest_hit<7>(nodes, tris, o, d, alive, skip, t_out, hit_out, stack); break;
+    }
 }
 
 // Closest hit with an independent walk per lane (same result as closest_hit): each lane follows

@@ -74,7 +74,7 @@ __global__ void k_pack_mat(const float* __restrict__ rs, const float* __restrict
 // BATCH: the launch covers n_scenes designs; hardware block b runs on XCD b % 8, so design s is
 // handled entirely by XCD s % 8 (its BVH stays in that XCD's L2) in design-major order.
 template <bool RECORDS, bool BATCH>
-__global__ __launch_bounds__(256) void k_trace(TraceArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_trace(TraceArgs a)
 {
     __shared__ int s_stack[kWaves][kStackDepth];
     __shared__ int s_lane[kWaves][kLaneStack][64];
@@ -146,7 +146,9 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a)
             float t;
             int hit;
             // primary rays of a tile are coherent: one shared node sequence; secondary rays scatter
-            if (b == 1 || !a.lane_walk)
+            if (b == 1)
+                closest_hit_parallel(nodes, tris, o, d, alive, skip, t, hit, stack, fr.d);
+            else if (!a.lane_walk)
                 closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
             else
                 closest_hit_lane(nodes, tris, o, d, alive, skip, t, hit, lstack);
