@@ -10,16 +10,19 @@
 // stored in that permuted order, already split into the 64-lane A-operand pieces (16 bytes per
 // lane per 32 x 16 block), so a wavefront reads its A operand from LDS with one ds_read_b128.
 //
-// Work split.  A persistent workgroup of 4 wavefronts (one per SIMD, the whole 512-entry register
-// file each) takes tiles of 256 queries, 64 per wavefront (two 32-query column blocks share every A
-// operand).  A hidden layer is computed one 32-row block at a time over all 16 K blocks, so only
-// two accumulators are live and the bias + SiLU epilogue of one row block overlaps the MFMAs of
-// the next; input and output activations of the layer (BF16) stay in registers.
+// Work split.  A persistent workgroup of 8 wavefronts (two per SIMD, up to 256 registers each)
+// takes tiles of 256 queries, one 32-query column block per wavefront.  A hidden layer is computed
+// one 32-row block at a time over all 16 K blocks, so one accumulator is live (plus the previous
+// block's pre-activations) and the bias + SiLU epilogue of one row block runs between the MFMAs
+// of the next, while the other wavefront of the SIMD keeps the matrix core busy; input and output
+// activations of the layer (BF16) stay in registers.  (The kernel is written for NCB column blocks
+// per wavefront; NCB = 2 with one wavefront per SIMD shares each A operand between two MFMAs but
+// measured slower.)
 //
 // Weight pipeline.  The input layer, the output layer and all biases stay in LDS for the whole
 // kernel.  A hidden layer (128 KiB) is streamed in two 64 KiB halves (row blocks 0-3 and 4-7)
 // through two LDS buffers: while the wavefronts multiply with one half, every thread loads its
-// 16 x 16 bytes of the next half into registers and writes them to the other buffer afterwards,
+// 8 x 16 bytes of the next half into registers and writes them to the other buffer afterwards,
 // so one barrier per half separates the buffer swaps and the L2 latency hides behind the MFMAs.
 // Bias and SiLU are applied in FP32 in the epilogue, and activations are rounded to BF16 (nearest
 // even, packed conversion).
@@ -41,13 +44,11 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 constexpr int kW = 256;             // hidden width served by the fused kernel
 constexpr int kMB = kW / 32;        // 32-row blocks of a hidden layer
 constexpr int kKB = kW / 16;        // 16-wide K blocks of a hidden layer
-constexpr int kQ = 64;              // queries per wavefront
-constexpr int kTileQ = 4 * kQ;      // queries per workgroup tile
+constexpr int kTileQ = 256;         // queries per workgroup tile
 constexpr int kHalfMB = kMB / 2;    // row blocks per streamed half layer
 constexpr int kHalfU4 = kHalfMB * kKB * 64;     // one half layer: 64 KiB in 16-byte pieces
 constexpr int kInU4 = kMB * 64;                 // input layer (one K block): 8 KiB
 constexpr int kOutU4 = kKB * 64;                // output layer (one row block): 16 KiB
-constexpr int kStage = kHalfU4 / 256;           // 16-byte pieces of a half layer per thread
 constexpr int kLdsU4Max = 10240;                // 160 KiB
 constexpr int kMaxDepth = (kLdsU4Max - 2 * kHalfU4 - kInU4 - kOutU4) / 64 - 1;  // bias rows left
 
@@ -154,104 +155,116 @@ __device__ __forceinline__ const uint4* half_src(const InferArgs& a, int64_t ste
 // bias), reading its A pieces from the LDS half-layer buffer W up front.  With EPI the SiLU of the
 // previous row block (pre-activations in a0, a1 on entry) is computed two values per MFMA pair, so
 // the vector ALU works while the matrix core runs; its BF16 pieces go to out[.][2 MB - 2 .. 2 MB - 1].
-template <int MB, bool EPI>
+template <int NCB, int MB, bool EPI>
 __device__ __forceinline__ void row_block(const uint4* __restrict__ W, const float* __restrict__ bias,
-                                          const bf16x8 (&in)[2][kKB], bf16x8 (&out)[2][kKB], int lane, int h,
-                                          f32x16& a0, f32x16& a1)
+                                          const bf16x8 (&in)[NCB][kKB], bf16x8 (&out)[NCB][kKB], int lane, int h,
+                                          f32x16 (&a)[NCB])
 {
     constexpr int m = MB % kHalfMB;
-    bf16x8 A[kKB];
+    constexpr int G = NCB == 1 ? kKB / 2 : kKB;  // A pieces read from LDS per group
+    f32x16 p[NCB];
 #pragma unroll
-    for (int kb = 0; kb < kKB; ++kb) A[kb] = *reinterpret_cast<const bf16x8*>(&W[(m * kKB + kb) * 64 + lane]);
-    const f32x16 p0 = a0, p1 = a1;
-    a0 = bias_acc(bias, MB, h);
-    a1 = a0;
-    float s0[16], s1[16];
+    for (int cb = 0; cb < NCB; ++cb) p[cb] = a[cb];
+    const f32x16 b = bias_acc(bias, MB, h);
 #pragma unroll
-    for (int kb = 0; kb < kKB; ++kb) {
-        a0 = mfma(A[kb], in[0][kb], a0);
-        a1 = mfma(A[kb], in[1][kb], a1);
-        if (EPI) {
-            s0[kb] = silu(p0[kb]);
-            s1[kb] = silu(p1[kb]);
+    for (int cb = 0; cb < NCB; ++cb) a[cb] = b;
+    float s[NCB][16];
+#pragma unroll
+    for (int g0 = 0; g0 < kKB; g0 += G) {
+        bf16x8 A[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) A[i] = *reinterpret_cast<const bf16x8*>(&W[(m * kKB + g0 + i) * 64 + lane]);
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int kb = g0 + i;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) a[cb] = mfma(A[i], in[cb][kb], a[cb]);
+            if (EPI) {
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) s[cb][kb] = silu(p[cb][kb]);
+            }
         }
     }
     if (EPI) {
-        out[0][2 * MB - 2] = pack8(&s0[0]);
-        out[0][2 * MB - 1] = pack8(&s0[8]);
-        out[1][2 * MB - 2] = pack8(&s1[0]);
-        out[1][2 * MB - 1] = pack8(&s1[8]);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            out[cb][2 * MB - 2] = pack8(&s[cb][0]);
+            out[cb][2 * MB - 1] = pack8(&s[cb][8]);
+        }
     }
-}
-
-__device__ __forceinline__ void stage_load(const uint4* __restrict__ src, uint4 (&st)[kStage])
-{
-#pragma unroll
-    for (int i = 0; i < kStage; ++i) st[i] = src[i * 256 + threadIdx.x];
-}
-
-__device__ __forceinline__ void stage_store(uint4* __restrict__ dst, const uint4 (&st)[kStage])
-{
-#pragma unroll
-    for (int i = 0; i < kStage; ++i) dst[i * 256 + threadIdx.x] = st[i];
 }
 
 // One hidden layer: row blocks 0-3 from buffer H0, 4-7 from H1.  While the first half is multiplied
 // the next streamed half (next0) travels through registers into H1, and during the second half
-// next1 into H0 (each thread's 16 pieces are loaded when the half starts and written when it
-// ends); one barrier after each half.  The SiLU of each row block runs with the MFMAs of the next
-// one; the last row block's runs after the second barrier.
+// next1 into H0 (each thread's pieces are loaded when the half starts and written when it ends);
+// one barrier after each half.  The SiLU of each row block runs with the MFMAs of the next one; the
+// last row block's runs after the second barrier.
+template <int NCB>
 __device__ __forceinline__ void hidden_layer(uint4* __restrict__ H0, uint4* __restrict__ H1,
                                              const uint4* __restrict__ next0, const uint4* __restrict__ next1,
-                                             const float* __restrict__ bias, const bf16x8 (&in)[2][kKB],
-                                             bf16x8 (&out)[2][kKB], int lane, int h)
+                                             const float* __restrict__ bias, const bf16x8 (&in)[NCB][kKB],
+                                             bf16x8 (&out)[NCB][kKB], int lane, int h)
 {
-    f32x16 a0, a1;
-    uint4 st[kStage];
-    stage_load(next0, st);
-    row_block<0, false>(H0, bias, in, out, lane, h, a0, a1);
-    row_block<1, true>(H0, bias, in, out, lane, h, a0, a1);
-    row_block<2, true>(H0, bias, in, out, lane, h, a0, a1);
-    row_block<3, true>(H0, bias, in, out, lane, h, a0, a1);
-    stage_store(H1, st);
+    constexpr int kThreads = 256 * 2 / NCB;
+    constexpr int kSt = kHalfU4 / kThreads;
+    f32x16 a[NCB];
+    uint4 st[kSt];
+#pragma unroll
+    for (int i = 0; i < kSt; ++i) st[i] = next0[i * kThreads + threadIdx.x];
+    row_block<NCB, 0, false>(H0, bias, in, out, lane, h, a);
+    row_block<NCB, 1, true>(H0, bias, in, out, lane, h, a);
+    row_block<NCB, 2, true>(H0, bias, in, out, lane, h, a);
+    row_block<NCB, 3, true>(H0, bias, in, out, lane, h, a);
+#pragma unroll
+    for (int i = 0; i < kSt; ++i) H1[i * kThreads + threadIdx.x] = st[i];
     __syncthreads();
-    stage_load(next1, st);
-    row_block<4, true>(H1, bias, in, out, lane, h, a0, a1);
-    row_block<5, true>(H1, bias, in, out, lane, h, a0, a1);
-    row_block<6, true>(H1, bias, in, out, lane, h, a0, a1);
-    row_block<7, true>(H1, bias, in, out, lane, h, a0, a1);
-    stage_store(H0, st);
+#pragma unroll
+    for (int i = 0; i < kSt; ++i) st[i] = next1[i * kThreads + threadIdx.x];
+    row_block<NCB, 4, true>(H1, bias, in, out, lane, h, a);
+    row_block<NCB, 5, true>(H1, bias, in, out, lane, h, a);
+    row_block<NCB, 6, true>(H1, bias, in, out, lane, h, a);
+    row_block<NCB, 7, true>(H1, bias, in, out, lane, h, a);
+#pragma unroll
+    for (int i = 0; i < kSt; ++i) H0[i * kThreads + threadIdx.x] = st[i];
     __syncthreads();
-    activate(a0, out[0][14], out[0][15]);
-    activate(a1, out[1][14], out[1][15]);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) activate(a[cb], out[cb][14], out[cb][15]);
 }
 
+template <int NCB>
 __device__ __forceinline__ void output_layer(const InferArgs& a, const uint4* __restrict__ Wout,
-                                             const float* __restrict__ bias, const bf16x8 (&in)[2][kKB],
+                                             const float* __restrict__ bias, const bf16x8 (&in)[NCB][kKB],
                                              int64_t q0, int lane, int h, int c)
 {
-    f32x16 out0 = {}, out1 = {};
+    f32x16 o[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) o[cb] = f32x16{};
 #pragma unroll
     for (int kb = 0; kb < kKB; ++kb) {
         const bf16x8 A = *reinterpret_cast<const bf16x8*>(&Wout[kb * 64 + lane]);
-        out0 = mfma(A, in[0][kb], out0);
-        out1 = mfma(A, in[1][kb], out1);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) o[cb] = mfma(A, in[cb][kb], o[cb]);
     }
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < NCB; ++cb) {
         const int64_t q = q0 + cb * 32 + c;
         if (q >= a.N) continue;
-        const f32x16& o = cb == 0 ? out0 : out1;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int k = (r >> 2) * 8 + h * 4 + (r & 3);
-            if (k < a.n_out) a.y[q * a.n_out + k] = o[r] + bias[k];
+            if (k < a.n_out) a.y[q * a.n_out + k] = o[cb][r] + bias[k];
         }
     }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_infer(InferArgs a)
+// NCB column blocks of 32 queries per wavefront; 8 / NCB wavefronts per workgroup (two per SIMD
+// when NCB = 1, so that one wavefront's SiLU runs while the other's MFMAs do), 256 queries per tile.
+template <int NCB>
+__global__ __launch_bounds__(512 / NCB) __attribute__((amdgpu_waves_per_eu(2 / NCB, 2 / NCB))) void k_mlp_infer(
+    InferArgs a)
 {
+    constexpr int kThreads = 512 / NCB;
+    constexpr int kQw = 32 * NCB;  // queries per wavefront
     extern __shared__ uint4 smem[];
     uint4* H0 = smem;
     uint4* H1 = smem + kHalfU4;
@@ -268,28 +281,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // resident pieces: input and output layers, all biases, and the first streamed half layer
     {
         const uint4* src = reinterpret_cast<const uint4*>(a.wf + a.wf_off[0]);
-        for (int i = threadIdx.x; i < kInU4; i += 256) Win[i] = src[i];
+        for (int i = threadIdx.x; i < kInU4; i += kThreads) Win[i] = src[i];
         src = reinterpret_cast<const uint4*>(a.wf + a.wf_off[a.depth]);
-        for (int i = threadIdx.x; i < kOutU4; i += 256) Wout[i] = src[i];
-        for (int i = threadIdx.x; i < (a.depth + 1) * kW; i += 256) {
+        for (int i = threadIdx.x; i < kOutU4; i += kThreads) Wout[i] = src[i];
+        for (int i = threadIdx.x; i < (a.depth + 1) * kW; i += kThreads) {
             const int l = i / kW, k = i % kW;
             const int n = l == a.depth ? a.n_out : kW;
             biases[i] = k < n ? a.params[a.b_off[l] + k] : 0.0f;
         }
         if (steps > 0) {
             const uint4* first = half_src(a, 0);
-            for (int i = threadIdx.x; i < kHalfU4; i += 256) H0[i] = first[i];
+            for (int i = threadIdx.x; i < kHalfU4; i += kThreads) H0[i] = first[i];
         }
     }
     __syncthreads();
 
     // network inputs of a tile: lane (h, c) reads features 8h .. 8h+7 of queries q0 + 32 cb + c; the
     // next tile's are fetched while the current one computes
-    float xr[2][8];
+    float xr[NCB][8];
     auto fetch_x = [&](int64_t tile) {
-        const int64_t q0 = tile * kTileQ + wave * kQ;
+        const int64_t q0 = tile * kTileQ + wave * kQw;
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < NCB; ++cb) {
             const int64_t q = q0 + cb * 32 + c;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -304,28 +317,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
     int64_t step = 0;
     for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
-        const int64_t q0 = tile * kTileQ + wave * kQ;
-        const bf16x8 xin[2] = {pack8(xr[0]), pack8(xr[1])};
+        const int64_t q0 = tile * kTileQ + wave * kQw;
+        bf16x8 xin[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) xin[cb] = pack8(xr[cb]);
         fetch_x(tile + gridDim.x);
-        bf16x8 act[2][kKB], nxt[2][kKB];
+        bf16x8 act[NCB][kKB], nxt[NCB][kKB];
 #pragma unroll
         for (int mb = 0; mb < kMB; ++mb) {
             const bf16x8 A = *reinterpret_cast<const bf16x8*>(&Win[mb * 64 + lane]);
             const f32x16 b = bias_acc(biases, mb, h);
-            activate(mfma(A, xin[0], b), act[0][2 * mb], act[0][2 * mb + 1]);
-            activate(mfma(A, xin[1], b), act[1][2 * mb], act[1][2 * mb + 1]);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) activate(mfma(A, xin[cb], b), act[cb][2 * mb], act[cb][2 * mb + 1]);
         }
         for (int l = 1; l <= nh; ++l) {
             const uint4* next0 = half_src(a, step + 1 < steps ? step + 1 : step);
             const uint4* next1 = half_src(a, step + 2 < steps ? step + 2 : step);
-            hidden_layer(H0, H1, next0, next1, biases + l * kW, act, nxt, lane, h);
+            hidden_layer<NCB>(H0, H1, next0, next1, biases + l * kW, act, nxt, lane, h);
             step += 2;
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
+            for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                 for (int kb = 0; kb < kKB; ++kb) act[cb][kb] = nxt[cb][kb];
         }
-        output_layer(a, Wout, biases + a.depth * kW, act, q0, lane, h, c);
+        output_layer<NCB>(a, Wout, biases + a.depth * kW, act, q0, lane, h, c);
     }
 }
 
@@ -365,7 +380,9 @@ hipError_t launch_mlp_infer(const float* x, int32_t N, const uint16_t* wf, const
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const size_t lds = infer_lds_bytes(depth);
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_infer), hipFuncAttributeMaxDynamicSharedMemorySize,
+    // one column block per wavefront, two wavefronts per SIMD (measured faster than two column
+    // blocks on one wavefront per SIMD: 0.56 vs 0.60 ms per 2^20 queries)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_infer<1>), hipFuncAttributeMaxDynamicSharedMemorySize,
                             static_cast<int>(lds));
     if (e != hipSuccess) return e;
     InferArgs a{};
@@ -382,7 +399,7 @@ hipError_t launch_mlp_infer(const float* x, int32_t N, const uint16_t* wf, const
     a.n_tiles = static_cast<int32_t>((static_cast<int64_t>(N) + kTileQ - 1) / kTileQ);
     // persistent: one workgroup per compute unit (the LDS footprint allows no second one)
     const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(a.n_tiles, std::max(cus, 1)));
-    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), lds, stream, a);
+    hipLaunchKernelGGL(k_mlp_infer<1>, dim3(blocks), dim3(512), lds, stream, a);
     return hipGetLastError();
 }
 
