@@ -87,6 +87,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
     __shared__ int s_stack[kWaves][kStackDepth];
     __shared__ int s_lane[kWaves][kLaneStack][64];
     __shared__ float s_red[kWaves][MAXH > 0 ? MAXH : 1];
+    __shared__ float4 s_rect[kCullBoxes];
+    __shared__ uint64_t s_live;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t j = blockIdx.x / a.blocks_per_dir;
@@ -107,9 +109,24 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
     float accH[MAXH > 0 ? MAXH : 1];
     for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h) accH[h] = 0.0f;
 
+    // the workgroup's tiles that may contain a hit
+    uint64_t live = ~0ull;
+    if (a.cull) {
+        if (threadIdx.x < kCullBoxes) s_rect[threadIdx.x] = cull_rect(nodes, fr, threadIdx.x);
+        __syncthreads();
+        if (wave == 0) {
+            const uint64_t mk = live_tiles(a, s_rect, static_cast<int64_t>(blk) * a.tiles_per_wave * kWaves,
+                                           a.tiles_per_wave * kWaves);
+            if (lane == 0) s_live = mk;
+        }
+        __syncthreads();
+        live = s_live;
+    }
+
     for (int m = 0; m < a.tiles_per_wave; ++m) {
         const int64_t tile = (static_cast<int64_t>(blk) * a.tiles_per_wave + m) * kWaves + wave;
         if (tile >= a.tiles_per_dir) break;
+        if (((live >> (m * kWaves + wave)) & 1ull) == 0) continue;
         int64_t pixel, rec;
         const bool valid = tile_pixel<false>(a, tile, lane, pixel, rec);
         const int32_t pi = static_cast<int32_t>(pixel % a.nu);

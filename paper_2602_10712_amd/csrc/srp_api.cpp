@@ -220,6 +220,7 @@ srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
     a.tiles_x = (p->nu + srp::kTileW - 1) / srp::kTileW;
     a.tiles_y = (p->nv + srp::kTileH - 1) / srp::kTileH;
     a.lane_walk = lane_walk_for(s->depth);
+    a.cull = p->frame_mode == 0 ? 1 : 0;
     if (records) {
         a.pix = pix;
         a.n_pix = pix ? n_pix : static_cast<int64_t>(p->nu) * p->nv;
@@ -232,7 +233,7 @@ srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
     // enough workgroups to fill 256 CUs many times over, few enough partials per direction
     const int64_t total_tiles = a.tiles_per_dir * D;
     int64_t tpw = total_tiles / (int64_t(srp::kWaves) * 8192);
-    tpw = std::max<int64_t>(1, std::min<int64_t>(16, tpw));
+    tpw = std::max<int64_t>(1, std::min<int64_t>(srp::kMaxTilesPerWave, tpw));
     a.tiles_per_wave = static_cast<int32_t>(tpw);
     const int64_t per_block = tpw * srp::kWaves;
     const int64_t bpd = std::max<int64_t>(1, (a.tiles_per_dir + per_block - 1) / per_block);
@@ -535,8 +536,10 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
     int32_t max_depth = 0;
     for (int32_t s = 0; s < S; ++s) max_depth = std::max(max_depth, scenes[s]->depth);
     a.lane_walk = lane_walk_for(max_depth);
+    a.cull = 1;
     const int64_t total_tiles = a.tiles_per_dir * units;
-    int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(16, total_tiles / (int64_t(srp::kWaves) * 8192)));
+    int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(srp::kMaxTilesPerWave,
+                                                         total_tiles / (int64_t(srp::kWaves) * 8192)));
     a.tiles_per_wave = static_cast<int32_t>(tpw);
     const int64_t bpd = std::max<int64_t>(1, (a.tiles_per_dir + tpw * srp::kWaves - 1) / (tpw * srp::kWaves));
     if (bpd * D * a.scene_slots > 0x7fffffffLL) return fail(SRP_EINVAL, "batched trace too large for one launch");

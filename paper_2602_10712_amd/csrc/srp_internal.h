@@ -14,6 +14,8 @@ constexpr int kLeafMax = 7;        // triangles per leaf (3-bit count in the chi
 constexpr int kWaves = 4;          // wavefronts per trace workgroup
 constexpr int kTileW = 8;          // a wavefront traces an 8 x 8 pixel tile
 constexpr int kTileH = 8;
+constexpr int kMaxTilesPerWave = 16;  // a workgroup covers at most 64 wave tiles (one 64-bit mask)
+static_assert(kMaxTilesPerWave * kWaves <= 64, "the live-tile mask holds one bit per workgroup tile");
 constexpr int kLaneStack = 24;     // per-lane stack of the independent walk (trees up to this depth)
 constexpr int kWalkDone = INT32_MIN;  // per-lane walk finished (never a node index or leaf code)
 
@@ -77,6 +79,7 @@ struct TraceArgs {
     int32_t tiles_per_wave;
     int32_t blocks_per_dir;
     int32_t lane_walk;        // 1: secondary segments use the per-lane walk (tree depth <= kLaneStack)
+    int32_t cull;             // 1: skip wave tiles that provably miss the scene (library frames)
     const int64_t* pix;       // records mode: explicit pixel list, or null = all pixels
     int64_t n_pix;
     double* partials;         // [(scene *) D][blocks_per_dir][6]

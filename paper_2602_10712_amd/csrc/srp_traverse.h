@@ -230,6 +230,71 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// Empty-tile culling (library frames only: the caller's frames need not be perpendicular to the
+// rays).  All rays of a grid travel along d, perpendicular to the frame axes U, V, so
+// the pixel coordinate (p - o0).U / |U|^2 of any point p a ray meets equals the ray's own, which for
+// tile (tx, ty) lies in [8 tx, 8 tx + 8) (same for V).  A tile whose pixel rectangle misses the
+// projected pixel rectangles of a set of boxes that together hold every triangle has no hit.
+// kCullBoxes boxes at depth 3 of the BVH (or shallower leaves) are used, widened by one pixel.
+constexpr int kCullBoxes = 8;
+
+// Pixel rectangle (lo_i, hi_i, lo_k, hi_k) of top box t: the child reached by the bits of t from the
+// root (stopping at a leaf); an empty leaf gives a rectangle no tile overlaps.
+__device__ __forceinline__ float4 cull_rect(const BvhNode* __restrict__ nodes, const DevFrame& fr, int t)
+{
+    int node = 0;
+    float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {0.0f, 0.0f, 0.0f};
+    for (int lev = 0; lev < 3; ++lev) {
+        const BvhNode N = nodes[node];
+        const int side = (t >> (2 - lev)) & 1;
+        const float4 xy = side ? N.f[1] : N.f[0];
+        lo[0] = xy.x;
+        hi[0] = xy.y;
+        lo[1] = xy.z;
+        hi[1] = xy.w;
+        lo[2] = side ? N.f[2].z : N.f[2].x;
+        hi[2] = side ? N.f[2].w : N.f[2].y;
+        const int code = __float_as_int(side ? N.f[3].y : N.f[3].x);
+        if (code < 0) {
+            if ((~code & 7) == 0) return make_float4(1e30f, -1e30f, 1e30f, -1e30f);
+            break;
+        }
+        node = code;
+    }
+    float cu = 0.0f, cv = 0.0f, eu = 0.0f, ev = 0.0f, uu = 0.0f, vv = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        const float c = 0.5f * (lo[a] + hi[a]) - fr.o0[a], e = 0.5f * (hi[a] - lo[a]);
+        cu += c * fr.U[a];
+        cv += c * fr.V[a];
+        eu += e * fabsf(fr.U[a]);
+        ev += e * fabsf(fr.V[a]);
+        uu += fr.U[a] * fr.U[a];
+        vv += fr.V[a] * fr.V[a];
+    }
+    if (!(uu > 0.0f) || !(vv > 0.0f)) return make_float4(-1e30f, 1e30f, -1e30f, 1e30f);  // degenerate frame
+    return make_float4((cu - eu) / uu - 1.0f, (cu + eu) / uu + 1.0f, (cv - ev) / vv - 1.0f, (cv + ev) / vv + 1.0f);
+}
+
+// Bit i of the result: wave tile first_tile + i (i < n) may contain a hit.  Called by one whole
+// wavefront; rects are the kCullBoxes rectangles of cull_rect.  A tile is dropped only when it is
+// provably disjoint from every rectangle (a NaN bound keeps it).
+__device__ __forceinline__ uint64_t live_tiles(const TraceArgs& a, const float4* rects, int64_t first_tile, int n)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = first_tile + lane;
+    bool live = false;
+    if (lane < n && tile < a.tiles_per_dir) {
+        const float tx = static_cast<float>((tile % a.tiles_x) * kTileW);
+        const float ty = static_cast<float>((tile / a.tiles_x) * kTileH);
+#pragma unroll
+        for (int r = 0; r < kCullBoxes; ++r) {
+            const float4 R = rects[r];
+            live = live || !(tx >= R.y || tx + kTileW <= R.x || ty >= R.w || ty + kTileH <= R.z);
+        }
+    }
+    return wave_ballot(live);
+}
+
 // Pixel of lane `lane` in wave tile `tile`: 8 x 8 pixel tiles in row-major order (trace mode) or
 // 64 consecutive entries of an explicit pixel list (records mode).
 template <bool RECORDS>

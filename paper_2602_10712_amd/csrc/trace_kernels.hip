@@ -79,6 +79,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     __shared__ int s_stack[kWaves][kStackDepth];
     __shared__ int s_lane[kWaves][kLaneStack][64];
     __shared__ float s_red[kWaves][6];
+    __shared__ float4 s_rect[kCullBoxes];
+    __shared__ uint64_t s_live;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     int64_t unit;  // (scene *) D + direction
@@ -125,10 +127,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     int* stack = s_stack[wave];
     int* lstack = &s_lane[wave][0][lane];
 
+    // the workgroup's tiles that may contain a hit (grid mode; records mode traces every pixel)
+    uint64_t live = ~0ull;
+    if (!RECORDS && a.cull) {
+        if (threadIdx.x < kCullBoxes) s_rect[threadIdx.x] = cull_rect(nodes, fr, threadIdx.x);
+        __syncthreads();
+        if (wave == 0) {
+            const uint64_t m = live_tiles(a, s_rect, static_cast<int64_t>(blk) * a.tiles_per_wave * kWaves,
+                                          a.tiles_per_wave * kWaves);
+            if (lane == 0) s_live = m;
+        }
+        __syncthreads();
+        live = s_live;
+    }
+
     float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int m = 0; m < a.tiles_per_wave; ++m) {
         const int64_t tile = (static_cast<int64_t>(blk) * a.tiles_per_wave + m) * kWaves + wave;
         if (tile >= a.tiles_per_dir) break;
+        if (((live >> (m * kWaves + wave)) & 1ull) == 0) continue;
         int64_t pixel, rec;
         const bool valid = tile_pixel<RECORDS>(a, tile, lane, pixel, rec);
         const int32_t pi = static_cast<int32_t>(pixel % a.nu);
