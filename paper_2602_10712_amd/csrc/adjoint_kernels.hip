@@ -80,8 +80,14 @@ __device__ __forceinline__ void wave_scatter_add(double* base, bool active, int 
 
 // MAXH: hinge tangents carried (0, 2 or 4); NS: non-final interaction slots per path (bounces - 1
 // at most), so that paths of up to 3 bounces keep only two slots in registers.
+//
+// The scene arrays and the written gradient arrays also come as separate __restrict__ parameters:
+// the atomics then provably leave the scene untouched, so node and triangle records of the coherent
+// walk can still be fetched through the scalar cache.
 template <int MAXH, int NS>
-__global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
+__global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* __restrict__ nodes,
+                                                 const TriRec* __restrict__ tris, const float4* __restrict__ mat,
+                                                 double* __restrict__ g_rho, double* __restrict__ hinge_partials)
 {
     const TraceArgs& a = A.t;
     __shared__ int s_stack[kWaves][kStackDepth];
@@ -95,8 +101,6 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
     const int32_t blk = blockIdx.x % a.blocks_per_dir;
     const DevFrame fr = a.frames[j];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
-    const BvhNode* __restrict__ nodes = a.nodes;
-    const TriRec* __restrict__ tris = a.tris;
     int* stack = s_stack[wave];
     int* lstack = &s_lane[wave][0][lane];
     const float gF[3] = {static_cast<float>(A.g_force[3 * j]), static_cast<float>(A.g_force[3 * j + 1]),
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
                 continue;
             }
             const TriRec tr = tris[hit];
-            const float4 mt = a.mat[hit];
+            const float4 mt = mat[hit];
             const float n[3] = {tr.f[1].w, tr.f[2].w, tr.f[3].x};
             const float v0[3] = {tr.f[0].x, tr.f[0].y, tr.f[0].z};
             const int fid = __float_as_int(tr.f[0].w);
@@ -293,12 +297,12 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
         for (int i = 0; i < NS; ++i) {
             const bool act = valid && i < K;
             if (wave_ballot(act) == 0) break;
-            wave_scatter_add(A.g_rho, act, arr[i] * A.n_tris + fac[i], Acc[i] * inv[i]);
+            wave_scatter_add(g_rho, act, arr[i] * A.n_tris + fac[i], Acc[i] * inv[i]);
         }
         const bool has_term = valid && term_f >= 0;
         if (wave_ballot(has_term)) {
-            wave_scatter_add(A.g_rho, has_term, term_f, term_s);
-            wave_scatter_add(A.g_rho, has_term, A.n_tris + term_f, term_d);
+            wave_scatter_add(g_rho, has_term, term_f, term_s);
+            wave_scatter_add(g_rho, has_term, A.n_tris + term_f, term_d);
         }
 #pragma unroll
         for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h)
@@ -314,7 +318,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A)
         if (threadIdx.x < MAXH) {
             double s = 0.0;
             for (int q = 0; q < kWaves; ++q) s += static_cast<double>(s_red[q][threadIdx.x]);
-            A.hinge_partials[(j * a.blocks_per_dir + blk) * kMaxHinges + threadIdx.x] = s;
+            hinge_partials[(j * a.blocks_per_dir + blk) * kMaxHinges + threadIdx.x] = s;
         }
     }
 }
@@ -361,9 +365,11 @@ template <int MAXH>
 void launch_adjoint_h(const AdjointArgs& a, unsigned blocks, hipStream_t stream)
 {
     if (a.t.bounces <= 3)
-        hipLaunchKernelGGL((k_adjoint<MAXH, 2>), dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+        hipLaunchKernelGGL((k_adjoint<MAXH, 2>), dim3(blocks), dim3(64 * kWaves), 0, stream, a, a.t.nodes, a.t.tris,
+                           a.t.mat, a.g_rho, a.hinge_partials);
     else
-        hipLaunchKernelGGL((k_adjoint<MAXH, kMaxBounces - 1>), dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+        hipLaunchKernelGGL((k_adjoint<MAXH, kMaxBounces - 1>), dim3(blocks), dim3(64 * kWaves), 0, stream, a,
+                           a.t.nodes, a.t.tris, a.t.mat, a.g_rho, a.hinge_partials);
 }
 
 }  // namespace
