@@ -49,3 +49,53 @@ def test_batch_matches_single_scene_traces_and_oracle():
     assert rel_l2(F[s].cpu().numpy(), ref.force) <= 1e-4
     with pytest.raises(p.SRPError):
         p.srp_batch_trace(scenes, sd, p.TraceParams(nu=8, nv=8, frame_mode=1), F, T)
+
+
+def test_full_size_batch_sampled():
+    """The batched benchmark launch itself: 256 MEO-style variants (log-uniform 2k-50k tris, random
+    hinges and materials), 256 Fibonacci directions x 512^2 rays, 3 bounces, one launch.  Sampled
+    designs equal their single-scene traces; two directions of the smallest design match the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2602_10712_amd as p
+    S, D, G = 256, 256, 512
+    rng = np.random.default_rng(6)
+    sizes = np.exp(rng.uniform(np.log(2000.0), np.log(50000.0), S)).astype(int)
+    dsg = si.random_designs(S, seed=6)
+
+    def make(k):
+        m = si.meo_variant(int(sizes[k]))
+        sc = p.Scene.from_mesh(m)
+        rs, rd = si.materials(m.n_tris, 100 + k)
+        sc.set_design(rs, rd, hinge_angles=dsg[k][:2])
+        return sc, m, rs, rd
+
+    with ThreadPoolExecutor(16) as ex:
+        built = list(ex.map(make, range(S)))
+    scenes = [b[0] for b in built]
+    sun = si.fibonacci_dirs(D)
+    sd = torch.as_tensor(sun, device="cuda")
+    params = p.TraceParams(nu=G, nv=G, bounces=3, jitter=1, seed=2)
+    F = torch.empty((S, D, 3), dtype=torch.float64, device="cuda")
+    T = torch.empty_like(F)
+    p.srp_batch_trace(scenes, sd, params, F, T)
+    torch.cuda.synchronize()
+    n_tris = np.array([b[1].n_tris for b in built])
+    small = int(np.argmin(n_tris))
+    for k in (small, int(np.argsort(n_tris)[S // 2]), int(np.argmax(n_tris)), 7, 200):
+        pk = p.TraceParams(nu=G, nv=G, bounces=3, jitter=1, seed=2, design_index=k)
+        Fs, Ts = scenes[k].trace(sd, pk)
+        torch.cuda.synchronize()
+        e = rel_l2(F[k].cpu().numpy(), Fs.cpu().numpy())
+        print(f"[batch design {k}, {n_tris[k]} tris] vs single-scene trace: rel L2 {e:.2e}")
+        assert e <= 1e-9
+        assert rel_l2(T[k].cpu().numpy(), Ts.cpu().numpy()) <= 1e-9
+    sc, m, rs, rd = built[small][0], built[small][1], built[small][2], built[small][3]
+    V = sc.vertices()
+    for j in (17, 190):
+        ref = oracle.trace(V, m.tris, rs, rd, sun[j:j + 1], nu=G, nv=G, bounces=3, seed=2, dir_index_base=j,
+                           design_index=small)
+        e = rel_l2(F[small, j:j + 1].cpu().numpy(), ref.force)
+        print(f"[batch design {small}, direction {j}] vs oracle: force rel L2 {e:.2e}")
+        assert e <= 1e-4
+    for sc in scenes:
+        sc.close()
