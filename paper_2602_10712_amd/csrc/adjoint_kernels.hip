@@ -81,13 +81,17 @@ __device__ __forceinline__ void wave_scatter_add(double* base, bool active, int 
 // MAXH: hinge tangents carried (0, 2 or 4); NS: non-final interaction slots per path (bounces - 1
 // at most), so that paths of up to 3 bounces keep only two slots in registers.
 //
-// The scene arrays and the written gradient arrays also come as separate __restrict__ parameters:
-// the atomics then provably leave the scene untouched, so node and triangle records of the coherent
-// walk can still be fetched through the scalar cache.
+// The scene arrays, frames, cotangents and the written gradient arrays also come as separate
+// __restrict__ parameters: the atomics then provably leave the inputs untouched, so node and
+// triangle records of the coherent walk, the frame and the cotangents can still be fetched through
+// the scalar cache into scalar registers.
 template <int MAXH, int NS>
 __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* __restrict__ nodes,
                                                  const TriRec* __restrict__ tris, const float4* __restrict__ mat,
-                                                 double* __restrict__ g_rho, double* __restrict__ hinge_partials)
+                                                 const DevFrame* __restrict__ frames,
+                                                 const double* __restrict__ g_force,
+                                                 const double* __restrict__ g_torque, double* __restrict__ g_rho,
+                                                 double* __restrict__ hinge_partials)
 {
     const TraceArgs& a = A.t;
     __shared__ int s_stack[kWaves][kStackDepth];
@@ -99,15 +103,15 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
     const int wave = threadIdx.x >> 6;
     const int64_t j = blockIdx.x / a.blocks_per_dir;
     const int32_t blk = blockIdx.x % a.blocks_per_dir;
-    const DevFrame fr = a.frames[j];
+    const DevFrame fr = frames[j];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
     int* stack = s_stack[wave];
     int* lstack = &s_lane[wave][0][lane];
-    const float gF[3] = {static_cast<float>(A.g_force[3 * j]), static_cast<float>(A.g_force[3 * j + 1]),
-                         static_cast<float>(A.g_force[3 * j + 2])};
+    const float gF[3] = {static_cast<float>(g_force[3 * j]), static_cast<float>(g_force[3 * j + 1]),
+                         static_cast<float>(g_force[3 * j + 2])};
     float gT[3] = {0.0f, 0.0f, 0.0f};
-    if (A.g_torque)
-        for (int c = 0; c < 3; ++c) gT[c] = static_cast<float>(A.g_torque[3 * j + c]);
+    if (g_torque)
+        for (int c = 0; c < 3; ++c) gT[c] = static_cast<float>(g_torque[3 * j + c]);
     const int H = A.n_hinges < MAXH ? A.n_hinges : MAXH;
 
     float accH[MAXH > 0 ? MAXH : 1];
@@ -366,10 +370,11 @@ void launch_adjoint_h(const AdjointArgs& a, unsigned blocks, hipStream_t stream)
 {
     if (a.t.bounces <= 3)
         hipLaunchKernelGGL((k_adjoint<MAXH, 2>), dim3(blocks), dim3(64 * kWaves), 0, stream, a, a.t.nodes, a.t.tris,
-                           a.t.mat, a.g_rho, a.hinge_partials);
+                           a.t.mat, a.t.frames, a.g_force, a.g_torque, a.g_rho, a.hinge_partials);
     else
         hipLaunchKernelGGL((k_adjoint<MAXH, kMaxBounces - 1>), dim3(blocks), dim3(64 * kWaves), 0, stream, a,
-                           a.t.nodes, a.t.tris, a.t.mat, a.g_rho, a.hinge_partials);
+                           a.t.nodes, a.t.tris, a.t.mat, a.t.frames, a.g_force, a.g_torque, a.g_rho,
+                           a.hinge_partials);
 }
 
 }  // namespace

@@ -1,5 +1,6 @@
 // libsrp host side: C ABI (include/srp.h), scene lifecycle, design application (hinge rotation
-// in FP64 + host BVH rebuild), workspace management and kernel launches.
+// in FP64; host BVH build at creation, refit of its boxes when hinge angles change), workspace
+// management and kernel launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

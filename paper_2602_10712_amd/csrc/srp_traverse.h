@@ -235,8 +235,10 @@ __device__ __forceinline__ float wave_sum(float v)
 // the pixel coordinate (p - o0).U / |U|^2 of any point p a ray meets equals the ray's own, which for
 // tile (tx, ty) lies in [8 tx, 8 tx + 8) (same for V).  A tile whose pixel rectangle misses the
 // projected pixel rectangles of a set of boxes that together hold every triangle has no hit.
-// kCullBoxes boxes at depth 3 of the BVH (or shallower leaves) are used, widened by one pixel.
-constexpr int kCullBoxes = 8;
+// kCullBoxes boxes at depth kCullDepth of the BVH (or shallower leaves) are used, widened by one
+// pixel.
+constexpr int kCullDepth = 3;
+constexpr int kCullBoxes = 1 << kCullDepth;
 
 // Pixel rectangle (lo_i, hi_i, lo_k, hi_k) of top box t: the child reached by the bits of t from the
 // root (stopping at a leaf); an empty leaf gives a rectangle no tile overlaps.
@@ -244,9 +246,9 @@ __device__ __forceinline__ float4 cull_rect(const BvhNode* __restrict__ nodes, c
 {
     int node = 0;
     float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {0.0f, 0.0f, 0.0f};
-    for (int lev = 0; lev < 3; ++lev) {
+    for (int lev = 0; lev < kCullDepth; ++lev) {
         const BvhNode N = nodes[node];
-        const int side = (t >> (2 - lev)) & 1;
+        const int side = (t >> (kCullDepth - 1 - lev)) & 1;
         const float4 xy = side ? N.f[1] : N.f[0];
         lo[0] = xy.x;
         hi[0] = xy.y;
