@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SRP Mrays/s (20k tri, 3 bounce) fwd & fwd+adjoint; surrogate force evals/s"
 HBM_PEAK_GBS = 8000.0
+ADJ_ATOMIC_BYTES = 16.0  # at most two FP64 gradient updates per hit
 
 
 def log(msg):
@@ -191,6 +192,19 @@ def main():
         fwd_adj = {"value": round(rays_a / (ms_adj * 1e-3) / 1e6, 2), "unit": "Mrays/s", "ms_per_step": round(ms_adj, 3),
                    "workload": f"{D} dirs x {g}x{g} rays, {args.bounces} bounces: forward trace + adjoint replay "
                                "(d/d rho_s, rho_d per facet, d/d 2 hinge angles)"}
+        try:
+            from paper_2602_10712_amd import ray_stats
+            sa = ray_stats(sc, sun, pa, n_dirs=16, pixel_stride=97)
+            # the forward pass and the replay each touch the path's nodes, triangles and hit records;
+            # the replay adds at most two FP64 gradient atomics per hit (one for the sampled event
+            # at a reflection, one each for rho_s and rho_d at the final interaction)
+            bpr = 2.0 * sa["bytes_per_ray"] + ADJ_ATOMIC_BYTES * sa["hits_per_ray"]
+            ach = bpr * rays_a / (ms_adj * 1e-3) / 1e9
+            fwd_adj["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_ray": round(bpr, 1),
+                                   "hits_per_ray": round(sa["hits_per_ray"], 4)}
+        except Exception as e:
+            log(f"adjoint roofline stats unavailable: {e!r}")
         log(f"forward+adjoint: {ms_adj:.2f} ms/step, {fwd_adj['value']:.1f} Mrays/s")
 
     # ---- surrogate inference: fused BF16-MFMA MLP 11 -> 4 x 256 (SiLU) -> 3 on 1M queries ---------

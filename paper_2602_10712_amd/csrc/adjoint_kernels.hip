@@ -101,8 +101,9 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
     __shared__ uint64_t s_live;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t j = blockIdx.x / a.blocks_per_dir;
-    const int32_t blk = blockIdx.x % a.blocks_per_dir;
+    int64_t j;
+    int32_t blk;
+    if (!block_unit(a, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
     const DevFrame fr = frames[j];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
     int* stack = s_stack[wave];
@@ -381,8 +382,10 @@ void launch_adjoint_h(const AdjointArgs& a, unsigned blocks, hipStream_t stream)
 
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream)
 {
-    const unsigned blocks = static_cast<unsigned>(a.t.D * a.t.blocks_per_dir);
-    if (blocks == 0) return hipSuccess;
+    const int64_t nb = single_scene_blocks(a.t);
+    if (nb == 0) return hipSuccess;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    const unsigned blocks = static_cast<unsigned>(nb);
     if (a.n_hinges == 0)
         launch_adjoint_h<0>(a, blocks, stream);
     else if (a.n_hinges <= 2)

@@ -234,12 +234,16 @@ srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
     // enough workgroups to fill 256 CUs many times over, few enough partials per direction
     const int64_t total_tiles = a.tiles_per_dir * D;
     int64_t tpw = total_tiles / (int64_t(srp::kWaves) * 8192);
-    tpw = std::max<int64_t>(1, std::min<int64_t>(srp::kMaxTilesPerWave, tpw));
+    tpw = std::max<int64_t>(1, std::min<int64_t>(srp::kTilesPerWaveLarge, tpw));
     a.tiles_per_wave = static_cast<int32_t>(tpw);
     const int64_t per_block = tpw * srp::kWaves;
     const int64_t bpd = std::max<int64_t>(1, (a.tiles_per_dir + per_block - 1) / per_block);
     if (bpd * D > 0x7fffffffLL) return fail(SRP_EINVAL, "trace too large for one launch");
     a.blocks_per_dir = static_cast<int32_t>(bpd);
+    // with at least one direction per XCD, each direction stays on one XCD (no image row is tied to
+    // an XCD); fewer directions are spread over all of them
+    a.xcd_major = D >= srp::kXcds ? 1 : 0;
+    if (srp::single_scene_blocks(a) > 0x7fffffffLL) return fail(SRP_EINVAL, "trace too large for one launch");
     SRP_HIP(ensure(s->d_partials, s->partials_cap, static_cast<size_t>(bpd * D * std::max(6, srp::kMaxHinges))));
     a.partials = s->d_partials;
     return SRP_OK;
@@ -539,7 +543,7 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
     a.lane_walk = lane_walk_for(max_depth);
     a.cull = 1;
     const int64_t total_tiles = a.tiles_per_dir * units;
-    int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(srp::kMaxTilesPerWave,
+    int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(srp::kTilesPerWaveLarge,
                                                          total_tiles / (int64_t(srp::kWaves) * 8192)));
     a.tiles_per_wave = static_cast<int32_t>(tpw);
     const int64_t bpd = std::max<int64_t>(1, (a.tiles_per_dir + tpw * srp::kWaves - 1) / (tpw * srp::kWaves));

@@ -16,6 +16,13 @@ constexpr int kTileW = 8;          // a wavefront traces an 8 x 8 pixel tile
 constexpr int kTileH = 8;
 constexpr int kMaxTilesPerWave = 16;  // a workgroup covers at most 64 wave tiles (one 64-bit mask)
 static_assert(kMaxTilesPerWave * kWaves <= 64, "the live-tile mask holds one bit per workgroup tile");
+// Tiles per wave of large traces.  A workgroup then spans 60 tiles, which does not divide the
+// power-of-two tile rows of the usual grids: spans drift across rows from one workgroup to the next,
+// so the round-robin placement of consecutive workgroups on shader engines does not hand the same
+// rows (panels seen edge-on, the bus) to the same engines in every direction.
+constexpr int kTilesPerWaveLarge = 15;
+static_assert(kTilesPerWaveLarge <= kMaxTilesPerWave, "within the live-tile mask");
+constexpr int kXcds = 8;           // MI355X: hardware workgroup b runs on accelerator complex b % 8
 constexpr int kLaneStack = 24;     // per-lane stack of the independent walk (trees up to this depth)
 constexpr int kWalkDone = INT32_MIN;  // per-lane walk finished (never a node index or leaf code)
 
@@ -80,12 +87,21 @@ struct TraceArgs {
     int32_t blocks_per_dir;
     int32_t lane_walk;        // 1: secondary segments use the per-lane walk (tree depth <= kLaneStack)
     int32_t cull;             // 1: skip wave tiles that provably miss the scene (library frames)
+    int32_t xcd_major;        // single scene: 1 = direction j is traced by the workgroups of XCD j % 8
     const int64_t* pix;       // records mode: explicit pixel list, or null = all pixels
     int64_t n_pix;
     double* partials;         // [(scene *) D][blocks_per_dir][6]
     int32_t* rec_hit;         // [D][n_pix][bounces]
     float* rec_force;         // [D][n_pix][3]
 };
+
+// Workgroups of a single-scene trace or adjoint launch.  Direction-major order needs D x
+// blocks_per_dir; XCD-major order pads D to whole groups of kXcds directions.
+inline int64_t single_scene_blocks(const TraceArgs& a)
+{
+    const int64_t dirs = a.xcd_major ? (a.D + kXcds - 1) / kXcds * kXcds : a.D;
+    return dirs * a.blocks_per_dir;
+}
 
 constexpr int kMaxHinges = 4;   // hinge-angle gradients supported by the adjoint
 

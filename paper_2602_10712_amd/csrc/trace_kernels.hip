@@ -111,8 +111,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
         eps = sd.eps;
         design += static_cast<uint32_t>(s);
     } else {
-        j = blockIdx.x / a.blocks_per_dir;
-        blk = blockIdx.x % a.blocks_per_dir;
+        if (!block_unit(a, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
         unit = j;
         nodes = a.nodes;
         tris = a.tris;
@@ -263,12 +262,15 @@ hipError_t launch_pack_materials(const float* rho_s, const float* rho_d, const f
 
 hipError_t launch_trace(const TraceArgs& a, bool records, hipStream_t stream)
 {
-    const unsigned blocks = static_cast<unsigned>(a.D * a.blocks_per_dir);
+    const int64_t blocks = single_scene_blocks(a);
     if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (records)
-        hipLaunchKernelGGL((k_trace<true, false>), dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+        hipLaunchKernelGGL((k_trace<true, false>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream,
+                           a);
     else
-        hipLaunchKernelGGL((k_trace<false, false>), dim3(blocks), dim3(64 * kWaves), 0, stream, a);
+        hipLaunchKernelGGL((k_trace<false, false>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream,
+                           a);
     return hipGetLastError();
 }
 
