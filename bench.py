@@ -47,10 +47,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_trace launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
-    scaled by a plain copy's counters), or None when the kernel sources changed since then."""
-    path = os.path.join(ROOT, "profiles", "k_trace_meo20k_traffic.md")
+def profile_record(name):
+    """The JSON record of a committed counter summary under profiles/, or None when it is missing or
+    the trace kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         text = open(path).read()
         blob = text.split("```json", 1)[1].split("```", 1)[0]
@@ -59,7 +59,19 @@ def measured_traffic():
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+def measured_traffic():
+    """HBM bytes per k_trace launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters)."""
+    rec = profile_record("k_trace_meo20k_traffic.md")
+    return None if rec is None else rec.get("hbm_bytes_per_launch")
+
+
+def measured_l2_hit_rate():
+    """L2 hit rate of k_trace on the benchmark workload (TCC_HIT / (TCC_HIT + TCC_MISS))."""
+    rec = profile_record("k_trace_meo20k_counters.md")
+    return None if rec is None else rec.get("l2_hit_rate")
 
 
 def parse():
@@ -294,6 +306,7 @@ def main():
         achieved = bytes_per_ray * rays / (np.median(step_ms) * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                    "l2_hit_rate": measured_l2_hit_rate(),
                     "bytes_per_ray": round(bytes_per_ray, 1), "segments_per_ray": round(st["segments_per_ray"], 4),
                     "nodes_per_segment": round(st["nodes_per_segment"], 2),
                     "tris_per_segment": round(st["tris_per_segment"], 2)}
