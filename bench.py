@@ -272,6 +272,14 @@ def main():
         tris_b = np.array([b[1] for b in built])
         sun_b = torch.as_tensor(si.fibonacci_dirs(args.batch_dirs), dtype=torch.float64, device=dev).contiguous()
         pb = p.TraceParams(nu=args.batch_grid, nv=args.batch_grid, bounces=args.bounces, jitter=1, seed=2)
+        # launch shape from the autotuner, on every 8th direction (untimed, like the BVH builds)
+        t0 = time.perf_counter()
+        tpw, tune_ms = p.srp_autotune_tiles_per_wave(scenes, sun_b[::8].contiguous(), pb,
+                                                     stream=stream.cuda_stream)
+        tune_s = time.perf_counter() - t0
+        pb.tiles_per_wave = tpw
+        log(f"batched: autotuned tiles_per_wave = {tpw} in {tune_s:.1f} s "
+            f"({', '.join(f'{k}: {v:.1f}' for k, v in tune_ms.items())} ms)")
         Fb = torch.empty((S_n, args.batch_dirs, 3), dtype=torch.float64, device=dev)
         Tb = torch.empty_like(Fb)
         for i in range(max(args.warmup, 1)):
@@ -288,7 +296,8 @@ def main():
         ms_b = e0.elapsed_time(e1) / nb
         rays_b = float(S_n) * args.batch_dirs * args.batch_grid ** 2
         batched = {"value": round(rays_b / (ms_b * 1e-3) / 1e6, 1), "unit": "Mrays/s", "ms_per_launch": round(ms_b, 2),
-                   "launches": nb, "scene_build_s": round(build_b, 2),
+                   "launches": nb, "scene_build_s": round(build_b, 2), "tiles_per_wave": tpw,
+                   "autotune_s": round(tune_s, 2),
                    "workload": f"{S_n} MEO-style variants ({int(tris_b.min())}-{int(tris_b.max())} tris, "
                                f"{int(tris_b.sum())} total), {args.batch_dirs} Fibonacci dirs x "
                                f"{args.batch_grid}x{args.batch_grid} rays, {args.bounces} bounces, one launch"}

@@ -70,7 +70,10 @@ typedef struct {
  *   frame_mode    0: the grid frame of each direction is derived from the mesh (Duff et al. 2017
  *                 basis of the propagation direction, rectangle bounding the projected box,
  *                 entry plane 0.01 L in front, L = twice the largest vertex distance from the
- *                 vertex mean); 1: the caller passes frames (see srp_frames for the layout) */
+ *                 vertex mean); 1: the caller passes frames (see srp_frames for the layout)
+ *   tiles_per_wave  launch shape only: 8 x 8-pixel tiles per wavefront and workgroup, 1..16, or 0
+ *                 for the library's rule (srp_autotune_tiles_per_wave measures the choices).  Results
+ *                 are the same up to the FP32 summation order of the per-wave partial sums. */
 typedef struct {
     int32_t nu, nv;
     int32_t bounces;
@@ -80,6 +83,7 @@ typedef struct {
     int64_t dir_index_base;
     int32_t design_index;
     int32_t frame_mode;
+    int32_t tiles_per_wave;
 } srp_trace_params;
 
 /* Creates a scene from a rest-pose mesh.  Host arrays, copied:
@@ -164,12 +168,23 @@ srp_status srp_scene_ray_stats(srp_scene scene, const double* sun_dirs, int64_t 
 /* Batched designs (paper Sec. 3.2, "Estimation": samples are drawn over many designs at once): one
  * launch traces S scenes for the same D sun directions (device double [D][3]).  Design s uses
  * Philox design index params->design_index + s and its own mesh-derived frames (frame_mode must be
- * 0).  force, torque: device double [S][D][3] (torque may be NULL).  Work is split design-major and
- * each design runs on one XCD (its BVH stays in one L2).  Workspace belongs to scenes[0]; all scenes
- * must be on the current device.  The design table is uploaded on `stream` from pinned staging; a
+ * 0).  force, torque: device double [S][D][3] (torque may be NULL).  The (design, direction) units
+ * are traced design-major, each direction of a design on one XCD and a design's directions spread
+ * over all of them, so the XCDs work through the designs together.  Workspace belongs to
+ * scenes[0]; all scenes must be on the current device.  The design table is uploaded on `stream` from pinned staging; a
  * call waits for the previous batch upload led by the same scene before reusing the staging. */
 srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
                            const srp_trace_params* params, double* force, double* torque, void* stream);
+
+/* Launch-shape autotuner (not part of the paper's method): traces the given workload once per
+ * candidate tiles_per_wave in 8..16 (S == 1: srp_trace of scenes[0]; S > 1: srp_batch_trace), after
+ * one warm-up run each, and returns the fastest in *best; ms_out (host double [9], nullable)
+ * receives every candidate's time in ms.  params->tiles_per_wave is ignored.  Pass a
+ * representative subset of the directions: the call runs 18 traces.  Synchronous; allocates a
+ * temporary force buffer.  Errors as for srp_trace / srp_batch_trace. */
+srp_status srp_autotune_tiles_per_wave(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
+                                       const srp_trace_params* params, int32_t* best, double* ms_out,
+                                       void* stream);
 
 srp_status srp_scene_destroy(srp_scene scene);
 

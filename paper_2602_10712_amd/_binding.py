@@ -30,12 +30,13 @@ class srp_hinge(ctypes.Structure):
 
 class TraceParams(ctypes.Structure):
     _fields_ = [("nu", I32), ("nv", I32), ("bounces", I32), ("jitter", I32), ("flux", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("dir_index_base", I64), ("design_index", I32), ("frame_mode", I32)]
+                ("seed", ctypes.c_uint64), ("dir_index_base", I64), ("design_index", I32), ("frame_mode", I32),
+                ("tiles_per_wave", I32)]
 
     def __init__(self, nu=256, nv=256, bounces=1, jitter=1, flux=1361.0, seed=0, dir_index_base=0, design_index=0,
-                 frame_mode=0):
+                 frame_mode=0, tiles_per_wave=0):
         super().__init__(int(nu), int(nv), int(bounces), int(bool(jitter)), float(flux), int(seed),
-                         int(dir_index_base), int(design_index), int(frame_mode))
+                         int(dir_index_base), int(design_index), int(frame_mode), int(tiles_per_wave))
 
 
 _sigs = {
@@ -49,6 +50,7 @@ _sigs = {
     "srp_scene_ray_stats": [P, P, I64, ctypes.POINTER(TraceParams), P, I64, P],
     "srp_trace_adjoint": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P, P, P, P],
     "srp_batch_trace": [P, I32, P, I64, ctypes.POINTER(TraceParams), P, P, P],
+    "srp_autotune_tiles_per_wave": [P, I32, P, I64, ctypes.POINTER(TraceParams), ctypes.POINTER(I32), P, P],
     "srp_scene_destroy": [P],
     "srp_mlp_create": [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)],
     "srp_mlp_num_params": [P, ctypes.POINTER(I64)],
@@ -213,6 +215,20 @@ def srp_batch_trace(scenes, sun_dirs, params: TraceParams, force, torque=None, s
     arr = (P * len(hs))(*[h.value if isinstance(h, P) else h for h in hs])
     _check(_lib.srp_batch_trace(ctypes.cast(arr, P), len(hs), _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params),
                                 _dptr(force), _dptr(torque), _stream(stream)))
+
+
+def srp_autotune_tiles_per_wave(scenes, sun_dirs, params: TraceParams, stream=None):
+    """Fastest tiles_per_wave (8..16) for this workload, and every candidate's time in ms (see srp.h).
+    One scene tunes srp_trace, several tune srp_batch_trace."""
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    hs = [s.handle if isinstance(s, Scene) else s for s in scenes]
+    arr = (P * len(hs))(*[h.value if isinstance(h, P) else h for h in hs])
+    best = I32(0)
+    ms = np.zeros(9)
+    _check(_lib.srp_autotune_tiles_per_wave(ctypes.cast(arr, P), len(hs), _dptr(sun_dirs), sun_dirs.shape[0],
+                                            ctypes.byref(params), ctypes.byref(best), _hptr(ms), _stream(stream)))
+    return int(best.value), dict(zip(range(8, 17), ms.tolist()))
 
 
 def srp_scene_ray_stats(scene, sun_dirs, params: TraceParams, pixel_stride=1, frames=None):

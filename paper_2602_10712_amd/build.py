@@ -29,7 +29,7 @@ def _compile(src: str, obj: str) -> None:
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip", *DEVICE, *EXTRA.get(src, []), *COMMON, "-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
+        cmd = [HIPCC, "--offload-arch=gfx950", *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
     subprocess.run(cmd, check=True)
 
 

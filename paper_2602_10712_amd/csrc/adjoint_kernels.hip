@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
     const int wave = threadIdx.x >> 6;
     int64_t j;
     int32_t blk;
-    if (!block_unit(a, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
+    if (!block_unit(a, a.D, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
     const DevFrame fr = frames[j];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
     int* stack = s_stack[wave];
@@ -382,7 +382,7 @@ void launch_adjoint_h(const AdjointArgs& a, unsigned blocks, hipStream_t stream)
 
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream)
 {
-    const int64_t nb = single_scene_blocks(a.t);
+    const int64_t nb = grid_blocks(a.t, a.t.D);
     if (nb == 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
     const unsigned blocks = static_cast<unsigned>(nb);

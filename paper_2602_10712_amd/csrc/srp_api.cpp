@@ -57,6 +57,12 @@ hipError_t ensure(T*& ptr, size_t& cap, size_t n)
 srp_status srp_fail(srp_status st, const std::string& msg) { return fail(st, msg); }
 
 namespace {
+// tiles_per_wave candidates of the autotuner
+constexpr int32_t kTuneFirst = 8;
+constexpr int32_t kTuneLast = srp::kMaxTilesPerWave;
+}  // namespace
+
+namespace {
 
 void rotate_hinges(srp_scene_s* s)
 {
@@ -162,6 +168,16 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
     return SRP_OK;
 }
 
+// Wave tiles per wave (and so per workgroup: kWaves times as many) of a trace of total_tiles
+// tiles: the caller's choice, else enough workgroups to fill 256 CUs many times over with few
+// partials per direction, at most kTilesPerWaveLarge.
+int64_t tiles_per_wave_for(const srp_trace_params* p, int64_t total_tiles)
+{
+    if (p->tiles_per_wave > 0) return p->tiles_per_wave;
+    const int64_t tpw = total_tiles / (int64_t(srp::kWaves) * 8192);
+    return std::max<int64_t>(1, std::min<int64_t>(srp::kTilesPerWaveLarge, tpw));
+}
+
 // Secondary segments take the per-lane walk when the tree fits its stack, unless the environment
 // sets SRP_SECONDARY_WALK=wave (every segment then takes the wave-coherent walk).  Both walks give
 // identical hits; the switch exists for performance comparisons.
@@ -183,6 +199,8 @@ srp_status check_params(const srp_trace_params* p)
     if (!(p->flux >= 0.0) || !std::isfinite(p->flux)) return fail(SRP_EINVAL, "flux must be finite and >= 0");
     if (p->frame_mode != 0 && p->frame_mode != 1) return fail(SRP_EINVAL, "frame_mode must be 0 or 1");
     if (p->dir_index_base < 0) return fail(SRP_EINVAL, "dir_index_base must be >= 0");
+    if (p->tiles_per_wave < 0 || p->tiles_per_wave > srp::kMaxTilesPerWave)
+        return fail(SRP_EINVAL, "tiles_per_wave must be in 0..16");
     return SRP_OK;
 }
 
@@ -231,10 +249,7 @@ srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
     } else {
         a.tiles_per_dir = static_cast<int64_t>(a.tiles_x) * a.tiles_y;
     }
-    // enough workgroups to fill 256 CUs many times over, few enough partials per direction
-    const int64_t total_tiles = a.tiles_per_dir * D;
-    int64_t tpw = total_tiles / (int64_t(srp::kWaves) * 8192);
-    tpw = std::max<int64_t>(1, std::min<int64_t>(srp::kTilesPerWaveLarge, tpw));
+    const int64_t tpw = tiles_per_wave_for(p, a.tiles_per_dir * D);
     a.tiles_per_wave = static_cast<int32_t>(tpw);
     const int64_t per_block = tpw * srp::kWaves;
     const int64_t bpd = std::max<int64_t>(1, (a.tiles_per_dir + per_block - 1) / per_block);
@@ -243,7 +258,7 @@ srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
     // with at least one direction per XCD, each direction stays on one XCD (no image row is tied to
     // an XCD); fewer directions are spread over all of them
     a.xcd_major = D >= srp::kXcds ? 1 : 0;
-    if (srp::single_scene_blocks(a) > 0x7fffffffLL) return fail(SRP_EINVAL, "trace too large for one launch");
+    if (srp::grid_blocks(a, D) > 0x7fffffffLL) return fail(SRP_EINVAL, "trace too large for one launch");
     SRP_HIP(ensure(s->d_partials, s->partials_cap, static_cast<size_t>(bpd * D * std::max(6, srp::kMaxHinges))));
     a.partials = s->d_partials;
     return SRP_OK;
@@ -510,9 +525,9 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
     }
     for (int32_t s = 0; s < S; ++s) {
         srp::SceneDesc& d = lead->h_batch_desc[s];
-        d.nodes = scenes[s]->d_nodes;
-        d.tris = scenes[s]->d_tris;
-        d.mat = scenes[s]->d_mat;
+        d.nodes = (decltype(d.nodes))scenes[s]->d_nodes;  // device passes see global-qualified members
+        d.tris = (decltype(d.tris))scenes[s]->d_tris;
+        d.mat = (decltype(d.mat))scenes[s]->d_mat;
         for (int k = 0; k < 3; ++k) d.com[k] = static_cast<float>(scenes[s]->com[k]);
         d.eps = static_cast<float>(1e-5 * scenes[s]->L);
     }
@@ -524,7 +539,6 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
     srp::TraceArgs a{};
     a.scenes = lead->d_batch_desc;
     a.n_scenes = S;
-    a.scene_slots = (S + 7) / 8 * 8;
     a.frames = lead->d_frames;
     a.D = D;
     a.nu = p->nu;
@@ -542,17 +556,66 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
     for (int32_t s = 0; s < S; ++s) max_depth = std::max(max_depth, scenes[s]->depth);
     a.lane_walk = lane_walk_for(max_depth);
     a.cull = 1;
-    const int64_t total_tiles = a.tiles_per_dir * units;
-    int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(srp::kTilesPerWaveLarge,
-                                                         total_tiles / (int64_t(srp::kWaves) * 8192)));
+    const int64_t tpw = tiles_per_wave_for(p, a.tiles_per_dir * units);
     a.tiles_per_wave = static_cast<int32_t>(tpw);
     const int64_t bpd = std::max<int64_t>(1, (a.tiles_per_dir + tpw * srp::kWaves - 1) / (tpw * srp::kWaves));
-    if (bpd * D * a.scene_slots > 0x7fffffffLL) return fail(SRP_EINVAL, "batched trace too large for one launch");
     a.blocks_per_dir = static_cast<int32_t>(bpd);
+    a.xcd_major = units >= srp::kXcds ? 1 : 0;
+    if (srp::grid_blocks(a, units) > 0x7fffffffLL) return fail(SRP_EINVAL, "batched trace too large for one launch");
     SRP_HIP(ensure(lead->d_partials, lead->partials_cap, static_cast<size_t>(bpd * units * 6)));
     a.partials = lead->d_partials;
     SRP_HIP(srp::launch_trace_batch(a, stream));
     SRP_HIP(srp::launch_reduce(lead->d_partials, units, a.blocks_per_dir, force, torque, stream));
+    return SRP_OK;
+}
+
+srp_status srp_autotune_tiles_per_wave(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
+                                       const srp_trace_params* p, int32_t* best, double* ms_out, void* stream_)
+{
+    if (!scenes || S < 1 || !best) return fail(SRP_EINVAL, "need scenes and an output");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (D < 1 || !sun_dirs) return fail(SRP_EINVAL, "need at least one sun direction");
+    for (int32_t s = 0; s < S; ++s)
+        if (!scenes[s]) return fail(SRP_EINVAL, "NULL scene");
+    st = bind_device(scenes[0]);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    double* F = nullptr;
+    const size_t bytes = sizeof(double) * 3 * static_cast<size_t>(S) * static_cast<size_t>(D);
+    SRP_HIP(hipMalloc(reinterpret_cast<void**>(&F), bytes));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    double best_ms = 0.0;
+    int32_t best_tpw = 0;
+    st = SRP_OK;
+    for (int32_t c = kTuneFirst; c <= kTuneLast && he == hipSuccess && st == SRP_OK; ++c) {
+        srp_trace_params q = *p;
+        q.tiles_per_wave = c;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && st == SRP_OK; ++rep) {  // the first run warms caches and clocks
+            if (rep == 1 && (he = hipEventRecord(e0, stream)) != hipSuccess) break;
+            st = S == 1 ? srp_trace(scenes[0], sun_dirs, D, &q, nullptr, F, nullptr, stream_)
+                        : srp_batch_trace(scenes, S, sun_dirs, D, &q, F, nullptr, stream_);
+        }
+        if (st != SRP_OK) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) break;
+        if (ms_out) ms_out[c - kTuneFirst] = ms;
+        if (best_tpw == 0 || ms < best_ms) {
+            best_ms = ms;
+            best_tpw = c;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(F);  // waits for the device
+    if (st != SRP_OK) return st;
+    if (he != hipSuccess) return fail(SRP_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(he));
+    *best = best_tpw;
     return SRP_OK;
 }
 

@@ -56,10 +56,20 @@ struct DevFrame {
 };
 
 // One design of a batched trace (device array, one entry per scene).
+// Pointers that kernels read from memory rather than receive as arguments carry the global address
+// space in device code, so loads through them are global (and scalar where the address is
+// wave-uniform) rather than generic; the host sees plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SRP_GLOBAL __attribute__((address_space(1)))
+#else
+#define SRP_GLOBAL
+#endif
+
+// One design of a batched trace.
 struct SceneDesc {
-    const BvhNode* nodes;
-    const TriRec* tris;
-    const float4* mat;
+    const SRP_GLOBAL BvhNode* nodes;
+    const SRP_GLOBAL TriRec* tris;
+    const SRP_GLOBAL float4* mat;
     float com[3];
     float eps;
 };
@@ -67,7 +77,6 @@ struct SceneDesc {
 struct TraceArgs {
     const SceneDesc* scenes;  // batched trace: [n_scenes] (null for a single scene)
     int32_t n_scenes;
-    int32_t scene_slots;      // designs in the launch grid (n_scenes rounded up to a multiple of 8)
     const BvhNode* nodes;
     const TriRec* tris;
     const float4* mat;        // BVH order: (rho_s, rho_d, p_spec, 0)
@@ -87,7 +96,7 @@ struct TraceArgs {
     int32_t blocks_per_dir;
     int32_t lane_walk;        // 1: secondary segments use the per-lane walk (tree depth <= kLaneStack)
     int32_t cull;             // 1: skip wave tiles that provably miss the scene (library frames)
-    int32_t xcd_major;        // single scene: 1 = direction j is traced by the workgroups of XCD j % 8
+    int32_t xcd_major;        // 1: unit u (direction, or design x direction) is traced by XCD u % 8
     const int64_t* pix;       // records mode: explicit pixel list, or null = all pixels
     int64_t n_pix;
     double* partials;         // [(scene *) D][blocks_per_dir][6]
@@ -95,12 +104,13 @@ struct TraceArgs {
     float* rec_force;         // [D][n_pix][3]
 };
 
-// Workgroups of a single-scene trace or adjoint launch.  Direction-major order needs D x
-// blocks_per_dir; XCD-major order pads D to whole groups of kXcds directions.
-inline int64_t single_scene_blocks(const TraceArgs& a)
+// Workgroups of a trace or adjoint launch over n_units units (directions, or (design, direction)
+// pairs).  Direction-major order needs n_units x blocks_per_dir; XCD-major order pads n_units to
+// whole groups of kXcds.
+inline int64_t grid_blocks(const TraceArgs& a, int64_t n_units)
 {
-    const int64_t dirs = a.xcd_major ? (a.D + kXcds - 1) / kXcds * kXcds : a.D;
-    return dirs * a.blocks_per_dir;
+    const int64_t units = a.xcd_major ? (n_units + kXcds - 1) / kXcds * kXcds : n_units;
+    return units * a.blocks_per_dir;
 }
 
 constexpr int kMaxHinges = 4;   // hinge-angle gradients supported by the adjoint

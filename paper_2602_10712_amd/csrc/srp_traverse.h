@@ -297,22 +297,23 @@ __device__ __forceinline__ uint64_t live_tiles(const TraceArgs& a, const float4*
     return wave_ballot(live);
 }
 
-// Direction j and workgroup index blk (within the direction) of hardware workgroup b of a
-// single-scene launch.  Direction-major: b = j * blocks_per_dir + blk.  XCD-major: the hardware
-// places workgroup b on accelerator complex (XCD) b % 8, and direction j is traced by XCD j % 8
-// alone, its workgroups consecutive in that XCD's share of the grid; the grid is padded to whole
-// groups of 8 directions and a padding workgroup gets false.
-__device__ __forceinline__ bool block_unit(const TraceArgs& a, int64_t b, int64_t& j, int32_t& blk)
+// Unit u (a direction, or a (design, direction) pair of a batched trace) and workgroup index blk
+// (within the unit) of hardware workgroup b, for n_units units.  Direction-major:
+// b = u * blocks_per_dir + blk.  XCD-major: the hardware places workgroup b on accelerator
+// complex (XCD) b % 8, and unit u is traced by XCD u % 8 alone, its workgroups consecutive in that
+// XCD's share of the grid; the grid is padded to whole groups of 8 units and a padding workgroup
+// gets false.
+__device__ __forceinline__ bool block_unit(const TraceArgs& a, int64_t n_units, int64_t b, int64_t& u, int32_t& blk)
 {
     if (!a.xcd_major) {
-        j = b / a.blocks_per_dir;
+        u = b / a.blocks_per_dir;
         blk = static_cast<int32_t>(b % a.blocks_per_dir);
         return true;
     }
     const int64_t k = b / kXcds;
-    j = b % kXcds + kXcds * (k / a.blocks_per_dir);
+    u = b % kXcds + kXcds * (k / a.blocks_per_dir);
     blk = static_cast<int32_t>(k % a.blocks_per_dir);
-    return j < a.D;
+    return u < n_units;
 }
 
 // Pixel of lane `lane` in wave tile `tile`: 8 x 8 pixel tiles in row-major order (trace mode) or

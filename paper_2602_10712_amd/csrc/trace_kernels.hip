@@ -71,73 +71,43 @@ __global__ void k_pack_mat(const float* __restrict__ rs, const float* __restrict
     mat[p] = make_float4(a, b, q, 0.0f);
 }
 
-// BATCH: the launch covers n_scenes designs; hardware block b runs on XCD b % 8, so design s is
-// handled entirely by XCD s % 8 (its BVH stays in that XCD's L2) in design-major order.
-template <bool RECORDS, bool BATCH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_trace(TraceArgs a)
+// LDS of one trace workgroup.
+struct TraceLds {
+    int stack[kWaves][kStackDepth];    // wave-uniform stacks of the coherent walk
+    int lane[kWaves][kLaneStack][64];  // per-lane stacks of the independent walk
+    float red[kWaves][6];              // per-wave force and torque sums
+    float4 rect[kCullBoxes];           // pixel rectangles of the culling boxes
+    uint64_t live;                     // workgroup tiles that may contain a hit
+};
+
+// One workgroup's share of direction j: wave tiles blk * tiles_per_wave * kWaves onward of the
+// direction's grid, traced against one scene and reduced into partials row `unit` (scene * D + j).
+// Every thread of the workgroup calls it (it holds barriers).
+template <bool RECORDS>
+__device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNode* __restrict__ nodes,
+                                                const TriRec* __restrict__ tris, const float4* __restrict__ mat,
+                                                const float com[3], float eps, uint32_t design, int64_t j,
+                                                int64_t unit, int32_t blk, TraceLds& L)
 {
-    __shared__ int s_stack[kWaves][kStackDepth];
-    __shared__ int s_lane[kWaves][kLaneStack][64];
-    __shared__ float s_red[kWaves][6];
-    __shared__ float4 s_rect[kCullBoxes];
-    __shared__ uint64_t s_live;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    int64_t unit;  // (scene *) D + direction
-    int32_t blk;
-    const BvhNode* __restrict__ nodes;
-    const TriRec* __restrict__ tris;
-    const float4* __restrict__ mat;
-    float com[3], eps;
-    uint32_t design = a.design_index;
-    int64_t j;
-    if (BATCH) {
-        const int64_t per_design = a.D * a.blocks_per_dir;
-        const int64_t b = blockIdx.x;
-        const int64_t xcd = b & 7, k = b >> 3;
-        const int64_t s = xcd + 8 * (k / per_design);
-        if (s >= a.n_scenes) return;
-        const int64_t r = k % per_design;
-        j = r / a.blocks_per_dir;
-        blk = static_cast<int32_t>(r % a.blocks_per_dir);
-        unit = s * a.D + j;
-        const SceneDesc sd = a.scenes[s];
-        nodes = sd.nodes;
-        tris = sd.tris;
-        mat = sd.mat;
-        com[0] = sd.com[0];
-        com[1] = sd.com[1];
-        com[2] = sd.com[2];
-        eps = sd.eps;
-        design += static_cast<uint32_t>(s);
-    } else {
-        if (!block_unit(a, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
-        unit = j;
-        nodes = a.nodes;
-        tris = a.tris;
-        mat = a.mat;
-        com[0] = a.com[0];
-        com[1] = a.com[1];
-        com[2] = a.com[2];
-        eps = a.eps;
-    }
     const DevFrame fr = a.frames[unit];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
-    int* stack = s_stack[wave];
-    int* lstack = &s_lane[wave][0][lane];
+    int* stack = L.stack[wave];
+    int* lstack = &L.lane[wave][0][lane];
 
     // the workgroup's tiles that may contain a hit (grid mode; records mode traces every pixel)
     uint64_t live = ~0ull;
     if (!RECORDS && a.cull) {
-        if (threadIdx.x < kCullBoxes) s_rect[threadIdx.x] = cull_rect(nodes, fr, threadIdx.x);
+        if (threadIdx.x < kCullBoxes) L.rect[threadIdx.x] = cull_rect(nodes, fr, threadIdx.x);
         __syncthreads();
         if (wave == 0) {
-            const uint64_t m = live_tiles(a, s_rect, static_cast<int64_t>(blk) * a.tiles_per_wave * kWaves,
+            const uint64_t m = live_tiles(a, L.rect, static_cast<int64_t>(blk) * a.tiles_per_wave * kWaves,
                                           a.tiles_per_wave * kWaves);
-            if (lane == 0) s_live = m;
+            if (lane == 0) L.live = m;
         }
         __syncthreads();
-        live = s_live;
+        live = L.live;
     }
 
     float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
@@ -206,14 +176,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     for (int c = 0; c < 6; ++c) acc[c] = wave_sum(acc[c]);
     if (lane == 0) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) s_red[wave][c] = acc[c];
+        for (int c = 0; c < 6; ++c) L.red[wave][c] = acc[c];
     }
     __syncthreads();
     if (threadIdx.x < 6) {
         double s = 0.0;
-        for (int q = 0; q < kWaves; ++q) s += static_cast<double>(s_red[q][threadIdx.x]);
+        for (int q = 0; q < kWaves; ++q) s += static_cast<double>(L.red[q][threadIdx.x]);
         a.partials[(unit * a.blocks_per_dir + blk) * 6 + threadIdx.x] = s;
     }
+}
+
+// Single scene: one workgroup per (direction, blk), placed by block_unit.
+template <bool RECORDS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_trace(TraceArgs a)
+{
+    __shared__ TraceLds L;
+    int64_t j;
+    int32_t blk;
+    if (!block_unit(a, a.D, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
+    trace_workgroup<RECORDS>(a, a.nodes, a.tris, a.mat, a.com, a.eps, a.design_index, j, j, blk, L);
+}
+
+// Batched designs: the n_scenes x D (design, direction) units in design-major order, placed like
+// the directions of a single scene (unit u on XCD u % 8), so all XCDs work through the designs
+// together and a design's directions are spread evenly over them.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_trace_batch(TraceArgs a)
+{
+    __shared__ TraceLds L;
+    int64_t u;
+    int32_t blk;
+    if (!block_unit(a, a.n_scenes * a.D, blockIdx.x, u, blk)) return;  // whole workgroup: grid padding
+    const int64_t s = u / a.D, j = u % a.D;
+    const SceneDesc sd = a.scenes[s];
+    trace_workgroup<false>(a, (const BvhNode*)sd.nodes, (const TriRec*)sd.tris, (const float4*)sd.mat, sd.com, sd.eps,
+                           a.design_index + static_cast<uint32_t>(s), j, u, blk, L);
 }
 
 __global__ void k_reduce(const double* __restrict__ partials, int64_t D, int32_t bpd, double* __restrict__ force,
@@ -262,24 +258,22 @@ hipError_t launch_pack_materials(const float* rho_s, const float* rho_d, const f
 
 hipError_t launch_trace(const TraceArgs& a, bool records, hipStream_t stream)
 {
-    const int64_t blocks = single_scene_blocks(a);
+    const int64_t blocks = grid_blocks(a, a.D);
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (records)
-        hipLaunchKernelGGL((k_trace<true, false>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream,
-                           a);
+        hipLaunchKernelGGL((k_trace<true>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
     else
-        hipLaunchKernelGGL((k_trace<false, false>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream,
-                           a);
+        hipLaunchKernelGGL((k_trace<false>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
     return hipGetLastError();
 }
 
 hipError_t launch_trace_batch(const TraceArgs& a, hipStream_t stream)
 {
-    const int64_t blocks = static_cast<int64_t>(a.scene_slots) * a.D * a.blocks_per_dir;
+    const int64_t blocks = grid_blocks(a, static_cast<int64_t>(a.n_scenes) * a.D);
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_trace<false, true>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
+    hipLaunchKernelGGL(k_trace_batch, dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ def generate_samples(mesh, designs, sun_per_design, params: B.TraceParams, flux=
         rd = th[3 + 2 * group].astype(np.float32)
         scene.set_design(rs, rd, hinge_angles=th[:2])
         p = B.TraceParams(params.nu, params.nv, params.bounces, params.jitter, flux, params.seed,
-                          0, d, params.frame_mode)
+                          0, d, params.frame_mode, params.tiles_per_wave)
         F, _ = scene.trace(sun_per_design[d], p)
         out[d] = F.cpu().numpy()
     scene.close()

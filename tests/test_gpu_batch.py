@@ -99,3 +99,45 @@ def test_full_size_batch_sampled():
         assert e <= 1e-4
     for sc in scenes:
         sc.close()
+
+
+def test_tiles_per_wave_and_autotuner():
+    """tiles_per_wave changes only the launch shape: forces agree to FP32 summation order (single
+    scene and batched, including the direction-major order of fewer than 8 units); the autotuner
+    returns one of its candidates 8..16 with a positive time for each."""
+    import paper_2602_10712_amd as p
+    scenes = []
+    for k, n in enumerate([3000, 12000, 30000]):
+        m = si.meo_variant(n)
+        th = si.random_designs(1, seed=300 + k)[0]
+        rs, rd = si.materials(m.n_tris, seed=400 + k)
+        sc = p.Scene.from_mesh(m)
+        sc.set_design(rs, rd, hinge_angles=th[:2])
+        scenes.append(sc)
+    dev = torch.device("cuda")
+    for D in (3, 12):
+        sun = torch.as_tensor(si.fibonacci_dirs(D), dtype=torch.float64, device=dev).contiguous()
+        out = []
+        for tpw in (0, 1, 7, 16):
+            prm = p.TraceParams(nu=160, nv=160, bounces=3, seed=9, tiles_per_wave=tpw)
+            # design s of a batch draws with design index s: trace design 1 alone with index 1
+            F, T = scenes[1].trace(sun.cpu().numpy(), p.TraceParams(nu=160, nv=160, bounces=3, seed=9,
+                                                                    design_index=1, tiles_per_wave=tpw))
+            Fb = torch.empty((3, D, 3), dtype=torch.float64, device=dev)
+            p.srp_batch_trace(scenes, sun, prm, Fb)
+            torch.cuda.synchronize()
+            out.append((F.cpu().numpy(), Fb.cpu().numpy()))
+        for F, Fb in out[1:]:
+            assert rel_l2(F, out[0][0]) <= 1e-6
+            assert rel_l2(Fb, out[0][1]) <= 1e-6
+        assert rel_l2(out[0][1][1], out[0][0]) <= 1e-6  # design 1 of the batch vs its own trace
+    with pytest.raises(p.SRPError):
+        scenes[0].trace(si.fibonacci_dirs(2), p.TraceParams(nu=16, nv=16, tiles_per_wave=17))
+    sun = torch.as_tensor(si.fibonacci_dirs(8), dtype=torch.float64, device=dev).contiguous()
+    prm = p.TraceParams(nu=128, nv=128, bounces=3, seed=9)
+    for group in (scenes, scenes[:1]):
+        best, ms = p.srp_autotune_tiles_per_wave(group, sun, prm)
+        assert 8 <= best <= 16 and sorted(ms) == list(range(8, 17))
+        assert all(v > 0.0 for v in ms.values()) and ms[best] == min(ms.values())
+    for sc in scenes:
+        sc.close()
