@@ -10,6 +10,7 @@ Prints ONE JSON line (see the design notes for the field definitions):
   fwd_adjoint      forward + adjoint replay Mrays/s at 512 x 512 rays per direction
   surrogate        fused MLP surrogate evals/s on 1M queries, with its MFMA roofline fraction
   batched          one launch over 256 design variants (2k-50k tris) x 256 dirs x 512^2 rays
+  orbit            one design-gradient iteration through a day of RK4 orbit (2881 directions, 512^2)
   roofline         dominant kernel (k_trace): algorithmic bytes per launch / mean launch time
   cpu_baseline     the FP64 oracle on a bounded sample of the same workload, host cores
 """
@@ -87,6 +88,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-orbit", action="store_true")
     ap.add_argument("--batch-designs", type=int, default=256)
     ap.add_argument("--batch-dirs", type=int, default=256)
     ap.add_argument("--batch-grid", type=int, default=512)
@@ -218,6 +220,34 @@ def main():
         except Exception as e:
             log(f"adjoint roofline stats unavailable: {e!r}")
         log(f"forward+adjoint: {ms_adj:.2f} ms/step, {fwd_adj['value']:.1f} Mrays/s")
+
+    # ---- design gradient through the orbit: 1 day of 60 s RK4 steps, 2881 stage-time sun directions ----
+    orbit = None
+    if not args.no_orbit:
+        sc_o = si.meo_orbit(n_steps=1440, dt=60.0)
+        po = p.TraceParams(nu=args.adjoint_grid, nv=args.adjoint_grid, bounces=args.bounces, jitter=1, seed=5)
+        prob = p.DesignProblem(mesh, sc_o, po, si.DESIGN_LO, si.DESIGN_HI)
+        theta_t = np.array([0.3, -0.2, 0.35, 0.1, 0.2, 0.3, 0.05, 0.4])
+        prob.r_target = prob.final_state(theta_t)[0][:3]
+        theta = np.array([0.0, 0.0, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25])
+        # each iteration moves the hinges, as an optimiser step does (BVH refit and upload included)
+        step_h = np.array([1e-3, -1e-3, 0, 0, 0, 0, 0, 0])
+        for i in range(max(args.warmup, 1)):
+            prob.loss_and_grad(theta - step_h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            prob.loss_and_grad(theta + i * step_h)
+        torch.cuda.synchronize()
+        ms_o = (time.perf_counter() - t0) * 1e3 / args.steps
+        n_st = prob.n_stage
+        orbit = {"ms_per_iteration": round(ms_o, 2), "stage_directions": n_st,
+                 "rays_per_pass": n_st * args.adjoint_grid ** 2,
+                 "workload": f"one design-gradient iteration: trace {n_st} stage-time sun directions x "
+                             f"{args.adjoint_grid}x{args.adjoint_grid} rays, RK4 over 1440 x 60 s steps, discrete "
+                             "adjoint with 24 checkpoints, ray adjoint, group sums (host wall clock)"}
+        log(f"orbit: {ms_o:.1f} ms per design-gradient iteration ({n_st} directions)")
+        prob.close()
 
     # ---- surrogate inference: fused BF16-MFMA MLP 11 -> 4 x 256 (SiLU) -> 3 on 1M queries ---------
     surrogate = None
@@ -351,7 +381,7 @@ def main():
                    "tris": mesh.n_tris, "dirs": D, "grid": args.grid, "bounces": args.bounces,
                    "bvh_nodes": info["n_nodes"], "bvh_build_s": round(build_s, 4)},
         "roofline": roofline, "cpu_baseline": cpu, "fwd_adjoint": fwd_adj,
-        "surrogate": surrogate, "batched": batched,
+        "surrogate": surrogate, "batched": batched, "orbit": orbit,
     }
     print(json.dumps(out), flush=True)
 
