@@ -123,8 +123,8 @@ srp_status srp_frames(srp_scene scene, const double* sun_dirs, int64_t D, int32_
 /* Forward trace.  sun_dirs device double [D][3] (unit, toward the Sun), frames device double
  * [D][12] when params->frame_mode == 1 (else ignored, may be NULL); force device double [D][3]
  * and torque device double [D][3] (torque may be NULL) are overwritten with the per-direction
- * sums.  The sum is deterministic: FP32 per ray and per wavefront, FP64 per workgroup and a
- * fixed-order FP64 sum per direction. */
+ * sums.  The sum is deterministic for given arguments: FP32 per ray and per wavefront, FP64 per
+ * workgroup and a fixed-order FP64 sum per direction. */
 srp_status srp_trace(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
                      const double* frames, double* force, double* torque, void* stream);
 
@@ -171,8 +171,9 @@ srp_status srp_scene_ray_stats(srp_scene scene, const double* sun_dirs, int64_t 
  * 0).  force, torque: device double [S][D][3] (torque may be NULL).  The (design, direction) units
  * are traced design-major, each direction of a design on one XCD and a design's directions spread
  * over all of them, so the XCDs work through the designs together.  Workspace belongs to
- * scenes[0]; all scenes must be on the current device.  The design table is uploaded on `stream` from pinned staging; a
- * call waits for the previous batch upload led by the same scene before reusing the staging. */
+ * scenes[0]; all scenes must be on the current device.  The design table is uploaded on `stream`
+ * from pinned staging; a call waits for the previous batch upload led by the same scene before
+ * reusing the staging. */
 srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
                            const srp_trace_params* params, double* force, double* torque, void* stream);
 
