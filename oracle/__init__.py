@@ -73,6 +73,10 @@ def lib():
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, P, ctypes.c_int64, P, P, P]
         L.oracle_trace_frozen.restype = ctypes.c_int
+        L.oracle_surface_estimate.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64,
+                                              ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
+                                              ctypes.c_int64, ctypes.c_uint32, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_surface_estimate.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -220,3 +224,49 @@ def trace_frozen(verts, verts0, tris, rho_s, rho_d, sun_dirs, ref_hits, frames_i
     if st != 0:
         raise ValueError(f"oracle_trace_frozen failed ({st})")
     return F, T
+
+
+class SurfaceResult:
+    def __init__(self, force, torque, facet=None, hits=None, lit=None, degen=None, sample_force=None):
+        self.force = force
+        self.torque = torque
+        self.facet = facet
+        self.hits = hits
+        self.lit = lit
+        self.degen = degen
+        self.sample_force = sample_force
+
+
+def surface_estimate(verts, tris, rho_s, rho_d, sun_dirs, *, n_samples: int, bounces: int, flux: float = 1361.0,
+                     seed: int = 0, dir_index_base: int = 0, design_index: int = 0, p_spec=None, com=None,
+                     records: bool = False, threads: int | None = None) -> SurfaceResult:
+    """FP64 surface-sampling estimate (area-sampled points, path-traced gathering with next-event
+    estimation toward the Sun); see srp_oracle.c for the definition.  force/torque: sample means."""
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    rs = np.ascontiguousarray(rho_s, dtype=np.float32)
+    rd = np.ascontiguousarray(rho_d, dtype=np.float32)
+    ps = None if p_spec is None else np.ascontiguousarray(p_spec, dtype=np.float32)
+    c = None if com is None else np.ascontiguousarray(com, dtype=np.float64)
+    sun = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
+    D = len(sun)
+    force = np.zeros((D, 3))
+    torque = np.zeros((D, 3))
+    fa = hi = li = dg = sf = None
+    if records:
+        fa = np.zeros((D, n_samples), dtype=np.int32)
+        hi = np.zeros((D, n_samples, max(bounces - 1, 1)), dtype=np.int32)
+        li = np.zeros((D, n_samples), dtype=np.int32)
+        dg = np.zeros((D, n_samples), dtype=np.uint8)
+        sf = np.zeros((D, n_samples, 3))
+    if threads is None:
+        threads = default_threads()
+    st = lib().oracle_surface_estimate(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd), _ptr(ps),
+                                       _ptr(c), _ptr(sun), D, int(n_samples), int(bounces), float(flux), int(seed),
+                                       int(dir_index_base), int(design_index), _ptr(force), _ptr(torque), _ptr(fa),
+                                       _ptr(hi), _ptr(li), _ptr(dg), _ptr(sf), int(threads))
+    if st != 0:
+        raise ValueError(f"oracle_surface_estimate failed ({st})")
+    if records and bounces == 1:
+        hi = hi[:, :, :0]
+    return SurfaceResult(force, torque, fa, hi, li, dg, sf)

@@ -1001,3 +1001,335 @@ int oracle_trace_frozen(const double* verts, const double* verts0, int64_t n_ver
     scene_free(&S0);
     return ORC_OK;
 }
+
+/* ========================================================================================== */
+/* Surface-sampling estimator (paper Sec. 3.2, "Estimation", and its equation for F).          */
+/*                                                                                            */
+/* Every sample picks a facet with probability proportional to its area and a uniform point x */
+/* on it (square-root barycentric mapping), gathers the light arriving at x by path tracing     */
+/* with next-event estimation toward the Sun at every path vertex, and converts it to momentum  */
+/* at x with one sampled outgoing event: with probability p_s a mirror reflection of weight     */
+/* rho_s/p_s, else a cosine-distributed direction o of weight rho_d/(1 - p_s).  The sample's    */
+/* force is the total area A times the force density at x; the estimate is the sample mean.    */
+/*                                                                                            */
+/* Light reaching x (force units per area, propagation p, deposit W (p - R(p))):               */
+/*   direct     W = Phi (n.s)/c if n.s > 0 and no sun-facing facet blocks the ray x -> s;       */
+/*   gathered   one cosine-distributed direction w1 about n (pdf cos/pi) leads to the closest   */
+/*              front-facing facet v1; the radiance it sends to x is the Lambertian share of    */
+/*              its own sunlight, rho_d/pi Phi (n1.s)+ (unblocked), plus what it reflects of    */
+/*              light from further vertices v2, ... (event sampled at each vertex: mirror       */
+/*              continuation with weight rho_s/p_s or cosine continuation with rho_d/(1-p_s)),  */
+/*              so W = pi/c * radiance and p = -w1.  Light reaching x has met at most B - 1     */
+/*              surfaces before x: vertices v1 .. v_{B-1}.                                      */
+/* Sunlight whose first reflection is an ideal mirror is not gathered (a delta light seen       */
+/* through a delta reflection has zero probability of being sampled); everything else has the  */
+/* same expectation as the ray-grid estimator with `bounces` = B.                              */
+/*                                                                                            */
+/* Random numbers: Philox counter (sample, global direction, stage, design); stage 0: facet,   */
+/* two barycentric uniforms, the event at x; stage 1: the outgoing direction at x (2) and the   */
+/* first gathering direction (2); stage k + 1: the event at v_k and its continuation direction. */
+/* ========================================================================================== */
+
+/* Sunlight reaching o along -s is blocked by any facet other than `skip` whose outward side
+ * faces the Sun (n.s > 0) and that the ray o + t s (t > 0) crosses.  *deg flags a ray passing
+ * within DEG_EDGE L of such a facet's edge, or crossing one nearly edge-on. */
+static int sun_blocked(const scene_t* S, const double o[3], const double s[3], int64_t skip, int* deg)
+{
+    const double L = S->L;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    int blocked = 0;
+    for (int64_t f = 0; f < S->n_tris; ++f) {
+        if (f == skip) continue;
+        const double cosn = dot3(s, S->nrm + 3 * f);
+        if (!(cosn > 0.0)) continue;
+        /* projection of the facet on the plane through o normal to s */
+        double q[3][3], along[3];
+        for (int c = 0; c < 3; ++c) {
+            double rel[3];
+            sub3(S->pv + 9 * f + 3 * c, o, rel);
+            along[c] = dot3(rel, s);
+            for (int a = 0; a < 3; ++a) q[c][a] = rel[a] - along[c] * s[a];
+        }
+        const double amax = fmax(along[0], fmax(along[1], along[2]));
+        if (amax < -DEG_NEAR * L) continue; /* entirely behind the origin */
+        /* signed areas of the projected point against the three edges */
+        double cr1[3], cr2[3], cr3[3], m0[3], m1[3], m2[3], e0[3], e1v[3], e2v[3];
+        sub3(zero, q[0], m0); sub3(zero, q[1], m1); sub3(zero, q[2], m2);
+        sub3(q[1], q[0], e0); sub3(q[2], q[1], e1v); sub3(q[0], q[2], e2v);
+        cross3(e0, m0, cr1); cross3(e1v, m1, cr2); cross3(e2v, m2, cr3);
+        const double s1 = dot3(cr1, s), s2 = dot3(cr2, s), s3 = dot3(cr3, s);
+        const int inside = (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
+        const double emin = fmin(point_segment_dist(zero, q[0], q[1]),
+                                 fmin(point_segment_dist(zero, q[1], q[2]), point_segment_dist(zero, q[2], q[0])));
+        if (emin < DEG_EDGE * L) *deg = 1;
+        if (cosn < DEG_GRAZE && (inside || emin < DEG_EDGE * L)) *deg = 1;
+        if (!inside) continue;
+        /* distance along s to the facet's plane */
+        const double tplane = dot3(S->nrm + 3 * f, (double[3]){S->pv[9 * f] - o[0], S->pv[9 * f + 1] - o[1],
+                                                             S->pv[9 * f + 2] - o[2]}) / cosn;
+        if (fabs(tplane) < DEG_NEAR * L) *deg = 1;
+        if (tplane > 0.0) blocked = 1;
+    }
+    return blocked;
+}
+
+/* cosine-distributed direction about the unit normal n from two uniforms (Malley's method) */
+static void cosine_dir(const double n[3], double u1, double u2, double out[3])
+{
+    double rad = sqrt(u1);
+    double phi = 2.0 * M_PI * u2;
+    double lx = rad * cos(phi), ly = rad * sin(phi), lz = sqrt(fmax(0.0, 1.0 - u1));
+    double t1[3], t2[3];
+    oracle_basis(n, t1, t2);
+    for (int c = 0; c < 3; ++c) out[c] = lx * t1[c] + ly * t2[c] + lz * n[c];
+}
+
+typedef struct {
+    uint64_t seed;
+    uint32_t design_index;
+    int32_t bounces;
+    double flux;
+    const double* cum; /* [T] cumulative facet areas, facet order */
+    double area;       /* total area */
+} gather_params_t;
+
+/* One sample of the surface-sampling estimator for direction `sun` (global index dir_global).
+ * Returns the sample's force and torque (area already applied) and, optionally, its record:
+ * facet, gathered vertices (B - 1 facets, -1 = none), sunlit flags (bit 0: x, bit k: v_k) and
+ * the degeneracy flag. */
+static void gather_sample(const scene_t* S, const gather_params_t* G, const double sun[3], uint32_t dir_global,
+                          uint32_t sample, double F[3], double T[3], int32_t* rec_facet, int32_t* rec_hits,
+                          int32_t* rec_lit, uint8_t* rec_deg)
+{
+    const int32_t B = G->bounces;
+    const double eps = 1e-5 * S->L;
+    int deg = 0;
+    double u0[4], u1[4];
+    draw4(G->seed, sample, dir_global, 0u, G->design_index, u0);
+    draw4(G->seed, sample, dir_global, 1u, G->design_index, u1);
+    /* facet by area: the first f with u A < cum[f] */
+    const double target = u0[0] * G->area;
+    int64_t lo = 0, hi = S->n_tris - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (target < G->cum[mid]) hi = mid; else lo = mid + 1;
+    }
+    const int64_t f = lo;
+    if (fabs(target - G->cum[f]) < 1e-12 * G->area || (f > 0 && fabs(target - G->cum[f - 1]) < 1e-12 * G->area))
+        deg = 1;
+    /* uniform point: x = v0 + sqrt(u1)(1 - u2) e1 + sqrt(u1) u2 e2 */
+    const double sq = sqrt(u0[1]);
+    const double b1 = sq * (1.0 - u0[2]), b2 = sq * u0[2];
+    double x[3];
+    for (int c = 0; c < 3; ++c) x[c] = S->v0[3 * f + c] + b1 * S->e1[3 * f + c] + b2 * S->e2[3 * f + c];
+    const double* n = S->nrm + 3 * f;
+    const double rs = (double)S->rho_s[f], rd = (double)S->rho_d[f];
+    const float ps = S->p_spec[f];
+    /* the outgoing event at x */
+    const int mirror = (float)u0[3] < ps;
+    const double kout = mirror ? rs / (double)ps : (rd > 0.0 ? rd / (1.0 - (double)ps) : 0.0);
+    double odir[3];
+    cosine_dir(n, u1[0], u1[1], odir);
+    double s[3] = {sun[0], sun[1], sun[2]};
+    double dep[3] = {0.0, 0.0, 0.0};
+    int32_t lit = 0;
+    double o[3];
+    for (int c = 0; c < 3; ++c) o[c] = x[c] + eps * n[c];
+    /* direct sunlight at x */
+    const double cs = dot3(n, s);
+    if (cs > 0.0 && !sun_blocked(S, o, s, f, &deg)) {
+        lit |= 1;
+        const double W = G->flux * cs / kSpeedOfLight;
+        double p[3] = {-s[0], -s[1], -s[2]};
+        double r[3];
+        const double pn = dot3(p, n);
+        for (int c = 0; c < 3; ++c) r[c] = p[c] - 2.0 * pn * n[c];
+        for (int c = 0; c < 3; ++c) dep[c] += W * (p[c] - kout * (mirror ? r[c] : odir[c]));
+    }
+    if (rec_hits)
+        for (int k = 0; k < B - 1; ++k) rec_hits[k] = -1;
+    if (B >= 2) {
+        /* gathered light: vertices v1 .. v_{B-1} */
+        double w[3];
+        cosine_dir(n, u1[2], u1[3], w);
+        double p1[3] = {-w[0], -w[1], -w[2]};
+        double radiance = 0.0; /* pi x radiance toward x, in units of Phi */
+        double beta = 1.0;
+        double ro[3] = {o[0], o[1], o[2]}, rdir[3] = {w[0], w[1], w[2]};
+        int64_t skip = f;
+        for (int k = 1; k <= B - 1; ++k) {
+            double t;
+            int64_t g = closest_hit(S, ro, rdir, skip, &t);
+            if (!deg) deg = segment_degenerate(S, ro, rdir, skip, g, t);
+            if (g < 0) break;
+            if (rec_hits) rec_hits[k - 1] = (int32_t)g;
+            const double* ng = S->nrm + 3 * g;
+            double y[3], oy[3];
+            for (int c = 0; c < 3; ++c) {
+                y[c] = ro[c] + t * rdir[c];
+                oy[c] = y[c] + eps * ng[c];
+            }
+            const double rsg = (double)S->rho_s[g], rdg = (double)S->rho_d[g];
+            const double cg = dot3(ng, s);
+            if (rdg > 0.0 && cg > 0.0 && !sun_blocked(S, oy, s, g, &deg)) {
+                lit |= 1 << k;
+                radiance += beta * rdg * cg;
+            }
+            if (k == B - 1) break;
+            /* continue from v_k: event, weight and the next gathering direction */
+            double ev[4];
+            draw4(G->seed, sample, dir_global, (uint32_t)(k + 1), G->design_index, ev);
+            const float psg = S->p_spec[g];
+            double nd[3];
+            if ((float)ev[0] < psg) {
+                /* light leaving v_k toward the previous vertex travels along -rdir; its mirror
+                   source direction is the reflection of rdir about the normal, reversed */
+                const double dn = dot3(rdir, ng);
+                for (int c = 0; c < 3; ++c) nd[c] = rdir[c] - 2.0 * dn * ng[c];
+                beta *= rsg / (double)psg;
+            } else {
+                cosine_dir(ng, ev[1], ev[2], nd);
+                beta *= rdg > 0.0 ? rdg / (1.0 - (double)psg) : 0.0;
+            }
+            if (beta == 0.0) break;
+            for (int c = 0; c < 3; ++c) {
+                ro[c] = oy[c];
+                rdir[c] = nd[c];
+            }
+            skip = g;
+        }
+        if (radiance > 0.0) {
+            const double W = G->flux * radiance / kSpeedOfLight;
+            double r[3];
+            const double pn = dot3(p1, n);
+            for (int c = 0; c < 3; ++c) r[c] = p1[c] - 2.0 * pn * n[c];
+            for (int c = 0; c < 3; ++c) dep[c] += W * (p1[c] - kout * (mirror ? r[c] : odir[c]));
+        }
+    }
+    double lever[3];
+    for (int c = 0; c < 3; ++c) {
+        F[c] = G->area * dep[c];
+        lever[c] = x[c] - S->com[c];
+    }
+    cross3(lever, F, T);
+    if (rec_facet) *rec_facet = (int32_t)f;
+    if (rec_lit) *rec_lit = lit;
+    if (rec_deg) *rec_deg = (uint8_t)deg;
+}
+
+typedef struct {
+    const scene_t* S;
+    const gather_params_t* G;
+    const double* sun_dirs;
+    int64_t n_dirs, n_samples, dir_index_base;
+    double* part_f; /* [D][chunks][3] */
+    double* part_t;
+    int32_t *rec_facet, *rec_hits, *rec_lit;
+    uint8_t* rec_deg;
+    double* sample_force;
+    int64_t next;
+    pthread_mutex_t lock;
+} gather_job_t;
+
+static void* gather_worker(void* argp)
+{
+    gather_job_t* J = (gather_job_t*)argp;
+    const int64_t per_dir = (J->n_samples + CHUNK - 1) / CHUNK;
+    const int64_t total = per_dir * J->n_dirs;
+    const int32_t B = J->G->bounces;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t item = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (item >= total) break;
+        const int64_t j = item / per_dir;
+        const int64_t s0 = (item % per_dir) * CHUNK;
+        const int64_t s1 = s0 + CHUNK < J->n_samples ? s0 + CHUNK : J->n_samples;
+        double* pf = J->part_f + 3 * item;
+        double* pt = J->part_t + 3 * item;
+        for (int64_t i = s0; i < s1; ++i) {
+            const int64_t rec = j * J->n_samples + i;
+            double F[3], T[3];
+            gather_sample(J->S, J->G, J->sun_dirs + 3 * j, (uint32_t)(J->dir_index_base + j), (uint32_t)i, F, T,
+                          J->rec_facet ? J->rec_facet + rec : NULL,
+                          J->rec_hits && B > 1 ? J->rec_hits + rec * (B - 1) : NULL,
+                          J->rec_lit ? J->rec_lit + rec : NULL, J->rec_deg ? J->rec_deg + rec : NULL);
+            for (int c = 0; c < 3; ++c) {
+                pf[c] += F[c];
+                pt[c] += T[c];
+            }
+            if (J->sample_force)
+                for (int c = 0; c < 3; ++c) J->sample_force[3 * rec + c] = F[c];
+        }
+    }
+    return NULL;
+}
+
+/*
+ * oracle_surface_estimate: surface-sampling estimate of the force and torque for n_dirs sun
+ * directions, n_samples samples each (sample index = Philox counter word 0).
+ *   verts, tris, rho_s, rho_d, p_spec, com, sun_dirs as for oracle_trace;
+ *   force, torque [n_dirs][3]: sample means (N, N m);
+ *   optional per-sample records [n_dirs][n_samples] (hits: [.. ][bounces - 1]) and forces [..][3].
+ * Samples are summed in chunks of 64, chunk sums in order: independent of the thread count.
+ */
+int oracle_surface_estimate(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                            const float* rho_s, const float* rho_d, const float* p_spec, const double* com,
+                            const double* sun_dirs, int64_t n_dirs, int64_t n_samples, int32_t bounces, double flux,
+                            uint64_t seed, int64_t dir_index_base, uint32_t design_index, double* force,
+                            double* torque, int32_t* rec_facet, int32_t* rec_hits, int32_t* rec_lit, uint8_t* rec_deg,
+                            double* sample_force, int32_t n_threads)
+{
+    if (!verts || n_verts <= 0 || !tris || n_tris <= 0 || !rho_s || !rho_d || !sun_dirs || n_dirs < 0 ||
+        n_samples < 1 || bounces < 1 || !force || !torque)
+        return ORC_EINVAL;
+    for (int64_t f = 0; f < n_tris; ++f)
+        if (!(rho_s[f] >= 0.0f) || !(rho_d[f] >= 0.0f) || rho_s[f] + rho_d[f] > 1.0f) return ORC_EINVAL;
+    scene_t S;
+    int st = scene_init(&S, verts, n_verts, tris, n_tris, rho_s, rho_d, p_spec, com);
+    if (st != ORC_OK) {
+        scene_free(&S);
+        return st;
+    }
+    double* cum = malloc(sizeof(double) * n_tris);
+    if (!cum) { scene_free(&S); return ORC_ENOMEM; }
+    double acc = 0.0;
+    for (int64_t f = 0; f < n_tris; ++f) {
+        double cr[3];
+        cross3(S.e1 + 3 * f, S.e2 + 3 * f, cr);
+        acc += 0.5 * sqrt(dot3(cr, cr));
+        cum[f] = acc;
+    }
+    gather_params_t G = {seed, design_index, bounces, flux, cum, acc};
+    if (n_threads < 1) n_threads = 1;
+    gather_job_t J;
+    memset(&J, 0, sizeof(J));
+    J.S = &S; J.G = &G; J.sun_dirs = sun_dirs; J.n_dirs = n_dirs; J.n_samples = n_samples;
+    J.dir_index_base = dir_index_base; J.rec_facet = rec_facet; J.rec_hits = rec_hits; J.rec_lit = rec_lit;
+    J.rec_deg = rec_deg; J.sample_force = sample_force;
+    const int64_t chunks = (n_samples + CHUNK - 1) / CHUNK;
+    J.part_f = calloc((size_t)3 * chunks * (n_dirs > 0 ? n_dirs : 1), sizeof(double));
+    J.part_t = calloc((size_t)3 * chunks * (n_dirs > 0 ? n_dirs : 1), sizeof(double));
+    if (!J.part_f || !J.part_t) {
+        free(J.part_f); free(J.part_t); free(cum); scene_free(&S);
+        return ORC_ENOMEM;
+    }
+    pthread_mutex_init(&J.lock, NULL);
+    pthread_t* th = malloc(sizeof(pthread_t) * n_threads);
+    for (int32_t t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, gather_worker, &J);
+    for (int32_t t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    for (int64_t j = 0; j < n_dirs; ++j)
+        for (int c = 0; c < 3; ++c) {
+            double sf = 0.0, stq = 0.0;
+            for (int64_t q = 0; q < chunks; ++q) {
+                sf += J.part_f[3 * (j * chunks + q) + c];
+                stq += J.part_t[3 * (j * chunks + q) + c];
+            }
+            force[3 * j + c] = sf / (double)n_samples;
+            torque[3 * j + c] = stq / (double)n_samples;
+        }
+    pthread_mutex_destroy(&J.lock);
+    free(th); free(J.part_f); free(J.part_t); free(cum);
+    scene_free(&S);
+    return ORC_OK;
+}
