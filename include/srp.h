@@ -177,6 +177,26 @@ srp_status srp_scene_ray_stats(srp_scene scene, const double* sun_dirs, int64_t 
 srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
                            const srp_trace_params* params, double* force, double* torque, void* stream);
 
+/* Surface-sampling estimator (paper Sec. 3.2, "Estimation", and its equation for F): for each of the
+ * S scenes and D sun directions (device double [D][3]), n_samples samples, each a facet drawn by area
+ * and a uniform point on it whose arriving light is gathered by path tracing with next-event
+ * estimation toward the Sun at every vertex (at most bounces - 1 gathered vertices), converted to
+ * force with one sampled outgoing event (mirror with weight rho_s/p_s, else a cosine direction with
+ * rho_d/(1 - p_s)).  force, torque (nullable): device double [S][D][3], sample means.  Scene s uses
+ * Philox design index params->design_index + s; counters (sample, global direction, stage,
+ * design).  brute_force = 1 tests every ray against every triangle of its scene (any tree depth);
+ * 0 walks each scene's BVH (SRP_EUNSUPPORTED for trees deeper than 24).  Sunlight whose first
+ * reflection is an ideal mirror is not gathered (a delta light through a delta reflection); all
+ * other light has the expectation of srp_trace with the same `bounces`.  Optional per-sample
+ * records, device int32: rec_facet [S][D][n_samples] (original facet), rec_lit [S][D][n_samples]
+ * (bit 0: x sunlit, bit k: gathered vertex k sunlit; required with rec_facet), rec_hits
+ * [S][D][n_samples][bounces - 1] (original facet of each gathered vertex, -1 none).  params: nu,
+ * nv, jitter, frame_mode and tiles_per_wave are ignored.  Scene table staged like srp_batch_trace. */
+srp_status srp_surface_estimate(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
+                                int64_t n_samples, const srp_trace_params* params, int32_t brute_force, double* force,
+                                double* torque, int32_t* rec_facet, int32_t* rec_hits, int32_t* rec_lit,
+                                void* stream);
+
 /* Launch-shape autotuner (not part of the paper's method): traces the given workload once per
  * candidate tiles_per_wave in 8..16 (S == 1: srp_trace of scenes[0]; S > 1: srp_batch_trace), after
  * one warm-up run each, and returns the fastest in *best; ms_out (host double [9], nullable)

@@ -51,6 +51,7 @@ _sigs = {
     "srp_trace_adjoint": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P, P, P, P],
     "srp_batch_trace": [P, I32, P, I64, ctypes.POINTER(TraceParams), P, P, P],
     "srp_autotune_tiles_per_wave": [P, I32, P, I64, ctypes.POINTER(TraceParams), ctypes.POINTER(I32), P, P],
+    "srp_surface_estimate": [P, I32, P, I64, I64, ctypes.POINTER(TraceParams), I32, P, P, P, P, P, P],
     "srp_scene_destroy": [P],
     "srp_mlp_create": [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)],
     "srp_mlp_num_params": [P, ctypes.POINTER(I64)],
@@ -215,6 +216,22 @@ def srp_batch_trace(scenes, sun_dirs, params: TraceParams, force, torque=None, s
     arr = (P * len(hs))(*[h.value if isinstance(h, P) else h for h in hs])
     _check(_lib.srp_batch_trace(ctypes.cast(arr, P), len(hs), _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params),
                                 _dptr(force), _dptr(torque), _stream(stream)))
+
+
+def srp_surface_estimate(scenes, sun_dirs, n_samples, params: TraceParams, force, torque=None, brute_force=False,
+                         rec_facet=None, rec_hits=None, rec_lit=None, stream=None):
+    """Surface-sampling estimate (see srp.h): force/torque device double [S][D][3]; records int32."""
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(force, torch.float64, "force")
+    _dtype_check(torque, torch.float64, "torque")
+    for name, t in (("rec_facet", rec_facet), ("rec_hits", rec_hits), ("rec_lit", rec_lit)):
+        _dtype_check(t, torch.int32, name)
+    hs = [s.handle if isinstance(s, Scene) else s for s in scenes]
+    arr = (P * len(hs))(*[h.value if isinstance(h, P) else h for h in hs])
+    _check(_lib.srp_surface_estimate(ctypes.cast(arr, P), len(hs), _dptr(sun_dirs), sun_dirs.shape[0], int(n_samples),
+                                     ctypes.byref(params), int(bool(brute_force)), _dptr(force), _dptr(torque),
+                                     _dptr(rec_facet), _dptr(rec_hits), _dptr(rec_lit), _stream(stream)))
 
 
 def srp_autotune_tiles_per_wave(scenes, sun_dirs, params: TraceParams, stream=None):

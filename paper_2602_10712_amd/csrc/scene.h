@@ -50,6 +50,18 @@ struct srp_scene_s {
     hipEvent_t batch_ev = nullptr;
     srp::SceneDesc* d_batch_desc = nullptr;
     size_t batch_desc_cap = 0;
+    // surface-sampling estimator: cumulative facet areas (FP64, original order), the BVH position
+    // of each original facet, and the scene table of calls led by this scene (pinned staging)
+    double area = 0;
+    double* d_cum_area = nullptr;
+    size_t cum_cap = 0;
+    int32_t* d_bvh_pos = nullptr;
+    size_t bvh_pos_cap = 0;
+    srp::SurfaceScene* h_surf_desc = nullptr;
+    size_t h_surf_desc_cap = 0;
+    hipEvent_t surf_ev = nullptr;
+    srp::SurfaceScene* d_surf_desc = nullptr;
+    size_t surf_desc_cap = 0;
 };
 
 // Records `msg` as the thread's last error and returns `st`.

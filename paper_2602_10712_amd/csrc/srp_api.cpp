@@ -155,6 +155,27 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
         std::memcpy(&hid_bits, &hid, 4);
         r.f[3] = make_float4(static_cast<float>(n[2]), hid_bits, 0.0f, 0.0f);
     }
+    // cumulative facet areas in original order (FP64) and the BVH position of each facet
+    std::vector<double> cum(s->n_tris);
+    std::vector<int32_t> pos(s->n_tris);
+    double acc = 0.0;
+    for (int64_t f = 0; f < s->n_tris; ++f) {
+        const double* a = &V[3 * static_cast<int64_t>(s->tris[3 * f])];
+        const double* b = &V[3 * static_cast<int64_t>(s->tris[3 * f + 1])];
+        const double* c = &V[3 * static_cast<int64_t>(s->tris[3 * f + 2])];
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+        acc += 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        cum[f] = acc;
+    }
+    for (int64_t p = 0; p < s->n_tris; ++p) pos[s->perm[p]] = static_cast<int32_t>(p);
+    s->area = acc;
+    SRP_HIP(ensure(s->d_cum_area, s->cum_cap, static_cast<size_t>(s->n_tris)));
+    SRP_HIP(ensure(s->d_bvh_pos, s->bvh_pos_cap, static_cast<size_t>(s->n_tris)));
+    SRP_HIP(hipMemcpyAsync(s->d_cum_area, cum.data(), cum.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    SRP_HIP(hipMemcpyAsync(s->d_bvh_pos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
     SRP_HIP(ensure(s->d_nodes, s->nodes_cap, s->h_nodes.size()));
     SRP_HIP(ensure(s->d_tris, s->tris_cap, static_cast<size_t>(s->n_tris)));
     SRP_HIP(ensure(s->d_perm, s->perm_cap, static_cast<size_t>(s->n_tris)));
@@ -569,6 +590,82 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
     return SRP_OK;
 }
 
+srp_status srp_surface_estimate(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
+                                int64_t n_samples, const srp_trace_params* p, int32_t brute_force, double* force,
+                                double* torque, int32_t* rec_facet, int32_t* rec_hits, int32_t* rec_lit,
+                                void* stream_)
+{
+    if (!scenes || S < 1) return fail(SRP_EINVAL, "need at least one scene");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (D < 0 || n_samples < 1) return fail(SRP_EINVAL, "D must be >= 0 and n_samples >= 1");
+    if (D == 0) return SRP_OK;
+    if (!sun_dirs || !force) return fail(SRP_EINVAL, "sun_dirs and force are required");
+    if ((rec_hits || rec_lit) && !rec_facet) return fail(SRP_EINVAL, "records need rec_facet");
+    if (rec_facet && !rec_lit) return fail(SRP_EINVAL, "rec_facet needs rec_lit");
+    if (p->dir_index_base + D > (int64_t(1) << 32)) return fail(SRP_EINVAL, "direction index exceeds 32 bits");
+    if (n_samples > (int64_t(1) << 32)) return fail(SRP_EINVAL, "sample index exceeds 32 bits");
+    srp_scene_s* lead = scenes[0];
+    for (int32_t s = 0; s < S; ++s) {
+        if (!scenes[s]) return fail(SRP_EINVAL, "NULL scene");
+        if (scenes[s]->device != lead->device) return fail(SRP_EINVAL, "all scenes must live on one device");
+        if (!brute_force && scenes[s]->depth > srp::kLaneStack)
+            return fail(SRP_EUNSUPPORTED, "BVH deeper than the per-lane stack: use brute force");
+    }
+    st = bind_device(lead);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if (lead->surf_ev) SRP_HIP(hipEventSynchronize(lead->surf_ev));
+    if (lead->h_surf_desc_cap < static_cast<size_t>(S)) {
+        if (lead->h_surf_desc) SRP_HIP(hipHostFree(lead->h_surf_desc));
+        lead->h_surf_desc = nullptr;
+        lead->h_surf_desc_cap = 0;
+        SRP_HIP(hipHostMalloc(reinterpret_cast<void**>(&lead->h_surf_desc), sizeof(srp::SurfaceScene) * S));
+        lead->h_surf_desc_cap = static_cast<size_t>(S);
+    }
+    for (int32_t s = 0; s < S; ++s) {
+        srp::SurfaceScene& d = lead->h_surf_desc[s];
+        d.nodes = (decltype(d.nodes))scenes[s]->d_nodes;  // device passes see global-qualified members
+        d.tris = (decltype(d.tris))scenes[s]->d_tris;
+        d.mat = (decltype(d.mat))scenes[s]->d_mat;
+        d.cum_area = (decltype(d.cum_area))scenes[s]->d_cum_area;
+        d.bvh_pos = (decltype(d.bvh_pos))scenes[s]->d_bvh_pos;
+        d.area = scenes[s]->area;
+        for (int k = 0; k < 3; ++k) d.com[k] = static_cast<float>(scenes[s]->com[k]);
+        d.eps = static_cast<float>(1e-5 * scenes[s]->L);
+        d.n_tris = static_cast<int32_t>(scenes[s]->n_tris);
+        d.pad = 0;
+    }
+    SRP_HIP(ensure(lead->d_surf_desc, lead->surf_desc_cap, static_cast<size_t>(S)));
+    SRP_HIP(hipMemcpyAsync(lead->d_surf_desc, lead->h_surf_desc, sizeof(srp::SurfaceScene) * S,
+                           hipMemcpyHostToDevice, stream));
+    if (!lead->surf_ev) SRP_HIP(hipEventCreateWithFlags(&lead->surf_ev, hipEventDisableTiming));
+    SRP_HIP(hipEventRecord(lead->surf_ev, stream));
+    srp::SurfaceArgs a{};
+    a.scenes = lead->d_surf_desc;
+    a.n_scenes = S;
+    a.bounces = p->bounces;
+    a.sun = sun_dirs;
+    a.D = D;
+    a.n_samples = n_samples;
+    const int64_t chunks = (n_samples + 255) / 256;
+    const int64_t units = static_cast<int64_t>(S) * D;
+    if (chunks > 0x7fffffffLL || units * chunks > 0x7fffffffLL) return fail(SRP_EINVAL, "estimate too large");
+    a.chunks = static_cast<int32_t>(chunks);
+    a.flux_c = static_cast<float>(p->flux / srp::kSpeedOfLight);
+    a.seed_lo = static_cast<uint32_t>(p->seed);
+    a.seed_hi = static_cast<uint32_t>(p->seed >> 32);
+    a.dir_index_base = p->dir_index_base;
+    a.design_index = static_cast<uint32_t>(p->design_index);
+    SRP_HIP(ensure(lead->d_partials, lead->partials_cap, static_cast<size_t>(units * chunks * 6)));
+    a.partials = lead->d_partials;
+    a.rec_facet = rec_facet;
+    a.rec_hits = p->bounces > 1 ? rec_hits : nullptr;
+    a.rec_lit = rec_lit;
+    SRP_HIP(srp::launch_surface(a, brute_force != 0, force, torque, stream));
+    return SRP_OK;
+}
+
 srp_status srp_autotune_tiles_per_wave(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
                                        const srp_trace_params* p, int32_t* best, double* ms_out, void* stream_)
 {
@@ -635,6 +732,14 @@ srp_status srp_scene_destroy(srp_scene s)
     (void)hipFree(s->d_grho);
     (void)hipFree(s->d_hdir);
     (void)hipFree(s->d_batch_desc);
+    (void)hipFree(s->d_cum_area);
+    (void)hipFree(s->d_bvh_pos);
+    (void)hipFree(s->d_surf_desc);
+    if (s->surf_ev) {
+        (void)hipEventSynchronize(s->surf_ev);
+        (void)hipEventDestroy(s->surf_ev);
+    }
+    (void)hipHostFree(s->h_surf_desc);
     if (s->batch_ev) {
         (void)hipEventSynchronize(s->batch_ev);
         (void)hipEventDestroy(s->batch_ev);

@@ -113,6 +113,39 @@ inline int64_t grid_blocks(const TraceArgs& a, int64_t n_units)
     return units * a.blocks_per_dir;
 }
 
+// One scene of the surface-sampling estimator: BVH-order records plus the cumulative facet areas
+// (FP64, original facet order) and the BVH position of every original facet.
+struct SurfaceScene {
+    const SRP_GLOBAL BvhNode* nodes;
+    const SRP_GLOBAL TriRec* tris;
+    const SRP_GLOBAL float4* mat;
+    const SRP_GLOBAL double* cum_area;
+    const SRP_GLOBAL int32_t* bvh_pos;
+    double area;              // total area
+    float com[3];
+    float eps;                // ray offset along the normal
+    int32_t n_tris;
+    int32_t pad;
+};
+
+struct SurfaceArgs {
+    const SurfaceScene* scenes;  // [n_scenes]
+    int32_t n_scenes;
+    int32_t bounces;
+    const double* sun;           // [D][3]
+    int64_t D;
+    int64_t n_samples;           // per (scene, direction) unit
+    int32_t chunks;              // workgroups per unit
+    float flux_c;                // Phi / c
+    uint32_t seed_lo, seed_hi;
+    int64_t dir_index_base;
+    uint32_t design_index;
+    double* partials;            // [units][chunks][6]
+    int32_t* rec_facet;          // [units][n_samples] or null
+    int32_t* rec_hits;           // [units][n_samples][bounces - 1] or null
+    int32_t* rec_lit;            // [units][n_samples] (with rec_facet)
+};
+
 constexpr int kMaxHinges = 4;   // hinge-angle gradients supported by the adjoint
 
 struct AdjointArgs {
@@ -138,6 +171,7 @@ hipError_t launch_trace_batch(const TraceArgs& a, hipStream_t stream);
 hipError_t launch_reduce(const double* partials, int64_t D, int32_t blocks_per_dir, double* force, double* torque,
                          hipStream_t stream);
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream);
+hipError_t launch_surface(const SurfaceArgs& a, bool brute, double* force, double* torque, hipStream_t stream);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream);
 hipError_t launch_finish_adjoint(const double* g_rho, int32_t n_tris, float* g_rho_s, float* g_rho_d,
                                  const double* hinge_partials, int64_t D, int32_t blocks_per_dir, int32_t n_hinges,
