@@ -11,6 +11,7 @@ Prints ONE JSON line (see the design notes for the field definitions):
   surrogate        fused MLP surrogate evals/s on 1M queries, with its MFMA roofline fraction
   batched          one launch over 256 design variants (2k-50k tris) x 256 dirs x 512^2 rays
   orbit            one design-gradient iteration through a day of RK4 orbit (2881 directions, 512^2)
+  surface          the paper's surface-sampling estimator: samples/s with the BVH and by brute force
   roofline         dominant kernel (k_trace): algorithmic bytes per launch / mean launch time
   cpu_baseline     the FP64 oracle on a bounded sample of the same workload, host cores
 """
@@ -89,6 +90,7 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-orbit", action="store_true")
+    ap.add_argument("--no-surface", action="store_true")
     ap.add_argument("--batch-designs", type=int, default=256)
     ap.add_argument("--batch-dirs", type=int, default=256)
     ap.add_argument("--batch-grid", type=int, default=512)
@@ -275,6 +277,24 @@ def main():
                      "batch": nq, "roofline": {"bound": "mfma", "achieved": round(tf, 1), "peak": 2500.0,
                                                "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4)}}
         log(f"surrogate: {ms_s:.3f} ms per {nq} queries, {nq / ms_s / 1e6:.3f} G evals/s, {tf:.1f} TFLOP/s")
+        # training throughput: one Adam step = forward with kept activations, MSE gradient, backward
+        # and the update, on batches of 4096 synthetic samples (the training recipe's batch)
+        bt = 4096
+        xt = (torch.rand((bt, 11), generator=gen) * 2 - 1).to(dev)
+        yt = torch.randn((bt, 3), generator=gen).to(dev)
+        for i in range(20):
+            net.train_step(xt, yt, 1e-4, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        n_tr = 200
+        e0.record(stream)
+        for i in range(n_tr):
+            net.train_step(xt, yt, 1e-4, stream=stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_t = e0.elapsed_time(e1) / n_tr
+        surrogate["training"] = {"samples_per_s": round(bt / (ms_t * 1e-3), 1), "ms_per_step": round(ms_t, 4),
+                                 "batch": bt, "tflops": round(3 * 400384 * bt / (ms_t * 1e-3) / 1e12, 1)}
+        log(f"surrogate training: {ms_t:.3f} ms per Adam step of {bt} samples, {bt / ms_t / 1e3:.2f} M samples/s")
         net.close()
 
     # ---- batched designs: 256 MEO-style variants, 256 directions each, one launch ---------------
@@ -335,6 +355,55 @@ def main():
         for sck in scenes:
             sck.close()
 
+    # ---- the paper's own estimator: surface sampling, BVH walk vs brute force -------------------
+    surface = None
+    if not args.no_surface:
+        def surf_time(scenes_s, D_s, N_s, brute):
+            sun_s = torch.as_tensor(si.fibonacci_dirs(D_s), dtype=torch.float64, device=dev).contiguous()
+            Fs = torch.empty((len(scenes_s), D_s, 3), dtype=torch.float64, device=dev)
+            ps_ = p.TraceParams(bounces=args.bounces, seed=3)
+            p.srp_surface_estimate(scenes_s, sun_s, N_s, ps_, Fs, brute_force=brute, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            reps = 3
+            e0.record(stream)
+            for _ in range(reps):
+                p.srp_surface_estimate(scenes_s, sun_s, N_s, ps_, Fs, brute_force=brute, stream=stream.cuda_stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms_ = e0.elapsed_time(e1) / reps
+            return {"samples_per_s": round(len(scenes_s) * D_s * N_s / (ms_ * 1e-3), 1), "ms": round(ms_, 3),
+                    "designs": len(scenes_s), "dirs": D_s, "samples": N_s}
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        bw = si.box_wing()
+        rbs, rbd = si.materials(bw.n_tris, 1)
+        sbw = p.Scene.from_mesh(bw)
+        sbw.set_design(rbs, rbd)
+        surface = {
+            "workload": f"{args.bounces} bounces; samples per second of the whole estimate (facet by area, point, "
+                        "gathering with next-event estimation, outgoing event)",
+            "meo_bvh": surf_time([sc], 64, 65536, False),
+            "meo_brute_force": surf_time([sc], 64, 4096, True),
+            "box_wing_bvh": surf_time([sbw], 64, 65536, False),
+            "box_wing_brute_force": surf_time([sbw], 64, 65536, True),
+        }
+        # samples per design above which building a BVH (host SAH build, timed here on one thread)
+        # and walking it beats testing every triangle, for the 20.6k-triangle satellite
+        t0 = time.perf_counter()
+        for _ in range(3):
+            tmp = p.Scene.from_mesh(mesh)
+            tmp.close()
+        build_one = (time.perf_counter() - t0) / 3
+        r_b = surface["meo_bvh"]["samples_per_s"]
+        r_f = surface["meo_brute_force"]["samples_per_s"]
+        surface["meo_bvh_build_s"] = round(build_one, 4)
+        surface["meo_crossover_samples_per_design"] = round(build_one / (1.0 / r_f - 1.0 / r_b))
+        log(f"surface estimator: MEO BVH {r_b / 1e9:.2f} G samples/s, brute force {r_f / 1e6:.2f} M samples/s, "
+            f"box-wing BVH {surface['box_wing_bvh']['samples_per_s'] / 1e9:.2f} / brute "
+            f"{surface['box_wing_brute_force']['samples_per_s'] / 1e9:.2f} G samples/s; crossover "
+            f"{surface['meo_crossover_samples_per_design']} samples per design")
+        sbw.close()
+
     # ---- roofline of the dominant kernel --------------------------------------------------------
     roofline = None
     try:
@@ -381,7 +450,7 @@ def main():
                    "tris": mesh.n_tris, "dirs": D, "grid": args.grid, "bounces": args.bounces,
                    "bvh_nodes": info["n_nodes"], "bvh_build_s": round(build_s, 4)},
         "roofline": roofline, "cpu_baseline": cpu, "fwd_adjoint": fwd_adj,
-        "surrogate": surrogate, "batched": batched, "orbit": orbit,
+        "surrogate": surrogate, "batched": batched, "orbit": orbit, "surface": surface,
     }
     print(json.dumps(out), flush=True)
 
