@@ -91,6 +91,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-orbit", action="store_true")
     ap.add_argument("--no-surface", action="store_true")
+    ap.add_argument("--no-surrogate-training", action="store_true")
     ap.add_argument("--batch-designs", type=int, default=256)
     ap.add_argument("--batch-dirs", type=int, default=256)
     ap.add_argument("--batch-grid", type=int, default=512)
@@ -279,22 +280,23 @@ def main():
         log(f"surrogate: {ms_s:.3f} ms per {nq} queries, {nq / ms_s / 1e6:.3f} G evals/s, {tf:.1f} TFLOP/s")
         # training throughput: one Adam step = forward with kept activations, MSE gradient, backward
         # and the update, on batches of 4096 synthetic samples (the training recipe's batch)
-        bt = 4096
-        xt = (torch.rand((bt, 11), generator=gen) * 2 - 1).to(dev)
-        yt = torch.randn((bt, 3), generator=gen).to(dev)
-        for i in range(20):
-            net.train_step(xt, yt, 1e-4, stream=stream.cuda_stream)
-        torch.cuda.synchronize()
-        n_tr = 200
-        e0.record(stream)
-        for i in range(n_tr):
-            net.train_step(xt, yt, 1e-4, stream=stream.cuda_stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_t = e0.elapsed_time(e1) / n_tr
-        surrogate["training"] = {"samples_per_s": round(bt / (ms_t * 1e-3), 1), "ms_per_step": round(ms_t, 4),
-                                 "batch": bt, "tflops": round(3 * 400384 * bt / (ms_t * 1e-3) / 1e12, 1)}
-        log(f"surrogate training: {ms_t:.3f} ms per Adam step of {bt} samples, {bt / ms_t / 1e3:.2f} M samples/s")
+        if not args.no_surrogate_training:
+            bt = 4096
+            xt = (torch.rand((bt, 11), generator=gen) * 2 - 1).to(dev)
+            yt = torch.randn((bt, 3), generator=gen).to(dev)
+            for i in range(20):
+                net.train_step(xt, yt, 1e-4, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            n_tr = 200
+            e0.record(stream)
+            for i in range(n_tr):
+                net.train_step(xt, yt, 1e-4, stream=stream.cuda_stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms_t = e0.elapsed_time(e1) / n_tr
+            surrogate["training"] = {"samples_per_s": round(bt / (ms_t * 1e-3), 1), "ms_per_step": round(ms_t, 4),
+                                     "batch": bt, "tflops": round(3 * 400384 * bt / (ms_t * 1e-3) / 1e12, 1)}
+            log(f"surrogate training: {ms_t:.3f} ms per Adam step of {bt} samples, {bt / ms_t / 1e3:.2f} M samples/s")
         net.close()
 
     # ---- batched designs: 256 MEO-style variants, 256 directions each, one launch ---------------
