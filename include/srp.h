@@ -207,6 +207,15 @@ srp_status srp_autotune_tiles_per_wave(const srp_scene* scenes, int32_t S, const
                                        const srp_trace_params* params, int32_t* best, double* ms_out,
                                        void* stream);
 
+/* Rebuilds the scene's BVH on the GPU from its current geometry (linear BVH, Karras, HPG 2012:
+ * Morton codes of the triangle centroids, radix sort, parallel radix-tree construction, bottom-up
+ * boxes; subtrees of at most 4 triangles become leaves; nodes in pre-order).  Replaces the tree
+ * built at creation (binned SAH on the host): traces give the same hits, as the closest hit with its
+ * index tie-break does not depend on the tree.  Later hinge changes refit the new tree.  At least
+ * 8 triangles; SRP_EUNSUPPORTED when the tree would exceed the traversal stack.  Synchronous on
+ * `stream`; allocates a temporary workspace.  *n_nodes_out, *depth_out (nullable): the new tree. */
+srp_status srp_scene_build_gpu(srp_scene scene, int32_t* n_nodes_out, int32_t* depth_out, void* stream);
+
 srp_status srp_scene_destroy(srp_scene scene);
 
 /* ---------------------------------------------------------------------------------------------

@@ -52,6 +52,7 @@ _sigs = {
     "srp_batch_trace": [P, I32, P, I64, ctypes.POINTER(TraceParams), P, P, P],
     "srp_autotune_tiles_per_wave": [P, I32, P, I64, ctypes.POINTER(TraceParams), ctypes.POINTER(I32), P, P],
     "srp_surface_estimate": [P, I32, P, I64, I64, ctypes.POINTER(TraceParams), I32, P, P, P, P, P, P],
+    "srp_scene_build_gpu": [P, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
     "srp_scene_destroy": [P],
     "srp_mlp_create": [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)],
     "srp_mlp_num_params": [P, ctypes.POINTER(I64)],
@@ -216,6 +217,14 @@ def srp_batch_trace(scenes, sun_dirs, params: TraceParams, force, torque=None, s
     arr = (P * len(hs))(*[h.value if isinstance(h, P) else h for h in hs])
     _check(_lib.srp_batch_trace(ctypes.cast(arr, P), len(hs), _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params),
                                 _dptr(force), _dptr(torque), _stream(stream)))
+
+
+def srp_scene_build_gpu(scene, stream=None):
+    """Rebuilds the scene's BVH on the GPU (see srp.h); returns (nodes, depth) of the new tree."""
+    nn, dd = I32(0), I32(0)
+    _check(_lib.srp_scene_build_gpu(scene.handle if isinstance(scene, Scene) else scene, ctypes.byref(nn),
+                                    ctypes.byref(dd), _stream(stream)))
+    return int(nn.value), int(dd.value)
 
 
 def srp_surface_estimate(scenes, sun_dirs, n_samples, params: TraceParams, force, torque=None, brute_force=False,

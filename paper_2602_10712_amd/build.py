@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsrp.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["srp_api.cpp", "bvh_build.cpp", "ray_stats.cpp", "trace_kernels.hip", "adjoint_kernels.hip", "surface_kernels.hip", "mlp_api.cpp", "mlp_kernels.hip", "mlp_infer.hip",
+SOURCES = ["srp_api.cpp", "bvh_build.cpp", "ray_stats.cpp", "trace_kernels.hip", "adjoint_kernels.hip", "surface_kernels.hip", "bvh_gpu.hip", "mlp_api.cpp", "mlp_kernels.hip", "mlp_infer.hip",
            "orbit.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

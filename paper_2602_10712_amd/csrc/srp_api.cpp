@@ -590,6 +590,101 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
     return SRP_OK;
 }
 
+srp_status srp_scene_build_gpu(srp_scene s, int32_t* n_nodes_out, int32_t* depth_out, void* stream_)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    if (s->n_tris < 8) return fail(SRP_EUNSUPPORTED, "GPU build needs at least 8 triangles");
+    if (s->n_tris > 0x3fffffff) return fail(SRP_EUNSUPPORTED, "too many triangles for the GPU build");
+    srp_status st = bind_device(s);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    SRP_HIP(hipStreamSynchronize(stream));  // kernels in flight may still read the current tree
+    const int32_t n = static_cast<int32_t>(s->n_tris);
+    srp::LbvhArgs a{};
+    a.n = n;
+    float ext[3];
+    for (int k = 0; k < 3; ++k) ext[k] = static_cast<float>(std::max(s->hi[k] - s->lo[k], 1e-30));
+    a.lo = make_float3(static_cast<float>(s->lo[0]), static_cast<float>(s->lo[1]), static_cast<float>(s->lo[2]));
+    a.scale = make_float3(1024.0f / ext[0], 1024.0f / ext[1], 1024.0f / ext[2]);
+    a.pad = static_cast<float>(1e-6 * s->L);
+    a.tris_in = s->d_tris;
+    a.mat_in = s->d_mat;
+    a.perm_in = s->d_perm;
+    // workspace: one block, carved in 256-byte-aligned pieces
+    a.sort_bytes = srp::lbvh_sort_bytes(n);
+    const size_t nn = static_cast<size_t>(n);
+    const size_t sizes[] = {4 * nn, 4 * nn, 4 * nn, 4 * nn, a.sort_bytes, 64 * nn, 16 * nn, 4 * nn, 8 * nn, 8 * nn,
+                            4 * nn, 4 * nn, 4 * nn, 24 * nn, 24 * nn, 4 * nn, 64 * nn, 4};
+    size_t total = 0;
+    for (size_t z : sizes) total += (z + 255) / 256 * 256;
+    char* ws = nullptr;
+    SRP_HIP(hipMalloc(reinterpret_cast<void**>(&ws), total));
+    size_t off = 0;
+    auto take = [&](size_t z) {
+        char* p = ws + off;
+        off += (z + 255) / 256 * 256;
+        return p;
+    };
+    a.keys = reinterpret_cast<uint32_t*>(take(sizes[0]));
+    a.keys_sorted = reinterpret_cast<uint32_t*>(take(sizes[1]));
+    a.pos = reinterpret_cast<int32_t*>(take(sizes[2]));
+    a.order = reinterpret_cast<int32_t*>(take(sizes[3]));
+    a.sort_tmp = take(sizes[4]);
+    a.tris_out = reinterpret_cast<srp::TriRec*>(take(sizes[5]));
+    a.mat_out = reinterpret_cast<float4*>(take(sizes[6]));
+    a.perm_out = reinterpret_cast<int32_t*>(take(sizes[7]));
+    a.child = reinterpret_cast<int2*>(take(sizes[8]));
+    a.range = reinterpret_cast<int2*>(take(sizes[9]));
+    a.parent = reinterpret_cast<int32_t*>(take(sizes[10]));
+    a.leaf_parent = reinterpret_cast<int32_t*>(take(sizes[11]));
+    a.visits = reinterpret_cast<uint32_t*>(take(sizes[12]));
+    a.leaf_box = reinterpret_cast<float*>(take(sizes[13]));
+    a.node_box = reinterpret_cast<float*>(take(sizes[14]));
+    a.kept = reinterpret_cast<int32_t*>(take(sizes[15]));
+    a.nodes_out = reinterpret_cast<srp::BvhNode*>(take(sizes[16]));
+    a.depth_out = reinterpret_cast<int32_t*>(take(sizes[17]));
+    hipError_t e = srp::launch_lbvh(a, stream);
+    int32_t count = 0, depth = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&count, a.kept, 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&depth, a.depth_out, 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess && (count < 1 || count > n - 1)) e = hipErrorUnknown;
+    if (e != hipSuccess || depth >= srp::kMaxTreeDepth) {
+        (void)hipFree(ws);
+        if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("GPU BVH build: ") + hipGetErrorString(e));
+        return fail(SRP_EUNSUPPORTED, "GPU-built tree deeper than the traversal stack");
+    }
+    // adopt the new tree and record order; refresh the host copies (refit, statistics)
+    std::vector<srp::BvhNode> nodes(count);
+    std::vector<int32_t> perm(n);
+    std::vector<srp::TriRec> recs(n);
+    e = hipMemcpy(nodes.data(), a.nodes_out, sizeof(srp::BvhNode) * count, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(perm.data(), a.perm_out, 4 * nn, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(recs.data(), a.tris_out, sizeof(srp::TriRec) * nn, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = ensure(s->d_nodes, s->nodes_cap, static_cast<size_t>(count));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_nodes, a.nodes_out, sizeof(srp::BvhNode) * count, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_tris, a.tris_out, sizeof(srp::TriRec) * nn, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d_mat, a.mat_out, 16 * nn, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d_perm, a.perm_out, 4 * nn, hipMemcpyDeviceToDevice, stream);
+    std::vector<int32_t> pos(n);
+    for (int32_t p = 0; p < n; ++p) pos[perm[p]] = p;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_bvh_pos, pos.data(), 4 * nn, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(ws);
+    if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("GPU BVH build: ") + hipGetErrorString(e));
+    s->h_nodes = std::move(nodes);
+    s->perm = std::move(perm);
+    s->h_tris = std::move(recs);
+    s->n_nodes = count;
+    s->depth = depth;
+    if (n_nodes_out) *n_nodes_out = count;
+    if (depth_out) *depth_out = depth;
+    return SRP_OK;
+}
+
 srp_status srp_surface_estimate(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
                                 int64_t n_samples, const srp_trace_params* p, int32_t brute_force, double* force,
                                 double* torque, int32_t* rec_facet, int32_t* rec_hits, int32_t* rec_lit,

@@ -146,6 +146,36 @@ struct SurfaceArgs {
     int32_t* rec_lit;            // [units][n_samples] (with rec_facet)
 };
 
+// GPU BVH build (linear BVH): buffers of one build over n >= 2 triangles.
+constexpr int kLbvhLeaf = 4;    // subtrees of at most this many triangles become one leaf
+struct LbvhArgs {
+    int32_t n;
+    float3 lo, scale;               // Morton grid: (centroid - lo) * scale in [0, 1024)
+    float pad;                      // box widening, metres
+    const TriRec* tris_in;          // current order
+    const float4* mat_in;
+    const int32_t* perm_in;         // current position -> original facet
+    uint32_t* keys;                 // [n]
+    uint32_t* keys_sorted;          // [n]
+    int32_t* pos;                   // [n]
+    int32_t* order;                 // [n] new position -> current position
+    void* sort_tmp;
+    size_t sort_bytes;
+    TriRec* tris_out;               // [n] new order
+    float4* mat_out;
+    int32_t* perm_out;
+    int2* child;                    // [n - 1] inner index, or ~leaf
+    int2* range;                    // [n - 1] first, last leaf
+    int32_t* parent;                // [n - 1]
+    int32_t* leaf_parent;           // [n]
+    uint32_t* visits;               // [n - 1] (n words cleared)
+    float* leaf_box;                // [n][6]
+    float* node_box;                // [n - 1][6]
+    int32_t* kept;                  // [n - 1] kept inner nodes per subtree; kept[0] = node count
+    BvhNode* nodes_out;             // [n - 1], pre-order, kept[0] of them written
+    int32_t* depth_out;             // deepest level (root = 0)
+};
+
 constexpr int kMaxHinges = 4;   // hinge-angle gradients supported by the adjoint
 
 struct AdjointArgs {
@@ -171,6 +201,8 @@ hipError_t launch_trace_batch(const TraceArgs& a, hipStream_t stream);
 hipError_t launch_reduce(const double* partials, int64_t D, int32_t blocks_per_dir, double* force, double* torque,
                          hipStream_t stream);
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream);
+size_t lbvh_sort_bytes(int32_t n);
+hipError_t launch_lbvh(const LbvhArgs& a, hipStream_t stream);
 hipError_t launch_surface(const SurfaceArgs& a, bool brute, double* force, double* torque, hipStream_t stream);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream);
 hipError_t launch_finish_adjoint(const double* g_rho, int32_t n_tris, float* g_rho_s, float* g_rho_d,
