@@ -406,6 +406,49 @@ def main():
             f"{surface['meo_crossover_samples_per_design']} samples per design")
         sbw.close()
 
+        # the same tree rebuilt on the GPU (linear BVH): the build's cost, what the tree costs the
+        # ray-grid trace and the surface walk, and the crossover when each design gets a GPU build
+        sg = p.Scene.from_mesh(mesh)
+        sg.set_design(rs, rd, hinge_angles=angles)
+        p.srp_scene_build_gpu(sg, stream=stream.cuda_stream)  # first call: workspace, code objects
+        tb = []
+        for _ in range(7):
+            t0 = time.perf_counter()
+            nn_g, dep_g = p.srp_scene_build_gpu(sg, stream=stream.cuda_stream)
+            tb.append(time.perf_counter() - t0)
+        gpu_build = float(np.median(tb))
+        sun_t = sun_d[::8].contiguous()
+        Ft = torch.empty((sun_t.shape[0], 3), dtype=torch.float64, device=dev)
+
+        def trace_ms(scene):
+            p.srp_trace(scene.handle, sun_t, params, Ft, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(3):
+                p.srp_trace(scene.handle, sun_t, params, Ft, stream=stream.cuda_stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 3
+
+        rays_t = float(sun_t.shape[0]) * args.grid * args.grid
+        ms_sah, ms_lbvh = trace_ms(sc), trace_ms(sg)
+        s_lbvh = surf_time([sg], 64, 65536, False)
+        r_bg = s_lbvh["samples_per_s"]
+        surface["meo_gpu_build"] = {
+            "build_s": round(gpu_build, 5), "nodes": nn_g, "depth": dep_g,
+            "sah_nodes": info["n_nodes"], "sah_depth": info["depth"],
+            "trace_mrays_s_sah": round(rays_t / (ms_sah * 1e-3) / 1e6, 1),
+            "trace_mrays_s_lbvh": round(rays_t / (ms_lbvh * 1e-3) / 1e6, 1),
+            "surface_bvh_samples_per_s": r_bg,
+            "crossover_samples_per_design": round(gpu_build / (1.0 / r_f - 1.0 / r_bg)),
+            "workload": f"{sun_t.shape[0]} dirs x {args.grid}x{args.grid} rays for the trace rates; build_s is the "
+                        "whole synchronous call (kernels, read-back of the host copies), median of 7"}
+        log(f"GPU BVH build: {gpu_build * 1e3:.2f} ms ({nn_g} nodes, depth {dep_g}); trace SAH "
+            f"{surface['meo_gpu_build']['trace_mrays_s_sah']:.0f} vs LBVH "
+            f"{surface['meo_gpu_build']['trace_mrays_s_lbvh']:.0f} Mrays/s; surface LBVH {r_bg / 1e9:.2f} G samples/s;"
+            f" crossover {surface['meo_gpu_build']['crossover_samples_per_design']} samples per design")
+        sg.close()
+
     # ---- roofline of the dominant kernel --------------------------------------------------------
     roofline = None
     try:

@@ -213,7 +213,10 @@ srp_status srp_autotune_tiles_per_wave(const srp_scene* scenes, int32_t S, const
  * built at creation (binned SAH on the host): traces give the same hits, as the closest hit with its
  * index tie-break does not depend on the tree.  Later hinge changes refit the new tree.  At least
  * 8 triangles; SRP_EUNSUPPORTED when the tree would exceed the traversal stack.  Synchronous on
- * `stream`; allocates a temporary workspace.  *n_nodes_out, *depth_out (nullable): the new tree. */
+ * `stream`; the build workspace (about 250 bytes per triangle plus the sort's) stays with the scene
+ * for later rebuilds.  *n_nodes_out, *depth_out (nullable): the new tree.  The paper's simulation
+ * evaluation (BVH-comparison figure) times a linear-BVH build against brute-force intersection
+ * per design; this build is what that comparison takes on this GPU. */
 srp_status srp_scene_build_gpu(srp_scene scene, int32_t* n_nodes_out, int32_t* depth_out, void* stream);
 
 srp_status srp_scene_destroy(srp_scene scene);

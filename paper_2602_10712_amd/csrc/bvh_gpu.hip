@@ -3,17 +3,25 @@
 // into leaves and the kept inner nodes written in pre-order (the layout of the host-built tree:
 // node 0 the root, every child after its parent).
 //
-//   1. 30-bit Morton code of every triangle centroid (10 bits per axis over the scene box);
+//   1. 30-bit Morton code of every triangle centroid (10 bits per axis, cubic cells over the scene
+//      box);
 //   2. radix sort of (code, position) pairs (rocPRIM);
-//   3. triangle, material and permutation records gathered into the sorted order;
+//   3. triangle, material and permutation records gathered into the sorted order, with the box
+//      of every triangle;
 //   4. the binary radix tree over the sorted codes (one thread per inner node; equal codes are
 //      ordered by position), parents and leaf ranges;
-//   5. bottom-up boxes and kept-node counts: one thread per triangle climbs toward the root, the
-//      second thread to reach a node finishes it (device-scope counter per node);
-//   6. pre-order positions from the counts (each kept node walks to the root) and the node records.
+//   5. the leaf records of the final tree: every maximal subtree of at most kLbvhLeaf triangles,
+//      and every single triangle outside them; a scan over the leaves that open one counts the
+//      kept inner nodes of any subtree (a full binary tree over its leaf records);
+//   6. a window table (box of leaves [i, i + 2^k) for every k), from which the box of any node,
+//      a contiguous leaf range, is the union of two windows;
+//   7. pre-order positions (each kept node walks to the root) and the node records.
+// Every node covers a contiguous range of sorted leaves, so no step waits on another thread: there
+// is no bottom-up pass with device-scope counters and fences, whose cost grows with the tree height.
 #include <float.h>
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "srp_internal.h"
 
@@ -49,17 +57,88 @@ __global__ void k_morton(const TriRec* __restrict__ tris, int32_t n, float3 lo, 
     pos[i] = i;
 }
 
-// records at their sorted positions; perm maps positions to original facets
+struct Box6 {
+    float lo[3], hi[3];
+};
+
+__device__ __forceinline__ Box6 tri_box(const TriRec& t)
+{
+    Box6 b;
+    const float v0[3] = {t.f[0].x, t.f[0].y, t.f[0].z};
+    const float e1[3] = {t.f[1].x, t.f[1].y, t.f[1].z};
+    const float e2[3] = {t.f[2].x, t.f[2].y, t.f[2].z};
+    for (int a = 0; a < 3; ++a) {
+        const float p1 = v0[a] + e1[a], p2 = v0[a] + e2[a];
+        b.lo[a] = fminf(v0[a], fminf(p1, p2));
+        b.hi[a] = fmaxf(v0[a], fmaxf(p1, p2));
+    }
+    return b;
+}
+
+// window-table entries: (lo.x, hi.x), (lo.y, hi.y), (lo.z, hi.z)
+__device__ __forceinline__ Box6 load_box(const float* __restrict__ w, int64_t i)
+{
+    const float2* q = reinterpret_cast<const float2*>(w + 6 * i);
+    Box6 r;
+    for (int a = 0; a < 3; ++a) {
+        const float2 v = q[a];
+        r.lo[a] = v.x;
+        r.hi[a] = v.y;
+    }
+    return r;
+}
+
+__device__ __forceinline__ void store_box(float* __restrict__ w, int64_t i, const Box6& b)
+{
+    float2* q = reinterpret_cast<float2*>(w + 6 * i);
+    for (int a = 0; a < 3; ++a) q[a] = make_float2(b.lo[a], b.hi[a]);
+}
+
+__device__ __forceinline__ Box6 join(const Box6& a, const Box6& b)
+{
+    Box6 r;
+    for (int k = 0; k < 3; ++k) {
+        r.lo[k] = fminf(a.lo[k], b.lo[k]);
+        r.hi[k] = fmaxf(a.hi[k], b.hi[k]);
+    }
+    return r;
+}
+
+// records at their sorted positions; perm maps positions to original facets, bvh_pos the inverse;
+// level 0 of the window table holds the triangle boxes
 __global__ void k_gather(const TriRec* __restrict__ tris_in, const float4* __restrict__ mat_in,
                          const int32_t* __restrict__ perm_in, const int32_t* __restrict__ order, int32_t n,
-                         TriRec* __restrict__ tris_out, float4* __restrict__ mat_out, int32_t* __restrict__ perm_out)
+                         TriRec* __restrict__ tris_out, float4* __restrict__ mat_out, int32_t* __restrict__ perm_out,
+                         int32_t* __restrict__ bvh_pos_out, float* __restrict__ win)
 {
     const int32_t k = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
     if (k >= n) return;
     const int32_t q = order[k];
-    tris_out[k] = tris_in[q];
+    const TriRec t = tris_in[q];
+    const int32_t f = perm_in[q];
+    tris_out[k] = t;
     mat_out[k] = mat_in[q];
-    perm_out[k] = perm_in[q];
+    perm_out[k] = f;
+    bvh_pos_out[f] = k;
+    store_box(win, k, tri_box(t));
+}
+
+// level k of the window table from level k - 1: box of leaves [i, i + 2 half)
+__global__ void k_window(const float* __restrict__ prev, float* __restrict__ cur, int32_t count, int32_t half)
+{
+    const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= count) return;
+    store_box(cur, i, join(load_box(prev, i), load_box(prev, static_cast<int64_t>(i) + half)));
+}
+
+// box of sorted leaves [a, b]: the union of the two windows of the largest power of two not above
+// its length that start at a and end at b
+__device__ __forceinline__ Box6 range_box(const float* __restrict__ win, int32_t n, int32_t a, int32_t b)
+{
+    const uint32_t len = static_cast<uint32_t>(b - a + 1);
+    const int k = 31 - __clz(len);
+    const float* level = win + static_cast<int64_t>(k) * n * 6;
+    return join(load_box(level, a), load_box(level, b - (1 << k) + 1));
 }
 
 // common-prefix length of sorted keys i and j (ties broken by position); -1 outside [0, n)
@@ -104,88 +183,52 @@ __global__ void k_karras(const uint32_t* __restrict__ keys, int32_t n, int2* __r
     if (i == 0) parent[0] = -1;
 }
 
-struct Box6 {
-    float lo[3], hi[3];
-};
-
-__device__ __forceinline__ Box6 tri_box(const TriRec& t)
+// Marks the leaves that open a leaf record of the final tree: the record of leaf p is the largest
+// subtree of at most kLbvhLeaf triangles that holds it (p alone when its parent holds more).
+__global__ void k_frontier(const int2* __restrict__ range, const int32_t* __restrict__ parent,
+                           const int32_t* __restrict__ leaf_parent, int32_t n, int32_t* __restrict__ start)
 {
-    Box6 b;
-    const float v0[3] = {t.f[0].x, t.f[0].y, t.f[0].z};
-    const float e1[3] = {t.f[1].x, t.f[1].y, t.f[1].z};
-    const float e2[3] = {t.f[2].x, t.f[2].y, t.f[2].z};
-    for (int a = 0; a < 3; ++a) {
-        const float p1 = v0[a] + e1[a], p2 = v0[a] + e2[a];
-        b.lo[a] = fminf(v0[a], fminf(p1, p2));
-        b.hi[a] = fmaxf(v0[a], fmaxf(p1, p2));
+    const int32_t p = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= n) return;
+    int32_t first = p;
+    int32_t y = leaf_parent[p];
+    while (y >= 0) {  // the root holds n >= 8 triangles, so the walk stops below it
+        const int2 r = range[y];
+        if (r.y - r.x + 1 > kLbvhLeaf) break;
+        first = r.x;
+        y = parent[y];
     }
-    return b;
+    start[p] = first == p ? 1 : 0;
 }
 
-__device__ __forceinline__ Box6 load_box(const float* b, int32_t i)
+// kept inner nodes in the subtree of inner node x: its leaf records minus one; 0 when x is collapsed
+__device__ __forceinline__ int32_t kept_nodes(const int2* __restrict__ range, const int32_t* __restrict__ scan,
+                                              int32_t x)
 {
-    Box6 r;
-    for (int a = 0; a < 3; ++a) {
-        r.lo[a] = b[6 * i + a];
-        r.hi[a] = b[6 * i + 3 + a];
-    }
-    return r;
+    const int2 r = range[x];
+    if (r.y - r.x + 1 <= kLbvhLeaf) return 0;
+    return scan[r.y + 1] - scan[r.x] - 1;
 }
 
-// Bottom-up: boxes of inner nodes and, per inner node, the number of kept inner nodes in its
-// subtree (0 when its subtree holds at most kLbvhLeaf triangles and becomes a leaf).
-__global__ void k_bottom_up(const TriRec* __restrict__ tris, int32_t n, const int2* __restrict__ child,
-                            const int2* __restrict__ range, const int32_t* __restrict__ parent,
-                            const int32_t* __restrict__ leaf_parent, uint32_t* visits, float* leaf_box,
-                            float* node_box, int32_t* kept)
-{
-    const int32_t k = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (k >= n) return;
-    const Box6 lb = tri_box(tris[k]);
-    for (int a = 0; a < 3; ++a) {
-        leaf_box[6 * k + a] = lb.lo[a];
-        leaf_box[6 * k + 3 + a] = lb.hi[a];
-    }
-    int32_t node = leaf_parent[k];
-    while (node >= 0) {
-        __threadfence();  // this thread's boxes are visible before its arrival is counted
-        const uint32_t seen = atomicAdd(&visits[node], 1u);
-        if (seen == 0) return;  // the sibling subtree is not done; its thread finishes this node
-        __threadfence();  // see the sibling's boxes
-        const int2 c = child[node];
-        const Box6 b0 = c.x >= 0 ? load_box(node_box, c.x) : load_box(leaf_box, ~c.x);
-        const Box6 b1 = c.y >= 0 ? load_box(node_box, c.y) : load_box(leaf_box, ~c.y);
-        for (int a = 0; a < 3; ++a) {
-            node_box[6 * node + a] = fminf(b0.lo[a], b1.lo[a]);
-            node_box[6 * node + 3 + a] = fmaxf(b0.hi[a], b1.hi[a]);
-        }
-        const int2 r = range[node];
-        const int32_t k0 = c.x >= 0 ? kept[c.x] : 0;
-        const int32_t k1 = c.y >= 0 ? kept[c.y] : 0;
-        kept[node] = (r.y - r.x + 1 <= kLbvhLeaf && node != 0) ? 0 : 1 + k0 + k1;
-        node = parent[node];
-    }
-}
-
-// Pre-order node records of the kept inner nodes.  A node is kept when neither it nor an ancestor
-// holds at most kLbvhLeaf triangles (the root always is).
+// Pre-order node records of the kept inner nodes (those holding more than kLbvhLeaf triangles;
+// their ancestors hold more still).
 __global__ void k_emit(int32_t n, const int2* __restrict__ child, const int2* __restrict__ range,
-                       const int32_t* __restrict__ parent, const int32_t* __restrict__ kept,
-                       const float* __restrict__ leaf_box, const float* __restrict__ node_box, float pad,
-                       BvhNode* __restrict__ out, int32_t* __restrict__ depth_out)
+                       const int32_t* __restrict__ parent, const int32_t* __restrict__ scan,
+                       const float* __restrict__ win, float pad, BvhNode* __restrict__ out,
+                       int32_t* __restrict__ depth_out)
 {
     const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n - 1) return;
-    if (kept[i] == 0) return;
+    const int2 ri = range[i];
+    if (ri.y - ri.x + 1 <= kLbvhLeaf) return;
     // position: the root is 0; a left child follows its parent, a right child follows the parent's
     // left subtree
     int32_t pre = 0, depth = 0, node = i;
     while (node != 0) {
         const int32_t p = parent[node];
-        if (kept[p] == 0) return;  // inside a collapsed subtree
         const int2 c = child[p];
         pre += 1;
-        if (c.y == node && c.x >= 0) pre += kept[c.x];
+        if (c.y == node && c.x >= 0) pre += kept_nodes(range, scan, c.x);
         node = p;
         ++depth;
     }
@@ -198,16 +241,17 @@ __global__ void k_emit(int32_t n, const int2* __restrict__ child, const int2* __
         const int32_t ch = kids[slot];
         Box6 b;
         if (ch < 0) {
-            b = load_box(leaf_box, ~ch);
+            b = load_box(win, ~ch);
             codes[slot] = ~((~ch << 3) | 1);
         } else {
-            b = load_box(node_box, ch);
             const int2 r = range[ch];
-            if (kept[ch] == 0) {
+            b = range_box(win, n, r.x, r.y);
+            const int32_t k = kept_nodes(range, scan, ch);
+            if (k == 0) {
                 codes[slot] = ~((r.x << 3) | (r.y - r.x + 1));
             } else {
                 codes[slot] = next;
-                next += kept[ch];
+                next += k;
             }
         }
         const float lx = b.lo[0] - pad, hx = b.hi[0] + pad;
@@ -236,12 +280,15 @@ __global__ void k_fill_words(uint32_t* __restrict__ p, int64_t n, uint32_t v)
 
 }  // namespace
 
-size_t lbvh_sort_bytes(int32_t n)
+size_t lbvh_tmp_bytes(int32_t n)
 {
-    size_t bytes = 0;
-    (void)rocprim::radix_sort_pairs(nullptr, bytes, static_cast<const uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr),
-                              static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr), n, 0, 30);
-    return bytes;
+    size_t sort = 0, scan = 0;
+    (void)rocprim::radix_sort_pairs(nullptr, sort, static_cast<const uint32_t*>(nullptr),
+                                    static_cast<uint32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                                    static_cast<int32_t*>(nullptr), n, 0, 30);
+    (void)rocprim::inclusive_scan(nullptr, scan, static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
+                                  static_cast<size_t>(n), rocprim::plus<int32_t>());
+    return std::max(sort, scan);
 }
 
 hipError_t launch_lbvh(const LbvhArgs& a, hipStream_t stream)
@@ -253,20 +300,31 @@ hipError_t launch_lbvh(const LbvhArgs& a, hipStream_t stream)
                        a.pos);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t bytes = a.sort_bytes;
-    e = rocprim::radix_sort_pairs(a.sort_tmp, bytes, a.keys, a.keys_sorted, a.pos, a.order, n, 0u, 30u, stream);
+    size_t bytes = a.tmp_bytes;
+    e = rocprim::radix_sort_pairs(a.tmp, bytes, a.keys, a.keys_sorted, a.pos, a.order, n, 0u, 30u, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather, dim3(bl), dim3(threads), 0, stream, a.tris_in, a.mat_in, a.perm_in, a.order, n,
-                       a.tris_out, a.mat_out, a.perm_out);
-    hipLaunchKernelGGL(k_fill_words, dim3(bl), dim3(threads), 0, stream, a.visits, static_cast<int64_t>(n), 0u);
-    hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(threads), 0, stream, reinterpret_cast<uint32_t*>(a.depth_out),
-                       int64_t(1), 0u);
+                       a.tris_out, a.mat_out, a.perm_out, a.bvh_pos_out, a.win);
+    for (int32_t k = 1; k < a.levels; ++k) {
+        const int32_t half = 1 << (k - 1);
+        const int32_t count = n - (1 << k) + 1;
+        hipLaunchKernelGGL(k_window, dim3(static_cast<unsigned>((count + threads - 1) / threads)), dim3(threads), 0,
+                           stream, a.win + static_cast<int64_t>(k - 1) * n * 6, a.win + static_cast<int64_t>(k) * n * 6,
+                           count, half);
+    }
     hipLaunchKernelGGL(k_karras, dim3(bl), dim3(threads), 0, stream, a.keys_sorted, n, a.child, a.range, a.parent,
                        a.leaf_parent);
-    hipLaunchKernelGGL(k_bottom_up, dim3(bl), dim3(threads), 0, stream, a.tris_out, n, a.child, a.range, a.parent,
-                       a.leaf_parent, a.visits, a.leaf_box, a.node_box, a.kept);
-    hipLaunchKernelGGL(k_emit, dim3(bl), dim3(threads), 0, stream, n, a.child, a.range, a.parent, a.kept,
-                       a.leaf_box, a.node_box, a.pad, a.nodes_out, a.depth_out);
+    hipLaunchKernelGGL(k_frontier, dim3(bl), dim3(threads), 0, stream, a.range, a.parent, a.leaf_parent, n, a.start);
+    hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(threads), 0, stream, reinterpret_cast<uint32_t*>(a.scan),
+                       int64_t(1), 0u);
+    bytes = a.tmp_bytes;
+    e = rocprim::inclusive_scan(a.tmp, bytes, a.start, a.scan + 1, static_cast<size_t>(n), rocprim::plus<int32_t>(),
+                                stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(threads), 0, stream, reinterpret_cast<uint32_t*>(a.depth_out),
+                       int64_t(1), 0u);
+    hipLaunchKernelGGL(k_emit, dim3(bl), dim3(threads), 0, stream, n, a.child, a.range, a.parent, a.scan, a.win,
+                       a.pad, a.nodes_out, a.depth_out);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct srp_scene_s {
     std::vector<int32_t> perm;           // BVH triangle position -> original index
     std::vector<srp::BvhNode> h_nodes;   // host copies for the instrumented traversal
     std::vector<srp::TriRec> h_tris;
+    bool h_tris_stale = false;           // the device records changed (GPU build); read back on use
     srp::BvhNode* d_nodes = nullptr;
     size_t nodes_cap = 0;
     srp::TriRec* d_tris = nullptr;
@@ -62,6 +63,9 @@ struct srp_scene_s {
     hipEvent_t surf_ev = nullptr;
     srp::SurfaceScene* d_surf_desc = nullptr;
     size_t surf_desc_cap = 0;
+    // GPU BVH build: one workspace block, kept for later rebuilds
+    char* d_lbvh_ws = nullptr;
+    size_t lbvh_ws_cap = 0;
 };
 
 // Records `msg` as the thread's last error and returns `st`.

@@ -186,6 +186,7 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
                            stream));
     SRP_HIP(hipStreamSynchronize(stream));
     s->h_tris = std::move(recs);
+    s->h_tris_stale = false;
     return SRP_OK;
 }
 
@@ -602,82 +603,80 @@ srp_status srp_scene_build_gpu(srp_scene s, int32_t* n_nodes_out, int32_t* depth
     const int32_t n = static_cast<int32_t>(s->n_tris);
     srp::LbvhArgs a{};
     a.n = n;
-    float ext[3];
-    for (int k = 0; k < 3; ++k) ext[k] = static_cast<float>(std::max(s->hi[k] - s->lo[k], 1e-30));
+    // cubic Morton cells (one scale for all axes): per-axis scaling stretches the cells of long,
+    // flat parts such as solar arrays and roughly doubles the tree's surface-area cost
+    const double ext = std::max({s->hi[0] - s->lo[0], s->hi[1] - s->lo[1], s->hi[2] - s->lo[2], 1e-30});
+    const float sc = static_cast<float>(1024.0 / ext);
     a.lo = make_float3(static_cast<float>(s->lo[0]), static_cast<float>(s->lo[1]), static_cast<float>(s->lo[2]));
-    a.scale = make_float3(1024.0f / ext[0], 1024.0f / ext[1], 1024.0f / ext[2]);
+    a.scale = make_float3(sc, sc, sc);
     a.pad = static_cast<float>(1e-6 * s->L);
     a.tris_in = s->d_tris;
     a.mat_in = s->d_mat;
     a.perm_in = s->d_perm;
-    // workspace: one block, carved in 256-byte-aligned pieces
-    a.sort_bytes = srp::lbvh_sort_bytes(n);
+    int32_t levels = 1;
+    while ((int64_t(1) << levels) <= n) ++levels;
+    a.levels = levels;
+    // workspace: one block kept by the scene, carved in 256-byte-aligned pieces
+    a.tmp_bytes = srp::lbvh_tmp_bytes(n);
     const size_t nn = static_cast<size_t>(n);
-    const size_t sizes[] = {4 * nn, 4 * nn, 4 * nn, 4 * nn, a.sort_bytes, 64 * nn, 16 * nn, 4 * nn, 8 * nn, 8 * nn,
-                            4 * nn, 4 * nn, 4 * nn, 24 * nn, 24 * nn, 4 * nn, 64 * nn, 4};
+    const size_t sizes[] = {4 * nn, 4 * nn, 4 * nn, 4 * nn, a.tmp_bytes, 64 * nn, 16 * nn, 4 * nn, 4 * nn,
+                            8 * nn, 8 * nn, 4 * nn, 4 * nn, 4 * nn, 4 * (nn + 1), 24 * nn * levels, 64 * nn, 4};
     size_t total = 0;
     for (size_t z : sizes) total += (z + 255) / 256 * 256;
-    char* ws = nullptr;
-    SRP_HIP(hipMalloc(reinterpret_cast<void**>(&ws), total));
-    size_t off = 0;
-    auto take = [&](size_t z) {
+    SRP_HIP(ensure(s->d_lbvh_ws, s->lbvh_ws_cap, total));
+    char* ws = s->d_lbvh_ws;
+    size_t off = 0, piece = 0;
+    auto take = [&]() {
         char* p = ws + off;
-        off += (z + 255) / 256 * 256;
+        off += (sizes[piece++] + 255) / 256 * 256;
         return p;
     };
-    a.keys = reinterpret_cast<uint32_t*>(take(sizes[0]));
-    a.keys_sorted = reinterpret_cast<uint32_t*>(take(sizes[1]));
-    a.pos = reinterpret_cast<int32_t*>(take(sizes[2]));
-    a.order = reinterpret_cast<int32_t*>(take(sizes[3]));
-    a.sort_tmp = take(sizes[4]);
-    a.tris_out = reinterpret_cast<srp::TriRec*>(take(sizes[5]));
-    a.mat_out = reinterpret_cast<float4*>(take(sizes[6]));
-    a.perm_out = reinterpret_cast<int32_t*>(take(sizes[7]));
-    a.child = reinterpret_cast<int2*>(take(sizes[8]));
-    a.range = reinterpret_cast<int2*>(take(sizes[9]));
-    a.parent = reinterpret_cast<int32_t*>(take(sizes[10]));
-    a.leaf_parent = reinterpret_cast<int32_t*>(take(sizes[11]));
-    a.visits = reinterpret_cast<uint32_t*>(take(sizes[12]));
-    a.leaf_box = reinterpret_cast<float*>(take(sizes[13]));
-    a.node_box = reinterpret_cast<float*>(take(sizes[14]));
-    a.kept = reinterpret_cast<int32_t*>(take(sizes[15]));
-    a.nodes_out = reinterpret_cast<srp::BvhNode*>(take(sizes[16]));
-    a.depth_out = reinterpret_cast<int32_t*>(take(sizes[17]));
+    a.keys = reinterpret_cast<uint32_t*>(take());
+    a.keys_sorted = reinterpret_cast<uint32_t*>(take());
+    a.pos = reinterpret_cast<int32_t*>(take());
+    a.order = reinterpret_cast<int32_t*>(take());
+    a.tmp = take();
+    a.tris_out = reinterpret_cast<srp::TriRec*>(take());
+    a.mat_out = reinterpret_cast<float4*>(take());
+    a.perm_out = reinterpret_cast<int32_t*>(take());
+    a.bvh_pos_out = reinterpret_cast<int32_t*>(take());
+    a.child = reinterpret_cast<int2*>(take());
+    a.range = reinterpret_cast<int2*>(take());
+    a.parent = reinterpret_cast<int32_t*>(take());
+    a.leaf_parent = reinterpret_cast<int32_t*>(take());
+    a.start = reinterpret_cast<int32_t*>(take());
+    a.scan = reinterpret_cast<int32_t*>(take());
+    a.win = reinterpret_cast<float*>(take());
+    a.nodes_out = reinterpret_cast<srp::BvhNode*>(take());
+    a.depth_out = reinterpret_cast<int32_t*>(take());
     hipError_t e = srp::launch_lbvh(a, stream);
-    int32_t count = 0, depth = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&count, a.kept, 4, hipMemcpyDeviceToHost, stream);
+    int32_t records = 0, depth = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&records, a.scan + n, 4, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&depth, a.depth_out, 4, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    const int32_t count = records - 1;  // a full binary tree over its leaf records
     if (e == hipSuccess && (count < 1 || count > n - 1)) e = hipErrorUnknown;
-    if (e != hipSuccess || depth >= srp::kMaxTreeDepth) {
-        (void)hipFree(ws);
-        if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("GPU BVH build: ") + hipGetErrorString(e));
-        return fail(SRP_EUNSUPPORTED, "GPU-built tree deeper than the traversal stack");
-    }
-    // adopt the new tree and record order; refresh the host copies (refit, statistics)
+    if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("GPU BVH build: ") + hipGetErrorString(e));
+    if (depth >= srp::kMaxTreeDepth) return fail(SRP_EUNSUPPORTED, "GPU-built tree deeper than the traversal stack");
+    // adopt the new tree and record order; the host keeps the nodes and the order (refit, statistics)
     std::vector<srp::BvhNode> nodes(count);
     std::vector<int32_t> perm(n);
-    std::vector<srp::TriRec> recs(n);
-    e = hipMemcpy(nodes.data(), a.nodes_out, sizeof(srp::BvhNode) * count, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(perm.data(), a.perm_out, 4 * nn, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(recs.data(), a.tris_out, sizeof(srp::TriRec) * nn, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = ensure(s->d_nodes, s->nodes_cap, static_cast<size_t>(count));
+    e = ensure(s->d_nodes, s->nodes_cap, static_cast<size_t>(count));
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->d_nodes, a.nodes_out, sizeof(srp::BvhNode) * count, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->d_tris, a.tris_out, sizeof(srp::TriRec) * nn, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_mat, a.mat_out, 16 * nn, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_perm, a.perm_out, 4 * nn, hipMemcpyDeviceToDevice, stream);
-    std::vector<int32_t> pos(n);
-    for (int32_t p = 0; p < n; ++p) pos[perm[p]] = p;
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d_bvh_pos, a.bvh_pos_out, 4 * nn, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(s->d_bvh_pos, pos.data(), 4 * nn, hipMemcpyHostToDevice, stream);
+        e = hipMemcpyAsync(nodes.data(), a.nodes_out, sizeof(srp::BvhNode) * count, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), a.perm_out, 4 * nn, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    (void)hipFree(ws);
     if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("GPU BVH build: ") + hipGetErrorString(e));
     s->h_nodes = std::move(nodes);
     s->perm = std::move(perm);
-    s->h_tris = std::move(recs);
+    s->h_tris_stale = true;  // read back when the statistics need them
     s->n_nodes = count;
     s->depth = depth;
     if (n_nodes_out) *n_nodes_out = count;
@@ -830,6 +829,7 @@ srp_status srp_scene_destroy(srp_scene s)
     (void)hipFree(s->d_cum_area);
     (void)hipFree(s->d_bvh_pos);
     (void)hipFree(s->d_surf_desc);
+    (void)hipFree(s->d_lbvh_ws);
     if (s->surf_ev) {
         (void)hipEventSynchronize(s->surf_ev);
         (void)hipEventDestroy(s->surf_ev);

@@ -150,6 +150,7 @@ struct SurfaceArgs {
 constexpr int kLbvhLeaf = 4;    // subtrees of at most this many triangles become one leaf
 struct LbvhArgs {
     int32_t n;
+    int32_t levels;                 // window-table levels: floor(log2 n) + 1
     float3 lo, scale;               // Morton grid: (centroid - lo) * scale in [0, 1024)
     float pad;                      // box widening, metres
     const TriRec* tris_in;          // current order
@@ -159,20 +160,20 @@ struct LbvhArgs {
     uint32_t* keys_sorted;          // [n]
     int32_t* pos;                   // [n]
     int32_t* order;                 // [n] new position -> current position
-    void* sort_tmp;
-    size_t sort_bytes;
+    void* tmp;                      // sort and scan scratch
+    size_t tmp_bytes;
     TriRec* tris_out;               // [n] new order
     float4* mat_out;
-    int32_t* perm_out;
+    int32_t* perm_out;              // [n] new position -> original facet
+    int32_t* bvh_pos_out;           // [n] original facet -> new position
     int2* child;                    // [n - 1] inner index, or ~leaf
     int2* range;                    // [n - 1] first, last leaf
     int32_t* parent;                // [n - 1]
     int32_t* leaf_parent;           // [n]
-    uint32_t* visits;               // [n - 1] (n words cleared)
-    float* leaf_box;                // [n][6]
-    float* node_box;                // [n - 1][6]
-    int32_t* kept;                  // [n - 1] kept inner nodes per subtree; kept[0] = node count
-    BvhNode* nodes_out;             // [n - 1], pre-order, kept[0] of them written
+    int32_t* start;                 // [n] 1 where a leaf opens a leaf record of the final tree
+    int32_t* scan;                  // [n + 1] leaf records opened before each leaf; scan[n] - 1 nodes
+    float* win;                     // [levels][n][6] box of leaves [i, i + 2^level)
+    BvhNode* nodes_out;             // [n - 1], pre-order, scan[n] - 1 of them written
     int32_t* depth_out;             // deepest level (root = 0)
 };
 
@@ -201,7 +202,7 @@ hipError_t launch_trace_batch(const TraceArgs& a, hipStream_t stream);
 hipError_t launch_reduce(const double* partials, int64_t D, int32_t blocks_per_dir, double* force, double* torque,
                          hipStream_t stream);
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream);
-size_t lbvh_sort_bytes(int32_t n);
+size_t lbvh_tmp_bytes(int32_t n);
 hipError_t launch_lbvh(const LbvhArgs& a, hipStream_t stream);
 hipError_t launch_surface(const SurfaceArgs& a, bool brute, double* force, double* torque, hipStream_t stream);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream);
