@@ -288,6 +288,43 @@ srp_status srp_orbit_rk4_adjoint(const double* z0, double mu, double mass, doubl
                                  const double* F_body, const double* R_body_to_inertial, const double* g_final,
                                  int64_t ckpt_every, double* g_F, double* g_z0);
 
+/* ------------------------------------------------------------------------------------------- *
+ * Orbit and attitude together (paper Sec. 3.4.1, Eq. ODE, the 13-D state): many trajectories at
+ * once on the GPU, classic RK4 in FP64, with the force AND torque of every stage taken from a
+ * network (the proxy of Sec. 3.3) evaluated at the stage's body-frame Sun direction:
+ *   dr/dt = v,
+ *   dv/dt = -mu r / |r|^3 + nu R(q) F / mass,
+ *   dq/dt = 1/2 q (x) (0, w),
+ *   dw/dt = I^-1 (nu tau - w x (I w)),
+ * with q = (q0, q1, q2, q3) scalar first, R(q) the rotation of q / |q| (body -> inertial; the
+ * state quaternion is not renormalised), w the body-frame angular velocity, s_body = R(q)^T sun,
+ * network input x = [float(s_body), design row] and output y: F = force_scale y[0..2] (N, body
+ * frame), tau = torque_scale y[3..5] (N m, body frame).  nu is the cylinder eclipse factor: 0 when
+ * r . sun < 0 and |r - (r . sun) sun| < earth_radius, else 1 (earth_radius 0: always 1).
+ * ------------------------------------------------------------------------------------------- */
+typedef struct srp_attitude_params {
+    double mu;            /* gravitational parameter, m^3 / s^2, > 0 */
+    double mass;          /* kg, > 0 */
+    double inertia[9];    /* body-frame inertia tensor, kg m^2, row-major, symmetric positive definite */
+    double sun[3];        /* direction toward the Sun, inertial frame (normalised here), fixed */
+    double force_scale;   /* N per unit of network outputs 0..2 */
+    double torque_scale;  /* N m per unit of network outputs 3..5 */
+    double earth_radius;  /* m; 0 disables the eclipse */
+    double dt;            /* step, s, > 0 */
+    int64_t n_steps;      /* >= 0 */
+} srp_attitude_params;
+
+/* Integrates B trajectories: z0 and z_final device double [B][13] (r, v, q, w; SI units),
+ * design device float [B][n_in - 3] (NULL when the network has 3 inputs), z_all device double
+ * [n_steps + 1][B][13] or NULL.  The network (n_in >= 3, n_out >= 6; extra outputs ignored)
+ * answers 4 n_steps batched queries; its inference path is used, and the integration state lives
+ * in a workspace the network owns (about 360 + 4 n_in bytes per trajectory), so calls that use one
+ * network must be ordered on one stream.  Asynchronous on `stream`; z0 may alias z_final.  Every
+ * trajectory must keep r != 0 and q != 0 (no device check).  Errors: SRP_EINVAL (sizes, params,
+ * inertia not symmetric positive definite, network shape). */
+srp_status srp_attitude_rk4(srp_mlp model, const srp_attitude_params* params, const double* z0,
+                            const float* design, int64_t B, double* z_final, double* z_all, void* stream);
+
 /* Waits for `stream` and reports any pending device error as SRP_EDEVICE. */
 srp_status srp_sync(void* stream);
 

@@ -76,6 +76,25 @@ _lib.srp_last_error.argtypes = []
 _lib.srp_last_error.restype = ctypes.c_char_p
 
 
+class AttitudeParams(ctypes.Structure):
+    """srp_attitude_params (see srp.h)."""
+    _fields_ = [("mu", ctypes.c_double), ("mass", ctypes.c_double), ("inertia", ctypes.c_double * 9),
+                ("sun", ctypes.c_double * 3), ("force_scale", ctypes.c_double), ("torque_scale", ctypes.c_double),
+                ("earth_radius", ctypes.c_double), ("dt", ctypes.c_double), ("n_steps", I64)]
+
+    def __init__(self, mu, mass, inertia, sun, force_scale, torque_scale, dt, n_steps, earth_radius=0.0):
+        super().__init__()
+        self.mu, self.mass = float(mu), float(mass)
+        self.inertia[:] = [float(x) for x in np.asarray(inertia, dtype=np.float64).reshape(9)]
+        self.sun[:] = [float(x) for x in np.asarray(sun, dtype=np.float64).reshape(3)]
+        self.force_scale, self.torque_scale = float(force_scale), float(torque_scale)
+        self.earth_radius, self.dt, self.n_steps = float(earth_radius), float(dt), int(n_steps)
+
+
+_lib.srp_attitude_rk4.argtypes = [P, ctypes.POINTER(AttitudeParams), P, P, I64, P, P, P]
+_lib.srp_attitude_rk4.restype = I32
+
+
 class SRPError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"libsrp status {status}: {msg}")
@@ -510,3 +529,30 @@ def srp_orbit_rk4_adjoint(z0, mu, mass, dt, n_steps, F_body, R, g_final, ckpt_ev
     _check(_lib.srp_orbit_rk4_adjoint(_hptr(z0), float(mu), float(mass), float(dt), int(n_steps), _hptr(F), _hptr(Rm),
                                       _hptr(g), int(ckpt_every), _hptr(gF), _hptr(gz)))
     return gF, gz
+
+
+def srp_attitude_rk4(model, params: AttitudeParams, z0, design, z_final, z_all=None, stream=None):
+    """13-D orbit-and-attitude RK4 with the network as force-and-torque model (see srp.h): z0 and
+    z_final device double [B][13], design device float [B][n_in - 3] (or None), z_all device double
+    [n_steps + 1][B][13] or None."""
+    import torch
+    _dtype_check(z0, torch.float64, "z0")
+    _dtype_check(z_final, torch.float64, "z_final")
+    _dtype_check(z_all, torch.float64, "z_all")
+    _dtype_check(design, torch.float32, "design")
+    if not isinstance(model, Surrogate):
+        raise TypeError("model must be a Surrogate (its shape sizes the design rows)")
+    B = z0.shape[0]
+    nd = model.n_in - 3
+    if tuple(z0.shape) != (B, 13) or tuple(z_final.shape) != (B, 13):
+        raise ValueError("z0 and z_final must be [B][13]")
+    if nd > 0 and (design is None or tuple(design.shape) != (B, nd)):
+        raise ValueError(f"design must be [B][{nd}]")
+    if z_all is not None and tuple(z_all.shape) != (params.n_steps + 1, B, 13):
+        raise ValueError("z_all must be [n_steps + 1][B][13]")
+    for t in (z0, design, z_final, z_all):
+        if t is not None and not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+    h = model.handle
+    _check(_lib.srp_attitude_rk4(h, ctypes.byref(params), _dptr(z0), _dptr(design), z0.shape[0], _dptr(z_final),
+                                 _dptr(z_all), _stream(stream)))

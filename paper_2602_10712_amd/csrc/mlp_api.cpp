@@ -68,6 +68,9 @@ struct srp_mlp_s {
     float* d_col = nullptr;
     double* d_lpart = nullptr;
     int64_t cached_N = -1;
+    // workspace of callers that use the network as a model (attitude integration)
+    char* d_aux = nullptr;
+    size_t cap_aux = 0;
 };
 
 namespace {
@@ -400,6 +403,28 @@ srp_status srp_mlp_mse(srp_mlp m, const float* y, const float* target, int64_t N
     return SRP_OK;
 }
 
+}  // extern "C"
+
+namespace srp {
+
+void mlp_shape(const srp_mlp_s* m, int* n_in, int* n_out, int* device)
+{
+    *n_in = m->n_in;
+    *n_out = m->n_out;
+    *device = m->device;
+}
+
+hipError_t mlp_aux(srp_mlp_s* m, size_t bytes, void** out)
+{
+    hipError_t e = grow(m->d_aux, m->cap_aux, bytes);
+    *out = m->d_aux;
+    return e;
+}
+
+}  // namespace srp
+
+extern "C" {
+
 srp_status srp_mlp_destroy(srp_mlp m)
 {
     if (!m) return SRP_OK;
@@ -408,7 +433,8 @@ srp_status srp_mlp_destroy(srp_mlp m)
                     static_cast<void*>(m->d_v), static_cast<void*>(m->d_wb), static_cast<void*>(m->d_xb),
                     static_cast<void*>(m->d_Z), static_cast<void*>(m->d_A), static_cast<void*>(m->d_G),
                     static_cast<void*>(m->d_Gb), static_cast<void*>(m->d_col), static_cast<void*>(m->d_lpart),
-                    static_cast<void*>(m->d_wf), static_cast<void*>(m->d_wf_off), static_cast<void*>(m->d_b_off)})
+                    static_cast<void*>(m->d_wf), static_cast<void*>(m->d_wf_off), static_cast<void*>(m->d_b_off),
+                    static_cast<void*>(m->d_aux)})
         if (p) (void)hipFree(p);
     delete m;
     return SRP_OK;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct srp_mlp_s;
+
 namespace srp {
 
 enum GemmEpilogue : int32_t {
@@ -49,5 +51,10 @@ hipError_t launch_pack_mfma(const float* W, int out, int in, int layer, int dept
 hipError_t launch_mlp_infer(const float* x, int32_t N, const uint16_t* wf, const int64_t* wf_off_dev,
                             const float* params, const int64_t* b_off_dev, int n_in, int depth, int n_out, float* y,
                             hipStream_t stream);
+
+// The network as a model inside other integrators: its shape and a workspace it owns (grown on
+// demand, freed with the network; calls using one network must be ordered).
+void mlp_shape(const srp_mlp_s* m, int* n_in, int* n_out, int* device);
+hipError_t mlp_aux(srp_mlp_s* m, size_t bytes, void** out);
 
 }  // namespace srp

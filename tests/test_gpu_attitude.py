@@ -1,0 +1,200 @@
+"""GPU 13-D orbit-and-attitude integration (srp_attitude_rk4) vs the FP64 oracle, through the C ABI.
+
+Bars:
+  * network scaled to zero (gravity, rigid-body rotation, quaternion kinematics only): every state
+    component within 1e-10 of its block's norm -- both sides are FP64 RK4, only rounding differs;
+  * with the network as force-and-torque model: the difference between GPU and oracle states is at
+    most 2e-3 of the change the radiation causes (position, velocity, quaternion, rate; L2 over all
+    trajectories).  The network itself agrees with the oracle network to 1e-3 relative L2 (BF16
+    rounding flips of hidden activations), and over these horizons the radiation's effect is
+    linear in the network output to first order;
+  * the same with the cylinder eclipse on low orbits that pass behind the Earth;
+  * recorded states: z_all[0] = z0, z_all[n] = z_final bit for bit; n_steps = 0 copies z0; z0 may
+    alias z_final; a ragged batch (not a multiple of 256);
+  * at the benchmark's size (16,384 trajectories, 2,880 steps of 15 s), 4 sampled trajectories
+    against the oracle over the full 12 h;
+  * invalid arguments raise before anything is launched.
+"""
+import numpy as np
+import pytest
+
+from oracle import attitude as att
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MU = 3.986004418e14
+RE = 6378137.0
+INERTIA = np.array([[900.0, 12.0, -5.0], [12.0, 1300.0, 8.0], [-5.0, 8.0, 1600.0]])
+
+
+def initial_states(B, seed, radius=2.656e7, spread=0.05, in_plane_sun=None):
+    """Near-circular orbits of random orientation, random attitudes and body rates."""
+    rng = np.random.default_rng(seed)
+    z = np.zeros((B, 13))
+    for b in range(B):
+        n = rng.normal(size=3)
+        if in_plane_sun is not None:  # orbit plane containing the Sun direction
+            n = np.cross(in_plane_sun, rng.normal(size=3))
+        n /= np.linalg.norm(n)
+        u = np.cross(n, rng.normal(size=3))
+        u /= np.linalg.norm(u)
+        r = radius * (1 + spread * rng.uniform(-1, 1))
+        z[b, :3] = r * u
+        z[b, 3:6] = np.sqrt(MU / r) * np.cross(n, u)
+    q = rng.normal(size=(B, 4))
+    z[:, 6:10] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    z[:, 10:13] = rng.uniform(-0.02, 0.02, size=(B, 3))
+    return z
+
+
+def make_net(seed):
+    import paper_2602_10712_amd as p
+    net = p.Surrogate(n_in=11, width=256, depth=4, n_out=6, seed=seed)
+    layers = omlp.unpack(p.srp_mlp_get_params(net.handle)["params"].astype(np.float64), 11, 256, 4, 6)
+    return net, layers
+
+
+def run_gpu(net, prm, z0, design, keep=False):
+    import paper_2602_10712_amd as p
+    dev = torch.device("cuda")
+    z0d = torch.as_tensor(z0, dtype=torch.float64, device=dev).contiguous()
+    dd = torch.as_tensor(design, dtype=torch.float32, device=dev).contiguous()
+    zf = torch.empty_like(z0d)
+    za = torch.empty((prm.n_steps + 1,) + tuple(z0d.shape), dtype=torch.float64, device=dev) if keep else None
+    p.srp_attitude_rk4(net, prm, z0d, dd, zf, za)
+    torch.cuda.synchronize()
+    return (zf.cpu().numpy(), za.cpu().numpy()) if keep else zf.cpu().numpy()
+
+
+def blocks(z):
+    return {"r": z[..., 0:3], "v": z[..., 3:6], "q": z[..., 6:10], "w": z[..., 10:13]}
+
+
+def params(fs, ts, dt, n, re=0.0, sun=(0.3, -0.5, 0.81)):
+    import paper_2602_10712_amd as p
+    return p.AttitudeParams(MU, 1000.0, INERTIA, sun, fs, ts, dt, n, earth_radius=re)
+
+
+def oracle_run(layers, prm, z0, design, fs=None, ts=None):
+    fs = prm.force_scale if fs is None else fs
+    ts = prm.torque_scale if ts is None else ts
+    if fs == 0.0 and ts == 0.0:  # no radiation: the network's answer is scaled away
+        def model(s_body, d):
+            return np.zeros_like(s_body), np.zeros_like(s_body)
+    else:
+        model = att.mlp_model(layers, fs, ts)
+    return att.rk4(z0, np.asarray(design, dtype=np.float32).astype(np.float64), model, mu=prm.mu, mass=prm.mass,
+                   inertia=INERTIA, sun=np.array(list(prm.sun)) / np.linalg.norm(list(prm.sun)), dt=prm.dt,
+                   n_steps=prm.n_steps, earth_radius=prm.earth_radius)
+
+
+def check_effect(g, ref, free, bar=2e-3, label=""):
+    for k in ("r", "v", "q", "w"):
+        d = np.linalg.norm(blocks(g)[k] - blocks(ref)[k])
+        eff = np.linalg.norm(blocks(ref)[k] - blocks(free)[k])
+        print(f"  {label} {k}: |gpu - oracle| {d:.3e}, radiation effect {eff:.3e}, ratio {d / eff:.2e}")
+        assert eff > 0 and d <= bar * eff, k
+
+
+def test_free_motion_matches_oracle_fp64():
+    net, layers = make_net(1)
+    B = 300
+    z0 = initial_states(B, 11)
+    design = np.random.default_rng(2).uniform(-1, 1, (B, 8))
+    prm = params(0.0, 0.0, 30.0, 100)
+    g = run_gpu(net, prm, z0, design)
+    ref = oracle_run(layers, prm, z0, design)
+    for k in ("r", "v", "q", "w"):
+        d = np.abs(blocks(g)[k] - blocks(ref)[k]).max()
+        scale = np.linalg.norm(blocks(ref)[k], axis=-1).max()
+        print(f"free {k}: max |gpu - oracle| {d:.3e} of {scale:.3e}")
+        assert d <= 1e-10 * scale, k
+    net.close()
+
+
+@pytest.mark.parametrize("eclipse", [False, True])
+def test_network_driven_matches_oracle(eclipse):
+    net, layers = make_net(3)
+    B = 300
+    sun = np.array([0.3, -0.5, 0.81])
+    sun /= np.linalg.norm(sun)
+    if eclipse:  # low orbits in planes holding the Sun direction: about a third of each orbit in shadow
+        z0 = initial_states(B, 12, radius=7.0e6, spread=0.02, in_plane_sun=sun)
+        prm = params(5e-5, 2e-5, 10.0, 360, re=RE, sun=sun)
+    else:
+        z0 = initial_states(B, 13)
+        prm = params(5e-5, 2e-5, 30.0, 120, sun=sun)
+    design = np.random.default_rng(4).uniform(-1, 1, (B, 8))
+    g, za = run_gpu(net, prm, z0, design, keep=True)
+    ref = oracle_run(layers, prm, z0, design)
+    free = oracle_run(layers, prm, z0, design, fs=0.0, ts=0.0)
+    check_effect(g, ref, free, label="eclipse" if eclipse else "sunlit")
+    assert np.array_equal(za[0], z0) and np.array_equal(za[-1], g)
+    if eclipse:  # the shadow does switch the radiation off: the sunlit-only run differs
+        lit = oracle_run(layers, params(5e-5, 2e-5, 10.0, 360, re=0.0, sun=sun), z0, design)
+        assert np.linalg.norm(blocks(lit)["v"] - blocks(ref)["v"]) > 0.1 * np.linalg.norm(
+            blocks(ref)["v"] - blocks(free)["v"])
+    net.close()
+
+
+def test_zero_steps_alias_and_ragged():
+    import paper_2602_10712_amd as p
+    net, _ = make_net(5)
+    B = 257
+    z0 = initial_states(B, 14)
+    design = np.zeros((B, 8))
+    assert np.array_equal(run_gpu(net, params(1e-4, 1e-4, 10.0, 0), z0, design), z0)
+    dev = torch.device("cuda")
+    zd = torch.as_tensor(z0, device=dev).contiguous()
+    dd = torch.zeros((B, 8), dtype=torch.float32, device=dev)
+    ref = run_gpu(net, params(1e-4, 1e-4, 10.0, 7), z0, design)
+    p.srp_attitude_rk4(net, params(1e-4, 1e-4, 10.0, 7), zd, dd, zd)  # z0 aliases z_final
+    torch.cuda.synchronize()
+    assert np.array_equal(zd.cpu().numpy(), ref)
+    one = run_gpu(net, params(1e-4, 1e-4, 10.0, 7), z0[100:101], design[100:101])
+    assert np.array_equal(one[0], ref[100])  # trajectories are independent of the batch
+    net.close()
+
+
+def test_full_size_sampled_trajectories():
+    net, layers = make_net(7)
+    B, n = 16384, 2880
+    z0 = initial_states(B, 15)
+    design = np.random.default_rng(6).uniform(-1, 1, (B, 8))
+    prm = params(5e-5, 2e-5, 15.0, n)
+    g = run_gpu(net, prm, z0, design)
+    idx = np.array([0, 5000, 12345, B - 1])
+    ref = oracle_run(layers, prm, z0[idx], design[idx])
+    free = oracle_run(layers, prm, z0[idx], design[idx], fs=0.0, ts=0.0)
+    check_effect(g[idx], ref, free, label="12 h")
+    net.close()
+
+
+def test_invalid_arguments():
+    import paper_2602_10712_amd as p
+    net, _ = make_net(8)
+    dev = torch.device("cuda")
+    z = torch.zeros((4, 13), dtype=torch.float64, device=dev)
+    d = torch.zeros((4, 8), dtype=torch.float32, device=dev)
+    bad = params(1e-4, 1e-4, 10.0, 3)
+    bad.inertia[1] = 50.0  # not symmetric
+    with pytest.raises(p.SRPError):
+        p.srp_attitude_rk4(net, bad, z, d, z)
+    neg = params(1e-4, 1e-4, 10.0, 3)
+    neg.inertia[0] = -1.0
+    with pytest.raises(p.SRPError):
+        p.srp_attitude_rk4(net, neg, z, d, z)
+    with pytest.raises(p.SRPError):
+        p.srp_attitude_rk4(net, params(1e-4, 1e-4, -1.0, 3), z, d, z)
+    with pytest.raises(ValueError):
+        p.srp_attitude_rk4(net, params(1e-4, 1e-4, 10.0, 3), z, d[:3], z)
+    with pytest.raises(ValueError):
+        p.srp_attitude_rk4(net, params(1e-4, 1e-4, 10.0, 3), z, d, z, z_all=torch.zeros((3, 4, 13), device=dev,
+                                                                                         dtype=torch.float64))
+    small = p.Surrogate(n_in=11, width=256, depth=4, n_out=3, seed=1)
+    with pytest.raises(p.SRPError):
+        p.srp_attitude_rk4(small, params(1e-4, 1e-4, 10.0, 3), z, d, z)
+    small.close()
+    net.close()
