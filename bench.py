@@ -11,7 +11,10 @@ Prints ONE JSON line (see the design notes for the field definitions):
   surrogate        fused MLP surrogate evals/s on 1M queries, with its MFMA roofline fraction
   batched          one launch over 256 design variants (2k-50k tris) x 256 dirs x 512^2 rays
   orbit            one design-gradient iteration through a day of RK4 orbit (2881 directions, 512^2)
-  surface          the paper's surface-sampling estimator: samples/s with the BVH and by brute force
+  surface          the paper's surface-sampling estimator: samples/s with the BVH and by brute force;
+                   the GPU BVH build and what its tree costs the walks
+  attitude         13-D orbit-and-attitude RK4 (FP64) with the network answering force and torque at
+                   every stage: trajectory-steps/s for 65,536 trajectories x 2,880 steps of 15 s
   roofline         dominant kernel (k_trace): algorithmic bytes per launch / mean launch time
   cpu_baseline     the FP64 oracle on a bounded sample of the same workload, host cores
 """
@@ -92,6 +95,9 @@ def parse():
     ap.add_argument("--no-orbit", action="store_true")
     ap.add_argument("--no-surface", action="store_true")
     ap.add_argument("--no-surrogate-training", action="store_true")
+    ap.add_argument("--no-attitude", action="store_true")
+    ap.add_argument("--attitude-batch", type=int, default=65536)
+    ap.add_argument("--attitude-steps", type=int, default=2880)
     ap.add_argument("--batch-designs", type=int, default=256)
     ap.add_argument("--batch-dirs", type=int, default=256)
     ap.add_argument("--batch-grid", type=int, default=512)
@@ -299,6 +305,70 @@ def main():
             log(f"surrogate training: {ms_t:.3f} ms per Adam step of {bt} samples, {bt / ms_t / 1e3:.2f} M samples/s")
         net.close()
 
+    # ---- 13-D orbit and attitude: RK4 in FP64 with the network answering force and torque ---------
+    attitude = None
+    if not args.no_attitude:
+        B_a, n_a, dt_a = args.attitude_batch, args.attitude_steps, 15.0
+        net_a = p.Surrogate(11, 256, 4, 6, seed=1)
+        z0_a = torch.as_tensor(si.attitude_states(B_a, 21), dtype=torch.float64, device=dev).contiguous()
+        gen_a = np.random.default_rng(22)
+        des_a = torch.as_tensor(gen_a.uniform(-1, 1, (B_a, 8)), dtype=torch.float32, device=dev).contiguous()
+        zf_a = torch.empty_like(z0_a)
+
+        def att_params(n):
+            return p.AttitudeParams(si.MU_EARTH, 1000.0, si.ATTITUDE_INERTIA, (0.3, -0.5, 0.81), 5e-5, 2e-5, dt_a, n,
+                                    earth_radius=6378137.0)
+
+        p.srp_attitude_rk4(net_a, att_params(8), z0_a, des_a, zf_a, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        ea0 = torch.cuda.Event(enable_timing=True)
+        ea1 = torch.cuda.Event(enable_timing=True)
+        ea0.record(stream)
+        p.srp_attitude_rk4(net_a, att_params(n_a), z0_a, des_a, zf_a, stream=stream.cuda_stream)
+        ea1.record(stream)
+        torch.cuda.synchronize()
+        ms_a = ea0.elapsed_time(ea1)
+        # the network call at this batch on its own (same inputs shape), for the split of a stage
+        xa = torch.zeros((B_a, 11), dtype=torch.float32, device=dev)
+        xa[:, :3] = torch.nn.functional.normalize(torch.randn((B_a, 3), device=dev), dim=1)
+        ya = torch.empty((B_a, 6), dtype=torch.float32, device=dev)
+        p.srp_mlp_forward(net_a.handle, xa, ya, False, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        # launched from Python one by one the calls cannot keep up with the GPU, so the 200 calls are
+        # captured once into a HIP graph (inference allocates and clears nothing) and replayed
+        n_m = 200
+        ms_m = None
+        try:
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                cap = torch.cuda.current_stream()
+                for i in range(n_m):
+                    p.srp_mlp_forward(net_a.handle, xa, ya, False, stream=cap.cuda_stream)
+            graph.replay()
+            torch.cuda.synchronize()
+            ea0.record(stream)
+            graph.replay()
+            ea1.record(stream)
+            torch.cuda.synchronize()
+            ms_m = ea0.elapsed_time(ea1) / n_m
+            del graph
+        except RuntimeError as e:
+            log(f"attitude: graph timing of the network call unavailable: {e!r}")
+        stages = 4 * n_a
+        flop_q = 2.0 * (11 * 256 + 3 * 256 * 256 + 256 * 6)
+        tf_m = flop_q * B_a / (ms_m * 1e-3) / 1e12 if ms_m else None
+        attitude = {
+            "value": round(B_a * n_a / (ms_a * 1e-3), 1), "unit": "trajectory-steps/s", "ms": round(ms_a, 2),
+            "network_evals_per_s": round(stages * B_a / (ms_a * 1e-3), 1),
+            "ms_per_stage": round(ms_a / stages, 5), "network_ms_per_call": round(ms_m, 5) if ms_m else None,
+            "network_roofline": {"bound": "mfma", "achieved": round(tf_m, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                                 "frac": round(tf_m / 2500.0, 4)} if tf_m else None,
+            "workload": f"{B_a} trajectories x {n_a} RK4 steps of {dt_a:.0f} s (12 h), 13-D FP64 state, network "
+                        "11 -> 4 x 256 -> 6 (force, torque) at every stage, cylinder eclipse"}
+        log(f"attitude: {ms_a:.1f} ms for {B_a} x {n_a} steps, {attitude['value'] / 1e6:.1f} M trajectory-steps/s, "
+            f"{ms_a / stages * 1e3:.1f} us per stage (network {ms_m * 1e3 if ms_m else float('nan'):.1f} us)")
+        net_a.close()
+
     # ---- batched designs: 256 MEO-style variants, 256 directions each, one launch ---------------
     batched = None
     if not args.no_batch:
@@ -485,6 +555,23 @@ def main():
                "sample": f"{n_s} of the {D} directions x {g_s}x{g_s} rays, {args.bounces} bounces, FP64 brute force, "
                          f"{cpu_s:.1f} s"}
         log(f"cpu baseline: {cpu_mrays:.4f} Mrays/s on {cores} threads ({cpu_s:.1f} s)")
+        if attitude is not None:
+            # the 13-D integration of the oracle (numpy FP64, BF16-emulating network) on 2 trajectories
+            from oracle import attitude as oatt
+            from oracle import mlp as omlp
+            net_c = p.Surrogate(11, 256, 4, 6, seed=1)
+            layers = omlp.unpack(p.srp_mlp_get_params(net_c.handle)["params"].astype(np.float64), 11, 256, 4, 6)
+            net_c.close()
+            n_c = 240
+            zc = si.attitude_states(2, 21)
+            dc = np.random.default_rng(22).uniform(-1, 1, (2, 8)).astype(np.float32).astype(np.float64)
+            sun_c = np.array([0.3, -0.5, 0.81]) / np.linalg.norm([0.3, -0.5, 0.81])
+            t0 = time.perf_counter()
+            oatt.rk4(zc, dc, oatt.mlp_model(layers, 5e-5, 2e-5), mu=si.MU_EARTH, mass=1000.0,
+                     inertia=si.ATTITUDE_INERTIA, sun=sun_c, dt=15.0, n_steps=n_c, earth_radius=6378137.0)
+            att_s = time.perf_counter() - t0
+            cpu["attitude"] = {"value": round(2 * n_c / att_s, 2), "unit": "trajectory-steps/s", "cores": 1,
+                               "sample": f"2 trajectories x {n_c} steps, {att_s:.1f} s"}
 
     out = {
         "metric": METRIC, "value": round(mrays, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
@@ -495,7 +582,7 @@ def main():
                    "tris": mesh.n_tris, "dirs": D, "grid": args.grid, "bounces": args.bounces,
                    "bvh_nodes": info["n_nodes"], "bvh_build_s": round(build_s, 4)},
         "roofline": roofline, "cpu_baseline": cpu, "fwd_adjoint": fwd_adj,
-        "surrogate": surrogate, "batched": batched, "orbit": orbit, "surface": surface,
+        "surrogate": surrogate, "batched": batched, "orbit": orbit, "surface": surface, "attitude": attitude,
     }
     print(json.dumps(out), flush=True)
 

@@ -7,7 +7,7 @@ is sent back to the tracer when it lies outside the training box of the design s
 independently trained networks disagree by more than a threshold calibrated on held-out data.
 
 Inputs: x = [s_x, s_y, s_z, design scaled to [-1, 1] (8)]; outputs: F / F_ref with
-F_ref = Phi * A_ref / c.  All compute runs in libsrp; this module only sequences the calls.
+F_ref = Phi * A_ref / c (and, for networks that also answer torque, tau / (F_ref L_ref)).  All compute runs in libsrp; this module only sequences the calls.
 """
 from __future__ import annotations
 
@@ -26,22 +26,26 @@ def input_features(sun, theta, lo, hi):
     return np.concatenate([sun, scaled], 1).astype(np.float32)
 
 
-def generate_samples(mesh, designs, sun_per_design, params: B.TraceParams, flux=1361.0):
+def generate_samples(mesh, designs, sun_per_design, params: B.TraceParams, flux=1361.0, torque=False):
     """Traces every design for its own sun directions: designs [N_d][8], sun_per_design
-    [N_d][K][3] -> forces [N_d][K][3] (N, FP64, body frame)."""
+    [N_d][K][3] -> forces [N_d][K][3] (N, FP64, body frame), and with torque=True also the torques
+    about the centre of mass [N_d][K][3] (N m)."""
     scene = B.Scene.from_mesh(mesh)
     group = np.asarray(mesh.group)
     out = np.zeros((len(designs), sun_per_design.shape[1], 3))
+    out_t = np.zeros_like(out) if torque else None
     for d, th in enumerate(designs):
         rs = th[2 + 2 * group].astype(np.float32)
         rd = th[3 + 2 * group].astype(np.float32)
         scene.set_design(rs, rd, hinge_angles=th[:2])
         p = B.TraceParams(params.nu, params.nv, params.bounces, params.jitter, flux, params.seed,
                           0, d, params.frame_mode, params.tiles_per_wave)
-        F, _ = scene.trace(sun_per_design[d], p)
+        F, T = scene.trace(sun_per_design[d], p)
         out[d] = F.cpu().numpy()
+        if torque:
+            out_t[d] = T.cpu().numpy()
     scene.close()
-    return out
+    return (out, out_t) if torque else out
 
 
 def train(net: B.Surrogate, x, y, steps, batch=4096, lr=1e-3, lr_final=1e-5, seed=0, log_every=0):

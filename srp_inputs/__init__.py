@@ -381,3 +381,28 @@ def meo_orbit(n_steps: int = 1440, dt: float = 60.0, radius: float = 26_560_000.
     sun_body = np.ascontiguousarray(np.einsum("kij,i->kj", R, sun))
     return OrbitScenario(z0=z0, mu=MU_EARTH, mass=mass, dt=dt, n_steps=n_steps, R=R, sun_body=sun_body,
                          sun_inertial=sun)
+
+
+# body-frame inertia tensor of a 1000 kg bus with deployed arrays (kg m^2), slightly off-principal
+ATTITUDE_INERTIA = np.array([[900.0, 12.0, -5.0], [12.0, 1300.0, 8.0], [-5.0, 8.0, 1600.0]])
+
+
+def attitude_states(B: int, seed: int, radius: float = 2.656e7, spread: float = 0.05, sun_plane=None) -> np.ndarray:
+    """B seeded 13-D states (r, v, q, w): near-circular orbits of radius radius (1 +- spread) in
+    random planes (planes holding `sun_plane` when given, so that low orbits cross the shadow),
+    random unit attitude quaternions and body rates uniform in +-0.02 rad/s."""
+    rng = np.random.default_rng(seed)
+    z = np.zeros((B, 13))
+    n = rng.normal(size=(B, 3))
+    if sun_plane is not None:
+        n = np.cross(np.asarray(sun_plane, dtype=np.float64), n)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    u = np.cross(n, rng.normal(size=(B, 3)))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    r = radius * (1 + spread * rng.uniform(-1, 1, size=(B, 1)))
+    z[:, :3] = r * u
+    z[:, 3:6] = np.sqrt(MU_EARTH / r) * np.cross(n, u)
+    q = rng.normal(size=(B, 4))
+    z[:, 6:10] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    z[:, 10:13] = rng.uniform(-0.02, 0.02, size=(B, 3))
+    return z

@@ -11,7 +11,7 @@ Bars:
   * the same with the cylinder eclipse on low orbits that pass behind the Earth;
   * recorded states: z_all[0] = z0, z_all[n] = z_final bit for bit; n_steps = 0 copies z0; z0 may
     alias z_final; a ragged batch (not a multiple of 256);
-  * at the benchmark's size (16,384 trajectories, 2,880 steps of 15 s), 4 sampled trajectories
+  * at the benchmark's size (65,536 trajectories, 2,880 steps of 15 s), 4 sampled trajectories
     against the oracle over the full 12 h;
   * invalid arguments raise before anything is launched.
 """
@@ -20,33 +20,18 @@ import pytest
 
 from oracle import attitude as att
 from oracle import mlp as omlp
+import srp_inputs as si
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 MU = 3.986004418e14
 RE = 6378137.0
-INERTIA = np.array([[900.0, 12.0, -5.0], [12.0, 1300.0, 8.0], [-5.0, 8.0, 1600.0]])
+INERTIA = si.ATTITUDE_INERTIA
 
 
 def initial_states(B, seed, radius=2.656e7, spread=0.05, in_plane_sun=None):
-    """Near-circular orbits of random orientation, random attitudes and body rates."""
-    rng = np.random.default_rng(seed)
-    z = np.zeros((B, 13))
-    for b in range(B):
-        n = rng.normal(size=3)
-        if in_plane_sun is not None:  # orbit plane containing the Sun direction
-            n = np.cross(in_plane_sun, rng.normal(size=3))
-        n /= np.linalg.norm(n)
-        u = np.cross(n, rng.normal(size=3))
-        u /= np.linalg.norm(u)
-        r = radius * (1 + spread * rng.uniform(-1, 1))
-        z[b, :3] = r * u
-        z[b, 3:6] = np.sqrt(MU / r) * np.cross(n, u)
-    q = rng.normal(size=(B, 4))
-    z[:, 6:10] = q / np.linalg.norm(q, axis=1, keepdims=True)
-    z[:, 10:13] = rng.uniform(-0.02, 0.02, size=(B, 3))
-    return z
+    return si.attitude_states(B, seed, radius=radius, spread=spread, sun_plane=in_plane_sun)
 
 
 def make_net(seed):
@@ -160,12 +145,12 @@ def test_zero_steps_alias_and_ragged():
 
 def test_full_size_sampled_trajectories():
     net, layers = make_net(7)
-    B, n = 16384, 2880
+    B, n = 65536, 2880
     z0 = initial_states(B, 15)
     design = np.random.default_rng(6).uniform(-1, 1, (B, 8))
     prm = params(5e-5, 2e-5, 15.0, n)
     g = run_gpu(net, prm, z0, design)
-    idx = np.array([0, 5000, 12345, B - 1])
+    idx = np.array([0, 5000, 40000, B - 1])
     ref = oracle_run(layers, prm, z0[idx], design[idx])
     free = oracle_run(layers, prm, z0[idx], design[idx], fs=0.0, ts=0.0)
     check_effect(g[idx], ref, free, label="12 h")

@@ -1,0 +1,71 @@
+"""Force AND torque from one network (the proxy of Sec. 3.3 returns both): an 11 -> 4 x 256 -> 6
+network trained with the library's kernels on tracer samples of random designs, checked on held-out
+(direction, design) pairs against the tracer at 1024^2 rays, 3 bounces.
+
+Bars: force and torque relative RMS <= 2 %, and the torque below the error of the 128^2-ray labels
+it was trained on (the network averages label noise away).  The paper reports its proxy at about
+3-4 % average relative error (Tab. NNError); sharing one 256-wide network between force and torque
+costs force accuracy against the force-only network (which keeps its 1 % bar): measured 1.6 %
+force, 1.0 % torque.
+Torque about the centre of mass is a small difference of large moments (|tau| / |F| ~ 0.05-0.1 m on
+this satellite), so its relative label noise is several times the force's.
+
+Training set: 2048 random designs x 128 random sun directions traced at 128^2 rays; two networks
+averaged, 30,000 Adam steps of 4096 samples each (cosine decay from 1e-3); outputs F / F_ref and tau / (F_ref L_ref), L_ref =
+0.1 m.  Held out: 128 new designs x 16 new directions."""
+import time
+
+import numpy as np
+import pytest
+
+import srp_inputs as si
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+PHI, C = 1361.0, 299792458.0
+
+
+def test_force_torque_network_matches_tracer():
+    import paper_2602_10712_amd as p
+    from paper_2602_10712_amd import surrogate as S
+    mesh = si.meo_satellite()
+    lo, hi = si.DESIGN_LO, si.DESIGN_HI
+    f_ref = PHI * 20.0 / C
+    t_ref = f_ref * 0.1
+    n_d, k = 2048, 128
+    designs = si.random_designs(n_d, seed=14)
+    sun = si.random_dirs(n_d * k, seed=141).reshape(n_d, k, 3)
+    t0 = time.perf_counter()
+    F, T = S.generate_samples(mesh, designs, sun, p.TraceParams(nu=128, nv=128, bounces=3, seed=11), torque=True)
+    gen_s = time.perf_counter() - t0
+    x = S.input_features(sun.reshape(-1, 3), np.repeat(designs, k, 0), lo, hi)
+    y = np.concatenate([F.reshape(-1, 3) / f_ref, T.reshape(-1, 3) / t_ref], 1).astype(np.float32)
+    designs_t = si.random_designs(128, seed=15)
+    sun_t = si.random_dirs(128 * 16, seed=151).reshape(128, 16, 3)
+    F_t, T_t = S.generate_samples(mesh, designs_t, sun_t, p.TraceParams(nu=1024, nv=1024, bounces=3, seed=12),
+                                  torque=True)
+    F_t, T_t = F_t.reshape(-1, 3), T_t.reshape(-1, 3)
+    F_l, T_l = S.generate_samples(mesh, designs_t, sun_t, p.TraceParams(nu=128, nv=128, bounces=3, seed=13),
+                                  torque=True)
+    label_f, label_t = S.rel_rms(F_l.reshape(-1, 3), F_t), S.rel_rms(T_l.reshape(-1, 3), T_t)
+    x_t = S.input_features(sun_t.reshape(-1, 3), np.repeat(designs_t, 16, 0), lo, hi)
+    # two networks averaged, the recipe of the force-only surrogate
+    t0 = time.perf_counter()
+    outs = []
+    xq = torch.as_tensor(x_t, device="cuda")
+    for s in range(2):
+        net = p.Surrogate(11, 256, 4, 6, seed=300 + s)
+        S.train(net, x, y, steps=30000, batch=4096, lr=1e-3, seed=3 + s)
+        outs.append(net.forward(xq).double().cpu().numpy())
+        net.close()
+        print(f"network {s}: force {S.rel_rms(outs[-1][:, :3] * f_ref, F_t):.4f}, torque "
+              f"{S.rel_rms(outs[-1][:, 3:] * t_ref, T_t):.4f}", flush=True)
+    train_s = time.perf_counter() - t0
+    out = 0.5 * (outs[0] + outs[1])
+    err_f = S.rel_rms(out[:, :3] * f_ref, F_t)
+    err_t = S.rel_rms(out[:, 3:] * t_ref, T_t)
+    print(f"samples {len(x)} (generation {gen_s:.1f} s), training {train_s:.1f} s; held-out relative RMS: force "
+          f"{err_f:.4f} (128^2 labels {label_f:.4f}), torque {err_t:.4f} (128^2 labels {label_t:.4f})")
+    assert err_f <= 0.02
+    assert err_t <= 0.02 and err_t < label_t
