@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SRP Mrays/s (20k tri, 3 bounce) fwd & fwd+adjoint; surrogate force evals/s"
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 39.3  # non-packed FP32 lane-ops: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ADJ_ATOMIC_BYTES = 16.0  # at most two FP64 gradient updates per hit
 
 
@@ -77,6 +78,12 @@ def measured_l2_hit_rate():
     """L2 hit rate of k_trace on the benchmark workload (TCC_HIT / (TCC_HIT + TCC_MISS))."""
     rec = profile_record("k_trace_meo20k_counters.md")
     return None if rec is None else rec.get("l2_hit_rate")
+
+
+def measured_valu_issue():
+    """Fraction of the VALU issue ceiling (0.25 wave64 instructions per SIMD-cycle) k_trace uses."""
+    rec = profile_record("k_trace_meo20k_counters.md")
+    return None if rec is None else rec.get("valu_issue_frac")
 
 
 def parse():
@@ -533,6 +540,14 @@ def main():
                     "bytes_per_ray": round(bytes_per_ray, 1), "segments_per_ray": round(st["segments_per_ray"], 4),
                     "nodes_per_segment": round(st["nodes_per_segment"], 2),
                     "tris_per_segment": round(st["tris_per_segment"], 2)}
+        # the VALU roofline beside it: algorithmic lane-ops of the same walk (two child-box slab tests
+        # of ~16 ops per node visited, ~30 per triangle test) against 39.3 T non-packed lane-ops/s
+        # (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz); issue_frac is the counters' measured use of VALU issue
+        ops_ray = (2 * 16 * st["nodes_per_segment"] + 30 * st["tris_per_segment"]) * st["segments_per_ray"]
+        tops = ops_ray * rays / (np.median(step_ms) * 1e-3) / 1e12
+        roofline["valu"] = {"lane_ops_per_ray": round(ops_ray, 1), "achieved": round(tops, 2), "peak": VALU_PEAK_TOPS,
+                            "unit": "T lane-ops/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
+                            "issue_frac": measured_valu_issue()}
     except Exception as e:  # the stats entry point is optional for the timing itself
         log(f"roofline stats unavailable: {e!r}")
 
