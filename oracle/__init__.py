@@ -75,7 +75,8 @@ def lib():
         L.oracle_trace_frozen.restype = ctypes.c_int
         L.oracle_surface_estimate.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64,
                                               ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
-                                              ctypes.c_int64, ctypes.c_uint32, P, P, P, P, P, P, P, ctypes.c_int32]
+                                              ctypes.c_int64, ctypes.c_uint32, P, P, P, P, P, P, P, ctypes.c_int32,
+                                              ctypes.c_int32]
         L.oracle_surface_estimate.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -239,9 +240,10 @@ class SurfaceResult:
 
 def surface_estimate(verts, tris, rho_s, rho_d, sun_dirs, *, n_samples: int, bounces: int, flux: float = 1361.0,
                      seed: int = 0, dir_index_base: int = 0, design_index: int = 0, p_spec=None, com=None,
-                     records: bool = False, threads: int | None = None) -> SurfaceResult:
+                     records: bool = False, threads: int | None = None, sampling: int = 0) -> SurfaceResult:
     """FP64 surface-sampling estimate (area-sampled points, path-traced gathering with next-event
-    estimation toward the Sun); see srp_oracle.c for the definition.  force/torque: sample means."""
+    estimation toward the Sun); see srp_oracle.c for the definition.  force/torque: sample means.
+    sampling: bit 0 stratified surface, bit 1 uniform hemisphere directions (plain MC)."""
     verts = np.ascontiguousarray(verts, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     rs = np.ascontiguousarray(rho_s, dtype=np.float32)
@@ -264,7 +266,7 @@ def surface_estimate(verts, tris, rho_s, rho_d, sun_dirs, *, n_samples: int, bou
     st = lib().oracle_surface_estimate(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd), _ptr(ps),
                                        _ptr(c), _ptr(sun), D, int(n_samples), int(bounces), float(flux), int(seed),
                                        int(dir_index_base), int(design_index), _ptr(force), _ptr(torque), _ptr(fa),
-                                       _ptr(hi), _ptr(li), _ptr(dg), _ptr(sf), int(threads))
+                                       _ptr(hi), _ptr(li), _ptr(dg), _ptr(sf), int(sampling), int(threads))
     if st != 0:
         raise ValueError(f"oracle_surface_estimate failed ({st})")
     if records and bounces == 1:

@@ -1028,6 +1028,14 @@ int oracle_trace_frozen(const double* verts, const double* verts0, int64_t n_ver
 /* Random numbers: Philox counter (sample, global direction, stage, design); stage 0: facet,   */
 /* two barycentric uniforms, the event at x; stage 1: the outgoing direction at x (2) and the   */
 /* first gathering direction (2); stage k + 1: the event at v_k and its continuation direction. */
+/*                                                                                            */
+/* Variance-reduction options (the paper's convergence study compares plain MC, BRDF importance */
+/* sampling, stratified surface sampling and both; Sec. 4, simulation results):                 */
+/*   sampling bit 0  stratified surface: sample i of N uses (i + u)/N for the area coordinate,  */
+/*                   one sample per 1/N of the total area;                                      */
+/*   sampling bit 1  every sampled direction (outgoing, gathering, continuation) uniform over   */
+/*                   the hemisphere, weighted by 2 cos(theta) -- plain MC; without it, cosine     */
+/*                   sampling (the Lambertian BRDF's importance sampling), weight 1.            */
 /* ========================================================================================== */
 
 /* Sunlight reaching o along -s is blocked by any facet other than `skip` whose outward side
@@ -1084,6 +1092,24 @@ static void cosine_dir(const double n[3], double u1, double u2, double out[3])
     for (int c = 0; c < 3; ++c) out[c] = lx * t1[c] + ly * t2[c] + lz * n[c];
 }
 
+/* A direction on the hemisphere of n and its weight relative to cosine sampling: the cosine
+ * distribution (the Lambertian BRDF's importance sampling, weight 1) or, with `uniform`, the uniform
+ * distribution over solid angle (cos theta = u1, weight 2 cos theta = pi cos / (pi * 1 / (2 pi))). */
+static double hemi_dir(const double n[3], double u1, double u2, int uniform, double out[3])
+{
+    if (!uniform) {
+        cosine_dir(n, u1, u2, out);
+        return 1.0;
+    }
+    double rad = sqrt(fmax(0.0, 1.0 - u1 * u1));
+    double phi = 2.0 * M_PI * u2;
+    double lx = rad * cos(phi), ly = rad * sin(phi), lz = u1;
+    double t1[3], t2[3];
+    oracle_basis(n, t1, t2);
+    for (int c = 0; c < 3; ++c) out[c] = lx * t1[c] + ly * t2[c] + lz * n[c];
+    return 2.0 * u1;
+}
+
 typedef struct {
     uint64_t seed;
     uint32_t design_index;
@@ -1091,6 +1117,8 @@ typedef struct {
     double flux;
     const double* cum; /* [T] cumulative facet areas, facet order */
     double area;       /* total area */
+    int32_t sampling;  /* bit 0: stratified surface; bit 1: uniform hemisphere directions */
+    int64_t n_samples;
 } gather_params_t;
 
 /* One sample of the surface-sampling estimator for direction `sun` (global index dir_global).
@@ -1107,8 +1135,9 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
     double u0[4], u1[4];
     draw4(G->seed, sample, dir_global, 0u, G->design_index, u0);
     draw4(G->seed, sample, dir_global, 1u, G->design_index, u1);
-    /* facet by area: the first f with u A < cum[f] */
-    const double target = u0[0] * G->area;
+    /* facet by area: the first f with u A < cum[f]; stratified, sample i takes u = (i + u0) / N */
+    const double uf = (G->sampling & 1) ? ((double)sample + u0[0]) / (double)G->n_samples : u0[0];
+    const double target = uf * G->area;
     int64_t lo = 0, hi = S->n_tris - 1;
     while (lo < hi) {
         int64_t mid = (lo + hi) / 2;
@@ -1126,10 +1155,11 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
     const double rs = (double)S->rho_s[f], rd = (double)S->rho_d[f];
     const float ps = S->p_spec[f];
     /* the outgoing event at x */
+    const int uniform = (G->sampling & 2) != 0;
     const int mirror = (float)u0[3] < ps;
-    const double kout = mirror ? rs / (double)ps : (rd > 0.0 ? rd / (1.0 - (double)ps) : 0.0);
     double odir[3];
-    cosine_dir(n, u1[0], u1[1], odir);
+    const double wo = hemi_dir(n, u1[0], u1[1], uniform, odir);
+    const double kout = mirror ? rs / (double)ps : (rd > 0.0 ? rd / (1.0 - (double)ps) * wo : 0.0);
     double s[3] = {sun[0], sun[1], sun[2]};
     double dep[3] = {0.0, 0.0, 0.0};
     int32_t lit = 0;
@@ -1151,7 +1181,7 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
     if (B >= 2) {
         /* gathered light: vertices v1 .. v_{B-1} */
         double w[3];
-        cosine_dir(n, u1[2], u1[3], w);
+        const double wg = hemi_dir(n, u1[2], u1[3], uniform, w);
         double p1[3] = {-w[0], -w[1], -w[2]};
         double radiance = 0.0; /* pi x radiance toward x, in units of Phi */
         double beta = 1.0;
@@ -1188,8 +1218,8 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
                 for (int c = 0; c < 3; ++c) nd[c] = rdir[c] - 2.0 * dn * ng[c];
                 beta *= rsg / (double)psg;
             } else {
-                cosine_dir(ng, ev[1], ev[2], nd);
-                beta *= rdg > 0.0 ? rdg / (1.0 - (double)psg) : 0.0;
+                const double wv = hemi_dir(ng, ev[1], ev[2], uniform, nd);
+                beta *= rdg > 0.0 ? rdg / (1.0 - (double)psg) * wv : 0.0;
             }
             if (beta == 0.0) break;
             for (int c = 0; c < 3; ++c) {
@@ -1199,7 +1229,7 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
             skip = g;
         }
         if (radiance > 0.0) {
-            const double W = G->flux * radiance / kSpeedOfLight;
+            const double W = G->flux * radiance * wg / kSpeedOfLight;
             double r[3];
             const double pn = dot3(p1, n);
             for (int c = 0; c < 3; ++c) r[c] = p1[c] - 2.0 * pn * n[c];
@@ -1270,7 +1300,8 @@ static void* gather_worker(void* argp)
  * directions, n_samples samples each (sample index = Philox counter word 0).
  *   verts, tris, rho_s, rho_d, p_spec, com, sun_dirs as for oracle_trace;
  *   force, torque [n_dirs][3]: sample means (N, N m);
- *   optional per-sample records [n_dirs][n_samples] (hits: [.. ][bounces - 1]) and forces [..][3].
+ *   optional per-sample records [n_dirs][n_samples] (hits: [.. ][bounces - 1]) and forces [..][3];
+ *   sampling: 0..3, the variance-reduction bits above.
  * Samples are summed in chunks of 64, chunk sums in order: independent of the thread count.
  */
 int oracle_surface_estimate(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
@@ -1278,10 +1309,10 @@ int oracle_surface_estimate(const double* verts, int64_t n_verts, const int32_t*
                             const double* sun_dirs, int64_t n_dirs, int64_t n_samples, int32_t bounces, double flux,
                             uint64_t seed, int64_t dir_index_base, uint32_t design_index, double* force,
                             double* torque, int32_t* rec_facet, int32_t* rec_hits, int32_t* rec_lit, uint8_t* rec_deg,
-                            double* sample_force, int32_t n_threads)
+                            double* sample_force, int32_t sampling, int32_t n_threads)
 {
     if (!verts || n_verts <= 0 || !tris || n_tris <= 0 || !rho_s || !rho_d || !sun_dirs || n_dirs < 0 ||
-        n_samples < 1 || bounces < 1 || !force || !torque)
+        n_samples < 1 || bounces < 1 || !force || !torque || sampling < 0 || sampling > 3)
         return ORC_EINVAL;
     for (int64_t f = 0; f < n_tris; ++f)
         if (!(rho_s[f] >= 0.0f) || !(rho_d[f] >= 0.0f) || rho_s[f] + rho_d[f] > 1.0f) return ORC_EINVAL;
@@ -1300,7 +1331,7 @@ int oracle_surface_estimate(const double* verts, int64_t n_verts, const int32_t*
         acc += 0.5 * sqrt(dot3(cr, cr));
         cum[f] = acc;
     }
-    gather_params_t G = {seed, design_index, bounces, flux, cum, acc};
+    gather_params_t G = {seed, design_index, bounces, flux, cum, acc, sampling, n_samples};
     if (n_threads < 1) n_threads = 1;
     gather_job_t J;
     memset(&J, 0, sizeof(J));
