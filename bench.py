@@ -526,6 +526,33 @@ def main():
             f" crossover {surface['meo_gpu_build']['crossover_samples_per_design']} samples per design")
         sg.close()
 
+        # the paper's convergence study (MSE against a high-sample reference for plain MC, BRDF
+        # importance sampling, stratified surface sampling and both): 32 independent seeds of N
+        # samples for 16 directions, reference 2^22 samples per direction with both options
+        sun_v = torch.as_tensor(si.fibonacci_dirs(16), dtype=torch.float64, device=dev).contiguous()
+        Fv = torch.empty((1, 16, 3), dtype=torch.float64, device=dev)
+        p.srp_surface_estimate([sc], sun_v, 1 << 22, p.TraceParams(bounces=args.bounces, seed=999, sampling=1), Fv,
+                               stream=stream.cuda_stream)
+        ref_v = Fv.clone()
+        mse = {}
+        for n_v in (1024, 16384):
+            for mode, name in ((2, "plain"), (0, "brdf_is"), (3, "stratified"), (1, "both")):
+                acc = torch.zeros((), dtype=torch.float64, device=dev)
+                for k in range(32):
+                    p.srp_surface_estimate([sc], sun_v, n_v, p.TraceParams(bounces=args.bounces, seed=1000 + k,
+                                                                           sampling=mode), Fv, stream=stream.cuda_stream)
+                    acc += ((Fv - ref_v) ** 2).sum(-1).mean()
+                mse[f"{name}_{n_v}"] = (acc / 32).item()
+        scale = (ref_v ** 2).sum(-1).mean().item()
+        surface["variance"] = {
+            "mse_N2": {k: float(f"{v:.4e}") for k, v in mse.items()},
+            "rel_rms": {k: round((v / scale) ** 0.5, 5) for k, v in mse.items()},
+            "plain_over_both": {n: round(mse[f"plain_{n}"] / mse[f"both_{n}"], 2) for n in (1024, 16384)},
+            "workload": "satellite, 16 Fibonacci dirs, 32 seeds per option and sample count, reference 2^22 samples "
+                        "(stratified + importance sampled)"}
+        log("surface variance study (relative RMS): " + ", ".join(f"{k} {v:.4f}" for k, v in
+                                                               surface["variance"]["rel_rms"].items()))
+
     # ---- roofline of the dominant kernel --------------------------------------------------------
     roofline = None
     try:

@@ -73,7 +73,12 @@ typedef struct {
  *                 vertex mean); 1: the caller passes frames (see srp_frames for the layout)
  *   tiles_per_wave  launch shape only: 8 x 8-pixel tiles per wavefront and workgroup, 1..16, or 0
  *                 for the library's rule (srp_autotune_tiles_per_wave measures the choices).  Results
- *                 are the same up to the FP32 summation order of the per-wave partial sums. */
+ *                 are the same up to the FP32 summation order of the per-wave partial sums.
+ *   sampling      surface-sampling estimator only (srp_surface_estimate; ignored elsewhere): the variance-
+ *                 reduction options of the paper's convergence study, bit 0 stratified surface
+ *                 sampling (sample i of N takes the area coordinate (i + u)/N), bit 1 plain Monte
+ *                 Carlo directions (uniform over the hemisphere, weight 2 cos theta) instead of the
+ *                 Lambertian BRDF's cosine importance sampling; 0..3. */
 typedef struct {
     int32_t nu, nv;
     int32_t bounces;
@@ -84,6 +89,7 @@ typedef struct {
     int32_t design_index;
     int32_t frame_mode;
     int32_t tiles_per_wave;
+    int32_t sampling;
 } srp_trace_params;
 
 /* Creates a scene from a rest-pose mesh.  Host arrays, copied:

@@ -31,12 +31,12 @@ class srp_hinge(ctypes.Structure):
 class TraceParams(ctypes.Structure):
     _fields_ = [("nu", I32), ("nv", I32), ("bounces", I32), ("jitter", I32), ("flux", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("dir_index_base", I64), ("design_index", I32), ("frame_mode", I32),
-                ("tiles_per_wave", I32)]
+                ("tiles_per_wave", I32), ("sampling", I32)]
 
     def __init__(self, nu=256, nv=256, bounces=1, jitter=1, flux=1361.0, seed=0, dir_index_base=0, design_index=0,
-                 frame_mode=0, tiles_per_wave=0):
+                 frame_mode=0, tiles_per_wave=0, sampling=0):
         super().__init__(int(nu), int(nv), int(bounces), int(bool(jitter)), float(flux), int(seed),
-                         int(dir_index_base), int(design_index), int(frame_mode), int(tiles_per_wave))
+                         int(dir_index_base), int(design_index), int(frame_mode), int(tiles_per_wave), int(sampling))
 
 
 _sigs = {

@@ -223,6 +223,7 @@ srp_status check_params(const srp_trace_params* p)
     if (p->dir_index_base < 0) return fail(SRP_EINVAL, "dir_index_base must be >= 0");
     if (p->tiles_per_wave < 0 || p->tiles_per_wave > srp::kMaxTilesPerWave)
         return fail(SRP_EINVAL, "tiles_per_wave must be in 0..16");
+    if (p->sampling < 0 || p->sampling > 3) return fail(SRP_EINVAL, "sampling must be in 0..3");
     return SRP_OK;
 }
 
@@ -751,6 +752,7 @@ srp_status srp_surface_estimate(const srp_scene* scenes, int32_t S, const double
     a.seed_hi = static_cast<uint32_t>(p->seed >> 32);
     a.dir_index_base = p->dir_index_base;
     a.design_index = static_cast<uint32_t>(p->design_index);
+    a.sampling = p->sampling;
     SRP_HIP(ensure(lead->d_partials, lead->partials_cap, static_cast<size_t>(units * chunks * 6)));
     a.partials = lead->d_partials;
     a.rec_facet = rec_facet;

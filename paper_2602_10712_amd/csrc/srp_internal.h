@@ -140,6 +140,7 @@ struct SurfaceArgs {
     uint32_t seed_lo, seed_hi;
     int64_t dir_index_base;
     uint32_t design_index;
+    int32_t sampling;            // bit 0: stratified surface; bit 1: uniform hemisphere directions
     double* partials;            // [units][chunks][6]
     int32_t* rec_facet;          // [units][n_samples] or null
     int32_t* rec_hits;           // [units][n_samples][bounces - 1] or null

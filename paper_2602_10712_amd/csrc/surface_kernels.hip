@@ -171,6 +171,25 @@ __device__ __forceinline__ void cosine_dir(const float n[3], float u1, float u2,
     for (int a = 0; a < 3; ++a) out[a] = px * t1[a] + py * t2[a] + pz * n[a];
 }
 
+// A direction on the hemisphere of n and its weight relative to cosine sampling: cosine-distributed
+// (the Lambertian BRDF's importance sampling, weight 1) or, with `uniform`, uniform over solid angle
+// (cos theta = u1, weight 2 cos theta).
+__device__ __forceinline__ float hemi_dir(const float n[3], float u1, float u2, bool uniform, float out[3])
+{
+    if (!uniform) {
+        cosine_dir(n, u1, u2, out);
+        return 1.0f;
+    }
+    const float rad = sqrtf(fmaxf(0.0f, 1.0f - u1 * u1));
+    float sphi, cphi;
+    sincosf(6.283185307179586f * u2, &sphi, &cphi);
+    const float px = rad * cphi, py = rad * sphi, pz = u1;
+    float t1[3], t2[3];
+    duff_basis<float>(n, t1, t2);
+    for (int a = 0; a < 3; ++a) out[a] = px * t1[a] + py * t2[a] + pz * n[a];
+    return 2.0f * u1;
+}
+
 __device__ __forceinline__ void philox_at(uint32_t sample, uint32_t dir, uint32_t stage, uint32_t design,
                                           const SurfaceArgs& a, float u[4])
 {
@@ -195,7 +214,11 @@ __device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const Surfa
     philox_at(sample, dir, 1u, design, a, u1);
     // facet by area (FP64, original facet order): the first f with u A < cum[f]
     const double* __restrict__ cum = (const double*)sc.cum_area;
-    const double target = static_cast<double>(unit24(c0)) * sc.area;
+    // stratified: sample i of N takes the area coordinate (i + u) / N
+    const double uf = (a.sampling & 1)
+                          ? (static_cast<double>(sample) + static_cast<double>(unit24(c0))) / static_cast<double>(a.n_samples)
+                          : static_cast<double>(unit24(c0));
+    const double target = uf * sc.area;
     int lo = 0, hi = sc.n_tris - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -225,11 +248,12 @@ __device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const Surfa
         o[c] = x[c] + sc.eps * n[c];
     }
     const float rs = mt.x, rd = mt.y, ps = mt.z;
+    const bool uniform = (a.sampling & 2) != 0;
     const bool mirror = u0[3] < ps;
-    const float kout = mirror ? rs / ps : (rd > 0.0f ? rd / (1.0f - ps) : 0.0f);
     float odir[3], w[3];
-    cosine_dir(n, u1[0], u1[1], odir);
-    cosine_dir(n, u1[2], u1[3], w);
+    const float wo = hemi_dir(n, u1[0], u1[1], uniform, odir);
+    const float wg = hemi_dir(n, u1[2], u1[3], uniform, w);
+    const float kout = mirror ? rs / ps : (rd > 0.0f ? rd / (1.0f - ps) * wo : 0.0f);
     float dep[3] = {0.0f, 0.0f, 0.0f};
     int32_t lit = 0;
     const float cs = n[0] * s[0] + n[1] * s[1] + n[2] * s[2];
@@ -271,8 +295,8 @@ __device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const Surfa
                 for (int c = 0; c < 3; ++c) nd[c] = rdir[c] - 2.0f * dn * ng[c];
                 beta *= mg.x / mg.z;
             } else {
-                cosine_dir(ng, ev[1], ev[2], nd);
-                beta *= mg.y > 0.0f ? mg.y / (1.0f - mg.z) : 0.0f;
+                const float wv = hemi_dir(ng, ev[1], ev[2], uniform, nd);
+                beta *= mg.y > 0.0f ? mg.y / (1.0f - mg.z) * wv : 0.0f;
             }
             if (beta == 0.0f) break;
             for (int c = 0; c < 3; ++c) {
@@ -282,7 +306,7 @@ __device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const Surfa
             skip = g;
         }
         if (radiance > 0.0f) {
-            const float W = a.flux_c * radiance;
+            const float W = a.flux_c * radiance * wg;
             const float pv[3] = {-w[0], -w[1], -w[2]};
             const float pn = pv[0] * n[0] + pv[1] * n[1] + pv[2] * n[2];
             for (int c = 0; c < 3; ++c) {

@@ -7,7 +7,9 @@ Same Philox counters on both sides, so the samples are the same:
   * several designs in one call ("multi-world") equal each design's own call bit for bit;
   * ragged sample counts, one bounce, invalid arguments;
   * at the benchmark's sample count on the 20.6k-triangle satellite, the records of the first
-    512 samples of each direction match the oracle.
+    512 samples of each direction match the oracle;
+  * the variance-reduction options (stratified surface, plain-MC hemisphere directions, both):
+    records, force and torque against the oracle in each, BVH walk = brute force bit for bit.
 """
 import numpy as np
 import pytest
@@ -162,4 +164,30 @@ def test_full_size_meo_records_match_oracle():
     deg = check_records(sub, ref, 3, min_ok=0.85)  # 1 cm antenna facets and dish slivers: many samples near edges
     print(f"full size: degenerate {deg:.4f}")
     assert np.all(np.isfinite(g["F"])) and np.abs(g["F"]).max() > 0
+    sc.close()
+
+
+@pytest.mark.parametrize("sampling", [1, 2, 3])
+def test_sampling_options_match_oracle(sampling):
+    import paper_2602_10712_amd as p
+    m = si.meo_satellite(bus_n=6, cyl_sides=16, panel_n=4, dish_rings=8, dish_sectors=16, strut_sides=6)
+    rs, rd = si.materials(m.n_tris, 3)
+    sc = make(m, rs, rd, [0.1, 0.2])
+    V = sc.vertices()
+    sun = si.fibonacci_dirs(5)
+    n = 1500  # ragged: not a multiple of the 256-sample workgroup
+    prm = p.TraceParams(bounces=3, seed=25, design_index=2, sampling=sampling)
+    a = run([sc], sun, n, prm, False)
+    b = run([sc], sun, n, prm, True)
+    for k in ("F", "T", "facet", "lit", "hits"):
+        assert np.array_equal(a[k], b[k]), k
+    ref = oracle.surface_estimate(V, m.tris, rs, rd, sun, n_samples=n, bounces=3, seed=25, design_index=2,
+                                  com=m.com, records=True, sampling=sampling)
+    deg = check_records({k: v[0] for k, v in a.items()}, ref, 3)
+    assert rel_l2(a["F"][0], ref.force) <= 1e-4
+    assert rel_l2(a["T"][0], ref.torque) <= 1e-4
+    print(f"sampling {sampling}: degenerate {deg:.4f}")
+    with pytest.raises(p.SRPError):
+        p.srp_surface_estimate([sc], torch.as_tensor(sun, device="cuda"), 16, p.TraceParams(bounces=2, sampling=4),
+                               torch.empty((1, 5, 3), dtype=torch.float64, device="cuda"))
     sc.close()
