@@ -5,7 +5,7 @@ BVH) for 1024 spherical-Fibonacci sun directions x 1024 x 1024 parallel rays, up
 interactions per path, FP64 force and torque per direction.  Inputs (mesh, BVH, materials, sun
 directions) are resident in HBM before the timed region; the BVH build is timed separately.
 
-Prints ONE JSON line (see the design notes for the field definitions):
+Prints ONE JSON line:
   value            forward Mrays/s (primary grid rays, whole paths, per second)
   fwd_adjoint      forward + adjoint replay Mrays/s at 512 x 512 rays per direction
   surrogate        fused MLP surrogate evals/s on 1M queries, with its MFMA roofline fraction
@@ -119,8 +119,9 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this path is "
-              "described in the design notes but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path "
+              "(directions and designs would shard across ranks with one all-gather of the results)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 

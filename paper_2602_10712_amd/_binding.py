@@ -345,6 +345,10 @@ class Scene:
     def info(self):
         return srp_scene_info(self.handle)
 
+    def build_gpu(self, stream=None):
+        """Rebuilds the BVH on the GPU (srp_scene_build_gpu); returns (nodes, depth)."""
+        return srp_scene_build_gpu(self.handle, stream)
+
     def trace(self, sun_dirs, params: TraceParams, frames=None, stream=None):
         import torch
         sd = torch.as_tensor(sun_dirs, dtype=torch.float64, device="cuda").contiguous()

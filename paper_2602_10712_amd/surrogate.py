@@ -2,7 +2,7 @@
 
 The tracer generates samples (sun direction, design) -> body-frame force over random designs; the
 MLP (libsrp srp_mlp_*) is trained on them with Adam and then answers force queries at a fraction of
-the tracer's cost.  The tracer stays the judge of the surrogate's error and its fallback: a query
+the tracer's cost.  The tracer stays the reference for the surrogate's error and its fallback: a query
 is sent back to the tracer when it lies outside the training box of the design space or when two
 independently trained networks disagree by more than a threshold calibrated on held-out data.
 

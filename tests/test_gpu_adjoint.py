@@ -1,6 +1,6 @@
 """GPU adjoint (srp_trace_adjoint) vs the FP64 oracle, and the autograd Function.
 
-Bars (documented in the design notes):
+Bars:
   * reflectance gradients vs the oracle's FP64 adjoint: relative L2 over the stacked [2][T] vector
     <= 1e-4 on the box-wing (FP32 per ray, FP64 atomics) and <= 2e-3 on the 20k-triangle satellite,
     where ~1 % of paths are degenerate and a few of those take another facet sequence on the GPU;

@@ -80,6 +80,25 @@ def test_gpu_tree_gives_identical_traces(full):
     b.close()
 
 
+def test_statistics_follow_the_gpu_tree():
+    """The instrumented host traversal reads the GPU-built records back: the same hits (segments per
+    ray) as on the SAH tree, with the new tree's node counts."""
+    import paper_2602_10712_amd as p
+    m2 = si.meo_satellite(bus_n=6, cyl_sides=16, panel_n=4, dish_rings=8, dish_sectors=16, strut_sides=6)
+    rs, rd = si.materials(m2.n_tris, 5)
+    a, b, _, _ = pair(m2, rs, rd, [0.2, 0.1])
+    sun = si.fibonacci_dirs(8)
+    prm = p.TraceParams(nu=128, nv=128, bounces=3, seed=3)
+    sa = p.ray_stats(a, sun, prm, n_dirs=8, pixel_stride=7)
+    b.build_gpu()
+    sb = p.ray_stats(b, sun, prm, n_dirs=8, pixel_stride=7)
+    print(f"SAH tree: {sa['nodes_per_segment']:.2f} nodes/segment; GPU tree: {sb['nodes_per_segment']:.2f}")
+    assert sa["segments_per_ray"] == sb["segments_per_ray"]
+    assert sb["nodes_per_segment"] > 0
+    a.close()
+    b.close()
+
+
 def test_gpu_build_small_mesh_refused():
     import paper_2602_10712_amd as p
     m = si.plate(1.0, 1.0)

@@ -1,6 +1,6 @@
 """Surrogate MLP kernels vs the FP64 oracle with BF16 rounding emulation (oracle/mlp.py).
 
-Bars (documented in the design notes): forward outputs and gradients within 1e-3 relative L2 of
+Bars: forward outputs and gradients within 1e-3 relative L2 of
 the emulating oracle (FP32 accumulation order and rare single-activation rounding flips); one Adam
 step within 1e-3 of the oracle's update; checkpoint/resume reproduces the next step bit for bit.
 """

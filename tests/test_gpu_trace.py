@@ -1,6 +1,6 @@
 """GPU forward trace vs the FP64 oracle (parity), through the C ABI.
 
-Bars (documented in the design notes):
+Bars:
   * force and torque per direction: relative L2 over the stacked [D][3] array <= 1e-4;
   * hit indices: identical on every segment the oracle does not flag as degenerate (a path is
     degenerate from its first flagged segment on); the degenerate fraction is reported.
