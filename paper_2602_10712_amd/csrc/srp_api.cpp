@@ -656,8 +656,8 @@ srp_status srp_scene_build_gpu(srp_scene s, int32_t* n_nodes_out, int32_t* depth
     if (e == hipSuccess) e = hipMemcpyAsync(&depth, a.depth_out, 4, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     const int32_t count = records - 1;  // a full binary tree over its leaf records
-    if (e == hipSuccess && (count < 1 || count > n - 1)) e = hipErrorUnknown;
     if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("GPU BVH build: ") + hipGetErrorString(e));
+    if (count < 1 || count > n - 1) return fail(SRP_EDEVICE, "GPU BVH build: inconsistent node count");
     if (depth >= srp::kMaxTreeDepth) return fail(SRP_EUNSUPPORTED, "GPU-built tree deeper than the traversal stack");
     // adopt the new tree and record order; the host keeps the nodes and the order (refit, statistics)
     std::vector<srp::BvhNode> nodes(count);
