@@ -79,16 +79,21 @@ def deriv(z, design, model, mu, mass, inertia, inertia_inv, sun, earth_radius):
     return np.concatenate([v, acc, dq, dw], -1)
 
 
-def rk4(z0, design, model, *, mu, mass, inertia, sun, dt, n_steps, earth_radius=0.0, keep=False):
-    """z0 [B][13], design [B][k]; returns z_N [B][13] (and all states [n+1][B][13] if keep)."""
+def rk4(z0, design, model, *, mu, mass, inertia, sun, dt, n_steps, earth_radius=0.0, keep=False, steps_per_design=0):
+    """z0 [B][13], design [B][k]; returns z_N [B][13] (and all states [n+1][B][13] if keep).
+    With steps_per_design = L > 0 the design changes over time: design [S][B][k], and step n (all
+    four of its stages) uses row min(n // L, S - 1)."""
     z = np.array(z0, dtype=np.float64, copy=True).reshape(-1, 13)
-    design = np.asarray(design, dtype=np.float64).reshape(z.shape[0], -1)
+    B = z.shape[0]
+    sched = np.asarray(design, dtype=np.float64)
+    sched = sched.reshape(-1, B, sched.shape[-1]) if steps_per_design > 0 else sched.reshape(1, B, -1)
     inertia = np.asarray(inertia, dtype=np.float64).reshape(3, 3)
     inertia_inv = np.linalg.inv(inertia)
     sun = np.asarray(sun, dtype=np.float64)
-    args = (design, model, mu, mass, inertia, inertia_inv, sun, earth_radius)
     states = [z.copy()] if keep else None
-    for _ in range(n_steps):
+    for n in range(n_steps):
+        seg = min(n // steps_per_design, len(sched) - 1) if steps_per_design > 0 else 0
+        args = (sched[seg], model, mu, mass, inertia, inertia_inv, sun, earth_radius)
         k1 = deriv(z, *args)
         k2 = deriv(z + 0.5 * dt * k1, *args)
         k3 = deriv(z + 0.5 * dt * k2, *args)

@@ -184,3 +184,25 @@ def test_mlp_model_inputs_and_scales():
     F, tau = att.mlp_model(layers, 2.0, 3.0)(s, d)
     y, _ = omlp.forward(layers, np.concatenate([s, d], 1), emulate=True)
     assert np.array_equal(F, 2.0 * y[:, :3]) and np.array_equal(tau, 3.0 * y[:, 3:])
+
+
+def test_design_schedule_segments():
+    """A schedule of identical rows is the constant design; a schedule switches at step boundaries:
+    running its first segment alone and restarting from that state with the second gives the same
+    end state."""
+    layers = omlp.unpack(omlp.init_params(5, 16, 2, 6, seed=4), 5, 16, 2, 6)
+    model = att.mlp_model(layers, 3e-5, 1e-5)
+    z0 = state([2.656e7, 0, 0], [0, 3873.96, 0], axis_quat([1, 2, 2], 0.4), [0.01, -0.02, 0.005])
+    kw = dict(mu=MU, mass=1000.0, inertia=np.diag([300.0, 200.0, 100.0]), sun=np.array([0.6, 0.0, 0.8]), dt=30.0)
+    d1, d2 = np.array([[0.3, -0.7]]), np.array([[-0.9, 0.2]])
+    const = att.rk4(z0, d1, model, n_steps=20, **kw)
+    same = att.rk4(z0, np.stack([d1, d1]), model, n_steps=20, steps_per_design=10, **kw)
+    assert np.array_equal(const, same)
+    sched = att.rk4(z0, np.stack([d1, d2]), model, n_steps=20, steps_per_design=10, **kw)
+    half = att.rk4(z0, d1, model, n_steps=10, **kw)
+    rest = att.rk4(half, d2, model, n_steps=10, **kw)
+    assert np.array_equal(sched, rest)
+    assert not np.array_equal(sched, const)
+    # past the last row the schedule holds it
+    longer = att.rk4(z0, np.stack([d1, d2]), model, n_steps=25, steps_per_design=10, **kw)
+    assert np.array_equal(longer, att.rk4(rest, d2, model, n_steps=5, **kw))
