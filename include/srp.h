@@ -318,10 +318,14 @@ typedef struct srp_attitude_params {
     double earth_radius;  /* m; 0 disables the eclipse */
     double dt;            /* step, s, > 0 */
     int64_t n_steps;      /* >= 0 */
+    int64_t steps_per_design; /* 0: one design row per trajectory for the whole run; L > 0: the design
+                                 changes over time (e.g. panel angles), row min(n / L, S - 1) of a
+                                 [S][B][n_in - 3] schedule, S = max(1, ceil(n_steps / L)), for step n */
 } srp_attitude_params;
 
 /* Integrates B trajectories: z0 and z_final device double [B][13] (r, v, q, w; SI units),
- * design device float [B][n_in - 3] (NULL when the network has 3 inputs), z_all device double
+ * design device float [B][n_in - 3], or [S][B][n_in - 3] with steps_per_design (NULL when the
+ * network has 3 inputs), z_all device double
  * [n_steps + 1][B][13] or NULL.  The network (n_in >= 3, n_out >= 6; extra outputs ignored)
  * answers 4 n_steps batched queries; its inference path is used, and the integration state lives
  * in a workspace the network owns (about 360 + 4 n_in bytes per trajectory), so calls that use one

@@ -80,10 +80,13 @@ class AttitudeParams(ctypes.Structure):
     """srp_attitude_params (see srp.h)."""
     _fields_ = [("mu", ctypes.c_double), ("mass", ctypes.c_double), ("inertia", ctypes.c_double * 9),
                 ("sun", ctypes.c_double * 3), ("force_scale", ctypes.c_double), ("torque_scale", ctypes.c_double),
-                ("earth_radius", ctypes.c_double), ("dt", ctypes.c_double), ("n_steps", I64)]
+                ("earth_radius", ctypes.c_double), ("dt", ctypes.c_double), ("n_steps", I64),
+                ("steps_per_design", I64)]
 
-    def __init__(self, mu, mass, inertia, sun, force_scale, torque_scale, dt, n_steps, earth_radius=0.0):
+    def __init__(self, mu, mass, inertia, sun, force_scale, torque_scale, dt, n_steps, earth_radius=0.0,
+                 steps_per_design=0):
         super().__init__()
+        self.steps_per_design = int(steps_per_design)
         self.mu, self.mass = float(mu), float(mass)
         self.inertia[:] = [float(x) for x in np.asarray(inertia, dtype=np.float64).reshape(9)]
         self.sun[:] = [float(x) for x in np.asarray(sun, dtype=np.float64).reshape(3)]
@@ -550,7 +553,11 @@ def srp_attitude_rk4(model, params: AttitudeParams, z0, design, z_final, z_all=N
     nd = model.n_in - 3
     if tuple(z0.shape) != (B, 13) or tuple(z_final.shape) != (B, 13):
         raise ValueError("z0 and z_final must be [B][13]")
-    if nd > 0 and (design is None or tuple(design.shape) != (B, nd)):
+    if params.steps_per_design > 0 and nd > 0:
+        n_seg = max(1, -(-params.n_steps // params.steps_per_design))
+        if design is None or tuple(design.shape) != (n_seg, B, nd):
+            raise ValueError(f"design must be [{n_seg}][B][{nd}] for this schedule")
+    elif nd > 0 and (design is None or tuple(design.shape) != (B, nd)):
         raise ValueError(f"design must be [B][{nd}]")
     if z_all is not None and tuple(z_all.shape) != (params.n_steps + 1, B, 13):
         raise ValueError("z_all must be [n_steps + 1][B][13]")

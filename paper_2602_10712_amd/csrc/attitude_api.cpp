@@ -4,6 +4,7 @@
 //   init, then per step and stage: network inference on the stage inputs, stage kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -59,6 +60,7 @@ srp_status srp_attitude_rk4(srp_mlp model, const srp_attitude_params* p, const d
         !(p->earth_radius >= 0) || !std::isfinite(p->force_scale) || !std::isfinite(p->torque_scale))
         return srp_fail(SRP_EINVAL, "bad integration parameters");
     if (p->n_steps > (int64_t(1) << 40)) return srp_fail(SRP_EINVAL, "too many steps");
+    if (p->steps_per_design < 0) return srp_fail(SRP_EINVAL, "steps_per_design must be >= 0");
     const double sn = std::sqrt(p->sun[0] * p->sun[0] + p->sun[1] * p->sun[1] + p->sun[2] * p->sun[2]);
     if (!(sn > 0) || !std::isfinite(sn)) return srp_fail(SRP_EINVAL, "sun direction must be finite and nonzero");
     srp::AttArgs a{};
@@ -84,6 +86,11 @@ srp_status srp_attitude_rk4(srp_mlp model, const srp_attitude_params* p, const d
     a.h = p->dt;
     a.z_all = z_all;
     a.z_final = z_final;
+    a.design = design;
+    a.steps_per_design = n_in > 3 ? p->steps_per_design : 0;
+    a.n_segments = a.steps_per_design > 0
+                       ? std::max<int64_t>(1, (p->n_steps + a.steps_per_design - 1) / a.steps_per_design)
+                       : 1;
     // workspace: Z, Y, A [13][B] double, X [B][n_in] float, O [B][n_out] float
     const size_t nb = static_cast<size_t>(B);
     const size_t s_state = align256(13 * nb * sizeof(double));

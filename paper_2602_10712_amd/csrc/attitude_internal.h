@@ -26,6 +26,9 @@ struct AttArgs {
     const float* O;
     double* z_all;    // [n_steps + 1][B][13] or null
     double* z_final;  // [B][13]
+    const float* design;       // [n_segments][B][n_in - 3] (one segment: constant design)
+    int64_t steps_per_design;  // 0: constant
+    int64_t n_segments;
 };
 
 // k_att_init: Z = Y = z0, network input of stage 1 (design columns written once), z_all[0].

@@ -124,6 +124,13 @@ __global__ void k_att_stage(AttArgs a, int stage, int64_t step, int last)
             if (out) out[c] = y[c];
             if (last) a.z_final[13 * b + c] = y[c];
         }
+        // a design schedule: the next step's row (its stages all use it)
+        if (a.steps_per_design > 0 && !last) {
+            const int64_t seg = min((step + 1) / a.steps_per_design, a.n_segments - 1);
+            const int nd = a.n_in - 3;
+            const float* row = a.design + (seg * B + b) * nd;
+            for (int j = 0; j < nd; ++j) a.X[b * a.n_in + 3 + j] = row[j];
+        }
     }
     write_input(a, y, b);
 }

@@ -9,6 +9,8 @@ Bars:
     rounding flips of hidden activations), and over these horizons the radiation's effect is
     linear in the network output to first order;
   * the same with the cylinder eclipse on low orbits that pass behind the Earth;
+  * a design schedule (rows switching every L steps) against the oracle's; identical rows equal the
+    constant design bit for bit;
   * recorded states: z_all[0] = z0, z_all[n] = z_final bit for bit; n_steps = 0 copies z0; z0 may
     alias z_final; a ragged batch (not a multiple of 256);
   * at the benchmark's size (65,536 trajectories, 2,880 steps of 15 s), 4 sampled trajectories
@@ -140,6 +142,33 @@ def test_zero_steps_alias_and_ragged():
     assert np.array_equal(zd.cpu().numpy(), ref)
     one = run_gpu(net, params(1e-4, 1e-4, 10.0, 7), z0[100:101], design[100:101])
     assert np.array_equal(one[0], ref[100])  # trajectories are independent of the batch
+    net.close()
+
+
+def test_design_schedule_matches_oracle():
+    """Designs that change over time (every 20 steps, 3 rows): GPU against the oracle's schedule, and a
+    schedule of identical rows equals the constant design bit for bit."""
+    import paper_2602_10712_amd as p
+    net, layers = make_net(11)
+    B, n, L = 300, 60, 20
+    z0 = initial_states(B, 17)
+    rng = np.random.default_rng(8)
+    sched = rng.uniform(-1, 1, (3, B, 8)).astype(np.float32)
+    prm = params(5e-5, 2e-5, 20.0, n, re=RE)
+    prm_s = p.AttitudeParams(MU, 1000.0, INERTIA, tuple(prm.sun), 5e-5, 2e-5, 20.0, n, earth_radius=RE,
+                             steps_per_design=L)
+    g = run_gpu(net, prm_s, z0, sched)
+    sun = np.array(list(prm.sun)) / np.linalg.norm(list(prm.sun))
+    kw = dict(mu=MU, mass=1000.0, inertia=INERTIA, sun=sun, dt=20.0, n_steps=n, earth_radius=RE)
+    ref = att.rk4(z0, sched.astype(np.float64), att.mlp_model(layers, 5e-5, 2e-5), steps_per_design=L, **kw)
+    free = att.rk4(z0, sched.astype(np.float64), lambda s_, d_: (np.zeros_like(s_), np.zeros_like(s_)),
+                   steps_per_design=L, **kw)
+    check_effect(g, ref, free, label="schedule")
+    const = run_gpu(net, prm, z0, sched[0])
+    same = run_gpu(net, prm_s, z0, np.stack([sched[0]] * 3))
+    assert np.array_equal(const, same)
+    with pytest.raises(ValueError):  # a schedule of the wrong length
+        run_gpu(net, prm_s, z0, sched[:2])
     net.close()
 
 
