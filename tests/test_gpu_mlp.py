@@ -124,3 +124,39 @@ def test_mlp_invalid_arguments():
         p.srp_mlp_backward(s.handle, torch.zeros((4, 3), dtype=torch.float32, device="cuda"))
     with pytest.raises(ValueError):
         s.set_params(np.zeros(5, np.float32))
+
+
+def test_inference_in_a_captured_graph_replays_like_eager():
+    """Fused inference captured into a HIP graph (it allocates and clears nothing): every replay,
+    with eager work and synchronisations between replays, equals the eager result bit for bit."""
+    import paper_2602_10712_amd as p
+    net = p.Surrogate(11, 256, 4, 6, seed=12)
+    dev = torch.device("cuda")
+    g = torch.Generator(device="cpu").manual_seed(12)
+    xs = [(torch.rand((5000 + 700 * i, 11), generator=g) * 2 - 1).to(dev) for i in range(3)]
+    ys = [torch.empty((x.shape[0], 6), dtype=torch.float32, device=dev) for x in xs]
+    eager = []
+    for x in xs:
+        y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=dev)
+        p.srp_mlp_forward(net.handle, x, y)
+        eager.append(y)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        cap = torch.cuda.current_stream()
+        for x, y in zip(xs, ys):
+            p.srp_mlp_forward(net.handle, x, y, stream=cap.cuda_stream)
+    for rep in range(4):
+        for y in ys:
+            y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for y, e in zip(ys, eager):
+            assert torch.equal(y, e), rep
+        # eager work between replays
+        scratch = torch.empty((9000, 6), dtype=torch.float32, device=dev)
+        p.srp_mlp_forward(net.handle, torch.rand((9000, 11), device=dev), scratch)
+        torch.cuda.synchronize()
+    del graph
+    net.close()
