@@ -93,13 +93,8 @@ extern "C" srp_status srp_scene_ray_stats(srp_scene s, const double* sun_dirs, i
     if (hipSetDevice(s->device) != hipSuccess || hipMemcpy(mat.data(), s->d_mat, sizeof(float4) * s->n_tris,
                                                            hipMemcpyDeviceToHost) != hipSuccess)
         return srp_fail(SRP_EDEVICE, "copying the materials to the host failed");
-    if (s->h_tris_stale) {
-        s->h_tris.resize(s->n_tris);
-        if (hipMemcpy(s->h_tris.data(), s->d_tris, sizeof(srp::TriRec) * s->n_tris, hipMemcpyDeviceToHost) !=
-            hipSuccess)
-            return srp_fail(SRP_EDEVICE, "copying the triangle records to the host failed");
-        s->h_tris_stale = false;
-    }
+    const srp_status pulled = srp_pull_host_tree(s);
+    if (pulled != SRP_OK) return pulled;
     const int64_t n_pix = static_cast<int64_t>(p->nu) * p->nv;
     const unsigned n_thr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<Counts> part(n_thr);

@@ -26,6 +26,7 @@ struct srp_scene_s {
     std::vector<srp::BvhNode> h_nodes;   // host copies for the instrumented traversal
     std::vector<srp::TriRec> h_tris;
     bool h_tris_stale = false;           // the device records changed (GPU build); read back on use
+    bool h_tree_stale = false;           // the device nodes and order changed (GPU build); read back on use
     srp::BvhNode* d_nodes = nullptr;
     size_t nodes_cap = 0;
     srp::TriRec* d_tris = nullptr;
@@ -70,3 +71,7 @@ struct srp_scene_s {
 
 // Records `msg` as the thread's last error and returns `st`.
 srp_status srp_fail(srp_status st, const std::string& msg);
+
+// Brings the host copies of the tree (nodes, order, triangle records) up to date after a build on
+// the device; host code that reads them (refit, statistics) calls this first.  Synchronous.
+srp_status srp_pull_host_tree(srp_scene_s* s);

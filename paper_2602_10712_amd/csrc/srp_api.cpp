@@ -54,6 +54,29 @@ hipError_t ensure(T*& ptr, size_t& cap, size_t n)
 
 }  // namespace
 
+srp_status srp_pull_host_tree(srp_scene_s* s)
+{
+    if (!s->h_tree_stale && !s->h_tris_stale) return SRP_OK;
+    if (hipSetDevice(s->device) != hipSuccess) return srp_fail(SRP_EDEVICE, "hipSetDevice failed");
+    if (s->h_tree_stale) {
+        s->h_nodes.resize(static_cast<size_t>(s->n_nodes));
+        s->perm.resize(static_cast<size_t>(s->n_tris));
+        if (hipMemcpy(s->h_nodes.data(), s->d_nodes, sizeof(srp::BvhNode) * s->n_nodes, hipMemcpyDeviceToHost) !=
+                hipSuccess ||
+            hipMemcpy(s->perm.data(), s->d_perm, sizeof(int32_t) * s->n_tris, hipMemcpyDeviceToHost) != hipSuccess)
+            return srp_fail(SRP_EDEVICE, "copying the tree to the host failed");
+        s->h_tree_stale = false;
+    }
+    if (s->h_tris_stale) {
+        s->h_tris.resize(static_cast<size_t>(s->n_tris));
+        if (hipMemcpy(s->h_tris.data(), s->d_tris, sizeof(srp::TriRec) * s->n_tris, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return srp_fail(SRP_EDEVICE, "copying the triangle records to the host failed");
+        s->h_tris_stale = false;
+    }
+    return SRP_OK;
+}
+
 srp_status srp_fail(srp_status st, const std::string& msg) { return fail(st, msg); }
 
 namespace {
@@ -102,6 +125,10 @@ double scene_size(const std::vector<double>& v, int64_t n)
 // the triangle records and uploads both.
 srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
 {
+    if (refit) {
+        const srp_status st = srp_pull_host_tree(s);
+        if (st != SRP_OK) return st;
+    }
     const auto& V = s->cur;
     for (int a = 0; a < 3; ++a) {
         s->lo[a] = INFINITY;
@@ -122,6 +149,7 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
         s->depth = bvh.depth;
         s->perm = std::move(bvh.perm);
         s->h_nodes = std::move(bvh.nodes);
+        s->h_tree_stale = false;
     }
     std::vector<srp::TriRec> recs(s->n_tris);
     for (int64_t p = 0; p < s->n_tris; ++p) {
@@ -659,9 +687,8 @@ srp_status srp_scene_build_gpu(srp_scene s, int32_t* n_nodes_out, int32_t* depth
     if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("GPU BVH build: ") + hipGetErrorString(e));
     if (count < 1 || count > n - 1) return fail(SRP_EDEVICE, "GPU BVH build: inconsistent node count");
     if (depth >= srp::kMaxTreeDepth) return fail(SRP_EUNSUPPORTED, "GPU-built tree deeper than the traversal stack");
-    // adopt the new tree and record order; the host keeps the nodes and the order (refit, statistics)
-    std::vector<srp::BvhNode> nodes(count);
-    std::vector<int32_t> perm(n);
+    // adopt the new tree and record order; the host copies are read back only when host code needs
+    // them (refit, statistics)
     e = ensure(s->d_nodes, s->nodes_cap, static_cast<size_t>(count));
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->d_nodes, a.nodes_out, sizeof(srp::BvhNode) * count, hipMemcpyDeviceToDevice, stream);
@@ -670,14 +697,10 @@ srp_status srp_scene_build_gpu(srp_scene s, int32_t* n_nodes_out, int32_t* depth
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_mat, a.mat_out, 16 * nn, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_perm, a.perm_out, 4 * nn, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_bvh_pos, a.bvh_pos_out, 4 * nn, hipMemcpyDeviceToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(nodes.data(), a.nodes_out, sizeof(srp::BvhNode) * count, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(perm.data(), a.perm_out, 4 * nn, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("GPU BVH build: ") + hipGetErrorString(e));
-    s->h_nodes = std::move(nodes);
-    s->perm = std::move(perm);
-    s->h_tris_stale = true;  // read back when the statistics need them
+    s->h_tree_stale = true;
+    s->h_tris_stale = true;
     s->n_nodes = count;
     s->depth = depth;
     if (n_nodes_out) *n_nodes_out = count;
