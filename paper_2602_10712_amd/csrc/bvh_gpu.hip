@@ -13,12 +13,15 @@
 //   5. the leaf records of the final tree: every maximal subtree of at most kLbvhLeaf triangles,
 //      and every single triangle outside them; a scan over the leaves that open one counts the
 //      kept inner nodes of any subtree (a full binary tree over its leaf records);
-//   6. a window table (box of leaves [i, i + 2^k) for every k), from which the box of any node,
-//      a contiguous leaf range, is the union of two windows;
+//   6. a window table (box of leaves [i, i + 2^k) for every k; the first eight levels in one pass
+//      through LDS), from which the box of any node, a contiguous leaf range, is the union of two
+//      windows;
 //   7. pre-order positions (each kept node walks to the root) and the node records.
 // Every node covers a contiguous range of sorted leaves, so no step waits on another thread: there
 // is no bottom-up pass with device-scope counters and fences, whose cost grows with the tree height.
 #include <float.h>
+
+#include <algorithm>
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
@@ -129,6 +132,44 @@ __global__ void k_window(const float* __restrict__ prev, float* __restrict__ cur
     const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= count) return;
     store_box(cur, i, join(load_box(prev, i), load_box(prev, static_cast<int64_t>(i) + half)));
+}
+
+// Levels 1 .. n_levels (at most kWinFused) of the window table in one pass: a workgroup stages the
+// level-0 boxes of its 256 entries and of the 255 leaves after them in LDS and builds each level
+// there (min and max are exact, so the result equals level-by-level construction).
+constexpr int kWinFused = 8;
+constexpr int kWinSpan = 512;  // 256 entries + 2^kWinFused - 1 following leaves, rounded up
+
+__global__ __launch_bounds__(256) void k_window_fused(float* __restrict__ win, int32_t n, int32_t n_levels)
+{
+    __shared__ float2 sb[2][kWinSpan][3];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 256;
+    for (int j = threadIdx.x; j < kWinSpan; j += 256) {
+        const int64_t g = i0 + j;
+        const Box6 b = g < n ? load_box(win, g) : Box6{{FLT_MAX, FLT_MAX, FLT_MAX}, {-FLT_MAX, -FLT_MAX, -FLT_MAX}};
+        for (int a = 0; a < 3; ++a) sb[0][j][a] = make_float2(b.lo[a], b.hi[a]);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int k = 1; k <= n_levels; ++k) {
+        const int half = 1 << (k - 1);
+        for (int j = threadIdx.x; j < kWinSpan - (1 << k) + 1; j += 256)
+            for (int a = 0; a < 3; ++a) {
+                const float2 u = sb[cur][j][a], v = sb[cur][j + half][a];
+                sb[cur ^ 1][j][a] = make_float2(fminf(u.x, v.x), fmaxf(u.y, v.y));
+            }
+        __syncthreads();
+        cur ^= 1;
+        const int64_t g = i0 + threadIdx.x;
+        if (g < static_cast<int64_t>(n) - (1 << k) + 1) {
+            Box6 b;
+            for (int a = 0; a < 3; ++a) {
+                b.lo[a] = sb[cur][threadIdx.x][a].x;
+                b.hi[a] = sb[cur][threadIdx.x][a].y;
+            }
+            store_box(win + static_cast<int64_t>(k) * n * 6, g, b);
+        }
+    }
 }
 
 // box of sorted leaves [a, b]: the union of the two windows of the largest power of two not above
@@ -305,7 +346,10 @@ hipError_t launch_lbvh(const LbvhArgs& a, hipStream_t stream)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather, dim3(bl), dim3(threads), 0, stream, a.tris_in, a.mat_in, a.perm_in, a.order, n,
                        a.tris_out, a.mat_out, a.perm_out, a.bvh_pos_out, a.win);
-    for (int32_t k = 1; k < a.levels; ++k) {
+    const int32_t fused = std::min<int32_t>(a.levels - 1, kWinFused);
+    if (fused > 0)
+        hipLaunchKernelGGL(k_window_fused, dim3(bl), dim3(threads), 0, stream, a.win, n, fused);
+    for (int32_t k = fused + 1; k < a.levels; ++k) {
         const int32_t half = 1 << (k - 1);
         const int32_t count = n - (1 << k) + 1;
         hipLaunchKernelGGL(k_window, dim3(static_cast<unsigned>((count + threads - 1) / threads)), dim3(threads), 0,
