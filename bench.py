@@ -80,6 +80,12 @@ def measured_l2_hit_rate():
     return None if rec is None else rec.get("l2_hit_rate")
 
 
+def measured_l2_slot_frac():
+    """Share of the L2 request slots (8 XCDs x 16 channels x 1 per cycle) k_trace uses."""
+    rec = profile_record("k_trace_meo20k_counters.md")
+    return None if rec is None else rec.get("l2_slot_frac")
+
+
 def measured_valu_issue():
     """Fraction of the VALU issue ceiling (0.25 wave64 instructions per SIMD-cycle) k_trace uses."""
     rec = profile_record("k_trace_meo20k_counters.md")
@@ -564,7 +570,7 @@ def main():
         achieved = bytes_per_ray * rays / (np.median(step_ms) * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                    "l2_hit_rate": measured_l2_hit_rate(),
+                    "l2_hit_rate": measured_l2_hit_rate(), "l2_slot_frac": measured_l2_slot_frac(),
                     "bytes_per_ray": round(bytes_per_ray, 1), "segments_per_ray": round(st["segments_per_ray"], 4),
                     "nodes_per_segment": round(st["nodes_per_segment"], 2),
                     "tris_per_segment": round(st["tris_per_segment"], 2)}
