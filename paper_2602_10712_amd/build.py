@@ -34,14 +34,16 @@ def _compile(src: str, obj: str) -> None:
 
 
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(OBJDIR, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-        if verbose:
-            print("hipcc", src, file=sys.stderr)
-        _compile(src, obj)
-        objs.append(obj)
+    objs = [os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+    if verbose:
+        print("hipcc", " ".join(SOURCES), file=sys.stderr)
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        for f in [pool.submit(_compile, src, obj) for src, obj in zip(SOURCES, objs)]:
+            f.result()
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", "-o", tmp, *objs], check=True)
     os.replace(tmp, LIB)
