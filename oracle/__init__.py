@@ -62,12 +62,14 @@ def lib():
         L.oracle_trace.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, P,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                    ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, P, ctypes.c_int64,
-                                   P, P, P, P, P, P, ctypes.c_int32]
+                                   P, P, P, P, P, P, P, ctypes.c_int32]
         L.oracle_trace.restype = ctypes.c_int
+        L.oracle_degen_thresholds.argtypes = [P]
+        L.oracle_degen_thresholds.restype = None
         L.oracle_trace_adjoint_rho.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, P,
                                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, P,
-                                               ctypes.c_int64, P, P, P, P, ctypes.c_int32]
+                                               ctypes.c_int64, P, P, P, P, ctypes.c_int32, P, ctypes.c_int32]
         L.oracle_trace_adjoint_rho.restype = ctypes.c_int
         L.oracle_trace_frozen.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, P,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
@@ -121,14 +123,27 @@ def default_pspec(rho_s, rho_d) -> np.ndarray:
     return np.array([f(float(a), float(b)) for a, b in zip(rs, rd)], dtype=np.float32)
 
 
+def degen_thresholds() -> dict:
+    """Thresholds of the degenerate-segment classification: tie, edge and near in units of the scene
+    size L, grazing as a cosine."""
+    out = np.zeros(4)
+    lib().oracle_degen_thresholds(_ptr(out))
+    return dict(zip(("tie", "edge", "graze", "near"), out.tolist()))
+
+
 class TraceResult:
-    def __init__(self, force, torque, hit_prim=None, degen=None, ray_force=None, ray_torque=None):
+    def __init__(self, force, torque, hit_prim=None, degen=None, ray_force=None, ray_torque=None, hit_x=None):
         self.force = force
         self.torque = torque
         self.hit_prim = hit_prim
         self.degen = degen
         self.ray_force = ray_force
         self.ray_torque = ray_torque
+        self.hit_x = hit_x
+
+    def path_degenerate(self) -> np.ndarray:
+        """[D][n_pix] bool: the path has a degenerate segment (records only)."""
+        return self.degen.astype(bool).any(axis=2)
 
 
 def trace(verts, tris, rho_s, rho_d, sun_dirs, *, nu: int, nv: int, bounces: int, jitter: bool = True,
@@ -149,29 +164,32 @@ def trace(verts, tris, rho_s, rho_d, sun_dirs, *, nu: int, nv: int, bounces: int
     n_pix = nu * nv if px is None else len(px)
     force = np.zeros((D, 3))
     torque = np.zeros((D, 3))
-    hp = dg = rf = rt = None
+    hp = dg = rf = rt = hx = None
     if records:
         hp = np.zeros((D, n_pix, bounces), dtype=np.int32)
         dg = np.zeros((D, n_pix, bounces), dtype=np.uint8)
         rf = np.zeros((D, n_pix, 3))
         rt = np.zeros((D, n_pix, 3))
+        hx = np.zeros((D, n_pix, bounces, 3))
     if threads is None:
         threads = default_threads()
     st = lib().oracle_trace(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd), _ptr(ps), _ptr(c),
                             _ptr(sun), D, _ptr(fr), nu, nv, bounces, int(bool(jitter)), float(flux), int(seed),
                             int(dir_index_base), int(design_index), _ptr(px), n_pix, _ptr(force), _ptr(torque),
-                            _ptr(hp), _ptr(dg), _ptr(rf), _ptr(rt), int(threads))
+                            _ptr(hp), _ptr(dg), _ptr(rf), _ptr(rt), _ptr(hx), int(threads))
     if st != 0:
         raise ValueError(f"oracle_trace failed ({st})")
-    return TraceResult(force, torque, hp, dg, rf, rt)
+    return TraceResult(force, torque, hp, dg, rf, rt, hx)
 
 
 def trace_adjoint_rho(verts, tris, rho_s, rho_d, sun_dirs, g_force, g_torque=None, *, nu: int, nv: int, bounces: int,
                       jitter: bool = True, flux: float = 1361.0, seed: int = 0, dir_index_base: int = 0,
                       design_index: int = 0, p_spec=None, com=None, frames_in=None, pix=None,
-                      threads: int | None = None):
+                      threads: int | None = None, drop_degenerate: bool = False):
     """FP64 dL/d rho_s, dL/d rho_d [n_tris] of L = sum_j g_force[j] . F_j + g_torque[j] . tau_j for the
-    estimator with frozen counters and specular-sampling probabilities (see srp_oracle.c)."""
+    estimator with frozen counters and specular-sampling probabilities (see srp_oracle.c).
+    With drop_degenerate, paths with a degenerate segment are left out and a third value is
+    returned: the [D][n_pix] bool mask of those paths."""
     verts = np.ascontiguousarray(verts, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     rs = np.ascontiguousarray(rho_s, dtype=np.float32)
@@ -187,14 +205,18 @@ def trace_adjoint_rho(verts, tris, rho_s, rho_d, sun_dirs, g_force, g_torque=Non
     gT = None if g_torque is None else np.ascontiguousarray(g_torque, dtype=np.float64).reshape(D, 3)
     g_rs = np.zeros(len(tris))
     g_rd = np.zeros(len(tris))
+    mask = np.zeros((D, n_pix), dtype=np.uint8) if drop_degenerate else None
     if threads is None:
         threads = default_threads()
     st = lib().oracle_trace_adjoint_rho(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd), _ptr(ps),
                                         _ptr(c), _ptr(sun), D, _ptr(fr), nu, nv, bounces, int(bool(jitter)),
                                         float(flux), int(seed), int(dir_index_base), int(design_index), _ptr(px),
-                                        n_pix, _ptr(gF), _ptr(gT), _ptr(g_rs), _ptr(g_rd), int(threads))
+                                        n_pix, _ptr(gF), _ptr(gT), _ptr(g_rs), _ptr(g_rd), int(bool(drop_degenerate)),
+                                        _ptr(mask), int(threads))
     if st != 0:
         raise ValueError(f"oracle_trace_adjoint_rho failed ({st})")
+    if drop_degenerate:
+        return g_rs, g_rd, mask.astype(bool)
     return g_rs, g_rd
 
 

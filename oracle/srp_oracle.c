@@ -311,6 +311,15 @@ static int64_t closest_hit(const scene_t* S, const double o[3], const double d[3
 #define DEG_GRAZE 1e-5
 #define DEG_NEAR 3e-6
 
+/* The four thresholds above (tie, edge, grazing, near), in units of L except GRAZE (a cosine). */
+void oracle_degen_thresholds(double out[4])
+{
+    out[0] = DEG_TIE;
+    out[1] = DEG_EDGE;
+    out[2] = DEG_GRAZE;
+    out[3] = DEG_NEAR;
+}
+
 static double point_segment_dist(const double p[3], const double a[3], const double b[3])
 {
     double ab[3], ap[3];
@@ -394,8 +403,10 @@ typedef struct {
  * and torque it deposits.  Optionally records, per surface interaction, the hit triangle
  * (-1 = the path escaped) and the degeneracy flag. */
 static void trace_path(const scene_t* S, const double fr[12], const double sun[3], const params_t* P, int64_t pixel,
-                       uint32_t dir_global, double F[3], double T[3], int32_t* hits, uint8_t* degen)
+                       uint32_t dir_global, double F[3], double T[3], int32_t* hits, uint8_t* degen, double* hx)
 {
+    if (hx)
+        for (int q = 0; q < 3 * P->bounces; ++q) hx[q] = NAN;
     const int32_t nu = P->nu;
     const int64_t i = pixel % nu, k = pixel / nu;
     double a = 0.5, b = 0.5;
@@ -439,6 +450,8 @@ static void trace_path(const scene_t* S, const double fr[12], const double sun[3
             x[c] = o[c] + t * d[c];
             lever[c] = x[c] - S->com[c];
         }
+        if (hx)
+            for (int c = 0; c < 3; ++c) hx[3 * (bnc - 1) + c] = x[c];
         const double cth = -dot3(d, n);
         double r[3];
         for (int c = 0; c < 3; ++c) r[c] = d[c] + 2.0 * cth * n[c];
@@ -510,6 +523,7 @@ typedef struct {
     uint8_t* degen;
     double* ray_force;
     double* ray_torque;
+    double* hit_x;
     int64_t next; /* work counter (rows of 64 pixels) */
     pthread_mutex_t lock;
     int32_t n_threads;
@@ -545,7 +559,8 @@ static void* worker(void* argp)
             double F[3], T[3];
             trace_path(J->S, J->frames + 12 * j, J->sun_dirs + 3 * j, J->P, pixel,
                        (uint32_t)(J->P->dir_index_base + j), F, T,
-                       J->hit_prim ? J->hit_prim + rec * B : NULL, J->degen ? J->degen + rec * B : NULL);
+                       J->hit_prim ? J->hit_prim + rec * B : NULL, J->degen ? J->degen + rec * B : NULL,
+                       J->hit_x ? J->hit_x + rec * B * 3 : NULL);
             for (int c = 0; c < 3; ++c) {
                 pf[c] += F[c];
                 pt[c] += T[c];
@@ -567,16 +582,17 @@ static void* worker(void* argp)
  *   frames [n_dirs][12] or NULL (computed from the mesh bounding box),
  *   pix [n_pix] explicit pixel list (pixel = i + k*nu) or NULL (all nu*nv pixels; n_pix ignored),
  *   force, torque [n_dirs][3] sums over the traced pixels (N, N m),
- *   hit_prim, degen [n_dirs][n_pix][bounces], ray_force, ray_torque [n_dirs][n_pix][3]: optional
- *   per-ray records.  Pixels are summed sequentially within chunks of 64; chunk sums are added
- *   in chunk order, so the result does not depend on the thread count.
+ *   hit_prim, degen [n_dirs][n_pix][bounces], ray_force, ray_torque [n_dirs][n_pix][3], hit_x
+ *   [n_dirs][n_pix][bounces][3] (hit points, NaN where the path has ended): optional per-ray
+ *   records.  Pixels are summed sequentially within chunks of 64; chunk sums are added in chunk
+ *   order, so the result does not depend on the thread count.
  */
 int oracle_trace(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris, const float* rho_s,
                  const float* rho_d, const float* p_spec, const double* com, const double* sun_dirs, int64_t n_dirs,
                  const double* frames, int32_t nu, int32_t nv, int32_t bounces, int32_t jitter, double flux,
                  uint64_t seed, int64_t dir_index_base, uint32_t design_index, const int64_t* pix, int64_t n_pix,
                  double* force, double* torque, int32_t* hit_prim, uint8_t* degen, double* ray_force,
-                 double* ray_torque, int32_t n_threads)
+                 double* ray_torque, double* hit_x, int32_t n_threads)
 {
     if (!verts || n_verts <= 0 || !tris || n_tris <= 0 || !rho_s || !rho_d || !sun_dirs || n_dirs < 0 || nu <= 0 ||
         nv <= 0 || bounces < 1 || !force || !torque)
@@ -604,7 +620,7 @@ int oracle_trace(const double* verts, int64_t n_verts, const int32_t* tris, int6
     memset(&J, 0, sizeof(J));
     J.S = &S; J.P = &P; J.frames = frames; J.sun_dirs = sun_dirs; J.n_dirs = n_dirs;
     J.pix = pix; J.n_pix = n_pix; J.hit_prim = hit_prim; J.degen = degen;
-    J.ray_force = ray_force; J.ray_torque = ray_torque; J.n_threads = n_threads;
+    J.ray_force = ray_force; J.ray_torque = ray_torque; J.hit_x = hit_x; J.n_threads = n_threads;
     J.n_chunks = (n_pix + CHUNK - 1) / CHUNK;
     J.part_f = calloc((size_t)3 * J.n_chunks * (n_dirs > 0 ? n_dirs : 1) + 3, sizeof(double));
     J.part_t = calloc((size_t)3 * J.n_chunks * (n_dirs > 0 ? n_dirs : 1) + 3, sizeof(double));
@@ -657,8 +673,12 @@ typedef struct {
     double c;       /* loss coefficient of the W_b term: -(G_b . o_b) */
 } grad_step_t;
 
-static void adjoint_path(const scene_t* S, const double fr[12], const double sun[3], const params_t* P, int64_t pixel,
-                         uint32_t dir_global, const double gF[3], const double gT[3], double* g_rs, double* g_rd)
+/* Adds one path's gradient terms and returns 1 when the path is degenerate (a segment flagged by
+ * segment_degenerate, classified as in trace_path).  With drop_degenerate set, a degenerate path
+ * adds nothing. */
+static int adjoint_path(const scene_t* S, const double fr[12], const double sun[3], const params_t* P, int64_t pixel,
+                        uint32_t dir_global, const double gF[3], const double gT[3], double* g_rs, double* g_rd,
+                        int drop_degenerate)
 {
     const int32_t nu = P->nu;
     const int64_t i = pixel % nu, k = pixel / nu;
@@ -686,9 +706,11 @@ static void adjoint_path(const scene_t* S, const double fr[12], const double sun
     int64_t tf = -1;
     double tg = 0.0, td = 0.0; /* G . r and G . n at the terminal interaction */
     double W_in = w;           /* current weight (for the terminal coefficients) */
+    int deg = 0;
     for (int bnc = 1; bnc <= P->bounces; ++bnc) {
         double t;
         int64_t f = closest_hit(S, o, d, skip, &t);
+        if (drop_degenerate && !deg) deg = segment_degenerate(S, o, d, skip, f, t);
         if (f < 0) break;
         const double* n = S->nrm + 3 * f;
         double x[3], lever[3], G[3], gx[3];
@@ -743,6 +765,7 @@ static void adjoint_path(const scene_t* S, const double fr[12], const double sun
         skip = f;
     }
     (void)W_in;
+    if (deg) return 1;
     /* L = w coef0 + sum_b W_b c_b + W_K (-(rho_s G.r + 2/3 rho_d G.n)) at the terminal one */
     double term_c = 0.0;
     if (have_term) term_c = -((double)S->rho_s[tf] * tg + (2.0 / 3.0) * (double)S->rho_d[tf] * td);
@@ -772,6 +795,7 @@ static void adjoint_path(const scene_t* S, const double fr[12], const double sun
         g_rs[tf] += -WK * tg;
         g_rd[tf] += -WK * (2.0 / 3.0) * td;
     }
+    return 0;
 }
 
 typedef struct {
@@ -787,6 +811,8 @@ typedef struct {
     double* g_rs; /* [threads][T] */
     double* g_rd;
     int32_t n_threads;
+    int32_t drop_degenerate;
+    uint8_t* path_degen; /* [D][n_pix] or NULL */
 } adj_job_t;
 
 typedef struct {
@@ -809,8 +835,10 @@ static void* adj_worker(void* argp)
         int64_t p1 = p0 + CHUNK < J->n_pix ? p0 + CHUNK : J->n_pix;
         for (int64_t q = p0; q < p1; ++q) {
             int64_t pixel = J->pix ? J->pix[q] : q;
-            adjoint_path(J->S, J->frames + 12 * j, J->sun_dirs + 3 * j, J->P, pixel,
-                         (uint32_t)(J->P->dir_index_base + j), J->gF + 3 * j, J->gT + 3 * j, gs, gd);
+            const int dg = adjoint_path(J->S, J->frames + 12 * j, J->sun_dirs + 3 * j, J->P, pixel,
+                                        (uint32_t)(J->P->dir_index_base + j), J->gF + 3 * j, J->gT + 3 * j, gs, gd,
+                                        J->drop_degenerate);
+            if (J->path_degen) J->path_degen[j * J->n_pix + q] = (uint8_t)dg;
         }
     }
     return NULL;
@@ -818,13 +846,15 @@ static void* adj_worker(void* argp)
 
 /* oracle_trace_adjoint_rho: dL/d rho_s and dL/d rho_d per facet (ADDED to g_rho_s, g_rho_d
  * [n_tris]) for L = sum_j gF[j] . F_j + gT[j] . tau_j, with the inputs of oracle_trace.
- * gT may be NULL (zero). */
+ * gT may be NULL (zero).  drop_degenerate != 0 leaves out every path with a degenerate segment
+ * (the rule of the hit records) and marks it in path_degen [n_dirs][n_pix] (may be NULL). */
 int oracle_trace_adjoint_rho(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                              const float* rho_s, const float* rho_d, const float* p_spec, const double* com,
                              const double* sun_dirs, int64_t n_dirs, const double* frames, int32_t nu, int32_t nv,
                              int32_t bounces, int32_t jitter, double flux, uint64_t seed, int64_t dir_index_base,
                              uint32_t design_index, const int64_t* pix, int64_t n_pix, const double* gF,
-                             const double* gT, double* g_rho_s, double* g_rho_d, int32_t n_threads)
+                             const double* gT, double* g_rho_s, double* g_rho_d, int32_t drop_degenerate,
+                             uint8_t* path_degen, int32_t n_threads)
 {
     if (!verts || !tris || !rho_s || !rho_d || !sun_dirs || !gF || !g_rho_s || !g_rho_d || nu <= 0 || nv <= 0 ||
         bounces < 1 || bounces > 15 || n_dirs < 0)
@@ -849,7 +879,8 @@ int oracle_trace_adjoint_rho(const double* verts, int64_t n_verts, const int32_t
     }
     params_t P = {nu, nv, bounces, jitter, flux, seed, dir_index_base, design_index};
     if (n_threads < 1) n_threads = 1;
-    adj_job_t J = {&S, &P, frames, sun_dirs, n_dirs, pix, n_pix, gF, gT, NULL, NULL, n_threads};
+    adj_job_t J = {&S, &P, frames, sun_dirs, n_dirs, pix, n_pix, gF, gT, NULL, NULL, n_threads, drop_degenerate,
+                   path_degen};
     J.g_rs = calloc((size_t)n_threads * n_tris, sizeof(double));
     J.g_rd = calloc((size_t)n_threads * n_tris, sizeof(double));
     pthread_t* th = malloc(sizeof(pthread_t) * n_threads);
