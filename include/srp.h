@@ -134,6 +134,21 @@ srp_status srp_frames(srp_scene scene, const double* sun_dirs, int64_t D, int32_
 srp_status srp_trace(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
                      const double* frames, double* force, double* torque, void* stream);
 
+/* srp_trace for callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, kernels and results as
+ * srp_trace (bit-identical), but the per-direction grid frames and FP64 per-workgroup partial
+ * sums live in one fixed array of SRP_NOALLOC_WORKSPACE_BYTES (16 MiB) that the library holds
+ * on each device it runs on until the process ends; the call allocates nothing (the scene itself
+ * must already exist).  A trace needs 64 D bytes (rounded up to 256) plus 48 bytes per direction
+ * and workgroup: about 13.2 KB per direction at 1024 x 1024 pixels with the library's launch
+ * shape, so up to ~1,260 directions per call there.  Larger requests fail with SRP_EINVAL and
+ * enqueue nothing.  Every call on a device shares that device's array, which keeps the last
+ * call's contents (every partial sum is rewritten before it is read): calls that overlap on one
+ * device, on different streams or threads, race and must be ordered by the caller. */
+#define SRP_NOALLOC_WORKSPACE_BYTES (16u << 20)
+srp_status srp_trace_noalloc(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
+                             const double* frames, double* force, double* torque, void* stream);
+
 /* Per-ray records of the same estimator for an explicit pixel list (parity and debugging).
  *   pix device int64 [n_pix] pixel ids (i + k*nu), or NULL for all nu*nv pixels in order;
  *   hit_prim device int32 [D][n_pix][bounces]: ORIGINAL index of the facet hit at each

@@ -46,6 +46,7 @@ _sigs = {
     "srp_scene_info": [P, P, P, P],
     "srp_frames": [P, P, I64, I32, I32, P, P],
     "srp_trace": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P],
+    "srp_trace_noalloc": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P],
     "srp_trace_records": [P, P, I64, ctypes.POINTER(TraceParams), P, P, I64, P, P, P],
     "srp_scene_ray_stats": [P, P, I64, ctypes.POINTER(TraceParams), P, I64, P],
     "srp_trace_adjoint": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P, P, P, P],
@@ -198,6 +199,16 @@ def srp_trace(scene, sun_dirs, params: TraceParams, force, torque=None, frames=N
     _dtype_check(frames, torch.float64, "frames")
     _check(_lib.srp_trace(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params), _dptr(frames),
                           _dptr(force), _dptr(torque), _stream(stream)))
+
+
+def srp_trace_noalloc(scene, sun_dirs, params: TraceParams, force, torque=None, frames=None, stream=None):
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(force, torch.float64, "force")
+    _dtype_check(torque, torch.float64, "torque")
+    _dtype_check(frames, torch.float64, "frames")
+    _check(_lib.srp_trace_noalloc(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params), _dptr(frames),
+                                  _dptr(force), _dptr(torque), _stream(stream)))
 
 
 def srp_trace_records(scene, sun_dirs, params: TraceParams, hit_prim, ray_force=None, pix=None, frames=None,

@@ -75,3 +75,20 @@ srp_status srp_fail(srp_status st, const std::string& msg);
 // Brings the host copies of the tree (nodes, order, triangle records) up to date after a build on
 // the device; host code that reads them (refit, statistics) calls this first.  Synchronous.
 srp_status srp_pull_host_tree(srp_scene_s* s);
+
+namespace srp {
+
+// Device memory a forward trace takes its workspace from instead of the scene's own buffers:
+// the grid frames first (rounded up to 256 bytes), then the per-workgroup partial sums.
+struct TraceWorkspace {
+    void* base;
+    size_t bytes;
+};
+
+// srp_trace with its argument checks; `ws` NULL uses (and grows) the scene's workspace, else the
+// trace runs in ws and fails with SRP_EINVAL, enqueueing nothing, when ws is too small.
+srp_status trace_into(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                      const double* frames, double* force, double* torque, hipStream_t stream,
+                      const TraceWorkspace* ws);
+
+}  // namespace srp

@@ -264,18 +264,18 @@ srp_status bind_device(const srp_scene_s* s)
 }
 
 // Frames launch + trace arguments shared by srp_trace, srp_trace_records and srp_trace_adjoint.
+// The grid frames and per-workgroup partial sums live in the scene's workspace, or in `ws` when it
+// is given (forward traces only): then nothing is allocated and a trace that needs more than
+// ws->bytes is rejected before anything is enqueued.
 srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
                          const double* frames, bool records, const int64_t* pix, int64_t n_pix, int32_t* rec_hit,
-                         float* rec_force, hipStream_t stream, srp::TraceArgs& a)
+                         float* rec_force, hipStream_t stream, srp::TraceArgs& a,
+                         const srp::TraceWorkspace* ws = nullptr)
 {
-    SRP_HIP(ensure(s->d_frames, s->frames_cap, static_cast<size_t>(D)));
-    SRP_HIP(srp::launch_frames(sun_dirs, D, s->lo, s->hi, s->L, p->nu, p->nv, p->flux,
-                               p->frame_mode == 1 ? frames : nullptr, nullptr, s->d_frames, stream));
     a = srp::TraceArgs{};
     a.nodes = s->d_nodes;
     a.tris = s->d_tris;
     a.mat = s->d_mat;
-    a.frames = s->d_frames;
     a.D = D;
     a.nu = p->nu;
     a.nv = p->nv;
@@ -310,8 +310,25 @@ srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
     // an XCD); fewer directions are spread over all of them
     a.xcd_major = D >= srp::kXcds ? 1 : 0;
     if (srp::grid_blocks(a, D) > 0x7fffffffLL) return fail(SRP_EINVAL, "trace too large for one launch");
-    SRP_HIP(ensure(s->d_partials, s->partials_cap, static_cast<size_t>(bpd * D * std::max(6, srp::kMaxHinges))));
-    a.partials = s->d_partials;
+    const size_t n_partials = static_cast<size_t>(bpd * D * std::max(6, srp::kMaxHinges));
+    if (ws) {
+        const size_t frame_bytes = (static_cast<size_t>(D) * sizeof(srp::DevFrame) + 255) / 256 * 256;
+        const size_t need = frame_bytes + n_partials * sizeof(double);
+        if (need > ws->bytes)
+            return fail(SRP_EINVAL, "this trace needs " + std::to_string(need) + " bytes of workspace (" +
+                                        std::to_string(D) + " directions x " + std::to_string(bpd) +
+                                        " workgroups each); the fixed workspace holds " + std::to_string(ws->bytes));
+        a.frames = reinterpret_cast<srp::DevFrame*>(ws->base);
+        a.partials = reinterpret_cast<double*>(static_cast<char*>(ws->base) + frame_bytes);
+    } else {
+        SRP_HIP(ensure(s->d_frames, s->frames_cap, static_cast<size_t>(D)));
+        SRP_HIP(ensure(s->d_partials, s->partials_cap, n_partials));
+        a.frames = s->d_frames;
+        a.partials = s->d_partials;
+    }
+    SRP_HIP(srp::launch_frames(sun_dirs, D, s->lo, s->hi, s->L, p->nu, p->nv, p->flux,
+                               p->frame_mode == 1 ? frames : nullptr, nullptr,
+                               const_cast<srp::DevFrame*>(a.frames), stream));
     return SRP_OK;
 }
 
@@ -328,6 +345,32 @@ srp_status enqueue_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
 }
 
 }  // namespace
+
+namespace srp {
+
+srp_status trace_into(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                      const double* frames, double* force, double* torque, hipStream_t stream,
+                      const TraceWorkspace* ws)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (D < 0) return fail(SRP_EINVAL, "D must be >= 0");
+    if (D == 0) return SRP_OK;
+    if (!sun_dirs || !force) return fail(SRP_EINVAL, "sun_dirs and force are required");
+    if (p->frame_mode == 1 && !frames) return fail(SRP_EINVAL, "frame_mode 1 needs frames");
+    if (p->dir_index_base + D > (int64_t(1) << 32)) return fail(SRP_EINVAL, "direction index exceeds 32 bits");
+    st = bind_device(s);
+    if (st != SRP_OK) return st;
+    TraceArgs a;
+    st = prepare_trace(s, sun_dirs, D, p, frames, false, nullptr, 0, nullptr, nullptr, stream, a, ws);
+    if (st != SRP_OK) return st;
+    SRP_HIP(launch_trace(a, false, stream));
+    SRP_HIP(launch_reduce(a.partials, D, a.blocks_per_dir, force, torque, stream));
+    return SRP_OK;
+}
+
+}  // namespace srp
 
 extern "C" {
 
@@ -464,22 +507,7 @@ srp_status srp_frames(srp_scene s, const double* sun_dirs, int64_t D, int32_t nu
 srp_status srp_trace(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p, const double* frames,
                      double* force, double* torque, void* stream_)
 {
-    if (!s) return fail(SRP_EINVAL, "scene is NULL");
-    srp_status st = check_params(p);
-    if (st != SRP_OK) return st;
-    if (D < 0) return fail(SRP_EINVAL, "D must be >= 0");
-    if (D == 0) return SRP_OK;
-    if (!sun_dirs || !force) return fail(SRP_EINVAL, "sun_dirs and force are required");
-    if (p->frame_mode == 1 && !frames) return fail(SRP_EINVAL, "frame_mode 1 needs frames");
-    if (p->dir_index_base + D > (int64_t(1) << 32)) return fail(SRP_EINVAL, "direction index exceeds 32 bits");
-    st = bind_device(s);
-    if (st != SRP_OK) return st;
-    hipStream_t stream = static_cast<hipStream_t>(stream_);
-    int32_t bpd = 0;
-    st = enqueue_trace(s, sun_dirs, D, p, frames, false, nullptr, 0, nullptr, nullptr, stream, &bpd);
-    if (st != SRP_OK) return st;
-    SRP_HIP(srp::launch_reduce(s->d_partials, D, bpd, force, torque, stream));
-    return SRP_OK;
+    return srp::trace_into(s, sun_dirs, D, p, frames, force, torque, static_cast<hipStream_t>(stream_), nullptr);
 }
 
 srp_status srp_trace_records(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
