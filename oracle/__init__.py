@@ -124,11 +124,23 @@ def default_pspec(rho_s, rho_d) -> np.ndarray:
 
 
 def degen_thresholds() -> dict:
-    """Thresholds of the degenerate-segment classification: tie, edge and near in units of the scene
-    size L, grazing as a cosine."""
-    out = np.zeros(4)
+    """Constants of the degenerate-segment classification (see srp_oracle.c): lat, the position
+    uncertainty across a primary ray in units of the scene size L (it grows by 1/cos(theta) at each
+    interaction); depth, the base uncertainty of an origin's distance from a plane, in units of L;
+    graze, the cosine below which a hit counts as grazing."""
+    out = np.zeros(3)
     lib().oracle_degen_thresholds(_ptr(out))
-    return dict(zip(("tie", "edge", "graze", "near"), out.tolist()))
+    return dict(zip(("lat", "depth", "graze"), out.tolist()))
+
+
+def degeneracy_uncertainty(L, cosines) -> np.ndarray:
+    """Uncertainty across the ray (m) of the segments of one path whose earlier interactions had
+    the given incidence cosines: u_1 = lat L, u_(b+1) = u_b / max(cos_b, graze) + lat L."""
+    th = degen_thresholds()
+    u = [th["lat"] * L]
+    for c in cosines:
+        u.append(u[-1] / max(c, th["graze"]) + th["lat"] * L)
+    return np.array(u)
 
 
 class TraceResult:

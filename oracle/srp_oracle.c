@@ -298,26 +298,45 @@ static int64_t closest_hit(const scene_t* S, const double o[3], const double d[3
 
 /* ---- degeneracy classification of one segment ------------------------------------------- */
 /* A segment is flagged when a float32 evaluation could plausibly choose a different closest
- * hit than this double evaluation:
- *   (i)   another front-facing hit lies within TIE * L of the closest one in t;
- *   (ii)  the ray passes within EDGE * L (measured in the plane normal to the ray) of an edge of
- *         a triangle that lies along the ray no farther than the closest hit (+ TIE * L);
+ * hit than this double evaluation.  Two uncertainties bound how the float32 ray differs:
+ *   u   its position across the ray (metres).  A primary ray carries u = LAT * L.  An interaction
+ *       at incidence cos(theta) spreads the hit point's error over the surface by 1/cos(theta)
+ *       and the point is rounded again, so the next segment carries u' = u / cos(theta) + LAT * L
+ *       (degeneracy_step).
+ *   up  the distance of its origin from the plane of a triangle with normal n:
+ *       DEPTH * L + u |n x m| for a segment leaving a facet with normal m (the spread error lies in
+ *       that facet's plane), DEPTH * L + u for a primary ray.
+ * The ray then meets that triangle's plane at a t uncertain by tau = up / |cos|.  The rules:
+ *   (i)   another front-facing triangle whose plane the ray meets within tau_f + tau_hit of the
+ *         closest hit in t;
+ *   (ii)  the ray passes within u (measured in the plane normal to the ray) of an edge of a
+ *         triangle whose plane it meets no nearer than -tau_f and no farther than
+ *         t_hit + tau_f + tau_hit;
  *   (iii) the closest hit is grazing: cos(theta) < GRAZE;
- *   (v)   the closest hit is at t < NEAR * L, or a front-facing triangle containing the ray's
- *         projection (within EDGE * L) has its plane within NEAR * L of the origin.
- * (The specular/diffuse event needs no margin: both paths compare the same float32 numbers.) */
-#define DEG_TIE 1e-5
-#define DEG_EDGE 1e-5
+ *   (iv)  the ray passes through (or within u of) a triangle seen nearly edge-on (|cos| <= GRAZE)
+ *         within that depth range;
+ *   (v)   the closest hit is at t < tau_hit, or a front-facing triangle containing the ray's
+ *         projection (within u) has its plane within tau_f of the origin.
+ * (The specular/diffuse event needs no margin: both paths compare the same float32 numbers.)
+ * LAT and DEPTH are at least ten times the largest float32 errors measured on the GPU tracer for
+ * the 20.6k-triangle satellite (3 bounces): hit points off across the ray by <= 0.101 of a model
+ * with LAT = 1e-6, along it by <= 0.231 of that u / cos, and off their facet's plane by <= 2.4e-7 L. */
+#define DEG_LAT 1.2e-6
+#define DEG_DEPTH 2.5e-6
 #define DEG_GRAZE 1e-5
-#define DEG_NEAR 3e-6
 
-/* The four thresholds above (tie, edge, grazing, near), in units of L except GRAZE (a cosine). */
-void oracle_degen_thresholds(double out[4])
+/* LAT and DEPTH (in units of L) and GRAZE (a cosine). */
+void oracle_degen_thresholds(double out[3])
 {
-    out[0] = DEG_TIE;
-    out[1] = DEG_EDGE;
+    out[0] = DEG_LAT;
+    out[1] = DEG_DEPTH;
     out[2] = DEG_GRAZE;
-    out[3] = DEG_NEAR;
+}
+
+/* Position uncertainty of the segment after an interaction at incidence cosine c. */
+static double degeneracy_step(const scene_t* S, double u, double c)
+{
+    return u / fmax(c, DEG_GRAZE) + DEG_LAT * S->L;
 }
 
 static double point_segment_dist(const double p[3], const double a[3], const double b[3])
@@ -333,15 +352,24 @@ static double point_segment_dist(const double p[3], const double a[3], const dou
     return sqrt(dot3(q, q));
 }
 
-static int segment_degenerate(const scene_t* S, const double o[3], const double d[3], int64_t skip, int64_t hit,
-                              double thit)
+/* Uncertainty of the origin's distance from the plane of triangle f (see above). */
+static double plane_uncertainty(const scene_t* S, int64_t skip, int64_t f, double u)
 {
-    const double L = S->L;
-    const double tmax = (hit >= 0) ? thit + DEG_TIE * L : INFINITY;
+    if (skip < 0) return DEG_DEPTH * S->L + u;
+    double c[3];
+    cross3(S->nrm + 3 * f, S->nrm + 3 * skip, c);
+    return DEG_DEPTH * S->L + u * sqrt(dot3(c, c));
+}
+
+static int segment_degenerate(const scene_t* S, const double o[3], const double d[3], int64_t skip, int64_t hit,
+                              double thit, double u)
+{
+    double chit = 1.0, tau_hit = 0.0;
     if (hit >= 0) {
-        double c = -dot3(d, S->nrm + 3 * hit);
-        if (c < DEG_GRAZE) return 1;
-        if (thit < DEG_NEAR * L) return 1;
+        chit = -dot3(d, S->nrm + 3 * hit);
+        if (chit < DEG_GRAZE) return 1;  /* (iii) */
+        tau_hit = plane_uncertainty(S, skip, hit, u) / chit;
+        if (thit < tau_hit) return 1;    /* (v) */
     }
     const double zero[3] = {0.0, 0.0, 0.0};
     for (int64_t f = 0; f < S->n_tris; ++f) {
@@ -354,13 +382,24 @@ static int segment_degenerate(const scene_t* S, const double o[3], const double 
             along[c] = dot3(rel, d);
             for (int a = 0; a < 3; ++a) q[c][a] = rel[a] - along[c] * d[a];
         }
-        double amin = fmin(along[0], fmin(along[1], along[2]));
-        double amax = fmax(along[0], fmax(along[1], along[2]));
-        if (amax < -DEG_NEAR * L - DEG_EDGE * L || amin > tmax) continue;
-        double e0 = point_segment_dist(zero, q[0], q[1]);
-        double e1 = point_segment_dist(zero, q[1], q[2]);
-        double e2 = point_segment_dist(zero, q[2], q[0]);
-        double emin = fmin(e0, fmin(e1, e2));
+        const double amin = fmin(along[0], fmin(along[1], along[2]));
+        const double amax = fmax(along[0], fmax(along[1], along[2]));
+        const double cosn = dot3(d, S->nrm + 3 * f);
+        const int edge_on = fabs(cosn) <= DEG_GRAZE;
+        /* depth relevance: where (and how uncertainly) the ray meets the triangle's plane */
+        double tplane = 0.0, tau = 0.0;
+        if (!edge_on) {
+            tplane = dot3(S->nrm + 3 * f, (double[3]){S->pv[9 * f] - o[0], S->pv[9 * f + 1] - o[1],
+                                                      S->pv[9 * f + 2] - o[2]}) / cosn;
+            tau = plane_uncertainty(S, skip, f, u) / fabs(cosn);
+            if (tplane < -tau) continue;                                /* behind the origin */
+            if (hit >= 0 && tplane > thit + tau + tau_hit) continue;     /* beyond the hit */
+        } else {
+            if (amax < -u) continue;
+            if (hit >= 0 && amin > thit + tau_hit) continue;
+        }
+        const double emin = fmin(point_segment_dist(zero, q[0], q[1]),
+                                 fmin(point_segment_dist(zero, q[1], q[2]), point_segment_dist(zero, q[2], q[0])));
         /* is the projected ray point inside the projected triangle? (signed areas) */
         double n1[3], n2[3], n3[3];
         double a0[3], a1[3], a2[3];
@@ -370,19 +409,14 @@ static int segment_degenerate(const scene_t* S, const double o[3], const double 
         cross3(a0, m0, n1); cross3(a1, m1, n2); cross3(a2, m2, n3);
         double s1 = dot3(n1, d), s2 = dot3(n2, d), s3 = dot3(n3, d);
         int inside = (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
-        if (!inside && emin >= DEG_EDGE * L) continue;
-        /* (ii) near an edge of a triangle the ray meets or narrowly misses */
-        if (emin < DEG_EDGE * L && amin <= tmax) return 1;
-        /* plane distance along the ray for a non-grazing triangle */
-        double cosn = dot3(d, S->nrm + 3 * f);
-        if (fabs(cosn) > DEG_GRAZE) {
-            double tplane = dot3(S->nrm + 3 * f, (double[3]){S->pv[9 * f] - o[0], S->pv[9 * f + 1] - o[1], S->pv[9 * f + 2] - o[2]}) / cosn;
+        if (!inside && emin >= u) continue;
+        if (emin < u) return 1;   /* (ii) near an edge of a triangle it meets or narrowly misses */
+        if (edge_on) return 1;    /* (iv) through a triangle seen edge-on */
+        if (cosn < 0.0) {
             /* (i) a second front-facing hit close to the closest one */
-            if (cosn < 0.0 && f != hit && hit >= 0 && fabs(tplane - thit) < DEG_TIE * L) return 1;
+            if (f != hit && hit >= 0 && fabs(tplane - thit) < tau + tau_hit) return 1;
             /* (v) a front-facing plane crossing very near the origin */
-            if (cosn < 0.0 && fabs(tplane) < DEG_NEAR * L) return 1;
-        } else if (amin <= tmax && amax >= -DEG_NEAR * L) {
-            return 1; /* grazing triangle the ray passes through */
+            if (fabs(tplane) < tau) return 1;
         }
     }
     return 0;
@@ -429,11 +463,12 @@ static void trace_path(const scene_t* S, const double fr[12], const double sun[3
     F[0] = F[1] = F[2] = 0.0;
     T[0] = T[1] = T[2] = 0.0;
     int deg = 0;
+    double unc = DEG_LAT * S->L; /* position uncertainty of the segment (degeneracy rules) */
     for (int bnc = 1; bnc <= P->bounces; ++bnc) {
         double t;
         int64_t f = closest_hit(S, o, d, skip, &t);
         if (degen) {
-            if (!deg) deg = segment_degenerate(S, o, d, skip, f, t);
+            if (!deg) deg = segment_degenerate(S, o, d, skip, f, t, unc);
             degen[bnc - 1] = (uint8_t)deg;
         }
         if (hits) hits[bnc - 1] = (int32_t)f;
@@ -453,6 +488,7 @@ static void trace_path(const scene_t* S, const double fr[12], const double sun[3
         if (hx)
             for (int c = 0; c < 3; ++c) hx[3 * (bnc - 1) + c] = x[c];
         const double cth = -dot3(d, n);
+        unc = degeneracy_step(S, unc, cth);
         double r[3];
         for (int c = 0; c < 3; ++c) r[c] = d[c] + 2.0 * cth * n[c];
         const double rs = (double)S->rho_s[f], rd = (double)S->rho_d[f];
@@ -707,10 +743,11 @@ static int adjoint_path(const scene_t* S, const double fr[12], const double sun[
     double tg = 0.0, td = 0.0; /* G . r and G . n at the terminal interaction */
     double W_in = w;           /* current weight (for the terminal coefficients) */
     int deg = 0;
+    double unc = DEG_LAT * S->L;
     for (int bnc = 1; bnc <= P->bounces; ++bnc) {
         double t;
         int64_t f = closest_hit(S, o, d, skip, &t);
-        if (drop_degenerate && !deg) deg = segment_degenerate(S, o, d, skip, f, t);
+        if (drop_degenerate && !deg) deg = segment_degenerate(S, o, d, skip, f, t, unc);
         if (f < 0) break;
         const double* n = S->nrm + 3 * f;
         double x[3], lever[3], G[3], gx[3];
@@ -721,6 +758,7 @@ static int adjoint_path(const scene_t* S, const double fr[12], const double sun[
         cross3(gT, lever, gx);
         for (int c = 0; c < 3; ++c) G[c] = gF[c] + gx[c];
         const double cth = -dot3(d, n);
+        unc = degeneracy_step(S, unc, cth);
         double r[3];
         for (int c = 0; c < 3; ++c) r[c] = d[c] + 2.0 * cth * n[c];
         /* incoming term: W_{b-1} (G . d_{b-1}) */
@@ -1071,10 +1109,12 @@ int oracle_trace_frozen(const double* verts, const double* verts0, int64_t n_ver
 
 /* Sunlight reaching o along -s is blocked by any facet other than `skip` whose outward side
  * faces the Sun (n.s > 0) and that the ray o + t s (t > 0) crosses.  *deg flags a ray passing
- * within DEG_EDGE L of such a facet's edge, or crossing one nearly edge-on. */
-static int sun_blocked(const scene_t* S, const double o[3], const double s[3], int64_t skip, int* deg)
+ * within u (its position uncertainty, see segment_degenerate) of such a facet's edge, crossing
+ * one nearly edge-on, or meeting its plane within u / cos of the origin. */
+static int sun_blocked(const scene_t* S, const double o[3], const double s[3], int64_t skip, double u, int* deg)
 {
-    const double L = S->L;
+    /* (the origin lies just off the plane of facet `skip`: see segment_degenerate for the
+       uncertainty of its distance from another plane) */
     const double zero[3] = {0.0, 0.0, 0.0};
     int blocked = 0;
     for (int64_t f = 0; f < S->n_tris; ++f) {
@@ -1090,7 +1130,7 @@ static int sun_blocked(const scene_t* S, const double o[3], const double s[3], i
             for (int a = 0; a < 3; ++a) q[c][a] = rel[a] - along[c] * s[a];
         }
         const double amax = fmax(along[0], fmax(along[1], along[2]));
-        if (amax < -DEG_NEAR * L) continue; /* entirely behind the origin */
+        if (amax < -plane_uncertainty(S, skip, f, u)) continue; /* entirely behind the origin */
         /* signed areas of the projected point against the three edges */
         double cr1[3], cr2[3], cr3[3], m0[3], m1[3], m2[3], e0[3], e1v[3], e2v[3];
         sub3(zero, q[0], m0); sub3(zero, q[1], m1); sub3(zero, q[2], m2);
@@ -1100,13 +1140,13 @@ static int sun_blocked(const scene_t* S, const double o[3], const double s[3], i
         const int inside = (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
         const double emin = fmin(point_segment_dist(zero, q[0], q[1]),
                                  fmin(point_segment_dist(zero, q[1], q[2]), point_segment_dist(zero, q[2], q[0])));
-        if (emin < DEG_EDGE * L) *deg = 1;
-        if (cosn < DEG_GRAZE && (inside || emin < DEG_EDGE * L)) *deg = 1;
+        if (emin < u) *deg = 1;
+        if (cosn < DEG_GRAZE && (inside || emin < u)) *deg = 1;
         if (!inside) continue;
         /* distance along s to the facet's plane */
         const double tplane = dot3(S->nrm + 3 * f, (double[3]){S->pv[9 * f] - o[0], S->pv[9 * f + 1] - o[1],
                                                              S->pv[9 * f + 2] - o[2]}) / cosn;
-        if (fabs(tplane) < DEG_NEAR * L) *deg = 1;
+        if (fabs(tplane) < plane_uncertainty(S, skip, f, u) / fmax(cosn, DEG_GRAZE)) *deg = 1;
         if (tplane > 0.0) blocked = 1;
     }
     return blocked;
@@ -1198,7 +1238,8 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
     for (int c = 0; c < 3; ++c) o[c] = x[c] + eps * n[c];
     /* direct sunlight at x */
     const double cs = dot3(n, s);
-    if (cs > 0.0 && !sun_blocked(S, o, s, f, &deg)) {
+    double unc = DEG_LAT * S->L; /* position uncertainty of the sample point (degeneracy rules) */
+    if (cs > 0.0 && !sun_blocked(S, o, s, f, unc, &deg)) {
         lit |= 1;
         const double W = G->flux * cs / kSpeedOfLight;
         double p[3] = {-s[0], -s[1], -s[2]};
@@ -1221,10 +1262,11 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
         for (int k = 1; k <= B - 1; ++k) {
             double t;
             int64_t g = closest_hit(S, ro, rdir, skip, &t);
-            if (!deg) deg = segment_degenerate(S, ro, rdir, skip, g, t);
+            if (!deg) deg = segment_degenerate(S, ro, rdir, skip, g, t, unc);
             if (g < 0) break;
             if (rec_hits) rec_hits[k - 1] = (int32_t)g;
             const double* ng = S->nrm + 3 * g;
+            unc = degeneracy_step(S, unc, -dot3(rdir, ng));
             double y[3], oy[3];
             for (int c = 0; c < 3; ++c) {
                 y[c] = ro[c] + t * rdir[c];
@@ -1232,7 +1274,7 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
             }
             const double rsg = (double)S->rho_s[g], rdg = (double)S->rho_d[g];
             const double cg = dot3(ng, s);
-            if (rdg > 0.0 && cg > 0.0 && !sun_blocked(S, oy, s, g, &deg)) {
+            if (rdg > 0.0 && cg > 0.0 && !sun_blocked(S, oy, s, g, unc, &deg)) {
                 lit |= 1 << k;
                 radiance += beta * rdg * cg;
             }

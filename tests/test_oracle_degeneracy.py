@@ -2,22 +2,25 @@
 reflectance adjoint restricted to non-degenerate paths (CPU only).
 
 A segment is degenerate when an FP32 evaluation could choose another closest hit than the FP64
-one; the rules and thresholds are stated in srp_oracle.c.  Each pin places single rays with
+one; the rules are stated in srp_oracle.c.  A primary segment's position uncertainty across the
+ray is u = LAT * L; after an interaction at incidence cos(theta) it becomes u / cos(theta) + LAT L.
+A primary ray meets a plane at incidence cos at a t uncertain by tau = (DEPTH L + u) / cos.  Each pin places single rays with
 caller frames (one ray per "direction": pixel (0, 0) of a 1 x 1 grid, centre at a chosen point)
 and compares the flags with the answer of plane geometry computed here, independently:
-  * a cube seen face-on: flagged exactly where the ray passes within EDGE * L of an edge of the
-    lit face in the image plane (the face's own diagonal included, the side faces edge-on along
-    the silhouette), never because of the unseen back face;
+  * a cube seen face-on: flagged exactly where the ray passes within u of an edge of the lit
+    face in the image plane (the face's own diagonal included, the side faces edge-on along the
+    silhouette), never because of the unseen back face;
+  * a lone plate: rays just inside or just outside its outer edges;
   * coincident layers: a two-sided sheet (opposite windings) is not a tie, a doubled sheet with
-    the same winding always is; two parallel sheets tie below TIE * L apart and not above;
+    the same winding always is; two parallel sheets tie below 2 tau apart and not above;
   * edges of a sheet behind the closest hit do not count;
   * a grazing plate is flagged;
-  * an entry plane within NEAR * L of a lit facet, in front of it or just behind it, is flagged,
-    one farther away is not.
-The grazing rule (cos theta < GRAZE) has no case of its own: a facet that steep projects to a
-sliver narrower than GRAZE times its size, so with GRAZE <= EDGE every ray meeting it is also
-within EDGE * L of its edges.  Mutations of the rules (the edge or near rule without the factor L,
-back-facing layers counted as ties, degenerate paths kept in the adjoint) each fail a pin here.
+  * an entry plane within tau of a lit facet, in front of it or just behind it, is flagged, one
+    farther away is not;
+  * the uncertainty grows at an interaction: after a 45-degree mirror, a ray meeting a second
+    plate 1.5 u from its edge is flagged (u there is (sqrt(2) + 1) LAT L), one 3.5 u away is not.
+Mutations of the rules (the edge or near rule without the factor L, back-facing layers counted
+as ties, no growth of u at an interaction, degenerate paths kept in the adjoint) each fail a pin.
 """
 import numpy as np
 
@@ -69,7 +72,7 @@ def test_cube_face_on_edges_and_diagonal():
     V = np.concatenate([f[0] for f in faces])
     T = np.concatenate([f[1] + 4 * i for i, f in enumerate(faces)]).astype(np.int32)
     L = scene_size(V)
-    th = oracle.degen_thresholds()["edge"] * L
+    th = oracle.degen_thresholds()["lat"] * L
     # the lit face z = +0.5 (light along -z); its triangles' edges in the image plane (x, y)
     top = [t for t in T if np.allclose(V[t][:, 2], 0.5)]
     assert len(top) == 2
@@ -103,7 +106,7 @@ def test_plate_outer_edges():
     so only the edge rule can flag a ray that passes just inside (a hit) or just outside (a miss)."""
     m = si.plate(3.0, 2.0)
     L = scene_size(m.verts)
-    th = oracle.degen_thresholds()["edge"] * L
+    th = oracle.degen_thresholds()["lat"] * L
     pts, expect = [], []
     for off in (0.3, 0.7, 1.5, 3.0):
         for sgn in (-1.0, 1.0):  # inside, outside
@@ -118,7 +121,8 @@ def test_plate_outer_edges():
 def test_coincident_layers():
     v, t = si.quad_grid((-1, -1, 0), (2, 0, 0), (0, 2, 0), 1, 1)  # faces +z
     L_single = scene_size(v)
-    tie = oracle.degen_thresholds()["tie"]
+    dt = oracle.degen_thresholds()
+    tau = (dt["depth"] + dt["lat"]) * L_single  # normal incidence
     rng = np.random.default_rng(1)
     pts = np.column_stack([rng.uniform(-0.6, 0.6, (60, 2)), np.zeros(60)])
     pts = pts[np.abs(pts[:, 0] - pts[:, 1]) > 0.05]  # clear of the shared diagonal (x = y)
@@ -132,9 +136,9 @@ def test_coincident_layers():
     T3 = np.concatenate([t, t + len(v)]).astype(np.int32)
     deg, hit = flags(np.concatenate([v, v]), T3, pts, [0, 0, 1.0], 1.0)
     assert deg.all() and (hit < 2).all()
-    # two parallel sheets dz apart: a tie below TIE * L, distinct hits above
-    for frac, tied in ((0.4, True), (2.5, False)):
-        dz = frac * tie * L_single  # L grows by dz/2 at most: well inside the margins
+    # two parallel sheets dz apart: a tie below tau_f + tau_hit = 2 tau, distinct hits above
+    for frac, tied in ((0.4, True), (0.75, True), (2.5, False)):
+        dz = frac * 2 * tau  # L grows by dz/2 at most: well inside the margins
         v2 = v + np.array([0, 0, -dz])
         deg, hit = flags(np.concatenate([v, v2]), T3, pts, [0, 0, 1.0], 1.0)
         assert bool(deg.all()) == tied and not (deg.any() and not tied)
@@ -177,9 +181,10 @@ def test_grazing_plate_flagged():
 def test_entry_plane_near_a_lit_facet():
     m = si.plate(4.0, 4.0)  # L = 5.7 m, so thresholds in metres differ from those in units of L
     L = scene_size(m.verts)
-    near = oracle.degen_thresholds()["near"]
+    dt = oracle.degen_thresholds()
+    tau = (dt["depth"] + dt["lat"]) * L  # normal incidence
     p = [[0.25, -0.1, 0.0]]
-    for h, flagged in ((0.4 * near * L, True), (3.0 * near * L, False)):
+    for h, flagged in ((0.4 * tau, True), (3.0 * tau, False)):
         deg, hit = flags(m.verts, m.tris, p, [0, 0, 1.0], h)
         assert bool(deg[0]) == flagged and hit[0] >= 0
         # the ray starting just behind the facet's plane misses it; an FP32 walk might not
@@ -251,3 +256,40 @@ def test_adjoint_without_degenerate_paths():
     scale = np.abs(full[0]).max() + np.abs(full[1]).max()
     assert np.abs(gs + rest_s - full[0]).max() < 1e-12 * scale
     assert np.abs(gd + rest_d - full[1]).max() < 1e-12 * scale
+
+
+def test_uncertainty_grows_at_an_interaction():
+    """A mirror at 45 degrees (plane y + z = 0, facing +y+z) sends light travelling along -z off
+    along +y to a plate in y = 2 facing -y whose lower edge lies at z = ze.  A primary ray at
+    (x0, y0) leaves the mirror from (x0, y0, -y0) + eps n (eps = 1e-5 L) and meets the plate at
+    z = -y0 + eps / sqrt(2), a distance delta above the edge.  The second segment carries
+    u2 = u1 / cos(45) + LAT L, so delta = 1.5 u1 is flagged there while the primary segment is
+    not, and delta = 3.5 u1 is flagged nowhere."""
+    vm, tm = si.quad_grid((-1, -1, 1), (2, 0, 0), (0, 2, -2), 1, 1)  # mirror, faces +y+z
+    ze = -0.2
+    vb, tb = si.quad_grid((-1, 2, ze), (2, 0, 0), (0, 0, 2), 1, 1)    # plate, faces -y
+    V = np.concatenate([vm, vb])
+    T = np.concatenate([tm, tb + len(vm)]).astype(np.int32)
+    L = scene_size(V)
+    u1 = oracle.degen_thresholds()["lat"] * L
+    u2 = u1 * np.sqrt(2.0) + u1
+    assert np.isclose(oracle.degeneracy_uncertainty(L, [np.sqrt(0.5)])[1], u2)
+    eps = 1e-5 * L
+    pts, expect = [], []
+    for frac, flagged in ((1.5, True), (3.5, False)):
+        delta = frac * u1
+        y0 = -(ze + delta) + eps / np.sqrt(2.0)
+        pts.append((0.3, y0, -y0))
+        expect.append(flagged)
+    n = len(pts)
+    fr = single_rays(pts, [0, 0, 1.0], 3.0)
+    sd = np.tile([0, 0, 1.0], (n, 1))
+    rs = np.array([1.0, 1.0, 0.0, 0.0], np.float32)  # mirror: rho_s = 1; plate: black
+    rd = np.zeros(4, np.float32)
+    res = oracle.trace(V, T, rs, rd, sd, nu=1, nv=1, bounces=2, jitter=False, frames_in=fr, records=True)
+    assert (res.hit_prim[:, 0, 0] < 2).all() and (res.hit_prim[:, 0, 1] >= 2).all()
+    # the second hit lies where the geometry above puts it
+    for q in range(n):
+        assert abs(res.hit_x[q, 0, 1, 2] - ze - (1.5, 3.5)[q] * u1) < 1e-3 * u1
+    assert not res.degen[:, 0, 0].any()
+    assert np.array_equal(res.degen[:, 0, 1].astype(bool), np.array(expect))
