@@ -73,7 +73,12 @@ def lib():
         L.oracle_trace_adjoint_rho.restype = ctypes.c_int
         L.oracle_trace_frozen.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, P,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                          ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, P, ctypes.c_int64, P, P, P]
+                                          ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, P, ctypes.c_int64, P,
+                                          ctypes.c_int32, P, P]
+        L.oracle_edge_term.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, P, P, P,
+                                       ctypes.c_int64, P, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
+                                       ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, P, P, ctypes.c_int32]
+        L.oracle_edge_term.restype = ctypes.c_int
         L.oracle_trace_frozen.restype = ctypes.c_int
         L.oracle_surface_estimate.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64,
                                               ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
@@ -234,9 +239,10 @@ def trace_adjoint_rho(verts, tris, rho_s, rho_d, sun_dirs, g_force, g_torque=Non
 
 def trace_frozen(verts, verts0, tris, rho_s, rho_d, sun_dirs, ref_hits, frames_in, *, nu: int, nv: int, bounces: int,
                  jitter: bool = True, flux: float = 1361.0, seed: int = 0, dir_index_base: int = 0,
-                 design_index: int = 0, p_spec=None, com=None, pix=None):
+                 design_index: int = 0, p_spec=None, com=None, pix=None, footprint: bool = True):
     """Frozen-visibility estimate (F, tau) at vertices `verts` with the facet sequences `ref_hits`
-    [D][n_pix][bounces] recorded at the reference vertices `verts0` (see srp_oracle.c)."""
+    [D][n_pix][bounces] recorded at the reference vertices `verts0` (see srp_oracle.c); footprint
+    scales each path by its primary facet's projected-area ratio."""
     verts = np.ascontiguousarray(verts, dtype=np.float64)
     verts0 = np.ascontiguousarray(verts0, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
@@ -255,10 +261,41 @@ def trace_frozen(verts, verts0, tris, rho_s, rho_d, sun_dirs, ref_hits, frames_i
     st = lib().oracle_trace_frozen(_ptr(verts), _ptr(verts0), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd),
                                    _ptr(ps), _ptr(c), _ptr(sun), D, _ptr(fr), nu, nv, bounces, int(bool(jitter)),
                                    float(flux), int(seed), int(dir_index_base), int(design_index), _ptr(px), n_pix,
-                                   _ptr(hits), _ptr(F), _ptr(T))
+                                   _ptr(hits), int(bool(footprint)), _ptr(F), _ptr(T))
     if st != 0:
         raise ValueError(f"oracle_trace_frozen failed ({st})")
     return F, T
+
+
+def edge_term(verts, tris, vert_hinge, hinge_origin, hinge_axis, rho_s, rho_d, sun_dirs, frames_in, *, bounces: int,
+              samples: int, flux: float = 1361.0, seed: int = 0, dir_index_base: int = 0, design_index: int = 0,
+              p_spec=None, com=None, threads: int | None = None):
+    """Visibility-edge part of d(F, tau)/d(hinge angle) by edge sampling (see srp_oracle.c):
+    [D][H][6] (force, torque per radian) and the number of moving edges."""
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    vh = np.ascontiguousarray(vert_hinge, dtype=np.int32)
+    ho = np.ascontiguousarray(hinge_origin, dtype=np.float64).reshape(-1, 3)
+    ha = np.ascontiguousarray(hinge_axis, dtype=np.float64).reshape(-1, 3)
+    ha = np.ascontiguousarray(ha / np.linalg.norm(ha, axis=1)[:, None]) if len(ha) else ha
+    rs = np.ascontiguousarray(rho_s, dtype=np.float32)
+    rd = np.ascontiguousarray(rho_d, dtype=np.float32)
+    ps = None if p_spec is None else np.ascontiguousarray(p_spec, dtype=np.float32)
+    c = None if com is None else np.ascontiguousarray(com, dtype=np.float64)
+    sun = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
+    D = len(sun)
+    fr = np.ascontiguousarray(frames_in, dtype=np.float64).reshape(D, 12)
+    out = np.zeros((D, len(ho), 6))
+    ne = ctypes.c_int64(0)
+    if threads is None:
+        threads = default_threads()
+    st = lib().oracle_edge_term(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(vh), _ptr(ho), _ptr(ha), len(ho),
+                                _ptr(rs), _ptr(rd), _ptr(ps), _ptr(c), _ptr(sun), D, _ptr(fr), int(bounces), float(flux),
+                                int(seed), int(dir_index_base), int(design_index), int(samples), _ptr(out),
+                                ctypes.byref(ne), int(threads))
+    if st != 0:
+        raise ValueError(f"oracle_edge_term failed ({st})")
+    return out, int(ne.value)
 
 
 class SurfaceResult:

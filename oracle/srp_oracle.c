@@ -433,31 +433,16 @@ typedef struct {
     uint32_t design_index;
 } params_t;
 
-/* Traces primary pixel `pixel` of direction j (global index dir_global) and returns the force
- * and torque it deposits.  Optionally records, per surface interaction, the hit triangle
- * (-1 = the path escaped) and the degeneracy flag. */
-static void trace_path(const scene_t* S, const double fr[12], const double sun[3], const params_t* P, int64_t pixel,
-                       uint32_t dir_global, double F[3], double T[3], int32_t* hits, uint8_t* degen, double* hx)
+/* Follows one path from origin o along d with ray-tube force w over up to P->bounces surface
+ * interactions and returns the force and torque it deposits.  Random draws use the Philox
+ * counter (ctr0, dir_global, bounce, design index) with key `seed`.  Optionally records, per
+ * interaction, the hit triangle (-1 = the path escaped), the degeneracy flag and the hit point. */
+static void follow_path(const scene_t* S, double o[3], double d[3], double w, const params_t* P, uint64_t seed,
+                        uint32_t ctr0, uint32_t dir_global, double F[3], double T[3], int32_t* hits, uint8_t* degen,
+                        double* hx)
 {
     if (hx)
         for (int q = 0; q < 3 * P->bounces; ++q) hx[q] = NAN;
-    const int32_t nu = P->nu;
-    const int64_t i = pixel % nu, k = pixel / nu;
-    double a = 0.5, b = 0.5;
-    if (P->jitter) {
-        double r[4];
-        draw4(P->seed, (uint32_t)pixel, dir_global, 0u, P->design_index, r);
-        a = r[0];
-        b = r[1];
-    }
-    const double* u = fr;
-    const double* v = fr + 3;
-    const double* o0 = fr + 6;
-    const double du = fr[9], dv = fr[10];
-    double o[3], d[3];
-    for (int c = 0; c < 3; ++c) o[c] = o0[c] + ((double)i + a) * du * u[c] + ((double)k + b) * dv * v[c];
-    propagation_dir(sun, d);
-    double w = P->flux * du * dv / kSpeedOfLight; /* force carried by the ray tube, N */
     const double eps = 1e-5 * S->L;
     int64_t skip = -1;
     F[0] = F[1] = F[2] = 0.0;
@@ -512,7 +497,7 @@ static void trace_path(const scene_t* S, const double fr[12], const double sun[3
             break;
         }
         double ev[4];
-        draw4(P->seed, (uint32_t)pixel, dir_global, (uint32_t)bnc, P->design_index, ev);
+        draw4(seed, ctr0, dir_global, (uint32_t)bnc, P->design_index, ev);
         const float ps = S->p_spec[f];
         double odir[3], w2;
         if ((float)ev[0] < ps) {
@@ -539,6 +524,31 @@ static void trace_path(const scene_t* S, const double fr[12], const double sun[3
         w = w2;
         skip = f;
     }
+}
+
+/* Traces primary pixel `pixel` of direction j (global index dir_global) and returns the force
+ * and torque it deposits, with the optional per-interaction records of follow_path. */
+static void trace_path(const scene_t* S, const double fr[12], const double sun[3], const params_t* P, int64_t pixel,
+                       uint32_t dir_global, double F[3], double T[3], int32_t* hits, uint8_t* degen, double* hx)
+{
+    const int32_t nu = P->nu;
+    const int64_t i = pixel % nu, k = pixel / nu;
+    double a = 0.5, b = 0.5;
+    if (P->jitter) {
+        double r[4];
+        draw4(P->seed, (uint32_t)pixel, dir_global, 0u, P->design_index, r);
+        a = r[0];
+        b = r[1];
+    }
+    const double* u = fr;
+    const double* v = fr + 3;
+    const double* o0 = fr + 6;
+    const double du = fr[9], dv = fr[10];
+    double o[3], d[3];
+    for (int c = 0; c < 3; ++c) o[c] = o0[c] + ((double)i + a) * du * u[c] + ((double)k + b) * dv * v[c];
+    propagation_dir(sun, d);
+    const double w = P->flux * du * dv / kSpeedOfLight; /* force carried by the ray tube, N */
+    follow_path(S, o, d, w, P, P->seed, (uint32_t)pixel, dir_global, F, T, hits, degen, hx);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -946,12 +956,12 @@ int oracle_trace_adjoint_rho(const double* verts, int64_t n_verts, const int32_t
 /* oracle_trace records at theta_0); at the current vertices each segment meets the PLANE of   */
 /* its frozen facet, so hit points move with the facets, normals and mirror directions turn,    */
 /* and the Lambertian direction is rebuilt in the basis of the turned normal from the same      */
-/* draws.  The path's deposits are scaled by P_f(theta)/P_f(theta_0), where P_f is the area of  */
-/* the primary facet projected on the grid plane (1/2 ((v1-v0) x (v2-v0)) . (-d)): the ray grid */
-/* samples each facet in proportion to its projected area, and this factor carries the          */
-/* first-order change of that share for a facet no other facet shadows.  Visibility changes     */
-/* between facets (silhouettes, shadows) are excluded.  Its derivative at theta_0 is the        */
-/* gradient the GPU adjoint computes for hinge angles.                                         */
+/* draws.  Its derivative at theta_0 is the pathwise part of the hinge-angle gradient: each     */
+/* path keeps its image position and its facet sequence.  With `footprint` set, the path's     */
+/* deposits are also scaled by P_f(theta)/P_f(theta_0), where P_f is the area of the primary    */
+/* facet projected on the grid plane (1/2 ((v1-v0) x (v2-v0)) . (-d)): the first-order change   */
+/* of the facet's share of the grid for a facet no other facet shadows (an approximation of   */
+/* the visibility-edge terms that oracle_edge_term estimates exactly).                          */
 /* ========================================================================================== */
 static double proj_area(const double* pv, const double d[3])
 {
@@ -967,7 +977,7 @@ int oracle_trace_frozen(const double* verts, const double* verts0, int64_t n_ver
                         const double* sun_dirs, int64_t n_dirs, const double* frames, int32_t nu, int32_t nv,
                         int32_t bounces, int32_t jitter, double flux, uint64_t seed, int64_t dir_index_base,
                         uint32_t design_index, const int64_t* pix, int64_t n_pix, const int32_t* ref_hits,
-                        double* force, double* torque)
+                        int32_t footprint, double* force, double* torque)
 {
     if (!verts || !verts0 || !tris || !rho_s || !rho_d || !sun_dirs || !frames || !ref_hits || !force || !torque ||
         nu <= 0 || nv <= 0 || bounces < 1)
@@ -1003,7 +1013,8 @@ int oracle_trace_frozen(const double* verts, const double* verts0, int64_t n_ver
             for (int c = 0; c < 3; ++c)
                 o[c] = fr[6 + c] + ((double)i + a) * fr[9] * fr[c] + ((double)k + b) * fr[10] * fr[3 + c];
             propagation_dir(sun_dirs + 3 * j, d);
-            const double scale = proj_area(S.pv + 9 * hits[0], d) / proj_area(S0.pv + 9 * hits[0], d);
+            const double scale =
+                footprint ? proj_area(S.pv + 9 * hits[0], d) / proj_area(S0.pv + 9 * hits[0], d) : 1.0;
             double w = flux * fr[9] * fr[10] / kSpeedOfLight;
             double PF[3] = {0, 0, 0}, PT[3] = {0, 0, 0};
             for (int bnc = 1; bnc <= bounces; ++bnc) {
@@ -1068,6 +1079,239 @@ int oracle_trace_frozen(const double* verts, const double* verts0, int64_t n_ver
     }
     scene_free(&S);
     scene_free(&S0);
+    return ORC_OK;
+}
+
+/* ========================================================================================== */
+/* Visibility-edge terms of the hinge-angle gradient, by edge sampling.                         */
+/*                                                                                            */
+/* Per sun direction the ray grid estimates F = (Phi/c) int g(y) dy over the grid plane, where  */
+/* g(y) is the momentum that a unit-weight path started at image point y deposits (all its      */
+/* interactions).  Turning hinge k moves the images of the edges of the facets it carries, and  */
+/* g jumps across them (silhouettes against the background or against other surfaces, edges     */
+/* between facets of different material, occlusion of one part by another).  The derivative    */
+/* of the integral is the pathwise part (oracle_trace_frozen without footprint factor: every    */
+/* path keeps its image position and facet sequence) plus, for every moving edge,              */
+/*     (Phi/c) int_edge (g(y - delta n) - g(y + delta n)) v_n dl,                              */
+/* n the edge's unit normal in the grid plane, v_n = n . (the image velocity of the edge point  */
+/* under the rotation about the hinge axis), delta -> 0.  Edges hidden behind other surfaces    */
+/* contribute nothing because g is the same on both sides.                                     */
+/*                                                                                            */
+/* Estimator: the moving edges are the distinct edges of facets whose three vertices the hinge */
+/* carries, numbered by first appearance in facet order (an edge coincident with an earlier    */
+/* one -- the two layers of a two-sided sheet, the shared edge of two facets -- counts once).   */
+/* Edge e takes M stratified points s = (m + xi)/M along it; both side points y -+ delta n with */
+/* delta = 1e-5 L start a full path with the same draws (Philox key seed ^ EDGE_KEY, counter   */
+/* (e M + m, direction, bounce, design); xi is the first uniform of bounce 0), and the edge's   */
+/* contribution is (Phi/c) (len/M) sum_m v_n(s_m) (deposit(y-) - deposit(y+)).  Secondary       */
+/* visibility edges (reflected light crossing an edge) are not included.                       */
+/* ========================================================================================== */
+#define EDGE_KEY 0x9E3779B97F4A7C15ULL
+
+typedef struct {
+    double key[6]; /* the two endpoint positions, lexicographically ordered */
+    int64_t order; /* facet * 3 + edge slot */
+    int32_t a, b;  /* vertex indices (a, b in the facet's winding order) */
+    int32_t hinge;
+} edge_rec_t;
+
+static int cmp_edge_key(const void* pa, const void* pb)
+{
+    const edge_rec_t* x = (const edge_rec_t*)pa;
+    const edge_rec_t* y = (const edge_rec_t*)pb;
+    for (int c = 0; c < 6; ++c) {
+        if (x->key[c] < y->key[c]) return -1;
+        if (x->key[c] > y->key[c]) return 1;
+    }
+    return (x->order > y->order) - (x->order < y->order);
+}
+
+static int cmp_edge_order(const void* pa, const void* pb)
+{
+    const edge_rec_t* x = (const edge_rec_t*)pa;
+    const edge_rec_t* y = (const edge_rec_t*)pb;
+    return (x->order > y->order) - (x->order < y->order);
+}
+
+static int pos_less(const double* p, const double* q)
+{
+    for (int c = 0; c < 3; ++c) {
+        if (p[c] < q[c]) return 1;
+        if (p[c] > q[c]) return 0;
+    }
+    return 0;
+}
+
+/* Distinct moving edges, in order of first appearance; returns the count (or -1). */
+static int64_t moving_edges(const double* verts, const int32_t* tris, int64_t n_tris, const int32_t* vert_hinge,
+                            edge_rec_t** out)
+{
+    edge_rec_t* all = malloc(sizeof(edge_rec_t) * (size_t)(3 * n_tris + 1));
+    if (!all) return -1;
+    int64_t n = 0;
+    for (int64_t f = 0; f < n_tris; ++f) {
+        const int32_t* t = tris + 3 * f;
+        const int32_t k = vert_hinge[t[0]];
+        if (k < 0 || vert_hinge[t[1]] != k || vert_hinge[t[2]] != k) continue;
+        for (int e = 0; e < 3; ++e) {
+            edge_rec_t r;
+            r.a = t[e];
+            r.b = t[(e + 1) % 3];
+            r.hinge = k;
+            r.order = 3 * f + e;
+            const double* pa = verts + 3 * r.a;
+            const double* pb = verts + 3 * r.b;
+            const double* lo = pos_less(pb, pa) ? pb : pa;
+            const double* hi = lo == pa ? pb : pa;
+            for (int c = 0; c < 3; ++c) {
+                r.key[c] = lo[c];
+                r.key[3 + c] = hi[c];
+            }
+            all[n++] = r;
+        }
+    }
+    qsort(all, (size_t)n, sizeof(edge_rec_t), cmp_edge_key);
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (i > 0 && memcmp(all[i].key, all[i - 1].key, sizeof(all[i].key)) == 0) continue;
+        all[m++] = all[i];
+    }
+    qsort(all, (size_t)m, sizeof(edge_rec_t), cmp_edge_order);
+    *out = all;
+    return m;
+}
+
+typedef struct {
+    const scene_t* S;
+    const params_t* P;
+    const edge_rec_t* E;
+    int64_t n_edges;
+    const double* verts;
+    const double* hinge_origin;
+    const double* hinge_axis;
+    int32_t n_hinges;
+    const double* frames;
+    const double* sun_dirs;
+    int64_t n_dirs;
+    int32_t samples;
+    double* out; /* [n_dirs][n_hinges][6] */
+    int32_t n_threads;
+    int32_t tid;
+} edge_job_t;
+
+static void* edge_worker(void* argp)
+{
+    edge_job_t* J = (edge_job_t*)argp;
+    const scene_t* S = J->S;
+    const params_t* P = J->P;
+    const double delta = 1e-5 * S->L;
+    const uint64_t key = P->seed ^ EDGE_KEY;
+    const int32_t M = J->samples;
+    for (int64_t j = J->tid; j < J->n_dirs; j += J->n_threads) { /* whole directions: deterministic sums */
+        const double* fr = J->frames + 12 * j;
+        const double* u = fr;
+        const double* v = fr + 3;
+        const double* o0 = fr + 6;
+        const uint32_t dir_global = (uint32_t)(P->dir_index_base + j);
+        double d[3];
+        propagation_dir(J->sun_dirs + 3 * j, d);
+        double* acc = J->out + (size_t)j * J->n_hinges * 6;
+        for (int64_t e = 0; e < J->n_edges; ++e) {
+            const edge_rec_t* r = J->E + e;
+            const double* p0 = J->verts + 3 * r->a;
+            const double* p1 = J->verts + 3 * r->b;
+            double rel0[3], rel1[3];
+            sub3(p0, o0, rel0);
+            sub3(p1, o0, rel1);
+            const double y0[2] = {dot3(rel0, u), dot3(rel0, v)};
+            const double y1[2] = {dot3(rel1, u), dot3(rel1, v)};
+            const double ty[2] = {y1[0] - y0[0], y1[1] - y0[1]};
+            const double len = sqrt(ty[0] * ty[0] + ty[1] * ty[1]);
+            if (!(len > 0.0)) continue; /* an edge seen end-on sweeps no area */
+            const double nrm[2] = {ty[1] / len, -ty[0] / len};
+            const double* ho = J->hinge_origin + 3 * r->hinge;
+            const double* ha = J->hinge_axis + 3 * r->hinge;
+            double sum[6] = {0, 0, 0, 0, 0, 0};
+            for (int32_t m = 0; m < M; ++m) {
+                const uint32_t ctr0 = (uint32_t)(e * M + m);
+                double xi[4];
+                draw4(key, ctr0, dir_global, 0u, P->design_index, xi);
+                const double sp = ((double)m + xi[0]) / (double)M;
+                /* the edge point, its image and its image velocity under the rotation */
+                double x[3], rx[3], xd[3];
+                for (int c = 0; c < 3; ++c) x[c] = p0[c] + sp * (p1[c] - p0[c]);
+                sub3(x, ho, rx);
+                cross3(ha, rx, xd);
+                const double vn = dot3(xd, u) * nrm[0] + dot3(xd, v) * nrm[1];
+                const double y[2] = {y0[0] + sp * ty[0], y0[1] + sp * ty[1]};
+                double Fm[3], Tm[3], Fp[3], Tp[3];
+                for (int side = 0; side < 2; ++side) {
+                    const double sgn = side == 0 ? -1.0 : 1.0;
+                    const double yy[2] = {y[0] + sgn * delta * nrm[0], y[1] + sgn * delta * nrm[1]};
+                    double o[3], dd[3] = {d[0], d[1], d[2]};
+                    for (int c = 0; c < 3; ++c) o[c] = o0[c] + yy[0] * u[c] + yy[1] * v[c];
+                    follow_path(S, o, dd, 1.0, P, key, ctr0, dir_global, side == 0 ? Fm : Fp, side == 0 ? Tm : Tp,
+                                NULL, NULL, NULL);
+                }
+                for (int c = 0; c < 3; ++c) {
+                    sum[c] += vn * (Fm[c] - Fp[c]);
+                    sum[3 + c] += vn * (Tm[c] - Tp[c]);
+                }
+            }
+            const double scale = P->flux / kSpeedOfLight * len / (double)M;
+            for (int c = 0; c < 6; ++c) acc[6 * r->hinge + c] += scale * sum[c];
+        }
+    }
+    return NULL;
+}
+
+/*
+ * oracle_edge_term: the visibility-edge part of d(F, tau)/d(hinge angle) for n_dirs sun
+ * directions (see above).  verts [n_verts][3] are the current vertices, vert_hinge [n_verts] the
+ * hinge carrying each vertex (-1: rigid), hinge_origin/hinge_axis [n_hinges][3] (axis unit) the
+ * hinge lines, frames [n_dirs][12] the grid frames, `samples` = M points per edge.  Writes
+ * dF [n_dirs][n_hinges][6] (force then torque, per radian).  Also returns the edge count in
+ * *n_edges_out (may be NULL).
+ */
+int oracle_edge_term(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                     const int32_t* vert_hinge, const double* hinge_origin, const double* hinge_axis, int32_t n_hinges,
+                     const float* rho_s, const float* rho_d, const float* p_spec, const double* com,
+                     const double* sun_dirs, int64_t n_dirs, const double* frames, int32_t bounces, double flux,
+                     uint64_t seed, int64_t dir_index_base, uint32_t design_index, int32_t samples, double* dF,
+                     int64_t* n_edges_out, int32_t n_threads)
+{
+    if (!verts || !tris || !vert_hinge || (n_hinges > 0 && (!hinge_origin || !hinge_axis)) || !rho_s || !rho_d ||
+        !sun_dirs || !frames || !dF || bounces < 1 || samples < 1 || n_dirs < 0 || n_hinges < 0)
+        return ORC_EINVAL;
+    scene_t S;
+    int st = scene_init(&S, verts, n_verts, tris, n_tris, rho_s, rho_d, p_spec, com);
+    if (st != ORC_OK) {
+        scene_free(&S);
+        return st;
+    }
+    edge_rec_t* E = NULL;
+    const int64_t ne = moving_edges(verts, tris, n_tris, vert_hinge, &E);
+    if (ne < 0) {
+        scene_free(&S);
+        return ORC_ENOMEM;
+    }
+    if (n_edges_out) *n_edges_out = ne;
+    memset(dF, 0, sizeof(double) * 6 * (size_t)(n_dirs * n_hinges));
+    params_t P = {1, 1, bounces, 0, flux, seed, dir_index_base, design_index};
+    if (n_threads < 1) n_threads = 1;
+    pthread_t* th = malloc(sizeof(pthread_t) * n_threads);
+    edge_job_t* jobs = malloc(sizeof(edge_job_t) * n_threads);
+    for (int32_t t = 0; t < n_threads; ++t) {
+        edge_job_t J = {&S, &P, E, ne, verts, hinge_origin, hinge_axis, n_hinges, frames, sun_dirs, n_dirs, samples,
+                        dF, n_threads, t};
+        jobs[t] = J;
+        pthread_create(&th[t], NULL, edge_worker, &jobs[t]);
+    }
+    for (int32_t t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    free(th);
+    free(jobs);
+    free(E);
+    scene_free(&S);
     return ORC_OK;
 }
 
