@@ -78,7 +78,15 @@ typedef struct {
  *                 reduction options of the paper's convergence study, bit 0 stratified surface
  *                 sampling (sample i of N takes the area coordinate (i + u)/N), bit 1 plain Monte
  *                 Carlo directions (uniform over the hemisphere, weight 2 cos theta) instead of the
- *                 Lambertian BRDF's cosine importance sampling; 0..3. */
+ *                 Lambertian BRDF's cosine importance sampling; 0..3.
+ *   edge_samples  srp_trace_adjoint only: points per moving edge for the visibility-edge part of the
+ *                 hinge-angle gradient (0: that part is left out), 0..4096; see srp_trace_adjoint.
+ *   ray_mask      device uint32 bitmap [D][ceil(nu * nv / 32)] or NULL: a set bit (p & 31) in word
+ *                 p >> 5 of direction j leaves primary pixel p of that direction out, its whole path
+ *                 included (no deposit, no gradient; in records its hits are -1 and its force 0).
+ *                 srp_trace, srp_trace_noalloc, srp_trace_records and srp_trace_adjoint only (other
+ *                 calls reject it with SRP_EUNSUPPORTED).  For restricting a trace to a region of the
+ *                 image and for parity checks on a chosen set of rays. */
 typedef struct {
     int32_t nu, nv;
     int32_t bounces;
@@ -90,6 +98,8 @@ typedef struct {
     int32_t frame_mode;
     int32_t tiles_per_wave;
     int32_t sampling;
+    int32_t edge_samples;
+    const uint32_t* ray_mask;
 } srp_trace_params;
 
 /* Creates a scene from a rest-pose mesh.  Host arrays, copied:
@@ -104,15 +114,33 @@ srp_status srp_scene_create(const double* verts, int64_t n_verts, const int32_t*
 
 /* Applies a design (paper Sec. 3.1: the design maps to a mesh with per-face materials):
  *   hinge_angles host [n_hinges] radians (NULL = keep the current angles); the panel vertices
- *   are rotated in FP64 and, when the angles change, the boxes of the rest-pose BVH are refitted
- *   on the host (same topology and triangle order) and uploaded;
+ *   are rotated in FP64 and, when the angles change, the triangle records are rebuilt on the host
+ *   and uploaded and the boxes of the current BVH are refitted on the device (same topology and
+ *   triangle order; each box the union of its records' boxes, widened by 1e-6 L and rounded
+ *   outward);
  *   rho_s, rho_d device float [n_tris] (original facet order), 0 <= rho, rho_s + rho_d <= 1;
  *   p_spec device float [n_tris] or NULL: frozen probability of sampling the specular event at
- *   each facet.  NULL selects rho_s/(rho_s + rho_d) clamped to [0.01, 0.99] when both are
- *   positive, else 1 (mirror only) or 0.
+ *   each facet, in [0, 1], 0 only where rho_s = 0 and 1 only where rho_d = 0 (else an event with
+ *   nonzero reflectance could never be sampled: SRP_EINVAL).  NULL selects rho_s/(rho_s + rho_d)
+ *   clamped to [0.01, 0.99] when both are positive, else 1 (mirror only) or 0.
  * Synchronises `stream` once to validate the materials (SRP_EINVAL if out of range). */
 srp_status srp_scene_set_design(srp_scene scene, const double* hinge_angles, const float* rho_s,
                                 const float* rho_d, const float* p_spec, void* stream);
+
+/* Replaces the rest-pose vertices (paper Sec. 3.1: any design that maps to a mesh of fixed
+ * connectivity, e.g. a parametric bus or panel size), keeping the triangles, the hinge
+ * assignment, the hinge angles (applied on top of the new rest pose) and the materials.
+ *   verts host double [n_verts][3], copied; n_verts must equal the scene's;
+ *   mode 0: keep the tree and refit its boxes on the device (fast; traversal slows down as the
+ *           geometry drifts from the pose the tree was built for), 1: build a new SAH tree on the
+ *           host (the packed materials are reordered with the records).
+ * The moving edges of the hinge gradient are re-derived from the new rest pose.  Synchronises
+ * `stream`.  Errors: SRP_EINVAL (NULL, size, mode), SRP_EDEGENERATE (non-finite vertex or a
+ * zero-area facet in the new pose; the scene keeps its old geometry), SRP_EUNSUPPORTED (mode 1:
+ * tree deeper than the traversal stack; the scene keeps its old geometry), SRP_EDEVICE (the scene
+ * is left undefined and must be destroyed). */
+srp_status srp_scene_set_vertices(srp_scene scene, const double* verts, int64_t n_verts, int32_t mode,
+                                  void* stream);
 
 /* Host copy of the current (hinge-rotated) vertices, [n_verts][3]. */
 srp_status srp_scene_get_vertices(srp_scene scene, double* verts_out, int64_t n_verts);
@@ -152,10 +180,12 @@ srp_status srp_trace_noalloc(srp_scene scene, const double* sun_dirs, int64_t D,
 /* Per-ray records of the same estimator for an explicit pixel list (parity and debugging).
  *   pix device int64 [n_pix] pixel ids (i + k*nu), or NULL for all nu*nv pixels in order;
  *   hit_prim device int32 [D][n_pix][bounces]: ORIGINAL index of the facet hit at each
- *   interaction, -1 after the path ended; ray_force device float [D][n_pix][3] or NULL. */
+ *   interaction, -1 after the path ended; ray_force device float [D][n_pix][3] or NULL;
+ *   hit_point device float [D][n_pix][bounces][3] or NULL: the FP32 hit point of each interaction
+ *   (body frame, m), NaN after the path ended.  A ray_mask in params is indexed by pixel id. */
 srp_status srp_trace_records(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
                              const double* frames, const int64_t* pix, int64_t n_pix, int32_t* hit_prim,
-                             float* ray_force, void* stream);
+                             float* ray_force, float* hit_point, void* stream);
 
 /* Reverse-mode gradient of the forward estimator (paper Sec. 3.4, differentiable radiation
  * pressure: gradients of force and torque with respect to the design), for the same rays as
@@ -166,11 +196,21 @@ srp_status srp_trace_records(srp_scene scene, const double* sun_dirs, int64_t D,
  *                           sequences held fixed (the specular-sampling probabilities are
  *                           frozen, so each path's weight is a polynomial in the reflectances);
  *   dL/d hinge angle        to g_hinge (device double [n_hinges], may be NULL; at most 4 hinges,
- *                           else SRP_EUNSUPPORTED): derivative of every hit point, normal, grid
- *                           footprint and secondary ray under the rotation, with the facet hit at
- *                           every interaction held fixed.  Terms from rays that cross a
- *                           silhouette edge as the panel turns (visibility changes) are not
- *                           included.
+ *                           else SRP_EUNSUPPORTED), in two parts: the pathwise part -- every path
+ *                           keeps its image position and the facet hit at every interaction, and
+ *                           its hit points, normals and secondary rays follow the rotation; and,
+ *                           with params->edge_samples = M > 0, the visibility-edge part by edge
+ *                           sampling -- for every distinct edge of a hinge-carried facet, M
+ *                           stratified points along its image, each starting full paths just on
+ *                           either side of it (1e-5 L away, same draws: Philox key seed ^
+ *                           0x9E3779B97F4A7C15, counter (edge * M + point, direction, bounce,
+ *                           design)), the jump of their deposit times the edge's normal image
+ *                           velocity (silhouettes against the background or other surfaces,
+ *                           occlusion, edges between facets).  Edges are numbered by first
+ *                           appearance over the facets; coincident edges count once.  Left out:
+ *                           visibility edges of reflected light, and the dependence of the grid
+ *                           frame on the design (the estimator's expectation does not depend on
+ *                           it).  With edge terms, at most 65535 directions per call.
  * Gradients are summed in FP64 (wavefront-aggregated atomics per facet, fixed-order sums per
  * direction for the hinges) and rounded to float for g_rho_s and g_rho_d.  Uses scene workspace;
  * calls on the same scene must be ordered on one stream. */
@@ -181,8 +221,9 @@ srp_status srp_trace_adjoint(srp_scene scene, const double* sun_dirs, int64_t D,
 /* Traversal statistics for the bandwidth model: a host-side single-ray depth-first closest-hit
  * traversal (nearer child first) of this scene's BVH on the same rays as srp_trace, for every
  * pixel_stride-th pixel of each direction.  sun_dirs and frames are HOST arrays here.
- * out host double [5]: primary rays, ray segments (traversals), BVH nodes fetched, triangles
- * tested, surface hits.  Synchronous; reads the materials back from the device. */
+ * out host double [6]: primary rays, ray segments (traversals), BVH nodes fetched, triangles
+ * tested, surface hits, primary rays that hit the scene.  Synchronous; reads the materials back
+ * from the device.  A ray_mask in params is rejected (SRP_EUNSUPPORTED). */
 srp_status srp_scene_ray_stats(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
                                const double* frames, int64_t pixel_stride, double* out);
 
@@ -262,6 +303,22 @@ srp_status srp_mlp_num_params(srp_mlp mlp, int64_t* n);
  * the pre-activations and BF16 activations for a following srp_mlp_backward on the same x and N
  * (library-owned workspace); 0 runs the inference path. */
 srp_status srp_mlp_forward(srp_mlp mlp, const float* x, int64_t N, float* y, int32_t keep_activations, void* stream);
+
+/* The surrogate as the paper uses its proxy (Sec. 3.3: the network answers force queries in place
+ * of the simulator), with the simulator kept as fallback: two independently trained networks a and
+ * b of the same shape (n_in >= 3) evaluate x device float [N][n_in] -- the sun unit vector, then the
+ * design inputs scaled to [-1, 1] -- and the call writes
+ *   y         device float [N][n_out]: out_scale * (y_a + y_b) / 2;
+ *   disagree  device float [N] or NULL: ||y_a - y_b|| in network units;
+ *   fail_idx  device int32 [N]: in ascending order, the queries that fail the confidence test --
+ *             outside the training domain (| ||x[0:3]|| - 1 | > 1e-5 or |x_i| > 1 + 1e-6 for a
+ *             design input) or disagreement above `threshold` (NaN fails everything);
+ *   n_fail    device int32 [1]: their number (entries of fail_idx beyond it are unspecified).
+ * The caller traces the failing queries (srp_trace) and overwrites their rows of y.  Workspace
+ * (both networks' outputs, flags, compaction scratch) belongs to network a; calls using a must be
+ * ordered.  0 <= N <= 2^30. */
+srp_status srp_mlp_ensemble(srp_mlp a, srp_mlp b, const float* x, int64_t N, float threshold, float out_scale,
+                            float* y, float* disagree, int32_t* fail_idx, int32_t* n_fail, void* stream);
 
 /* Back-propagates g_y = dL/dy (device float [N][n_out]) through the kept activations: weight and
  * bias gradients are ADDED to the library's gradient buffer; g_x (device float [N][n_in], may be

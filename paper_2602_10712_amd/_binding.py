@@ -29,25 +29,45 @@ class srp_hinge(ctypes.Structure):
 
 
 class TraceParams(ctypes.Structure):
+    """srp_trace_params.  ray_mask: a device tensor of 32-bit words (see ray_mask_bits) or None; the
+    object keeps a reference to it, so it stays alive as long as these parameters."""
     _fields_ = [("nu", I32), ("nv", I32), ("bounces", I32), ("jitter", I32), ("flux", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("dir_index_base", I64), ("design_index", I32), ("frame_mode", I32),
-                ("tiles_per_wave", I32), ("sampling", I32)]
+                ("tiles_per_wave", I32), ("sampling", I32), ("edge_samples", I32), ("ray_mask", P)]
 
     def __init__(self, nu=256, nv=256, bounces=1, jitter=1, flux=1361.0, seed=0, dir_index_base=0, design_index=0,
-                 frame_mode=0, tiles_per_wave=0, sampling=0):
+                 frame_mode=0, tiles_per_wave=0, sampling=0, ray_mask=None, edge_samples=0):
         super().__init__(int(nu), int(nv), int(bounces), int(bool(jitter)), float(flux), int(seed),
-                         int(dir_index_base), int(design_index), int(frame_mode), int(tiles_per_wave), int(sampling))
+                         int(dir_index_base), int(design_index), int(frame_mode), int(tiles_per_wave), int(sampling),
+                         int(edge_samples), _dptr(ray_mask))
+        self._mask_ref = ray_mask
+
+
+def ray_mask_bits(left_out, device="cuda"):
+    """Packs a bool array [D][nu * nv] (True = primary pixel left out) into the uint32 bitmap
+    [D][ceil(nu * nv / 32)] that srp_trace_params.ray_mask takes (bit p & 31 of word p >> 5), as a
+    device tensor (int32 storage of the same bits)."""
+    import torch
+    m = np.asarray(left_out, dtype=bool)
+    m = m.reshape(m.shape[0], -1)
+    words = (m.shape[1] + 31) // 32
+    pad = np.zeros((m.shape[0], words * 32), dtype=bool)
+    pad[:, :m.shape[1]] = m
+    w = np.packbits(pad.reshape(m.shape[0], words, 4, 8), axis=-1, bitorder="little").astype(np.uint32)
+    packed = (w[..., 0, 0] | (w[..., 1, 0] << 8) | (w[..., 2, 0] << 16) | (w[..., 3, 0] << 24)).view(np.int32)
+    return torch.from_numpy(np.ascontiguousarray(packed)).to(device)
 
 
 _sigs = {
     "srp_scene_create": [P, I64, P, I64, P, P, I32, P, ctypes.POINTER(P)],
     "srp_scene_set_design": [P, P, P, P, P, P],
     "srp_scene_get_vertices": [P, P, I64],
+    "srp_scene_set_vertices": [P, P, I64, I32, P],
     "srp_scene_info": [P, P, P, P],
     "srp_frames": [P, P, I64, I32, I32, P, P],
     "srp_trace": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P],
     "srp_trace_noalloc": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P],
-    "srp_trace_records": [P, P, I64, ctypes.POINTER(TraceParams), P, P, I64, P, P, P],
+    "srp_trace_records": [P, P, I64, ctypes.POINTER(TraceParams), P, P, I64, P, P, P, P],
     "srp_scene_ray_stats": [P, P, I64, ctypes.POINTER(TraceParams), P, I64, P],
     "srp_trace_adjoint": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P, P, P, P],
     "srp_batch_trace": [P, I32, P, I64, ctypes.POINTER(TraceParams), P, P, P],
@@ -58,6 +78,7 @@ _sigs = {
     "srp_mlp_create": [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)],
     "srp_mlp_num_params": [P, ctypes.POINTER(I64)],
     "srp_mlp_forward": [P, P, I64, P, I32, P],
+    "srp_mlp_ensemble": [P, P, P, I64, ctypes.c_float, ctypes.c_float, P, P, P, P, P],
     "srp_mlp_backward": [P, P, I64, P, P],
     "srp_mlp_adam_step": [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
     "srp_mlp_zero_grad": [P, P],
@@ -172,6 +193,11 @@ def srp_scene_set_design(scene, hinge_angles, rho_s, rho_d, p_spec=None, stream=
     _check(_lib.srp_scene_set_design(scene, _hptr(ang), _dptr(rho_s), _dptr(rho_d), _dptr(p_spec), _stream(stream)))
 
 
+def srp_scene_set_vertices(scene, verts, mode=0, stream=None):
+    v = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 3)
+    _check(_lib.srp_scene_set_vertices(scene, _hptr(v), v.shape[0], int(mode), _stream(stream)))
+
+
 def srp_scene_get_vertices(scene, n_verts):
     out = np.zeros((n_verts, 3))
     _check(_lib.srp_scene_get_vertices(scene, _hptr(out), n_verts))
@@ -212,15 +238,17 @@ def srp_trace_noalloc(scene, sun_dirs, params: TraceParams, force, torque=None, 
 
 
 def srp_trace_records(scene, sun_dirs, params: TraceParams, hit_prim, ray_force=None, pix=None, frames=None,
-                      stream=None):
+                      stream=None, hit_point=None):
     import torch
     _dtype_check(sun_dirs, torch.float64, "sun_dirs")
     _dtype_check(hit_prim, torch.int32, "hit_prim")
     _dtype_check(ray_force, torch.float32, "ray_force")
+    _dtype_check(hit_point, torch.float32, "hit_point")
     _dtype_check(pix, torch.int64, "pix")
     n_pix = 0 if pix is None else pix.shape[0]
     _check(_lib.srp_trace_records(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params), _dptr(frames),
-                                  _dptr(pix), n_pix, _dptr(hit_prim), _dptr(ray_force), _stream(stream)))
+                                  _dptr(pix), n_pix, _dptr(hit_prim), _dptr(ray_force), _dptr(hit_point),
+                                  _stream(stream)))
 
 
 def srp_trace_adjoint(scene, sun_dirs, params: TraceParams, g_force, g_torque=None, g_rho_s=None, g_rho_d=None,
@@ -294,10 +322,10 @@ def srp_scene_ray_stats(scene, sun_dirs, params: TraceParams, pixel_stride=1, fr
     """Host arrays in, dict out: rays, segments, nodes, tris, hits (see srp.h)."""
     sd = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
     fr = None if frames is None else np.ascontiguousarray(frames, dtype=np.float64).reshape(-1, 12)
-    out = np.zeros(5)
+    out = np.zeros(6)
     _check(_lib.srp_scene_ray_stats(scene, _hptr(sd), len(sd), ctypes.byref(params), _hptr(fr), int(pixel_stride),
                                     _hptr(out)))
-    return dict(zip(("rays", "segments", "nodes", "tris", "hits"), out.tolist()))
+    return dict(zip(("rays", "segments", "nodes", "tris", "hits", "hit_rays"), out.tolist()))
 
 
 # bytes a single ray must touch (bandwidth model): one 64-byte node record per node fetched,
@@ -309,7 +337,7 @@ def ray_stats(scene, sun_dirs, params: TraceParams, n_dirs=16, pixel_stride=97):
     """Per-ray averages of srp_scene_ray_stats over n_dirs directions spread over sun_dirs."""
     sd = np.asarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
     idx = np.linspace(0, len(sd) - 1, min(n_dirs, len(sd))).astype(int)
-    tot = {"rays": 0.0, "segments": 0.0, "nodes": 0.0, "tris": 0.0, "hits": 0.0}
+    tot = {"rays": 0.0, "segments": 0.0, "nodes": 0.0, "tris": 0.0, "hits": 0.0, "hit_rays": 0.0}
     for j in idx:
         p = TraceParams(params.nu, params.nv, params.bounces, params.jitter, params.flux, params.seed,
                         params.dir_index_base + int(j), params.design_index, 0)
@@ -318,7 +346,7 @@ def ray_stats(scene, sun_dirs, params: TraceParams, n_dirs=16, pixel_stride=97):
             tot[k] += st[k]
     r, s = max(tot["rays"], 1.0), max(tot["segments"], 1.0)
     return {"rays": tot["rays"], "segments_per_ray": tot["segments"] / r, "nodes_per_segment": tot["nodes"] / s,
-            "tris_per_segment": tot["tris"] / s, "hits_per_ray": tot["hits"] / r,
+            "tris_per_segment": tot["tris"] / s, "hits_per_ray": tot["hits"] / r, "hit_ray_fraction": tot["hit_rays"] / r,
             "bytes_per_ray": (NODE_BYTES * tot["nodes"] + TRI_BYTES * tot["tris"] + HIT_BYTES * tot["hits"]) / r}
 
 
@@ -356,6 +384,11 @@ class Scene:
     def vertices(self):
         return srp_scene_get_vertices(self.handle, self.n_verts)
 
+    def set_vertices(self, verts, rebuild=False, stream=None):
+        """New rest-pose vertices (srp_scene_set_vertices): the tree refitted on the device, or
+        rebuilt on the host when `rebuild`."""
+        srp_scene_set_vertices(self.handle, verts, 1 if rebuild else 0, stream)
+
     def info(self):
         return srp_scene_info(self.handle)
 
@@ -387,17 +420,19 @@ class Scene:
         srp_trace_adjoint(self.handle, sd, params, gF, gT, grs, grd, gh if self.n_hinges else None, fr, stream)
         return grs, grd, gh[:self.n_hinges]
 
-    def records(self, sun_dirs, params: TraceParams, pix=None, frames=None, stream=None):
+    def records(self, sun_dirs, params: TraceParams, pix=None, frames=None, stream=None, points=False):
+        """(hit_prim, ray_force) or, with points, (hit_prim, ray_force, hit_point) as device tensors."""
         import torch
         sd = torch.as_tensor(sun_dirs, dtype=torch.float64, device="cuda").contiguous()
         D = sd.shape[0]
         n_pix = params.nu * params.nv if pix is None else len(pix)
         hp = torch.empty((D, n_pix, params.bounces), dtype=torch.int32, device="cuda")
         rf = torch.empty((D, n_pix, 3), dtype=torch.float32, device="cuda")
+        hx = torch.empty((D, n_pix, params.bounces, 3), dtype=torch.float32, device="cuda") if points else None
         px = None if pix is None else torch.as_tensor(np.asarray(pix), dtype=torch.int64, device="cuda").contiguous()
         fr = None if frames is None else torch.as_tensor(frames, dtype=torch.float64, device="cuda").contiguous()
-        srp_trace_records(self.handle, sd, params, hp, rf, px, fr, stream)
-        return hp, rf
+        srp_trace_records(self.handle, sd, params, hp, rf, px, fr, stream, hit_point=hx)
+        return (hp, rf, hx) if points else (hp, rf)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -431,6 +466,17 @@ def srp_mlp_forward(mlp, x, y, keep_activations=False, stream=None):
     _dtype_check(x, torch.float32, "x")
     _dtype_check(y, torch.float32, "y")
     _check(_lib.srp_mlp_forward(mlp, _dptr(x), x.shape[0], _dptr(y), int(bool(keep_activations)), _stream(stream)))
+
+
+def srp_mlp_ensemble(mlp_a, mlp_b, x, threshold, out_scale, y, fail_idx, n_fail, disagree=None, stream=None):
+    import torch
+    _dtype_check(x, torch.float32, "x")
+    _dtype_check(y, torch.float32, "y")
+    _dtype_check(disagree, torch.float32, "disagree")
+    _dtype_check(fail_idx, torch.int32, "fail_idx")
+    _dtype_check(n_fail, torch.int32, "n_fail")
+    _check(_lib.srp_mlp_ensemble(mlp_a, mlp_b, _dptr(x), x.shape[0], float(threshold), float(out_scale), _dptr(y),
+                                 _dptr(disagree), _dptr(fail_idx), _dptr(n_fail), _stream(stream)))
 
 
 def srp_mlp_backward(mlp, g_y, g_x=None, stream=None):

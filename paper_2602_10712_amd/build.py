@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libsrp.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["srp_api.cpp", "bvh_build.cpp", "ray_stats.cpp", "trace_kernels.hip", "adjoint_kernels.hip", "surface_kernels.hip", "bvh_gpu.hip", "mlp_api.cpp", "mlp_kernels.hip", "mlp_infer.hip",
-           "orbit.cpp", "attitude_kernels.hip", "attitude_api.cpp", "noalloc.hip"]
+           "orbit.cpp", "attitude_kernels.hip", "attitude_api.cpp", "noalloc.hip", "ensemble.hip", "edge_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

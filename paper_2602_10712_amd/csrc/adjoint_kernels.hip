@@ -14,14 +14,12 @@
 //    products that leave one factor out are carried forward per interaction slot, so no division
 //    by k occurs.  Per-facet sums use wavefront-aggregated FP64 atomics.
 //
-//  * dL/d theta_h (hinge angles): forward-mode tangents with each path's facet sequence frozen.
-//    Hit points slide along the ray onto the turned facet planes, normals and mirror directions
-//    turn, the Lambertian direction follows the basis of the turned normal, and the secondary
-//    origin x + eps n follows the hit point and the normal.  A footprint term scales the path by
-//    d log P_f / d theta for its primary facet f, where P_f is the facet's area projected on the
-//    grid plane: the ray grid samples a facet in proportion to P_f.  Visibility changes between
-//    facets (silhouette, shadow and occlusion edges) and the grid frame's own dependence on the
-//    design are excluded.
+//  * dL/d theta_h (hinge angles), pathwise part: forward-mode tangents with each path at its image
+//    position and its facet sequence frozen.  Hit points slide along the ray onto the turned facet
+//    planes, normals and mirror directions turn, the Lambertian direction follows the basis of the
+//    turned normal, and the secondary origin x + eps n follows the hit point and the normal.  The
+//    primary-visibility edges of the moving facets add the boundary part (edge_kernels.hip); the
+//    secondary-visibility edges and the grid frame's own dependence on the design are excluded.
 #include <float.h>
 
 #include "srp_internal.h"
@@ -145,6 +143,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
                     a.jitter != 0, o, d);
         float w = fr.w;
         bool alive = valid;
+        if (a.ray_mask && valid && ray_masked(a, j, pixel)) alive = false;  // a left-out path adds nothing
         int skip = -1;
 
         // reflectance adjoint state
@@ -161,10 +160,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
         int K = 0;
         int term_f = -1;
         float term_s = 0.0f, term_d = 0.0f;
-        float Lpath = 0.0f;
-        // hinge tangents: origin Od, direction Dd, accumulated dL, footprint factor
-        float Od[MAXH > 0 ? MAXH : 1][3], Dd[MAXH > 0 ? MAXH : 1][3], Ld[MAXH > 0 ? MAXH : 1],
-            phi[MAXH > 0 ? MAXH : 1];
+        // hinge tangents: origin Od, direction Dd, accumulated dL
+        float Od[MAXH > 0 ? MAXH : 1][3], Dd[MAXH > 0 ? MAXH : 1][3], Ld[MAXH > 0 ? MAXH : 1];
 #pragma unroll
         for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h) {
             for (int c = 0; c < 3; ++c) {
@@ -172,7 +169,6 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
                 Dd[h][c] = 0.0f;
             }
             Ld[h] = 0.0f;
-            phi[h] = 0.0f;
         }
 
         for (int b = 1; b <= a.bounces; ++b) {
@@ -205,7 +201,6 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
             float G[3];
             cross3f(gT, l, G);
             for (int c = 0; c < 3; ++c) G[c] += gF[c];
-            Lpath += dot3f(G, g);
 
             // ---- reflectances: coefficient of the current weight W_K from the incident term
             const float cin = dot3f(G, d_in);
@@ -251,10 +246,6 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
                                           v0[2] - A.hinge_origin[h][2]};
                     cross3f(ax, n, nd);
                     cross3f(ax, rel, pd);
-                    if (b == 1) {
-                        // d log P_f / d theta, P_f = A_f (n . (-d))
-                        phi[h] = dot3f(nd, d_in) / dot3f(n, d_in);
-                    }
                 }
                 const float xp[3] = {x[0] - v0[0], x[1] - v0[1], x[2] - v0[2]};
                 float q[3];
@@ -311,7 +302,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
         }
 #pragma unroll
         for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h)
-            if (valid && h < H) accH[h] += Ld[h] + Lpath * phi[h];
+            if (valid && h < H) accH[h] += Ld[h];
     }
 
     if (MAXH > 0) {
@@ -404,16 +395,21 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_finish_adjoint(const double* g_rho, int32_t n_tris, float* g_rho_s, float* g_rho_d,
-                                 const double* hinge_partials, int64_t D, int32_t blocks_per_dir, int32_t n_hinges,
-                                 double* per_dir, double* g_hinge, hipStream_t stream)
+hipError_t launch_reduce_hinges(const double* hinge_partials, int64_t D, int32_t blocks_per_dir, double* per_dir,
+                                hipStream_t stream)
 {
     const int threads = 256;
-    if (n_hinges > 0 && g_hinge) {
-        const int64_t nt = D * kMaxHinges;
-        hipLaunchKernelGGL(k_reduce_hinges, dim3(static_cast<unsigned>((nt + threads - 1) / threads)), dim3(threads), 0,
-                           stream, hinge_partials, D, blocks_per_dir, per_dir);
-    }
+    const int64_t nt = D * kMaxHinges;
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_hinges, dim3(static_cast<unsigned>((nt + threads - 1) / threads)), dim3(threads), 0,
+                       stream, hinge_partials, D, blocks_per_dir, per_dir);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_adjoint(const double* g_rho, int32_t n_tris, float* g_rho_s, float* g_rho_d, int64_t D,
+                                 int32_t n_hinges, const double* per_dir, double* g_hinge, hipStream_t stream)
+{
+    const int threads = 256;
     const int64_t n = n_tris > n_hinges ? n_tris : n_hinges;
     hipLaunchKernelGGL(k_finish_adjoint, dim3(static_cast<unsigned>((n + threads - 1) / threads)), dim3(threads), 0,
                        stream, g_rho, n_tris, g_rho_s, g_rho_d, per_dir, D, n_hinges, g_hinge);

@@ -17,6 +17,8 @@
 //      through LDS), from which the box of any node, a contiguous leaf range, is the union of two
 //      windows;
 //   7. pre-order positions (each kept node walks to the root) and the node records.
+// The same window table refits a kept tree after the vertices move (launch_refit): every child
+// slot's subtree covers a contiguous range of records, so its box is the union of two windows.
 // Every node covers a contiguous range of sorted leaves, so no step waits on another thread: there
 // is no bottom-up pass with device-scope counters and fences, whose cost grows with the tree height.
 #include <float.h>
@@ -256,7 +258,7 @@ __device__ __forceinline__ int32_t kept_nodes(const int2* __restrict__ range, co
 __global__ void k_emit(int32_t n, const int2* __restrict__ child, const int2* __restrict__ range,
                        const int32_t* __restrict__ parent, const int32_t* __restrict__ scan,
                        const float* __restrict__ win, float pad, BvhNode* __restrict__ out,
-                       int32_t* __restrict__ depth_out)
+                       int4* __restrict__ ranges_out, int32_t* __restrict__ depth_out)
 {
     const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n - 1) return;
@@ -276,6 +278,7 @@ __global__ void k_emit(int32_t n, const int2* __restrict__ child, const int2* __
     const int2 c = child[i];
     BvhNode rec;
     int32_t codes[2];
+    int2 cover[2];
     const int32_t kids[2] = {c.x, c.y};
     int32_t next = pre + 1;
     for (int slot = 0; slot < 2; ++slot) {
@@ -284,8 +287,10 @@ __global__ void k_emit(int32_t n, const int2* __restrict__ child, const int2* __
         if (ch < 0) {
             b = load_box(win, ~ch);
             codes[slot] = ~((~ch << 3) | 1);
+            cover[slot] = make_int2(~ch, ~ch);
         } else {
             const int2 r = range[ch];
+            cover[slot] = r;
             b = range_box(win, n, r.x, r.y);
             const int32_t k = kept_nodes(range, scan, ch);
             if (k == 0) {
@@ -310,7 +315,47 @@ __global__ void k_emit(int32_t n, const int2* __restrict__ child, const int2* __
     }
     rec.f[3] = make_float4(__int_as_float(codes[0]), __int_as_float(codes[1]), 0.0f, 0.0f);
     out[pre] = rec;
+    ranges_out[pre] = make_int4(cover[0].x, cover[0].y, cover[1].x, cover[1].y);
     atomicMax(depth_out, depth + 1);  // the children of this node sit one level below it
+}
+
+// Refit of a kept tree: level 0 of the window table from the current records (in tree order).
+__global__ void k_tri_boxes(const TriRec* __restrict__ tris, int32_t n, float* __restrict__ win)
+{
+    const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    store_box(win, i, tri_box(tris[i]));
+}
+
+// Refit of a kept tree: the two child boxes of node i from the record ranges their subtrees cover
+// (ranges[i] = first0, last0, first1, last1; last < first for an empty leaf, whose unreachable box
+// stays), widened by pad and rounded outward.
+__global__ void k_refit_nodes(BvhNode* __restrict__ nodes, const int4* __restrict__ ranges, int32_t n_nodes,
+                              const float* __restrict__ win, int32_t n, float pad)
+{
+    const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n_nodes) return;
+    const int4 r = ranges[i];
+    BvhNode rec = nodes[i];
+    for (int slot = 0; slot < 2; ++slot) {
+        const int32_t a = slot == 0 ? r.x : r.z, b = slot == 0 ? r.y : r.w;
+        if (b < a) continue;
+        const Box6 bx = range_box(win, n, a, b);
+        // widened, then one more ulp outward: the rounded sums can never cut into the box
+        const float lx = nextafterf(bx.lo[0] - pad, -FLT_MAX), hx = nextafterf(bx.hi[0] + pad, FLT_MAX);
+        const float ly = nextafterf(bx.lo[1] - pad, -FLT_MAX), hy = nextafterf(bx.hi[1] + pad, FLT_MAX);
+        const float lz = nextafterf(bx.lo[2] - pad, -FLT_MAX), hz = nextafterf(bx.hi[2] + pad, FLT_MAX);
+        if (slot == 0) {
+            rec.f[0] = make_float4(lx, hx, ly, hy);
+            rec.f[2].x = lz;
+            rec.f[2].y = hz;
+        } else {
+            rec.f[1] = make_float4(lx, hx, ly, hy);
+            rec.f[2].z = lz;
+            rec.f[2].w = hz;
+        }
+    }
+    nodes[i] = rec;
 }
 
 __global__ void k_fill_words(uint32_t* __restrict__ p, int64_t n, uint32_t v)
@@ -332,6 +377,34 @@ size_t lbvh_tmp_bytes(int32_t n)
     return std::max(sort, scan);
 }
 
+// Levels 1 .. levels - 1 of the window table over n boxes (level 0 filled).
+void launch_windows(float* win, int32_t n, int32_t levels, hipStream_t stream)
+{
+    const int threads = 256;
+    const unsigned bl = static_cast<unsigned>((n + threads - 1) / threads);
+    const int32_t fused = std::min<int32_t>(levels - 1, kWinFused);
+    if (fused > 0) hipLaunchKernelGGL(k_window_fused, dim3(bl), dim3(threads), 0, stream, win, n, fused);
+    for (int32_t k = fused + 1; k < levels; ++k) {
+        const int32_t half = 1 << (k - 1);
+        const int32_t count = n - (1 << k) + 1;
+        hipLaunchKernelGGL(k_window, dim3(static_cast<unsigned>((count + threads - 1) / threads)), dim3(threads), 0,
+                           stream, win + static_cast<int64_t>(k - 1) * n * 6, win + static_cast<int64_t>(k) * n * 6,
+                           count, half);
+    }
+}
+
+hipError_t launch_refit(const TriRec* tris, int32_t n, BvhNode* nodes, const int4* ranges, int32_t n_nodes, float* win,
+                        int32_t levels, float pad, hipStream_t stream)
+{
+    const int threads = 256;
+    hipLaunchKernelGGL(k_tri_boxes, dim3(static_cast<unsigned>((n + threads - 1) / threads)), dim3(threads), 0, stream,
+                       tris, n, win);
+    launch_windows(win, n, levels, stream);
+    hipLaunchKernelGGL(k_refit_nodes, dim3(static_cast<unsigned>((n_nodes + threads - 1) / threads)), dim3(threads), 0,
+                       stream, nodes, ranges, n_nodes, win, n, pad);
+    return hipGetLastError();
+}
+
 hipError_t launch_lbvh(const LbvhArgs& a, hipStream_t stream)
 {
     const int32_t n = a.n;
@@ -346,16 +419,7 @@ hipError_t launch_lbvh(const LbvhArgs& a, hipStream_t stream)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather, dim3(bl), dim3(threads), 0, stream, a.tris_in, a.mat_in, a.perm_in, a.order, n,
                        a.tris_out, a.mat_out, a.perm_out, a.bvh_pos_out, a.win);
-    const int32_t fused = std::min<int32_t>(a.levels - 1, kWinFused);
-    if (fused > 0)
-        hipLaunchKernelGGL(k_window_fused, dim3(bl), dim3(threads), 0, stream, a.win, n, fused);
-    for (int32_t k = fused + 1; k < a.levels; ++k) {
-        const int32_t half = 1 << (k - 1);
-        const int32_t count = n - (1 << k) + 1;
-        hipLaunchKernelGGL(k_window, dim3(static_cast<unsigned>((count + threads - 1) / threads)), dim3(threads), 0,
-                           stream, a.win + static_cast<int64_t>(k - 1) * n * 6, a.win + static_cast<int64_t>(k) * n * 6,
-                           count, half);
-    }
+    launch_windows(a.win, n, a.levels, stream);
     hipLaunchKernelGGL(k_karras, dim3(bl), dim3(threads), 0, stream, a.keys_sorted, n, a.child, a.range, a.parent,
                        a.leaf_parent);
     hipLaunchKernelGGL(k_frontier, dim3(bl), dim3(threads), 0, stream, a.range, a.parent, a.leaf_parent, n, a.start);
@@ -368,7 +432,7 @@ hipError_t launch_lbvh(const LbvhArgs& a, hipStream_t stream)
     hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(threads), 0, stream, reinterpret_cast<uint32_t*>(a.depth_out),
                        int64_t(1), 0u);
     hipLaunchKernelGGL(k_emit, dim3(bl), dim3(threads), 0, stream, n, a.child, a.range, a.parent, a.scan, a.win,
-                       a.pad, a.nodes_out, a.depth_out);
+                       a.pad, a.nodes_out, a.ranges_out, a.depth_out);
     return hipGetLastError();
 }
 

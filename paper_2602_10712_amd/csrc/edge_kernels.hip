@@ -1,0 +1,209 @@
+// Visibility-edge terms of the hinge-angle gradient by edge sampling, gfx950.
+//
+// Per sun direction the ray grid estimates F = (Phi/c) int g(y) dy over the grid plane, g(y) the
+// momentum a unit-weight path started at image point y deposits.  Turning a hinge moves the
+// images of the edges of the facets it carries, across which g jumps (silhouettes, edges between
+// facets, occlusion of one part by another).  Besides the pathwise part that k_adjoint computes
+// (every path at its image position with its facet sequence held), the derivative has, for every
+// moving edge, (Phi/c) int_edge (g(y - delta n) - g(y + delta n)) v_n dl: n the edge's unit
+// normal in the grid plane, v_n the normal image velocity of the edge point under the rotation.
+//
+// k_edge_term  one lane per (edge, sample): sample s = (m + xi)/M along moving edge e, the two side
+//              points y -+ delta n (delta = the secondary-ray offset, 1e-5 L) each start a full path
+//              with the same Philox draws (key seed ^ kEdgeKey, counter (e M + m, direction,
+//              bounce, design)), and the lane adds (Phi/c)(len/M) v_n (deposit(y-) - deposit(y+))
+//              contracted with the direction's cotangents to its hinge.  Paths are walked per lane
+//              (the two side points of neighbouring samples diverge after their first hit).
+// k_add_edges  per-direction sums of the workgroup partials, added in a fixed order to the
+//              per-direction hinge sums of the adjoint.
+#include <float.h>
+
+#include "srp_internal.h"
+#include "srp_path.h"
+#include "srp_traverse.h"
+
+namespace srp {
+namespace {
+
+constexpr uint64_t kEdgeKey = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ void cross3e(const float a[3], const float b[3], float r[3])
+{
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// One unit-weight path from o along d; its force and torque about com.
+template <bool LANE>
+__device__ __forceinline__ void edge_path(const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris,
+                                          const float4* __restrict__ mat, float o[3], float d[3], bool alive,
+                                          int bounces, uint32_t ctr0, uint32_t dir, uint32_t design, uint32_t key_lo,
+                                          uint32_t key_hi, float eps, const float com[3], int* stack, int* lstack,
+                                          float F[3], float T[3])
+{
+    float w = 1.0f;
+    int skip = -1;
+    for (int c = 0; c < 3; ++c) F[c] = T[c] = 0.0f;
+    for (int b = 1; b <= bounces; ++b) {
+        if (wave_ballot(alive) == 0) break;
+        float t;
+        int hit;
+        if (LANE)
+            closest_hit_lane(nodes, tris, o, d, alive, skip, t, hit, lstack);
+        else
+            closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
+        if (!alive) continue;
+        if (hit < 0) {
+            alive = false;
+            continue;
+        }
+        const TriRec tr = tris[hit];
+        const float4 mt = mat[hit];
+        const float n[3] = {tr.f[1].w, tr.f[2].w, tr.f[3].x};
+        float x[3], g[3];
+        alive = interact(o, d, w, t, n, mt.x, mt.y, mt.z, b, bounces, ctr0, dir, design, key_lo, key_hi, eps, x, g);
+        const float l[3] = {x[0] - com[0], x[1] - com[1], x[2] - com[2]};
+        float tq[3];
+        cross3e(l, g, tq);
+        for (int c = 0; c < 3; ++c) {
+            F[c] += g[c];
+            T[c] += tq[c];
+        }
+        skip = hit;
+    }
+}
+
+template <bool LANE>
+__global__ __launch_bounds__(256) void k_edge_term(EdgeArgs E, const BvhNode* __restrict__ nodes,
+                                                   const TriRec* __restrict__ tris, const float4* __restrict__ mat,
+                                                   const DevFrame* __restrict__ frames,
+                                                   const double* __restrict__ g_force,
+                                                   const double* __restrict__ g_torque,
+                                                   double* __restrict__ partials)
+{
+    __shared__ int s_stack[kWaves][kStackDepth];
+    __shared__ int s_lane[kWaves][kLaneStack][64];
+    __shared__ float s_red[kWaves][kMaxHinges];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t j = blockIdx.y;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n_samp = static_cast<int64_t>(E.n_edges) * E.samples;
+    const bool valid = idx < n_samp;
+    const int e = valid ? static_cast<int>(idx / E.samples) : 0;
+    const int m = valid ? static_cast<int>(idx % E.samples) : 0;
+    const DevFrame fr = frames[j];
+    const uint32_t dir = static_cast<uint32_t>(E.dir_index_base + j);
+    const int4 ed = E.edges[e];
+    const float4 p0v = E.verts[ed.x], p1v = E.verts[ed.y];
+    const float p0[3] = {p0v.x, p0v.y, p0v.z}, p1[3] = {p1v.x, p1v.y, p1v.z};
+    const int h = ed.z;
+    // grid-plane axes and pixel sizes of the frame
+    const float du = sqrtf(fr.U[0] * fr.U[0] + fr.U[1] * fr.U[1] + fr.U[2] * fr.U[2]);
+    const float dv = sqrtf(fr.V[0] * fr.V[0] + fr.V[1] * fr.V[1] + fr.V[2] * fr.V[2]);
+    const float u[3] = {fr.U[0] / du, fr.U[1] / du, fr.U[2] / du};
+    const float v[3] = {fr.V[0] / dv, fr.V[1] / dv, fr.V[2] / dv};
+    const float r0[3] = {p0[0] - fr.o0[0], p0[1] - fr.o0[1], p0[2] - fr.o0[2]};
+    const float r1[3] = {p1[0] - fr.o0[0], p1[1] - fr.o0[1], p1[2] - fr.o0[2]};
+    const float y0u = r0[0] * u[0] + r0[1] * u[1] + r0[2] * u[2];
+    const float y0v = r0[0] * v[0] + r0[1] * v[1] + r0[2] * v[2];
+    const float tu = (r1[0] * u[0] + r1[1] * u[1] + r1[2] * u[2]) - y0u;
+    const float tv = (r1[0] * v[0] + r1[1] * v[1] + r1[2] * v[2]) - y0v;
+    const float len = sqrtf(tu * tu + tv * tv);
+    const bool live = valid && len > 0.0f;  // an edge seen end-on sweeps no area
+    const float nu_ = live ? tv / len : 0.0f, nv_ = live ? -tu / len : 0.0f;
+    const uint32_t key_lo = E.seed_lo ^ static_cast<uint32_t>(kEdgeKey);
+    const uint32_t key_hi = E.seed_hi ^ static_cast<uint32_t>(kEdgeKey >> 32);
+    const uint32_t ctr0 = static_cast<uint32_t>(static_cast<int64_t>(e) * E.samples + m);
+    uint32_t c0 = ctr0, c1 = dir, c2 = 0u, c3 = E.design_index;
+    philox4x32_10(c0, c1, c2, c3, key_lo, key_hi);
+    const float sp = (static_cast<float>(m) + unit24(c0)) / static_cast<float>(E.samples);
+    // the edge point, its image, and its image velocity under the rotation about hinge h
+    float x[3], rx[3], xd[3];
+    for (int c = 0; c < 3; ++c) x[c] = p0[c] + sp * (p1[c] - p0[c]);
+    for (int c = 0; c < 3; ++c) rx[c] = x[c] - E.hinge_origin[h & 3][c];
+    cross3e(E.hinge_axis[h & 3], rx, xd);
+    const float vn = (xd[0] * u[0] + xd[1] * u[1] + xd[2] * u[2]) * nu_ +
+                     (xd[0] * v[0] + xd[1] * v[1] + xd[2] * v[2]) * nv_;
+    const float yu = y0u + sp * tu, yv = y0v + sp * tv;
+    float Fs[2][3], Ts[2][3];
+    int* stack = s_stack[wave];
+    int* lstack = &s_lane[wave][0][lane];
+    for (int side = 0; side < 2; ++side) {
+        const float sg = side == 0 ? -E.delta : E.delta;
+        const float au = yu + sg * nu_, av = yv + sg * nv_;
+        float o[3], d[3];
+        for (int c = 0; c < 3; ++c) {
+            o[c] = fr.o0[c] + au * u[c] + av * v[c];
+            d[c] = fr.d[c];
+        }
+        edge_path<LANE>(nodes, tris, mat, o, d, live, E.bounces, ctr0, dir, E.design_index, key_lo, key_hi, E.eps,
+                        E.com, stack, lstack, Fs[side], Ts[side]);
+    }
+    // contribution to dL/d theta_h, L = gF . F + gT . tau
+    const float flux_c = fr.w / (du * dv);
+    const float scale = live ? flux_c * len / static_cast<float>(E.samples) * vn : 0.0f;
+    float gF[3], gT[3] = {0.0f, 0.0f, 0.0f};
+    for (int c = 0; c < 3; ++c) gF[c] = static_cast<float>(g_force[3 * j + c]);
+    if (g_torque)
+        for (int c = 0; c < 3; ++c) gT[c] = static_cast<float>(g_torque[3 * j + c]);
+    float Lc = 0.0f;
+    for (int c = 0; c < 3; ++c) Lc += gF[c] * (Fs[0][c] - Fs[1][c]) + gT[c] * (Ts[0][c] - Ts[1][c]);
+    Lc *= scale;
+    float acc[kMaxHinges];
+#pragma unroll
+    for (int k = 0; k < kMaxHinges; ++k) acc[k] = wave_sum(h == k ? Lc : 0.0f);
+    if (lane == 0)
+        for (int k = 0; k < kMaxHinges; ++k) s_red[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < kMaxHinges) {
+        double s = 0.0;
+        for (int q = 0; q < kWaves; ++q) s += static_cast<double>(s_red[q][threadIdx.x]);
+        partials[(j * gridDim.x + blockIdx.x) * kMaxHinges + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_add_edges(const double* __restrict__ partials, int64_t D, int32_t blocks,
+                            double* __restrict__ per_dir)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= D * kMaxHinges) return;
+    const int64_t j = t / kMaxHinges;
+    const int k = static_cast<int>(t % kMaxHinges);
+    double s = 0.0;
+    for (int32_t b = 0; b < blocks; ++b) s += partials[(j * blocks + b) * kMaxHinges + k];
+    per_dir[t] += s;
+}
+
+}  // namespace
+
+int32_t edge_blocks(const EdgeArgs& E)
+{
+    const int64_t n = static_cast<int64_t>(E.n_edges) * E.samples;
+    return static_cast<int32_t>((n + 255) / 256);
+}
+
+hipError_t launch_edge_term(const EdgeArgs& E, const BvhNode* nodes, const TriRec* tris, const float4* mat,
+                            const DevFrame* frames, const double* g_force, const double* g_torque, int lane_walk,
+                            double* partials, double* per_dir, hipStream_t stream)
+{
+    const int32_t nb = edge_blocks(E);
+    if (E.D <= 0 || nb <= 0) return hipSuccess;
+    if (E.D > 65535) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(nb), static_cast<unsigned>(E.D));
+    if (lane_walk)
+        hipLaunchKernelGGL((k_edge_term<true>), grid, dim3(64 * kWaves), 0, stream, E, nodes, tris, mat, frames, g_force,
+                           g_torque, partials);
+    else
+        hipLaunchKernelGGL((k_edge_term<false>), grid, dim3(64 * kWaves), 0, stream, E, nodes, tris, mat, frames,
+                           g_force, g_torque, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nt = E.D * kMaxHinges;
+    hipLaunchKernelGGL(k_add_edges, dim3(static_cast<unsigned>((nt + 255) / 256)), dim3(256), 0, stream, partials, E.D,
+                       nb, per_dir);
+    return hipGetLastError();
+}
+
+}  // namespace srp

@@ -59,18 +59,26 @@ struct srp_mlp_s {
     int64_t* d_wf_off = nullptr;  // device copies of wf_off and b_off
     int64_t* d_b_off = nullptr;
     // workspaces
-    size_t cap_xb = 0, cap_Z = 0, cap_A = 0, cap_G = 0, cap_Gb = 0, cap_col = 0, cap_lp = 0;
+    size_t cap_xb = 0, cap_Z = 0, cap_A = 0, cap_G = 0, cap_Gb = 0, cap_lp = 0;
     uint16_t* d_xb = nullptr;
     float* d_Z = nullptr;
     uint16_t* d_A = nullptr;
     float* d_G = nullptr;
     uint16_t* d_Gb = nullptr;  // two halves, ping-pong
-    float* d_col = nullptr;
     double* d_lpart = nullptr;
     int64_t cached_N = -1;
     // workspace of callers that use the network as a model (attitude integration)
     char* d_aux = nullptr;
     size_t cap_aux = 0;
+    // ensemble workspace (this network as member a): both outputs, flags, compaction scratch
+    char* d_ens = nullptr;
+    size_t cap_ens = 0;
+    // split-batch weight-gradient partials [splits][fout][fin] and bias partials per layer
+    float* d_wpart = nullptr;
+    size_t cap_wpart = 0;
+    float* d_bpart = nullptr;
+    size_t cap_bpart = 0;
+    bool wf_stale = false;  // the fused kernel's weight pieces lag the masters (refreshed before use)
 };
 
 namespace {
@@ -83,16 +91,36 @@ srp_status bind(const srp_mlp_s* m)
     return SRP_OK;
 }
 
+// The fused inference kernel's weight pieces, rebuilt from the masters when they changed.
+srp_status refresh_fused(srp_mlp_s* m, hipStream_t stream)
+{
+    if (!m->fused || !m->wf_stale) return SRP_OK;
+    for (int l = 0; l <= m->depth; ++l)
+        MLP_HIP(srp::launch_pack_mfma(m->d_p + m->w_off[l], m->fout[l], m->fin[l], l, m->depth, m->d_wf + m->wf_off[l],
+                                      stream));
+    m->wf_stale = false;
+    return SRP_OK;
+}
+
 srp_status repack(srp_mlp_s* m, hipStream_t stream)
 {
-    for (int l = 0; l <= m->depth; ++l) {
+    for (int l = 0; l <= m->depth; ++l)
         MLP_HIP(srp::launch_pack(m->d_p + m->w_off[l], m->fout[l], m->fin[l], m->d_wb + m->wb_off[l], m->fout_pad[l],
                                  m->fin_pad[l], stream));
-        if (m->fused)
-            MLP_HIP(srp::launch_pack_mfma(m->d_p + m->w_off[l], m->fout[l], m->fin[l], l, m->depth,
-                                          m->d_wf + m->wf_off[l], stream));
-    }
-    return SRP_OK;
+    m->wf_stale = true;
+    return refresh_fused(m, stream);
+}
+
+// Batch splits of a layer's weight gradient: enough workgroups to fill the chip (about 256 tiles x
+// splits), at least 32 rows per split.  Returns the split count; *kc receives rows per split.
+int wgrad_splits(int fout, int fin, int64_t K, int* kc)
+{
+    const int tiles = ((fout + 63) / 64) * ((fin + 63) / 64);
+    const int64_t want = std::max<int64_t>(1, 256 / tiles);
+    int64_t c = (K + want - 1) / want;
+    c = std::max<int64_t>(32, (c + 31) / 32 * 32);
+    *kc = static_cast<int>(c);
+    return static_cast<int>((K + c - 1) / c);
 }
 
 srp_status ensure_ws(srp_mlp_s* m, int64_t N, bool training)
@@ -105,7 +133,6 @@ srp_status ensure_ws(srp_mlp_s* m, int64_t N, bool training)
         MLP_HIP(grow(m->d_Z, m->cap_Z, static_cast<size_t>(m->depth * N * m->width)));
         MLP_HIP(grow(m->d_G, m->cap_G, static_cast<size_t>(N * wmax)));
         MLP_HIP(grow(m->d_Gb, m->cap_Gb, static_cast<size_t>(2 * N * wmax)));
-        MLP_HIP(grow(m->d_col, m->cap_col, static_cast<size_t>(64 * wmax)));
     } else if (m->depth > 1) {
         // inference without cache: two activation buffers (ping-pong)
         MLP_HIP(grow(m->d_A, m->cap_A, static_cast<size_t>(2 * N * m->width)));
@@ -216,6 +243,8 @@ srp_status srp_mlp_forward(srp_mlp m, const float* x, int64_t N, float* y, int32
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     const bool training = keep_activations != 0;
     if (!training && m->fused) {
+        st = refresh_fused(m, stream);
+        if (st != SRP_OK) return st;
         MLP_HIP(srp::launch_mlp_infer(x, static_cast<int32_t>(N), m->d_wf, m->d_wf_off, m->d_p, m->d_b_off, m->n_in,
                                       m->depth, m->n_out, y, stream));
         m->cached_N = -1;
@@ -265,6 +294,40 @@ srp_status srp_mlp_forward(srp_mlp m, const float* x, int64_t N, float* y, int32
     return SRP_OK;
 }
 
+srp_status srp_mlp_ensemble(srp_mlp a, srp_mlp b, const float* x, int64_t N, float threshold, float out_scale,
+                            float* y, float* disagree, int32_t* fail_idx, int32_t* n_fail, void* stream_)
+{
+    if (!a || !b) return srp_fail(SRP_EINVAL, "both networks are required");
+    if (a->n_in != b->n_in || a->n_out != b->n_out || a->device != b->device)
+        return srp_fail(SRP_EINVAL, "the two networks must have the same inputs, outputs and device");
+    if (a->n_in < 3) return srp_fail(SRP_EINVAL, "the inputs must start with the sun unit vector (n_in >= 3)");
+    if (N < 0 || N > (int64_t(1) << 30)) return srp_fail(SRP_EINVAL, "N must be in 0..2^30");
+    if (!n_fail) return srp_fail(SRP_EINVAL, "n_fail is required");
+    if (N > 0 && (!x || !y || !fail_idx)) return srp_fail(SRP_EINVAL, "x, y and fail_idx are required");
+    srp_status st = bind(a);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if (N == 0) {
+        MLP_HIP(hipMemsetAsync(n_fail, 0, sizeof(int32_t), stream));
+        return SRP_OK;
+    }
+    const size_t out_bytes = (static_cast<size_t>(N) * a->n_out * sizeof(float) + 255) / 256 * 256;
+    const size_t flag_bytes = (static_cast<size_t>(N) + 255) / 256 * 256;
+    const size_t tmp_bytes = srp::ensemble_select_bytes(N);
+    MLP_HIP(grow(a->d_ens, a->cap_ens, 2 * out_bytes + flag_bytes + tmp_bytes));
+    float* ya = reinterpret_cast<float*>(a->d_ens);
+    float* yb = reinterpret_cast<float*>(a->d_ens + out_bytes);
+    uint8_t* flag = reinterpret_cast<uint8_t*>(a->d_ens + 2 * out_bytes);
+    void* tmp = a->d_ens + 2 * out_bytes + flag_bytes;
+    st = srp_mlp_forward(a, x, N, ya, 0, stream_);
+    if (st != SRP_OK) return st;
+    st = srp_mlp_forward(b, x, N, yb, 0, stream_);
+    if (st != SRP_OK) return st;
+    MLP_HIP(srp::launch_ensemble(x, a->n_in, ya, yb, a->n_out, N, threshold, out_scale, y, disagree, flag, tmp,
+                                 tmp_bytes, fail_idx, n_fail, stream));
+    return SRP_OK;
+}
+
 srp_status srp_mlp_backward(srp_mlp m, const float* g_y, int64_t N, float* g_x, void* stream_)
 {
     if (!m || !g_y) return srp_fail(SRP_EINVAL, "mlp and g_y are required");
@@ -276,26 +339,52 @@ srp_status srp_mlp_backward(srp_mlp m, const float* g_y, int64_t N, float* g_x, 
     const int64_t wmax = std::max(m->width, round8(m->n_out));
     uint16_t* gb[2] = {m->d_Gb, m->d_Gb + N * wmax};
     int cur = 0;
-    // output layer: dL/dz = g_y (FP32); its bias gradient and BF16 copy
-    MLP_HIP(srp::launch_colsum(g_y, N, m->n_out, m->n_out, m->d_col, m->d_g + m->b_off[m->depth], stream));
+    // split-batch partials of every layer's weight and bias gradients, summed at the end
+    srp::ReduceArgs red{};
+    red.layers = m->depth + 1;
+    int64_t part_total = 0, bpart_total = 0, total = 0;
+    int kc[srp::kMaxLayers];
+    for (int l = 0; l <= m->depth; ++l) {
+        const int S = wgrad_splits(m->fout[l], m->fin[l], N, &kc[l]);
+        red.first[l] = total;
+        red.fin[l] = m->fin[l];
+        red.fout[l] = m->fout[l];
+        red.splits[l] = S;
+        red.w_off[l] = m->w_off[l];
+        red.b_off[l] = m->b_off[l];
+        red.part_off[l] = part_total;
+        red.bpart_off[l] = bpart_total;
+        part_total += static_cast<int64_t>(S) * m->fout[l] * m->fin[l];
+        bpart_total += static_cast<int64_t>(S) * m->fout[l];
+        total += static_cast<int64_t>(m->fout[l]) * m->fin[l] + m->fout[l];
+    }
+    red.total = total;
+    MLP_HIP(grow(m->d_wpart, m->cap_wpart, static_cast<size_t>(part_total)));
+    MLP_HIP(grow(m->d_bpart, m->cap_bpart, static_cast<size_t>(bpart_total)));
+    red.part = m->d_wpart;
+    red.bpart = m->d_bpart;
+    red.grad = m->d_g;
+    // output layer: dL/dz = g_y (FP32) and its BF16 copy
     MLP_HIP(srp::launch_to_bf16(g_y, N, m->n_out, m->n_out, gb[cur], m->fout_pad[m->depth], stream));
     for (int l = m->depth; l >= 0; --l) {
         const uint16_t* in = l == 0 ? m->d_xb : m->d_A + static_cast<int64_t>(l - 1) * N * m->width;
         const int in_ld = l == 0 ? m->fin_pad[0] : m->width;
         const int g_ld = m->fout_pad[l];
-        // weight gradient: dW_l[o][i] += sum_n dL/dz[n][o] a_{l-1}[n][i]
-        srp::GemmArgs w{};
-        w.A = gb[cur];
-        w.lda = g_ld;
-        w.B = in;
-        w.ldb = in_ld;
+        // weight gradient dW_l[o][i] = sum_n dL/dz[n][o] a_{l-1}[n][i] and bias gradient sum_n dL/dz[n][o]
+        srp::WgradArgs w{};
+        w.G = gb[cur];
+        w.ldg = g_ld;
+        w.A = in;
+        w.lda = in_ld;
+        w.Gf = l == m->depth ? g_y : m->d_G;
+        w.ldgf = l == m->depth ? m->n_out : m->width;
         w.M = m->fout[l];
         w.N = m->fin[l];
         w.K = N32;
-        w.epi = srp::kEpiAccumulate;
-        w.C = m->d_g + m->w_off[l];
-        w.ldc = m->fin[l];
-        MLP_HIP(srp::launch_gemm(w, true, false, stream));
+        w.kc = kc[l];
+        w.part = m->d_wpart + red.part_off[l];
+        w.bpart = m->d_bpart + red.bpart_off[l];
+        MLP_HIP(srp::launch_wgrad(w, red.splits[l], stream));
         if (l == 0 && !g_x) break;
         // input gradient of the layer: dL/da_{l-1} = dL/dz_l . W_l, times SiLU'(z_{l-1}) below layer 0
         srp::GemmArgs d{};
@@ -315,7 +404,6 @@ srp_status srp_mlp_backward(srp_mlp m, const float* g_y, int64_t N, float* g_x, 
             d.Cb = gb[cur ^ 1];
             d.ldcb = m->width;
             MLP_HIP(srp::launch_gemm(d, false, false, stream));
-            MLP_HIP(srp::launch_colsum(m->d_G, N, m->width, m->width, m->d_col, m->d_g + m->b_off[l - 1], stream));
             cur ^= 1;
         } else {
             d.N = m->n_in;
@@ -325,6 +413,7 @@ srp_status srp_mlp_backward(srp_mlp m, const float* g_y, int64_t N, float* g_x, 
             MLP_HIP(srp::launch_gemm(d, false, false, stream));
         }
     }
+    MLP_HIP(srp::launch_wgrad_reduce(red, stream));
     return SRP_OK;
 }
 
@@ -337,11 +426,30 @@ srp_status srp_mlp_adam_step(srp_mlp m, float lr, float b1, float b2, float eps,
     if (st != SRP_OK) return st;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     m->step += 1;
-    const float c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(b1), static_cast<double>(m->step)));
-    const float c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(b2), static_cast<double>(m->step)));
-    MLP_HIP(srp::launch_adam(m->d_p, m->d_g, m->d_m, m->d_v, m->P, lr, b1, b2, eps, c1, c2, stream));
-    MLP_HIP(srp::launch_fill_f32(m->d_g, m->P, 0.0f, stream));
-    return repack(m, stream);
+    srp::AdamPackArgs a{};
+    a.p = m->d_p;
+    a.g = m->d_g;
+    a.m = m->d_m;
+    a.v = m->d_v;
+    a.P = m->P;
+    a.lr = lr;
+    a.b1 = b1;
+    a.b2 = b2;
+    a.eps = eps;
+    a.c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(b1), static_cast<double>(m->step)));
+    a.c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(b2), static_cast<double>(m->step)));
+    a.layers = m->depth + 1;
+    for (int l = 0; l <= m->depth; ++l) {
+        a.w_off[l] = m->w_off[l];
+        a.wb_off[l] = m->wb_off[l];
+        a.fin[l] = m->fin[l];
+        a.fout[l] = m->fout[l];
+        a.fin_pad[l] = m->fin_pad[l];
+    }
+    a.wb = m->d_wb;
+    MLP_HIP(srp::launch_adam_pack(a, stream));
+    m->wf_stale = true;
+    return SRP_OK;
 }
 
 srp_status srp_mlp_zero_grad(srp_mlp m, void* stream)
@@ -432,9 +540,10 @@ srp_status srp_mlp_destroy(srp_mlp m)
     for (void* p : {static_cast<void*>(m->d_p), static_cast<void*>(m->d_g), static_cast<void*>(m->d_m),
                     static_cast<void*>(m->d_v), static_cast<void*>(m->d_wb), static_cast<void*>(m->d_xb),
                     static_cast<void*>(m->d_Z), static_cast<void*>(m->d_A), static_cast<void*>(m->d_G),
-                    static_cast<void*>(m->d_Gb), static_cast<void*>(m->d_col), static_cast<void*>(m->d_lpart),
+                    static_cast<void*>(m->d_Gb), static_cast<void*>(m->d_lpart),
                     static_cast<void*>(m->d_wf), static_cast<void*>(m->d_wf_off), static_cast<void*>(m->d_b_off),
-                    static_cast<void*>(m->d_aux)})
+                    static_cast<void*>(m->d_aux), static_cast<void*>(m->d_ens), static_cast<void*>(m->d_wpart),
+                    static_cast<void*>(m->d_bpart)})
         if (p) (void)hipFree(p);
     delete m;
     return SRP_OK;

@@ -33,11 +33,51 @@ struct GemmArgs {
 };
 
 hipError_t launch_gemm(const GemmArgs& g, bool trans_a, bool trans_b, hipStream_t stream);
-hipError_t launch_colsum(const float* G, int64_t rows, int cols, int ldg, float* part, float* out, hipStream_t stream);
+
+// Split-batch weight gradient of one layer (see k_wgrad): G [K][ldg] and A [K][lda] BF16, Gf the
+// FP32 gradient [K][ldgf] for the bias partials (null: none); part [splits][M][N], bpart
+// [splits][M]; kc rows per split.
+struct WgradArgs {
+    const uint16_t* G;
+    const uint16_t* A;
+    const float* Gf;
+    int32_t M, N, K, kc;
+    int32_t ldg, lda, ldgf;
+    float* part;
+    float* bpart;
+};
+hipError_t launch_wgrad(const WgradArgs& g, int splits, hipStream_t stream);
+
+constexpr int kMaxLayers = 17;
+// Fixed-order sum of the split partials of every layer into the gradient buffer.
+struct ReduceArgs {
+    int32_t layers;
+    int64_t total;                 // sum over layers of fout * fin + fout
+    int64_t first[kMaxLayers];     // running start of each layer in that enumeration
+    int32_t fin[kMaxLayers], fout[kMaxLayers], splits[kMaxLayers];
+    int64_t w_off[kMaxLayers], b_off[kMaxLayers], part_off[kMaxLayers], bpart_off[kMaxLayers];
+    const float* part;
+    const float* bpart;
+    float* grad;
+};
+hipError_t launch_wgrad_reduce(const ReduceArgs& r, hipStream_t stream);
+
+// Adam step on all P parameters, gradient cleared, BF16 row-major packs rewritten.
+struct AdamPackArgs {
+    float* p;
+    float* g;
+    float* m;
+    float* v;
+    int64_t P;
+    float lr, b1, b2, eps, c1, c2;
+    int32_t layers;
+    int64_t w_off[kMaxLayers], wb_off[kMaxLayers];
+    int32_t fin[kMaxLayers], fout[kMaxLayers], fin_pad[kMaxLayers];
+    uint16_t* wb;
+};
+hipError_t launch_adam_pack(const AdamPackArgs& a, hipStream_t stream);
 hipError_t launch_to_bf16(const float* in, int64_t rows, int cols, int ld_in, uint16_t* out, int ld_out,
                           hipStream_t stream);
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
-                       float c1, float c2, hipStream_t stream);
 hipError_t launch_pack(const float* W, int out, int in, uint16_t* Wb, int out_pad, int in_pad, hipStream_t stream);
 hipError_t launch_mse(const float* y, const float* t, int64_t count, float* gy, double* partial, double* loss,
                       hipStream_t stream);
@@ -51,6 +91,13 @@ hipError_t launch_pack_mfma(const float* W, int out, int in, int layer, int dept
 hipError_t launch_mlp_infer(const float* x, int32_t N, const uint16_t* wf, const int64_t* wf_off_dev,
                             const float* params, const int64_t* b_off_dev, int n_in, int depth, int n_out, float* y,
                             hipStream_t stream);
+
+// Ensemble confidence test (ensemble.hip): mean, disagreement and failure flags of two networks'
+// outputs, then the failing query indices compacted in ascending order.
+size_t ensemble_select_bytes(int64_t N);
+hipError_t launch_ensemble(const float* x, int n_in, const float* ya, const float* yb, int n_out, int64_t N,
+                           float threshold, float scale, float* y, float* dis, uint8_t* flag, void* tmp,
+                           size_t tmp_bytes, int32_t* fail_idx, int32_t* n_fail, hipStream_t stream);
 
 // The network as a model inside other integrators: its shape and a workspace it owns (grown on
 // demand, freed with the network; calls using one network must be ordered).

@@ -9,8 +9,11 @@
 //             tile each), K staged through LDS 32 at a time, with the epilogue of the layer fused:
 //             bias + SiLU (hidden forward), bias (output), x SiLU'(z) (back-propagation), += (weight
 //             gradients over the batch).
-// k_colsum_*  bias gradients (column sums over the batch, fixed order)
-// k_adam      Adam with bias correction on the FP32 master weights
+// k_wgrad     weight gradient of one layer split over the batch (64 x 64 tiles x batch chunks, each
+//             chunk's tile stored on its own), with the bias partials (FP32 column sums) of the chunk
+// k_wgrad_reduce  the chunks of every layer added to the gradient buffer in a fixed order
+// k_adam_pack Adam with bias correction on the FP32 master weights, gradient cleared, BF16 copies
+//             of the weights rewritten in the row-major padded packs
 // k_pack      FP32 master -> BF16 weights (row-major, zero-padded input and output widths)
 // k_mse       loss and dL/dy of the mean squared error
 #include <hip/hip_runtime.h>
@@ -24,7 +27,9 @@ namespace {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
-constexpr int kTM = 64, kTN = 64, kTK = 32, kLdsK = kTK + 8;
+// 64 x 64 output tiles; K staged through LDS 128 at a time (every load of a chunk issued before
+// the one barrier that precedes its products, so a chunk costs one memory latency)
+constexpr int kTM = 64, kTN = 64, kTK = 128, kLdsK = kTK + 8;
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -55,6 +60,73 @@ __device__ __forceinline__ void load8(const uint16_t* __restrict__ p, int valid,
     }
 }
 
+// Rows [r0, r0 + 64) x k in [k0, k1) of a BF16 operand, loaded into registers (zeros outside
+// [0, rows) x [k0, k1)) and then stored to lds[row][k - k0]: the two halves are separate so that
+// the next chunk's loads are in flight during this chunk's products.  KMAJOR = false: the operand
+// is stored [row][ld] (k contiguous); KMAJOR = true: stored [k][ld] (rows contiguous), scattered
+// into the k-contiguous LDS layout.
+template <bool KMAJOR>
+__device__ __forceinline__ void load_tile(const uint16_t* __restrict__ src, int ld, int rows, int r0, int k0, int k1,
+                                          uint16_t (&v)[4][8])
+{
+    const int tid = threadIdx.x;
+    const bool vec = (ld % 8) == 0;
+    if (!KMAJOR) {
+        // 16 threads per row, 8 k each: 16 rows per pass, 4 passes
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int row = p * 16 + (tid >> 4), kc = (tid & 15) * 8;
+            const int r = r0 + row, k = k0 + kc;
+            const int valid = (r < rows && k < k1) ? min(8, k1 - k) : 0;
+            load8(src + static_cast<int64_t>(r < rows ? r : 0) * ld + (k < k1 ? k : k0), valid, vec, v[p]);
+        }
+    } else {
+        // 8 threads per k, 8 rows each: 32 k per pass, 4 passes
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int kk = p * 32 + (tid >> 3), rc = (tid & 7) * 8;
+            const int k = k0 + kk, r = r0 + rc;
+            const int valid = (k < k1 && r < rows) ? min(8, rows - r) : 0;
+            load8(src + static_cast<int64_t>(k < k1 ? k : k0) * ld + (r < rows ? r : 0), valid, vec, v[p]);
+        }
+    }
+}
+
+template <bool KMAJOR>
+__device__ __forceinline__ void store_tile(const uint16_t (&v)[4][8], uint16_t (*lds)[kLdsK])
+{
+    const int tid = threadIdx.x;
+    if (!KMAJOR) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int row = p * 16 + (tid >> 4), kc = (tid & 15) * 8;
+            *reinterpret_cast<uint4*>(&lds[row][kc]) = *reinterpret_cast<const uint4*>(v[p]);
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int kk = p * 32 + (tid >> 3), rc = (tid & 7) * 8;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) lds[rc + i][kk] = v[p][i];
+        }
+    }
+}
+
+// The products of one staged chunk: wave (wm, wn) accumulates its 32 x 32 block over the chunk.
+__device__ __forceinline__ void mfma_chunk(const uint16_t (*As)[kLdsK], const uint16_t (*Bs)[kLdsK], int wm, int wn,
+                                           int lane, f32x16& acc)
+{
+#pragma unroll
+    for (int ks = 0; ks < kTK; ks += 16) {
+        // operand layouts of v_mfma_f32_32x32x16_bf16: lane l holds A[l%32][8(l/32)+j] and
+        // B[8(l/32)+j][l%32], j = 0..7
+        const int kq = ks + 8 * (lane >> 5);
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][kq]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + (lane & 31)][kq]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+}
+
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
@@ -65,107 +137,187 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
     const int wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
-    const bool vecA = (g.lda % 8) == 0, vecB = (g.ldb % 8) == 0;
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
+    uint16_t va[4][8], vb[4][8];
+    load_tile<TA>(g.A, g.lda, g.M, m0, 0, min(g.K, kTK), va);   // A [m][k], or stored [k][m] when transposed
+    load_tile<!TB>(g.B, g.ldb, g.N, n0, 0, min(g.K, kTK), vb);  // B stored [n][k] when transposed, else [k][n]
     for (int k0 = 0; k0 < g.K; k0 += kTK) {
-        uint16_t v[8];
-        if (!TA) {  // A[m][k], contiguous in k
-            const int row = tid >> 2, kc = (tid & 3) * 8;
-            const int m = m0 + row, k = k0 + kc;
-            const int valid = (m < g.M) ? min(8, g.K - k) : 0;
-            load8(g.A + static_cast<int64_t>(m < g.M ? m : 0) * g.lda + (k < g.K ? k : 0), valid, vecA, v);
-            *reinterpret_cast<uint4*>(&As[row][kc]) = *reinterpret_cast<const uint4*>(v);
-        } else {  // A stored [k][m]: 8 consecutive m of one k, scattered into As
-            const int kk = tid >> 3, mc = (tid & 7) * 8;
-            const int k = k0 + kk, m = m0 + mc;
-            const int valid = (k < g.K) ? min(8, g.M - m) : 0;
-            load8(g.A + static_cast<int64_t>(k < g.K ? k : 0) * g.lda + (m < g.M ? m : 0), valid, vecA, v);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) As[mc + i][kk] = v[i];
-        }
-        if (TB) {  // B stored [n][k], contiguous in k
-            const int row = tid >> 2, kc = (tid & 3) * 8;
-            const int n = n0 + row, k = k0 + kc;
-            const int valid = (n < g.N) ? min(8, g.K - k) : 0;
-            load8(g.B + static_cast<int64_t>(n < g.N ? n : 0) * g.ldb + (k < g.K ? k : 0), valid, vecB, v);
-            *reinterpret_cast<uint4*>(&Bs[row][kc]) = *reinterpret_cast<const uint4*>(v);
-        } else {  // B stored [k][n]: 8 consecutive n of one k
-            const int kk = tid >> 3, nc = (tid & 7) * 8;
-            const int k = k0 + kk, n = n0 + nc;
-            const int valid = (k < g.K) ? min(8, g.N - n) : 0;
-            load8(g.B + static_cast<int64_t>(k < g.K ? k : 0) * g.ldb + (n < g.N ? n : 0), valid, vecB, v);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) Bs[nc + i][kk] = v[i];
-        }
+        store_tile<TA>(va, As);
+        store_tile<!TB>(vb, Bs);
         __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < kTK; ks += 16) {
-            // operand layouts of v_mfma_f32_32x32x16_bf16: lane l holds A[l%32][8(l/32)+j] and
-            // B[8(l/32)+j][l%32], j = 0..7
-            const int kq = ks + 8 * (lane >> 5);
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][kq]);
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + (lane & 31)][kq]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        const int k2 = k0 + kTK;
+        if (k2 < g.K) {
+            load_tile<TA>(g.A, g.lda, g.M, m0, k2, min(g.K, k2 + kTK), va);
+            load_tile<!TB>(g.B, g.ldb, g.N, n0, k2, min(g.K, k2 + kTK), vb);
         }
+        mfma_chunk(As, Bs, wm, wn, lane, acc);
         __syncthreads();
     }
 
-    // D layout: lane l, register r -> row (r/4)*8 + (l/32)*4 + r%4, column l%32
+    // D layout: lane l, register r -> row (r/4)*8 + (l/32)*4 + r%4, column l%32.  Every load the
+    // epilogue needs is issued before its first store (the stores could alias them otherwise, which
+    // would serialise sixteen memory round trips).
     const int n = n0 + wn * 32 + (lane & 31);
     if (n >= g.N) return;
+    const int mb = m0 + wm * 32 + (lane >> 5) * 4;
+    const float bn = g.bias ? g.bias[n] : 0.0f;
+    if (g.epi == kEpiBackprop) {
+        float zv[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int m = m0 + wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        if (m >= g.M) continue;
-        float x = acc[r];
-        switch (g.epi) {
-            case kEpiStore:
-                if (g.bias) x += g.bias[n];
-                g.C[static_cast<int64_t>(m) * g.ldc + n] = x;
-                break;
-            case kEpiHidden: {
-                const float z = x + g.bias[n];
+        for (int r = 0; r < 16; ++r) {
+            const int m = mb + (r >> 2) * 8 + (r & 3);
+            zv[r] = m < g.M ? g.Z[static_cast<int64_t>(m) * g.ldz + n] : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = mb + (r >> 2) * 8 + (r & 3);
+            if (m >= g.M) continue;
+            const float gz = acc[r] * silu_grad_f(zv[r]);
+            if (g.C) g.C[static_cast<int64_t>(m) * g.ldc + n] = gz;
+            g.Cb[static_cast<int64_t>(m) * g.ldcb + n] = f2bf(gz);
+        }
+    } else if (g.epi == kEpiAccumulate) {
+        float cv[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = mb + (r >> 2) * 8 + (r & 3);
+            cv[r] = m < g.M ? g.C[static_cast<int64_t>(m) * g.ldc + n] : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = mb + (r >> 2) * 8 + (r & 3);
+            if (m < g.M) g.C[static_cast<int64_t>(m) * g.ldc + n] = cv[r] + acc[r];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = mb + (r >> 2) * 8 + (r & 3);
+            if (m >= g.M) continue;
+            const float z = g.bias ? acc[r] + bn : acc[r];
+            if (g.epi == kEpiStore) {
+                g.C[static_cast<int64_t>(m) * g.ldc + n] = z;
+            } else {  // kEpiHidden
                 if (g.C) g.C[static_cast<int64_t>(m) * g.ldc + n] = z;
                 g.Cb[static_cast<int64_t>(m) * g.ldcb + n] = f2bf(silu_f(z));
-                break;
             }
-            case kEpiBackprop: {
-                const float gz = x * silu_grad_f(g.Z[static_cast<int64_t>(m) * g.ldz + n]);
-                if (g.C) g.C[static_cast<int64_t>(m) * g.ldc + n] = gz;
-                g.Cb[static_cast<int64_t>(m) * g.ldcb + n] = f2bf(gz);
-                break;
-            }
-            default:  // kEpiAccumulate
-                g.C[static_cast<int64_t>(m) * g.ldc + n] += x;
-                break;
         }
     }
 }
 
-// bias gradients: out[c] += sum_r G[r][c] (FP32) in two fixed-order passes: chunk sums, then the
-// sum of the chunk sums
-constexpr int kColChunks = 64;
-__global__ void k_colsum_part(const float* __restrict__ G, int64_t rows, int cols, int ldg, float* __restrict__ part)
+// Weight gradient of one layer, split over the batch: dW[m][n] = sum_k G[k][m] A[k][n] with G the
+// BF16 back-propagated gradient [K][ldg] and A the layer's BF16 input [K][lda]; workgroup (x, y, z)
+// computes the 64 x 64 tile (y, x) over batch rows [z kc, (z + 1) kc) and stores it to
+// part[z][M][N] (no atomics: the chunks are added in a fixed order by k_wgrad_reduce).  Workgroups of
+// tile column 0 also sum the FP32 gradient Gf [K][ldgf] over their rows: the bias partial
+// bpart[z][M].
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs g)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    const int64_t per = (rows + kColChunks - 1) / kColChunks;
-    const int64_t r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
-    float s = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) s += G[r * ldg + c];
-    part[static_cast<int64_t>(blockIdx.y) * cols + c] = s;
+    __shared__ __attribute__((aligned(16))) uint16_t As[kTM][kLdsK];  // [m][k]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTN][kLdsK];  // [n][k]
+    __shared__ float bsum[4][kTM];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+    const int kbeg = blockIdx.z * g.kc;
+    const int kend = min(g.K, kbeg + g.kc);
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+
+    uint16_t va[4][8], vb[4][8];
+    if (kbeg < kend) {
+        load_tile<true>(g.G, g.ldg, g.M, m0, kbeg, min(kend, kbeg + kTK), va);  // G stored [k][m]
+        load_tile<true>(g.A, g.lda, g.N, n0, kbeg, min(kend, kbeg + kTK), vb);  // A stored [k][n]
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += kTK) {
+        store_tile<true>(va, As);
+        store_tile<true>(vb, Bs);
+        __syncthreads();
+        const int k2 = k0 + kTK;
+        if (k2 < kend) {
+            load_tile<true>(g.G, g.ldg, g.M, m0, k2, min(kend, k2 + kTK), va);
+            load_tile<true>(g.A, g.lda, g.N, n0, k2, min(kend, k2 + kTK), vb);
+        }
+        mfma_chunk(As, Bs, wm, wn, lane, acc);
+        __syncthreads();
+    }
+    float* out = g.part + static_cast<int64_t>(blockIdx.z) * g.M * g.N;
+    const int n = n0 + wn * 32 + (lane & 31);
+    if (n < g.N) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = m0 + wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+            if (m < g.M) out[static_cast<int64_t>(m) * g.N + n] = acc[r];
+        }
+    }
+    if (blockIdx.x == 0 && g.Gf) {
+        // bias partial: column m of the FP32 gradient over this workgroup's rows, in 4 interleaved
+        // row groups, then the 4 group sums in order
+        const int mm = tid & 63, grp = tid >> 6;
+        const int m = m0 + mm;
+        float s = 0.0f;
+        if (m < g.M)
+#pragma unroll 8
+            for (int k = kbeg + grp; k < kend; k += 4) s += g.Gf[static_cast<int64_t>(k) * g.ldgf + m];
+        bsum[grp][mm] = s;
+        __syncthreads();
+        if (grp == 0 && m < g.M)
+            g.bpart[static_cast<int64_t>(blockIdx.z) * g.M + m] = ((bsum[0][mm] + bsum[1][mm]) + bsum[2][mm]) + bsum[3][mm];
+    }
 }
 
-__global__ void k_colsum_final(const float* __restrict__ part, int cols, float* __restrict__ out)
+// grad[w_off + i] += sum_z part[z][i] and grad[b_off + m] += sum_z bpart[z][m] for every layer, the
+// chunks in order (deterministic)
+__global__ void k_wgrad_reduce(ReduceArgs r)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    float s = 0.0f;
-    for (int q = 0; q < kColChunks; ++q) s += part[static_cast<int64_t>(q) * cols + c];
-    out[c] += s;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= r.total) return;
+    int l = 0;
+    while (l + 1 < r.layers && i >= r.first[l + 1]) ++l;
+    const int64_t j = i - r.first[l];
+    const int64_t nw = static_cast<int64_t>(r.fout[l]) * r.fin[l];
+    const int S = r.splits[l];
+    if (j < nw) {
+        const float* p = r.part + r.part_off[l] + j;
+        float s = 0.0f;
+        for (int z = 0; z < S; ++z) s += p[static_cast<int64_t>(z) * nw];
+        r.grad[r.w_off[l] + j] += s;
+    } else {
+        const int64_t m = j - nw;
+        const float* p = r.bpart + r.bpart_off[l] + m;
+        float s = 0.0f;
+        for (int z = 0; z < S; ++z) s += p[static_cast<int64_t>(z) * r.fout[l]];
+        r.grad[r.b_off[l] + m] += s;
+    }
+}
+
+// Adam on every parameter (FP32 masters), the gradient cleared, and each weight's BF16 copy
+// written to its place in the row-major padded packs the GEMMs read (padding stays zero)
+__global__ void k_adam_pack(AdamPackArgs a)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.P) return;
+    const float g = a.g[i];
+    const float mi = a.b1 * a.m[i] + (1.0f - a.b1) * g;
+    const float vi = a.b2 * a.v[i] + (1.0f - a.b2) * g * g;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float p = a.p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    a.p[i] = p;
+    a.g[i] = 0.0f;
+    int l = 0;
+    while (l + 1 < a.layers && i >= a.w_off[l + 1]) ++l;
+    const int64_t j = i - a.w_off[l];
+    const int64_t nw = static_cast<int64_t>(a.fout[l]) * a.fin[l];
+    if (j < nw) {
+        const int r = static_cast<int>(j / a.fin[l]), c = static_cast<int>(j % a.fin[l]);
+        a.wb[a.wb_off[l] + static_cast<int64_t>(r) * a.fin_pad[l] + c] = f2bf(p);
+    }
 }
 
 // FP32 -> BF16 of a [rows][cols] matrix into a [rows][ld_out] matrix, zero-padding columns
@@ -183,19 +335,6 @@ __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
-}
-
-__global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m, float* __restrict__ v,
-                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float g = gr[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * g;
-    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
 // weight matrix of one layer: master FP32 [out][in] -> BF16 [out_pad][in_pad] (zeros outside)
@@ -254,10 +393,24 @@ hipError_t launch_gemm(const GemmArgs& g, bool ta, bool tb, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float* G, int64_t rows, int cols, int ldg, float* part, float* out, hipStream_t stream)
+hipError_t launch_wgrad(const WgradArgs& g, int splits, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, kColChunks), dim3(64), 0, stream, G, rows, cols, ldg, part);
-    hipLaunchKernelGGL(k_colsum_final, dim3((cols + 63) / 64), dim3(64), 0, stream, part, cols, out);
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM, splits);
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_wgrad_reduce(const ReduceArgs& r, hipStream_t stream)
+{
+    if (r.total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(static_cast<unsigned>((r.total + 255) / 256)), dim3(256), 0, stream, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam_pack(const AdamPackArgs& a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_adam_pack, dim3(static_cast<unsigned>((a.P + 255) / 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -275,14 +428,6 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_f32, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, p, n, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
-                       float c1, float c2, hipStream_t stream)
-{
-    hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, p, g, m, v, n, lr,
-                       b1, b2, eps, c1, c2);
     return hipGetLastError();
 }
 

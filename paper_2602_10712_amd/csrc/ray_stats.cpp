@@ -19,7 +19,7 @@
 namespace {
 
 struct Counts {
-    double rays = 0, segments = 0, nodes = 0, tris = 0, hits = 0;
+    double rays = 0, segments = 0, nodes = 0, tris = 0, hits = 0, hit_rays = 0;
 };
 
 int closest_hit_counted(const std::vector<srp::BvhNode>& nodes, const std::vector<srp::TriRec>& tris, const float o[3],
@@ -89,6 +89,7 @@ extern "C" srp_status srp_scene_ray_stats(srp_scene s, const double* sun_dirs, i
     if (p->nu < 1 || p->nv < 1 || p->bounces < 1 || p->bounces > srp::kMaxBounces)
         return srp_fail(SRP_EINVAL, "bad trace parameters");
     if (p->frame_mode == 1 && !frames) return srp_fail(SRP_EINVAL, "frame_mode 1 needs frames");
+    if (p->ray_mask) return srp_fail(SRP_EUNSUPPORTED, "ray_mask is not supported by the statistics");
     std::vector<float4> mat(s->n_tris);
     if (hipSetDevice(s->device) != hipSuccess || hipMemcpy(mat.data(), s->d_mat, sizeof(float4) * s->n_tris,
                                                            hipMemcpyDeviceToHost) != hipSuccess)
@@ -126,6 +127,7 @@ extern "C" srp_status srp_scene_ray_stats(srp_scene s, const double* sun_dirs, i
                         const int hit = closest_hit_counted(s->h_nodes, s->h_tris, o, d, skip, t, c);
                         if (hit < 0) break;
                         c.hits += 1;
+                        if (b == 1) c.hit_rays += 1;
                         const srp::TriRec& tr = s->h_tris[hit];
                         const float n[3] = {tr.f[1].w, tr.f[2].w, tr.f[3].x};
                         float x[3], g[3];
@@ -151,11 +153,13 @@ extern "C" srp_status srp_scene_ray_stats(srp_scene s, const double* sun_dirs, i
         tot.nodes += c.nodes;
         tot.tris += c.tris;
         tot.hits += c.hits;
+        tot.hit_rays += c.hit_rays;
     }
     out[0] = tot.rays;
     out[1] = tot.segments;
     out[2] = tot.nodes;
     out[3] = tot.tris;
     out[4] = tot.hits;
+    out[5] = tot.hit_rays;
     return SRP_OK;
 }

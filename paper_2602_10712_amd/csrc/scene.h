@@ -26,7 +26,8 @@ struct srp_scene_s {
     std::vector<srp::BvhNode> h_nodes;   // host copies for the instrumented traversal
     std::vector<srp::TriRec> h_tris;
     bool h_tris_stale = false;           // the device records changed (GPU build); read back on use
-    bool h_tree_stale = false;           // the device nodes and order changed (GPU build); read back on use
+    bool h_tree_stale = false;           // the device nodes (and order) changed; read back on use
+    bool h_perm_stale = false;           // the device record order changed (GPU build); read back on use
     srp::BvhNode* d_nodes = nullptr;
     size_t nodes_cap = 0;
     srp::TriRec* d_tris = nullptr;
@@ -67,6 +68,23 @@ struct srp_scene_s {
     // GPU BVH build: one workspace block, kept for later rebuilds
     char* d_lbvh_ws = nullptr;
     size_t lbvh_ws_cap = 0;
+    // visibility-edge terms of the hinge gradient: the distinct edges of hinge-carried facets
+    // (vertex a, vertex b, hinge), numbered by first appearance in facet order, and the current
+    // vertex positions on the device
+    std::vector<int4> h_edges;
+    int4* d_edges = nullptr;
+    size_t edges_cap = 0;
+    float4* d_vpos = nullptr;
+    size_t vpos_cap = 0;
+    double* d_edge_part = nullptr;       // [D][edge workgroups][kMaxHinges]
+    size_t edge_part_cap = 0;
+    // device refit of the current tree: record ranges of every node's two child slots (valid for
+    // ranges_nodes == n_nodes) and the window-table workspace
+    int4* d_ranges = nullptr;
+    size_t ranges_cap = 0;
+    int32_t ranges_nodes = -1;
+    float* d_win = nullptr;
+    size_t win_cap = 0;
 };
 
 // Records `msg` as the thread's last error and returns `st`.

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -66,6 +68,7 @@ srp_status srp_pull_host_tree(srp_scene_s* s)
             hipMemcpy(s->perm.data(), s->d_perm, sizeof(int32_t) * s->n_tris, hipMemcpyDeviceToHost) != hipSuccess)
             return srp_fail(SRP_EDEVICE, "copying the tree to the host failed");
         s->h_tree_stale = false;
+        s->h_perm_stale = false;
     }
     if (s->h_tris_stale) {
         s->h_tris.resize(static_cast<size_t>(s->n_tris));
@@ -121,14 +124,88 @@ double scene_size(const std::vector<double>& v, int64_t n)
     return 2.0 * std::sqrt(r2);
 }
 
-// Builds (or, when only hinge angles changed, refits) the BVH from the current vertices, rebuilds
-// the triangle records and uploads both.
-srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
+// The distinct edges of hinge-carried facets (all three vertices on one hinge), in order of first
+// appearance over the facets and their edge slots; edges at the same pair of rest positions (the
+// two layers of a two-sided sheet, the edge two facets share) are one edge.
+void build_moving_edges(srp_scene_s* s)
 {
-    if (refit) {
-        const srp_status st = srp_pull_host_tree(s);
-        if (st != SRP_OK) return st;
+    s->h_edges.clear();
+    std::map<std::array<double, 6>, int> seen;
+    for (int64_t f = 0; f < s->n_tris; ++f) {
+        const int32_t* t = &s->tris[3 * f];
+        const int32_t k = s->vhinge[t[0]];
+        if (k < 0 || s->vhinge[t[1]] != k || s->vhinge[t[2]] != k) continue;
+        for (int e = 0; e < 3; ++e) {
+            const int32_t a = t[e], b = t[(e + 1) % 3];
+            const double* pa = &s->rest[3 * a];
+            const double* pb = &s->rest[3 * b];
+            const bool swap = std::lexicographical_compare(pb, pb + 3, pa, pa + 3);
+            const double* lo = swap ? pb : pa;
+            const double* hi = swap ? pa : pb;
+            const std::array<double, 6> key = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]};
+            if (seen.emplace(key, 1).second) s->h_edges.push_back(make_int4(a, b, k, 0));
+        }
     }
+}
+
+// Current vertex positions (FP32) for the edge terms; synchronous with `stream`.
+hipError_t upload_vertices(srp_scene_s* s, hipStream_t stream)
+{
+    if (s->h_edges.empty()) return hipSuccess;
+    hipError_t e0 = ensure(s->d_vpos, s->vpos_cap, static_cast<size_t>(s->n_verts));
+    if (e0 != hipSuccess) return e0;
+    std::vector<float4> v(static_cast<size_t>(s->n_verts));
+    for (int64_t i = 0; i < s->n_verts; ++i)
+        v[i] = make_float4(static_cast<float>(s->cur[3 * i]), static_cast<float>(s->cur[3 * i + 1]),
+                           static_cast<float>(s->cur[3 * i + 2]), 0.0f);
+    hipError_t e = hipMemcpyAsync(s->d_vpos, v.data(), v.size() * sizeof(float4), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    return e;
+}
+
+// The moving edges of the rest pose and the current vertex positions, on the device; synchronous.
+hipError_t upload_edges(srp_scene_s* s, hipStream_t stream)
+{
+    build_moving_edges(s);
+    if (s->h_edges.empty()) return hipSuccess;
+    hipError_t e = ensure(s->d_edges, s->edges_cap, s->h_edges.size());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_edges, s->h_edges.data(), sizeof(int4) * s->h_edges.size(), hipMemcpyHostToDevice,
+                           stream);
+    if (e == hipSuccess) e = upload_vertices(s, stream);
+    return e;
+}
+
+// Record ranges of every node's two child slots (first0, last0, first1, last1; last < first for
+// an empty leaf) of a pre-order tree whose leaves hold consecutive records.
+std::vector<int4> child_ranges(const std::vector<srp::BvhNode>& nodes)
+{
+    const int32_t n = static_cast<int32_t>(nodes.size());
+    std::vector<int4> r(n);
+    std::vector<int2> own(n);
+    for (int32_t i = n - 1; i >= 0; --i) {
+        int32_t codes[2];
+        std::memcpy(codes, &nodes[i].f[3], 8);
+        int2 sl[2];
+        for (int slot = 0; slot < 2; ++slot) {
+            const int32_t c = codes[slot];
+            if (c >= 0) {
+                sl[slot] = own[c];
+            } else {
+                const int32_t first = (~c) >> 3, cnt = (~c) & 7;
+                sl[slot] = make_int2(first, first + cnt - 1);
+            }
+        }
+        r[i] = make_int4(sl[0].x, sl[0].y, sl[1].x, sl[1].y);
+        const bool e0 = sl[0].y < sl[0].x, e1 = sl[1].y < sl[1].x;
+        own[i] = e0 ? sl[1] : e1 ? sl[0] : make_int2(std::min(sl[0].x, sl[1].x), std::max(sl[0].y, sl[1].y));
+    }
+    return r;
+}
+
+// Bounds and scene size of the current vertices.
+void update_bounds(srp_scene_s* s)
+{
     const auto& V = s->cur;
     for (int a = 0; a < 3; ++a) {
         s->lo[a] = INFINITY;
@@ -140,9 +217,17 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
             s->hi[a] = std::max(s->hi[a], V[3 * i + a]);
         }
     s->L = scene_size(V, s->n_verts);
-    if (refit && !s->h_nodes.empty()) {
-        srp::refit_bvh(s->h_nodes, s->perm, V.data(), s->tris.data(), 1e-6 * s->L);
-    } else {
+}
+
+// Bounds, scene size, triangle records and cumulative areas for the current vertices; the tree
+// is built on the host, or (refit) kept and its boxes refitted on the device.  Fails before any
+// change to the tree or the records when the new tree is deeper than the traversal stack.
+srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
+{
+    const auto& V = s->cur;
+    update_bounds(s);
+    const bool device_refit = refit && s->d_nodes && s->ranges_nodes == s->n_nodes;
+    if (!device_refit) {
         srp::BvhBuildResult bvh = srp::build_bvh(V.data(), s->tris.data(), s->n_tris, 1e-6 * s->L);
         if (bvh.depth >= srp::kStackDepth - 1) return fail(SRP_EUNSUPPORTED, "BVH deeper than the traversal stack");
         s->n_nodes = static_cast<int32_t>(bvh.nodes.size());
@@ -150,6 +235,13 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
         s->perm = std::move(bvh.perm);
         s->h_nodes = std::move(bvh.nodes);
         s->h_tree_stale = false;
+    } else {
+        // the records are formed on the host in tree order: bring the order back after a GPU build
+        if (s->h_perm_stale) {
+            const srp_status st = srp_pull_host_tree(s);
+            if (st != SRP_OK) return st;
+        }
+        s->h_tree_stale = true;  // the refit changes the device boxes only; the host order stays valid
     }
     std::vector<srp::TriRec> recs(s->n_tris);
     for (int64_t p = 0; p < s->n_tris; ++p) {
@@ -204,14 +296,28 @@ srp_status rebuild(srp_scene_s* s, hipStream_t stream, bool refit = false)
     SRP_HIP(ensure(s->d_bvh_pos, s->bvh_pos_cap, static_cast<size_t>(s->n_tris)));
     SRP_HIP(hipMemcpyAsync(s->d_cum_area, cum.data(), cum.size() * sizeof(double), hipMemcpyHostToDevice, stream));
     SRP_HIP(hipMemcpyAsync(s->d_bvh_pos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-    SRP_HIP(ensure(s->d_nodes, s->nodes_cap, s->h_nodes.size()));
     SRP_HIP(ensure(s->d_tris, s->tris_cap, static_cast<size_t>(s->n_tris)));
-    SRP_HIP(ensure(s->d_perm, s->perm_cap, static_cast<size_t>(s->n_tris)));
-    SRP_HIP(hipMemcpyAsync(s->d_nodes, s->h_nodes.data(), s->h_nodes.size() * sizeof(srp::BvhNode),
-                           hipMemcpyHostToDevice, stream));
     SRP_HIP(hipMemcpyAsync(s->d_tris, recs.data(), recs.size() * sizeof(srp::TriRec), hipMemcpyHostToDevice, stream));
-    SRP_HIP(hipMemcpyAsync(s->d_perm, s->perm.data(), s->perm.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                           stream));
+    if (!device_refit) {
+        SRP_HIP(ensure(s->d_nodes, s->nodes_cap, s->h_nodes.size()));
+        SRP_HIP(ensure(s->d_perm, s->perm_cap, static_cast<size_t>(s->n_tris)));
+        SRP_HIP(hipMemcpyAsync(s->d_nodes, s->h_nodes.data(), s->h_nodes.size() * sizeof(srp::BvhNode),
+                               hipMemcpyHostToDevice, stream));
+        SRP_HIP(hipMemcpyAsync(s->d_perm, s->perm.data(), s->perm.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               stream));
+        const std::vector<int4> ranges = child_ranges(s->h_nodes);
+        SRP_HIP(ensure(s->d_ranges, s->ranges_cap, ranges.size()));
+        SRP_HIP(hipMemcpyAsync(s->d_ranges, ranges.data(), ranges.size() * sizeof(int4), hipMemcpyHostToDevice,
+                               stream));
+        s->ranges_nodes = s->n_nodes;
+    } else {
+        const int32_t n = static_cast<int32_t>(s->n_tris);
+        int32_t levels = 1;
+        while ((int64_t(1) << levels) <= n) ++levels;
+        SRP_HIP(ensure(s->d_win, s->win_cap, static_cast<size_t>(6) * n * levels));
+        SRP_HIP(srp::launch_refit(s->d_tris, n, s->d_nodes, s->d_ranges, s->n_nodes, s->d_win, levels,
+                                  static_cast<float>(1e-6 * s->L), stream));
+    }
     SRP_HIP(hipStreamSynchronize(stream));
     s->h_tris = std::move(recs);
     s->h_tris_stale = false;
@@ -252,6 +358,7 @@ srp_status check_params(const srp_trace_params* p)
     if (p->tiles_per_wave < 0 || p->tiles_per_wave > srp::kMaxTilesPerWave)
         return fail(SRP_EINVAL, "tiles_per_wave must be in 0..16");
     if (p->sampling < 0 || p->sampling > 3) return fail(SRP_EINVAL, "sampling must be in 0..3");
+    if (p->edge_samples < 0 || p->edge_samples > 4096) return fail(SRP_EINVAL, "edge_samples must be in 0..4096");
     return SRP_OK;
 }
 
@@ -270,9 +377,12 @@ srp_status bind_device(const srp_scene_s* s)
 srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
                          const double* frames, bool records, const int64_t* pix, int64_t n_pix, int32_t* rec_hit,
                          float* rec_force, hipStream_t stream, srp::TraceArgs& a,
-                         const srp::TraceWorkspace* ws = nullptr)
+                         const srp::TraceWorkspace* ws = nullptr, float* rec_point = nullptr)
 {
     a = srp::TraceArgs{};
+    a.ray_mask = p->ray_mask;
+    a.mask_words = (static_cast<int64_t>(p->nu) * p->nv + 31) / 32;
+    a.rec_point = rec_point;
     a.nodes = s->d_nodes;
     a.tris = s->d_tris;
     a.mat = s->d_mat;
@@ -334,10 +444,11 @@ srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
 
 srp_status enqueue_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
                          const double* frames, bool records, const int64_t* pix, int64_t n_pix, int32_t* rec_hit,
-                         float* rec_force, hipStream_t stream, int32_t* bpd_out)
+                         float* rec_force, float* rec_point, hipStream_t stream, int32_t* bpd_out)
 {
     srp::TraceArgs a;
-    srp_status st = prepare_trace(s, sun_dirs, D, p, frames, records, pix, n_pix, rec_hit, rec_force, stream, a);
+    srp_status st = prepare_trace(s, sun_dirs, D, p, frames, records, pix, n_pix, rec_hit, rec_force, stream, a,
+                                  nullptr, rec_point);
     if (st != SRP_OK) return st;
     SRP_HIP(srp::launch_trace(a, records, stream));
     *bpd_out = a.blocks_per_dir;
@@ -435,6 +546,7 @@ srp_status srp_scene_create(const double* verts, int64_t n_verts, const int32_t*
     e = ensure(s->d_mat, s->mat_cap, static_cast<size_t>(n_tris));
     if (e == hipSuccess) e = hipMemset(s->d_mat, 0, sizeof(float4) * n_tris);
     if (e == hipSuccess) e = ensure(s->d_flag, s->flag_cap, 1);
+    if (e == hipSuccess) e = upload_edges(s, nullptr);
     if (e != hipSuccess) {
         srp_scene_destroy(s);
         return fail(SRP_EDEVICE, std::string("scene buffers: ") + hipGetErrorString(e));
@@ -463,6 +575,7 @@ srp_status srp_scene_set_design(srp_scene s, const double* hinge_angles, const f
             rotate_hinges(s);
             st = rebuild(s, stream, s->refit_on_hinge);
             if (st != SRP_OK) return st;
+            SRP_HIP(upload_vertices(s, stream));
         }
     }
     SRP_HIP(hipMemsetAsync(s->d_flag, 0, sizeof(int32_t), stream));
@@ -471,7 +584,70 @@ srp_status srp_scene_set_design(srp_scene s, const double* hinge_angles, const f
     SRP_HIP(hipMemcpyAsync(&flag, s->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     SRP_HIP(hipStreamSynchronize(stream));
     if (flag & 1) return fail(SRP_EINVAL, "reflectances must satisfy rho_s >= 0, rho_d >= 0, rho_s + rho_d <= 1");
-    if (flag & 2) return fail(SRP_EINVAL, "p_spec must lie in [0, 1]");
+    if (flag & 2)
+        return fail(SRP_EINVAL, "p_spec must lie in [0, 1], and may be 0 only where rho_s = 0 and 1 only where rho_d = 0");
+    return SRP_OK;
+}
+
+srp_status srp_scene_set_vertices(srp_scene s, const double* verts, int64_t n_verts, int32_t mode, void* stream_)
+{
+    if (!s || !verts) return fail(SRP_EINVAL, "NULL argument");
+    if (n_verts != s->n_verts) return fail(SRP_EINVAL, "n_verts does not match the scene");
+    if (mode != 0 && mode != 1) return fail(SRP_EINVAL, "mode must be 0 (refit the tree) or 1 (rebuild it)");
+    for (int64_t i = 0; i < 3 * n_verts; ++i)
+        if (!std::isfinite(verts[i])) return fail(SRP_EDEGENERATE, "non-finite vertex");
+    srp_status st = bind_device(s);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    // every facet of the new pose must keep a positive area before anything changes
+    std::vector<double> old_rest;
+    old_rest.swap(s->rest);
+    s->rest.assign(verts, verts + 3 * n_verts);
+    rotate_hinges(s);
+    for (int64_t f = 0; f < s->n_tris; ++f) {
+        const double* a = &s->cur[3 * static_cast<int64_t>(s->tris[3 * f])];
+        const double* b = &s->cur[3 * static_cast<int64_t>(s->tris[3 * f + 1])];
+        const double* c = &s->cur[3 * static_cast<int64_t>(s->tris[3 * f + 2])];
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+        const double len = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        if (!(len > 0.0) || !std::isfinite(len)) {
+            s->rest.swap(old_rest);
+            rotate_hinges(s);
+            return fail(SRP_EDEGENERATE, "zero-area or non-finite facet");
+        }
+    }
+    SRP_HIP(hipStreamSynchronize(stream));  // kernels in flight may still read the old tree
+    // a rebuild reorders the records: the packed materials follow their facets
+    std::vector<int32_t> old_pos;
+    if (mode == 1) {
+        if (s->h_perm_stale) {
+            st = srp_pull_host_tree(s);
+            if (st != SRP_OK) return st;
+        }
+        old_pos.resize(static_cast<size_t>(s->n_tris));
+        for (int64_t q = 0; q < s->n_tris; ++q) old_pos[s->perm[q]] = static_cast<int32_t>(q);
+    }
+    st = rebuild(s, stream, mode == 0);
+    if (st == SRP_EUNSUPPORTED) {
+        // a tree deeper than the stack: nothing changed but the bounds
+        s->rest.swap(old_rest);
+        rotate_hinges(s);
+        update_bounds(s);
+        return st;
+    }
+    if (st != SRP_OK) return st;
+    if (mode == 1) {
+        std::vector<float4> m_old(static_cast<size_t>(s->n_tris)), m_new(static_cast<size_t>(s->n_tris));
+        SRP_HIP(hipMemcpyAsync(m_old.data(), s->d_mat, sizeof(float4) * s->n_tris, hipMemcpyDeviceToHost, stream));
+        SRP_HIP(hipStreamSynchronize(stream));
+        for (int64_t q = 0; q < s->n_tris; ++q) m_new[q] = m_old[old_pos[s->perm[q]]];
+        SRP_HIP(hipMemcpyAsync(s->d_mat, m_new.data(), sizeof(float4) * s->n_tris, hipMemcpyHostToDevice, stream));
+        SRP_HIP(hipStreamSynchronize(stream));
+    }
+    SRP_HIP(upload_edges(s, stream));
     return SRP_OK;
 }
 
@@ -512,7 +688,7 @@ srp_status srp_trace(srp_scene s, const double* sun_dirs, int64_t D, const srp_t
 
 srp_status srp_trace_records(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
                              const double* frames, const int64_t* pix, int64_t n_pix, int32_t* hit_prim,
-                             float* ray_force, void* stream_)
+                             float* ray_force, float* hit_point, void* stream_)
 {
     if (!s) return fail(SRP_EINVAL, "scene is NULL");
     srp_status st = check_params(p);
@@ -525,7 +701,7 @@ srp_status srp_trace_records(srp_scene s, const double* sun_dirs, int64_t D, con
     st = bind_device(s);
     if (st != SRP_OK) return st;
     int32_t bpd = 0;
-    return enqueue_trace(s, sun_dirs, D, p, frames, true, pix, n_pix, hit_prim, ray_force,
+    return enqueue_trace(s, sun_dirs, D, p, frames, true, pix, n_pix, hit_prim, ray_force, hit_point,
                          static_cast<hipStream_t>(stream_), &bpd);
 }
 
@@ -543,6 +719,8 @@ srp_status srp_trace_adjoint(srp_scene s, const double* sun_dirs, int64_t D, con
     if (p->dir_index_base + D > (int64_t(1) << 32)) return fail(SRP_EINVAL, "direction index exceeds 32 bits");
     if (g_hinge && s->n_hinges > srp::kMaxHinges)
         return fail(SRP_EUNSUPPORTED, "hinge gradients support at most 4 hinges");
+    if (g_hinge && p->edge_samples > 0 && D > 65535)
+        return fail(SRP_EUNSUPPORTED, "visibility-edge terms support at most 65535 directions per call");
     st = bind_device(s);
     if (st != SRP_OK) return st;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
@@ -564,8 +742,36 @@ srp_status srp_trace_adjoint(srp_scene s, const double* sun_dirs, int64_t D, con
         }
     A.hinge_partials = s->d_partials;  // sized for kMaxHinges per workgroup
     SRP_HIP(srp::launch_adjoint(A, stream));
-    SRP_HIP(srp::launch_finish_adjoint(s->d_grho, A.n_tris, g_rho_s, g_rho_d, s->d_partials, D, A.t.blocks_per_dir,
-                                       A.n_hinges, s->d_hdir, g_hinge, stream));
+    if (A.n_hinges > 0) {
+        SRP_HIP(srp::launch_reduce_hinges(s->d_partials, D, A.t.blocks_per_dir, s->d_hdir, stream));
+        if (p->edge_samples > 0 && !s->h_edges.empty()) {
+            srp::EdgeArgs E{};
+            E.edges = s->d_edges;
+            E.verts = s->d_vpos;
+            E.n_edges = static_cast<int32_t>(s->h_edges.size());
+            E.samples = p->edge_samples;
+            E.D = D;
+            E.bounces = p->bounces;
+            E.seed_lo = A.t.seed_lo;
+            E.seed_hi = A.t.seed_hi;
+            E.dir_index_base = p->dir_index_base;
+            E.design_index = A.t.design_index;
+            E.eps = A.t.eps;
+            E.delta = A.t.eps;
+            for (int c = 0; c < 3; ++c) E.com[c] = A.t.com[c];
+            for (int k = 0; k < A.n_hinges; ++k)
+                for (int c = 0; c < 3; ++c) {
+                    E.hinge_axis[k][c] = A.hinge_axis[k][c];
+                    E.hinge_origin[k][c] = A.hinge_origin[k][c];
+                }
+            const int64_t nb = srp::edge_blocks(E);
+            SRP_HIP(ensure(s->d_edge_part, s->edge_part_cap, static_cast<size_t>(D * nb * srp::kMaxHinges)));
+            SRP_HIP(srp::launch_edge_term(E, s->d_nodes, s->d_tris, s->d_mat, A.t.frames, g_force, g_torque,
+                                          A.t.lane_walk, s->d_edge_part, s->d_hdir, stream));
+        }
+    }
+    SRP_HIP(srp::launch_finish_adjoint(s->d_grho, A.n_tris, g_rho_s, g_rho_d, D, A.n_hinges, s->d_hdir, g_hinge,
+                                       stream));
     return SRP_OK;
 }
 
@@ -574,6 +780,7 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
 {
     if (!scenes || S < 1) return fail(SRP_EINVAL, "need at least one scene");
     srp_status st = check_params(p);
+    if (st == SRP_OK && p->ray_mask) return fail(SRP_EUNSUPPORTED, "ray_mask is supported by single-scene traces only");
     if (st != SRP_OK) return st;
     if (p->frame_mode != 0) return fail(SRP_EUNSUPPORTED, "batched traces derive their frames from each mesh");
     if (D < 0) return fail(SRP_EINVAL, "D must be >= 0");
@@ -677,7 +884,7 @@ srp_status srp_scene_build_gpu(srp_scene s, int32_t* n_nodes_out, int32_t* depth
     a.tmp_bytes = srp::lbvh_tmp_bytes(n);
     const size_t nn = static_cast<size_t>(n);
     const size_t sizes[] = {4 * nn, 4 * nn, 4 * nn, 4 * nn, a.tmp_bytes, 64 * nn, 16 * nn, 4 * nn, 4 * nn,
-                            8 * nn, 8 * nn, 4 * nn, 4 * nn, 4 * nn, 4 * (nn + 1), 24 * nn * levels, 64 * nn, 4};
+                            8 * nn, 8 * nn, 4 * nn, 4 * nn, 4 * nn, 4 * (nn + 1), 24 * nn * levels, 64 * nn, 16 * nn, 4};
     size_t total = 0;
     for (size_t z : sizes) total += (z + 255) / 256 * 256;
     SRP_HIP(ensure(s->d_lbvh_ws, s->lbvh_ws_cap, total));
@@ -705,6 +912,7 @@ srp_status srp_scene_build_gpu(srp_scene s, int32_t* n_nodes_out, int32_t* depth
     a.scan = reinterpret_cast<int32_t*>(take());
     a.win = reinterpret_cast<float*>(take());
     a.nodes_out = reinterpret_cast<srp::BvhNode*>(take());
+    a.ranges_out = reinterpret_cast<int4*>(take());
     a.depth_out = reinterpret_cast<int32_t*>(take());
     hipError_t e = srp::launch_lbvh(a, stream);
     int32_t records = 0, depth = 0;
@@ -725,10 +933,15 @@ srp_status srp_scene_build_gpu(srp_scene s, int32_t* n_nodes_out, int32_t* depth
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_mat, a.mat_out, 16 * nn, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_perm, a.perm_out, 4 * nn, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_bvh_pos, a.bvh_pos_out, 4 * nn, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = ensure(s->d_ranges, s->ranges_cap, static_cast<size_t>(count));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_ranges, a.ranges_out, sizeof(int4) * count, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("GPU BVH build: ") + hipGetErrorString(e));
     s->h_tree_stale = true;
     s->h_tris_stale = true;
+    s->h_perm_stale = true;
+    s->ranges_nodes = count;
     s->n_nodes = count;
     s->depth = depth;
     if (n_nodes_out) *n_nodes_out = count;
@@ -743,6 +956,7 @@ srp_status srp_surface_estimate(const srp_scene* scenes, int32_t S, const double
 {
     if (!scenes || S < 1) return fail(SRP_EINVAL, "need at least one scene");
     srp_status st = check_params(p);
+    if (st == SRP_OK && p->ray_mask) return fail(SRP_EUNSUPPORTED, "ray_mask is supported by single-scene traces only");
     if (st != SRP_OK) return st;
     if (D < 0 || n_samples < 1) return fail(SRP_EINVAL, "D must be >= 0 and n_samples >= 1");
     if (D == 0) return SRP_OK;
@@ -818,6 +1032,7 @@ srp_status srp_autotune_tiles_per_wave(const srp_scene* scenes, int32_t S, const
 {
     if (!scenes || S < 1 || !best) return fail(SRP_EINVAL, "need scenes and an output");
     srp_status st = check_params(p);
+    if (st == SRP_OK && p->ray_mask) return fail(SRP_EUNSUPPORTED, "ray_mask is supported by single-scene traces only");
     if (st != SRP_OK) return st;
     if (D < 1 || !sun_dirs) return fail(SRP_EINVAL, "need at least one sun direction");
     for (int32_t s = 0; s < S; ++s)
@@ -883,6 +1098,9 @@ srp_status srp_scene_destroy(srp_scene s)
     (void)hipFree(s->d_bvh_pos);
     (void)hipFree(s->d_surf_desc);
     (void)hipFree(s->d_lbvh_ws);
+    (void)hipFree(s->d_edges);
+    (void)hipFree(s->d_vpos);
+    (void)hipFree(s->d_edge_part);
     if (s->surf_ev) {
         (void)hipEventSynchronize(s->surf_ev);
         (void)hipEventDestroy(s->surf_ev);

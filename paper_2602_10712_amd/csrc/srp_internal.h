@@ -102,7 +102,16 @@ struct TraceArgs {
     double* partials;         // [(scene *) D][blocks_per_dir][6]
     int32_t* rec_hit;         // [D][n_pix][bounces]
     float* rec_force;         // [D][n_pix][3]
+    float* rec_point;         // [D][n_pix][bounces][3] hit points (NaN after the path ended), or null
+    const uint32_t* ray_mask; // single scene: [D][mask_words] bitmap of primary pixels left out, or null
+    int64_t mask_words;       // words per direction: ceil(nu * nv / 32)
 };
+
+// Primary pixel `pixel` of direction j (of a single-scene call) is left out by the caller's mask.
+__device__ __forceinline__ bool ray_masked(const TraceArgs& a, int64_t j, int64_t pixel)
+{
+    return ((a.ray_mask[j * a.mask_words + (pixel >> 5)] >> (pixel & 31)) & 1u) != 0u;
+}
 
 // Workgroups of a trace or adjoint launch over n_units units (directions, or (design, direction)
 // pairs).  Direction-major order needs n_units x blocks_per_dir; XCD-major order pads n_units to
@@ -175,6 +184,7 @@ struct LbvhArgs {
     int32_t* scan;                  // [n + 1] leaf records opened before each leaf; scan[n] - 1 nodes
     float* win;                     // [levels][n][6] box of leaves [i, i + 2^level)
     BvhNode* nodes_out;             // [n - 1], pre-order, scan[n] - 1 of them written
+    int4* ranges_out;               // [n - 1] record ranges of each written node's child slots
     int32_t* depth_out;             // deepest level (root = 0)
 };
 
@@ -203,12 +213,39 @@ hipError_t launch_trace_batch(const TraceArgs& a, hipStream_t stream);
 hipError_t launch_reduce(const double* partials, int64_t D, int32_t blocks_per_dir, double* force, double* torque,
                          hipStream_t stream);
 hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream);
+
+// Visibility-edge terms of the hinge-angle gradient (edge_kernels.hip).
+struct EdgeArgs {
+    const int4* edges;      // [n_edges]: vertex a, vertex b, hinge, 0 (distinct moving edges)
+    const float4* verts;    // [n_verts] current vertex positions
+    int32_t n_edges;
+    int32_t samples;        // points per edge
+    int64_t D;
+    int32_t bounces;
+    uint32_t seed_lo, seed_hi;
+    int64_t dir_index_base;
+    uint32_t design_index;
+    float eps;              // secondary-ray offset along the normal
+    float delta;            // offset of the two side points from the edge
+    float com[3];
+    float hinge_origin[kMaxHinges][3];
+    float hinge_axis[kMaxHinges][3];
+};
+int32_t edge_blocks(const EdgeArgs& E);
+hipError_t launch_edge_term(const EdgeArgs& E, const BvhNode* nodes, const TriRec* tris, const float4* mat,
+                            const DevFrame* frames, const double* g_force, const double* g_torque, int lane_walk,
+                            double* partials, double* per_dir, hipStream_t stream);
+hipError_t launch_reduce_hinges(const double* hinge_partials, int64_t D, int32_t blocks_per_dir, double* per_dir,
+                                hipStream_t stream);
 size_t lbvh_tmp_bytes(int32_t n);
 hipError_t launch_lbvh(const LbvhArgs& a, hipStream_t stream);
+// Device refit of a kept tree over n records: win holds [levels][n][6] floats of workspace,
+// ranges[i] the record ranges (first0, last0, first1, last1) of node i's two child slots.
+hipError_t launch_refit(const TriRec* tris, int32_t n, BvhNode* nodes, const int4* ranges, int32_t n_nodes, float* win,
+                        int32_t levels, float pad, hipStream_t stream);
 hipError_t launch_surface(const SurfaceArgs& a, bool brute, double* force, double* torque, hipStream_t stream);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream);
-hipError_t launch_finish_adjoint(const double* g_rho, int32_t n_tris, float* g_rho_s, float* g_rho_d,
-                                 const double* hinge_partials, int64_t D, int32_t blocks_per_dir, int32_t n_hinges,
-                                 double* per_dir, double* g_hinge, hipStream_t stream);
+hipError_t launch_finish_adjoint(const double* g_rho, int32_t n_tris, float* g_rho_s, float* g_rho_d, int64_t D,
+                                 int32_t n_hinges, const double* per_dir, double* g_hinge, hipStream_t stream);
 
 }  // namespace srp

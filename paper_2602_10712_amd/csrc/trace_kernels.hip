@@ -60,7 +60,9 @@ __global__ void k_pack_mat(const float* __restrict__ rs, const float* __restrict
     float q;
     if (ps) {
         q = ps[f];
-        if (!(q >= 0.0f && q <= 1.0f)) flag |= 2;
+        // a probability outside [0, 1], or one that can never choose an event whose reflectance
+        // is not zero (that lobe's momentum would silently go missing from the estimate)
+        if (!(q >= 0.0f && q <= 1.0f) || (q == 0.0f && a > 0.0f) || (q == 1.0f && b > 0.0f)) flag |= 2;
     } else if (a > 0.0f && b > 0.0f) {
         q = a / (a + b);
         q = fminf(fmaxf(q, 0.01f), 0.99f);
@@ -124,6 +126,7 @@ __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNod
                     a.jitter != 0, o, d);
         float w = fr.w;
         bool alive = valid;
+        if (a.ray_mask && valid && ray_masked(a, j, pixel)) alive = false;
         int skip = -1;
         float ray[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         int b_done = 0;
@@ -151,6 +154,12 @@ __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNod
             float x[3], g[3];
             alive = interact(o, d, w, t, n, mt.x, mt.y, mt.z, b, a.bounces, static_cast<uint32_t>(pixel), dir_global,
                              design, a.seed_lo, a.seed_hi, eps, x, g);
+            if (RECORDS && a.rec_point) {
+                float* rp = a.rec_point + ((j * a.n_pix + rec) * a.bounces + (b - 1)) * 3;
+                rp[0] = x[0];
+                rp[1] = x[1];
+                rp[2] = x[2];
+            }
             const float lx = x[0] - com[0], ly = x[1] - com[1], lz = x[2] - com[2];
             ray[0] += g[0];
             ray[1] += g[1];
@@ -161,7 +170,13 @@ __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNod
             skip = hit;
         }
         if (RECORDS && valid) {
-            for (int b = b_done + 1; b <= a.bounces; ++b) a.rec_hit[(j * a.n_pix + rec) * a.bounces + (b - 1)] = -1;
+            for (int b = b_done + 1; b <= a.bounces; ++b) {
+                a.rec_hit[(j * a.n_pix + rec) * a.bounces + (b - 1)] = -1;
+                if (a.rec_point) {
+                    float* rp = a.rec_point + ((j * a.n_pix + rec) * a.bounces + (b - 1)) * 3;
+                    rp[0] = rp[1] = rp[2] = __builtin_nanf("");
+                }
+            }
             if (a.rec_force) {
                 float* rf = a.rec_force + (j * a.n_pix + rec) * 3;
                 rf[0] = ray[0];

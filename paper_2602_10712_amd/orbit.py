@@ -110,3 +110,65 @@ class DesignProblem:
 
     def close(self):
         self.scene.close()
+
+
+class SurrogateDesignProblem(DesignProblem):
+    """The same design problem with the force at every stage time answered by the surrogate ensemble
+    instead of the tracer -- the paper's Alg. 1, where the proxy sits inside the ODE.  The force is
+    the ensemble mean scaled by f_ref (srp_mlp_ensemble, fused inference); its design gradient is
+    the networks' input gradient (srp_mlp_backward with g_x) chained with the orbit adjoint and the
+    input scaling 2 / (hi - lo).  The networks' weight-gradient buffers are cleared afterwards."""
+
+    def __init__(self, mesh, scenario, nets, f_ref, lo, hi, r_target=None, ckpt_every=60):
+        self.mesh = mesh
+        self.sc = scenario
+        self.nets = nets
+        self.f_ref = float(f_ref)
+        self.lo = np.asarray(lo, dtype=np.float64)
+        self.hi = np.asarray(hi, dtype=np.float64)
+        self.sun_np = np.asarray(scenario.sun_body, dtype=np.float64)
+        self.group = np.asarray(mesh.group)
+        self.r_target = None if r_target is None else np.asarray(r_target, dtype=np.float64)
+        self.ckpt_every = ckpt_every
+        self.n_stage = 2 * scenario.n_steps + 1
+        assert self.sun_np.shape[0] == self.n_stage
+        n = self.n_stage
+        self._y = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        self._dis = torch.empty(n, dtype=torch.float32, device="cuda")
+        self._idx = torch.empty(n, dtype=torch.int32, device="cuda")
+        self._cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    def inputs(self, theta):
+        th = np.broadcast_to(np.asarray(theta, dtype=np.float64), (self.n_stage, 8))
+        scaled = 2.0 * (th - self.lo) / (self.hi - self.lo) - 1.0
+        x = np.concatenate([self.sun_np, scaled], 1).astype(np.float32)
+        return torch.as_tensor(x, device="cuda").contiguous()
+
+    def forces(self, theta):
+        x = self.inputs(theta)
+        B.srp_mlp_ensemble(self.nets[0].handle, self.nets[1].handle, x, np.inf, self.f_ref, self._y, self._idx,
+                           self._cnt)
+        return self._y.cpu().numpy().astype(np.float64)
+
+    def loss_and_grad(self, theta):
+        theta = np.asarray(theta, dtype=np.float64)
+        x = self.inputs(theta)
+        z, F = self.final_state(theta)
+        d = z[:3] - self.r_target
+        g_final = np.concatenate([2.0 * d, np.zeros(3)])
+        gF, _ = B.srp_orbit_rk4_adjoint(self.sc.z0, self.sc.mu, self.sc.mass, self.sc.dt, self.sc.n_steps, F,
+                                        self.sc.R, g_final, self.ckpt_every)
+        # F = f_ref (y_a + y_b) / 2: each network receives dL/dy = f_ref / 2 dL/dF
+        g_y = torch.as_tensor((0.5 * self.f_ref * gF).astype(np.float32), device="cuda").contiguous()
+        g_x = np.zeros((self.n_stage, x.shape[1]))
+        for net in self.nets:
+            net.forward(x, keep_activations=True)
+            gx = torch.empty_like(x)
+            B.srp_mlp_backward(net.handle, g_y, gx)
+            B.srp_mlp_zero_grad(net.handle)
+            g_x += gx.cpu().numpy().astype(np.float64)
+        grad = g_x[:, 3:].sum(0) * 2.0 / (self.hi - self.lo)
+        return float(d @ d), grad
+
+    def close(self):
+        pass

@@ -72,55 +72,70 @@ def rel_rms(pred, ref):
 
 
 class SurrogateForce:
-    """Two-member ensemble with a domain check and a disagreement threshold; failing queries are
-    answered by the tracer."""
+    """Two-member ensemble with the library's confidence test (srp_mlp_ensemble: mean, disagreement,
+    domain check, compaction of failing queries); failing queries are answered by the tracer."""
 
     def __init__(self, nets, lo, hi, f_ref, threshold):
+        assert len(nets) == 2
         self.nets = nets
         self.lo = np.asarray(lo, dtype=np.float64)
         self.hi = np.asarray(hi, dtype=np.float64)
         self.f_ref = f_ref
         self.threshold = threshold
 
-    def predict(self, x):
+    def evaluate(self, x, out_scale=None, threshold=None, stream=None):
+        """srp_mlp_ensemble on inputs x [N][11] (host or device): device tensors (y [N][n_out] scaled by
+        out_scale (default f_ref), disagreement [N], failing query indices [N] int32, their count [1])."""
         xd = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
-        ys = [n.forward(xd) for n in self.nets]
-        mean = sum(ys) / len(ys)
-        disagree = torch.linalg.vector_norm(ys[0] - ys[1], dim=1) if len(ys) > 1 else torch.zeros(len(xd), device="cuda")
-        return mean, disagree
+        n = xd.shape[0]
+        y = torch.empty((n, self.nets[0].n_out), dtype=torch.float32, device="cuda")
+        dis = torch.empty(n, dtype=torch.float32, device="cuda")
+        idx = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+        B.srp_mlp_ensemble(self.nets[0].handle, self.nets[1].handle, xd,
+                           self.threshold if threshold is None else threshold,
+                           self.f_ref if out_scale is None else out_scale, y, idx, cnt, disagree=dis, stream=stream)
+        return y, dis, idx, cnt
+
+    def predict(self, x):
+        """Ensemble mean (network units) and disagreement, no test applied."""
+        y, dis, _, _ = self.evaluate(x, out_scale=1.0, threshold=np.inf)
+        return y, dis
 
     @staticmethod
-    def calibrate(disagree, err, target):
-        """Largest disagreement threshold whose accepted queries keep the relative RMS error <= target
-        (err: per-query squared error divided by the mean squared reference)."""
+    def calibrate(disagree, err, target, max_coverage=1.0):
+        """Disagreement threshold for held-out queries: the largest one whose accepted queries keep the
+        relative RMS error <= target (err: per-query squared error divided by the mean squared
+        reference), lowered if needed so that at most max_coverage of the queries are accepted."""
         order = np.argsort(disagree)
         cum = np.cumsum(err[order]) / np.arange(1, len(err) + 1)
         ok = np.nonzero(np.sqrt(cum) <= target)[0]
-        return float(disagree[order][ok[-1]]) if len(ok) else 0.0
-
-    def in_domain(self, sun, theta):
-        th = np.asarray(theta, dtype=np.float64).reshape(-1, 8)
-        unit = np.abs(np.linalg.norm(np.asarray(sun).reshape(-1, 3), axis=1) - 1.0) < 1e-6
-        return unit & np.all((th >= self.lo - 1e-12) & (th <= self.hi + 1e-12), axis=1)
+        thr = float(disagree[order][ok[-1]]) if len(ok) else 0.0
+        if max_coverage < 1.0:
+            thr = min(thr, float(np.quantile(disagree, max_coverage)))
+        return thr
 
     def forces(self, mesh, sun, theta, params: B.TraceParams):
-        """Forces [N][3] (N): surrogate where it is trusted, tracer elsewhere; also the fallback mask."""
-        x = input_features(sun, np.clip(theta, self.lo, self.hi), self.lo, self.hi)
-        mean, dis = self.predict(x)
-        F = mean.double().cpu().numpy() * self.f_ref
-        fall = (~self.in_domain(sun, theta)) | (dis.cpu().numpy() > self.threshold)
-        if fall.any():
-            idx = np.nonzero(fall)[0]
-            th = np.asarray(theta, dtype=np.float64).reshape(-1, 8)
+        """Forces [N][3] (N, device FP32 tensor): the ensemble where it passes the confidence test, the
+        tracer elsewhere; also the host bool mask of the queries the tracer answered."""
+        sun = np.asarray(sun, dtype=np.float64).reshape(-1, 3)
+        th = np.asarray(theta, dtype=np.float64).reshape(-1, 8)
+        x = input_features(sun, th, self.lo, self.hi)
+        F, _, idx, cnt = self.evaluate(x)
+        n_fail = int(cnt.item())
+        fall = np.zeros(len(x), dtype=bool)
+        if n_fail:
+            sel_all = idx[:n_fail].cpu().numpy().astype(np.int64)
+            fall[sel_all] = True
             # group the failing queries by design and trace each design once
-            designs, inv = np.unique(th[idx], axis=0, return_inverse=True)
+            designs, inv = np.unique(th[sel_all], axis=0, return_inverse=True)
             scene = B.Scene.from_mesh(mesh)
             group = np.asarray(mesh.group)
             for k, dsg in enumerate(designs):
-                sel = idx[inv.ravel() == k]
+                sel = sel_all[inv.ravel() == k]
                 scene.set_design(dsg[2 + 2 * group].astype(np.float32), dsg[3 + 2 * group].astype(np.float32),
                                  hinge_angles=dsg[:2])
-                Ft, _ = scene.trace(np.asarray(sun).reshape(-1, 3)[sel], params)
-                F[sel] = Ft.cpu().numpy()
+                Ft, _ = scene.trace(sun[sel], params)
+                F.index_copy_(0, torch.as_tensor(sel, device="cuda"), Ft.to(torch.float32))
             scene.close()
         return F, fall

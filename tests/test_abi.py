@@ -63,3 +63,21 @@ def test_every_exported_entry_point_is_declared():
     exported = {n for n in exported if n.startswith("srp_")}
     undeclared = sorted(exported - declared_functions())
     assert not undeclared, undeclared
+
+
+def test_ray_mask_bits_layout():
+    """ray_mask_bits packs pixel p of direction j into bit p & 31 of word p >> 5 (host-side packing,
+    checked on the CPU)."""
+    lib_path = os.path.join(ROOT, "paper_2602_10712_amd", "libsrp.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("libsrp.so not built")
+    import numpy as np
+    import paper_2602_10712_amd as p
+    rng = np.random.default_rng(0)
+    m = rng.random((3, 70)) < 0.3
+    w = p.ray_mask_bits(m, device="cpu").numpy().view(np.uint32)
+    assert w.shape == (3, 3)
+    for j in range(3):
+        for q in range(96):
+            bit = (int(w[j, q >> 5]) >> (q & 31)) & 1
+            assert bit == (int(m[j, q]) if q < 70 else 0)

@@ -90,7 +90,8 @@ def test_full_size_batch_sampled():
         assert e <= 1e-9
         assert rel_l2(T[k].cpu().numpy(), Ts.cpu().numpy()) <= 1e-9
     sc, m, rs, rd = built[small][0], built[small][1], built[small][2], built[small][3]
-    V = sc.vertices()
+    V = apply_hinges(m.verts, m.vert_hinge, m.hinge_origin, m.hinge_axis, dsg[small][:2])
+    assert np.allclose(sc.vertices(), V, rtol=0, atol=1e-12)
     for j in (17, 190):
         ref = oracle.trace(V, m.tris, rs, rd, sun[j:j + 1], nu=G, nv=G, bounces=3, seed=2, dir_index_base=j,
                            design_index=small)

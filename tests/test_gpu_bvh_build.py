@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 import srp_inputs as si
+from oracle.design import apply_hinges
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -73,7 +74,9 @@ def test_gpu_tree_gives_identical_traces(full):
     Fb, _ = b.trace(sun, prm)
     assert torch.equal(Fa, Fb)
     if not full:
-        ref = oracle.trace(b.vertices(), m.tris, rs, rd, sun[:4], nu=256, nv=256, bounces=3, seed=31)
+        V = apply_hinges(m.verts, m.vert_hinge, m.hinge_origin, m.hinge_axis, [-0.3, 0.2])
+        assert np.allclose(b.vertices(), V, rtol=0, atol=1e-12)
+        ref = oracle.trace(V, m.tris, rs, rd, sun[:4], nu=256, nv=256, bounces=3, seed=31)
         rel = np.linalg.norm(Fb.cpu().numpy()[:4] - ref.force) / np.linalg.norm(ref.force)
         assert rel <= 1e-4
     a.close()
@@ -107,3 +110,104 @@ def test_gpu_build_small_mesh_refused():
         p.srp_scene_build_gpu(sc)
     assert e.value.status == -5
     sc.close()
+
+
+def _warp(V):
+    """A smooth deformation close to the identity (no facet collapses)."""
+    return V + 0.03 * np.stack([np.sin(1.3 * V[:, 1]), np.sin(0.7 * V[:, 2]), np.sin(0.9 * V[:, 0])], 1)
+
+
+@pytest.mark.parametrize("gpu_tree", [False, True])
+def test_device_refit_matches_a_fresh_build(gpu_tree):
+    """A hinge change refits the boxes of the kept tree on the device (SAH tree from the host, or
+    the GPU-built tree): traces and hit records are bit-identical to a scene built from scratch on
+    the rotated vertices, whose closest hits do not depend on the tree."""
+    import dataclasses
+    import paper_2602_10712_amd as p
+    m = si.meo_satellite()
+    rs, rd = si.materials(m.n_tris, 6)
+    ang = [0.45, -0.6]
+    a = p.Scene.from_mesh(m)
+    if gpu_tree:
+        a.build_gpu()
+    a.set_design(rs, rd, hinge_angles=ang)
+    V = apply_hinges(m.verts, m.vert_hinge, m.hinge_origin, m.hinge_axis, ang)
+    c = p.Scene.from_mesh(dataclasses.replace(m, verts=V))
+    c.set_design(rs, rd)
+    assert np.array_equal(a.vertices(), c.vertices())
+    sun = si.fibonacci_dirs(32)
+    prm = p.TraceParams(nu=256, nv=256, bounces=3, seed=17)
+    Fa, Ta = a.trace(sun, prm)
+    Fc, Tc = c.trace(sun, prm)
+    assert torch.equal(Fa, Fc) and torch.equal(Ta, Tc)
+    pix = np.arange(0, 256 * 256, 29)
+    ha, fa = records(a, sun, prm, pix)
+    hc, fc = records(c, sun, prm, pix)
+    assert np.array_equal(ha, hc) and np.array_equal(fa, fc)
+    a.close()
+    c.close()
+
+
+def test_set_vertices_refit_and_rebuild():
+    """srp_scene_set_vertices: a new rest pose under the same hinge angles and materials, with the
+    tree refitted on the device or rebuilt on the host, traces bit-identically to a scene created
+    from the new pose; the oracle agrees on a small mesh; bad input leaves the scene as it was."""
+    import dataclasses
+    import paper_2602_10712_amd as p
+    for full in (True, False):
+        if full:
+            m = si.meo_satellite()
+        else:
+            m = si.meo_satellite(bus_n=6, cyl_sides=16, panel_n=4, dish_rings=8, dish_sectors=16, strut_sides=6)
+        rs, rd = si.materials(m.n_tris, 8)
+        ang = [0.2, -0.35]
+        W = _warp(m.verts)
+        c = p.Scene.from_mesh(dataclasses.replace(m, verts=W))
+        c.set_design(rs, rd, hinge_angles=ang)
+        sun = si.fibonacci_dirs(16)
+        prm = p.TraceParams(nu=256, nv=256, bounces=3, seed=23)
+        Fc, Tc = c.trace(sun, prm)
+        for rebuild in (False, True):
+            a = p.Scene.from_mesh(m)
+            a.set_design(rs, rd, hinge_angles=ang)
+            a.set_vertices(W, rebuild=rebuild)
+            assert np.array_equal(a.vertices(), c.vertices())
+            Fa, Ta = a.trace(sun, prm)
+            assert torch.equal(Fa, Fc) and torch.equal(Ta, Tc), (full, rebuild)
+            # the hinge angles stay applied on top of the new rest pose
+            a.set_design(rs, rd, hinge_angles=[0.0, 0.0])
+            assert np.allclose(a.vertices(), W, rtol=0, atol=1e-12)
+            a.close()
+        if not full:
+            Vw = apply_hinges(W, m.vert_hinge, m.hinge_origin, m.hinge_axis, ang)
+            assert np.allclose(c.vertices(), Vw, rtol=0, atol=1e-12)
+            ref = oracle.trace(Vw, m.tris, rs, rd, sun[:4], nu=256, nv=256, bounces=3, seed=23)
+            rel = np.linalg.norm(Fc.cpu().numpy()[:4] - ref.force) / np.linalg.norm(ref.force)
+            assert rel <= 1e-4
+        c.close()
+    # errors: size, mode, a non-finite vertex, a collapsed facet; the scene keeps its geometry
+    a = p.Scene.from_mesh(m)
+    a.set_design(rs, rd, hinge_angles=ang)
+    V0 = a.vertices()
+    F0, _ = a.trace(sun, prm)
+    with pytest.raises(p.SRPError) as e:
+        a.set_vertices(W[:-1])
+    assert e.value.status == -1
+    with pytest.raises(p.SRPError) as e:
+        p.srp_scene_set_vertices(a.handle, W, mode=2)
+    assert e.value.status == -1
+    bad = W.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(p.SRPError) as e:
+        a.set_vertices(bad)
+    assert e.value.status == -4
+    bad = W.copy()
+    t0 = m.tris[3]
+    bad[t0[1]] = bad[t0[0]]
+    with pytest.raises(p.SRPError) as e:
+        a.set_vertices(bad, rebuild=True)
+    assert e.value.status == -4
+    assert np.array_equal(a.vertices(), V0)
+    F1, _ = a.trace(sun, prm)
+    assert torch.equal(F0, F1)
+    a.close()

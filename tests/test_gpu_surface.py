@@ -16,6 +16,7 @@ import pytest
 
 import oracle
 import srp_inputs as si
+from oracle.design import apply_hinges
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -45,10 +46,10 @@ def run(scenes, sun, n, params, brute, records=True):
     return out
 
 
-def check_records(g, ref, bounces, min_ok=0.95):
+def check_records(g, ref, bounces, min_ok=0.99):
     """Records identical on every sample the oracle does not flag; samples start on the surface, so
-    their shadow and gathering rays often begin within the 1e-5 L edge band of a neighbouring facet
-    (flagged); the flagged ones that still agree are reported."""
+    their shadow and gathering rays sometimes begin within the position uncertainty of a
+    neighbouring facet's edge (flagged); the flagged ones that still agree are reported."""
     ok = ref.degen == 0
     assert ok.mean() > min_ok, f"degenerate fraction {1 - ok.mean():.4f}"
     assert np.array_equal(g["facet"][ok], ref.facet[ok])
@@ -94,7 +95,8 @@ def test_meo_small_bvh_equals_brute_and_oracle():
     rs, rd = si.materials(m.n_tris, 3)
     th = np.array([0.2, -0.3])
     sc = make(m, rs, rd, th)
-    V = sc.vertices()
+    V = apply_hinges(m.verts, m.vert_hinge, m.hinge_origin, m.hinge_axis, th)
+    assert np.allclose(sc.vertices(), V, rtol=0, atol=1e-12)
     sun = si.fibonacci_dirs(6)
     n = 1000  # not a multiple of the 256-sample workgroup
     prm = p.TraceParams(bounces=3, seed=22, design_index=4)
@@ -161,7 +163,7 @@ def test_full_size_meo_records_match_oracle():
     k = 512
     ref = oracle.surface_estimate(m.verts, m.tris, rs, rd, sun, n_samples=k, bounces=3, seed=24, records=True)
     sub = {key: g[key][0][:, :k] for key in ("facet", "lit", "hits")}
-    deg = check_records(sub, ref, 3, min_ok=0.85)  # 1 cm antenna facets and dish slivers: many samples near edges
+    deg = check_records(sub, ref, 3, min_ok=0.98)  # 1 cm antenna facets and dish slivers (measured 0.8 % flagged)
     print(f"full size: degenerate {deg:.4f}")
     assert np.all(np.isfinite(g["F"])) and np.abs(g["F"]).max() > 0
     sc.close()
@@ -173,7 +175,8 @@ def test_sampling_options_match_oracle(sampling):
     m = si.meo_satellite(bus_n=6, cyl_sides=16, panel_n=4, dish_rings=8, dish_sectors=16, strut_sides=6)
     rs, rd = si.materials(m.n_tris, 3)
     sc = make(m, rs, rd, [0.1, 0.2])
-    V = sc.vertices()
+    V = apply_hinges(m.verts, m.vert_hinge, m.hinge_origin, m.hinge_axis, [0.1, 0.2])
+    assert np.allclose(sc.vertices(), V, rtol=0, atol=1e-12)
     sun = si.fibonacci_dirs(5)
     n = 1500  # ragged: not a multiple of the 256-sample workgroup
     prm = p.TraceParams(bounces=3, seed=25, design_index=2, sampling=sampling)

@@ -96,7 +96,7 @@ def test_meo_small_hits_and_force(bounces):
     torch.cuda.synchronize()
     orc = oracle.trace(V_ref, m.tris, rs, rd, sun, nu=nu, nv=nv, bounces=bounces, seed=7, records=True)
     frac = check_hits(hp.cpu().numpy(), orc, f"meo B={bounces}")
-    assert frac < 0.03
+    assert frac < 4e-3  # segments on or after a flagged one (measured 1.8e-3 at 3 bounces)
     eF, eT = rel_l2(F.cpu().numpy(), orc.force), torque_err(T.cpu().numpy(), orc.torque, orc.force, V_ref)
     print(f"meo B={bounces} force rel L2 {eF:.3e} torque err {eT:.3e}")
     assert eF <= 1e-4 and eT <= 1e-4
