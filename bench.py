@@ -257,6 +257,32 @@ def main():
             log(f"adjoint roofline stats unavailable: {e!r}")
         log(f"forward+adjoint: {ms_adj:.2f} ms/step, {fwd_adj['value']:.1f} Mrays/s")
 
+        # the two halves alone, and the adjoint with the visibility-edge part of the hinge gradient
+        # (edge sampling: 16 points per moving edge and direction, two side paths each)
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(args.steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / args.steps
+
+        pe = p.TraceParams(nu=g, nv=g, bounces=args.bounces, jitter=1, seed=2, edge_samples=16)
+        ms_f = timed(lambda: p.srp_trace(sc.handle, sun_d, pa, F, T, stream=stream.cuda_stream))
+        ms_b = timed(lambda: p.srp_trace_adjoint(sc.handle, sun_d, pa, gF, gT, g_rs, g_rd, g_h,
+                                                 stream=stream.cuda_stream))
+        ms_e = timed(lambda: p.srp_trace_adjoint(sc.handle, sun_d, pe, gF, gT, g_rs, g_rd, g_h,
+                                                 stream=stream.cuda_stream))
+        fwd_adj["forward_ms"] = round(ms_f, 3)
+        fwd_adj["adjoint_ms"] = round(ms_b, 3)
+        fwd_adj["adjoint_over_forward"] = round(ms_b / ms_f, 3)
+        fwd_adj["edge_term"] = {"edge_samples": 16, "adjoint_ms_with_edges": round(ms_e, 3),
+                                "edge_ms": round(ms_e - ms_b, 3)}
+        log(f"forward {ms_f:.2f} ms, adjoint {ms_b:.2f} ms ({ms_b / ms_f:.2f}x), adjoint with edge terms "
+            f"{ms_e:.2f} ms")
+
     # ---- design gradient through the orbit: 1 day of 60 s RK4 steps, 2881 stage-time sun directions ----
     orbit = None
     if not args.no_orbit:
@@ -283,6 +309,25 @@ def main():
                              f"{args.adjoint_grid}x{args.adjoint_grid} rays, RK4 over 1440 x 60 s steps, discrete "
                              "adjoint with 24 checkpoints, ray adjoint, group sums (host wall clock)"}
         log(f"orbit: {ms_o:.1f} ms per design-gradient iteration ({n_st} directions)")
+        # the same iteration with the two-network surrogate answering the force at every stage time
+        # (the proxy inside the ODE): ensemble inference, RK4, orbit adjoint, the networks' input
+        # gradients.  Networks of the benchmark's shape; the time does not depend on their weights.
+        nets = [p.Surrogate(11, 256, 4, 3, seed=7 + s) for s in range(2)]
+        sp = p.SurrogateDesignProblem(mesh, sc_o, nets, 1361.0 * 20.0 / 299792458.0, si.DESIGN_LO, si.DESIGN_HI,
+                                      r_target=prob.r_target)
+        for i in range(max(args.warmup, 1)):
+            sp.loss_and_grad(theta - step_h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            sp.loss_and_grad(theta + i * step_h)
+        torch.cuda.synchronize()
+        ms_so = (time.perf_counter() - t0) * 1e3 / args.steps
+        orbit["surrogate_ms_per_iteration"] = round(ms_so, 2)
+        orbit["surrogate_speedup"] = round(ms_o / ms_so, 1)
+        log(f"orbit with the surrogate: {ms_so:.2f} ms per iteration ({ms_o / ms_so:.0f}x)")
+        for net_o in nets:
+            net_o.close()
         prob.close()
 
     # ---- surrogate inference: fused BF16-MFMA MLP 11 -> 4 x 256 (SiLU) -> 3 on 1M queries ---------
@@ -311,6 +356,29 @@ def main():
                      "batch": nq, "roofline": {"bound": "mfma", "achieved": round(tf, 1), "peak": 2500.0,
                                                "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4)}}
         log(f"surrogate: {ms_s:.3f} ms per {nq} queries, {nq / ms_s / 1e6:.3f} G evals/s, {tf:.1f} TFLOP/s")
+        # the ensemble as the pipeline calls it: both networks, their mean, the disagreement and
+        # domain test and the compaction of the failing queries (srp_mlp_ensemble), one call
+        net_b = p.Surrogate(11, 256, 4, 3, seed=1)
+        y_e = torch.empty((nq, 3), dtype=torch.float32, device=dev)
+        idx_e = torch.empty(nq, dtype=torch.int32, device=dev)
+        cnt_e = torch.empty(1, dtype=torch.int32, device=dev)
+
+        def ens():
+            p.srp_mlp_ensemble(net.handle, net_b.handle, xq, 0.05, 1.0, y_e, idx_e, cnt_e, stream=stream.cuda_stream)
+
+        for i in range(max(args.warmup, 1)):
+            ens()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(args.steps):
+            ens()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_e = e0.elapsed_time(e1) / args.steps
+        surrogate["ensemble"] = {"value": round(nq / (ms_e * 1e-3), 1), "unit": "evals/s", "ms_per_batch": round(ms_e, 4),
+                                 "note": "two networks + disagreement/domain test + compaction of failing queries"}
+        log(f"ensemble: {ms_e:.3f} ms per {nq} queries, {nq / ms_e / 1e6:.3f} G evals/s")
+        net_b.close()
         # training throughput: one Adam step = forward with kept activations, MSE gradient, backward
         # and the update, on batches of 4096 synthetic samples (the training recipe's batch)
         if not args.no_surrogate_training:
@@ -327,8 +395,9 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             ms_t = e0.elapsed_time(e1) / n_tr
+            tf_t = 3 * 400384 * bt / (ms_t * 1e-3) / 1e12
             surrogate["training"] = {"samples_per_s": round(bt / (ms_t * 1e-3), 1), "ms_per_step": round(ms_t, 4),
-                                     "batch": bt, "tflops": round(3 * 400384 * bt / (ms_t * 1e-3) / 1e12, 1)}
+                                     "batch": bt, "tflops": round(tf_t, 2), "frac_of_bf16_peak": round(tf_t / 2500.0, 4)}
             log(f"surrogate training: {ms_t:.3f} ms per Adam step of {bt} samples, {bt / ms_t / 1e3:.2f} M samples/s")
         net.close()
 
@@ -616,7 +685,8 @@ def main():
         idx = np.linspace(0, D - 1, n_s).astype(int)
         # the host share of one GPU is 16 cores whatever the machine reports
         cores = max(1, min(16, len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16"))))
-        V = sc.vertices()
+        from oracle.design import apply_hinges
+        V = apply_hinges(mesh.verts, mesh.vert_hinge, mesh.hinge_origin, mesh.hinge_axis, angles)
         t0 = time.perf_counter()
         for k, j in enumerate(idx):
             oracle.trace(V, mesh.tris, rs, rd, sun[j:j + 1], nu=g_s, nv=g_s, bounces=args.bounces, seed=2,

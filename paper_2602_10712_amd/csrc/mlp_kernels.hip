@@ -285,12 +285,14 @@ __global__ void k_wgrad_reduce(ReduceArgs r)
     if (j < nw) {
         const float* p = r.part + r.part_off[l] + j;
         float s = 0.0f;
+#pragma unroll 8
         for (int z = 0; z < S; ++z) s += p[static_cast<int64_t>(z) * nw];
         r.grad[r.w_off[l] + j] += s;
     } else {
         const int64_t m = j - nw;
         const float* p = r.bpart + r.bpart_off[l] + m;
         float s = 0.0f;
+#pragma unroll 8
         for (int z = 0; z < S; ++z) s += p[static_cast<int64_t>(z) * r.fout[l]];
         r.grad[r.b_off[l] + m] += s;
     }

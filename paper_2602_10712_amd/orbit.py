@@ -57,11 +57,9 @@ class DesignProblem:
         d = z[:3] - self.r_target
         return float(d @ d)
 
-    def loss_and_grad(self, theta):
-        theta = np.asarray(theta, dtype=np.float64)
-        z, F = self.final_state(theta)
-        d = z[:3] - self.r_target
-        g_final = np.concatenate([2.0 * d, np.zeros(3)])
+    def design_grad(self, theta, F, g_final):
+        """d(g_final . z_N)/d theta for the forces F of design theta: the RK4 adjoint (checkpointed)
+        chained into the ray adjoint and summed per group."""
         gF, _ = B.srp_orbit_rk4_adjoint(self.sc.z0, self.sc.mu, self.sc.mass, self.sc.dt, self.sc.n_steps, F,
                                         self.sc.R, g_final, self.ckpt_every)
         g_rs, g_rd, g_h = self.scene.adjoint(self.sun, self.params, gF)
@@ -73,7 +71,21 @@ class DesignProblem:
             m = self.group == k
             grad[2 + 2 * k] = g_rs[m].sum()
             grad[3 + 2 * k] = g_rd[m].sum()
-        return float(d @ d), grad
+        return grad
+
+    def loss_and_grad(self, theta):
+        theta = np.asarray(theta, dtype=np.float64)
+        z, F = self.final_state(theta)
+        d = z[:3] - self.r_target
+        return float(d @ d), self.design_grad(theta, F, np.concatenate([2.0 * d, np.zeros(3)]))
+
+    def miss_and_jacobian(self, theta):
+        """The final-position miss r = r_N - r_target [3] and its Jacobian dr/d theta [3][8]: one
+        forward pass and one adjoint pass per position component."""
+        theta = np.asarray(theta, dtype=np.float64)
+        z, F = self.final_state(theta)
+        J = np.stack([self.design_grad(theta, F, np.eye(6)[i]) for i in range(3)])
+        return z[:3] - self.r_target, J
 
     def clip(self, theta):
         th = np.clip(theta, self.lo, self.hi)
@@ -106,6 +118,39 @@ class DesignProblem:
             if callback:
                 callback(t, L, theta)
         hist.append(self.loss(theta))
+        return theta, hist
+
+    def optimise_lm(self, theta0, iters=10, max_step=0.15, lam=1e-3, free=None, callback=None):
+        """Levenberg-Marquardt on the three components of the final-position miss.  In parameters
+        scaled to their ranges the step is the damped minimum-norm solution
+        ds = -Js^T (Js Js^T + lam tr(Js Js^T)/3 I)^-1 r (three residuals, up to eight parameters),
+        capped at max_step of each range and clipped to the bounds.  A step that lowers the loss is
+        taken and the damping divided by 3; otherwise the damping is multiplied by 10.  Returns
+        (theta, history of losses of the accepted points)."""
+        theta = self.clip(np.asarray(theta0, dtype=np.float64))
+        mask = np.ones(8) if free is None else np.asarray(free, dtype=np.float64)
+        scale = (self.hi - self.lo) * mask
+        r, J = self.miss_and_jacobian(theta)
+        L = float(r @ r)
+        hist = [L]
+        for t in range(1, iters + 1):
+            Js = J * scale
+            A = Js @ Js.T
+            ds = -Js.T @ np.linalg.solve(A + lam * np.trace(A) / 3.0 * np.eye(3), r)
+            big = np.abs(ds).max()
+            if big > max_step:
+                ds *= max_step / big
+            th_new = self.clip(theta + ds * scale)
+            r_new, J_new = self.miss_and_jacobian(th_new)
+            L_new = float(r_new @ r_new)
+            if L_new < L:
+                theta, r, J, L = th_new, r_new, J_new, L_new
+                lam = max(lam / 3.0, 1e-9)
+                hist.append(L)
+            else:
+                lam *= 10.0
+            if callback:
+                callback(t, L, theta)
         return theta, hist
 
     def close(self):
@@ -150,12 +195,8 @@ class SurrogateDesignProblem(DesignProblem):
                            self._cnt)
         return self._y.cpu().numpy().astype(np.float64)
 
-    def loss_and_grad(self, theta):
-        theta = np.asarray(theta, dtype=np.float64)
+    def design_grad(self, theta, F, g_final):
         x = self.inputs(theta)
-        z, F = self.final_state(theta)
-        d = z[:3] - self.r_target
-        g_final = np.concatenate([2.0 * d, np.zeros(3)])
         gF, _ = B.srp_orbit_rk4_adjoint(self.sc.z0, self.sc.mu, self.sc.mass, self.sc.dt, self.sc.n_steps, F,
                                         self.sc.R, g_final, self.ckpt_every)
         # F = f_ref (y_a + y_b) / 2: each network receives dL/dy = f_ref / 2 dL/dF
@@ -167,8 +208,7 @@ class SurrogateDesignProblem(DesignProblem):
             B.srp_mlp_backward(net.handle, g_y, gx)
             B.srp_mlp_zero_grad(net.handle)
             g_x += gx.cpu().numpy().astype(np.float64)
-        grad = g_x[:, 3:].sum(0) * 2.0 / (self.hi - self.lo)
-        return float(d @ d), grad
+        return g_x[:, 3:].sum(0) * 2.0 / (self.hi - self.lo)
 
     def close(self):
         pass

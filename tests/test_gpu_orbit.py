@@ -62,9 +62,11 @@ def test_group_gradient_vs_central_differences():
 
 
 def test_optimise_to_hidden_design():
-    """The six group reflectances (exact gradients) are optimised from a uniform start toward a
-    hidden design's end point with the hinge angles held at the hidden values; then all eight
-    parameters from zero hinge angles, the hinge gradients with their visibility-edge part."""
+    """The six group reflectances (exact gradients) are optimised by Adam from a uniform start
+    toward a hidden design's end point with the hinge angles held at the hidden values; then all
+    eight parameters from zero hinge angles by Levenberg-Marquardt on the three components of the
+    miss (their Jacobian rows from three adjoint passes, the hinge rows with their visibility-edge
+    part) to within 0.1 m."""
     prob = _problem(720, 128)
     theta_star = np.array([0.3, -0.2, 0.35, 0.1, 0.2, 0.3, 0.05, 0.4])
     prob.r_target = prob.final_state(theta_star)[0][:3]
@@ -76,6 +78,9 @@ def test_optimise_to_hidden_design():
     assert hist[-1] <= 1e-2 * L0
     theta1 = np.array([0.0, 0.0, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25])
     L1 = prob.loss(theta1)
-    theta, hist = prob.optimise(theta1, iters=40)
-    print(f"all eight: miss distance {np.sqrt(L1):.3f} m -> {np.sqrt(hist[-1]):.4f} m; theta {np.round(theta, 3)}")
+    theta, hist = prob.optimise_lm(theta1, iters=10)
+    print(f"all eight: miss distance {np.sqrt(L1):.3f} m -> {np.sqrt(hist[-1]):.4f} m in {len(hist) - 1} accepted "
+          f"steps; theta {np.round(theta, 3)}")
+    assert np.sqrt(hist[-1]) <= 0.1
+    assert abs(prob.loss(theta) - hist[-1]) <= 1e-12 + 1e-9 * hist[-1]
     prob.close()

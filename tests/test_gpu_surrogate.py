@@ -136,6 +136,45 @@ def test_surrogate_trains_and_beats_tracer_at_matched_error():
     assert np.allclose(Fo[1].double().cpu().numpy(), ref[0, 0], rtol=1e-6)
     sc.close()
 
+    # the proxy inside the ODE (Alg. 1): one design-gradient iteration of the orbit problem with the
+    # ensemble answering the force at every stage time, against the same iteration with the tracer
+    scn = si.meo_orbit(n_steps=240, dt=60.0)
+    theta_c = held[40].copy()
+    delta = np.array([0.0, 0.0, 0.04, -0.04, 0.03, 0.03, -0.03, 0.02])
+    tp = p.DesignProblem(mesh, scn, p.TraceParams(nu=256, nv=256, bounces=3, seed=5), lo, hi)
+    tp.r_target = tp.final_state(theta_c + delta)[0][:3]
+    spb = p.SurrogateDesignProblem(mesh, scn, nets, f_ref, lo, hi, r_target=tp.r_target)
+    F_t, F_s = tp.forces(theta_c), spb.forces(theta_c)
+    err_f = np.linalg.norm(F_s - F_t) / np.linalg.norm(F_t)
+    L_s, g_s = spb.loss_and_grad(theta_c)
+    L_t, g_t = tp.loss_and_grad(theta_c)
+    # the surrogate's own gradient against central differences of its loss (steps of 4 % of each
+    # reflectance range: the BF16 inputs quantise the network below that)
+    fd = np.zeros(6)
+    for k in range(2, 8):
+        hp, hm = theta_c.copy(), theta_c.copy()
+        hp[k] += 0.02
+        hm[k] -= 0.02
+        fd[k - 2] = (spb.loss(hp) - spb.loss(hm)) / 0.04
+    err_g = np.abs(g_s[2:] - fd).max() / np.abs(fd).max()
+    cos = g_s[2:] @ g_t[2:] / (np.linalg.norm(g_s[2:]) * np.linalg.norm(g_t[2:]))
+    times = {}
+    for name, prob in (("tracer", tp), ("surrogate", spb)):
+        prob.loss_and_grad(theta_c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            prob.loss_and_grad(theta_c)
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) / 5
+    print(f"orbit iteration (481 stage times, 256^2 tracer): forces {err_f:.4f} apart; loss tracer {L_t:.4e}, "
+          f"surrogate {L_s:.4e}; reflectance gradient vs its central differences {err_g:.4f}, cosine to the "
+          f"tracer's {cos:.4f}; {times['tracer'] * 1e3:.2f} ms vs {times['surrogate'] * 1e3:.2f} ms per iteration")
+    assert err_f <= 0.02
+    assert err_g <= 0.05
+    assert cos >= 0.9
+    tp.close()
+
 
 def test_ensemble_confidence_call():
     """srp_mlp_ensemble on hand-made queries: the mean is the average of the two networks, the
