@@ -158,6 +158,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
             arr[i] = 0;
         }
         int K = 0;
+        int touched = 0;  // bit h: the path has met a facet that hinge h turns
         int term_f = -1;
         float term_s = 0.0f, term_d = 0.0f;
         // hinge tangents: origin Od, direction Dd, accumulated dL
@@ -235,10 +236,13 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
                 ++K;
             }
 
-            // ---- hinge tangents
+            // ---- hinge tangents.  A path that has met no facet of hinge h carries exactly zero
+            // tangents for it and adds a signed zero, so a wave none of whose paths has skips h.
+            if (hid >= 0 && hid < MAXH) touched |= 1 << hid;
 #pragma unroll
             for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h) {
                 if (h >= H) continue;
+                if (wave_ballot((touched >> h) & 1) == 0) continue;
                 float nd[3] = {0.0f, 0.0f, 0.0f}, pd[3] = {0.0f, 0.0f, 0.0f};
                 if (hid == h) {
                     const float* ax = A.hinge_axis[h];

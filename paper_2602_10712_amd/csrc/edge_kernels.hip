@@ -12,8 +12,10 @@
 //              points y -+ delta n (delta = the secondary-ray offset, 1e-5 L) each start a full path
 //              with the same Philox draws (key seed ^ kEdgeKey, counter (e M + m, direction,
 //              bounce, design)), and the lane adds (Phi/c)(len/M) v_n (deposit(y-) - deposit(y+))
-//              contracted with the direction's cotangents to its hinge.  Paths are walked per lane
-//              (the two side points of neighbouring samples diverge after their first hit).
+//              contracted with the direction's cotangents to its hinge.  Paths are walked per lane:
+//              a wave holds the samples of a few edges that can each span the whole panel, so the
+//              union of the nodes its side paths need is large (the wave-coherent walk, tried for
+//              the parallel first segments, took twice as long).
 // k_add_edges  per-direction sums of the workgroup partials, added in a fixed order to the
 //              per-direction hinge sums of the adjoint.
 #include <float.h>
