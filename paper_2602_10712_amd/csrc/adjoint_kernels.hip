@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
     __shared__ float4 s_rect[kCullBoxes];
     __shared__ uint64_t s_live;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t j;
     int32_t blk;
     if (!block_unit(a, a.D, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
@@ -135,9 +135,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
         if (tile >= a.tiles_per_dir) break;
         if (((live >> (m * kWaves + wave)) & 1ull) == 0) continue;
         int64_t pixel, rec;
-        const bool valid = tile_pixel<false>(a, tile, lane, pixel, rec);
-        const int32_t pi = static_cast<int32_t>(pixel % a.nu);
-        const int32_t pk = static_cast<int32_t>(pixel / a.nu);
+        int32_t pi, pk;
+        const bool valid = tile_pixel<false>(a, tile, lane, pixel, rec, pi, pk);
         float o[3], d[3];
         primary_ray(fr, pi, pk, static_cast<uint32_t>(pixel), dir_global, a.design_index, a.seed_lo, a.seed_hi,
                     a.jitter != 0, o, d);

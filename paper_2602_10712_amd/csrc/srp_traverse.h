@@ -319,18 +319,25 @@ __device__ __forceinline__ bool block_unit(const TraceArgs& a, int64_t n_units, 
 // Pixel of lane `lane` in wave tile `tile`: 8 x 8 pixel tiles in row-major order (trace mode) or
 // 64 consecutive entries of an explicit pixel list (records mode).
 template <bool RECORDS>
-__device__ __forceinline__ bool tile_pixel(const TraceArgs& a, int64_t tile, int lane, int64_t& pixel, int64_t& rec)
+__device__ __forceinline__ bool tile_pixel(const TraceArgs& a, int64_t tile, int lane, int64_t& pixel, int64_t& rec,
+                                           int32_t& pi, int32_t& pk)
 {
     if (RECORDS) {
         rec = tile * 64 + lane;
         const bool valid = rec < a.n_pix;
         pixel = valid ? (a.pix ? a.pix[rec] : rec) : 0;
+        pi = static_cast<int32_t>(pixel % a.nu);
+        pk = static_cast<int32_t>(pixel / a.nu);
         return valid;
     }
+    // a grid holds at most 2^31 pixels, so tile and pixel indices fit 32 bits; the tile index is
+    // wave-uniform, so its division runs once per wave
     rec = 0;
-    const int64_t tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int64_t pi = tx * kTileW + (lane & 7), pk = ty * kTileH + (lane >> 3);
-    pixel = pi + pk * a.nu;
+    const uint32_t t = static_cast<uint32_t>(tile), tiles_x = static_cast<uint32_t>(a.tiles_x);
+    const uint32_t tx = t % tiles_x, ty = t / tiles_x;
+    pi = static_cast<int32_t>(tx * kTileW + (lane & 7));
+    pk = static_cast<int32_t>(ty * kTileH + (lane >> 3));
+    pixel = static_cast<int64_t>(pi) + static_cast<int64_t>(pk) * a.nu;
     return pi < a.nu && pk < a.nv;
 }
 

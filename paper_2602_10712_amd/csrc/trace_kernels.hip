@@ -92,7 +92,7 @@ __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNod
                                                 int64_t unit, int32_t blk, TraceLds& L)
 {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const DevFrame fr = a.frames[unit];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
     int* stack = L.stack[wave];
@@ -118,9 +118,8 @@ __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNod
         if (tile >= a.tiles_per_dir) break;
         if (((live >> (m * kWaves + wave)) & 1ull) == 0) continue;
         int64_t pixel, rec;
-        const bool valid = tile_pixel<RECORDS>(a, tile, lane, pixel, rec);
-        const int32_t pi = static_cast<int32_t>(pixel % a.nu);
-        const int32_t pk = static_cast<int32_t>(pixel / a.nu);
+        int32_t pi, pk;
+        const bool valid = tile_pixel<RECORDS>(a, tile, lane, pixel, rec, pi, pk);
         float o[3], d[3];
         primary_ray(fr, pi, pk, static_cast<uint32_t>(pixel), dir_global, design, a.seed_lo, a.seed_hi,
                     a.jitter != 0, o, d);
