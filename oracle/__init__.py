@@ -80,7 +80,7 @@ def lib():
                                        ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, P, P, ctypes.c_int32]
         L.oracle_edge_term.restype = ctypes.c_int
         L.oracle_trace_frozen.restype = ctypes.c_int
-        L.oracle_surface_estimate.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64,
+        L.oracle_surface_estimate.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int64,
                                               ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
                                               ctypes.c_int64, ctypes.c_uint32, P, P, P, P, P, P, P, ctypes.c_int32,
                                               ctypes.c_int32]
@@ -311,15 +311,18 @@ class SurfaceResult:
 
 def surface_estimate(verts, tris, rho_s, rho_d, sun_dirs, *, n_samples: int, bounces: int, flux: float = 1361.0,
                      seed: int = 0, dir_index_base: int = 0, design_index: int = 0, p_spec=None, com=None,
-                     records: bool = False, threads: int | None = None, sampling: int = 0) -> SurfaceResult:
+                     records: bool = False, threads: int | None = None, sampling: int = 0,
+                     phong=None) -> SurfaceResult:
     """FP64 surface-sampling estimate (area-sampled points, path-traced gathering with next-event
     estimation toward the Sun); see srp_oracle.c for the definition.  force/torque: sample means.
-    sampling: bit 0 stratified surface, bit 1 uniform hemisphere directions (plain MC)."""
+    sampling: bit 0 stratified surface, bit 1 uniform hemisphere directions (plain MC).
+    phong: per-facet Phong exponents (>= 1, inf = ideal mirror), None = all mirrors."""
     verts = np.ascontiguousarray(verts, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     rs = np.ascontiguousarray(rho_s, dtype=np.float32)
     rd = np.ascontiguousarray(rho_d, dtype=np.float32)
     ps = None if p_spec is None else np.ascontiguousarray(p_spec, dtype=np.float32)
+    ph = None if phong is None else np.ascontiguousarray(np.broadcast_to(phong, (len(tris),)), dtype=np.float32)
     c = None if com is None else np.ascontiguousarray(com, dtype=np.float64)
     sun = np.ascontiguousarray(sun_dirs, dtype=np.float64).reshape(-1, 3)
     D = len(sun)
@@ -335,7 +338,7 @@ def surface_estimate(verts, tris, rho_s, rho_d, sun_dirs, *, n_samples: int, bou
     if threads is None:
         threads = default_threads()
     st = lib().oracle_surface_estimate(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(rs), _ptr(rd), _ptr(ps),
-                                       _ptr(c), _ptr(sun), D, int(n_samples), int(bounces), float(flux), int(seed),
+                                       _ptr(ph), _ptr(c), _ptr(sun), D, int(n_samples), int(bounces), float(flux), int(seed),
                                        int(dir_index_base), int(design_index), _ptr(force), _ptr(torque), _ptr(fa),
                                        _ptr(hi), _ptr(li), _ptr(dg), _ptr(sf), int(sampling), int(threads))
     if st != 0:

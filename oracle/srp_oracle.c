@@ -217,6 +217,7 @@ typedef struct {
     const float* rho_s;
     const float* rho_d;
     float* p_spec;
+    const float* phong; /* [T] Phong exponents (surface estimator), NULL: every specular event a mirror */
     double com[3];
     double L;  /* scene size (see scene_size) */
 } scene_t;
@@ -1321,22 +1322,30 @@ int oracle_edge_term(const double* verts, int64_t n_verts, const int32_t* tris, 
 /* Every sample picks a facet with probability proportional to its area and a uniform point x */
 /* on it (square-root barycentric mapping), gathers the light arriving at x by path tracing     */
 /* with next-event estimation toward the Sun at every path vertex, and converts it to momentum  */
-/* at x with one sampled outgoing event: with probability p_s a mirror reflection of weight     */
+/* at x with one sampled outgoing event: with probability p_s the specular event of weight      */
 /* rho_s/p_s, else a cosine-distributed direction o of weight rho_d/(1 - p_s).  The sample's    */
 /* force is the total area A times the force density at x; the estimate is the sample mean.    */
+/*                                                                                            */
+/* Materials (the paper's per-face Phong parameters): BRDF rho_d/pi + rho_s (m + 2)/(2 pi)      */
+/* ((r.o)+)^m, r the mirror direction of the arriving light (the modified Phong model of        */
+/* Lafortune and Willems 1994), exponent m >= 1 per facet; m infinite is the ideal mirror.  A   */
+/* specular event samples the lobe about r (BRDF importance sampling: cos(alpha) =               */
+/* u^(1/(m+1)), pdf (m+1)/(2 pi) cos^m alpha), so a lobe direction o carries the weight         */
+/* (m + 2)/(m + 1) (n.o)+ per unit rho_s (0 below the horizon).  Sunlight reflected into a lobe */
+/* is gathered by next-event estimation like the Lambertian share.                             */
 /*                                                                                            */
 /* Light reaching x (force units per area, propagation p, deposit W (p - R(p))):               */
 /*   direct     W = Phi (n.s)/c if n.s > 0 and no sun-facing facet blocks the ray x -> s;       */
 /*   gathered   one cosine-distributed direction w1 about n (pdf cos/pi) leads to the closest   */
-/*              front-facing facet v1; the radiance it sends to x is the Lambertian share of    */
-/*              its own sunlight, rho_d/pi Phi (n1.s)+ (unblocked), plus what it reflects of    */
-/*              light from further vertices v2, ... (event sampled at each vertex: mirror       */
-/*              continuation with weight rho_s/p_s or cosine continuation with rho_d/(1-p_s)),  */
-/*              so W = pi/c * radiance and p = -w1.  Light reaching x has met at most B - 1     */
-/*              surfaces before x: vertices v1 .. v_{B-1}.                                      */
+/*              front-facing facet v1; the radiance it sends to x is the BRDF share of its own  */
+/*              sunlight, (rho_d/pi + lobe toward x) Phi (n1.s)+ (unblocked), plus what it      */
+/*              reflects of light from further vertices v2, ... (event sampled at each vertex:  */
+/*              specular continuation with weight rho_s/p_s times the lobe weight, or cosine    */
+/*              continuation with rho_d/(1-p_s)), so W = pi/c * radiance and p = -w1.  Light    */
+/*              reaching x has met at most B - 1 surfaces before x: vertices v1 .. v_{B-1}.     */
 /* Sunlight whose first reflection is an ideal mirror is not gathered (a delta light seen       */
 /* through a delta reflection has zero probability of being sampled); everything else has the  */
-/* same expectation as the ray-grid estimator with `bounces` = B.                              */
+/* same expectation as the ray-grid estimator with `bounces` = B (which has ideal mirrors only). */
 /*                                                                                            */
 /* Random numbers: Philox counter (sample, global direction, stage, design); stage 0: facet,   */
 /* two barycentric uniforms, the event at x; stage 1: the outgoing direction at x (2) and the   */
@@ -1348,7 +1357,8 @@ int oracle_edge_term(const double* verts, int64_t n_verts, const int32_t* tris, 
 /*                   one sample per 1/N of the total area;                                      */
 /*   sampling bit 1  every sampled direction (outgoing, gathering, continuation) uniform over   */
 /*                   the hemisphere, weighted by 2 cos(theta) -- plain MC; without it, cosine     */
-/*                   sampling (the Lambertian BRDF's importance sampling), weight 1.            */
+/*                   sampling (the Lambertian BRDF's importance sampling), weight 1.  A lobe      */
+/*                   direction is then uniform too, weighted by (m + 2) ((r.o)+)^m (n.o).        */
 /* ========================================================================================== */
 
 /* Sunlight reaching o along -s is blocked by any facet other than `skip` whose outward side
@@ -1425,6 +1435,33 @@ static double hemi_dir(const double n[3], double u1, double u2, int uniform, dou
     return 2.0 * u1;
 }
 
+/* The specular event for light of propagation p at a point with normal n: the outgoing direction
+ * and its weight per unit rho_s.  An ideal mirror (m infinite) reflects into r = p - 2 (p.n) n with
+ * weight 1; a Phong lobe of exponent m draws o about r from (u1, u2) (weight (m + 2)/(m + 1) (n.o)+)
+ * or, with `uniform`, over the hemisphere of n (weight (m + 2) ((r.o)+)^m (n.o)). */
+static double specular_dir(const double p[3], const double n[3], double m, double u1, double u2, int uniform,
+                           double out[3])
+{
+    double r[3];
+    const double pn = dot3(p, n);
+    for (int c = 0; c < 3; ++c) r[c] = p[c] - 2.0 * pn * n[c];
+    if (isinf(m)) {
+        for (int c = 0; c < 3; ++c) out[c] = r[c];
+        return 1.0;
+    }
+    if (uniform) {
+        hemi_dir(n, u1, u2, 1, out);
+        return (m + 2.0) * pow(fmax(0.0, dot3(r, out)), m) * dot3(n, out);
+    }
+    const double ca = pow(u1, 1.0 / (m + 1.0));
+    const double sa = sqrt(fmax(0.0, 1.0 - ca * ca));
+    const double phi = 2.0 * M_PI * u2;
+    double t1[3], t2[3];
+    oracle_basis(r, t1, t2);
+    for (int c = 0; c < 3; ++c) out[c] = sa * cos(phi) * t1[c] + sa * sin(phi) * t2[c] + ca * r[c];
+    return (m + 2.0) / (m + 1.0) * fmax(0.0, dot3(n, out));
+}
+
 typedef struct {
     uint64_t seed;
     uint32_t design_index;
@@ -1469,12 +1506,14 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
     const double* n = S->nrm + 3 * f;
     const double rs = (double)S->rho_s[f], rd = (double)S->rho_d[f];
     const float ps = S->p_spec[f];
-    /* the outgoing event at x */
+    const double mx = S->phong ? (double)S->phong[f] : INFINITY;
+    /* the outgoing event at x: specular (about each arriving contribution's mirror direction,
+       drawn from the same two uniforms) or one cosine direction for all contributions */
     const int uniform = (G->sampling & 2) != 0;
-    const int mirror = (float)u0[3] < ps;
+    const int spec = (float)u0[3] < ps;
     double odir[3];
     const double wo = hemi_dir(n, u1[0], u1[1], uniform, odir);
-    const double kout = mirror ? rs / (double)ps : (rd > 0.0 ? rd / (1.0 - (double)ps) * wo : 0.0);
+    const double kdif = rd > 0.0 ? rd / (1.0 - (double)ps) * wo : 0.0;
     double s[3] = {sun[0], sun[1], sun[2]};
     double dep[3] = {0.0, 0.0, 0.0};
     int32_t lit = 0;
@@ -1487,10 +1526,10 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
         lit |= 1;
         const double W = G->flux * cs / kSpeedOfLight;
         double p[3] = {-s[0], -s[1], -s[2]};
-        double r[3];
-        const double pn = dot3(p, n);
-        for (int c = 0; c < 3; ++c) r[c] = p[c] - 2.0 * pn * n[c];
-        for (int c = 0; c < 3; ++c) dep[c] += W * (p[c] - kout * (mirror ? r[c] : odir[c]));
+        double od[3];
+        double k = kdif;
+        if (spec) k = rs / (double)ps * specular_dir(p, n, mx, u1[0], u1[1], uniform, od);
+        for (int c = 0; c < 3; ++c) dep[c] += W * (p[c] - k * (spec ? od[c] : odir[c]));
     }
     if (rec_hits)
         for (int k = 0; k < B - 1; ++k) rec_hits[k] = -1;
@@ -1517,10 +1556,21 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
                 oy[c] = y[c] + eps * ng[c];
             }
             const double rsg = (double)S->rho_s[g], rdg = (double)S->rho_d[g];
+            const double mg = S->phong ? (double)S->phong[g] : INFINITY;
+            const int lobe = rsg > 0.0 && !isinf(mg);
             const double cg = dot3(ng, s);
-            if (rdg > 0.0 && cg > 0.0 && !sun_blocked(S, oy, s, g, unc, &deg)) {
+            if ((rdg > 0.0 || lobe) && cg > 0.0 && !sun_blocked(S, oy, s, g, unc, &deg)) {
                 lit |= 1 << k;
-                radiance += beta * rdg * cg;
+                double add = rdg * cg;
+                if (lobe) {
+                    /* pi times the lobe's radiance toward the previous vertex (along -rdir) for
+                       sunlight of propagation -s: rho_s (m + 2)/2 ((r.(-rdir))+)^m (n.s) */
+                    const double sn = dot3(s, ng);
+                    double rsun[3];
+                    for (int c = 0; c < 3; ++c) rsun[c] = -s[c] + 2.0 * sn * ng[c];
+                    add += rsg * (mg + 2.0) * 0.5 * pow(fmax(0.0, -dot3(rsun, rdir)), mg) * cg;
+                }
+                radiance += beta * add;
             }
             if (k == B - 1) break;
             /* continue from v_k: event, weight and the next gathering direction */
@@ -1529,11 +1579,9 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
             const float psg = S->p_spec[g];
             double nd[3];
             if ((float)ev[0] < psg) {
-                /* light leaving v_k toward the previous vertex travels along -rdir; its mirror
-                   source direction is the reflection of rdir about the normal, reversed */
-                const double dn = dot3(rdir, ng);
-                for (int c = 0; c < 3; ++c) nd[c] = rdir[c] - 2.0 * dn * ng[c];
-                beta *= rsg / (double)psg;
+                /* light leaving v_k toward the previous vertex travels along -rdir; it comes from
+                   about the reflection of rdir (the lobe is symmetric in its two directions) */
+                beta *= rsg / (double)psg * specular_dir(rdir, ng, mg, ev[1], ev[2], uniform, nd);
             } else {
                 const double wv = hemi_dir(ng, ev[1], ev[2], uniform, nd);
                 beta *= rdg > 0.0 ? rdg / (1.0 - (double)psg) * wv : 0.0;
@@ -1547,10 +1595,10 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
         }
         if (radiance > 0.0) {
             const double W = G->flux * radiance * wg / kSpeedOfLight;
-            double r[3];
-            const double pn = dot3(p1, n);
-            for (int c = 0; c < 3; ++c) r[c] = p1[c] - 2.0 * pn * n[c];
-            for (int c = 0; c < 3; ++c) dep[c] += W * (p1[c] - kout * (mirror ? r[c] : odir[c]));
+            double od[3];
+            double k = kdif;
+            if (spec) k = rs / (double)ps * specular_dir(p1, n, mx, u1[0], u1[1], uniform, od);
+            for (int c = 0; c < 3; ++c) dep[c] += W * (p1[c] - k * (spec ? od[c] : odir[c]));
         }
     }
     double lever[3];
@@ -1616,13 +1664,15 @@ static void* gather_worker(void* argp)
  * oracle_surface_estimate: surface-sampling estimate of the force and torque for n_dirs sun
  * directions, n_samples samples each (sample index = Philox counter word 0).
  *   verts, tris, rho_s, rho_d, p_spec, com, sun_dirs as for oracle_trace;
+ *   phong [n_tris] Phong exponents, each >= 1 or +infinity (ideal mirror); NULL: all mirrors;
  *   force, torque [n_dirs][3]: sample means (N, N m);
  *   optional per-sample records [n_dirs][n_samples] (hits: [.. ][bounces - 1]) and forces [..][3];
  *   sampling: 0..3, the variance-reduction bits above.
  * Samples are summed in chunks of 64, chunk sums in order: independent of the thread count.
  */
 int oracle_surface_estimate(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
-                            const float* rho_s, const float* rho_d, const float* p_spec, const double* com,
+                            const float* rho_s, const float* rho_d, const float* p_spec, const float* phong,
+                            const double* com,
                             const double* sun_dirs, int64_t n_dirs, int64_t n_samples, int32_t bounces, double flux,
                             uint64_t seed, int64_t dir_index_base, uint32_t design_index, double* force,
                             double* torque, int32_t* rec_facet, int32_t* rec_hits, int32_t* rec_lit, uint8_t* rec_deg,
@@ -1633,12 +1683,16 @@ int oracle_surface_estimate(const double* verts, int64_t n_verts, const int32_t*
         return ORC_EINVAL;
     for (int64_t f = 0; f < n_tris; ++f)
         if (!(rho_s[f] >= 0.0f) || !(rho_d[f] >= 0.0f) || rho_s[f] + rho_d[f] > 1.0f) return ORC_EINVAL;
+    if (phong)
+        for (int64_t f = 0; f < n_tris; ++f)
+            if (!(phong[f] >= 1.0f)) return ORC_EINVAL;
     scene_t S;
     int st = scene_init(&S, verts, n_verts, tris, n_tris, rho_s, rho_d, p_spec, com);
     if (st != ORC_OK) {
         scene_free(&S);
         return st;
     }
+    S.phong = phong;
     double* cum = malloc(sizeof(double) * n_tris);
     if (!cum) { scene_free(&S); return ORC_ENOMEM; }
     double acc = 0.0;
