@@ -127,6 +127,18 @@ srp_status srp_scene_create(const double* verts, int64_t n_verts, const int32_t*
 srp_status srp_scene_set_design(srp_scene scene, const double* hinge_angles, const float* rho_s,
                                 const float* rho_d, const float* p_spec, void* stream);
 
+/* Per-face Phong exponents (paper Sec. 3.2, "Estimation": the design maps to a mesh with per-face
+ * Phong material parameters) for the surface-sampling estimator: facet f reflects with the
+ * modified Phong BRDF rho_d/pi + rho_s (m + 2)/(2 pi) ((r.o)+)^m (Lafortune and Willems 1994), r
+ * the mirror direction of the arriving light, m = exponents[f].
+ *   exponents device float [n_tris] (original facet order), each >= 1 or +infinity (the ideal
+ *   mirror), copied; NULL restores ideal mirrors everywhere.
+ * Kept across srp_scene_set_design, GPU rebuilds and srp_scene_set_vertices.  The ray-grid calls
+ * (srp_trace*, srp_trace_adjoint, srp_batch_trace, srp_scene_ray_stats) model ideal mirrors only
+ * and refuse a scene with any finite exponent (SRP_EUNSUPPORTED).  Synchronises `stream`.
+ * Errors: SRP_EINVAL (an exponent below 1 or NaN; the scene keeps its exponents). */
+srp_status srp_scene_set_phong(srp_scene scene, const float* exponents, void* stream);
+
 /* Replaces the rest-pose vertices (paper Sec. 3.1: any design that maps to a mesh of fixed
  * connectivity, e.g. a parametric bus or panel size), keeping the triangles, the hinge
  * assignment, the hinge angles (applied on top of the new rest pose) and the materials.
@@ -243,13 +255,15 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
  * S scenes and D sun directions (device double [D][3]), n_samples samples, each a facet drawn by area
  * and a uniform point on it whose arriving light is gathered by path tracing with next-event
  * estimation toward the Sun at every vertex (at most bounces - 1 gathered vertices), converted to
- * force with one sampled outgoing event (mirror with weight rho_s/p_s, else a cosine direction with
- * rho_d/(1 - p_s)).  force, torque (nullable): device double [S][D][3], sample means.  Scene s uses
+ * force with one sampled outgoing event (specular with weight rho_s/p_s, else a cosine direction with
+ * rho_d/(1 - p_s)).  Specular events follow each facet's Phong lobe (srp_scene_set_phong: the lobe
+ * is importance-sampled about the mirror direction, weight (m + 2)/(m + 1) (n.o)+; sunlight a
+ * gathered vertex reflects into its lobe is added by next-event estimation) or the ideal mirror.  force, torque (nullable): device double [S][D][3], sample means.  Scene s uses
  * Philox design index params->design_index + s; counters (sample, global direction, stage,
  * design).  brute_force = 1 tests every ray against every triangle of its scene (any tree depth);
  * 0 walks each scene's BVH (SRP_EUNSUPPORTED for trees deeper than 24).  Sunlight whose first
  * reflection is an ideal mirror is not gathered (a delta light through a delta reflection); all
- * other light has the expectation of srp_trace with the same `bounces`.  Optional per-sample
+ * other light has the expectation of srp_trace with the same `bounces` (for scenes of mirrors).  Optional per-sample
  * records, device int32: rec_facet [S][D][n_samples] (original facet), rec_lit [S][D][n_samples]
  * (bit 0: x sunlit, bit k: gathered vertex k sunlit; required with rec_facet), rec_hits
  * [S][D][n_samples][bounces - 1] (original facet of each gathered vertex, -1 none).  params: nu,
@@ -258,6 +272,33 @@ srp_status srp_surface_estimate(const srp_scene* scenes, int32_t S, const double
                                 int64_t n_samples, const srp_trace_params* params, int32_t brute_force, double* force,
                                 double* torque, int32_t* rec_facet, int32_t* rec_hits, int32_t* rec_lit,
                                 void* stream);
+
+/* Multi-world surface sampling (paper Sec. 3.2, "Estimation": the samples are drawn over random
+ * designs, so each sample's rays meet a different world and every ray is tested against every
+ * triangle): n_pairs (sun direction, design) pairs, each answered by `samples` samples of the
+ * estimator of srp_surface_estimate on its own design.  A design turns the scene's hinged parts
+ * from the REST pose (srp_scene_create / srp_scene_set_vertices; the scene's own hinge angles,
+ * materials and Phong exponents are not used) and gives every facet the materials of its group.
+ *   facet_group host int32 [n_tris] (original facet order), groups 0 .. n_groups - 1, n_groups <= 64;
+ *   sun_dirs    device double [n_pairs][3];
+ *   designs     device float [n_pairs][n_hinges + 3 n_groups]: the hinge angles (rad), then for
+ *               each group rho_s, rho_d and the Phong exponent (>= 1, +infinity: ideal mirror);
+ *               the specular-sampling probability follows srp_scene_set_design's default rule;
+ *   force, torque (nullable): device double [n_pairs][3], each pair's sample mean;
+ *   records (optional, as for srp_surface_estimate): rec_facet, rec_lit [n_pairs][samples],
+ *   rec_hits [n_pairs][samples][bounces - 1].
+ * Pair i draws the samples that srp_surface_estimate draws for direction index dir_index_base + i
+ * and design index params->design_index (counters (sample, dir_index_base + i, stage, design)).  A
+ * lane turns its rays into each part's rest frame instead of moving the part, so all lanes share
+ * the rest-pose records.  params: bounces, flux, seed, dir_index_base, design_index and sampling
+ * are used.  Uses scene workspace (24 bytes per sample); synchronises `stream` twice (the check of
+ * the designs).  Errors: SRP_EINVAL (sizes, groups, a design's materials out of range or a hinge
+ * angle not finite), SRP_EUNSUPPORTED (more than 4 hinges, or a facet spanning a hinge and the
+ * body). */
+srp_status srp_surface_designs(srp_scene scene, const int32_t* facet_group, int32_t n_groups, const double* sun_dirs,
+                               const float* designs, int64_t n_pairs, int32_t samples,
+                               const srp_trace_params* params, double* force, double* torque, int32_t* rec_facet,
+                               int32_t* rec_hits, int32_t* rec_lit, void* stream);
 
 /* Launch-shape autotuner (not part of the paper's method): traces the given workload once per
  * candidate tiles_per_wave in 8..16 (S == 1: srp_trace of scenes[0]; S > 1: srp_batch_trace), after

@@ -85,6 +85,11 @@ def lib():
                                               ctypes.c_int64, ctypes.c_uint32, P, P, P, P, P, P, P, ctypes.c_int32,
                                               ctypes.c_int32]
         L.oracle_surface_estimate.restype = ctypes.c_int
+        L.oracle_surface_designs.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, ctypes.c_int32, P,
+                                             ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                             ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32,
+                                             ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_surface_designs.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -346,3 +351,46 @@ def surface_estimate(verts, tris, rho_s, rho_d, sun_dirs, *, n_samples: int, bou
     if records and bounces == 1:
         hi = hi[:, :, :0]
     return SurfaceResult(force, torque, fa, hi, li, dg, sf)
+
+
+def surface_designs(verts, tris, vert_hinge, hinge_origin, hinge_axis, group, n_groups, designs, sun, *,
+                    samples: int, bounces: int, flux: float = 1361.0, seed: int = 0, dir_index_base: int = 0,
+                    design_index: int = 0, sampling: int = 0, com=None, records: bool = False,
+                    threads: int | None = None) -> SurfaceResult:
+    """FP64 multi-world surface sampling: pair i (sun[i], designs[i]) applies its hinge angles to the
+    rest pose and its group materials (rho_s, rho_d, Phong exponent per group) and averages
+    `samples` samples with direction index dir_index_base + i (see srp_oracle.c).  force/torque:
+    [N][3] per pair; records [N][samples]."""
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    vh = None if vert_hinge is None else np.ascontiguousarray(vert_hinge, dtype=np.int32)
+    ho = np.ascontiguousarray(hinge_origin, dtype=np.float64).reshape(-1, 3)
+    ha = np.ascontiguousarray(hinge_axis, dtype=np.float64).reshape(-1, 3)
+    ha = np.ascontiguousarray(ha / np.linalg.norm(ha, axis=1)[:, None]) if len(ha) else ha
+    grp = np.ascontiguousarray(group, dtype=np.int32)
+    dsg = np.ascontiguousarray(designs, dtype=np.float64).reshape(len(np.atleast_2d(designs)), -1)
+    sn = np.ascontiguousarray(sun, dtype=np.float64).reshape(-1, 3)
+    N = len(sn)
+    assert dsg.shape == (N, len(ho) + 3 * int(n_groups))
+    c = None if com is None else np.ascontiguousarray(com, dtype=np.float64)
+    force = np.zeros((N, 3))
+    torque = np.zeros((N, 3))
+    fa = hi = li = dg = None
+    if records:
+        fa = np.zeros((N, samples), dtype=np.int32)
+        hi = np.zeros((N, samples, max(bounces - 1, 1)), dtype=np.int32)
+        li = np.zeros((N, samples), dtype=np.int32)
+        dg = np.zeros((N, samples), dtype=np.uint8)
+    if threads is None:
+        threads = default_threads()
+    st = lib().oracle_surface_designs(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(vh), _ptr(ho), _ptr(ha),
+                                      len(ho), _ptr(grp), int(n_groups), _ptr(dsg), _ptr(sn), N, int(samples),
+                                      int(bounces), float(flux), int(seed), int(dir_index_base), int(design_index),
+                                      int(sampling), _ptr(c), _ptr(force), _ptr(torque), _ptr(fa), _ptr(hi), _ptr(li),
+                                      _ptr(dg), int(threads))
+    if st != 0:
+        raise ValueError(f"oracle_surface_designs failed ({st})")
+    if records and bounces == 1:
+        hi = hi[:, :, :0]
+    return SurfaceResult(force, torque, fa, hi, li, dg, None)
+

@@ -1462,6 +1462,18 @@ static double specular_dir(const double p[3], const double n[3], double m, doubl
     return (m + 2.0) / (m + 1.0) * fmax(0.0, dot3(n, out));
 }
 
+/* Whether the specular weight of direction o is nonzero by the model (as opposed to by rounding):
+ * always for the ideal mirror; for a lobe, o above the horizon and, when drawn uniformly, inside
+ * the lobe's half-space r.o > 0. */
+static int lobe_open(const double p[3], const double n[3], double m, int uniform, const double o[3])
+{
+    if (isinf(m)) return 1;
+    double r[3];
+    const double pn = dot3(p, n);
+    for (int c = 0; c < 3; ++c) r[c] = p[c] - 2.0 * pn * n[c];
+    return dot3(n, o) > 0.0 && (!uniform || dot3(r, o) > 0.0);
+}
+
 typedef struct {
     uint64_t seed;
     uint32_t design_index;
@@ -1578,15 +1590,20 @@ static void gather_sample(const scene_t* S, const gather_params_t* G, const doub
             draw4(G->seed, sample, dir_global, (uint32_t)(k + 1), G->design_index, ev);
             const float psg = S->p_spec[g];
             double nd[3];
+            int live;
             if ((float)ev[0] < psg) {
                 /* light leaving v_k toward the previous vertex travels along -rdir; it comes from
                    about the reflection of rdir (the lobe is symmetric in its two directions) */
                 beta *= rsg / (double)psg * specular_dir(rdir, ng, mg, ev[1], ev[2], uniform, nd);
+                live = rsg > 0.0 && lobe_open(rdir, ng, mg, uniform, nd);
             } else {
                 const double wv = hemi_dir(ng, ev[1], ev[2], uniform, nd);
                 beta *= rdg > 0.0 ? rdg / (1.0 - (double)psg) * wv : 0.0;
+                live = rdg > 0.0 && wv > 0.0;
             }
-            if (beta == 0.0) break;
+            /* the path ends where its weight is zero by the model (a zero reflectance, a direction on
+               or below the horizon or outside the lobe), not where a long product underflows */
+            if (!live) break;
             for (int c = 0; c < 3; ++c) {
                 ro[c] = oy[c];
                 rdir[c] = nd[c];
@@ -1734,4 +1751,186 @@ int oracle_surface_estimate(const double* verts, int64_t n_verts, const int32_t*
     free(th); free(J.part_f); free(J.part_t); free(cum);
     scene_free(&S);
     return ORC_OK;
+}
+
+/* ========================================================================================== */
+/* Multi-world surface sampling (paper Sec. 3.2, "Estimation": the samples are drawn over      */
+/* random designs, so each sample's rays meet a different world).  Pair i (a sun direction and */
+/* a design) rotates the panels of the rest-pose mesh by its hinge angles (Rodrigues' formula,  */
+/* FP64, vertex by vertex), gives every facet the materials of its group, and averages K       */
+/* samples of the estimator above with the Philox counter (k, dir_index_base + i, stage,       */
+/* design_index): the same samples the single-design estimator draws for that world when its  */
+/* direction index is dir_index_base + i.                                                      */
+/* ========================================================================================== */
+
+typedef struct {
+    const double* verts;
+    int64_t n_verts;
+    const int32_t* tris;
+    int64_t n_tris;
+    const int32_t* vert_hinge;
+    const double* hinge_origin;
+    const double* hinge_axis;
+    int32_t n_hinges;
+    const int32_t* group;
+    int32_t n_groups;
+    const double* designs; /* [N][H + 3 G] */
+    const double* sun;     /* [N][3] */
+    int64_t n_pairs, samples;
+    int32_t bounces, sampling;
+    double flux;
+    uint64_t seed;
+    int64_t dir_index_base;
+    uint32_t design_index;
+    const double* com;
+    double *force, *torque;
+    int32_t *rec_facet, *rec_hits, *rec_lit;
+    uint8_t* rec_deg;
+    int64_t next;
+    int status;
+    pthread_mutex_t lock;
+} designs_job_t;
+
+/* Vertex positions of one design: every vertex carried by hinge h rotates by its angle about
+ * (origin_h, axis_h), right-hand rule. */
+static void design_vertices(const designs_job_t* J, const double* angles, double* out)
+{
+    for (int64_t v = 0; v < J->n_verts; ++v) {
+        const double* p = J->verts + 3 * v;
+        const int32_t h = J->vert_hinge ? J->vert_hinge[v] : -1;
+        if (h < 0) {
+            for (int c = 0; c < 3; ++c) out[3 * v + c] = p[c];
+            continue;
+        }
+        const double* o = J->hinge_origin + 3 * h;
+        const double* k = J->hinge_axis + 3 * h;
+        const double ct = cos(angles[h]), st = sin(angles[h]);
+        double r[3], kr[3];
+        sub3(p, o, r);
+        cross3(k, r, kr);
+        const double kd = dot3(k, r);
+        for (int c = 0; c < 3; ++c) out[3 * v + c] = o[c] + r[c] * ct + kr[c] * st + k[c] * kd * (1.0 - ct);
+    }
+}
+
+static void* designs_worker(void* argp)
+{
+    designs_job_t* J = (designs_job_t*)argp;
+    const int64_t T = J->n_tris;
+    const int32_t H = J->n_hinges, B = J->bounces;
+    double* V = malloc(sizeof(double) * 3 * J->n_verts);
+    float* rs = malloc(sizeof(float) * T);
+    float* rd = malloc(sizeof(float) * T);
+    float* ph = malloc(sizeof(float) * T);
+    double* cum = malloc(sizeof(double) * T);
+    if (!V || !rs || !rd || !ph || !cum) {
+        pthread_mutex_lock(&J->lock);
+        J->status = ORC_ENOMEM;
+        pthread_mutex_unlock(&J->lock);
+        free(V); free(rs); free(rd); free(ph); free(cum);
+        return NULL;
+    }
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        const int64_t i = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (i >= J->n_pairs) break;
+        const double* dsg = J->designs + (int64_t)i * (H + 3 * J->n_groups);
+        design_vertices(J, dsg, V);
+        for (int64_t f = 0; f < T; ++f) {
+            const double* mg = dsg + H + 3 * J->group[f];
+            rs[f] = (float)mg[0];
+            rd[f] = (float)mg[1];
+            ph[f] = (float)mg[2];
+        }
+        scene_t S;
+        int st = scene_init(&S, V, J->n_verts, J->tris, T, rs, rd, NULL, J->com);
+        if (st != ORC_OK) {
+            scene_free(&S);
+            pthread_mutex_lock(&J->lock);
+            J->status = st;
+            pthread_mutex_unlock(&J->lock);
+            break;
+        }
+        S.phong = ph;
+        double acc = 0.0;
+        for (int64_t f = 0; f < T; ++f) {
+            double cr[3];
+            cross3(S.e1 + 3 * f, S.e2 + 3 * f, cr);
+            acc += 0.5 * sqrt(dot3(cr, cr));
+            cum[f] = acc;
+        }
+        gather_params_t G = {J->seed, J->design_index, B, J->flux, cum, acc, J->sampling, J->samples};
+        double sf[3] = {0.0, 0.0, 0.0}, stq[3] = {0.0, 0.0, 0.0};
+        for (int64_t k = 0; k < J->samples; ++k) {
+            const int64_t rec = i * J->samples + k;
+            double F[3], Tq[3];
+            gather_sample(&S, &G, J->sun + 3 * i, (uint32_t)(J->dir_index_base + i), (uint32_t)k, F, Tq,
+                          J->rec_facet ? J->rec_facet + rec : NULL,
+                          J->rec_hits && B > 1 ? J->rec_hits + rec * (B - 1) : NULL,
+                          J->rec_lit ? J->rec_lit + rec : NULL, J->rec_deg ? J->rec_deg + rec : NULL);
+            for (int c = 0; c < 3; ++c) {
+                sf[c] += F[c];
+                stq[c] += Tq[c];
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            J->force[3 * i + c] = sf[c] / (double)J->samples;
+            J->torque[3 * i + c] = stq[c] / (double)J->samples;
+        }
+        scene_free(&S);
+    }
+    free(V); free(rs); free(rd); free(ph); free(cum);
+    return NULL;
+}
+
+/*
+ * oracle_surface_designs: the surface-sampling estimator for n_pairs (sun direction, design) pairs.
+ *   verts [n_verts][3] rest pose; tris; vert_hinge [n_verts] (-1 rigid, NULL all rigid);
+ *   hinge_origin, hinge_axis [n_hinges][3] (axes of unit length); group [n_tris] in [0, n_groups);
+ *   designs [n_pairs][n_hinges + 3 n_groups]: hinge angles (rad), then per group rho_s, rho_d and
+ *   the Phong exponent (>= 1, or +infinity for the ideal mirror); sun [n_pairs][3];
+ *   samples per pair; com [3] or NULL; force, torque [n_pairs][3]: per-pair sample means;
+ *   optional records [n_pairs][samples] as for oracle_surface_estimate.
+ */
+int oracle_surface_designs(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                           const int32_t* vert_hinge, const double* hinge_origin, const double* hinge_axis,
+                           int32_t n_hinges, const int32_t* group, int32_t n_groups, const double* designs,
+                           const double* sun, int64_t n_pairs, int64_t samples, int32_t bounces, double flux,
+                           uint64_t seed, int64_t dir_index_base, uint32_t design_index, int32_t sampling,
+                           const double* com, double* force, double* torque, int32_t* rec_facet, int32_t* rec_hits,
+                           int32_t* rec_lit, uint8_t* rec_deg, int32_t n_threads)
+{
+    if (!verts || n_verts <= 0 || !tris || n_tris <= 0 || n_hinges < 0 || (n_hinges > 0 && (!hinge_origin ||
+        !hinge_axis)) || !group || n_groups < 1 || !designs || !sun || n_pairs < 0 || samples < 1 || bounces < 1 ||
+        !force || !torque || sampling < 0 || sampling > 3)
+        return ORC_EINVAL;
+    for (int64_t f = 0; f < n_tris; ++f)
+        if (group[f] < 0 || group[f] >= n_groups) return ORC_EINVAL;
+    if (vert_hinge)
+        for (int64_t v = 0; v < n_verts; ++v)
+            if (vert_hinge[v] < -1 || vert_hinge[v] >= n_hinges) return ORC_EINVAL;
+    const int64_t P = n_hinges + 3 * n_groups;
+    for (int64_t i = 0; i < n_pairs; ++i)
+        for (int32_t g = 0; g < n_groups; ++g) {
+            const double* m = designs + i * P + n_hinges + 3 * g;
+            const float a = (float)m[0], b = (float)m[1];
+            if (!(a >= 0.0f) || !(b >= 0.0f) || !(a + b <= 1.0f) || !((float)m[2] >= 1.0f)) return ORC_EINVAL;
+        }
+    designs_job_t J;
+    memset(&J, 0, sizeof(J));
+    J.verts = verts; J.n_verts = n_verts; J.tris = tris; J.n_tris = n_tris; J.vert_hinge = vert_hinge;
+    J.hinge_origin = hinge_origin; J.hinge_axis = hinge_axis; J.n_hinges = n_hinges; J.group = group;
+    J.n_groups = n_groups; J.designs = designs; J.sun = sun; J.n_pairs = n_pairs; J.samples = samples;
+    J.bounces = bounces; J.sampling = sampling; J.flux = flux; J.seed = seed; J.dir_index_base = dir_index_base;
+    J.design_index = design_index; J.com = com; J.force = force; J.torque = torque; J.rec_facet = rec_facet;
+    J.rec_hits = rec_hits; J.rec_lit = rec_lit; J.rec_deg = rec_deg; J.status = ORC_OK;
+    pthread_mutex_init(&J.lock, NULL);
+    if (n_threads < 1) n_threads = 1;
+    pthread_t* th = malloc(sizeof(pthread_t) * n_threads);
+    for (int32_t t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, designs_worker, &J);
+    for (int32_t t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    free(th);
+    pthread_mutex_destroy(&J.lock);
+    return J.status;
 }

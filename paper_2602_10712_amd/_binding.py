@@ -63,6 +63,7 @@ _sigs = {
     "srp_scene_set_design": [P, P, P, P, P, P],
     "srp_scene_get_vertices": [P, P, I64],
     "srp_scene_set_vertices": [P, P, I64, I32, P],
+    "srp_scene_set_phong": [P, P, P],
     "srp_scene_info": [P, P, P, P],
     "srp_frames": [P, P, I64, I32, I32, P, P],
     "srp_trace": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P],
@@ -73,6 +74,7 @@ _sigs = {
     "srp_batch_trace": [P, I32, P, I64, ctypes.POINTER(TraceParams), P, P, P],
     "srp_autotune_tiles_per_wave": [P, I32, P, I64, ctypes.POINTER(TraceParams), ctypes.POINTER(I32), P, P],
     "srp_surface_estimate": [P, I32, P, I64, I64, ctypes.POINTER(TraceParams), I32, P, P, P, P, P, P],
+    "srp_surface_designs": [P, P, I32, P, P, I64, I32, ctypes.POINTER(TraceParams), P, P, P, P, P, P],
     "srp_scene_build_gpu": [P, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
     "srp_scene_destroy": [P],
     "srp_mlp_create": [I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)],
@@ -198,6 +200,12 @@ def srp_scene_set_vertices(scene, verts, mode=0, stream=None):
     _check(_lib.srp_scene_set_vertices(scene, _hptr(v), v.shape[0], int(mode), _stream(stream)))
 
 
+def srp_scene_set_phong(scene, exponents=None, stream=None):
+    import torch
+    _dtype_check(exponents, torch.float32, "exponents")
+    _check(_lib.srp_scene_set_phong(scene, _dptr(exponents), _stream(stream)))
+
+
 def srp_scene_get_vertices(scene, n_verts):
     out = np.zeros((n_verts, 3))
     _check(_lib.srp_scene_get_vertices(scene, _hptr(out), n_verts))
@@ -304,6 +312,24 @@ def srp_surface_estimate(scenes, sun_dirs, n_samples, params: TraceParams, force
                                      _dptr(rec_facet), _dptr(rec_hits), _dptr(rec_lit), _stream(stream)))
 
 
+def srp_surface_designs(scene, facet_group, n_groups, sun_dirs, designs, samples, params: TraceParams, force,
+                        torque=None, rec_facet=None, rec_hits=None, rec_lit=None, stream=None):
+    """Multi-world surface sampling (see srp.h): facet_group host int32 [n_tris]; sun_dirs device
+    double [N][3]; designs device float [N][n_hinges + 3 n_groups]; force/torque device double [N][3]."""
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(designs, torch.float32, "designs")
+    _dtype_check(force, torch.float64, "force")
+    _dtype_check(torque, torch.float64, "torque")
+    for name, t in (("rec_facet", rec_facet), ("rec_hits", rec_hits), ("rec_lit", rec_lit)):
+        _dtype_check(t, torch.int32, name)
+    g = np.ascontiguousarray(facet_group, dtype=np.int32)
+    h = scene.handle if isinstance(scene, Scene) else scene
+    _check(_lib.srp_surface_designs(h, _hptr(g), int(n_groups), _dptr(sun_dirs), _dptr(designs), sun_dirs.shape[0],
+                                    int(samples), ctypes.byref(params), _dptr(force), _dptr(torque), _dptr(rec_facet),
+                                    _dptr(rec_hits), _dptr(rec_lit), _stream(stream)))
+
+
 def srp_autotune_tiles_per_wave(scenes, sun_dirs, params: TraceParams, stream=None):
     """Fastest tiles_per_wave (8..16) for this workload, and every candidate's time in ms (see srp.h).
     One scene tunes srp_trace, several tune srp_batch_trace."""
@@ -383,6 +409,14 @@ class Scene:
 
     def vertices(self):
         return srp_scene_get_vertices(self.handle, self.n_verts)
+
+    def set_phong(self, exponents=None, stream=None):
+        """Per-facet Phong exponents for the surface-sampling estimator (srp_scene_set_phong);
+        None restores ideal mirrors."""
+        import torch
+        ex = None if exponents is None else torch.as_tensor(
+            np.broadcast_to(np.asarray(exponents, dtype=np.float32), (self.n_tris,)).copy(), device="cuda")
+        srp_scene_set_phong(self.handle, ex, stream)
 
     def set_vertices(self, verts, rebuild=False, stream=None):
         """New rest-pose vertices (srp_scene_set_vertices): the tree refitted on the device, or

@@ -90,6 +90,7 @@ extern "C" srp_status srp_scene_ray_stats(srp_scene s, const double* sun_dirs, i
         return srp_fail(SRP_EINVAL, "bad trace parameters");
     if (p->frame_mode == 1 && !frames) return srp_fail(SRP_EINVAL, "frame_mode 1 needs frames");
     if (p->ray_mask) return srp_fail(SRP_EUNSUPPORTED, "ray_mask is not supported by the statistics");
+    if (s->phong_finite) return srp_fail(SRP_EUNSUPPORTED, "Phong lobes are served by srp_surface_estimate only");
     std::vector<float4> mat(s->n_tris);
     if (hipSetDevice(s->device) != hipSuccess || hipMemcpy(mat.data(), s->d_mat, sizeof(float4) * s->n_tris,
                                                            hipMemcpyDeviceToHost) != hipSuccess)

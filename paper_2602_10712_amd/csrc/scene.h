@@ -74,6 +74,19 @@ struct srp_scene_s {
     std::vector<int4> h_edges;
     int4* d_edges = nullptr;
     size_t edges_cap = 0;
+    // multi-world surface sampling: rest-pose records grouped by part (kept while the rest pose and
+    // the facet groups stay the same) and the per-sample output of the last call
+    srp::TriRec* d_mw_tris = nullptr;
+    int32_t* d_mw_pos = nullptr;
+    std::vector<int32_t> mw_groups;      // groups the records were built with (empty: not built)
+    int32_t mw_part_end[srp::kMaxHinges + 1] = {};
+    int32_t mw_part_hinge[srp::kMaxHinges + 1] = {};
+    int32_t mw_n_parts = 0;
+    float* d_mw_samples = nullptr;
+    size_t mw_samples_cap = 0;
+    // Phong exponents of the surface-sampling estimator (original facet order; NULL: ideal mirrors)
+    float* d_phong = nullptr;
+    bool phong_finite = false;  // some facet has a finite lobe (the ray-grid calls refuse the scene)
     float4* d_vpos = nullptr;
     size_t vpos_cap = 0;
     double* d_edge_part = nullptr;       // [D][edge workgroups][kMaxHinges]

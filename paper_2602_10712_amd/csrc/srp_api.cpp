@@ -379,6 +379,8 @@ srp_status prepare_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
                          float* rec_force, hipStream_t stream, srp::TraceArgs& a,
                          const srp::TraceWorkspace* ws = nullptr, float* rec_point = nullptr)
 {
+    if (s->phong_finite)
+        return fail(SRP_EUNSUPPORTED, "Phong lobes are served by srp_surface_estimate only (the ray grid has mirrors)");
     a = srp::TraceArgs{};
     a.ray_mask = p->ray_mask;
     a.mask_words = (static_cast<int64_t>(p->nu) * p->nv + 31) / 32;
@@ -546,6 +548,8 @@ srp_status srp_scene_create(const double* verts, int64_t n_verts, const int32_t*
     e = ensure(s->d_mat, s->mat_cap, static_cast<size_t>(n_tris));
     if (e == hipSuccess) e = hipMemset(s->d_mat, 0, sizeof(float4) * n_tris);
     if (e == hipSuccess) e = ensure(s->d_flag, s->flag_cap, 1);
+    if (e == hipSuccess) e = srp::launch_pack_phong(nullptr, s->d_perm, n_tris, s->d_mat, s->d_flag, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e == hipSuccess) e = upload_edges(s, nullptr);
     if (e != hipSuccess) {
         srp_scene_destroy(s);
@@ -579,13 +583,49 @@ srp_status srp_scene_set_design(srp_scene s, const double* hinge_angles, const f
         }
     }
     SRP_HIP(hipMemsetAsync(s->d_flag, 0, sizeof(int32_t), stream));
-    SRP_HIP(srp::launch_pack_materials(rho_s, rho_d, p_spec, s->d_perm, s->n_tris, s->d_mat, s->d_flag, stream));
+    SRP_HIP(srp::launch_pack_materials(rho_s, rho_d, p_spec, s->d_phong, s->d_perm, s->n_tris, s->d_mat, s->d_flag,
+                                       stream));
     int32_t flag = 0;
     SRP_HIP(hipMemcpyAsync(&flag, s->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     SRP_HIP(hipStreamSynchronize(stream));
     if (flag & 1) return fail(SRP_EINVAL, "reflectances must satisfy rho_s >= 0, rho_d >= 0, rho_s + rho_d <= 1");
     if (flag & 2)
         return fail(SRP_EINVAL, "p_spec must lie in [0, 1], and may be 0 only where rho_s = 0 and 1 only where rho_d = 0");
+    return SRP_OK;
+}
+
+srp_status srp_scene_set_phong(srp_scene s, const float* exponents, void* stream_)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    srp_status st = bind_device(s);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    SRP_HIP(hipStreamSynchronize(stream));  // kernels in flight may still read the materials
+    // a private copy, checked before anything of the scene changes
+    float* staged = nullptr;
+    if (exponents) {
+        SRP_HIP(hipMalloc(reinterpret_cast<void**>(&staged), sizeof(float) * s->n_tris));
+        hipError_t e = hipMemcpyAsync(staged, exponents, sizeof(float) * s->n_tris, hipMemcpyDeviceToDevice, stream);
+        if (e != hipSuccess) {
+            (void)hipFree(staged);
+            return fail(SRP_EDEVICE, std::string("copying the exponents: ") + hipGetErrorString(e));
+        }
+    }
+    int32_t flag = 0;
+    hipError_t e = hipMemsetAsync(s->d_flag, 0, sizeof(int32_t), stream);
+    if (e == hipSuccess) e = srp::launch_pack_phong(staged, s->d_perm, s->n_tris, nullptr, s->d_flag, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, s->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess || (flag & 1)) {
+        (void)hipFree(staged);
+        if (e != hipSuccess) return fail(SRP_EDEVICE, std::string("checking the exponents: ") + hipGetErrorString(e));
+        return fail(SRP_EINVAL, "Phong exponents must be >= 1 (or +infinity for an ideal mirror)");
+    }
+    (void)hipFree(s->d_phong);
+    s->d_phong = staged;
+    s->phong_finite = (flag & 2) != 0;
+    SRP_HIP(srp::launch_pack_phong(s->d_phong, s->d_perm, s->n_tris, s->d_mat, s->d_flag, stream));
+    SRP_HIP(hipStreamSynchronize(stream));
     return SRP_OK;
 }
 
@@ -648,6 +688,7 @@ srp_status srp_scene_set_vertices(srp_scene s, const double* verts, int64_t n_ve
         SRP_HIP(hipStreamSynchronize(stream));
     }
     SRP_HIP(upload_edges(s, stream));
+    s->mw_groups.clear();  // the multi-world records hold the old rest pose
     return SRP_OK;
 }
 
@@ -791,6 +832,8 @@ srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun
     for (int32_t s = 0; s < S; ++s) {
         if (!scenes[s]) return fail(SRP_EINVAL, "NULL scene in the batch");
         if (scenes[s]->device != lead->device) return fail(SRP_EINVAL, "all scenes must live on one device");
+        if (scenes[s]->phong_finite)
+            return fail(SRP_EUNSUPPORTED, "Phong lobes are served by srp_surface_estimate only (the ray grid has mirrors)");
     }
     st = bind_device(lead);
     if (st != SRP_OK) return st;
@@ -1027,6 +1070,149 @@ srp_status srp_surface_estimate(const srp_scene* scenes, int32_t S, const double
     return SRP_OK;
 }
 
+namespace {
+
+// Rest-pose facet records grouped by rigid part (the body, then each hinge) for the multi-world
+// estimator; a facet spanning a hinge and the body (it would stretch, not turn) is refused.
+srp_status build_multiworld(srp_scene_s* s, const int32_t* group)
+{
+    if (!s->mw_groups.empty() && std::equal(s->mw_groups.begin(), s->mw_groups.end(), group)) return SRP_OK;
+    const int64_t T = s->n_tris;
+    std::vector<int32_t> part(static_cast<size_t>(T));
+    for (int64_t f = 0; f < T; ++f) {
+        const int32_t h0 = s->vhinge[s->tris[3 * f]], h1 = s->vhinge[s->tris[3 * f + 1]], h2 = s->vhinge[s->tris[3 * f + 2]];
+        if (h0 != h1 || h1 != h2)
+            return fail(SRP_EUNSUPPORTED, "a facet spans a hinge and the body: its design would stretch it");
+        part[f] = h0 + 1;
+    }
+    const int32_t n_parts = s->n_hinges + 1;
+    std::vector<int32_t> order(static_cast<size_t>(T));
+    for (int64_t f = 0; f < T; ++f) order[f] = static_cast<int32_t>(f);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return part[a] < part[b]; });
+    std::vector<srp::TriRec> recs(static_cast<size_t>(T));
+    std::vector<int32_t> pos(static_cast<size_t>(T));
+    const auto& V = s->rest;
+    for (int64_t q = 0; q < T; ++q) {
+        const int32_t f = order[q];
+        pos[f] = static_cast<int32_t>(q);
+        const double* a = &V[3 * static_cast<int64_t>(s->tris[3 * f])];
+        const double* b = &V[3 * static_cast<int64_t>(s->tris[3 * f + 1])];
+        const double* c = &V[3 * static_cast<int64_t>(s->tris[3 * f + 2])];
+        double e1[3], e2[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = b[k] - a[k];
+            e2[k] = c[k] - a[k];
+        }
+        double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; ++k) n[k] /= len;
+        int32_t fid = f, hid = part[f] - 1, gid = group[f];
+        float fb, hb, gb;
+        std::memcpy(&fb, &fid, 4);
+        std::memcpy(&hb, &hid, 4);
+        std::memcpy(&gb, &gid, 4);
+        srp::TriRec& r = recs[q];
+        r.f[0] = make_float4(static_cast<float>(a[0]), static_cast<float>(a[1]), static_cast<float>(a[2]), fb);
+        r.f[1] = make_float4(static_cast<float>(e1[0]), static_cast<float>(e1[1]), static_cast<float>(e1[2]),
+                             static_cast<float>(n[0]));
+        r.f[2] = make_float4(static_cast<float>(e2[0]), static_cast<float>(e2[1]), static_cast<float>(e2[2]),
+                             static_cast<float>(n[1]));
+        r.f[3] = make_float4(static_cast<float>(n[2]), hb, gb, 0.0f);
+    }
+    if (!s->d_mw_tris) {
+        SRP_HIP(hipMalloc(reinterpret_cast<void**>(&s->d_mw_tris), sizeof(srp::TriRec) * T));
+        SRP_HIP(hipMalloc(reinterpret_cast<void**>(&s->d_mw_pos), sizeof(int32_t) * T));
+    }
+    SRP_HIP(hipMemcpy(s->d_mw_tris, recs.data(), sizeof(srp::TriRec) * T, hipMemcpyHostToDevice));
+    SRP_HIP(hipMemcpy(s->d_mw_pos, pos.data(), sizeof(int32_t) * T, hipMemcpyHostToDevice));
+    s->mw_n_parts = n_parts;
+    for (int32_t q = 0; q < n_parts; ++q) {
+        int32_t end = 0;
+        for (int64_t f = 0; f < T; ++f) end += part[f] <= q ? 1 : 0;
+        s->mw_part_end[q] = end;
+        s->mw_part_hinge[q] = q - 1;
+    }
+    s->mw_groups.assign(group, group + T);
+    return SRP_OK;
+}
+
+}  // namespace
+
+srp_status srp_surface_designs(srp_scene s, const int32_t* facet_group, int32_t n_groups, const double* sun_dirs,
+                               const float* designs, int64_t n_pairs, int32_t samples, const srp_trace_params* p,
+                               double* force, double* torque, int32_t* rec_facet, int32_t* rec_hits, int32_t* rec_lit,
+                               void* stream_)
+{
+    if (!s || !facet_group) return fail(SRP_EINVAL, "scene and facet_group are required");
+    srp_status st = check_params(p);
+    if (st == SRP_OK && p->ray_mask) return fail(SRP_EUNSUPPORTED, "ray_mask is supported by single-scene traces only");
+    if (st != SRP_OK) return st;
+    if (n_groups < 1 || n_groups > 64) return fail(SRP_EINVAL, "n_groups must be in 1..64");
+    if (s->n_hinges > srp::kMaxHinges) return fail(SRP_EUNSUPPORTED, "at most 4 hinges");
+    if (n_pairs < 0 || samples < 1) return fail(SRP_EINVAL, "n_pairs must be >= 0 and samples >= 1");
+    if (n_pairs == 0) return SRP_OK;
+    if (!sun_dirs || !designs || !force) return fail(SRP_EINVAL, "sun_dirs, designs and force are required");
+    if ((rec_hits || rec_lit) && !rec_facet) return fail(SRP_EINVAL, "records need rec_facet");
+    if (rec_facet && !rec_lit) return fail(SRP_EINVAL, "rec_facet needs rec_lit");
+    if (p->dir_index_base + n_pairs > (int64_t(1) << 32)) return fail(SRP_EINVAL, "direction index exceeds 32 bits");
+    if (n_pairs * samples > (int64_t(1) << 40)) return fail(SRP_EINVAL, "too many samples in one call");
+    for (int64_t f = 0; f < s->n_tris; ++f)
+        if (facet_group[f] < 0 || facet_group[f] >= n_groups) return fail(SRP_EINVAL, "facet group out of range");
+    st = bind_device(s);
+    if (st != SRP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    SRP_HIP(hipStreamSynchronize(stream));  // the records and the sample buffer may be in use
+    st = build_multiworld(s, facet_group);
+    if (st != SRP_OK) return st;
+    // materials of every pair in range
+    int32_t flag = 0;
+    SRP_HIP(hipMemsetAsync(s->d_flag, 0, sizeof(int32_t), stream));
+    SRP_HIP(srp::launch_check_designs(designs, n_pairs, s->n_hinges, n_groups, s->d_flag, stream));
+    SRP_HIP(hipMemcpyAsync(&flag, s->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    SRP_HIP(hipStreamSynchronize(stream));
+    if (flag) return fail(SRP_EINVAL, "a design's materials are out of range (rho >= 0, rho_s + rho_d <= 1, exponent >= 1)"
+                                      " or a hinge angle is not finite");
+    SRP_HIP(ensure(s->d_mw_samples, s->mw_samples_cap, static_cast<size_t>(n_pairs * samples * 6)));
+    srp::MwArgs a{};
+    a.base.bounces = p->bounces;
+    a.base.flux_c = static_cast<float>(p->flux / srp::kSpeedOfLight);
+    a.base.seed_lo = static_cast<uint32_t>(p->seed);
+    a.base.seed_hi = static_cast<uint32_t>(p->seed >> 32);
+    a.base.dir_index_base = p->dir_index_base;
+    a.base.design_index = static_cast<uint32_t>(p->design_index);
+    a.base.sampling = p->sampling;
+    a.sc.tris = (decltype(a.sc.tris))s->d_mw_tris;
+    a.sc.pos = (decltype(a.sc.pos))s->d_mw_pos;
+    a.sc.cum_area = (decltype(a.sc.cum_area))s->d_cum_area;
+    a.sc.area = s->area;
+    for (int k = 0; k < 3; ++k) a.sc.com[k] = static_cast<float>(s->com[k]);
+    a.sc.eps = static_cast<float>(1e-5 * s->L);
+    a.sc.n_tris = static_cast<int32_t>(s->n_tris);
+    a.sc.n_parts = s->mw_n_parts;
+    for (int32_t q = 0; q <= srp::kMaxHinges; ++q) {
+        a.sc.part_end[q] = q < s->mw_n_parts ? s->mw_part_end[q] : 0;
+        a.sc.part_hinge[q] = q < s->mw_n_parts ? s->mw_part_hinge[q] : -1;
+    }
+    for (int32_t h = 0; h < srp::kMaxHinges; ++h)
+        for (int k = 0; k < 3; ++k) {
+            a.sc.hinge_origin[h][k] = h < s->n_hinges ? static_cast<float>(s->hinges[h].origin[k]) : 0.0f;
+            a.sc.hinge_axis[h][k] = h < s->n_hinges ? static_cast<float>(s->hinges[h].axis[k]) : 0.0f;
+        }
+    a.sun = sun_dirs;
+    a.designs = designs;
+    a.n_pairs = n_pairs;
+    a.samples = samples;
+    a.n_hinges = s->n_hinges;
+    a.n_groups = n_groups;
+    a.stride = s->n_hinges + 3 * n_groups;
+    a.sample_out = s->d_mw_samples;
+    a.rec_facet = rec_facet;
+    a.rec_hits = p->bounces > 1 ? rec_hits : nullptr;
+    a.rec_lit = rec_lit;
+    SRP_HIP(srp::launch_surface_designs(a, force, torque, stream));
+    return SRP_OK;
+}
+
 srp_status srp_autotune_tiles_per_wave(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
                                        const srp_trace_params* p, int32_t* best, double* ms_out, void* stream_)
 {
@@ -1099,6 +1285,10 @@ srp_status srp_scene_destroy(srp_scene s)
     (void)hipFree(s->d_surf_desc);
     (void)hipFree(s->d_lbvh_ws);
     (void)hipFree(s->d_edges);
+    (void)hipFree(s->d_phong);
+    (void)hipFree(s->d_mw_tris);
+    (void)hipFree(s->d_mw_pos);
+    (void)hipFree(s->d_mw_samples);
     (void)hipFree(s->d_vpos);
     (void)hipFree(s->d_edge_part);
     if (s->surf_ev) {

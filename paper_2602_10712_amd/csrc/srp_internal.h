@@ -23,6 +23,7 @@ static_assert(kMaxTilesPerWave * kWaves <= 64, "the live-tile mask holds one bit
 constexpr int kTilesPerWaveLarge = 15;
 static_assert(kTilesPerWaveLarge <= kMaxTilesPerWave, "within the live-tile mask");
 constexpr int kXcds = 8;           // MI355X: hardware workgroup b runs on accelerator complex b % 8
+constexpr int kMaxHinges = 4;     // hinge-angle gradients (adjoint) and multi-world hinges supported
 constexpr int kLaneStack = 24;     // per-lane stack of the independent walk (trees up to this depth)
 constexpr int kWalkDone = INT32_MIN;  // per-lane walk finished (never a node index or leaf code)
 
@@ -156,6 +157,44 @@ struct SurfaceArgs {
     int32_t* rec_lit;            // [units][n_samples] (with rec_facet)
 };
 
+// Multi-world surface sampling: the rest-pose mesh with its facet records grouped by rigid part
+// (part 0 the body, part q a hinge), each pair's design applied by turning its rays into the
+// parts' rest frames.
+struct MwScene {
+    const SRP_GLOBAL TriRec* tris;     // rest-pose records, grouped by part; f[3].y hinge, f[3].z group
+    const SRP_GLOBAL int32_t* pos;     // original facet -> record
+    const SRP_GLOBAL double* cum_area; // cumulative facet areas, original order
+    double area;
+    float com[3];
+    float eps;
+    int32_t n_tris;
+    int32_t n_parts;
+    int32_t part_end[kMaxHinges + 1];    // exclusive record ends
+    int32_t part_hinge[kMaxHinges + 1];  // -1: the body
+    float hinge_origin[kMaxHinges][3];
+    float hinge_axis[kMaxHinges][3];
+};
+
+struct MwArgs {
+    SurfaceArgs base;      // sampling, bounces, flux_c, seed_lo/hi (per-unit fields unused)
+    MwScene sc;
+    const double* sun;     // [N][3]
+    const float* designs;  // [N][stride]: hinge angles, then per group rho_s, rho_d, Phong exponent
+    int64_t n_pairs;
+    int32_t samples;       // per pair
+    int32_t n_hinges;
+    int32_t n_groups;
+    int32_t stride;
+    float* sample_out;     // [N * samples][6] force and torque of each sample
+    int32_t* rec_facet;    // [N][samples] or null
+    int32_t* rec_hits;     // [N][samples][bounces - 1] or null
+    int32_t* rec_lit;      // [N][samples] (with rec_facet)
+};
+// flags |= 1 for a pair whose materials are out of range (rho < 0, rho_s + rho_d > 1, exponent < 1)
+hipError_t launch_check_designs(const float* designs, int64_t n_pairs, int32_t n_hinges, int32_t n_groups,
+                                int32_t* flags, hipStream_t stream);
+hipError_t launch_surface_designs(const MwArgs& a, double* force, double* torque, hipStream_t stream);
+
 // GPU BVH build (linear BVH): buffers of one build over n >= 2 triangles.
 constexpr int kLbvhLeaf = 4;    // subtrees of at most this many triangles become one leaf
 struct LbvhArgs {
@@ -188,7 +227,6 @@ struct LbvhArgs {
     int32_t* depth_out;             // deepest level (root = 0)
 };
 
-constexpr int kMaxHinges = 4;   // hinge-angle gradients supported by the adjoint
 
 struct AdjointArgs {
     TraceArgs t;                 // geometry, frames and grid of the replayed forward trace
@@ -206,8 +244,12 @@ struct AdjointArgs {
 hipError_t launch_frames(const double* sun_dirs, int64_t D, const double lo[3], const double hi[3], double L,
                          int32_t nu, int32_t nv, double flux, const double* caller_frames, double* frames64,
                          DevFrame* frames32, hipStream_t stream);
-hipError_t launch_pack_materials(const float* rho_s, const float* rho_d, const float* p_spec, const int32_t* perm,
-                                 int64_t n, float4* mat, int32_t* bad_flag, hipStream_t stream);
+hipError_t launch_pack_materials(const float* rho_s, const float* rho_d, const float* p_spec, const float* phong,
+                                 const int32_t* perm, int64_t n, float4* mat, int32_t* bad_flag, hipStream_t stream);
+// Phong exponents (original facet order, NULL: +infinity) into mat[].w (mat NULL: check only);
+// flags |= 1 for an exponent below 1 or NaN, |= 2 when any is finite.
+hipError_t launch_pack_phong(const float* phong, const int32_t* perm, int64_t n, float4* mat, int32_t* flags,
+                             hipStream_t stream);
 hipError_t launch_trace(const TraceArgs& a, bool records, hipStream_t stream);
 hipError_t launch_trace_batch(const TraceArgs& a, hipStream_t stream);
 hipError_t launch_reduce(const double* partials, int64_t D, int32_t blocks_per_dir, double* force, double* torque,

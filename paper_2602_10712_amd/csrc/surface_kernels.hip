@@ -3,11 +3,20 @@
 // One lane evaluates one sample: a facet drawn by area (FP64 search of the cumulative areas in
 // original facet order) and a uniform point x on it (square-root barycentric mapping); the light
 // reaching x is gathered by path tracing with next-event estimation toward the Sun at every path
-// vertex (one cosine-distributed gathering direction at x, then mirror or cosine continuations
-// with weights rho_s/p_s and rho_d/(1 - p_s), up to bounces - 1 vertices); one sampled outgoing
-// event at x (mirror with weight rho_s/p_s, else a cosine direction with rho_d/(1 - p_s)) turns
-// every arriving contribution of power W and propagation p into the deposit W (p - reflected).
-// The sample's force is the total area times that force density.
+// vertex (one cosine-distributed gathering direction at x, then specular or cosine continuations
+// with weights rho_s/p_s (times the lobe weight) and rho_d/(1 - p_s), up to bounces - 1
+// vertices); one sampled outgoing event at x (specular with weight rho_s/p_s, else a cosine
+// direction with rho_d/(1 - p_s)) turns every arriving contribution of power W and propagation p
+// into the deposit W (p - reflected).  The sample's force is the total area times that force
+// density.
+//
+// Materials: the modified Phong BRDF rho_d/pi + rho_s (m + 2)/(2 pi) ((r.o)+)^m (Lafortune and
+// Willems 1994), r the mirror direction of the arriving light, exponent m per facet (mat.w;
+// +infinity is the ideal mirror).  A specular event draws o about r with cos(alpha) =
+// u^(1/(m+1)) (the lobe's importance sampling), weight (m + 2)/(m + 1) (n.o)+ per unit rho_s, or
+// under the plain-MC option uniformly over the hemisphere, weight (m + 2) ((r.o)+)^m (n.o).
+// Sunlight that a gathered vertex reflects into its lobe toward the previous vertex is added by
+// next-event estimation like its Lambertian share.
 //
 // Shadow rays: sunlight reaching a point along -s is blocked by a facet whose outward side faces
 // the Sun (n.s > 0) and that the ray toward the Sun crosses; gathering rays take the closest facet
@@ -190,6 +199,44 @@ __device__ __forceinline__ float hemi_dir(const float n[3], float u1, float u2, 
     return 2.0f * u1;
 }
 
+// The specular event for light of propagation p at a point with normal n: the outgoing direction
+// and its weight per unit rho_s (see the header comment); m = +infinity is the ideal mirror.
+__device__ __forceinline__ float specular_dir(const float p[3], const float n[3], float m, float u1, float u2,
+                                              bool uniform, float out[3])
+{
+    const float pn = p[0] * n[0] + p[1] * n[1] + p[2] * n[2];
+    float r[3];
+    for (int c = 0; c < 3; ++c) r[c] = p[c] - 2.0f * pn * n[c];
+    if (!(m < INFINITY)) {
+        for (int c = 0; c < 3; ++c) out[c] = r[c];
+        return 1.0f;
+    }
+    if (uniform) {
+        hemi_dir(n, u1, u2, true, out);
+        const float ro = fmaxf(0.0f, r[0] * out[0] + r[1] * out[1] + r[2] * out[2]);
+        return (m + 2.0f) * powf(ro, m) * (n[0] * out[0] + n[1] * out[1] + n[2] * out[2]);
+    }
+    const float ca = powf(u1, 1.0f / (m + 1.0f));
+    const float sa = sqrtf(fmaxf(0.0f, 1.0f - ca * ca));
+    float sphi, cphi;
+    sincosf(6.283185307179586f * u2, &sphi, &cphi);
+    float t1[3], t2[3];
+    duff_basis<float>(r, t1, t2);
+    for (int c = 0; c < 3; ++c) out[c] = sa * cphi * t1[c] + sa * sphi * t2[c] + ca * r[c];
+    return (m + 2.0f) / (m + 1.0f) * fmaxf(0.0f, n[0] * out[0] + n[1] * out[1] + n[2] * out[2]);
+}
+
+// Whether the specular weight of direction o is nonzero by the model (not by rounding): always for
+// the ideal mirror; for a lobe, o above the horizon and, when drawn uniformly, with r.o > 0.
+__device__ __forceinline__ bool lobe_open(const float p[3], const float n[3], float m, bool uniform, const float o[3])
+{
+    if (!(m < INFINITY)) return true;
+    const float pn = p[0] * n[0] + p[1] * n[1] + p[2] * n[2];
+    float ro = 0.0f;
+    for (int c = 0; c < 3; ++c) ro += (p[c] - 2.0f * pn * n[c]) * o[c];
+    return n[0] * o[0] + n[1] * o[1] + n[2] * o[2] > 0.0f && (!uniform || ro > 0.0f);
+}
+
 __device__ __forceinline__ void philox_at(uint32_t sample, uint32_t dir, uint32_t stage, uint32_t design,
                                           const SurfaceArgs& a, float u[4])
 {
@@ -201,25 +248,222 @@ __device__ __forceinline__ void philox_at(uint32_t sample, uint32_t dir, uint32_
     u[3] = unit24(c3);
 }
 
-// One sample: force and torque (area applied) and its record.
+// The geometry a sample sees, for one scene in its current pose: facet records in BVH order, the
+// BVH walk or brute force for its rays.
 template <bool BRUTE>
-__device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const SurfaceScene& sc, const float s[3],
+struct SceneGeo {
+    const SurfaceScene& sc;
+    int* __restrict__ lstack;
+    __device__ __forceinline__ double area() const { return sc.area; }
+    __device__ __forceinline__ int n_tris() const { return sc.n_tris; }
+    __device__ __forceinline__ const double* cum() const { return (const double*)sc.cum_area; }
+    __device__ __forceinline__ float eps() const { return sc.eps; }
+    __device__ __forceinline__ const float* com() const { return sc.com; }
+    // record of original facet f
+    __device__ __forceinline__ int position(int f) const { return ((const int32_t*)sc.bvh_pos)[f]; }
+    // point at barycentric (b1, b2) of record p, its outward normal and its material
+    __device__ __forceinline__ void point(int p, float b1, float b2, float x[3], float n[3], float4& mt) const
+    {
+        const TriRec tr = ((const TriRec*)sc.tris)[p];
+        mt = ((const float4*)sc.mat)[p];
+        n[0] = tr.f[1].w;
+        n[1] = tr.f[2].w;
+        n[2] = tr.f[3].x;
+        x[0] = tr.f[0].x + b1 * tr.f[1].x + b2 * tr.f[2].x;
+        x[1] = tr.f[0].y + b1 * tr.f[1].y + b2 * tr.f[2].y;
+        x[2] = tr.f[0].z + b1 * tr.f[1].z + b2 * tr.f[2].z;
+    }
+    // normal, original index and material of record g
+    __device__ __forceinline__ void facet(int g, float ng[3], int& id, float4& mt) const
+    {
+        const TriRec tg = ((const TriRec*)sc.tris)[g];
+        mt = ((const float4*)sc.mat)[g];
+        ng[0] = tg.f[1].w;
+        ng[1] = tg.f[2].w;
+        ng[2] = tg.f[3].x;
+        id = __float_as_int(tg.f[0].w);
+    }
+    __device__ __forceinline__ bool blocked(const float o[3], const float s[3], int skip) const
+    {
+        return sun_blocked<BRUTE>(sc, o, s, skip, lstack);
+    }
+    __device__ __forceinline__ int closest(const float o[3], const float d[3], int skip, float& t) const
+    {
+        return gather_hit<BRUTE>(sc, o, d, skip, t, lstack);
+    }
+};
+
+// The geometry of one pair of the multi-world estimator: the rest-pose records of every rigid part,
+// this lane's hinge angles turning them.  Instead of moving the part, a ray is turned into the part's
+// rest frame (by the inverse rotation about its hinge), so all lanes test the same records -- a
+// wave-uniform loop over every triangle with scalar loads, each lane in its own world.  Points and
+// normals of the part are turned back into the world frame.
+struct MwGeo {
+    const MwScene& sc;
+    float cs[kMaxHinges], sn[kMaxHinges];  // cos and sin of this lane's hinge angles
+    const float* mat;                       // this lane's group materials [3 G]
+    __device__ __forceinline__ double area() const { return sc.area; }
+    __device__ __forceinline__ int n_tris() const { return sc.n_tris; }
+    __device__ __forceinline__ const double* cum() const { return (const double*)sc.cum_area; }
+    __device__ __forceinline__ float eps() const { return sc.eps; }
+    __device__ __forceinline__ const float* com() const { return sc.com; }
+    __device__ __forceinline__ int position(int f) const { return ((const int32_t*)sc.pos)[f]; }
+    // hinge h's rotation (selected without indexing registers by a lane-varying h)
+    struct Turn {
+        float c, s, k[3], o[3];
+    };
+    __device__ __forceinline__ Turn hinge(int h, float sgn) const
+    {
+        Turn r{1.0f, 0.0f, {0.0f, 0.0f, 1.0f}, {0.0f, 0.0f, 0.0f}};
+#pragma unroll
+        for (int q = 0; q < kMaxHinges; ++q)
+            if (h == q) {
+                r.c = cs[q];
+                r.s = sgn * sn[q];
+                for (int a = 0; a < 3; ++a) {
+                    r.k[a] = sc.hinge_axis[q][a];
+                    r.o[a] = sc.hinge_origin[q][a];
+                }
+            }
+        return r;
+    }
+    // v turned by the rotation (Rodrigues' formula), or the point v turned about the hinge line
+    __device__ __forceinline__ static void turn(const Turn& r, const float v[3], float out[3])
+    {
+        const float kv = r.k[0] * v[0] + r.k[1] * v[1] + r.k[2] * v[2];
+        const float kx[3] = {r.k[1] * v[2] - r.k[2] * v[1], r.k[2] * v[0] - r.k[0] * v[2],
+                             r.k[0] * v[1] - r.k[1] * v[0]};
+        for (int a = 0; a < 3; ++a) out[a] = v[a] * r.c + kx[a] * r.s + r.k[a] * kv * (1.0f - r.c);
+    }
+    __device__ __forceinline__ static void turn_point(const Turn& r, const float v[3], float out[3])
+    {
+        const float d[3] = {v[0] - r.o[0], v[1] - r.o[1], v[2] - r.o[2]};
+        turn(r, d, out);
+        for (int a = 0; a < 3; ++a) out[a] += r.o[a];
+    }
+    __device__ __forceinline__ float4 material(const TriRec& tr) const
+    {
+        const float* m = mat + 3 * __float_as_int(tr.f[3].z);
+        const float a = m[0], b = m[1];
+        float q;
+        if (a > 0.0f && b > 0.0f) {
+            q = a / (a + b);
+            q = fminf(fmaxf(q, 0.01f), 0.99f);
+        } else {
+            q = a > 0.0f ? 1.0f : 0.0f;
+        }
+        return make_float4(a, b, q, m[2]);
+    }
+    __device__ __forceinline__ void point(int p, float b1, float b2, float x[3], float n[3], float4& mt) const
+    {
+        const TriRec tr = ((const TriRec*)sc.tris)[p];
+        mt = material(tr);
+        const float xr[3] = {tr.f[0].x + b1 * tr.f[1].x + b2 * tr.f[2].x, tr.f[0].y + b1 * tr.f[1].y + b2 * tr.f[2].y,
+                             tr.f[0].z + b1 * tr.f[1].z + b2 * tr.f[2].z};
+        const float nr[3] = {tr.f[1].w, tr.f[2].w, tr.f[3].x};
+        const int h = __float_as_int(tr.f[3].y);
+        if (h < 0) {
+            for (int a = 0; a < 3; ++a) {
+                x[a] = xr[a];
+                n[a] = nr[a];
+            }
+        } else {
+            const Turn r = hinge(h, 1.0f);
+            turn_point(r, xr, x);
+            turn(r, nr, n);
+        }
+    }
+    __device__ __forceinline__ void facet(int g, float ng[3], int& id, float4& mt) const
+    {
+        const TriRec tg = ((const TriRec*)sc.tris)[g];
+        mt = material(tg);
+        const float nr[3] = {tg.f[1].w, tg.f[2].w, tg.f[3].x};
+        const int h = __float_as_int(tg.f[3].y);
+        if (h < 0) {
+            for (int a = 0; a < 3; ++a) ng[a] = nr[a];
+        } else {
+            turn(hinge(h, 1.0f), nr, ng);
+        }
+        id = __float_as_int(tg.f[0].w);
+    }
+    // the ray in the rest frame of part q
+    __device__ __forceinline__ void to_part(int q, const float o[3], const float d[3], float o2[3], float d2[3]) const
+    {
+        const int h = sc.part_hinge[q];
+        if (h < 0) {
+            for (int a = 0; a < 3; ++a) {
+                o2[a] = o[a];
+                d2[a] = d[a];
+            }
+        } else {
+            const Turn r = hinge(h, -1.0f);
+            turn_point(r, o, o2);
+            turn(r, d, d2);
+        }
+    }
+    __device__ __forceinline__ bool blocked(const float o[3], const float s[3], int skip) const
+    {
+        const TriRec* __restrict__ tris = (const TriRec*)sc.tris;
+        bool blk = false;
+        int begin = 0;
+        for (int q = 0; q < sc.n_parts; ++q) {
+            float o2[3], s2[3];
+            to_part(q, o, s, o2, s2);
+            for (int tri = begin; tri < sc.part_end[q]; ++tri) {
+                const TriRec* T = tris + tri;
+                const float t = tri_hit_back(o2, s2, T->f[0], T->f[1], T->f[2]);
+                blk = blk || (t > 0.0f && tri != skip);
+            }
+            begin = sc.part_end[q];
+        }
+        return blk;
+    }
+    __device__ __forceinline__ int closest(const float o[3], const float d[3], int skip, float& t_out) const
+    {
+        const TriRec* __restrict__ tris = (const TriRec*)sc.tris;
+        float tbest = FLT_MAX;
+        int hit = -1, hit_id = 0x7fffffff;
+        int begin = 0;
+        for (int q = 0; q < sc.n_parts; ++q) {
+            float o2[3], d2[3];
+            to_part(q, o, d, o2, d2);
+            for (int tri = begin; tri < sc.part_end[q]; ++tri) {
+                const TriRec* T = tris + tri;
+                const float4 g0 = T->f[0], g1 = T->f[1], g2 = T->f[2];
+                const float t = tri_hit(o2, d2, g0, g1, g2);
+                const int id = __float_as_int(g0.w);
+                if (t > 0.0f && tri != skip && (t < tbest || (t == tbest && id < hit_id))) {
+                    tbest = t;
+                    hit = tri;
+                    hit_id = id;
+                }
+            }
+            begin = sc.part_end[q];
+        }
+        t_out = tbest;
+        return hit;
+    }
+};
+
+// One sample: force and torque (area applied) and its record.  `n_samples` scales the stratified
+// area coordinate.
+template <class Geo>
+__device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const Geo& geo, int64_t n_samples, const float s[3],
                                                uint32_t sample, uint32_t dir, uint32_t design, float F[3], float T[3],
-                                               int32_t& rec_facet, int32_t* rec_hits, int32_t& rec_lit,
-                                               int* __restrict__ lstack)
+                                               int32_t& rec_facet, int32_t* rec_hits, int32_t& rec_lit)
 {
     float u0[4], u1[4];
     uint32_t c0 = sample, c1 = dir, c2 = 0u, c3 = design;
     philox4x32_10(c0, c1, c2, c3, a.seed_lo, a.seed_hi);
     philox_at(sample, dir, 1u, design, a, u1);
     // facet by area (FP64, original facet order): the first f with u A < cum[f]
-    const double* __restrict__ cum = (const double*)sc.cum_area;
+    const double* __restrict__ cum = geo.cum();
     // stratified: sample i of N takes the area coordinate (i + u) / N
     const double uf = (a.sampling & 1)
-                          ? (static_cast<double>(sample) + static_cast<double>(unit24(c0))) / static_cast<double>(a.n_samples)
+                          ? (static_cast<double>(sample) + static_cast<double>(unit24(c0))) / static_cast<double>(n_samples)
                           : static_cast<double>(unit24(c0));
-    const double target = uf * sc.area;
-    int lo = 0, hi = sc.n_tris - 1;
+    const double target = uf * geo.area();
+    int lo = 0, hi = geo.n_tris() - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (target < cum[mid])
@@ -228,44 +472,36 @@ __device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const Surfa
             lo = mid + 1;
     }
     rec_facet = lo;
-    const int p = ((const int32_t*)sc.bvh_pos)[lo];
-    const TriRec tr = ((const TriRec*)sc.tris)[p];
-    const float4 mt = ((const float4*)sc.mat)[p];
+    const int p = geo.position(lo);
     u0[1] = unit24(c1);
     u0[2] = unit24(c2);
     u0[3] = unit24(c3);
     const float sq = sqrtf(u0[1]);
     const float b1 = sq * (1.0f - u0[2]), b2 = sq * u0[2];
     float x[3], n[3], o[3];
-    const float v0[3] = {tr.f[0].x, tr.f[0].y, tr.f[0].z};
-    const float e1[3] = {tr.f[1].x, tr.f[1].y, tr.f[1].z};
-    const float e2[3] = {tr.f[2].x, tr.f[2].y, tr.f[2].z};
-    n[0] = tr.f[1].w;
-    n[1] = tr.f[2].w;
-    n[2] = tr.f[3].x;
-    for (int c = 0; c < 3; ++c) {
-        x[c] = v0[c] + b1 * e1[c] + b2 * e2[c];
-        o[c] = x[c] + sc.eps * n[c];
-    }
-    const float rs = mt.x, rd = mt.y, ps = mt.z;
+    float4 mt;
+    geo.point(p, b1, b2, x, n, mt);
+    for (int c = 0; c < 3; ++c) o[c] = x[c] + geo.eps() * n[c];
+    const float rs = mt.x, rd = mt.y, ps = mt.z, mx = mt.w;
     const bool uniform = (a.sampling & 2) != 0;
-    const bool mirror = u0[3] < ps;
+    // the outgoing event at x: specular (about each arriving contribution's mirror direction,
+    // drawn from the same two uniforms) or one cosine direction for all contributions
+    const bool spec = u0[3] < ps;
     float odir[3], w[3];
     const float wo = hemi_dir(n, u1[0], u1[1], uniform, odir);
     const float wg = hemi_dir(n, u1[2], u1[3], uniform, w);
-    const float kout = mirror ? rs / ps : (rd > 0.0f ? rd / (1.0f - ps) * wo : 0.0f);
+    const float kdif = rd > 0.0f ? rd / (1.0f - ps) * wo : 0.0f;
     float dep[3] = {0.0f, 0.0f, 0.0f};
     int32_t lit = 0;
     const float cs = n[0] * s[0] + n[1] * s[1] + n[2] * s[2];
-    if (cs > 0.0f && !sun_blocked<BRUTE>(sc, o, s, p, lstack)) {
+    if (cs > 0.0f && !geo.blocked(o, s, p)) {
         lit |= 1;
         const float W = a.flux_c * cs;
         const float pv[3] = {-s[0], -s[1], -s[2]};
-        const float pn = pv[0] * n[0] + pv[1] * n[1] + pv[2] * n[2];
-        for (int c = 0; c < 3; ++c) {
-            const float r = pv[c] - 2.0f * pn * n[c];
-            dep[c] += W * (pv[c] - kout * (mirror ? r : odir[c]));
-        }
+        float od[3];
+        float k = kdif;
+        if (spec) k = rs / ps * specular_dir(pv, n, mx, u1[0], u1[1], uniform, od);
+        for (int c = 0; c < 3; ++c) dep[c] += W * (pv[c] - k * (spec ? od[c] : odir[c]));
     }
     if (a.bounces >= 2) {
         float ro[3] = {o[0], o[1], o[2]}, rdir[3] = {w[0], w[1], w[2]};
@@ -273,32 +509,46 @@ __device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const Surfa
         float beta = 1.0f, radiance = 0.0f;
         for (int k = 1; k <= a.bounces - 1; ++k) {
             float t;
-            const int g = gather_hit<BRUTE>(sc, ro, rdir, skip, t, lstack);
+            const int g = geo.closest(ro, rdir, skip, t);
             if (g < 0) break;
-            const TriRec tg = ((const TriRec*)sc.tris)[g];
-            if (rec_hits) rec_hits[k - 1] = __float_as_int(tg.f[0].w);
-            const float4 mg = ((const float4*)sc.mat)[g];
-            const float ng[3] = {tg.f[1].w, tg.f[2].w, tg.f[3].x};
+            float ng[3];
+            float4 mg;
+            int gid;
+            geo.facet(g, ng, gid, mg);
+            if (rec_hits) rec_hits[k - 1] = gid;
             float oy[3];
-            for (int c = 0; c < 3; ++c) oy[c] = ro[c] + t * rdir[c] + sc.eps * ng[c];
+            for (int c = 0; c < 3; ++c) oy[c] = ro[c] + t * rdir[c] + geo.eps() * ng[c];
             const float cg = ng[0] * s[0] + ng[1] * s[1] + ng[2] * s[2];
-            if (mg.y > 0.0f && cg > 0.0f && !sun_blocked<BRUTE>(sc, oy, s, g, lstack)) {
+            const bool lobe = mg.x > 0.0f && mg.w < INFINITY;
+            if ((mg.y > 0.0f || lobe) && cg > 0.0f && !geo.blocked(oy, s, g)) {
                 lit |= 1 << k;
-                radiance += beta * mg.y * cg;
+                float add = mg.y * cg;
+                if (lobe) {
+                    // pi times the lobe's radiance toward the previous vertex (along -rdir) for
+                    // sunlight of propagation -s
+                    const float sn = s[0] * ng[0] + s[1] * ng[1] + s[2] * ng[2];
+                    float rr = 0.0f;
+                    for (int c = 0; c < 3; ++c) rr -= (-s[c] + 2.0f * sn * ng[c]) * rdir[c];
+                    add += mg.x * (mg.w + 2.0f) * 0.5f * powf(fmaxf(0.0f, rr), mg.w) * cg;
+                }
+                radiance += beta * add;
             }
             if (k == a.bounces - 1) break;
             float ev[4];
             philox_at(sample, dir, static_cast<uint32_t>(k + 1), design, a, ev);
             float nd[3];
+            bool live;
             if (ev[0] < mg.z) {
-                const float dn = rdir[0] * ng[0] + rdir[1] * ng[1] + rdir[2] * ng[2];
-                for (int c = 0; c < 3; ++c) nd[c] = rdir[c] - 2.0f * dn * ng[c];
-                beta *= mg.x / mg.z;
+                // light leaving the vertex along -rdir comes from about the reflection of rdir
+                beta *= mg.x / mg.z * specular_dir(rdir, ng, mg.w, ev[1], ev[2], uniform, nd);
+                live = mg.x > 0.0f && lobe_open(rdir, ng, mg.w, uniform, nd);
             } else {
                 const float wv = hemi_dir(ng, ev[1], ev[2], uniform, nd);
                 beta *= mg.y > 0.0f ? mg.y / (1.0f - mg.z) * wv : 0.0f;
+                live = mg.y > 0.0f && wv > 0.0f;
             }
-            if (beta == 0.0f) break;
+            // the path ends where its weight is zero by the model, not where the product underflows
+            if (!live) break;
             for (int c = 0; c < 3; ++c) {
                 ro[c] = oy[c];
                 rdir[c] = nd[c];
@@ -308,16 +558,16 @@ __device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const Surfa
         if (radiance > 0.0f) {
             const float W = a.flux_c * radiance * wg;
             const float pv[3] = {-w[0], -w[1], -w[2]};
-            const float pn = pv[0] * n[0] + pv[1] * n[1] + pv[2] * n[2];
-            for (int c = 0; c < 3; ++c) {
-                const float r = pv[c] - 2.0f * pn * n[c];
-                dep[c] += W * (pv[c] - kout * (mirror ? r : odir[c]));
-            }
+            float od[3];
+            float k = kdif;
+            if (spec) k = rs / ps * specular_dir(pv, n, mx, u1[0], u1[1], uniform, od);
+            for (int c = 0; c < 3; ++c) dep[c] += W * (pv[c] - k * (spec ? od[c] : odir[c]));
         }
     }
-    const float A = static_cast<float>(sc.area);
+    const float A = static_cast<float>(geo.area());
     for (int c = 0; c < 3; ++c) F[c] = A * dep[c];
-    const float lx = x[0] - sc.com[0], ly = x[1] - sc.com[1], lz = x[2] - sc.com[2];
+    const float* com = geo.com();
+    const float lx = x[0] - com[0], ly = x[1] - com[1], lz = x[2] - com[2];
     T[0] = ly * F[2] - lz * F[1];
     T[1] = lz * F[0] - lx * F[2];
     T[2] = lx * F[1] - ly * F[0];
@@ -345,10 +595,12 @@ __global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a)
     for (int k = 0; k < kMaxBounces; ++k) hits[k] = -1;
     int32_t facet = -1, lit = 0;
     // brute force keeps every lane in the wave-uniform triangle loops; the walk skips invalid lanes
-    if (BRUTE || valid)
-        surface_sample<BRUTE>(a, sc, s, static_cast<uint32_t>(valid ? i : 0), static_cast<uint32_t>(a.dir_index_base + j),
-                              a.design_index + static_cast<uint32_t>(scene), F, T, facet,
-                              a.rec_hits ? hits : nullptr, lit, &s_lane[wave][0][lane]);
+    if (BRUTE || valid) {
+        const SceneGeo<BRUTE> geo{sc, &s_lane[wave][0][lane]};
+        surface_sample(a, geo, a.n_samples, s, static_cast<uint32_t>(valid ? i : 0),
+                       static_cast<uint32_t>(a.dir_index_base + j), a.design_index + static_cast<uint32_t>(scene), F, T,
+                       facet, a.rec_hits ? hits : nullptr, lit);
+    }
     if (!valid)
         for (int c = 0; c < 3; ++c) F[c] = T[c] = 0.0f;
     if (valid && a.rec_facet) {
@@ -372,6 +624,74 @@ __global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a)
     }
 }
 
+// Multi-world: lane = (pair, sample); pair i's design turns the parts, its sun direction lights
+// them.  Every lane runs the wave-uniform triangle loops (invalid lanes too, with pair 0).
+__global__ __launch_bounds__(kSurfThreads) void k_surface_designs(MwArgs A)
+{
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * kSurfThreads + threadIdx.x;
+    const bool valid = idx < A.n_pairs * A.samples;
+    const int64_t i = valid ? idx / A.samples : 0;
+    const int32_t k = valid ? static_cast<int32_t>(idx % A.samples) : 0;
+    const float* row = A.designs + i * A.stride;
+    MwGeo geo{A.sc, {}, {}, row + A.n_hinges};
+    for (int h = 0; h < kMaxHinges; ++h) {
+        const float ang = h < A.n_hinges ? row[h] : 0.0f;
+        sincosf(ang, &geo.sn[h], &geo.cs[h]);
+    }
+    const float s[3] = {static_cast<float>(A.sun[3 * i]), static_cast<float>(A.sun[3 * i + 1]),
+                        static_cast<float>(A.sun[3 * i + 2])};
+    float F[3], T[3];
+    int32_t hits[kMaxBounces];
+    for (int q = 0; q < kMaxBounces; ++q) hits[q] = -1;
+    int32_t facet = -1, lit = 0;
+    surface_sample(A.base, geo, A.samples, s, static_cast<uint32_t>(k), static_cast<uint32_t>(A.base.dir_index_base + i),
+                   A.base.design_index, F, T, facet, A.rec_hits ? hits : nullptr, lit);
+    if (!valid) return;
+    float* out = A.sample_out + idx * 6;
+    for (int c = 0; c < 3; ++c) {
+        out[c] = F[c];
+        out[3 + c] = T[c];
+    }
+    if (A.rec_facet) {
+        A.rec_facet[idx] = facet;
+        A.rec_lit[idx] = lit;
+        if (A.rec_hits)
+            for (int q = 0; q < A.base.bounces - 1; ++q) A.rec_hits[idx * (A.base.bounces - 1) + q] = hits[q];
+    }
+}
+
+// Mean of each pair's samples, in sample order (FP64).
+__global__ void k_pair_mean(const float* __restrict__ sample_out, int64_t n_pairs, int32_t samples,
+                            double* __restrict__ force, double* __restrict__ torque)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n_pairs * 6) return;
+    const int64_t i = t / 6;
+    const int c = static_cast<int>(t % 6);
+    double sum = 0.0;
+    for (int32_t k = 0; k < samples; ++k) sum += static_cast<double>(sample_out[(i * samples + k) * 6 + c]);
+    sum /= static_cast<double>(samples);
+    if (c < 3)
+        force[3 * i + c] = sum;
+    else if (torque)
+        torque[3 * i + c - 3] = sum;
+}
+
+__global__ void k_check_designs(const float* __restrict__ designs, int64_t n_pairs, int32_t n_hinges, int32_t n_groups,
+                                int32_t* __restrict__ flags)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n_pairs * n_groups) return;
+    const int64_t i = t / n_groups;
+    const int g = static_cast<int>(t % n_groups);
+    const float* row = designs + i * (n_hinges + 3 * n_groups);
+    const float* m = row + n_hinges + 3 * g;
+    bool bad = !(m[0] >= 0.0f) || !(m[1] >= 0.0f) || !(m[0] + m[1] <= 1.0f) || !(m[2] >= 1.0f);
+    if (g == 0)
+        for (int h = 0; h < n_hinges; ++h) bad = bad || !(fabsf(row[h]) < INFINITY);
+    if (bad) atomicOr(flags, 1);
+}
+
 // Fixed-order mean over the workgroups of each unit.
 __global__ void k_surface_mean(const double* __restrict__ partials, int64_t units, int32_t chunks, double inv_n,
                                double* __restrict__ force, double* __restrict__ torque)
@@ -389,6 +709,31 @@ __global__ void k_surface_mean(const double* __restrict__ partials, int64_t unit
 }
 
 }  // namespace
+
+hipError_t launch_check_designs(const float* designs, int64_t n_pairs, int32_t n_hinges, int32_t n_groups,
+                                int32_t* flags, hipStream_t stream)
+{
+    const int64_t n = n_pairs * n_groups;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_designs, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, designs,
+                       n_pairs, n_hinges, n_groups, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_surface_designs(const MwArgs& a, double* force, double* torque, hipStream_t stream)
+{
+    const int64_t total = a.n_pairs * a.samples;
+    if (total == 0) return hipSuccess;
+    const int64_t blocks = (total + kSurfThreads - 1) / kSurfThreads;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_surface_designs, dim3(static_cast<unsigned>(blocks)), dim3(kSurfThreads), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = a.n_pairs * 6;
+    hipLaunchKernelGGL(k_pair_mean, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, a.sample_out,
+                       a.n_pairs, a.samples, force, torque);
+    return hipGetLastError();
+}
 
 hipError_t launch_surface(const SurfaceArgs& a, bool brute, double* force, double* torque, hipStream_t stream)
 {

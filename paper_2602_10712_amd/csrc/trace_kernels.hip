@@ -3,7 +3,9 @@
 // k_frames     per sun direction: propagation d = -s, Duff et al. (JCGT 2017) basis (u, v),
 //              rectangle bounding the projected mesh box, entry plane, ray-tube force
 //              w = Phi du dv / c  (FP64, rounded to FP32 for the trace).
-// k_pack_mat   per facet (BVH order): rho_s, rho_d and the frozen specular-sampling probability.
+// k_pack_mat   per facet (BVH order): rho_s, rho_d, the frozen specular-sampling probability and the
+//              Phong exponent (+infinity: ideal mirror; only the surface-sampling estimator reads it).
+// k_pack_phong the Phong exponents alone, validated (>= 1 or +infinity).
 // k_trace      one wavefront traces an 8 x 8 pixel tile of parallel rays.  Traversal of the BVH is
 //              wavefront-coherent: the whole wave walks one node sequence with a wave-uniform
 //              stack in LDS, node and triangle records are fetched once per wave through the
@@ -48,8 +50,8 @@ __global__ void k_frames(const double* __restrict__ sun, int64_t D, BoxArg box, 
 
 // ---- materials ----------------------------------------------------------------------------------
 __global__ void k_pack_mat(const float* __restrict__ rs, const float* __restrict__ rd, const float* __restrict__ ps,
-                           const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ mat,
-                           int32_t* __restrict__ bad)
+                           const float* __restrict__ phong, const int32_t* __restrict__ perm, int64_t n,
+                           float4* __restrict__ mat, int32_t* __restrict__ bad)
 {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -70,7 +72,20 @@ __global__ void k_pack_mat(const float* __restrict__ rs, const float* __restrict
         q = a > 0.0f ? 1.0f : 0.0f;
     }
     if (flag) atomicOr(bad, flag);
-    mat[p] = make_float4(a, b, q, 0.0f);
+    mat[p] = make_float4(a, b, q, phong ? phong[f] : INFINITY);
+}
+
+__global__ void k_pack_phong(const float* __restrict__ phong, const int32_t* __restrict__ perm, int64_t n,
+                             float4* __restrict__ mat, int32_t* __restrict__ flags)
+{
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float m = phong ? phong[perm[p]] : INFINITY;
+    int flag = 0;
+    if (!(m >= 1.0f)) flag |= 1;           // below 1, or NaN
+    if (m >= 1.0f && m < INFINITY) flag |= 2;  // a finite lobe
+    if (flag) atomicOr(flags, flag);
+    if (mat) mat[p].w = m;
 }
 
 // LDS of one trace workgroup.
@@ -260,13 +275,22 @@ hipError_t launch_frames(const double* sun_dirs, int64_t D, const double lo[3], 
     return hipGetLastError();
 }
 
-hipError_t launch_pack_materials(const float* rho_s, const float* rho_d, const float* p_spec, const int32_t* perm,
-                                 int64_t n, float4* mat, int32_t* bad_flag, hipStream_t stream)
+hipError_t launch_pack_materials(const float* rho_s, const float* rho_d, const float* p_spec, const float* phong,
+                                 const int32_t* perm, int64_t n, float4* mat, int32_t* bad_flag, hipStream_t stream)
 {
     const int threads = 256;
     const unsigned blocks = static_cast<unsigned>((n + threads - 1) / threads);
-    hipLaunchKernelGGL(k_pack_mat, dim3(blocks), dim3(threads), 0, stream, rho_s, rho_d, p_spec, perm, n, mat,
+    hipLaunchKernelGGL(k_pack_mat, dim3(blocks), dim3(threads), 0, stream, rho_s, rho_d, p_spec, phong, perm, n, mat,
                        bad_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_phong(const float* phong, const int32_t* perm, int64_t n, float4* mat, int32_t* flags,
+                             hipStream_t stream)
+{
+    const int threads = 256;
+    const unsigned blocks = static_cast<unsigned>((n + threads - 1) / threads);
+    hipLaunchKernelGGL(k_pack_phong, dim3(blocks), dim3(threads), 0, stream, phong, perm, n, mat, flags);
     return hipGetLastError();
 }
 
