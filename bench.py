@@ -617,30 +617,70 @@ def main():
 
         # the paper's convergence study (MSE against a high-sample reference for plain MC, BRDF
         # importance sampling, stratified surface sampling and both): 32 independent seeds of N
-        # samples for 16 directions, reference 2^22 samples per direction with both options
-        sun_v = torch.as_tensor(si.fibonacci_dirs(16), dtype=torch.float64, device=dev).contiguous()
-        Fv = torch.empty((1, 16, 3), dtype=torch.float64, device=dev)
-        p.srp_surface_estimate([sc], sun_v, 1 << 22, p.TraceParams(bounces=args.bounces, seed=999, sampling=1), Fv,
-                               stream=stream.cuda_stream)
-        ref_v = Fv.clone()
-        mse = {}
-        for n_v in (1024, 16384):
-            for mode, name in ((2, "plain"), (0, "brdf_is"), (3, "stratified"), (1, "both")):
-                acc = torch.zeros((), dtype=torch.float64, device=dev)
-                for k in range(32):
-                    p.srp_surface_estimate([sc], sun_v, n_v, p.TraceParams(bounces=args.bounces, seed=1000 + k,
-                                                                           sampling=mode), Fv, stream=stream.cuda_stream)
-                    acc += ((Fv - ref_v) ** 2).sum(-1).mean()
-                mse[f"{name}_{n_v}"] = (acc / 32).item()
-        scale = (ref_v ** 2).sum(-1).mean().item()
-        surface["variance"] = {
-            "mse_N2": {k: float(f"{v:.4e}") for k, v in mse.items()},
-            "rel_rms": {k: round((v / scale) ** 0.5, 5) for k, v in mse.items()},
-            "plain_over_both": {n: round(mse[f"plain_{n}"] / mse[f"both_{n}"], 2) for n in (1024, 16384)},
-            "workload": "satellite, 16 Fibonacci dirs, 32 seeds per option and sample count, reference 2^22 samples "
-                        "(stratified + importance sampled)"}
-        log("surface variance study (relative RMS): " + ", ".join(f"{k} {v:.4f}" for k, v in
-                                                               surface["variance"]["rel_rms"].items()))
+        # samples for 16 directions, reference 2^22 samples per direction with both options; once
+        # with ideal mirrors and once with every facet a Phong lobe (m = 20), where importance
+        # sampling of the lobe matters
+        def variance_study(scene, what):
+            sun_v = torch.as_tensor(si.fibonacci_dirs(16), dtype=torch.float64, device=dev).contiguous()
+            Fv = torch.empty((1, 16, 3), dtype=torch.float64, device=dev)
+            p.srp_surface_estimate([scene], sun_v, 1 << 22, p.TraceParams(bounces=args.bounces, seed=999, sampling=1),
+                                   Fv, stream=stream.cuda_stream)
+            ref_v = Fv.clone()
+            mse = {}
+            for n_v in (1024, 16384):
+                for mode, name in ((2, "plain"), (0, "brdf_is"), (3, "stratified"), (1, "both")):
+                    acc = torch.zeros((), dtype=torch.float64, device=dev)
+                    for k in range(32):
+                        p.srp_surface_estimate([scene], sun_v, n_v, p.TraceParams(bounces=args.bounces, seed=1000 + k,
+                                                                                  sampling=mode), Fv,
+                                               stream=stream.cuda_stream)
+                        acc += ((Fv - ref_v) ** 2).sum(-1).mean()
+                    mse[f"{name}_{n_v}"] = (acc / 32).item()
+            scale = (ref_v ** 2).sum(-1).mean().item()
+            out = {"mse_N2": {k: float(f"{v:.4e}") for k, v in mse.items()},
+                   "rel_rms": {k: round((v / scale) ** 0.5, 5) for k, v in mse.items()},
+                   "plain_over_both": {n: round(mse[f"plain_{n}"] / mse[f"both_{n}"], 2) for n in (1024, 16384)},
+                   "workload": f"satellite ({what}), 16 Fibonacci dirs, 32 seeds per option and sample count, "
+                               "reference 2^22 samples (stratified + importance sampled)"}
+            log(f"surface variance study, {what} (relative RMS): " +
+                ", ".join(f"{k} {v:.4f}" for k, v in out["rel_rms"].items()))
+            return out
+
+        surface["variance"] = variance_study(sc, "ideal mirrors")
+        sp = p.Scene.from_mesh(mesh)
+        sp.set_design(rs, rd, hinge_angles=angles)
+        sp.set_phong(np.full(mesh.n_tris, 20.0, np.float32))
+        surface["variance_phong"] = variance_study(sp, "every facet a Phong lobe, m = 20")
+        sp.close()
+
+        # multi-world sampling (the paper's setting: every pair of sun direction and design its own
+        # world, brute force): 16384 random designs x 16 samples on the satellite, 3 bounces
+        n_pw, k_pw = 16384, 16
+        grp = np.asarray(mesh.group, dtype=np.int32)
+        rng_pw = np.random.default_rng(17)
+        dsg_pw = np.concatenate([rng_pw.uniform(-0.5, 0.5, (n_pw, 2))] + [
+            np.stack([rng_pw.uniform(0, 0.5, n_pw), rng_pw.uniform(0, 0.5, n_pw), rng_pw.uniform(1, 60, n_pw)], 1)
+            for _ in range(3)], 1).astype(np.float32)
+        d_pw = torch.as_tensor(dsg_pw, device=dev).contiguous()
+        s_pw = torch.as_tensor(si.random_dirs(n_pw, seed=18), dtype=torch.float64, device=dev).contiguous()
+        F_pw = torch.empty((n_pw, 3), dtype=torch.float64, device=dev)
+        rest = p.Scene.from_mesh(mesh)
+        prm_pw = p.TraceParams(bounces=args.bounces, seed=19)
+        p.srp_surface_designs(rest, grp, 3, s_pw, d_pw, k_pw, prm_pw, F_pw, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            p.srp_surface_designs(rest, grp, 3, s_pw, d_pw, k_pw, prm_pw, F_pw, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        ms_pw = (time.perf_counter() - t0) * 1e3 / 3
+        surface["multi_world"] = {"samples_per_s": round(n_pw * k_pw / (ms_pw * 1e-3), 1), "ms": round(ms_pw, 3),
+                                  "pairs": n_pw, "samples_per_pair": k_pw,
+                                  "workload": "satellite, 16384 (sun direction, design) pairs with random hinge angles, "
+                                              "group reflectances and Phong exponents, 16 samples each, brute force "
+                                              "(host wall clock of the call, which checks the designs first)"}
+        log(f"multi-world sampling: {ms_pw:.2f} ms for {n_pw} x {k_pw} samples, "
+            f"{n_pw * k_pw / ms_pw / 1e3:.2f} M samples/s")
+        rest.close()
 
     # ---- roofline of the dominant kernel --------------------------------------------------------
     # k_trace walks a scene that stays in every XCD's L2 (99.9 % hits, counters under profiles/), so

@@ -84,3 +84,75 @@ def test_optimise_to_hidden_design():
     assert np.sqrt(hist[-1]) <= 0.1
     assert abs(prob.loss(theta) - hist[-1]) <= 1e-12 + 1e-9 * hist[-1]
     prob.close()
+
+
+def test_chain_matches_oracle_chain():
+    """The whole design-gradient chain on the box-wing (64^2 rays, 3 bounces, 240 steps of 60 s)
+    against the oracle's chain built from its own parts: FP64 brute-force forces at the 481 stage
+    times, the oracle's RK4 and its complex-step dL/dF, the oracle's reflectance adjoint summed per
+    group, and for the hinges the oracle's frozen-visibility estimator (central differences) plus
+    its edge-sampling term with the same draws."""
+    import paper_2602_10712_amd as p
+    import oracle
+    from oracle import orbit as oorb
+    from oracle.design import apply_hinges
+    mesh = si.box_wing()
+    sc = si.meo_orbit(n_steps=240, dt=60.0)
+    G, M = 64, 4
+    params = p.TraceParams(nu=G, nv=G, bounces=3, seed=5, edge_samples=M)
+    prob = p.DesignProblem(mesh, sc, params, si.DESIGN_LO, si.DESIGN_HI)
+    theta_star = np.array([0.25, -0.15, 0.3, 0.2, 0.15, 0.35, 0.1, 0.3])
+    theta = np.array([0.1, -0.05, 0.2, 0.25, 0.2, 0.3, 0.15, 0.25])
+    grp = np.asarray(mesh.group)
+
+    def oracle_forces(th):
+        V = apply_hinges(mesh.verts, mesh.vert_hinge, mesh.hinge_origin, mesh.hinge_axis, th[:2])
+        rs = th[2 + 2 * grp].astype(np.float32)
+        rd = th[3 + 2 * grp].astype(np.float32)
+        r = oracle.trace(V, mesh.tris, rs, rd, sc.sun_body, nu=G, nv=G, bounces=3, seed=5, com=mesh.com,
+                         records=True)
+        return V, rs, rd, r
+
+    _, _, _, r_star = oracle_forces(theta_star)
+    zt = oorb.rk4(sc.z0, sc.mu, sc.mass, sc.dt, sc.n_steps, r_star.force, sc.R)
+    prob.r_target = zt[:3]
+    L, g = prob.loss_and_grad(theta)
+    z_gpu, F_gpu = prob.final_state(theta)
+    V0, rs, rd, r0 = oracle_forces(theta)
+    assert np.linalg.norm(F_gpu - r0.force) <= 1e-4 * np.linalg.norm(r0.force)
+    gF, z_orc = oorb.grad_forces(sc.z0, sc.mu, sc.mass, sc.dt, sc.n_steps, r0.force, sc.R, prob.r_target,
+                                 return_final=True)
+    z_free = oorb.rk4(sc.z0, sc.mu, sc.mass, sc.dt, sc.n_steps, np.zeros_like(r0.force), sc.R)
+    shift = np.linalg.norm(z_orc[:3] - z_free[:3])
+    L_orc = float(((z_orc[:3] - prob.r_target) ** 2).sum())
+    # reflectance groups: the oracle's adjoint with the oracle's dL/dF
+    g_rs, g_rd = oracle.trace_adjoint_rho(V0, mesh.tris, rs, rd, sc.sun_body, gF, nu=G, nv=G, bounces=3, seed=5,
+                                          com=mesh.com)
+    g_orc = np.zeros(8)
+    for k in range(3):
+        g_orc[2 + 2 * k] = g_rs[grp == k].sum()
+        g_orc[3 + 2 * k] = g_rd[grp == k].sum()
+    # hinges: pathwise (frozen facet sequences, central differences) + visibility edges
+    fr = oracle.frames(V0, sc.sun_body, G, G)
+    h = 1e-4
+    for k in range(2):
+        tp, tm = theta[:2].copy(), theta[:2].copy()
+        tp[k] += h
+        tm[k] -= h
+        Fp, _ = oracle.trace_frozen(apply_hinges(mesh.verts, mesh.vert_hinge, mesh.hinge_origin, mesh.hinge_axis, tp),
+                                    V0, mesh.tris, rs, rd, sc.sun_body, r0.hit_prim, fr, nu=G, nv=G, bounces=3, seed=5,
+                                    com=mesh.com, footprint=False)
+        Fm, _ = oracle.trace_frozen(apply_hinges(mesh.verts, mesh.vert_hinge, mesh.hinge_origin, mesh.hinge_axis, tm),
+                                    V0, mesh.tris, rs, rd, sc.sun_body, r0.hit_prim, fr, nu=G, nv=G, bounces=3, seed=5,
+                                    com=mesh.com, footprint=False)
+        g_orc[k] = float((gF * (Fp - Fm) / (2 * h)).sum())
+    dE, _ = oracle.edge_term(V0, mesh.tris, mesh.vert_hinge, mesh.hinge_origin, mesh.hinge_axis, rs, rd, sc.sun_body,
+                             fr, bounces=3, seed=5, samples=M, com=mesh.com)
+    g_orc[:2] += np.einsum("jkc,jc->k", dE[:, :2, :3], gF)
+    print(f"final position {np.linalg.norm(z_gpu[:3] - z_orc[:3]):.3e} m apart (radiation shift {shift:.3f} m); "
+          f"loss {L:.6e} vs {L_orc:.6e}\n  GPU chain    {g}\n  oracle chain {g_orc}")
+    assert np.linalg.norm(z_gpu[:3] - z_orc[:3]) <= 1e-4 * shift
+    assert abs(L - L_orc) <= 1e-4 * L_orc
+    assert np.all(np.abs(g[2:] - g_orc[2:]) <= 1e-4 * np.abs(g_orc[2:]).max())
+    assert np.all(np.abs(g[:2] - g_orc[:2]) <= 5e-3 * np.abs(g_orc[:2]).max())
+    prob.close()
