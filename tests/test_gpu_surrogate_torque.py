@@ -2,17 +2,18 @@
 network trained with the library's kernels on tracer samples of random designs, checked on held-out
 (direction, design) pairs against the tracer at 1024^2 rays, 3 bounces.
 
-Bars: force and torque relative RMS <= 2 %, and the torque below the error of the 128^2-ray labels
-it was trained on (the network averages label noise away).  The paper reports its proxy at about
-3-4 % average relative error (Tab. NNError); sharing one 256-wide network between force and torque
-costs force accuracy against the force-only network (which keeps its 1 % bar): measured 1.6 %
-force, 1.0 % torque.
+Bars: force relative RMS <= 1 % (the force-only network's bar), torque <= 2 % and below the error of
+the 128^2-ray labels it was trained on (the network averages label noise away).  The paper reports
+its proxy at about 3-4 % average relative error (Tab. NNError).
 Torque about the centre of mass is a small difference of large moments (|tau| / |F| ~ 0.05-0.1 m on
 this satellite), so its relative label noise is several times the force's.
 
-Training set: 2048 random designs x 128 random sun directions traced at 128^2 rays; two networks
-averaged, 30,000 Adam steps of 4096 samples each (cosine decay from 1e-3); outputs F / F_ref and tau / (F_ref L_ref), L_ref =
-0.1 m.  Held out: 128 new designs x 16 new directions."""
+Training set: 4096 random designs x 256 random sun directions (1,048,576 samples) traced at 128^2
+rays; two networks averaged, 30,000 Adam steps of 4096 samples each (cosine decay from 1e-3);
+outputs F / F_ref and tau / (F_ref L_ref).  L_ref sets the torque's weight in the MSE against the
+force's: at L_ref = 0.1 m (about |tau| / |F|) the noisier torque labels took capacity from the force
+(1.5 % force, 0.95 % torque); at 0.5 m the held-out errors were 0.74 % and 1.0 %, at 1 m 0.66 % and
+1.1 %.  Held out: 128 new designs x 16 new directions."""
 import time
 
 import numpy as np
@@ -32,8 +33,8 @@ def test_force_torque_network_matches_tracer():
     mesh = si.meo_satellite()
     lo, hi = si.DESIGN_LO, si.DESIGN_HI
     f_ref = PHI * 20.0 / C
-    t_ref = f_ref * 0.1
-    n_d, k = 2048, 128
+    t_ref = f_ref * 0.5
+    n_d, k = 4096, 256
     designs = si.random_designs(n_d, seed=14)
     sun = si.random_dirs(n_d * k, seed=141).reshape(n_d, k, 3)
     t0 = time.perf_counter()
@@ -67,5 +68,5 @@ def test_force_torque_network_matches_tracer():
     err_t = S.rel_rms(out[:, 3:] * t_ref, T_t)
     print(f"samples {len(x)} (generation {gen_s:.1f} s), training {train_s:.1f} s; held-out relative RMS: force "
           f"{err_f:.4f} (128^2 labels {label_f:.4f}), torque {err_t:.4f} (128^2 labels {label_t:.4f})")
-    assert err_f <= 0.02
+    assert err_f <= 0.01
     assert err_t <= 0.02 and err_t < label_t
