@@ -35,7 +35,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SRP Mrays/s (20k tri, 3 bounce) fwd & fwd+adjoint; surrogate force evals/s"
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_TOPS = 39.3  # non-packed FP32 lane-ops: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# Vector-ALU issue rates of gfx950 in lanes per SIMD-cycle, by instruction class (measured by
+# paper_2602_10712_amd/valu_rates): FP32 FMA/MUL/ADD and integer add 32 (the 157.3 TFLOP/s FP32
+# vector peak: 256 CUs x 4 SIMDs x 32 lanes x 2 flop x 2.4 GHz), min/max/compare/select 16,
+# transcendentals (reciprocal, exp) 8.
+LANES_FAST, LANES_HALF, LANES_TRANS = 32.0, 16.0, 8.0
+SIMDS, CLOCK_GHZ = 1024, 2.4
+FP32_LANE_PEAK_TOPS = SIMDS * LANES_FAST * CLOCK_GHZ / 1e3  # 78.6 T lane-ops/s, every op an FMA
+# Algorithmic lane-ops of the walk by class.  Child-box slab test: 6 FMA (two slab distances per
+# axis) + 11 min/max/compare (order each axis's pair, combine the three axes with the ray's
+# interval, test entry <= exit).  Moller-Trumbore triangle test: 29 FMA/MUL/ADD (two cross
+# products, three dot products, the edge offset, the barycentric sum, t = num / det), 7
+# compare/select, 1 reciprocal.
+BOX_FAST, BOX_HALF = 6, 11
+TRI_FAST, TRI_HALF, TRI_TRANS = 29, 7, 1
 ADJ_ATOMIC_BYTES = 16.0  # at most two FP64 gradient updates per hit
 
 
@@ -89,9 +102,38 @@ def measured_l2_slot_frac():
 
 
 def measured_valu_issue():
-    """Fraction of the VALU issue ceiling (0.25 wave64 instructions per SIMD-cycle) k_trace uses."""
+    """Issue time the instruction mix k_trace actually issued needs at the class rates (counters),
+    as a fraction of the launch's cycles: [low, high], since the counters do not separate the fast
+    moves and bitwise operations from the half-rate min/max/compare/select."""
     rec = profile_record("k_trace_meo20k_counters.md")
     return None if rec is None else rec.get("valu_issue_frac")
+
+
+def walk_lane_ops(st, passes=1.0):
+    """Algorithmic lane-ops per ray of the BVH walk, by class, from the host single-ray traversal
+    statistics (child-box tests two per node visited, triangle tests per segment)."""
+    seg = st["segments_per_ray"] * passes
+    boxes = 2.0 * st["nodes_per_segment"] * seg
+    tris = st["tris_per_segment"] * seg
+    fast = BOX_FAST * boxes + TRI_FAST * tris
+    half = BOX_HALF * boxes + TRI_HALF * tris
+    trans = TRI_TRANS * tris
+    return fast, half, trans
+
+
+def alu_roofline(st, rays, seconds, passes=1.0):
+    """ALU roofline of the walk: algorithmic lane-ops / time against the class-weighted peak (the
+    rate the SIMDs reach on exactly this mix of FMA-class, half-rate and transcendental lane-ops)."""
+    fast, half, trans = walk_lane_ops(st, passes)
+    ops = fast + half + trans
+    cycles_per_ray = fast / LANES_FAST + half / LANES_HALF + trans / LANES_TRANS  # SIMD-cycles
+    peak = ops / cycles_per_ray * SIMDS * CLOCK_GHZ / 1e3
+    achieved = ops * rays / seconds / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": "T lane-ops/s",
+            "frac": round(achieved / peak, 4), "lane_ops_per_ray": round(ops, 1),
+            "lane_ops_by_class": {"fma_class": round(fast, 1), "half_rate": round(half, 1), "transcendental": round(trans, 2)},
+            "peak_if_all_fma": {"peak": round(FP32_LANE_PEAK_TOPS, 1), "frac": round(achieved / FP32_LANE_PEAK_TOPS, 4),
+                                "note": "every lane-op at the FP32 FMA rate (157.3 TFLOP/s with an FMA as one lane-op)"}}
 
 
 def parse():
@@ -243,16 +285,14 @@ def main():
             # ALU roofline, as for the forward: the forward and the replay each run the walk's
             # algorithmic lane-ops; the HBM-equivalent figure (the forward's bytes twice plus at most
             # two FP64 gradient atomics per hit) stays beside it, labelled
-            ops_a = 2.0 * (2 * 16 * sa["nodes_per_segment"] + 30 * sa["tris_per_segment"]) * sa["segments_per_ray"]
-            tops_a = ops_a * rays_a / (ms_adj * 1e-3) / 1e12
             bpr = 2.0 * sa["bytes_per_ray"] + ADJ_ATOMIC_BYTES * sa["hits_per_ray"]
             ach = bpr * rays_a / (ms_adj * 1e-3) / 1e9
-            fwd_adj["roofline"] = {"bound": "alu", "achieved": round(tops_a, 3), "peak": VALU_PEAK_TOPS,
-                                   "unit": "T lane-ops/s", "frac": round(tops_a / VALU_PEAK_TOPS, 4),
-                                   "lane_ops_per_ray": round(ops_a, 1), "hits_per_ray": round(sa["hits_per_ray"], 4),
-                                   "hbm_equivalent": {"achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                                      "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_ray": round(bpr, 1),
-                                                      "note": "not a bound: the scene is L2-resident"}}
+            fwd_adj["roofline"] = alu_roofline(sa, rays_a, ms_adj * 1e-3, passes=2.0)
+            fwd_adj["roofline"].update({"hits_per_ray": round(sa["hits_per_ray"], 4),
+                                        "hbm_equivalent": {"achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                                           "frac": round(ach / HBM_PEAK_GBS, 4),
+                                                           "bytes_per_ray": round(bpr, 1),
+                                                           "note": "not a bound: the scene is L2-resident"}})
         except Exception as e:
             log(f"adjoint roofline stats unavailable: {e!r}")
         log(f"forward+adjoint: {ms_adj:.2f} ms/step, {fwd_adj['value']:.1f} Mrays/s")
@@ -684,34 +724,33 @@ def main():
 
     # ---- roofline of the dominant kernel --------------------------------------------------------
     # k_trace walks a scene that stays in every XCD's L2 (99.9 % hits, counters under profiles/), so
-    # what binds it is VALU issue, not HBM: the roofline is the ALU one.  Algorithmic lane-ops of the
-    # walk a ray needs (two child-box slab tests of ~16 lane-ops per node visited, ~30 per triangle
-    # test, node and triangle counts from the host's single-ray traversal of the same BVH) against
-    # 39.3 T non-packed FP32 lane-ops/s (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz).  issue_frac is the
-    # counters' measured share of the VALU issue ceiling; the HBM-equivalent figure (algorithmic
-    # bytes against 8 TB/s) is kept beside it, labelled, and exceeds 1 because the scene is cached.
+    # what binds it is vector-ALU issue, not HBM: the roofline is the ALU one.  Algorithmic lane-ops
+    # of the walk a ray needs (two child-box slab tests per node visited, triangle tests, counts from
+    # the host's single-ray traversal of the same BVH) against the peak of that op mix (FMA-class
+    # lane-ops at 32 lanes per SIMD-cycle, min/max/compare at 16, reciprocals at 8; 1024 SIMDs at
+    # 2.4 GHz); the all-FMA peak (78.6 T) is kept beside it.  issue_frac is the counters' issued
+    # instruction mix at the same class rates, as a share of the launch's cycles (a range); the HBM-equivalent
+    # figure (algorithmic bytes against 8 TB/s) is kept beside it, labelled, and exceeds 1 because
+    # the scene is cached.
     roofline = None
     try:
         from paper_2602_10712_amd import ray_stats
         st = ray_stats(sc, sun, params, n_dirs=16, pixel_stride=97)
         launch_s = np.median(step_ms) * 1e-3  # one launch = all D x grid^2 rays (frames + reduce < 1 %)
-        ops_ray = (2 * 16 * st["nodes_per_segment"] + 30 * st["tris_per_segment"]) * st["segments_per_ray"]
-        tops = ops_ray * rays / launch_s / 1e12
         bytes_per_ray = st["bytes_per_ray"]
         hbm_eq = bytes_per_ray * rays / launch_s / 1e9
-        roofline = {"bound": "alu", "achieved": round(tops, 3), "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
-                    "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(),
-                    "lane_ops_per_ray": round(ops_ray, 1), "issue_frac": measured_valu_issue(),
-                    "l2_hit_rate": measured_l2_hit_rate(), "l2_slot_frac": measured_l2_slot_frac(),
-                    "segments_per_ray": round(st["segments_per_ray"], 4),
-                    "hits_per_ray": round(st["hits_per_ray"], 4),
-                    "nodes_per_segment": round(st["nodes_per_segment"], 2),
-                    "tris_per_segment": round(st["tris_per_segment"], 2),
-                    "hbm_equivalent": {"note": "algorithmic bytes / launch time against the HBM peak; the scene "
-                                               "is L2-resident, so this is not a bound and may exceed 1",
-                                       "achieved": round(hbm_eq, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                       "frac": round(hbm_eq / HBM_PEAK_GBS, 4),
-                                       "bytes_per_ray": round(bytes_per_ray, 1)}}
+        roofline = alu_roofline(st, rays, launch_s)
+        roofline.update({"traffic": measured_traffic(), "issue_frac": measured_valu_issue(),
+                         "l2_hit_rate": measured_l2_hit_rate(), "l2_slot_frac": measured_l2_slot_frac(),
+                         "segments_per_ray": round(st["segments_per_ray"], 4),
+                         "hits_per_ray": round(st["hits_per_ray"], 4),
+                         "nodes_per_segment": round(st["nodes_per_segment"], 2),
+                         "tris_per_segment": round(st["tris_per_segment"], 2),
+                         "hbm_equivalent": {"note": "algorithmic bytes / launch time against the HBM peak; the "
+                                                    "scene is L2-resident, so this is not a bound and may exceed 1",
+                                            "achieved": round(hbm_eq, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                            "frac": round(hbm_eq / HBM_PEAK_GBS, 4),
+                                            "bytes_per_ray": round(bytes_per_ray, 1)}})
         rates["segments_per_s"] = round(st["segments_per_ray"] * rays / launch_s, 1)
         rates["hits_per_s"] = round(st["hits_per_ray"] * rays / launch_s, 1)
     except Exception as e:  # the stats entry point is optional for the timing itself

@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsrp.so")
 OBJDIR = os.path.join(HERE, "_build")
+VALU_RATES = os.path.join(HERE, "valu_rates")
 
 SOURCES = ["srp_api.cpp", "bvh_build.cpp", "ray_stats.cpp", "trace_kernels.hip", "adjoint_kernels.hip", "surface_kernels.hip", "bvh_gpu.hip", "mlp_api.cpp", "mlp_kernels.hip", "mlp_infer.hip",
            "orbit.cpp", "attitude_kernels.hip", "attitude_api.cpp", "noalloc.hip", "ensemble.hip", "edge_kernels.hip"]
@@ -47,6 +48,9 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", "-o", tmp, *objs], check=True)
     os.replace(tmp, LIB)
+    # stand-alone measurement of the vector ALU's issue rates (the ALU roofline's ceilings)
+    subprocess.run([HIPCC, "-x", "hip", *DEVICE, "-O3", "-std=c++17", os.path.join(CSRC, "valu_rates.hip"), "-o",
+                    VALU_RATES], check=True)
     return LIB
 
 
