@@ -121,10 +121,14 @@ def walk_lane_ops(st, passes=1.0):
     return fast, half, trans
 
 
-def alu_roofline(st, rays, seconds, passes=1.0):
+def alu_roofline(st, rays, seconds, passes=1.0, extra_tris_per_ray=0.0):
     """ALU roofline of the walk: algorithmic lane-ops / time against the class-weighted peak (the
-    rate the SIMDs reach on exactly this mix of FMA-class, half-rate and transcendental lane-ops)."""
+    rate the SIMDs reach on exactly this mix of FMA-class, half-rate and transcendental lane-ops).
+    extra_tris_per_ray: triangle tests beyond the walks (the recorded adjoint's)."""
     fast, half, trans = walk_lane_ops(st, passes)
+    fast += TRI_FAST * extra_tris_per_ray
+    half += TRI_HALF * extra_tris_per_ray
+    trans += TRI_TRANS * extra_tris_per_ray
     ops = fast + half + trans
     cycles_per_ray = fast / LANES_FAST + half / LANES_HALF + trans / LANES_TRANS  # SIMD-cycles
     peak = ops / cycles_per_ray * SIMDS * CLOCK_GHZ / 1e3
@@ -257,7 +261,16 @@ def main():
         g_rd = torch.zeros(mesh.n_tris, dtype=torch.float32, device=dev)
         g_h = torch.zeros(2, dtype=torch.float64, device=dev)
 
+        # the forward records every path's facets, and the adjoint reads them back instead of
+        # walking the BVH again (same gradients as the walking replay, srp_trace_adjoint)
+        paths = torch.empty(p.srp_path_record_bytes(sc.handle, D, pa) // 4, dtype=torch.int32, device=dev)
+
         def step_adj():
+            p.srp_trace_recorded(sc.handle, sun_d, pa, F, T, paths, stream=stream.cuda_stream)
+            p.srp_trace_adjoint_recorded(sc.handle, sun_d, pa, gF, paths, gT, g_rs, g_rd, g_h,
+                                         stream=stream.cuda_stream)
+
+        def step_replay():
             p.srp_trace(sc.handle, sun_d, pa, F, T, stream=stream.cuda_stream)
             p.srp_trace_adjoint(sc.handle, sun_d, pa, gF, gT, g_rs, g_rd, g_h, stream=stream.cuda_stream)
 
@@ -274,8 +287,9 @@ def main():
         ms_adj = e0.elapsed_time(e1) / args.steps
         rays_a = float(D) * g * g
         fwd_adj = {"value": round(rays_a / (ms_adj * 1e-3) / 1e6, 2), "unit": "Mrays/s", "ms_per_step": round(ms_adj, 3),
-                   "workload": f"{D} dirs x {g}x{g} rays, {args.bounces} bounces: forward trace + adjoint replay "
-                               "(d/d rho_s, rho_d per facet, d/d 2 hinge angles)"}
+                   "workload": f"{D} dirs x {g}x{g} rays, {args.bounces} bounces: forward trace recording each "
+                               "path's facets + adjoint over the record (d/d rho_s, rho_d per facet, d/d 2 hinge "
+                               "angles)", "record_bytes": int(paths.numel() * 4)}
         try:
             from paper_2602_10712_amd import ray_stats
             sa = ray_stats(sc, sun, pa, n_dirs=16, pixel_stride=97)
@@ -285,9 +299,12 @@ def main():
             # ALU roofline, as for the forward: the forward and the replay each run the walk's
             # algorithmic lane-ops; the HBM-equivalent figure (the forward's bytes twice plus at most
             # two FP64 gradient atomics per hit) stays beside it, labelled
-            bpr = 2.0 * sa["bytes_per_ray"] + ADJ_ATOMIC_BYTES * sa["hits_per_ray"]
+            # recorded paths: one walk per ray (the adjoint re-tests only the recorded triangle of
+            # each segment: counted), 4 B of record written and read per segment
+            bpr = sa["bytes_per_ray"] + ADJ_ATOMIC_BYTES * sa["hits_per_ray"] + 8.0 * sa["segments_per_ray"]
             ach = bpr * rays_a / (ms_adj * 1e-3) / 1e9
-            fwd_adj["roofline"] = alu_roofline(sa, rays_a, ms_adj * 1e-3, passes=2.0)
+            fwd_adj["roofline"] = alu_roofline(sa, rays_a, ms_adj * 1e-3, passes=1.0,
+                                               extra_tris_per_ray=sa["hits_per_ray"])
             fwd_adj["roofline"].update({"hits_per_ray": round(sa["hits_per_ray"], 4),
                                         "hbm_equivalent": {"achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                                            "frac": round(ach / HBM_PEAK_GBS, 4),
@@ -311,17 +328,27 @@ def main():
 
         pe = p.TraceParams(nu=g, nv=g, bounces=args.bounces, jitter=1, seed=2, edge_samples=16)
         ms_f = timed(lambda: p.srp_trace(sc.handle, sun_d, pa, F, T, stream=stream.cuda_stream))
+        ms_fr = timed(lambda: p.srp_trace_recorded(sc.handle, sun_d, pa, F, T, paths, stream=stream.cuda_stream))
+        ms_br = timed(lambda: p.srp_trace_adjoint_recorded(sc.handle, sun_d, pa, gF, paths, gT, g_rs, g_rd, g_h,
+                                                           stream=stream.cuda_stream))
+        ms_e = timed(lambda: p.srp_trace_adjoint_recorded(sc.handle, sun_d, pe, gF, paths, gT, g_rs, g_rd, g_h,
+                                                          stream=stream.cuda_stream))
         ms_b = timed(lambda: p.srp_trace_adjoint(sc.handle, sun_d, pa, gF, gT, g_rs, g_rd, g_h,
                                                  stream=stream.cuda_stream))
-        ms_e = timed(lambda: p.srp_trace_adjoint(sc.handle, sun_d, pe, gF, gT, g_rs, g_rd, g_h,
-                                                 stream=stream.cuda_stream))
+        ms_rp = timed(step_replay)
         fwd_adj["forward_ms"] = round(ms_f, 3)
-        fwd_adj["adjoint_ms"] = round(ms_b, 3)
-        fwd_adj["adjoint_over_forward"] = round(ms_b / ms_f, 3)
+        fwd_adj["recorded_forward_ms"] = round(ms_fr, 3)
+        fwd_adj["adjoint_ms"] = round(ms_br, 3)
+        fwd_adj["adjoint_over_forward"] = round(ms_br / ms_f, 3)
+        fwd_adj["replay"] = {"note": "srp_trace + srp_trace_adjoint: the adjoint walks the BVH again",
+                             "ms_per_step": round(ms_rp, 3), "value": round(rays_a / (ms_rp * 1e-3) / 1e6, 2),
+                             "adjoint_ms": round(ms_b, 3), "adjoint_over_forward": round(ms_b / ms_f, 3)}
         fwd_adj["edge_term"] = {"edge_samples": 16, "adjoint_ms_with_edges": round(ms_e, 3),
-                                "edge_ms": round(ms_e - ms_b, 3)}
-        log(f"forward {ms_f:.2f} ms, adjoint {ms_b:.2f} ms ({ms_b / ms_f:.2f}x), adjoint with edge terms "
-            f"{ms_e:.2f} ms")
+                                "edge_ms": round(ms_e - ms_br, 3)}
+        log(f"forward {ms_f:.2f} ms (recording {ms_fr:.2f} ms), adjoint over the record {ms_br:.2f} ms "
+            f"({ms_br / ms_f:.2f}x), walking replay {ms_b:.2f} ms ({ms_b / ms_f:.2f}x); forward+adjoint with the "
+            f"replay {ms_rp:.2f} ms; adjoint with edge terms {ms_e:.2f} ms")
+        del paths
 
     # ---- design gradient through the orbit: 1 day of 60 s RK4 steps, 2881 stage-time sun directions ----
     orbit = None

@@ -230,6 +230,33 @@ srp_status srp_trace_adjoint(srp_scene scene, const double* sun_dirs, int64_t D,
                              const double* frames, const double* g_force, const double* g_torque, float* g_rho_s,
                              float* g_rho_d, double* g_hinge, void* stream);
 
+/* Path records: the forward keeps the facet sequence of every traced path so that the adjoint
+ * (paper Sec. 3.4, same gradients as srp_trace_adjoint) does not walk the BVH a second time.
+ *
+ * srp_path_record_bytes: size of the record for D directions and these params, host int64:
+ *   D x bounces x ceil(nu/8) x ceil(nv/8) x 64 x 4 bytes (one int32 per traced interaction slot;
+ *   about 3.2 GB for 1024 directions at 512 x 512 and 3 bounces).
+ * srp_trace_recorded: srp_trace (same arguments, kernels and bit-identical force and torque) that
+ *   also writes the record into `paths` (device, caller-owned, at least srp_path_record_bytes
+ *   bytes, layout private to the library).  Only the slots of paths that were traced are written.
+ * srp_trace_adjoint_recorded: srp_trace_adjoint with the same arguments and the same results,
+ *   taking each path's facets from `paths` and recomputing each hit with the same ray-triangle
+ *   test.  `paths` must come from the LAST srp_trace_recorded on this scene, with no design,
+ *   vertex, Phong or BVH change since, and the same sun_dirs pointer, D, params (every field; the
+ *   ray_mask pointer) and, with frame_mode 1, frames pointer: otherwise SRP_EINVAL.  The contents
+ *   behind those pointers are the caller's to keep unchanged; a record that does not match them
+ *   gives wrong gradients (indices are range-checked, so never an out-of-bounds read).
+ * Paths of at most 3 interactions (params->bounces <= 3, else SRP_EUNSUPPORTED).
+ * Errors as srp_trace / srp_trace_adjoint, plus SRP_EINVAL for a NULL or too small record. */
+srp_status srp_path_record_bytes(srp_scene scene, int64_t D, const srp_trace_params* params, int64_t* bytes);
+srp_status srp_trace_recorded(srp_scene scene, const double* sun_dirs, int64_t D, const srp_trace_params* params,
+                              const double* frames, double* force, double* torque, int32_t* paths,
+                              int64_t paths_bytes, void* stream);
+srp_status srp_trace_adjoint_recorded(srp_scene scene, const double* sun_dirs, int64_t D,
+                                      const srp_trace_params* params, const double* frames, const double* g_force,
+                                      const double* g_torque, const int32_t* paths, int64_t paths_bytes,
+                                      float* g_rho_s, float* g_rho_d, double* g_hinge, void* stream);
+
 /* Traversal statistics for the bandwidth model: a host-side single-ray depth-first closest-hit
  * traversal (nearer child first) of this scene's BVH on the same rays as srp_trace, for every
  * pixel_stride-th pixel of each direction.  sun_dirs and frames are HOST arrays here.

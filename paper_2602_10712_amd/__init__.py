@@ -10,7 +10,7 @@ import importlib
 _BINDING_NAMES = {"SRPError", "Scene", "TraceParams", "lib_path", "srp_frames", "srp_scene_create",
                   "srp_scene_destroy", "srp_scene_get_vertices", "srp_scene_set_vertices", "srp_scene_set_phong", "srp_scene_info", "srp_scene_set_design",
                   "srp_sync", "srp_trace", "srp_trace_noalloc", "srp_trace_records", "ray_mask_bits", "srp_scene_ray_stats", "ray_stats",
-                  "srp_trace_adjoint", "srp_batch_trace", "srp_autotune_tiles_per_wave", "srp_surface_estimate", "srp_surface_designs", "srp_scene_build_gpu", "Surrogate", "srp_mlp_create", "srp_mlp_num_params", "srp_mlp_forward", "srp_mlp_ensemble",
+                  "srp_trace_adjoint", "srp_path_record_bytes", "srp_trace_recorded", "srp_trace_adjoint_recorded", "PathRecord", "srp_batch_trace", "srp_autotune_tiles_per_wave", "srp_surface_estimate", "srp_surface_designs", "srp_scene_build_gpu", "Surrogate", "srp_mlp_create", "srp_mlp_num_params", "srp_mlp_forward", "srp_mlp_ensemble",
                   "srp_mlp_backward", "srp_mlp_adam_step", "srp_mlp_zero_grad", "srp_mlp_mse", "srp_mlp_get_params",
                   "srp_mlp_set_params", "srp_mlp_destroy", "srp_orbit_rk4", "srp_orbit_rk4_adjoint",
                   "AttitudeParams", "srp_attitude_rk4"}

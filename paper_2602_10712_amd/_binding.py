@@ -71,6 +71,9 @@ _sigs = {
     "srp_trace_records": [P, P, I64, ctypes.POINTER(TraceParams), P, P, I64, P, P, P, P],
     "srp_scene_ray_stats": [P, P, I64, ctypes.POINTER(TraceParams), P, I64, P],
     "srp_trace_adjoint": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P, P, P, P],
+    "srp_path_record_bytes": [P, I64, ctypes.POINTER(TraceParams), ctypes.POINTER(I64)],
+    "srp_trace_recorded": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P, I64, P],
+    "srp_trace_adjoint_recorded": [P, P, I64, ctypes.POINTER(TraceParams), P, P, P, P, I64, P, P, P, P],
     "srp_batch_trace": [P, I32, P, I64, ctypes.POINTER(TraceParams), P, P, P],
     "srp_autotune_tiles_per_wave": [P, I32, P, I64, ctypes.POINTER(TraceParams), ctypes.POINTER(I32), P, P],
     "srp_surface_estimate": [P, I32, P, I64, I64, ctypes.POINTER(TraceParams), I32, P, P, P, P, P, P],
@@ -276,6 +279,45 @@ def srp_trace_adjoint(scene, sun_dirs, params: TraceParams, g_force, g_torque=No
                                   _stream(stream)))
 
 
+def srp_path_record_bytes(scene, D, params: TraceParams):
+    """Bytes of the path record srp_trace_recorded writes for D directions."""
+    n = I64(0)
+    _check(_lib.srp_path_record_bytes(scene, D, ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def srp_trace_recorded(scene, sun_dirs, params: TraceParams, force, torque, paths, frames=None, stream=None):
+    """srp_trace that also writes every traced path's facets into `paths` (device int32 tensor of
+    at least srp_path_record_bytes bytes)."""
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(force, torch.float64, "force")
+    _dtype_check(torque, torch.float64, "torque")
+    _dtype_check(frames, torch.float64, "frames")
+    _dtype_check(paths, torch.int32, "paths")
+    _check(_lib.srp_trace_recorded(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params), _dptr(frames),
+                                   _dptr(force), _dptr(torque), _dptr(paths), paths.numel() * 4, _stream(stream)))
+
+
+def srp_trace_adjoint_recorded(scene, sun_dirs, params: TraceParams, g_force, paths, g_torque=None, g_rho_s=None,
+                               g_rho_d=None, g_hinge=None, frames=None, stream=None):
+    """srp_trace_adjoint taking the facets of every path from the record of the last
+    srp_trace_recorded with the same scene state and arguments (see srp.h)."""
+    import torch
+    _dtype_check(sun_dirs, torch.float64, "sun_dirs")
+    _dtype_check(g_force, torch.float64, "g_force")
+    _dtype_check(g_torque, torch.float64, "g_torque")
+    _dtype_check(g_rho_s, torch.float32, "g_rho_s")
+    _dtype_check(g_rho_d, torch.float32, "g_rho_d")
+    _dtype_check(g_hinge, torch.float64, "g_hinge")
+    _dtype_check(frames, torch.float64, "frames")
+    _dtype_check(paths, torch.int32, "paths")
+    _check(_lib.srp_trace_adjoint_recorded(scene, _dptr(sun_dirs), sun_dirs.shape[0], ctypes.byref(params),
+                                           _dptr(frames), _dptr(g_force), _dptr(g_torque), _dptr(paths),
+                                           paths.numel() * 4, _dptr(g_rho_s), _dptr(g_rho_d), _dptr(g_hinge),
+                                           _stream(stream)))
+
+
 def srp_batch_trace(scenes, sun_dirs, params: TraceParams, force, torque=None, stream=None):
     """scenes: sequence of scene handles (or Scene objects); force/torque device double [S][D][3]."""
     import torch
@@ -387,6 +429,16 @@ def srp_sync(stream=None):
 # ------------------------------------------------------------------------------------------------
 # convenience object over the same calls
 # ------------------------------------------------------------------------------------------------
+class PathRecord:
+    """What trace_recorded hands to adjoint_recorded: the device directions and frames of the call
+    (the adjoint must pass the same arrays) and the path record itself."""
+
+    def __init__(self, sun_dirs, frames, paths):
+        self.sun_dirs = sun_dirs
+        self.frames = frames
+        self.paths = paths
+
+
 class Scene:
     """A mesh on the GPU: srp_scene_create + srp_scene_set_design + traces."""
 
@@ -452,6 +504,34 @@ class Scene:
         grd = torch.zeros(self.n_tris, dtype=torch.float32, device=dev)
         gh = torch.zeros(max(self.n_hinges, 1), dtype=torch.float64, device=dev)
         srp_trace_adjoint(self.handle, sd, params, gF, gT, grs, grd, gh if self.n_hinges else None, fr, stream)
+        return grs, grd, gh[:self.n_hinges]
+
+    def trace_recorded(self, sun_dirs, params: TraceParams, frames=None, stream=None):
+        """trace() that also keeps every path's facets for adjoint_recorded; returns (F, T, record).
+        The record holds the device arrays the adjoint must see again (directions, frames, paths)."""
+        import torch
+        sd = torch.as_tensor(sun_dirs, dtype=torch.float64, device="cuda").contiguous()
+        D = sd.shape[0]
+        F = torch.empty((D, 3), dtype=torch.float64, device="cuda")
+        T = torch.empty((D, 3), dtype=torch.float64, device="cuda")
+        fr = None if frames is None else torch.as_tensor(frames, dtype=torch.float64, device="cuda").contiguous()
+        nb = srp_path_record_bytes(self.handle, D, params)
+        paths = torch.empty(max(nb // 4, 1), dtype=torch.int32, device="cuda")
+        srp_trace_recorded(self.handle, sd, params, F, T, paths, fr, stream)
+        return F, T, PathRecord(sd, fr, paths)
+
+    def adjoint_recorded(self, record, params: TraceParams, g_force, g_torque=None, stream=None):
+        """adjoint() for the paths of `record` (from trace_recorded with the same params and no design
+        change since); returns (dL/d rho_s, dL/d rho_d, dL/d hinge) as new device tensors."""
+        import torch
+        dev = torch.device("cuda")
+        gF = torch.as_tensor(g_force, dtype=torch.float64, device=dev).contiguous()
+        gT = None if g_torque is None else torch.as_tensor(g_torque, dtype=torch.float64, device=dev).contiguous()
+        grs = torch.zeros(self.n_tris, dtype=torch.float32, device=dev)
+        grd = torch.zeros(self.n_tris, dtype=torch.float32, device=dev)
+        gh = torch.zeros(max(self.n_hinges, 1), dtype=torch.float64, device=dev)
+        srp_trace_adjoint_recorded(self.handle, record.sun_dirs, params, gF, record.paths, gT, grs, grd,
+                                   gh if self.n_hinges else None, record.frames, stream)
         return grs, grd, gh[:self.n_hinges]
 
     def records(self, sun_dirs, params: TraceParams, pix=None, frames=None, stream=None, points=False):

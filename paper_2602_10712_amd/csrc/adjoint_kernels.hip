@@ -83,7 +83,12 @@ __device__ __forceinline__ void wave_scatter_add(double* base, bool active, int 
 // __restrict__ parameters: the atomics then provably leave the inputs untouched, so node and
 // triangle records of the coherent walk, the frame and the cotangents can still be fetched through
 // the scalar cache into scalar registers.
-template <int MAXH, int NS>
+//
+// REC: the facet of every interaction comes from the forward's path record (TraceArgs::path_hit)
+// instead of a second BVH walk; the hit distance is recomputed with the same triangle test on the
+// same ray, so every quantity equals the walking replay's.  A recorded index outside the scene is
+// taken as a miss (the record belongs to another call).
+template <int MAXH, int NS, bool REC>
 __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* __restrict__ nodes,
                                                  const TriRec* __restrict__ tris, const float4* __restrict__ mat,
                                                  const DevFrame* __restrict__ frames,
@@ -92,8 +97,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
                                                  double* __restrict__ hinge_partials)
 {
     const TraceArgs& a = A.t;
-    __shared__ int s_stack[kWaves][kStackDepth];
-    __shared__ int s_lane[kWaves][kLaneStack][64];
+    __shared__ int s_stack[REC ? 1 : kWaves][REC ? 1 : kStackDepth];
+    __shared__ int s_lane[REC ? 1 : kWaves][REC ? 1 : kLaneStack][64];
     __shared__ float s_red[kWaves][MAXH > 0 ? MAXH : 1];
     __shared__ float4 s_rect[kCullBoxes];
     __shared__ uint64_t s_live;
@@ -104,8 +109,8 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
     if (!block_unit(a, a.D, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
     const DevFrame fr = frames[j];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
-    int* stack = s_stack[wave];
-    int* lstack = &s_lane[wave][0][lane];
+    int* stack = s_stack[REC ? 0 : wave];
+    int* lstack = &s_lane[REC ? 0 : wave][0][lane];
     const float gF[3] = {static_cast<float>(g_force[3 * j]), static_cast<float>(g_force[3 * j + 1]),
                          static_cast<float>(g_force[3 * j + 2])};
     float gT[3] = {0.0f, 0.0f, 0.0f};
@@ -144,6 +149,13 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
         bool alive = valid;
         if (a.ray_mask && valid && ray_masked(a, j, pixel)) alive = false;  // a left-out path adds nothing
         int skip = -1;
+        // recorded triangles of the path's interactions (at most kRecordBounces), fetched together
+        int ph0 = -1, ph1 = -1, ph2 = -1;
+        if (REC && alive) {
+            ph0 = a.path_hit[path_slot(a, j, 1, tile, lane)];
+            if (a.bounces >= 2) ph1 = a.path_hit[path_slot(a, j, 2, tile, lane)];
+            if (a.bounces >= 3) ph2 = a.path_hit[path_slot(a, j, 3, tile, lane)];
+        }
 
         // reflectance adjoint state
         float R[NS], Acc[NS], inv[NS];
@@ -173,14 +185,24 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
 
         for (int b = 1; b <= a.bounces; ++b) {
             if (wave_ballot(alive) == 0) break;
-            float t;
-            int hit;
-            if (b == 1)
+            float t = -1.0f;
+            int hit = -1;
+            if (REC) {
+                if (alive) {
+                    hit = b == 1 ? ph0 : b == 2 ? ph1 : ph2;
+                    if (hit >= A.n_tris || hit < -1) hit = -1;
+                    if (hit >= 0) {
+                        const TriRec* T = tris + hit;
+                        t = tri_hit(o, d, T->f[0], T->f[1], T->f[2]);
+                    }
+                }
+            } else if (b == 1) {
                 closest_hit_parallel(nodes, tris, o, d, alive, skip, t, hit, stack, fr.d);
-            else if (!a.lane_walk)
+            } else if (!a.lane_walk) {
                 closest_hit(nodes, tris, o, d, alive, skip, t, hit, stack);
-            else
+            } else {
                 closest_hit_lane(nodes, tris, o, d, alive, skip, t, hit, lstack);
+            }
             if (!alive) continue;
             if (hit < 0) {
                 alive = false;
@@ -360,16 +382,27 @@ __global__ void k_finish_adjoint(const double* __restrict__ g_rho, int32_t n_tri
 
 namespace {
 
-template <int MAXH>
+template <int MAXH, bool REC>
 void launch_adjoint_h(const AdjointArgs& a, unsigned blocks, hipStream_t stream)
 {
     if (a.t.bounces <= 3)
-        hipLaunchKernelGGL((k_adjoint<MAXH, 2>), dim3(blocks), dim3(64 * kWaves), 0, stream, a, a.t.nodes, a.t.tris,
-                           a.t.mat, a.t.frames, a.g_force, a.g_torque, a.g_rho, a.hinge_partials);
+        hipLaunchKernelGGL((k_adjoint<MAXH, 2, REC>), dim3(blocks), dim3(64 * kWaves), 0, stream, a, a.t.nodes,
+                           a.t.tris, a.t.mat, a.t.frames, a.g_force, a.g_torque, a.g_rho, a.hinge_partials);
     else
-        hipLaunchKernelGGL((k_adjoint<MAXH, kMaxBounces - 1>), dim3(blocks), dim3(64 * kWaves), 0, stream, a,
+        hipLaunchKernelGGL((k_adjoint<MAXH, kMaxBounces - 1, REC>), dim3(blocks), dim3(64 * kWaves), 0, stream, a,
                            a.t.nodes, a.t.tris, a.t.mat, a.t.frames, a.g_force, a.g_torque, a.g_rho,
                            a.hinge_partials);
+}
+
+template <bool REC>
+void launch_adjoint_rec(const AdjointArgs& a, unsigned blocks, hipStream_t stream)
+{
+    if (a.n_hinges == 0)
+        launch_adjoint_h<0, REC>(a, blocks, stream);
+    else if (a.n_hinges <= 2)
+        launch_adjoint_h<2, REC>(a, blocks, stream);
+    else
+        launch_adjoint_h<kMaxHinges, REC>(a, blocks, stream);
 }
 
 }  // namespace
@@ -380,12 +413,10 @@ hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream)
     if (nb == 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
     const unsigned blocks = static_cast<unsigned>(nb);
-    if (a.n_hinges == 0)
-        launch_adjoint_h<0>(a, blocks, stream);
-    else if (a.n_hinges <= 2)
-        launch_adjoint_h<2>(a, blocks, stream);
+    if (a.t.path_hit)
+        launch_adjoint_rec<true>(a, blocks, stream);
     else
-        launch_adjoint_h<kMaxHinges>(a, blocks, stream);
+        launch_adjoint_rec<false>(a, blocks, stream);
     return hipGetLastError();
 }
 

@@ -17,6 +17,18 @@ struct srp_scene_s {
     std::vector<int32_t> tris, vhinge;
     std::vector<srp_hinge> hinges;       // axes normalised
     std::vector<double> angles;
+    // Bumped by every change of geometry or materials; a path record is valid for one value of it.
+    uint64_t geom_gen = 0;
+    // The last srp_trace_recorded call: its record buffer, the scene state and the arguments it ran
+    // with (pointers compared by address).
+    struct PathStamp {
+        const void* paths = nullptr;
+        uint64_t gen = 0;
+        const double* sun = nullptr;
+        const double* frames = nullptr;
+        int64_t D = 0;
+        srp_trace_params p{};
+    } path_stamp;
     bool refit_on_hinge = true;          // hinge changes refit the rest-pose tree instead of rebuilding
     double com[3] = {0, 0, 0};
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // current vertex bounding box
@@ -118,8 +130,12 @@ struct TraceWorkspace {
 
 // srp_trace with its argument checks; `ws` NULL uses (and grows) the scene's workspace, else the
 // trace runs in ws and fails with SRP_EINVAL, enqueueing nothing, when ws is too small.
+// `paths` (non-null only without ws): the path record to write, sized by path_record_bytes.
 srp_status trace_into(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
                       const double* frames, double* force, double* torque, hipStream_t stream,
-                      const TraceWorkspace* ws);
+                      const TraceWorkspace* ws, int32_t* paths = nullptr);
+
+// Bytes of the path record of a grid trace: D x bounces x wave tiles x 64 int32.
+int64_t path_record_bytes(const srp_trace_params* p, int64_t D);
 
 }  // namespace srp

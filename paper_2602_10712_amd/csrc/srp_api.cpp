@@ -461,9 +461,15 @@ srp_status enqueue_trace(srp_scene_s* s, const double* sun_dirs, int64_t D, cons
 
 namespace srp {
 
+int64_t path_record_bytes(const srp_trace_params* p, int64_t D)
+{
+    const int64_t tiles = static_cast<int64_t>((p->nu + kTileW - 1) / kTileW) * ((p->nv + kTileH - 1) / kTileH);
+    return D * p->bounces * tiles * 64 * static_cast<int64_t>(sizeof(int32_t));
+}
+
 srp_status trace_into(srp_scene_s* s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
                       const double* frames, double* force, double* torque, hipStream_t stream,
-                      const TraceWorkspace* ws)
+                      const TraceWorkspace* ws, int32_t* paths)
 {
     if (!s) return fail(SRP_EINVAL, "scene is NULL");
     srp_status st = check_params(p);
@@ -478,6 +484,7 @@ srp_status trace_into(srp_scene_s* s, const double* sun_dirs, int64_t D, const s
     TraceArgs a;
     st = prepare_trace(s, sun_dirs, D, p, frames, false, nullptr, 0, nullptr, nullptr, stream, a, ws);
     if (st != SRP_OK) return st;
+    a.path_hit = paths;
     SRP_HIP(launch_trace(a, false, stream));
     SRP_HIP(launch_reduce(a.partials, D, a.blocks_per_dir, force, torque, stream));
     return SRP_OK;
@@ -566,6 +573,7 @@ srp_status srp_scene_set_design(srp_scene s, const double* hinge_angles, const f
     if (!rho_s || !rho_d) return fail(SRP_EINVAL, "rho_s and rho_d are required");
     srp_status st = bind_device(s);
     if (st != SRP_OK) return st;
+    ++s->geom_gen;  // path records of earlier calls no longer describe the scene
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     if (hinge_angles) {
         bool changed = false;
@@ -599,6 +607,7 @@ srp_status srp_scene_set_phong(srp_scene s, const float* exponents, void* stream
     if (!s) return fail(SRP_EINVAL, "scene is NULL");
     srp_status st = bind_device(s);
     if (st != SRP_OK) return st;
+    ++s->geom_gen;  // path records of earlier calls no longer describe the scene
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     SRP_HIP(hipStreamSynchronize(stream));  // kernels in flight may still read the materials
     // a private copy, checked before anything of the scene changes
@@ -638,6 +647,7 @@ srp_status srp_scene_set_vertices(srp_scene s, const double* verts, int64_t n_ve
         if (!std::isfinite(verts[i])) return fail(SRP_EDEGENERATE, "non-finite vertex");
     srp_status st = bind_device(s);
     if (st != SRP_OK) return st;
+    ++s->geom_gen;  // path records of earlier calls no longer describe the scene
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     // every facet of the new pose must keep a positive area before anything changes
     std::vector<double> old_rest;
@@ -746,9 +756,9 @@ srp_status srp_trace_records(srp_scene s, const double* sun_dirs, int64_t D, con
                          static_cast<hipStream_t>(stream_), &bpd);
 }
 
-srp_status srp_trace_adjoint(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
-                             const double* frames, const double* g_force, const double* g_torque, float* g_rho_s,
-                             float* g_rho_d, double* g_hinge, void* stream_)
+static srp_status adjoint_into(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                               const double* frames, const double* g_force, const double* g_torque, float* g_rho_s,
+                               float* g_rho_d, double* g_hinge, void* stream_, const int32_t* paths)
 {
     if (!s) return fail(SRP_EINVAL, "scene is NULL");
     srp_status st = check_params(p);
@@ -768,6 +778,7 @@ srp_status srp_trace_adjoint(srp_scene s, const double* sun_dirs, int64_t D, con
     srp::AdjointArgs A{};
     st = prepare_trace(s, sun_dirs, D, p, frames, false, nullptr, 0, nullptr, nullptr, stream, A.t);
     if (st != SRP_OK) return st;
+    A.t.path_hit = const_cast<int32_t*>(paths);
     SRP_HIP(ensure(s->d_grho, s->grho_cap, static_cast<size_t>(2 * s->n_tris)));
     SRP_HIP(ensure(s->d_hdir, s->hdir_cap, static_cast<size_t>(D * srp::kMaxHinges)));
     SRP_HIP(srp::launch_fill_f64(s->d_grho, 2 * s->n_tris, 0.0, stream));
@@ -814,6 +825,78 @@ srp_status srp_trace_adjoint(srp_scene s, const double* sun_dirs, int64_t D, con
     SRP_HIP(srp::launch_finish_adjoint(s->d_grho, A.n_tris, g_rho_s, g_rho_d, D, A.n_hinges, s->d_hdir, g_hinge,
                                        stream));
     return SRP_OK;
+}
+
+srp_status srp_trace_adjoint(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                             const double* frames, const double* g_force, const double* g_torque, float* g_rho_s,
+                             float* g_rho_d, double* g_hinge, void* stream_)
+{
+    return adjoint_into(s, sun_dirs, D, p, frames, g_force, g_torque, g_rho_s, g_rho_d, g_hinge, stream_, nullptr);
+}
+
+static bool same_params(const srp_trace_params& a, const srp_trace_params& b)
+{
+    return a.nu == b.nu && a.nv == b.nv && a.bounces == b.bounces && a.jitter == b.jitter && a.flux == b.flux &&
+           a.seed == b.seed && a.dir_index_base == b.dir_index_base && a.design_index == b.design_index &&
+           a.frame_mode == b.frame_mode && a.tiles_per_wave == b.tiles_per_wave && a.sampling == b.sampling &&
+           a.ray_mask == b.ray_mask;
+}
+
+srp_status srp_path_record_bytes(srp_scene s, int64_t D, const srp_trace_params* p, int64_t* bytes)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (D < 0 || !bytes) return fail(SRP_EINVAL, "D must be >= 0 and bytes non-NULL");
+    *bytes = srp::path_record_bytes(p, D);
+    return SRP_OK;
+}
+
+srp_status srp_trace_recorded(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                              const double* frames, double* force, double* torque, int32_t* paths,
+                              int64_t paths_bytes, void* stream_)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (D < 0) return fail(SRP_EINVAL, "D must be >= 0");
+    if (!paths) return fail(SRP_EINVAL, "paths is required");
+    if (p->bounces > srp::kRecordBounces)
+        return fail(SRP_EUNSUPPORTED, "path records hold at most 3 interactions per path");
+    const int64_t need = srp::path_record_bytes(p, D);
+    if (paths_bytes < need)
+        return fail(SRP_EINVAL, "the path record needs " + std::to_string(need) + " bytes, got " +
+                                    std::to_string(paths_bytes));
+    s->path_stamp = srp_scene_s::PathStamp{};
+    st = srp::trace_into(s, sun_dirs, D, p, frames, force, torque, static_cast<hipStream_t>(stream_), nullptr, paths);
+    if (st != SRP_OK) return st;
+    s->path_stamp.paths = paths;
+    s->path_stamp.gen = s->geom_gen;
+    s->path_stamp.sun = sun_dirs;
+    s->path_stamp.frames = p->frame_mode == 1 ? frames : nullptr;
+    s->path_stamp.D = D;
+    s->path_stamp.p = *p;
+    return SRP_OK;
+}
+
+srp_status srp_trace_adjoint_recorded(srp_scene s, const double* sun_dirs, int64_t D, const srp_trace_params* p,
+                                      const double* frames, const double* g_force, const double* g_torque,
+                                      const int32_t* paths, int64_t paths_bytes, float* g_rho_s, float* g_rho_d,
+                                      double* g_hinge, void* stream_)
+{
+    if (!s) return fail(SRP_EINVAL, "scene is NULL");
+    srp_status st = check_params(p);
+    if (st != SRP_OK) return st;
+    if (!paths) return fail(SRP_EINVAL, "paths is required");
+    if (p->bounces > srp::kRecordBounces)
+        return fail(SRP_EUNSUPPORTED, "path records hold at most 3 interactions per path");
+    if (D < 0 || paths_bytes < srp::path_record_bytes(p, D)) return fail(SRP_EINVAL, "path record too small");
+    const srp_scene_s::PathStamp& k = s->path_stamp;
+    if (k.paths != paths || k.gen != s->geom_gen || k.sun != sun_dirs || k.D != D || !same_params(k.p, *p) ||
+        (p->frame_mode == 1 && k.frames != frames))
+        return fail(SRP_EINVAL, "paths was not written by the last srp_trace_recorded on this scene with the current "
+                                "design and these arguments");
+    return adjoint_into(s, sun_dirs, D, p, frames, g_force, g_torque, g_rho_s, g_rho_d, g_hinge, stream_, paths);
 }
 
 srp_status srp_batch_trace(const srp_scene* scenes, int32_t S, const double* sun_dirs, int64_t D,
@@ -905,6 +988,7 @@ srp_status srp_scene_build_gpu(srp_scene s, int32_t* n_nodes_out, int32_t* depth
     if (s->n_tris > 0x3fffffff) return fail(SRP_EUNSUPPORTED, "too many triangles for the GPU build");
     srp_status st = bind_device(s);
     if (st != SRP_OK) return st;
+    ++s->geom_gen;  // path records of earlier calls no longer describe the scene
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     SRP_HIP(hipStreamSynchronize(stream));  // kernels in flight may still read the current tree
     const int32_t n = static_cast<int32_t>(s->n_tris);

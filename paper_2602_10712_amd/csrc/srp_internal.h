@@ -8,6 +8,7 @@ namespace srp {
 
 constexpr double kSpeedOfLight = 299792458.0;  // m/s, exact
 constexpr int kMaxBounces = 8;
+constexpr int kRecordBounces = 3;  // interactions a path record holds (srp_trace_recorded)
 constexpr int kStackDepth = 64;    // wave-uniform traversal stack (tree depth is capped below it)
 constexpr int kMaxTreeDepth = 56;
 constexpr int kLeafMax = 7;        // triangles per leaf (3-bit count in the child code)
@@ -106,7 +107,16 @@ struct TraceArgs {
     float* rec_point;         // [D][n_pix][bounces][3] hit points (NaN after the path ended), or null
     const uint32_t* ray_mask; // single scene: [D][mask_words] bitmap of primary pixels left out, or null
     int64_t mask_words;       // words per direction: ceil(nu * nv / 32)
+    int32_t* path_hit;        // grid mode, single scene: [D][bounces][tiles_per_dir][64] triangle (BVH
+                              // order) each traced path hit at each interaction, -1 for none; written
+                              // by the forward, read by the adjoint instead of walking the BVH; or null
 };
+
+// Slot of (direction j, interaction b >= 1, wave tile, lane) in TraceArgs::path_hit.
+__host__ __device__ inline int64_t path_slot(const TraceArgs& a, int64_t j, int b, int64_t tile, int lane)
+{
+    return ((j * a.bounces + (b - 1)) * a.tiles_per_dir + tile) * 64 + lane;
+}
 
 // Primary pixel `pixel` of direction j (of a single-scene call) is left out by the caller's mask.
 __device__ __forceinline__ bool ray_masked(const TraceArgs& a, int64_t j, int64_t pixel)

@@ -99,12 +99,15 @@ struct TraceLds {
 
 // One workgroup's share of direction j: wave tiles blk * tiles_per_wave * kWaves onward of the
 // direction's grid, traced against one scene and reduced into partials row `unit` (scene * D + j).
-// Every thread of the workgroup calls it (it holds barriers).
-template <bool RECORDS>
+// Every thread of the workgroup calls it (it holds barriers).  RECORDS: per-pixel records for an
+// explicit pixel list; PATHS: also write the triangle each traced path hits at each interaction
+// into the path record (grid mode), for the adjoint.
+template <bool RECORDS, bool PATHS>
 __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNode* __restrict__ nodes,
                                                 const TriRec* __restrict__ tris, const float4* __restrict__ mat,
                                                 const float com[3], float eps, uint32_t design, int64_t j,
-                                                int64_t unit, int32_t blk, TraceLds& L)
+                                                int64_t unit, int32_t blk, TraceLds& L,
+                                                int32_t* __restrict__ paths = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -144,6 +147,10 @@ __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNod
         int skip = -1;
         float ray[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         int b_done = 0;
+        // path record (at most kRecordBounces interactions): the triangles are held in registers
+        // and stored after the path ends -- vector loads and stores share one wait counter, so a
+        // store inside the walk would make the walk's load waits conservative
+        int h0 = -1, h1 = -1, h2 = -1, n_rec = 0;
         for (int b = 1; b <= a.bounces; ++b) {
             if (wave_ballot(alive) == 0) break;
             float t;
@@ -156,6 +163,15 @@ __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNod
             else
                 closest_hit_lane(nodes, tris, o, d, alive, skip, t, hit, lstack);
             if (!alive) continue;
+            if (PATHS) {
+                n_rec = b;
+                if (b == 1)
+                    h0 = hit;
+                else if (b == 2)
+                    h1 = hit;
+                else
+                    h2 = hit;
+            }
             if (hit < 0) {
                 alive = false;
                 continue;
@@ -182,6 +198,11 @@ __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNod
             ray[4] += lz * g[0] - lx * g[2];
             ray[5] += lx * g[1] - ly * g[0];
             skip = hit;
+        }
+        if (PATHS) {
+            if (n_rec >= 1) paths[path_slot(a, j, 1, tile, lane)] = h0;
+            if (n_rec >= 2) paths[path_slot(a, j, 2, tile, lane)] = h1;
+            if (n_rec >= 3) paths[path_slot(a, j, 3, tile, lane)] = h2;
         }
         if (RECORDS && valid) {
             for (int b = b_done + 1; b <= a.bounces; ++b) {
@@ -223,7 +244,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     int64_t j;
     int32_t blk;
     if (!block_unit(a, a.D, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
-    trace_workgroup<RECORDS>(a, a.nodes, a.tris, a.mat, a.com, a.eps, a.design_index, j, j, blk, L);
+    trace_workgroup<RECORDS, false>(a, a.nodes, a.tris, a.mat, a.com, a.eps, a.design_index, j, j, blk, L);
+}
+
+// k_trace that also writes the path record.  The record and the scene arrays come as separate
+// __restrict__ parameters: the record stores then provably leave the scene untouched, and node
+// and triangle records can still be fetched through the scalar cache.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_trace_paths(
+    TraceArgs a, const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris, const float4* __restrict__ mat,
+    int32_t* __restrict__ paths)
+{
+    __shared__ TraceLds L;
+    int64_t j;
+    int32_t blk;
+    if (!block_unit(a, a.D, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
+    trace_workgroup<false, true>(a, nodes, tris, mat, a.com, a.eps, a.design_index, j, j, blk, L, paths);
 }
 
 // Batched designs: the n_scenes x D (design, direction) units in design-major order, placed like
@@ -237,8 +272,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     if (!block_unit(a, a.n_scenes * a.D, blockIdx.x, u, blk)) return;  // whole workgroup: grid padding
     const int64_t s = u / a.D, j = u % a.D;
     const SceneDesc sd = a.scenes[s];
-    trace_workgroup<false>(a, (const BvhNode*)sd.nodes, (const TriRec*)sd.tris, (const float4*)sd.mat, sd.com, sd.eps,
-                           a.design_index + static_cast<uint32_t>(s), j, u, blk, L);
+    trace_workgroup<false, false>(a, (const BvhNode*)sd.nodes, (const TriRec*)sd.tris, (const float4*)sd.mat, sd.com,
+                                  sd.eps, a.design_index + static_cast<uint32_t>(s), j, u, blk, L);
 }
 
 __global__ void k_reduce(const double* __restrict__ partials, int64_t D, int32_t bpd, double* __restrict__ force,
@@ -301,6 +336,9 @@ hipError_t launch_trace(const TraceArgs& a, bool records, hipStream_t stream)
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (records)
         hipLaunchKernelGGL((k_trace<true>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
+    else if (a.path_hit)
+        hipLaunchKernelGGL(k_trace_paths, dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a, a.nodes,
+                           a.tris, a.mat, a.path_hit);
     else
         hipLaunchKernelGGL((k_trace<false>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
     return hipGetLastError();

@@ -6,7 +6,10 @@ applies the design (hinge rotation + group reflectances), traces the body-frame 
 body-frame sun direction at every RK4 stage time in ONE batched srp_trace (the attitude depends on
 time only), integrates the orbit (srp_orbit_rk4) and scores L = |r_N - r_target|^2.  Its gradient
 chains the discrete RK4 adjoint (srp_orbit_rk4_adjoint, checkpointed) into the ray adjoint
-(srp_trace_adjoint, seeds = dL/dF at each stage time), then sums facet gradients per design group.
+(seeds = dL/dF at each stage time), then sums facet gradients per design group.  The forward
+records every path's facets (srp_trace_recorded) and the ray adjoint reads them back
+(srp_trace_adjoint_recorded) instead of walking the BVH again; record_paths=False uses the walking
+replay (srp_trace_adjoint), with the same gradients.
 All compute runs in libsrp; this module only sequences the calls.  Bounded parameters are clipped
 after every optimiser step (Sec. 3.4.3).
 """
@@ -22,7 +25,8 @@ GROUP_NAMES = ("hinge_1", "hinge_2", "rho_s_bus", "rho_d_bus", "rho_s_panel", "r
 
 
 class DesignProblem:
-    def __init__(self, mesh, scenario, params: B.TraceParams, lo, hi, r_target=None, ckpt_every=60):
+    def __init__(self, mesh, scenario, params: B.TraceParams, lo, hi, r_target=None, ckpt_every=60,
+                 record_paths=True):
         self.mesh = mesh
         self.sc = scenario
         self.params = params
@@ -35,6 +39,8 @@ class DesignProblem:
         self.ckpt_every = ckpt_every
         self.n_stage = 2 * scenario.n_steps + 1
         assert self.sun.shape[0] == self.n_stage
+        self.record_paths = record_paths and params.bounces <= 3  # records hold 3 interactions
+        self._record = None  # path record of the last forward (record_paths)
 
     def materials(self, theta):
         rs = theta[2 + 2 * self.group].astype(np.float32)
@@ -45,7 +51,11 @@ class DesignProblem:
         """Body-frame force at every stage time [2n+1][3] (host FP64)."""
         rs, rd = self.materials(theta)
         self.scene.set_design(rs, rd, hinge_angles=theta[:2])
-        F, _ = self.scene.trace(self.sun, self.params)
+        if self.record_paths:
+            self._record = None  # release the previous record before the new one is allocated
+            F, _, self._record = self.scene.trace_recorded(self.sun, self.params)
+        else:
+            F, _ = self.scene.trace(self.sun, self.params)
         return F.cpu().numpy()
 
     def final_state(self, theta):
@@ -62,7 +72,10 @@ class DesignProblem:
         chained into the ray adjoint and summed per group."""
         gF, _ = B.srp_orbit_rk4_adjoint(self.sc.z0, self.sc.mu, self.sc.mass, self.sc.dt, self.sc.n_steps, F,
                                         self.sc.R, g_final, self.ckpt_every)
-        g_rs, g_rd, g_h = self.scene.adjoint(self.sun, self.params, gF)
+        if self.record_paths and self._record is not None:
+            g_rs, g_rd, g_h = self.scene.adjoint_recorded(self._record, self.params, gF)
+        else:
+            g_rs, g_rd, g_h = self.scene.adjoint(self.sun, self.params, gF)
         g_rs = g_rs.cpu().numpy().astype(np.float64)
         g_rd = g_rd.cpu().numpy().astype(np.float64)
         grad = np.zeros(8)
@@ -154,6 +167,7 @@ class DesignProblem:
         return theta, hist
 
     def close(self):
+        self._record = None
         self.scene.close()
 
 
