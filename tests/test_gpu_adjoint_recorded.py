@@ -10,7 +10,8 @@ Bars:
     with and without edge samples;
   * reflectance gradients vs the oracle's FP64 adjoint on the box-wing: relative L2 <= 1e-4;
   * a record is refused (SRP_EINVAL) after a design change, for other arguments, when too small,
-    or when it is not the last one recorded.
+    or when it is not the last one recorded; paths of more than 3 interactions are not recorded
+    (SRP_EUNSUPPORTED).
 """
 import numpy as np
 import pytest
@@ -108,4 +109,6 @@ def test_stale_or_foreign_records_are_refused():
     with pytest.raises(p.SRPError):
         p.srp_trace_recorded(sc.handle, sun, params, torch.empty((8, 3), dtype=torch.float64, device="cuda"),
                              None, torch.empty(16, dtype=torch.int32, device="cuda"))
+    with pytest.raises(p.SRPError):  # a record holds three interactions per path
+        sc.trace_recorded(sun, p.TraceParams(nu=64, nv=64, bounces=4, seed=5))
     torch.cuda.synchronize()
