@@ -236,9 +236,10 @@ srp_status srp_trace_adjoint(srp_scene scene, const double* sun_dirs, int64_t D,
  * srp_path_record_bytes: size of the record for D directions and these params, host int64:
  *   D x bounces x ceil(nu/8) x ceil(nv/8) x 64 x 4 bytes (one int32 per traced interaction slot;
  *   about 3.2 GB for 1024 directions at 512 x 512 and 3 bounces).
- * srp_trace_recorded: srp_trace (same arguments, kernels and bit-identical force and torque) that
- *   also writes the record into `paths` (device, caller-owned, at least srp_path_record_bytes
- *   bytes, layout private to the library).  Only the slots of paths that were traced are written.
+ * srp_trace_recorded: srp_trace (same arguments, same paths; its own kernel, so force and torque
+ *   agree with srp_trace's to FP32 rounding, not bit for bit) that also writes the record into
+ *   `paths` (device, caller-owned, at least srp_path_record_bytes bytes, layout private to the
+ *   library).  Only the slots of paths that were traced are written.
  * srp_trace_adjoint_recorded: srp_trace_adjoint with the same arguments and the same results,
  *   taking each path's facets from `paths` and recomputing each hit with the same ray-triangle
  *   test.  `paths` must come from the LAST srp_trace_recorded on this scene, with no design,
