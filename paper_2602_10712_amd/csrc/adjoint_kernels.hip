@@ -76,6 +76,65 @@ __device__ __forceinline__ void wave_scatter_add(double* base, bool active, int 
     if (active) atomicAdd(base + key, static_cast<double>(val));
 }
 
+// Workgroup-level gradient table (used where the adjoint does not walk the BVH, which leaves its
+// LDS free): open addressing over kTableSize slots of (key, FP64 sum); the wave's pre-summed values
+// are added there with LDS atomics, and the table goes to the global gradient with one FP64 atomic
+// per distinct key when the workgroup ends.  A key that finds no slot within kTableProbes probes
+// goes straight to the global gradient.
+constexpr int kTableSize = 2048;
+constexpr int kTableProbes = 8;
+
+struct GradTable {
+    int key[kTableSize];
+    double val[kTableSize];
+};
+
+__device__ __forceinline__ void table_add(GradTable& T, double* base, int key, double v)
+{
+    uint32_t h = (static_cast<uint32_t>(key) * 0x9E3779B1u) >> (32 - 11);  // 11 bits: kTableSize
+    for (int p = 0; p < kTableProbes; ++p) {
+        const int slot = static_cast<int>((h + p) & (kTableSize - 1));
+        const int prev = atomicCAS(&T.key[slot], -1, key);
+        if (prev == -1 || prev == key) {
+            atomicAdd(&T.val[slot], v);
+            return;
+        }
+    }
+    atomicAdd(base + key, v);
+}
+
+// The workgroup's table in LDS (only kernels that use it allocate it).
+template <bool REC>
+__device__ __forceinline__ GradTable* grad_table()
+{
+    return nullptr;
+}
+template <>
+__device__ __forceinline__ GradTable* grad_table<true>()
+{
+    __shared__ GradTable t;
+    return &t;
+}
+
+// wave_scatter_add into the workgroup table instead of the global gradient.
+__device__ __forceinline__ void wave_table_add(GradTable& T, double* base, bool active, int key, float val)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = wave_ballot(active);
+    for (int it = 0; it < kScatterGroups && pending; ++it) {
+        const int leader = __ffsll(static_cast<unsigned long long>(pending)) - 1;
+        const int k = __shfl(key, leader, 64);
+        const bool match = active && key == k;
+        const uint64_t group = wave_ballot(match);
+        if ((group & (group - 1)) == 0) break;
+        const float sum = wave_sum(match ? val : 0.0f);
+        if (lane == leader) table_add(T, base, k, static_cast<double>(sum));
+        active = active && !match;
+        pending = wave_ballot(active);
+    }
+    if (active) table_add(T, base, key, static_cast<double>(val));
+}
+
 // MAXH: hinge tangents carried (0, 2 or 4); NS: non-final interaction slots per path (bounces - 1
 // at most), so that paths of up to 3 bounces keep only two slots in registers.
 //
@@ -89,7 +148,8 @@ __device__ __forceinline__ void wave_scatter_add(double* base, bool active, int 
 // same ray, so every quantity equals the walking replay's.  A recorded index outside the scene is
 // taken as a miss (the record belongs to another call).
 template <int MAXH, int NS, bool REC>
-__global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* __restrict__ nodes,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint(
+    AdjointArgs A, const BvhNode* __restrict__ nodes,
                                                  const TriRec* __restrict__ tris, const float4* __restrict__ mat,
                                                  const DevFrame* __restrict__ frames,
                                                  const double* __restrict__ g_force,
@@ -107,6 +167,14 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
     int64_t j;
     int32_t blk;
     if (!block_unit(a, a.D, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
+    GradTable* table = grad_table<REC>();
+    if (REC) {
+        for (int i = threadIdx.x; i < kTableSize; i += 64 * kWaves) {
+            table->key[i] = -1;
+            table->val[i] = 0.0;
+        }
+        __syncthreads();
+    }
     const DevFrame fr = frames[j];
     const uint32_t dir_global = static_cast<uint32_t>(a.dir_index_base + j);
     int* stack = s_stack[REC ? 0 : wave];
@@ -318,18 +386,33 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs A, const BvhNode* _
         for (int i = 0; i < NS; ++i) {
             const bool act = valid && i < K;
             if (wave_ballot(act) == 0) break;
-            wave_scatter_add(g_rho, act, arr[i] * A.n_tris + fac[i], Acc[i] * inv[i]);
+            if (REC)
+                wave_table_add(*table, g_rho, act, arr[i] * A.n_tris + fac[i], Acc[i] * inv[i]);
+            else
+                wave_scatter_add(g_rho, act, arr[i] * A.n_tris + fac[i], Acc[i] * inv[i]);
         }
         const bool has_term = valid && term_f >= 0;
         if (wave_ballot(has_term)) {
-            wave_scatter_add(g_rho, has_term, term_f, term_s);
-            wave_scatter_add(g_rho, has_term, A.n_tris + term_f, term_d);
+            if (REC) {
+                wave_table_add(*table, g_rho, has_term, term_f, term_s);
+                wave_table_add(*table, g_rho, has_term, A.n_tris + term_f, term_d);
+            } else {
+                wave_scatter_add(g_rho, has_term, term_f, term_s);
+                wave_scatter_add(g_rho, has_term, A.n_tris + term_f, term_d);
+            }
         }
 #pragma unroll
         for (int h = 0; h < (MAXH > 0 ? MAXH : 1); ++h)
             if (valid && h < H) accH[h] += Ld[h];
     }
 
+    if (REC) {  // the workgroup's table into the global gradient: one FP64 atomic per distinct key
+        __syncthreads();
+        for (int i = threadIdx.x; i < kTableSize; i += 64 * kWaves) {
+            const int k = table->key[i];
+            if (k >= 0) atomicAdd(g_rho + k, table->val[i]);
+        }
+    }
     if (MAXH > 0) {
 #pragma unroll
         for (int h = 0; h < MAXH; ++h) accH[h] = wave_sum(accH[h]);

@@ -4,9 +4,10 @@ walking replay (srp_trace_adjoint) and the FP64 oracle.
 Bars:
   * forces and torques of the recorded forward equal to srp_trace's within 1e-7 per direction (a
     separate kernel, whose FP32 expressions the compiler may contract differently; measured ~5e-9);
-  * hinge gradients (fixed-order sums) bit-identical to the walking replay; reflectance gradients
-    equal up to the order of the FP64 atomic sums (each path adds the same values): within 1e-6
-    of the largest entry; covered on the 20k-triangle satellite with hinge angles, a ragged grid
+  * hinge and reflectance gradients equal to the walking replay's within 1e-6 of the largest entry
+    (each path adds the same terms; the two kernels sum them in different orders and the compiler
+    may contract their FP32 expressions differently); covered on the 20k-triangle satellite with
+    hinge angles, a ragged grid
     (250^2: partial 8 x 8 tiles), a direction count that is not a multiple of 8, culled tiles,
     with and without edge samples;
   * reflectance gradients vs the oracle's FP64 adjoint on the box-wing: relative L2 <= 1e-4;
@@ -53,15 +54,17 @@ def test_recorded_equals_replay_on_satellite(edge_samples):
     torch.cuda.synchronize()
     for a, b in ((F0, F1), (T0, T1)):  # two kernels: FP32 expressions may be contracted differently
         assert float(((a - b).norm(dim=1) / a.norm(dim=1)).max()) <= 1e-7
-    assert torch.equal(a_h, b_h), (a_h, b_h)
+    ha, hb = a_h.cpu().numpy(), b_h.cpu().numpy()
+    print(f"hinge gradients: walking replay {ha}, over the record {hb}, largest difference "
+          f"{np.abs(ha - hb).max() / np.abs(ha).max():.2e} of the largest")
+    assert np.abs(ha - hb).max() <= 1e-6 * np.abs(ha).max()
     for a, b in ((a_rs, b_rs), (a_rd, b_rd)):
         a = a.cpu().numpy()
         b = b.cpu().numpy()
         scale = np.abs(a).max()
         assert scale > 0
         assert np.abs(a - b).max() <= 1e-6 * scale
-    print(f"edge samples {edge_samples}: hinge gradients {b_h.cpu().numpy()} identical; record "
-          f"{rec.paths.numel() * 4 / 1e6:.1f} MB")
+    print(f"edge samples {edge_samples}: record {rec.paths.numel() * 4 / 1e6:.1f} MB")
 
 
 def test_recorded_rho_gradients_match_oracle_box_wing():
