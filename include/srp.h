@@ -240,9 +240,11 @@ srp_status srp_trace_adjoint(srp_scene scene, const double* sun_dirs, int64_t D,
  *   agree with srp_trace's to FP32 rounding, not bit for bit) that also writes the record into
  *   `paths` (device, caller-owned, at least srp_path_record_bytes bytes, layout private to the
  *   library).  Only the slots of paths that were traced are written.
- * srp_trace_adjoint_recorded: srp_trace_adjoint with the same arguments and the same results,
- *   taking each path's facets from `paths` and recomputing each hit with the same ray-triangle
- *   test.  `paths` must come from the LAST srp_trace_recorded on this scene, with no design,
+ * srp_trace_adjoint_recorded: srp_trace_adjoint with the same arguments, taking each path's
+ *   facets from `paths` and recomputing each hit with the same ray-triangle test: every path adds
+ *   the same terms, summed in another order (per workgroup in LDS first, then one FP64 atomic per
+ *   facet and workgroup), so the gradients agree with srp_trace_adjoint's to rounding.  `paths`
+ *   must come from the LAST srp_trace_recorded on this scene, with no design,
  *   vertex, Phong or BVH change since, and the same sun_dirs pointer, D, params (every field; the
  *   ray_mask pointer) and, with frame_mode 1, frames pointer: otherwise SRP_EINVAL.  The contents
  *   behind those pointers are the caller's to keep unchanged; a record that does not match them
