@@ -77,7 +77,8 @@ def lib():
                                           ctypes.c_int32, P, P]
         L.oracle_edge_term.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, P, P, P,
                                        ctypes.c_int64, P, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
-                                       ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, P, P, ctypes.c_int32]
+                                       ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, P, ctypes.c_int64, P, P,
+                                       ctypes.c_int32]
         L.oracle_edge_term.restype = ctypes.c_int
         L.oracle_trace_frozen.restype = ctypes.c_int
         L.oracle_surface_estimate.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int64,
@@ -274,9 +275,10 @@ def trace_frozen(verts, verts0, tris, rho_s, rho_d, sun_dirs, ref_hits, frames_i
 
 def edge_term(verts, tris, vert_hinge, hinge_origin, hinge_axis, rho_s, rho_d, sun_dirs, frames_in, *, bounces: int,
               samples: int, flux: float = 1361.0, seed: int = 0, dir_index_base: int = 0, design_index: int = 0,
-              p_spec=None, com=None, threads: int | None = None):
+              p_spec=None, com=None, threads: int | None = None, drop_smooth: bool = True):
     """Visibility-edge part of d(F, tau)/d(hinge angle) by edge sampling (see srp_oracle.c):
-    [D][H][6] (force, torque per radian) and the number of moving edges."""
+    [D][H][6] (force, torque per radian) and the number of moving edges.  drop_smooth leaves out
+    the edges across which the integrand is continuous (oracle/edges.py)."""
     verts = np.ascontiguousarray(verts, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     vh = np.ascontiguousarray(vert_hinge, dtype=np.int32)
@@ -294,10 +296,14 @@ def edge_term(verts, tris, vert_hinge, hinge_origin, hinge_axis, rho_s, rho_d, s
     ne = ctypes.c_int64(0)
     if threads is None:
         threads = default_threads()
+    keep = None
+    if drop_smooth:
+        from .edges import smooth_edge_mask
+        keep = np.ascontiguousarray(~smooth_edge_mask(verts, tris, vh, rs, rd, ps), dtype=np.uint8)
     st = lib().oracle_edge_term(_ptr(verts), len(verts), _ptr(tris), len(tris), _ptr(vh), _ptr(ho), _ptr(ha), len(ho),
                                 _ptr(rs), _ptr(rd), _ptr(ps), _ptr(c), _ptr(sun), D, _ptr(fr), int(bounces), float(flux),
-                                int(seed), int(dir_index_base), int(design_index), int(samples), _ptr(out),
-                                ctypes.byref(ne), int(threads))
+                                int(seed), int(dir_index_base), int(design_index), int(samples), _ptr(keep),
+                                0 if keep is None else len(keep), _ptr(out), ctypes.byref(ne), int(threads))
     if st != 0:
         raise ValueError(f"oracle_edge_term failed ({st})")
     return out, int(ne.value)

@@ -1106,6 +1106,11 @@ int oracle_trace_frozen(const double* verts, const double* verts0, int64_t n_ver
 /* (e M + m, direction, bounce, design); xi is the first uniform of bounce 0), and the edge's   */
 /* contribution is (Phi/c) (len/M) sum_m v_n(s_m) (deposit(y-) - deposit(y+)).  Secondary       */
 /* visibility edges (reflected light crossing an edge) are not included.                       */
+/*                                                                                            */
+/* The caller may pass a keep mask over the edges in that numbering and leave out edges across */
+/* which g is continuous (a flat continuation of the surface with the same material): there    */
+/* the two side paths meet facets of one plane and material, leave in the same direction with  */
+/* the same draws, and their deposits differ by O(delta) only.                                 */
 /* ========================================================================================== */
 #define EDGE_KEY 0x9E3779B97F4A7C15ULL
 
@@ -1195,7 +1200,8 @@ typedef struct {
     const double* sun_dirs;
     int64_t n_dirs;
     int32_t samples;
-    double* out; /* [n_dirs][n_hinges][6] */
+    const uint8_t* keep; /* [n_edges] or NULL (all) */
+    double* out;         /* [n_dirs][n_hinges][6] */
     int32_t n_threads;
     int32_t tid;
 } edge_job_t;
@@ -1218,6 +1224,7 @@ static void* edge_worker(void* argp)
         propagation_dir(J->sun_dirs + 3 * j, d);
         double* acc = J->out + (size_t)j * J->n_hinges * 6;
         for (int64_t e = 0; e < J->n_edges; ++e) {
+            if (J->keep && !J->keep[e]) continue;
             const edge_rec_t* r = J->E + e;
             const double* p0 = J->verts + 3 * r->a;
             const double* p1 = J->verts + 3 * r->b;
@@ -1270,16 +1277,17 @@ static void* edge_worker(void* argp)
  * oracle_edge_term: the visibility-edge part of d(F, tau)/d(hinge angle) for n_dirs sun
  * directions (see above).  verts [n_verts][3] are the current vertices, vert_hinge [n_verts] the
  * hinge carrying each vertex (-1: rigid), hinge_origin/hinge_axis [n_hinges][3] (axis unit) the
- * hinge lines, frames [n_dirs][12] the grid frames, `samples` = M points per edge.  Writes
- * dF [n_dirs][n_hinges][6] (force then torque, per radian).  Also returns the edge count in
- * *n_edges_out (may be NULL).
+ * hinge lines, frames [n_dirs][12] the grid frames, `samples` = M points per edge, keep
+ * [n_keep] (NULL: every edge) the edges taken, in the numbering above (n_keep must equal the edge
+ * count).  Writes dF [n_dirs][n_hinges][6] (force then torque, per radian).  Also returns the
+ * edge count in *n_edges_out (may be NULL).
  */
 int oracle_edge_term(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                      const int32_t* vert_hinge, const double* hinge_origin, const double* hinge_axis, int32_t n_hinges,
                      const float* rho_s, const float* rho_d, const float* p_spec, const double* com,
                      const double* sun_dirs, int64_t n_dirs, const double* frames, int32_t bounces, double flux,
-                     uint64_t seed, int64_t dir_index_base, uint32_t design_index, int32_t samples, double* dF,
-                     int64_t* n_edges_out, int32_t n_threads)
+                     uint64_t seed, int64_t dir_index_base, uint32_t design_index, int32_t samples,
+                     const uint8_t* keep, int64_t n_keep, double* dF, int64_t* n_edges_out, int32_t n_threads)
 {
     if (!verts || !tris || !vert_hinge || (n_hinges > 0 && (!hinge_origin || !hinge_axis)) || !rho_s || !rho_d ||
         !sun_dirs || !frames || !dF || bounces < 1 || samples < 1 || n_dirs < 0 || n_hinges < 0)
@@ -1297,6 +1305,11 @@ int oracle_edge_term(const double* verts, int64_t n_verts, const int32_t* tris, 
         return ORC_ENOMEM;
     }
     if (n_edges_out) *n_edges_out = ne;
+    if (keep && n_keep != ne) {
+        free(E);
+        scene_free(&S);
+        return ORC_EINVAL;
+    }
     memset(dF, 0, sizeof(double) * 6 * (size_t)(n_dirs * n_hinges));
     params_t P = {1, 1, bounces, 0, flux, seed, dir_index_base, design_index};
     if (n_threads < 1) n_threads = 1;
@@ -1304,7 +1317,7 @@ int oracle_edge_term(const double* verts, int64_t n_verts, const int32_t* tris, 
     edge_job_t* jobs = malloc(sizeof(edge_job_t) * n_threads);
     for (int32_t t = 0; t < n_threads; ++t) {
         edge_job_t J = {&S, &P, E, ne, verts, hinge_origin, hinge_axis, n_hinges, frames, sun_dirs, n_dirs, samples,
-                        dF, n_threads, t};
+                        keep, dF, n_threads, t};
         jobs[t] = J;
         pthread_create(&th[t], NULL, edge_worker, &jobs[t]);
     }
