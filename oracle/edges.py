@@ -14,36 +14,49 @@ facets another hinge or the rigid body carries) is kept.
 The rule, per distinct moving edge (the numbering of oracle_edge_term: edges of facets whose
 three vertices one hinge carries, by first appearance over facets and edge slots, coincident
 edges counted once):
-  * the facets that contain the edge and are carried by a hinge are grouped by unit normal
-    (components equal within `tol`);
-  * the edge is smooth when every group holds exactly two facets, whose third vertices lie on
-    opposite sides of the edge, with equal rho_s, rho_d and (when given) p_spec.
-The two layers of a two-sided sheet form two groups (opposite normals), each checked on its own.
+  * every facet of the mesh that contains the edge (both endpoint positions) must be carried by
+    the edge's hinge (a facet of the rigid body or of another hinge moves differently);
+  * those facets are grouped by unit normal (components equal within `tol`); there are at most
+    two groups, and two only with opposite normals (the two layers of a two-sided sheet, each
+    checked on its own; planes that cross at the edge are a visibility discontinuity);
+  * every group holds exactly two facets, whose third vertices lie on opposite sides of the edge,
+    with equal rho_s, rho_d and (when given) p_spec.
 """
 import numpy as np
+
+
+def _carrier(vh, t):
+    """The hinge carrying all three vertices of facet t, else -1."""
+    k = int(vh[t[0]])
+    return k if k >= 0 and vh[t[1]] == k and vh[t[2]] == k else -1
 
 
 def moving_edges(verts, tris, vert_hinge):
     """Distinct edges of hinge-carried facets in order of first appearance.
 
-    Returns a list of (a, b, hinge, incident), incident = [(facet, opposite vertex), ...] over the
-    hinge-carried facets containing the edge (matched by the two endpoint positions)."""
+    Returns a list of (a, b, hinge, incident), incident = [(facet, opposite vertex), ...] over all
+    facets of the mesh containing the edge (matched by the two endpoint positions)."""
     V = np.asarray(verts, dtype=np.float64)
     T = np.asarray(tris)
     vh = np.asarray(vert_hinge)
     index = {}
     out = []
     for f, t in enumerate(T):
-        k = int(vh[t[0]])
-        if k < 0 or vh[t[1]] != k or vh[t[2]] != k:
+        k = _carrier(vh, t)
+        if k < 0:
             continue
         for slot in range(3):
-            a, b, c = int(t[slot]), int(t[(slot + 1) % 3]), int(t[(slot + 2) % 3])
+            a, b = int(t[slot]), int(t[(slot + 1) % 3])
             key = tuple(sorted([tuple(V[a]), tuple(V[b])]))
             if key not in index:
                 index[key] = len(out)
                 out.append((a, b, k, []))
-            out[index[key]][3].append((f, c))
+    for f, t in enumerate(T):
+        for slot in range(3):
+            a, b, c = int(t[slot]), int(t[(slot + 1) % 3]), int(t[(slot + 2) % 3])
+            key = tuple(sorted([tuple(V[a]), tuple(V[b])]))
+            if key in index:
+                out[index[key]][3].append((f, c))
     return out
 
 
@@ -55,9 +68,12 @@ def smooth_edge_mask(verts, tris, vert_hinge, rho_s, rho_d, p_spec=None, tol=1e-
     rs = np.asarray(rho_s, dtype=np.float32)
     rd = np.asarray(rho_d, dtype=np.float32)
     ps = None if p_spec is None else np.asarray(p_spec, dtype=np.float32)
-    edges = moving_edges(V, T, vert_hinge)
+    vh = np.asarray(vert_hinge)
+    edges = moving_edges(V, T, vh)
     out = np.zeros(len(edges), dtype=bool)
-    for e, (a, b, _, incident) in enumerate(edges):
+    for e, (a, b, k, incident) in enumerate(edges):
+        if any(_carrier(vh, T[f]) != k for f, _ in incident):
+            continue
         groups = []
         for f, c in incident:
             p = V[T[f]]
@@ -69,6 +85,8 @@ def smooth_edge_mask(verts, tris, vert_hinge, rho_s, rho_d, p_spec=None, tol=1e-
                     break
             else:
                 groups.append((n, [(f, c)]))
+        if len(groups) > 2 or (len(groups) == 2 and np.abs(groups[0][0] + groups[1][0]).max() > tol):
+            continue
         smooth = True
         for n, members in groups:
             if len(members) != 2:

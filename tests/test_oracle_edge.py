@@ -224,13 +224,21 @@ def test_smooth_edges_are_the_flat_interior_ones():
     rd2 = np.concatenate([rd, np.full(len(t), 0.2, np.float32)])
     s2 = smooth_edge_mask(V2, T2, vh2, rs2, rd2)
     assert len(s2) == len(edges) and (s2 == smooth).all()
-    # a rigid facet on an edge of the panel does not make that edge smooth
-    vr = np.array([[-0.6, 0.2, 0.0], [0.6, 0.2, 0.0], [0.0, -0.5, 0.0]])
-    V3 = np.concatenate([v, vr])
-    T3 = np.concatenate([t, np.array([[len(v) + 1, len(v), len(v) + 2]])]).astype(np.int32)
-    vh3 = np.concatenate([vh, np.full(3, -1, np.int32)])
-    s3 = smooth_edge_mask(V3, T3, vh3, np.append(rs, 0.3).astype(np.float32), np.append(rd, 0.25).astype(np.float32))
-    assert (s3 == smooth).all()
+    # an interior edge that a rigid facet also contains, or that a second (crossing) plane of the
+    # same hinge passes through, is kept
+    e_in = int(np.flatnonzero(smooth)[0])
+    a, b = edges[e_in][0], edges[e_in][1]
+    top, bottom = (v[a] + v[b]) / 2 + [0, 0, 0.3], (v[a] + v[b]) / 2 - [0, 0, 0.3]
+    V3 = np.concatenate([v, [top, bottom]])
+    mat3 = lambda k: (np.append(rs, [0.3] * k).astype(np.float32), np.append(rd, [0.25] * k).astype(np.float32))
+    T3 = np.concatenate([t, [[a, b, len(v)]]]).astype(np.int32)
+    vh3 = np.concatenate([vh, [-1, -1]]).astype(np.int32)
+    s3 = smooth_edge_mask(V3, T3, vh3, *mat3(1))
+    assert s3.sum() == smooth.sum() - 1 and not s3[e_in]
+    T4 = np.concatenate([t, [[a, b, len(v)], [b, a, len(v) + 1]]]).astype(np.int32)
+    vh4 = np.concatenate([vh, [0, 0]]).astype(np.int32)
+    s4 = smooth_edge_mask(V3, T4, vh4, *mat3(2))
+    assert not s4[e_in] and s4.sum() == smooth.sum() - 1
 
 
 def test_leaving_out_smooth_edges_changes_the_estimate_by_order_delta():
