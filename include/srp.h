@@ -219,7 +219,12 @@ srp_status srp_trace_records(srp_scene scene, const double* sun_dirs, int64_t D,
  *                           design)), the jump of their deposit times the edge's normal image
  *                           velocity (silhouettes against the background or other surfaces,
  *                           occlusion, edges between facets).  Edges are numbered by first
- *                           appearance over the facets; coincident edges count once.  Left out:
+ *                           appearance over the facets; coincident edges count once.  An edge
+ *                           across which the surface continues in one plane (every facet on it
+ *                           riding its hinge, one facet on each side of each layer) with equal
+ *                           rho_s, rho_d and p_spec on both sides carries no jump and is skipped,
+ *                           keeping its number (the first edge-sampled call after a change of the
+ *                           scene synchronises `stream` once to classify the edges).  Left out:
  *                           visibility edges of reflected light, and the dependence of the grid
  *                           frame on the design (the estimator's expectation does not depend on
  *                           it).  With edge terms, at most 65535 directions per call.

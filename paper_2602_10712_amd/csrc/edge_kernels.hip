@@ -8,11 +8,18 @@
 // moving edge, (Phi/c) int_edge (g(y - delta n) - g(y + delta n)) v_n dl: n the edge's unit
 // normal in the grid plane, v_n the normal image velocity of the edge point under the rotation.
 //
-// k_edge_term  one lane per (edge, sample): sample s = (m + xi)/M along moving edge e, the two side
-//              points y -+ delta n (delta = the secondary-ray offset, 1e-5 L) each start a full path
-//              with the same Philox draws (key seed ^ kEdgeKey, counter (e M + m, direction,
-//              bounce, design)), and the lane adds (Phi/c)(len/M) v_n (deposit(y-) - deposit(y+))
-//              contracted with the direction's cotangents to its hinge.  Paths are walked per lane:
+// Across an edge where the moving surface continues in one plane with the same material on both
+// sides, g is continuous (the two side paths meet the same plane and material and leave with the
+// same draws; their deposits differ by O(delta)), so such edges carry no term and are left out:
+// k_edge_keep marks them from facet pairs found on the host, and only the other edges are launched.
+//
+// k_edge_keep  one thread per moving edge: compares the packed materials of its facet pairs.
+// k_edge_term  one lane per (edge, sample): sample s = (m + xi)/M along moving edge e (e its index
+//              among all moving edges), the two side points y -+ delta n (delta = the
+//              secondary-ray offset, 1e-5 L) each start a full path with the same Philox draws
+//              (key seed ^ kEdgeKey, counter (e M + m, direction, bounce, design)), and the lane
+//              adds (Phi/c)(len/M) v_n (deposit(y-) - deposit(y+)) contracted with the direction's
+//              cotangents to its hinge.  Paths are walked per lane:
 //              a wave holds the samples of a few edges that can each span the whole panel, so the
 //              union of the nodes its side paths need is large (the wave-coherent walk, tried for
 //              the parallel first segments, took twice as long).
@@ -117,7 +124,7 @@ __global__ __launch_bounds__(256) void k_edge_term(EdgeArgs E, const BvhNode* __
     const float nu_ = live ? tv / len : 0.0f, nv_ = live ? -tu / len : 0.0f;
     const uint32_t key_lo = E.seed_lo ^ static_cast<uint32_t>(kEdgeKey);
     const uint32_t key_hi = E.seed_hi ^ static_cast<uint32_t>(kEdgeKey >> 32);
-    const uint32_t ctr0 = static_cast<uint32_t>(static_cast<int64_t>(e) * E.samples + m);
+    const uint32_t ctr0 = static_cast<uint32_t>(static_cast<int64_t>(ed.w) * E.samples + m);
     uint32_t c0 = ctr0, c1 = dir, c2 = 0u, c3 = E.design_index;
     philox4x32_10(c0, c1, c2, c3, key_lo, key_hi);
     const float sp = (static_cast<float>(m) + unit24(c0)) / static_cast<float>(E.samples);
@@ -166,6 +173,22 @@ __global__ __launch_bounds__(256) void k_edge_term(EdgeArgs E, const BvhNode* __
     }
 }
 
+__device__ __forceinline__ bool same_material(float4 a, float4 b)
+{
+    return a.x == b.x && a.y == b.y && a.z == b.z;
+}
+
+__global__ void k_edge_keep(const int4* __restrict__ pairs, int32_t n, const int32_t* __restrict__ bvh_pos,
+                            const float4* __restrict__ mat, int32_t* __restrict__ keep)
+{
+    const int32_t i = static_cast<int32_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int4 p = pairs[i];
+    bool flat = p.x >= 0 && same_material(mat[bvh_pos[p.x]], mat[bvh_pos[p.y]]);
+    if (flat && p.z >= 0) flat = same_material(mat[bvh_pos[p.z]], mat[bvh_pos[p.w]]);
+    keep[i] = flat ? 0 : 1;
+}
+
 __global__ void k_add_edges(const double* __restrict__ partials, int64_t D, int32_t blocks,
                             double* __restrict__ per_dir)
 {
@@ -184,6 +207,15 @@ int32_t edge_blocks(const EdgeArgs& E)
 {
     const int64_t n = static_cast<int64_t>(E.n_edges) * E.samples;
     return static_cast<int32_t>((n + 255) / 256);
+}
+
+hipError_t launch_edge_keep(const int4* pairs, int32_t n, const int32_t* bvh_pos, const float4* mat, int32_t* keep,
+                            hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge_keep, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, pairs, n,
+                       bvh_pos, mat, keep);
+    return hipGetLastError();
 }
 
 hipError_t launch_edge_term(const EdgeArgs& E, const BvhNode* nodes, const TriRec* tris, const float4* mat,

@@ -86,6 +86,22 @@ struct srp_scene_s {
     std::vector<int4> h_edges;
     int4* d_edges = nullptr;
     size_t edges_cap = 0;
+    // per moving edge, the facets on its two sides where the surface continues in one plane on
+    // the edge's hinge (original indices a0, b0 and, for the back layer of a two-sided sheet,
+    // a1, b1; a1 = -1: one layer; a0 = -1: no such continuation, the edge is always taken), from
+    // the rest pose
+    std::vector<int4> h_edge_pairs;
+    int4* d_edge_pairs = nullptr;
+    size_t edge_pairs_cap = 0;
+    // the edges the edge term takes under the current materials (vertex a, vertex b, hinge, index
+    // among all moving edges, which keys its draws), classified by the first edge-sampled adjoint
+    // after a change of the scene
+    std::vector<int4> h_live_edges;
+    int4* d_live_edges = nullptr;
+    size_t live_edges_cap = 0;
+    int32_t* d_edge_keep = nullptr;
+    size_t edge_keep_cap = 0;
+    uint64_t edge_class_gen = ~0ull;
     // multi-world surface sampling: rest-pose records grouped by part (kept while the rest pose and
     // the facet groups stay the same) and the per-sample output of the last call
     srp::TriRec* d_mw_tris = nullptr;

@@ -124,28 +124,149 @@ double scene_size(const std::vector<double>& v, int64_t n)
     return 2.0 * std::sqrt(r2);
 }
 
+// The hinge carrying all three vertices of facet f, else -1.
+int32_t facet_hinge(const srp_scene_s* s, int64_t f)
+{
+    const int32_t* t = &s->tris[3 * f];
+    const int32_t k = s->vhinge[t[0]];
+    return k >= 0 && s->vhinge[t[1]] == k && s->vhinge[t[2]] == k ? k : -1;
+}
+
+std::array<double, 6> edge_key(const srp_scene_s* s, int32_t a, int32_t b)
+{
+    const double* pa = &s->rest[3 * static_cast<int64_t>(a)];
+    const double* pb = &s->rest[3 * static_cast<int64_t>(b)];
+    const bool swap = std::lexicographical_compare(pb, pb + 3, pa, pa + 3);
+    const double* lo = swap ? pb : pa;
+    const double* hi = swap ? pa : pb;
+    return {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]};
+}
+
+// Where the surface continues across moving edge `ed` in one plane: every facet containing the
+// edge rides the edge's hinge, their unit normals (rest pose) fall into at most two groups with
+// opposite normals (the layers of a two-sided sheet), and each group holds two facets whose
+// third vertices lie on opposite sides of the edge.  Returns the two facet pairs (a0, b0, a1, b1;
+// a1 = b1 = -1 for one layer), or all -1 when the edge is not such a continuation.
+int4 flat_continuation(const srp_scene_s* s, const int4& ed, const std::vector<int2>& incident)
+{
+    const int4 none = make_int4(-1, -1, -1, -1);
+    constexpr double kTol = 1e-9;
+    struct Group {
+        double n[3];
+        int32_t f[2], c[2];
+        int count;
+    } g[2];
+    int ng = 0;
+    for (const int2& fc : incident) {
+        if (facet_hinge(s, fc.x) != ed.z) return none;
+        const double* p0 = &s->rest[3 * static_cast<int64_t>(s->tris[3 * static_cast<int64_t>(fc.x)])];
+        const double* p1 = &s->rest[3 * static_cast<int64_t>(s->tris[3 * static_cast<int64_t>(fc.x) + 1])];
+        const double* p2 = &s->rest[3 * static_cast<int64_t>(s->tris[3 * static_cast<int64_t>(fc.x) + 2])];
+        const double e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+        const double e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+        double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (double& x : n) x /= len;
+        int gi = -1;
+        for (int q = 0; q < ng && gi < 0; ++q)
+            if (std::max({std::fabs(g[q].n[0] - n[0]), std::fabs(g[q].n[1] - n[1]), std::fabs(g[q].n[2] - n[2])}) <= kTol)
+                gi = q;
+        if (gi < 0) {
+            if (ng == 2) return none;
+            gi = ng++;
+            std::copy(n, n + 3, g[gi].n);
+            g[gi].count = 0;
+        }
+        if (g[gi].count == 2) return none;
+        g[gi].f[g[gi].count] = fc.x;
+        g[gi].c[g[gi].count] = fc.y;
+        ++g[gi].count;
+    }
+    if (ng == 0) return none;
+    if (ng == 2 && std::max({std::fabs(g[0].n[0] + g[1].n[0]), std::fabs(g[0].n[1] + g[1].n[1]),
+                             std::fabs(g[0].n[2] + g[1].n[2])}) > kTol)
+        return none;
+    const double* pa = &s->rest[3 * static_cast<int64_t>(ed.x)];
+    const double* pb = &s->rest[3 * static_cast<int64_t>(ed.y)];
+    const double ab[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
+    for (int q = 0; q < ng; ++q) {
+        if (g[q].count != 2) return none;
+        double side[2];
+        for (int i = 0; i < 2; ++i) {
+            const double* pc = &s->rest[3 * static_cast<int64_t>(g[q].c[i])];
+            const double ac[3] = {pc[0] - pa[0], pc[1] - pa[1], pc[2] - pa[2]};
+            const double cr[3] = {ab[1] * ac[2] - ab[2] * ac[1], ab[2] * ac[0] - ab[0] * ac[2],
+                                  ab[0] * ac[1] - ab[1] * ac[0]};
+            side[i] = cr[0] * g[q].n[0] + cr[1] * g[q].n[1] + cr[2] * g[q].n[2];
+        }
+        if (!(side[0] * side[1] < 0.0)) return none;
+    }
+    return make_int4(g[0].f[0], g[0].f[1], ng == 2 ? g[1].f[0] : -1, ng == 2 ? g[1].f[1] : -1);
+}
+
 // The distinct edges of hinge-carried facets (all three vertices on one hinge), in order of first
 // appearance over the facets and their edge slots; edges at the same pair of rest positions (the
-// two layers of a two-sided sheet, the edge two facets share) are one edge.
+// two layers of a two-sided sheet, the edge two facets share) are one edge.  Also the facet pairs
+// across which each of them continues the surface in one plane (flat_continuation).
 void build_moving_edges(srp_scene_s* s)
 {
     s->h_edges.clear();
-    std::map<std::array<double, 6>, int> seen;
+    s->h_edge_pairs.clear();
+    std::map<std::array<double, 6>, int32_t> seen;
     for (int64_t f = 0; f < s->n_tris; ++f) {
+        const int32_t k = facet_hinge(s, f);
+        if (k < 0) continue;
         const int32_t* t = &s->tris[3 * f];
-        const int32_t k = s->vhinge[t[0]];
-        if (k < 0 || s->vhinge[t[1]] != k || s->vhinge[t[2]] != k) continue;
         for (int e = 0; e < 3; ++e) {
             const int32_t a = t[e], b = t[(e + 1) % 3];
-            const double* pa = &s->rest[3 * a];
-            const double* pb = &s->rest[3 * b];
-            const bool swap = std::lexicographical_compare(pb, pb + 3, pa, pa + 3);
-            const double* lo = swap ? pb : pa;
-            const double* hi = swap ? pa : pb;
-            const std::array<double, 6> key = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]};
-            if (seen.emplace(key, 1).second) s->h_edges.push_back(make_int4(a, b, k, 0));
+            if (seen.emplace(edge_key(s, a, b), static_cast<int32_t>(s->h_edges.size())).second)
+                s->h_edges.push_back(make_int4(a, b, k, 0));
         }
     }
+    if (s->h_edges.empty()) return;
+    std::vector<std::vector<int2>> incident(s->h_edges.size());  // (facet, opposite vertex)
+    for (int64_t f = 0; f < s->n_tris; ++f) {
+        const int32_t* t = &s->tris[3 * f];
+        for (int e = 0; e < 3; ++e) {
+            const auto it = seen.find(edge_key(s, t[e], t[(e + 1) % 3]));
+            if (it != seen.end()) incident[it->second].push_back(make_int2(static_cast<int32_t>(f), t[(e + 2) % 3]));
+        }
+    }
+    for (size_t i = 0; i < s->h_edges.size(); ++i)
+        s->h_edge_pairs.push_back(flat_continuation(s, s->h_edges[i], incident[i]));
+}
+
+// The edges the edge term takes under the current materials: an edge is left out where the
+// surface continues across it in one plane with the same (rho_s, rho_d, p_spec) on both sides of
+// every layer, since the momentum a path deposits is continuous there (the two side paths differ
+// by O(delta) only).  Synchronises `stream`.
+hipError_t classify_edges(srp_scene_s* s, hipStream_t stream)
+{
+    const size_t n = s->h_edges.size();
+    hipError_t e = ensure(s->d_edge_keep, s->edge_keep_cap, n);
+    if (e == hipSuccess)
+        e = srp::launch_edge_keep(s->d_edge_pairs, static_cast<int32_t>(n), s->d_bvh_pos, s->d_mat, s->d_edge_keep,
+                                  stream);
+    std::vector<int32_t> keep(n);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(keep.data(), s->d_edge_keep, sizeof(int32_t) * n, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    s->h_live_edges.clear();
+    for (size_t i = 0; i < n; ++i)
+        if (keep[i])
+            s->h_live_edges.push_back(
+                make_int4(s->h_edges[i].x, s->h_edges[i].y, s->h_edges[i].z, static_cast<int32_t>(i)));
+    if (!s->h_live_edges.empty()) {
+        e = ensure(s->d_live_edges, s->live_edges_cap, s->h_live_edges.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->d_live_edges, s->h_live_edges.data(), sizeof(int4) * s->h_live_edges.size(),
+                               hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+    }
+    s->edge_class_gen = s->geom_gen;
+    return hipSuccess;
 }
 
 // Current vertex positions (FP32) for the edge terms; synchronous with `stream`.
@@ -167,11 +288,16 @@ hipError_t upload_vertices(srp_scene_s* s, hipStream_t stream)
 hipError_t upload_edges(srp_scene_s* s, hipStream_t stream)
 {
     build_moving_edges(s);
+    s->edge_class_gen = ~0ull;
     if (s->h_edges.empty()) return hipSuccess;
     hipError_t e = ensure(s->d_edges, s->edges_cap, s->h_edges.size());
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->d_edges, s->h_edges.data(), sizeof(int4) * s->h_edges.size(), hipMemcpyHostToDevice,
                            stream);
+    if (e == hipSuccess) e = ensure(s->d_edge_pairs, s->edge_pairs_cap, s->h_edge_pairs.size());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_edge_pairs, s->h_edge_pairs.data(), sizeof(int4) * s->h_edge_pairs.size(),
+                           hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = upload_vertices(s, stream);
     return e;
 }
@@ -775,6 +901,8 @@ static srp_status adjoint_into(srp_scene s, const double* sun_dirs, int64_t D, c
     st = bind_device(s);
     if (st != SRP_OK) return st;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const bool edges = g_hinge && p->edge_samples > 0 && !s->h_edges.empty();
+    if (edges && s->edge_class_gen != s->geom_gen) SRP_HIP(classify_edges(s, stream));
     srp::AdjointArgs A{};
     st = prepare_trace(s, sun_dirs, D, p, frames, false, nullptr, 0, nullptr, nullptr, stream, A.t);
     if (st != SRP_OK) return st;
@@ -796,11 +924,11 @@ static srp_status adjoint_into(srp_scene s, const double* sun_dirs, int64_t D, c
     SRP_HIP(srp::launch_adjoint(A, stream));
     if (A.n_hinges > 0) {
         SRP_HIP(srp::launch_reduce_hinges(s->d_partials, D, A.t.blocks_per_dir, s->d_hdir, stream));
-        if (p->edge_samples > 0 && !s->h_edges.empty()) {
+        if (edges && !s->h_live_edges.empty()) {
             srp::EdgeArgs E{};
-            E.edges = s->d_edges;
+            E.edges = s->d_live_edges;
             E.verts = s->d_vpos;
-            E.n_edges = static_cast<int32_t>(s->h_edges.size());
+            E.n_edges = static_cast<int32_t>(s->h_live_edges.size());
             E.samples = p->edge_samples;
             E.D = D;
             E.bounces = p->bounces;
@@ -1369,6 +1497,9 @@ srp_status srp_scene_destroy(srp_scene s)
     (void)hipFree(s->d_surf_desc);
     (void)hipFree(s->d_lbvh_ws);
     (void)hipFree(s->d_edges);
+    (void)hipFree(s->d_edge_pairs);
+    (void)hipFree(s->d_live_edges);
+    (void)hipFree(s->d_edge_keep);
     (void)hipFree(s->d_phong);
     (void)hipFree(s->d_mw_tris);
     (void)hipFree(s->d_mw_pos);

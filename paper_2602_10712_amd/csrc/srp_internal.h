@@ -268,7 +268,7 @@ hipError_t launch_adjoint(const AdjointArgs& a, hipStream_t stream);
 
 // Visibility-edge terms of the hinge-angle gradient (edge_kernels.hip).
 struct EdgeArgs {
-    const int4* edges;      // [n_edges]: vertex a, vertex b, hinge, 0 (distinct moving edges)
+    const int4* edges;      // [n_edges]: vertex a, vertex b, hinge, index among all moving edges
     const float4* verts;    // [n_verts] current vertex positions
     int32_t n_edges;
     int32_t samples;        // points per edge
@@ -284,6 +284,10 @@ struct EdgeArgs {
     float hinge_axis[kMaxHinges][3];
 };
 int32_t edge_blocks(const EdgeArgs& E);
+// keep[i] = 0 where pairs[i] (facet pairs, original indices; x < 0: none) have equal packed
+// materials (rho_s, rho_d, p_spec) on both sides of every layer, else 1.
+hipError_t launch_edge_keep(const int4* pairs, int32_t n, const int32_t* bvh_pos, const float4* mat, int32_t* keep,
+                            hipStream_t stream);
 hipError_t launch_edge_term(const EdgeArgs& E, const BvhNode* nodes, const TriRec* tris, const float4* mat,
                             const DevFrame* frames, const double* g_force, const double* g_torque, int lane_walk,
                             double* partials, double* per_dir, hipStream_t stream);

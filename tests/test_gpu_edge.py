@@ -5,7 +5,9 @@ satellite.
 
   * same draws on both sides: the GPU's edge part (its adjoint with M edge samples minus the same
     adjoint without) equals the oracle's oracle_edge_term contracted with the cotangents, hinge by
-    hinge, to FP32 rounding and rare degenerate side paths;
+    hinge, to FP32 rounding and rare degenerate side paths; with per-facet materials (every edge a
+    material boundary) and with the design's group materials (the 5,888 interior edges of the
+    flat panels skipped on both sides), one scene re-classifying its edges after each design;
   * unbiasedness on the satellite: pathwise + edge, averaged over four jitter seeds at 1024^2, vs a
     central difference (h = 0.01) of the forward trace averaged over the same seeds; the pathwise
     part alone is printed beside it (its gap is the visibility-edge effect the paper names as the
@@ -28,9 +30,9 @@ def _lib():
 
 
 def test_edge_part_matches_oracle():
+    from oracle.edges import smooth_edge_mask
     p = _lib()
     m = si.meo_satellite()
-    rs, rd = si.materials(m.n_tris, 3)
     ang0 = [0.3, -0.25]
     V0 = apply_hinges(m.verts, m.vert_hinge, m.hinge_origin, m.hinge_axis, ang0)
     sun = si.fibonacci_dirs(1024)[[100, 350, 600, 900]]
@@ -40,22 +42,27 @@ def test_edge_part_matches_oracle():
     nu = nv = 64
     M = 4
     sc = p.Scene.from_mesh(m)
-    sc.set_design(rs, rd, hinge_angles=ang0)
-    assert np.allclose(sc.vertices(), V0, rtol=0, atol=1e-12)
     fr = oracle.frames(V0, sun, nu, nv)
-    _, _, g0 = sc.adjoint(sun, p.TraceParams(nu=nu, nv=nv, bounces=3, seed=8, frame_mode=1), gF, gT, frames=fr)
-    _, _, g1 = sc.adjoint(sun, p.TraceParams(nu=nu, nv=nv, bounces=3, seed=8, frame_mode=1, edge_samples=M), gF, gT,
-                          frames=fr)
-    torch.cuda.synchronize()
-    gpu_edge = g1.cpu().numpy() - g0.cpu().numpy()
-    dF, n_edges = oracle.edge_term(V0, m.tris, m.vert_hinge, m.hinge_origin, m.hinge_axis, rs, rd, sun, fr,
-                                   bounces=3, seed=8, samples=M)
-    orc_edge = np.einsum("jkc,jc->k", dF[:, :, :3], gF) + np.einsum("jkc,jc->k", dF[:, :, 3:], gT)
-    scale = np.abs(orc_edge).max()
-    err = np.abs(gpu_edge - orc_edge) / scale
-    print(f"{n_edges} moving edges x {M} points x 4 directions: edge part GPU {gpu_edge}, oracle {orc_edge}, "
-          f"rel err {err}")
-    assert np.all(err <= 2e-3)
+    design = np.concatenate([ang0, [0.2, 0.3, 0.1, 0.4, 0.25, 0.15]])
+    for name, (rs, rd) in (("group", si.design_materials(m, design)), ("per-facet", si.materials(m.n_tris, 3)),
+                           ("group again", si.design_materials(m, design))):
+        sc.set_design(rs, rd, hinge_angles=ang0)
+        assert np.allclose(sc.vertices(), V0, rtol=0, atol=1e-12)
+        _, _, g0 = sc.adjoint(sun, p.TraceParams(nu=nu, nv=nv, bounces=3, seed=8, frame_mode=1), gF, gT, frames=fr)
+        _, _, g1 = sc.adjoint(sun, p.TraceParams(nu=nu, nv=nv, bounces=3, seed=8, frame_mode=1, edge_samples=M), gF,
+                              gT, frames=fr)
+        torch.cuda.synchronize()
+        gpu_edge = g1.cpu().numpy() - g0.cpu().numpy()
+        dF, n_edges = oracle.edge_term(V0, m.tris, m.vert_hinge, m.hinge_origin, m.hinge_axis, rs, rd, sun, fr,
+                                       bounces=3, seed=8, samples=M)
+        n_smooth = int(smooth_edge_mask(V0, m.tris, m.vert_hinge, rs, rd).sum())
+        assert n_smooth == (5888 if name.startswith("group") else 0)
+        orc_edge = np.einsum("jkc,jc->k", dF[:, :, :3], gF) + np.einsum("jkc,jc->k", dF[:, :, 3:], gT)
+        scale = np.abs(orc_edge).max()
+        err = np.abs(gpu_edge - orc_edge) / scale
+        print(f"{name} materials: {n_edges} moving edges ({n_smooth} skipped) x {M} points x 4 directions: "
+              f"edge part GPU {gpu_edge}, oracle {orc_edge}, rel err {err}")
+        assert np.all(err <= 2e-3)
     sc.close()
 
 
