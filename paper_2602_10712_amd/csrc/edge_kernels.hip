@@ -19,10 +19,12 @@
 //              secondary-ray offset, 1e-5 L) each start a full path with the same Philox draws
 //              (key seed ^ kEdgeKey, counter (e M + m, direction, bounce, design)), and the lane
 //              adds (Phi/c)(len/M) v_n (deposit(y-) - deposit(y+)) contracted with the direction's
-//              cotangents to its hinge.  Paths are walked per lane:
-//              a wave holds the samples of a few edges that can each span the whole panel, so the
-//              union of the nodes its side paths need is large (the wave-coherent walk, tried for
-//              the parallel first segments, took twice as long).
+//              cotangents to its hinge.  Paths are walked per lane: a wave holds the samples of
+//              a few edges that can each span the whole panel, so the union of the nodes its side
+//              paths need is large (the wave-coherent walk, tried for the parallel first segments,
+//              took twice as long).  The lane's two side paths run 2 delta apart, mostly through
+//              the same nodes and, after equal interactions, in the same directions, so both are
+//              walked in one traversal (closest_hit_pair) that fetches each node once.
 // k_add_edges  per-direction sums of the workgroup partials, added in a fixed order to the
 //              per-direction hinge sums of the adjoint.
 #include <float.h>
@@ -83,6 +85,157 @@ __device__ __forceinline__ void edge_path(const BvhNode* __restrict__ nodes, con
     }
 }
 
+// Closest hits of a lane's two side rays in one per-lane walk: a node is entered when either ray
+// meets its box before that ray's best hit, the nearer child first by the smaller of the two rays'
+// entry distances, and a leaf's triangles are tested against both rays.  Every node a ray meets is
+// visited and a ray's closest hit (with its index tie-break) does not depend on the visiting
+// order, so each ray gets the hit of its own walk (closest_hit_lane); the two rays start 2 delta
+// apart along one direction and mostly visit the same nodes, whose records are fetched once.
+__device__ __forceinline__ void closest_hit_pair(const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris,
+                                                 const float (&o)[2][3], const float (&d)[2][3],
+                                                 const bool (&alive)[2], const int (&skip)[2], float (&t_out)[2],
+                                                 int (&hit_out)[2], int* __restrict__ lstack)
+{
+    float ix[2], iy[2], iz[2], nx[2], ny[2], nz[2], tbest[2];
+    int hit_id[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        ix[r] = safe_rcp(d[r][0]);
+        iy[r] = safe_rcp(d[r][1]);
+        iz[r] = safe_rcp(d[r][2]);
+        nx[r] = -o[r][0] * ix[r];
+        ny[r] = -o[r][1] * iy[r];
+        nz[r] = -o[r][2] * iz[r];
+        tbest[r] = alive[r] ? FLT_MAX : -1.0f;
+        hit_out[r] = -1;
+        hit_id[r] = 0x7fffffff;
+    }
+    int sp = 0;
+    int cur = alive[0] || alive[1] ? 0 : kWalkDone;
+    while (cur != kWalkDone) {
+        if (cur >= 0) {
+            const BvhNode* N = nodes + cur;
+            const float4 f0 = N->f[0];
+            const float4 f1 = N->f[1];
+            const float4 f2 = N->f[2];
+            const float4 f3 = N->f[3];
+            const int c0 = __float_as_int(f3.x);
+            const int c1 = __float_as_int(f3.y);
+            bool h0 = false, h1 = false;
+            float n0 = FLT_MAX, n1 = FLT_MAX;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const float ax0 = fmaf(f0.x, ix[r], nx[r]), ax1 = fmaf(f0.y, ix[r], nx[r]);
+                const float ay0 = fmaf(f0.z, iy[r], ny[r]), ay1 = fmaf(f0.w, iy[r], ny[r]);
+                const float az0 = fmaf(f2.x, iz[r], nz[r]), az1 = fmaf(f2.y, iz[r], nz[r]);
+                const float bx0 = fmaf(f1.x, ix[r], nx[r]), bx1 = fmaf(f1.y, ix[r], nx[r]);
+                const float by0 = fmaf(f1.z, iy[r], ny[r]), by1 = fmaf(f1.w, iy[r], ny[r]);
+                const float bz0 = fmaf(f2.z, iz[r], nz[r]), bz1 = fmaf(f2.w, iz[r], nz[r]);
+                const float tn0 = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), 0.0f));
+                const float tf0 = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tbest[r]));
+                const float tn1 = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), 0.0f));
+                const float tf1 = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tbest[r]));
+                if (tn0 <= tf0) {
+                    h0 = true;
+                    n0 = fminf(n0, tn0);
+                }
+                if (tn1 <= tf1) {
+                    h1 = true;
+                    n1 = fminf(n1, tn1);
+                }
+            }
+            if (h0 && h1) {
+                const bool swap = n1 < n0;
+                lstack[sp * 64] = swap ? c0 : c1;
+                ++sp;
+                cur = swap ? c1 : c0;
+            } else if (h0) {
+                cur = c0;
+            } else if (h1) {
+                cur = c1;
+            } else if (sp > 0) {
+                --sp;
+                cur = lstack[sp * 64];
+            } else {
+                cur = kWalkDone;
+            }
+        } else {
+            const int code = ~cur;
+            const int first = code >> 3;
+            const int cnt = code & 7;
+            for (int q = 0; q < cnt; ++q) {
+                const int tri = first + q;
+                const TriRec* T = tris + tri;
+                const float4 g0 = T->f[0];
+                const float4 g1 = T->f[1];
+                const float4 g2 = T->f[2];
+                const int id = __float_as_int(g0.w);
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const float t = tri_hit(o[r], d[r], g0, g1, g2);
+                    if (t > 0.0f && tri != skip[r] && (t < tbest[r] || (t == tbest[r] && id < hit_id[r]))) {
+                        tbest[r] = t;
+                        hit_out[r] = tri;
+                        hit_id[r] = id;
+                    }
+                }
+            }
+            if (sp > 0) {
+                --sp;
+                cur = lstack[sp * 64];
+            } else {
+                cur = kWalkDone;
+            }
+        }
+    }
+    t_out[0] = tbest[0];
+    t_out[1] = tbest[1];
+}
+
+// edge_path<true> for both side paths of a lane at once, every segment walked by closest_hit_pair;
+// each path takes exactly the steps it takes alone.
+__device__ __forceinline__ void edge_paths_pair(const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris,
+                                                const float4* __restrict__ mat, float (&o)[2][3], float (&d)[2][3],
+                                                bool live, int bounces, uint32_t ctr0, uint32_t dir, uint32_t design,
+                                                uint32_t key_lo, uint32_t key_hi, float eps, const float com[3],
+                                                int* lstack, float (&F)[2][3], float (&T)[2][3])
+{
+    float w[2] = {1.0f, 1.0f};
+    int skip[2] = {-1, -1};
+    bool alive[2] = {live, live};
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) F[r][c] = T[r][c] = 0.0f;
+    for (int b = 1; b <= bounces; ++b) {
+        if (wave_ballot(alive[0] || alive[1]) == 0) break;
+        float t[2];
+        int hit[2];
+        closest_hit_pair(nodes, tris, o, d, alive, skip, t, hit, lstack);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            if (!alive[r]) continue;
+            if (hit[r] < 0) {
+                alive[r] = false;
+                continue;
+            }
+            const TriRec tr = tris[hit[r]];
+            const float4 mt = mat[hit[r]];
+            const float n[3] = {tr.f[1].w, tr.f[2].w, tr.f[3].x};
+            float x[3], g[3];
+            alive[r] = interact(o[r], d[r], w[r], t[r], n, mt.x, mt.y, mt.z, b, bounces, ctr0, dir, design, key_lo,
+                                key_hi, eps, x, g);
+            const float l[3] = {x[0] - com[0], x[1] - com[1], x[2] - com[2]};
+            float tq[3];
+            cross3e(l, g, tq);
+            for (int c = 0; c < 3; ++c) {
+                F[r][c] += g[c];
+                T[r][c] += tq[c];
+            }
+            skip[r] = hit[r];
+        }
+    }
+}
+
 template <bool LANE>
 __global__ __launch_bounds__(256) void k_edge_term(EdgeArgs E, const BvhNode* __restrict__ nodes,
                                                    const TriRec* __restrict__ tris, const float4* __restrict__ mat,
@@ -139,16 +292,31 @@ __global__ __launch_bounds__(256) void k_edge_term(EdgeArgs E, const BvhNode* __
     float Fs[2][3], Ts[2][3];
     int* stack = s_stack[wave];
     int* lstack = &s_lane[wave][0][lane];
-    for (int side = 0; side < 2; ++side) {
-        const float sg = side == 0 ? -E.delta : E.delta;
-        const float au = yu + sg * nu_, av = yv + sg * nv_;
-        float o[3], d[3];
-        for (int c = 0; c < 3; ++c) {
-            o[c] = fr.o0[c] + au * u[c] + av * v[c];
-            d[c] = fr.d[c];
+    if (LANE) {
+        float o[2][3], d[2][3];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const float sg = side == 0 ? -E.delta : E.delta;
+            const float au = yu + sg * nu_, av = yv + sg * nv_;
+            for (int c = 0; c < 3; ++c) {
+                o[side][c] = fr.o0[c] + au * u[c] + av * v[c];
+                d[side][c] = fr.d[c];
+            }
         }
-        edge_path<LANE>(nodes, tris, mat, o, d, live, E.bounces, ctr0, dir, E.design_index, key_lo, key_hi, E.eps,
-                        E.com, stack, lstack, Fs[side], Ts[side]);
+        edge_paths_pair(nodes, tris, mat, o, d, live, E.bounces, ctr0, dir, E.design_index, key_lo, key_hi, E.eps,
+                        E.com, lstack, Fs, Ts);
+    } else {
+        for (int side = 0; side < 2; ++side) {
+            const float sg = side == 0 ? -E.delta : E.delta;
+            const float au = yu + sg * nu_, av = yv + sg * nv_;
+            float o[3], d[3];
+            for (int c = 0; c < 3; ++c) {
+                o[c] = fr.o0[c] + au * u[c] + av * v[c];
+                d[c] = fr.d[c];
+            }
+            edge_path<false>(nodes, tris, mat, o, d, live, E.bounces, ctr0, dir, E.design_index, key_lo, key_hi,
+                             E.eps, E.com, stack, lstack, Fs[side], Ts[side]);
+        }
     }
     // contribution to dL/d theta_h, L = gF . F + gT . tau
     const float flux_c = fr.w / (du * dv);
