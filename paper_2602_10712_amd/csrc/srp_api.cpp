@@ -469,7 +469,8 @@ int32_t lane_walk_for(int32_t depth)
         const char* e = std::getenv("SRP_SECONDARY_WALK");
         return e != nullptr && std::strcmp(e, "wave") == 0;
     }();
-    return !wave_only && depth <= srp::kLaneStack ? 1 : 0;
+    if (wave_only || depth > srp::kLaneStack) return 0;
+    return depth <= srp::kLaneStackShort ? 2 : 1;
 }
 
 srp_status check_params(const srp_trace_params* p)

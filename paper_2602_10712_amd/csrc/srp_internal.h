@@ -26,6 +26,8 @@ static_assert(kTilesPerWaveLarge <= kMaxTilesPerWave, "within the live-tile mask
 constexpr int kXcds = 8;           // MI355X: hardware workgroup b runs on accelerator complex b % 8
 constexpr int kMaxHinges = 4;     // hinge-angle gradients (adjoint) and multi-world hinges supported
 constexpr int kLaneStack = 24;     // per-lane stack of the independent walk (trees up to this depth)
+constexpr int kLaneStackShort = 20;  // the trace kernels' shorter per-lane stack for trees up to this
+                                     // depth: 21.7 KB of LDS per workgroup, so 7 workgroups share a CU
 constexpr int kWalkDone = INT32_MIN;  // per-lane walk finished (never a node index or leaf code)
 
 // BVH2 node, 64 bytes, both child boxes stored in the parent:
@@ -96,7 +98,8 @@ struct TraceArgs {
     int64_t tiles_per_dir;
     int32_t tiles_per_wave;
     int32_t blocks_per_dir;
-    int32_t lane_walk;        // 1: secondary segments use the per-lane walk (tree depth <= kLaneStack)
+    int32_t lane_walk;        // nonzero: secondary segments use the per-lane walk (tree depth <= kLaneStack);
+                              // 2: the tree also fits kLaneStackShort
     int32_t cull;             // 1: skip wave tiles that provably miss the scene (library frames)
     int32_t xcd_major;        // 1: unit u (direction, or design x direction) is traced by XCD u % 8
     const int64_t* pix;       // records mode: explicit pixel list, or null = all pixels

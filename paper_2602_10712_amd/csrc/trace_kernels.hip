@@ -88,10 +88,11 @@ __global__ void k_pack_phong(const float* __restrict__ phong, const int32_t* __r
     if (mat) mat[p].w = m;
 }
 
-// LDS of one trace workgroup.
+// LDS of one trace workgroup, with per-lane stacks of LS entries.
+template <int LS>
 struct TraceLds {
     int stack[kWaves][kStackDepth];    // wave-uniform stacks of the coherent walk
-    int lane[kWaves][kLaneStack][64];  // per-lane stacks of the independent walk
+    int lane[kWaves][LS][64];          // per-lane stacks of the independent walk
     float red[kWaves][6];              // per-wave force and torque sums
     float4 rect[kCullBoxes];           // pixel rectangles of the culling boxes
     uint64_t live;                     // workgroup tiles that may contain a hit
@@ -102,11 +103,11 @@ struct TraceLds {
 // Every thread of the workgroup calls it (it holds barriers).  RECORDS: per-pixel records for an
 // explicit pixel list; PATHS: also write the triangle each traced path hits at each interaction
 // into the path record (grid mode), for the adjoint.
-template <bool RECORDS, bool PATHS>
+template <bool RECORDS, bool PATHS, int LS>
 __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNode* __restrict__ nodes,
                                                 const TriRec* __restrict__ tris, const float4* __restrict__ mat,
                                                 const float com[3], float eps, uint32_t design, int64_t j,
-                                                int64_t unit, int32_t blk, TraceLds& L,
+                                                int64_t unit, int32_t blk, TraceLds<LS>& L,
                                                 int32_t* __restrict__ paths = nullptr)
 {
     const int lane = threadIdx.x & 63;
@@ -236,43 +237,49 @@ __device__ __forceinline__ void trace_workgroup(const TraceArgs& a, const BvhNod
     }
 }
 
-// Single scene: one workgroup per (direction, blk), placed by block_unit.
-template <bool RECORDS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_trace(TraceArgs a)
+// Single scene: one workgroup per (direction, blk), placed by block_unit.  LS = kLaneStackShort
+// for trees that fit it: the smaller LDS footprint (and at most 72 VGPRs) lets 7 workgroups share
+// a CU instead of 6.
+template <bool RECORDS, int LS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LS == kLaneStackShort ? 7 : 6))) void k_trace(
+    TraceArgs a)
 {
-    __shared__ TraceLds L;
+    __shared__ TraceLds<LS> L;
     int64_t j;
     int32_t blk;
     if (!block_unit(a, a.D, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
-    trace_workgroup<RECORDS, false>(a, a.nodes, a.tris, a.mat, a.com, a.eps, a.design_index, j, j, blk, L);
+    trace_workgroup<RECORDS, false, LS>(a, a.nodes, a.tris, a.mat, a.com, a.eps, a.design_index, j, j, blk, L);
 }
 
 // k_trace that also writes the path record.  The record and the scene arrays come as separate
 // __restrict__ parameters: the record stores then provably leave the scene untouched, and node
 // and triangle records can still be fetched through the scalar cache.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_trace_paths(
+template <int LS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LS == kLaneStackShort ? 7 : 6))) void k_trace_paths(
     TraceArgs a, const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris, const float4* __restrict__ mat,
     int32_t* __restrict__ paths)
 {
-    __shared__ TraceLds L;
+    __shared__ TraceLds<LS> L;
     int64_t j;
     int32_t blk;
     if (!block_unit(a, a.D, blockIdx.x, j, blk)) return;  // whole workgroup: grid padding
-    trace_workgroup<false, true>(a, nodes, tris, mat, a.com, a.eps, a.design_index, j, j, blk, L, paths);
+    trace_workgroup<false, true, LS>(a, nodes, tris, mat, a.com, a.eps, a.design_index, j, j, blk, L, paths);
 }
 
 // Batched designs: the n_scenes x D (design, direction) units in design-major order, placed like
 // the directions of a single scene (unit u on XCD u % 8), so all XCDs work through the designs
 // together and a design's directions are spread evenly over them.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_trace_batch(TraceArgs a)
+template <int LS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LS == kLaneStackShort ? 7 : 6))) void k_trace_batch(
+    TraceArgs a)
 {
-    __shared__ TraceLds L;
+    __shared__ TraceLds<LS> L;
     int64_t u;
     int32_t blk;
     if (!block_unit(a, a.n_scenes * a.D, blockIdx.x, u, blk)) return;  // whole workgroup: grid padding
     const int64_t s = u / a.D, j = u % a.D;
     const SceneDesc sd = a.scenes[s];
-    trace_workgroup<false, false>(a, (const BvhNode*)sd.nodes, (const TriRec*)sd.tris, (const float4*)sd.mat, sd.com,
+    trace_workgroup<false, false, LS>(a, (const BvhNode*)sd.nodes, (const TriRec*)sd.tris, (const float4*)sd.mat, sd.com,
                                   sd.eps, a.design_index + static_cast<uint32_t>(s), j, u, blk, L);
 }
 
@@ -334,13 +341,19 @@ hipError_t launch_trace(const TraceArgs& a, bool records, hipStream_t stream)
     const int64_t blocks = grid_blocks(a, a.D);
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(blocks)), block(64 * kWaves);
+    const bool short_stack = a.lane_walk == 2;
     if (records)
-        hipLaunchKernelGGL((k_trace<true>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
+        hipLaunchKernelGGL((k_trace<true, kLaneStack>), grid, block, 0, stream, a);
+    else if (a.path_hit && short_stack)
+        hipLaunchKernelGGL((k_trace_paths<kLaneStackShort>), grid, block, 0, stream, a, a.nodes, a.tris, a.mat,
+                           a.path_hit);
     else if (a.path_hit)
-        hipLaunchKernelGGL(k_trace_paths, dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a, a.nodes,
-                           a.tris, a.mat, a.path_hit);
+        hipLaunchKernelGGL((k_trace_paths<kLaneStack>), grid, block, 0, stream, a, a.nodes, a.tris, a.mat, a.path_hit);
+    else if (short_stack)
+        hipLaunchKernelGGL((k_trace<false, kLaneStackShort>), grid, block, 0, stream, a);
     else
-        hipLaunchKernelGGL((k_trace<false>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
+        hipLaunchKernelGGL((k_trace<false, kLaneStack>), grid, block, 0, stream, a);
     return hipGetLastError();
 }
 
@@ -349,7 +362,12 @@ hipError_t launch_trace_batch(const TraceArgs& a, hipStream_t stream)
     const int64_t blocks = grid_blocks(a, static_cast<int64_t>(a.n_scenes) * a.D);
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_trace_batch, dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0, stream, a);
+    if (a.lane_walk == 2)
+        hipLaunchKernelGGL((k_trace_batch<kLaneStackShort>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0,
+                           stream, a);
+    else
+        hipLaunchKernelGGL((k_trace_batch<kLaneStack>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves), 0,
+                           stream, a);
     return hipGetLastError();
 }
 
