@@ -236,8 +236,10 @@ __device__ __forceinline__ void edge_paths_pair(const BvhNode* __restrict__ node
     }
 }
 
+// Five waves per SIMD (96 VGPRs, a few spilled around the walk) beat four without spills (124
+// VGPRs): the divergent per-lane walks wait on fetches, and a fifth wave hides more of that.
 template <bool LANE>
-__global__ __launch_bounds__(256) void k_edge_term(EdgeArgs E, const BvhNode* __restrict__ nodes,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_edge_term(EdgeArgs E, const BvhNode* __restrict__ nodes,
                                                    const TriRec* __restrict__ tris, const float4* __restrict__ mat,
                                                    const DevFrame* __restrict__ frames,
                                                    const double* __restrict__ g_force,
