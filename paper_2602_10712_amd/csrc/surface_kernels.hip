@@ -574,9 +574,11 @@ __device__ __forceinline__ void surface_sample(const SurfaceArgs& a, const Geo& 
     rec_lit = lit;
 }
 
-// Workgroup = kSurfThreads consecutive samples of one unit (scene, direction).
+// Workgroup = kSurfThreads consecutive samples of one unit (scene, direction).  Five waves per
+// SIMD: the BVH mode (99 VGPRs at its natural allocation, four waves) then keeps 96 with 2
+// spilled, and its divergent per-lane walks hide more fetch latency (about 8 % faster).
 template <bool BRUTE>
-__global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a)
+__global__ __launch_bounds__(kSurfThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_surface(SurfaceArgs a)
 {
     __shared__ int s_lane[kSurfThreads / 64][kLaneStack][64];
     __shared__ float s_red[kSurfThreads / 64][6];
